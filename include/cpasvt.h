@@ -1,0 +1,191 @@
+/*
+ * cpasvt.h - C ABI of the MI355X (gfx950) library for singular value
+ * shrinkage by Chebyshev polynomial approximation (CPA), after Onuki, Ono,
+ * Shirai, Tanaka, "Fast Singular Value Shrinkage with Chebyshev Polynomial
+ * Approximation Based on Signal Sparsity".
+ *
+ * What is computed.  For X (m x n) and a shrinkage response h on the
+ * eigenvalues of the Gram (Sec. IV-A, eq. filter_response_ours; g(s) = s h(s^2)),
+ * the library returns
+ *     Y = X * hat H(X^T X)          (m >= n, Sec. III-B, eq. sing_shrink_from_eig_shrink)
+ *     Y = hat H(X X^T) * X          (m <  n, the same identity on X^T)
+ * where hat H is the K-term Chebyshev interpolant of h on [0, Lambda]
+ * (Sec. III-A, eqs. chebychev_series_matrix, chebychev_coeff_shifted) and
+ * Lambda >= lambda_max(Gram).  This is Algorithm 1 (Sec. III-B) with the
+ * sparsifying transform T = Id and no truncation, evaluated with the sum
+ * distributed over X: Y_0 = X, Y_1 = X hat B, Y_{k+1} = 2 Y_k hat B - Y_{k-1},
+ * Y = c_0/2 Y_0 + sum_k c_k Y_k, hat B = (2/Lambda) Gram - Id.  No SVD or EVD is
+ * computed.
+ *
+ * Conventions for every entry point.
+ *   - Matrices are row-major with a leading dimension (elements between the
+ *     starts of consecutive rows) >= the column count.
+ *   - Pointers named *_dev are device memory owned by the caller; the library
+ *     never frees them.  Pointers named *_host are host memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work is enqueued on it.  A call returns after enqueueing unless its
+ *     description says it synchronises `stream`.
+ *   - Argument errors are detected before anything is enqueued.  Nothing throws
+ *     or aborts across this interface; every call returns a cpa_status, and
+ *     cpa_last_error() gives a message for the calling thread.
+ *   - The library owns its workspace (grown on demand inside the context with
+ *     hipMalloc, freed by cpa_destroy).  Calls that share a context must not
+ *     run concurrently on different host threads or streams.
+ */
+#ifndef CPASVT_H
+#define CPASVT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CPA_OK = 0,
+    CPA_ERR_ARG = 1,          /* invalid argument (null pointer, K < 1, aliasing, bad enum) */
+    CPA_ERR_SHAPE = 2,        /* negative size, leading dimension too small, size above limits */
+    CPA_ERR_ALLOC = 3,        /* device workspace allocation failed */
+    CPA_ERR_HIP = 4,          /* a HIP runtime call failed */
+    CPA_ERR_NONFINITE = 5,    /* a spectral bound came out NaN or infinite */
+    CPA_ERR_BOUND = 6,        /* growth check failed even with the guaranteed bound */
+    CPA_ERR_UNSUPPORTED = 7   /* option combination not supported */
+} cpa_status;
+
+/* Members of the shrinkage family of Sec. IV-A (eq. filter_response_ours),
+ * h(x; w(x)/rho, tau) = (sqrt(x) - w(x)/rho) / sqrt(x) if sqrt(x) > tau, else 0:
+ *   CPA_SOFT            h(x; tau, tau)            g(s) = max(s - tau, 0)  (tau = 1/rho)
+ *   CPA_HARD            h(x; 0, tau)              g(s) = s if s > tau else 0
+ *   CPA_WEIGHTED_CONST  h(x; tau, tau)            a constant weight w/rho = tau
+ *   CPA_WEIGHTED_FN     h(x; w(x), w(x))          w(x) = w_c / (sqrt(max(x - w_sigma, 0)) + w_eps)
+ * The threshold test is strict (sqrt(x) == tau gives 0) and x <= 0 gives 0. */
+typedef enum { CPA_SOFT = 0, CPA_HARD = 1, CPA_WEIGHTED_CONST = 2, CPA_WEIGHTED_FN = 3 } cpa_kind;
+
+typedef struct {
+    int32_t kind;       /* cpa_kind */
+    int32_t reserved;   /* must be 0 */
+    double tau;         /* threshold (SOFT, HARD, WEIGHTED_CONST) */
+    double w_c;         /* WEIGHTED_FN numerator */
+    double w_sigma;     /* WEIGHTED_FN offset subtracted from x = s^2 */
+    double w_eps;       /* WEIGHTED_FN regulariser, > 0 */
+} cpa_shrinkage;
+
+/* How the spectral bound Lambda >= lambda_max(Gram) is obtained (Algorithm 1,
+ * the maximum-eigenvalue step; the paper does not fix a method):
+ *   CPA_BOUND_POWER      power iteration on the Gram: start vector entry i =
+ *                        2u - 1, u = (SplitMix64(seed + (i+1)*0x9E3779B97F4A7C15) >> 11) * 2^-53;
+ *                        w = Gram v, mu = v.w, stop when |mu_t - mu_{t-1}| <= power_tol * mu_t
+ *                        or after power_iters products; ||r|| = sqrt(max(||w||^2 - mu^2, 0));
+ *                        Lambda = min(mu + max(margin * mu, ||r||), ||Gram||_F)
+ *   CPA_BOUND_GIVEN      Lambda = opts.Lambda (must be >= 0 and finite)
+ *   CPA_BOUND_FROBENIUS  Lambda = ||Gram||_F (always an upper bound) */
+typedef enum { CPA_BOUND_POWER = 0, CPA_BOUND_GIVEN = 1, CPA_BOUND_FROBENIUS = 2 } cpa_bound_rule;
+
+/* Arithmetic of the Gram and recurrence products.
+ *   CPA_PREC_FP32   FP32 MFMA with FP32 accumulation. */
+typedef enum { CPA_PREC_FP32 = 0 } cpa_precision;
+
+typedef struct {
+    int32_t K;            /* number of Chebyshev coefficients (the paper's order alpha), >= 1 */
+    int32_t bound;        /* cpa_bound_rule */
+    double Lambda;        /* used with CPA_BOUND_GIVEN */
+    int32_t power_iters;  /* maximum Gram-vector products, >= 1 */
+    int32_t warm_start;   /* 1: start from the context's last power vector when its length matches */
+    double power_tol;     /* relative tolerance on successive Rayleigh quotients */
+    double margin;        /* relative margin delta added to the Rayleigh quotient */
+    uint64_t seed;        /* start-vector seed */
+    int32_t check;        /* 1: growth check max_k ||Y_k||_F / ||X||_F <= 1 + growth_tol, with one
+                             recompute at Lambda = ||Gram||_F on failure (synchronises the stream) */
+    int32_t precision;    /* cpa_precision */
+    double growth_tol;    /* tolerance of the growth check */
+} cpa_opts;
+
+/* Per-call report (host struct).  Filling it synchronises the stream. */
+typedef struct {
+    double Lambda;        /* bound used by the final evaluation */
+    double mu;            /* last Rayleigh quotient (0 unless CPA_BOUND_POWER) */
+    double resid;         /* last residual norm ||Gram v - mu v|| */
+    double fro_gram;      /* ||Gram||_F */
+    double max_growth;    /* max_k ||Y_k||_F / ||X||_F over k = 1..K-1 (0 if K == 1) */
+    int32_t power_iters_done;
+    int32_t fallback;     /* 1 when the growth check forced Lambda = ||Gram||_F */
+    int32_t side;         /* 0: Gram = X^T X (m >= n), 1: Gram = X X^T (m < n) */
+    int32_t reserved;
+} cpa_info;
+
+typedef struct cpa_ctx cpa_ctx;
+
+/* Context bound to one HIP device.  Allocates no device memory until first use. */
+cpa_status cpa_create(cpa_ctx** ctx_out, int device);
+cpa_status cpa_destroy(cpa_ctx* ctx);
+
+/* Static text for a status code. */
+const char* cpa_status_string(cpa_status s);
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* cpa_last_error(void);
+
+/* Fills opts with defaults: K = 16, POWER bound, power_iters = 100, power_tol = 1e-7,
+ * margin = 0.01, seed = 0, warm_start = 0, check = 0, FP32, growth_tol = 1e-3. */
+void cpa_default_opts(cpa_opts* opts);
+
+/* Chebyshev coefficients on the host in FP64 (Sec. III-A, eq. chebychev_coeff_shifted;
+ * Algorithm 1, coefficient step):
+ *   c_k = (2/K) sum_{l=1..K} cos(k theta_l) h(Lambda/2 (cos theta_l + 1)),
+ *   theta_l = pi (l - 1/2) / K,  k = 0..K-1.
+ * c_host must hold K doubles.  Lambda == 0 gives all zeros.  Pure host code. */
+cpa_status cpa_chebyshev_coeffs(const cpa_shrinkage* shrink, double Lambda, int K, double* c_host);
+
+/* The device bound alone: forms the Gram of X (FP32 MFMA) and applies opts->bound
+ * to it.  Writes Lambda to *Lambda_host and fills *info_host if non-null.
+ * Synchronises the stream. */
+cpa_status cpa_spectral_bound(cpa_ctx* ctx, void* stream, int m, int n,
+                              const float* X_dev, int64_t ldx, const cpa_opts* opts,
+                              double* Lambda_host, cpa_info* info_host);
+
+/* Dense shrinkage Y = hat G(X) of Algorithm 1 (T = Id), FP32 in and out.
+ * X_dev (m x n, ldx) is read only; Y_dev (m x n, ldy) is written and must not
+ * overlap X_dev (CPA_ERR_ARG).  m == 0 or n == 0 is a no-op.  Lambda == 0 (X == 0)
+ * gives Y = 0.  Asynchronous unless info_host != NULL or opts->check == 1. */
+cpa_status cpa_shrink_dense(cpa_ctx* ctx, void* stream, int m, int n,
+                            const float* X_dev, int64_t ldx, float* Y_dev, int64_t ldy,
+                            const cpa_shrinkage* shrink, const cpa_opts* opts,
+                            cpa_info* info_host);
+
+/* RPCA background modelling by ADMM (Appendix B, eq. admm_algorithm_mod) for
+ *   min ||L||_* + eta ||S||_1  s.t.  I = L + S,   z = K [l; s], K = [[Id,0],[0,Id],[Id,Id]].
+ * One iteration:
+ *   a = (z1-u1) + (z3-u3), b = (z2-u2) + (z3-u3), l = (2a-b)/3, s = (2b-a)/3;
+ *   z1 = CPA soft shrinkage of (l + u1) with tau = inv_rho   (the nuclear-norm prox);
+ *   z2 = sgn(s+u2) max(|s+u2| - eta_over_rho, 0);  z3 = I;
+ *   u1 += l - z1, u2 += s - z2, u3 += l + s - I;
+ *   E_t = ||l_new - l_old||_2 / ||l_new||_2.
+ * State: state_dev holds cpa_rpca_state_floats(m, n) floats laid out as seven
+ * consecutive m x n row-major blocks [l, s, z1, z2, u1, u2, u3] (z3 = I is not
+ * stored).  After any number of iterations L = block 0 and S = block 1.
+ * cpa_rpca_init writes the start l = s = u1 = u2 = u3 = 1 and z1 = z2 = 1
+ * (z = K [l; s]; the paper leaves z_0 unstated).
+ * cpa_rpca_iterate runs `iters` iterations from the given state; the spectral
+ * bound of each shrink uses opts (power iteration warm-started across
+ * iterations when opts->warm_start == 1).  Et_dev (device, `iters` doubles, may
+ * be NULL) receives E_t.  I_dev (m x n, ld = n) is read only.  Asynchronous. */
+int64_t cpa_rpca_state_floats(int m, int n);
+cpa_status cpa_rpca_init(cpa_ctx* ctx, void* stream, int m, int n, float* state_dev);
+cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const float* I_dev,
+                            float* state_dev, int iters, double inv_rho, double eta_over_rho,
+                            const cpa_opts* opts, double* Et_dev);
+
+/* Instrumentation: per-launch timing with HIP events.  While enabled, every
+ * launch of the recurrence GEMM (which = 0) and of the Gram GEMM (which = 1) is
+ * bracketed by a pair of events recorded on the caller's stream.
+ * cpa_timing_enable resets the record; cpa_timing_read waits for the recorded
+ * events and returns the summed kernel time in milliseconds and the number of
+ * launches since the last reset. */
+cpa_status cpa_timing_enable(cpa_ctx* ctx, int enable);
+cpa_status cpa_timing_read(cpa_ctx* ctx, int which, double* total_ms_host, int64_t* launches_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPASVT_H */

@@ -1,0 +1,286 @@
+"""Singular value shrinkage by Chebyshev polynomial approximation on MI355X.
+
+Thin ctypes binding over ``libcpasvt.so`` (C ABI in ``include/cpasvt.h``):
+argument marshalling only.  Every step of the shrinkage runs in the library's
+HIP kernels; torch supplies device memory and the current stream.  If the
+library has not been built the calls raise ``RuntimeError`` -- there is no CPU
+fallback.
+
+Typical use::
+
+    import torch, paper_1705_07112_amd as cpa
+    X = torch.randn(1024, 1024, device="cuda")
+    Y = cpa.shrink_dense(X, cpa.soft(10.0), cpa.Opts(K=30))
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcpasvt.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "cpasvt.h")
+
+SOFT, HARD, WEIGHTED_CONST, WEIGHTED_FN = 0, 1, 2, 3
+BOUND_POWER, BOUND_GIVEN, BOUND_FROBENIUS = 0, 1, 2
+PREC_FP32 = 0
+
+
+class CpaShrinkage(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("w_c", ctypes.c_double), ("w_sigma", ctypes.c_double), ("w_eps", ctypes.c_double)]
+
+
+class CpaOpts(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("bound", ctypes.c_int32), ("Lambda", ctypes.c_double),
+                ("power_iters", ctypes.c_int32), ("warm_start", ctypes.c_int32),
+                ("power_tol", ctypes.c_double), ("margin", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("check", ctypes.c_int32), ("precision", ctypes.c_int32), ("growth_tol", ctypes.c_double)]
+
+
+class CpaInfo(ctypes.Structure):
+    _fields_ = [("Lambda", ctypes.c_double), ("mu", ctypes.c_double), ("resid", ctypes.c_double),
+                ("fro_gram", ctypes.c_double), ("max_growth", ctypes.c_double),
+                ("power_iters_done", ctypes.c_int32), ("fallback", ctypes.c_int32),
+                ("side", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+class CpaError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{status_string(status)}: {message}")
+        self.status = status
+
+
+_lib = None
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_SIGS = {
+    "cpa_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int]),
+    "cpa_destroy": (ctypes.c_int, [_P]),
+    "cpa_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "cpa_last_error": (ctypes.c_char_p, []),
+    "cpa_default_opts": (None, [ctypes.POINTER(CpaOpts)]),
+    "cpa_chebyshev_coeffs": (ctypes.c_int, [ctypes.POINTER(CpaShrinkage), ctypes.c_double, ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_double)]),
+    "cpa_spectral_bound": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _I64, ctypes.POINTER(CpaOpts),
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(CpaInfo)]),
+    "cpa_shrink_dense": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _I64, _P, _I64,
+                                        ctypes.POINTER(CpaShrinkage), ctypes.POINTER(CpaOpts),
+                                        ctypes.POINTER(CpaInfo)]),
+    "cpa_rpca_state_floats": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int]),
+    "cpa_timing_enable": (ctypes.c_int, [_P, ctypes.c_int]),
+    "cpa_timing_read": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int64)]),
+    "cpa_rpca_init": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P]),
+    "cpa_rpca_iterate": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _P, ctypes.c_int, ctypes.c_double,
+                                        ctypes.c_double, ctypes.POINTER(CpaOpts), _P]),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run `python -m paper_1705_07112_amd.build`)")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(l, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = l
+    return _lib
+
+
+def declared_symbols() -> list[str]:
+    """Function names declared in include/cpasvt.h."""
+    text = open(HEADER_PATH).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cpa_[a-z0-9_]+)\s*\(", text)))
+
+
+def status_string(s: int) -> str:
+    return lib().cpa_status_string(int(s)).decode()
+
+
+def _check(status: int):
+    if status != 0:
+        raise CpaError(status, lib().cpa_last_error().decode())
+
+
+# ---- parameter helpers ------------------------------------------------------
+
+def soft(tau: float) -> CpaShrinkage:
+    return CpaShrinkage(SOFT, 0, float(tau), 0.0, 0.0, 1.0)
+
+
+def hard(tau: float) -> CpaShrinkage:
+    return CpaShrinkage(HARD, 0, float(tau), 0.0, 0.0, 1.0)
+
+
+def weighted_const(w_over_rho: float) -> CpaShrinkage:
+    return CpaShrinkage(WEIGHTED_CONST, 0, float(w_over_rho), 0.0, 0.0, 1.0)
+
+
+def weighted_fn(w_c: float, w_sigma: float, w_eps: float = 1e-6) -> CpaShrinkage:
+    return CpaShrinkage(WEIGHTED_FN, 0, 0.0, float(w_c), float(w_sigma), float(w_eps))
+
+
+@dataclass
+class Opts:
+    K: int = 16
+    bound: str = "power"          # "power" | "given" | "frobenius"
+    Lambda: float | None = None
+    power_iters: int = 100
+    warm_start: bool = False
+    power_tol: float = 1e-7
+    margin: float = 0.01
+    seed: int = 0
+    check: bool = False
+    growth_tol: float = 1e-3
+
+    def to_c(self) -> CpaOpts:
+        o = CpaOpts()
+        lib().cpa_default_opts(ctypes.byref(o))
+        o.K = int(self.K)
+        bound = self.bound
+        if self.Lambda is not None and bound == "power":
+            bound = "given"
+        o.bound = {"power": BOUND_POWER, "given": BOUND_GIVEN, "frobenius": BOUND_FROBENIUS}[bound]
+        o.Lambda = float(self.Lambda or 0.0)
+        o.power_iters = int(self.power_iters)
+        o.warm_start = int(bool(self.warm_start))
+        o.power_tol = float(self.power_tol)
+        o.margin = float(self.margin)
+        o.seed = int(self.seed)
+        o.check = int(bool(self.check))
+        o.precision = PREC_FP32
+        o.growth_tol = float(self.growth_tol)
+        return o
+
+
+# ---- device plumbing -----------------------------------------------------------
+
+_contexts: dict[int, int] = {}
+
+
+def context(device: int = 0) -> int:
+    if device not in _contexts:
+        h = ctypes.c_void_p()
+        _check(lib().cpa_create(ctypes.byref(h), int(device)))
+        _contexts[device] = h.value
+    return _contexts[device]
+
+
+def _stream(t):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _mat(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or t.dim() != 2:
+        raise TypeError(f"{name} must be a 2-D float32 CUDA tensor")
+    if t.stride(1) != 1:
+        raise ValueError(f"{name} must have unit column stride (row-major)")
+    return t.shape[0], t.shape[1], max(t.stride(0), t.shape[1])
+
+
+def chebyshev_coeffs(shrink: CpaShrinkage, Lambda: float, K: int) -> np.ndarray:
+    """FP64 coefficients from the library's host routine."""
+    out = (ctypes.c_double * int(K))()
+    _check(lib().cpa_chebyshev_coeffs(ctypes.byref(shrink), float(Lambda), int(K), out))
+    return np.array(out[:], dtype=np.float64)
+
+
+def shrink_dense(X, shrink: CpaShrinkage, opts: Opts, out=None, info: bool = False):
+    """Y = hat G(X) (Algorithm 1 with T = Id).  Returns Y, or (Y, info dict)."""
+    import torch
+    m, n, ldx = _mat(X, "X")
+    if out is None:
+        out = torch.empty((m, n), device=X.device, dtype=torch.float32)
+    _, _, ldy = _mat(out, "out")
+    if tuple(out.shape) != (m, n):
+        raise ValueError("out has the wrong shape")
+    ci = CpaInfo()
+    co = opts.to_c()
+    _check(lib().cpa_shrink_dense(ctypes.c_void_p(context(X.device.index or 0)), _stream(X), m, n,
+                                  ctypes.c_void_p(X.data_ptr()), ldx, ctypes.c_void_p(out.data_ptr()), ldy,
+                                  ctypes.byref(shrink), ctypes.byref(co), ctypes.byref(ci) if info else None))
+    return (out, ci.as_dict()) if info else out
+
+
+def spectral_bound(X, opts: Opts):
+    """(Lambda, info dict) for the Gram of X, computed on the device."""
+    m, n, ldx = _mat(X, "X")
+    lam = ctypes.c_double()
+    ci = CpaInfo()
+    co = opts.to_c()
+    _check(lib().cpa_spectral_bound(ctypes.c_void_p(context(X.device.index or 0)), _stream(X), m, n,
+                                    ctypes.c_void_p(X.data_ptr()), ldx, ctypes.byref(co), ctypes.byref(lam),
+                                    ctypes.byref(ci)))
+    return lam.value, ci.as_dict()
+
+
+def timing_enable(enable: bool = True, device: int = 0):
+    """Start (or stop) per-launch event timing of the GEMM kernels; resets the record."""
+    _check(lib().cpa_timing_enable(ctypes.c_void_p(context(device)), int(bool(enable))))
+
+
+def timing_read(which: str = "recurrence", device: int = 0):
+    """(total kernel milliseconds, launches) recorded since timing_enable."""
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _check(lib().cpa_timing_read(ctypes.c_void_p(context(device)), {"recurrence": 0, "gram": 1}[which],
+                                 ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value
+
+
+class RpcaAdmm:
+    """RPCA by ADMM (Appendix B of the paper) with CPA shrinkage, state on the device.
+
+    ``state`` holds the blocks [l, s, z1, z2, u1, u2, u3]; ``L`` and ``S`` view
+    the first two."""
+
+    def __init__(self, I, inv_rho: float, eta_over_rho: float, opts: Opts):
+        import torch
+        m, n, ld = _mat(I, "I")
+        if ld != n:
+            raise ValueError("I must be contiguous")
+        self.I, self.m, self.n = I, m, n
+        self.inv_rho, self.eta_over_rho, self.opts = float(inv_rho), float(eta_over_rho), opts
+        count = lib().cpa_rpca_state_floats(m, n)
+        self.state = torch.empty(count, device=I.device, dtype=torch.float32)
+        self.ctx = context(I.device.index or 0)
+        self.t = 0
+        _check(lib().cpa_rpca_init(ctypes.c_void_p(self.ctx), _stream(I), m, n,
+                                   ctypes.c_void_p(self.state.data_ptr())))
+
+    def block(self, i: int):
+        mn = self.m * self.n
+        return self.state[i * mn:(i + 1) * mn].view(self.m, self.n)
+
+    @property
+    def L(self):
+        return self.block(0)
+
+    @property
+    def S(self):
+        return self.block(1)
+
+    def iterate(self, iters: int, Et=None):
+        """Runs ``iters`` iterations; ``Et`` (float64 CUDA tensor, >= iters) receives E_t."""
+        co = self.opts.to_c()
+        ptr = ctypes.c_void_p(Et.data_ptr()) if Et is not None else None
+        _check(lib().cpa_rpca_iterate(ctypes.c_void_p(self.ctx), _stream(self.I), self.m, self.n,
+                                      ctypes.c_void_p(self.I.data_ptr()), ctypes.c_void_p(self.state.data_ptr()),
+                                      int(iters), self.inv_rho, self.eta_over_rho, ctypes.byref(co), ptr))
+        self.t += iters

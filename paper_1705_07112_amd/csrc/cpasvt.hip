@@ -1,0 +1,614 @@
+// Host side of the C ABI declared in include/cpasvt.h: argument checks,
+// workspace, and the launch sequence of one shrink
+//   Gram (MFMA) -> bound (power iteration / given / Frobenius) -> FP64
+//   coefficients on the device -> K-1 fused recurrence GEMMs
+// plus the RPCA ADMM driver around it.  Everything is enqueued on the
+// caller's stream; only calls that report host values synchronise.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/cpasvt.h"
+#include "admm.hpp"
+#include "gemm_f32.hpp"
+#include "shrink_fn.hpp"
+#include "spectral.hpp"
+
+using namespace cpa;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+cpa_status fail(cpa_status s, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+#define HIP_TRY(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) return fail(CPA_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kMaxPowerIters = 1000;
+constexpr int kMaxK = 4096;
+
+}  // namespace
+
+// Event pairs bracketing individual launches of one kernel family, for
+// per-launch timing with HIP events on the caller's stream.
+struct TimingLog {
+    std::vector<hipEvent_t> ev;   // start/end pairs, reused between records
+    size_t used = 0;              // pairs recorded since the last reset
+};
+
+struct cpa_ctx {
+    int device = 0;
+    int timing = 0;               // 1: bracket launches with events
+    TimingLog tlog[2];            // 0: recurrence GEMMs, 1: Gram GEMMs
+    void* ws = nullptr;        // main workspace
+    size_t ws_bytes = 0;
+    double* warm = nullptr;    // warm-start vector for power iteration
+    int warm_cap = 0;
+    int warm_d = -1;           // length of the stored vector, -1 if none
+};
+
+namespace {
+
+// Returns the event pair for the next launch of family `which` (nullptrs when timing is off).
+cpa_status timing_pair(cpa_ctx* ctx, int which, hipEvent_t& a, hipEvent_t& b) {
+    a = b = nullptr;
+    if (!ctx || !ctx->timing) return CPA_OK;
+    TimingLog& L = ctx->tlog[which];
+    if (2 * (L.used + 1) > L.ev.size()) {
+        for (int q = 0; q < 2; ++q) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            L.ev.push_back(e);
+        }
+    }
+    a = L.ev[2 * L.used];
+    b = L.ev[2 * L.used + 1];
+    ++L.used;
+    return CPA_OK;
+}
+
+struct Work {
+    float* G;
+    float* Yb[2];
+    double* w[2];
+    double* scal;
+    float* x;      // ADMM shrink input
+    double* admm;  // ADMM scalars (E_t sums), separate from the per-shrink block
+    ScalarLayout lay;
+};
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+cpa_status ensure_ws(cpa_ctx* ctx, int m, int n, int K, int maxit, bool admm, Work& w) {
+    const int d = std::min(m, n);
+    const int64_t mn = (int64_t)m * n;
+    w.lay.K = K;
+    w.lay.maxit = maxit;
+    size_t off = 0;
+    const size_t oG = off; off = align_up(off + sizeof(float) * (size_t)d * d);
+    const size_t oY0 = off; off = align_up(off + sizeof(float) * (size_t)mn);
+    const size_t oY1 = off; off = align_up(off + sizeof(float) * (size_t)mn);
+    const size_t ow0 = off; off = align_up(off + sizeof(double) * (size_t)d);
+    const size_t ow1 = off; off = align_up(off + sizeof(double) * (size_t)d);
+    const size_t os = off; off = align_up(off + sizeof(double) * (size_t)w.lay.total());
+    size_t ox = 0, oa = 0;
+    if (admm) {
+        ox = off; off = align_up(off + sizeof(float) * (size_t)mn);
+        oa = off; off = align_up(off + sizeof(double) * 16);
+    }
+    if (off > ctx->ws_bytes) {
+        if (ctx->ws) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipFree(ctx->ws));
+            ctx->ws = nullptr;
+            ctx->ws_bytes = 0;
+        }
+        if (hipMalloc(&ctx->ws, off) != hipSuccess) {
+            ctx->ws = nullptr;
+            return fail(CPA_ERR_ALLOC, "workspace allocation of %zu bytes failed", off);
+        }
+        ctx->ws_bytes = off;
+    }
+    char* b = static_cast<char*>(ctx->ws);
+    w.G = reinterpret_cast<float*>(b + oG);
+    w.Yb[0] = reinterpret_cast<float*>(b + oY0);
+    w.Yb[1] = reinterpret_cast<float*>(b + oY1);
+    w.w[0] = reinterpret_cast<double*>(b + ow0);
+    w.w[1] = reinterpret_cast<double*>(b + ow1);
+    w.scal = reinterpret_cast<double*>(b + os);
+    w.x = admm ? reinterpret_cast<float*>(b + ox) : nullptr;
+    w.admm = admm ? reinterpret_cast<double*>(b + oa) : nullptr;
+    if (d > ctx->warm_cap) {
+        if (ctx->warm) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipFree(ctx->warm));
+        }
+        ctx->warm = nullptr;
+        if (hipMalloc(&ctx->warm, sizeof(double) * (size_t)std::max(d, 1)) != hipSuccess) {
+            ctx->warm_cap = 0;
+            ctx->warm_d = -1;
+            return fail(CPA_ERR_ALLOC, "warm-start vector allocation failed");
+        }
+        ctx->warm_cap = std::max(d, 1);
+        ctx->warm_d = -1;
+    }
+    return CPA_OK;
+}
+
+Operand make_op(const float* p, int64_t ld, int xdim) {
+    Operand o;
+    o.p = p;
+    o.ld = ld;
+    o.xdim = xdim;
+    o.vec_ok = (ld % 4 == 0) && ((reinterpret_cast<uintptr_t>(p) & 15) == 0);
+    return o;
+}
+
+template <int BM, int BN, int LA, int LB, class Epi>
+cpa_status launch_gemm(hipStream_t st, const Operand& A, const Operand& B, int M, int N, int Kd, const Epi& epi,
+                       int sc_a1, int sc_a2, int sc_coef) {
+    const int ntm = (M + BM - 1) / BM, ntn = (N + BN - 1) / BN;
+    const int grid = ntm * ntn;
+    if (grid <= 0) return CPA_OK;
+    hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, LA, LB, Epi>), dim3(grid), dim3(GTHREADS), 0, st, A, B, M, N, Kd,
+                       epi, sc_a1, sc_a2, sc_coef);
+    HIP_TRY(hipGetLastError());
+    return CPA_OK;
+}
+
+// Tile size choice: 64 x 64 tiles keep >= 256 workgroups in flight from 1024 x 1024
+// outputs; larger outputs take 128 x 128 tiles for more reuse per workgroup.
+template <int LA, int LB, class Epi>
+cpa_status gemm_dispatch(hipStream_t st, const Operand& A, const Operand& B, int M, int N, int Kd, const Epi& epi,
+                         int sc_a1, int sc_a2, int sc_coef) {
+    const int64_t tiles128 = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
+    if (tiles128 >= 512) return launch_gemm<128, 128, LA, LB>(st, A, B, M, N, Kd, epi, sc_a1, sc_a2, sc_coef);
+    return launch_gemm<64, 64, LA, LB>(st, A, B, M, N, Kd, epi, sc_a1, sc_a2, sc_coef);
+}
+
+ShrinkParams to_params(const cpa_shrinkage* s) {
+    ShrinkParams p;
+    p.kind = s->kind;
+    p.tau = s->tau;
+    p.w_c = s->w_c;
+    p.w_sigma = s->w_sigma;
+    p.w_eps = s->w_eps;
+    return p;
+}
+
+cpa_status check_shrinkage(const cpa_shrinkage* s) {
+    if (!s) return fail(CPA_ERR_ARG, "shrinkage is NULL");
+    if (s->kind < 0 || s->kind > 3) return fail(CPA_ERR_ARG, "unknown shrinkage kind %d", s->kind);
+    if (s->kind != CPA_WEIGHTED_FN && !(std::isfinite(s->tau) && s->tau >= 0.0))
+        return fail(CPA_ERR_ARG, "tau must be finite and >= 0");
+    if (s->kind == CPA_WEIGHTED_FN &&
+        !(std::isfinite(s->w_c) && std::isfinite(s->w_sigma) && s->w_eps > 0.0 && s->w_c >= 0.0))
+        return fail(CPA_ERR_ARG, "weighted function needs finite w_c >= 0, w_sigma and w_eps > 0");
+    return CPA_OK;
+}
+
+cpa_status check_opts(const cpa_opts* o) {
+    if (!o) return fail(CPA_ERR_ARG, "opts is NULL");
+    if (o->K < 1 || o->K > kMaxK) return fail(CPA_ERR_ARG, "K must be in [1, %d], got %d", kMaxK, o->K);
+    if (o->bound < 0 || o->bound > 2) return fail(CPA_ERR_ARG, "unknown bound rule %d", o->bound);
+    if (o->bound == CPA_BOUND_GIVEN && !(std::isfinite(o->Lambda) && o->Lambda >= 0.0))
+        return fail(CPA_ERR_ARG, "given Lambda must be finite and >= 0");
+    if (o->bound == CPA_BOUND_POWER) {
+        if (o->power_iters < 1 || o->power_iters > kMaxPowerIters)
+            return fail(CPA_ERR_ARG, "power_iters must be in [1, %d]", kMaxPowerIters);
+        if (!(o->power_tol >= 0.0) || !(o->margin >= 0.0)) return fail(CPA_ERR_ARG, "power_tol and margin must be >= 0");
+    }
+    if (o->precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "precision %d not supported", o->precision);
+    return CPA_OK;
+}
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + bbytes && pb < pa + abytes;
+}
+
+cpa_status fill_scalars(hipStream_t st, const Work& w) {
+    const int n = w.lay.total();
+    hipLaunchKernelGGL(fill_f64_kernel, dim3((n + 255) / 256), dim3(256), 0, st, w.scal, n, 0.0);
+    HIP_TRY(hipGetLastError());
+    return CPA_OK;
+}
+
+// Gram into w.G (d x d, ld = d) with ||G||_F^2 and trace accumulated.
+cpa_status enqueue_gram_impl(hipStream_t st, int m, int n, const float* X, int64_t ldx, const Work& w);
+
+cpa_status enqueue_gram(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* X, int64_t ldx, const Work& w) {
+    hipEvent_t a, b;
+    cpa_status s = timing_pair(ctx, 1, a, b);
+    if (s != CPA_OK) return s;
+    if (a) HIP_TRY(hipEventRecord(a, st));
+    s = enqueue_gram_impl(st, m, n, X, ldx, w);
+    if (s != CPA_OK) return s;
+    if (b) HIP_TRY(hipEventRecord(b, st));
+    return CPA_OK;
+}
+
+cpa_status enqueue_gram_impl(hipStream_t st, int m, int n, const float* X, int64_t ldx, const Work& w) {
+    EpiGram epi;
+    const int d = std::min(m, n);
+    epi.C = w.G;
+    epi.ldc = d;
+    epi.fro2 = w.scal + SC_FRO2;
+    epi.trace = w.scal + SC_TRACE;
+    if (m >= n) {
+        // G(i, j) = sum_r X[r][i] X[r][j]
+        Operand A = make_op(X, ldx, n), B = make_op(X, ldx, n);
+        return gemm_dispatch<XCONTIG, XCONTIG>(st, A, B, n, n, m, epi, 0, 0, 0);
+    }
+    // G(i, j) = sum_c X[i][c] X[j][c]
+    Operand A = make_op(X, ldx, m), B = make_op(X, ldx, m);
+    return gemm_dispatch<KCONTIG, KCONTIG>(st, A, B, m, m, n, epi, 0, 0, 0);
+}
+
+cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkage* sh, const cpa_opts* o,
+                         const Work& w, int mode_override) {
+    int mode = o->bound == CPA_BOUND_POWER ? 0 : (o->bound == CPA_BOUND_GIVEN ? 1 : 2);
+    if (mode_override >= 0) mode = mode_override;
+    if (mode == 0) {
+        const bool warm = o->warm_start && ctx->warm_d == d;
+        const int gi = std::max(1, std::min(64, (d + 255) / 256));
+        hipLaunchKernelGGL(power_init_kernel, dim3(gi), dim3(256), 0, st, d, (uint64_t)o->seed,
+                           warm ? (const double*)ctx->warm : nullptr, w.w[0], w.scal, w.lay.pw_w2());
+        HIP_TRY(hipGetLastError());
+        const int gs = std::max(1, std::min(1024, (d + 3) / 4));
+        for (int t = 1; t <= o->power_iters; ++t) {
+            hipLaunchKernelGGL(power_step_kernel, dim3(gs), dim3(256), 0, st, d, (const float*)w.G, (int64_t)d,
+                               (const double*)w.w[(t - 1) & 1], w.w[t & 1], w.scal, t, o->power_tol,
+                               w.lay.pw_mu(), w.lay.pw_w2());
+            HIP_TRY(hipGetLastError());
+        }
+    }
+    hipLaunchKernelGGL(finish_bound_kernel, dim3(1), dim3(256), 0, st, mode, o->Lambda, d, o->power_iters, o->margin,
+                       (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? ctx->warm : nullptr, w.scal,
+                       to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2());
+    HIP_TRY(hipGetLastError());
+    if (mode == 0) ctx->warm_d = d;
+    return CPA_OK;
+}
+
+// K-1 recurrence steps (or the K == 1 scaling), accumulating into Y.
+cpa_status enqueue_recurrence(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* X, int64_t ldx, float* Y, int64_t ldy,
+                              int K, const Work& w) {
+    if (K == 1) {
+        const int64_t total = (int64_t)m * n;
+        const int grid = (int)std::min<int64_t>(4096, (total + 255) / 256);
+        hipLaunchKernelGGL(scale_copy_kernel, dim3(std::max(grid, 1)), dim3(256), 0, st, m, n, X, ldx, Y, ldy,
+                           (const double*)w.scal);
+        HIP_TRY(hipGetLastError());
+        return CPA_OK;
+    }
+    const int d = std::min(m, n);
+    const int norms = w.lay.norms();
+    for (int k = 0; k + 1 <= K - 1; ++k) {
+        EpiCheb epi;
+        const float* yk = k == 0 ? X : w.Yb[(k - 1) & 1];
+        const int64_t ldk = k == 0 ? ldx : n;
+        const float* yp = k <= 1 ? X : w.Yb[k & 1];
+        const int64_t ldp = k <= 1 ? ldx : n;
+        epi.Yk = yk;
+        epi.ldk = ldk;
+        epi.Yprev = yp;
+        epi.ldp = ldp;
+        epi.Ydst = w.Yb[k & 1];
+        epi.ldd = n;
+        epi.out = Y;
+        epi.ldo = ldy;
+        epi.scal = w.scal;
+        epi.step = k;
+        epi.last = (k + 1 == K - 1) ? 1 : 0;
+        epi.nrm2 = w.scal + norms + k + 1;
+        hipEvent_t ea, eb;
+        cpa_status s = timing_pair(ctx, 0, ea, eb);
+        if (s != CPA_OK) return s;
+        if (ea) HIP_TRY(hipEventRecord(ea, st));
+        if (m >= n) {
+            // Y_k G: A = Y_k (k contiguous), B(k, j) = G[k][j] (j contiguous)
+            Operand A = make_op(yk, ldk, m), B = make_op(w.G, d, n);
+            s = gemm_dispatch<KCONTIG, XCONTIG>(st, A, B, m, n, n, epi, SC_A1, SC_A2, SC_COEF);
+        } else {
+            // G Y_k: A(i, k) = G[k][i] (G symmetric; i contiguous), B = Y_k (j contiguous)
+            Operand A = make_op(w.G, d, m), B = make_op(yk, ldk, n);
+            s = gemm_dispatch<XCONTIG, XCONTIG>(st, A, B, m, n, m, epi, SC_A1, SC_A2, SC_COEF);
+        }
+        if (s != CPA_OK) return s;
+        if (eb) HIP_TRY(hipEventRecord(eb, st));
+    }
+    return CPA_OK;
+}
+
+cpa_status read_info(hipStream_t st, const Work& w, int K, int m, int n, cpa_info* info, double* growth_out) {
+    std::vector<double> h(w.lay.total());
+    HIP_TRY(hipMemcpyAsync(h.data(), w.scal, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    double g = 0.0;
+    const double x2 = h[SC_TRACE];
+    for (int k = 1; k < K; ++k) {
+        const double r = x2 > 0.0 ? std::sqrt(h[w.lay.norms() + k] / x2) : 0.0;
+        g = std::max(g, r);
+    }
+    if (growth_out) *growth_out = g;
+    if (info) {
+        info->Lambda = h[SC_LAMBDA];
+        info->mu = h[SC_MU];
+        info->resid = h[SC_RESID];
+        info->fro_gram = std::sqrt(std::max(h[SC_FRO2], 0.0));
+        info->max_growth = g;
+        info->power_iters_done = (int)h[SC_ITERS];
+        info->fallback = 0;
+        info->side = m >= n ? 0 : 1;
+        info->reserved = 0;
+    }
+    if (!std::isfinite(h[SC_LAMBDA])) return fail(CPA_ERR_NONFINITE, "spectral bound is not finite");
+    return CPA_OK;
+}
+
+cpa_status shrink_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* X, int64_t ldx, float* Y,
+                       int64_t ldy, const cpa_shrinkage* sh, const cpa_opts* o, cpa_info* info, const Work& w) {
+    const int d = std::min(m, n);
+    cpa_status s;
+    if ((s = fill_scalars(st, w)) != CPA_OK) return s;
+    if ((s = enqueue_gram(ctx, st, m, n, X, ldx, w)) != CPA_OK) return s;
+    if ((s = enqueue_bound(ctx, st, d, sh, o, w, -1)) != CPA_OK) return s;
+    if ((s = enqueue_recurrence(ctx, st, m, n, X, ldx, Y, ldy, o->K, w)) != CPA_OK) return s;
+    if (!info && !o->check) return CPA_OK;
+    double growth = 0.0;
+    if ((s = read_info(st, w, o->K, m, n, info, &growth)) != CPA_OK) return s;
+    if (o->check && growth > 1.0 + o->growth_tol) {
+        // bound too small: redo with the guaranteed bound ||G||_F (Gram is still valid)
+        if ((s = fill_scalars(st, w)) != CPA_OK) return s;
+        if ((s = enqueue_gram(ctx, st, m, n, X, ldx, w)) != CPA_OK) return s;
+        if ((s = enqueue_bound(ctx, st, d, sh, o, w, 2)) != CPA_OK) return s;
+        if ((s = enqueue_recurrence(ctx, st, m, n, X, ldx, Y, ldy, o->K, w)) != CPA_OK) return s;
+        if ((s = read_info(st, w, o->K, m, n, info, &growth)) != CPA_OK) return s;
+        if (info) info->fallback = 1;
+        if (growth > 1.0 + o->growth_tol)
+            return fail(CPA_ERR_BOUND, "growth %.6g exceeds 1 + %.3g even with Lambda = ||G||_F", growth, o->growth_tol);
+    }
+    return CPA_OK;
+}
+
+cpa_status check_dense_args(cpa_ctx* ctx, int m, int n, const float* X, int64_t ldx) {
+    if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
+    if (m < 0 || n < 0) return fail(CPA_ERR_SHAPE, "negative size %d x %d", m, n);
+    if ((int64_t)m * n > (int64_t)1 << 31) return fail(CPA_ERR_SHAPE, "matrix too large");
+    if (m > 0 && n > 0) {
+        if (!X) return fail(CPA_ERR_ARG, "X is NULL");
+        if (ldx < n) return fail(CPA_ERR_SHAPE, "ldx %lld < n %d", (long long)ldx, n);
+    }
+    return CPA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cpa_status cpa_create(cpa_ctx** ctx_out, int device) {
+    if (!ctx_out) return fail(CPA_ERR_ARG, "ctx_out is NULL");
+    *ctx_out = nullptr;
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(CPA_ERR_ARG, "device %d out of range (%d devices)", device, count);
+    HIP_TRY(hipSetDevice(device));
+    cpa_ctx* c = new (std::nothrow) cpa_ctx();
+    if (!c) return fail(CPA_ERR_ALLOC, "context allocation failed");
+    c->device = device;
+    *ctx_out = c;
+    return CPA_OK;
+}
+
+cpa_status cpa_destroy(cpa_ctx* ctx) {
+    if (!ctx) return CPA_OK;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->ws || ctx->warm) (void)hipDeviceSynchronize();
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->warm) (void)hipFree(ctx->warm);
+    for (auto& L : ctx->tlog)
+        for (hipEvent_t e : L.ev) (void)hipEventDestroy(e);
+    delete ctx;
+    return CPA_OK;
+}
+
+const char* cpa_status_string(cpa_status s) {
+    switch (s) {
+        case CPA_OK: return "CPA_OK";
+        case CPA_ERR_ARG: return "CPA_ERR_ARG";
+        case CPA_ERR_SHAPE: return "CPA_ERR_SHAPE";
+        case CPA_ERR_ALLOC: return "CPA_ERR_ALLOC";
+        case CPA_ERR_HIP: return "CPA_ERR_HIP";
+        case CPA_ERR_NONFINITE: return "CPA_ERR_NONFINITE";
+        case CPA_ERR_BOUND: return "CPA_ERR_BOUND";
+        case CPA_ERR_UNSUPPORTED: return "CPA_ERR_UNSUPPORTED";
+    }
+    return "CPA_ERR_UNKNOWN";
+}
+
+const char* cpa_last_error(void) { return g_err; }
+
+void cpa_default_opts(cpa_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->K = 16;
+    o->bound = CPA_BOUND_POWER;
+    o->Lambda = 0.0;
+    o->power_iters = 100;
+    o->warm_start = 0;
+    o->power_tol = 1e-7;
+    o->margin = 0.01;
+    o->seed = 0;
+    o->check = 0;
+    o->precision = CPA_PREC_FP32;
+    o->growth_tol = 1e-3;
+}
+
+cpa_status cpa_chebyshev_coeffs(const cpa_shrinkage* shrink, double Lambda, int K, double* c_host) {
+    cpa_status s = check_shrinkage(shrink);
+    if (s != CPA_OK) return s;
+    if (!c_host) return fail(CPA_ERR_ARG, "c_host is NULL");
+    if (K < 1 || K > kMaxK) return fail(CPA_ERR_ARG, "K must be in [1, %d]", kMaxK);
+    if (!(std::isfinite(Lambda) && Lambda >= 0.0)) return fail(CPA_ERR_ARG, "Lambda must be finite and >= 0");
+    const ShrinkParams p = to_params(shrink);
+    for (int k = 0; k < K; ++k) c_host[k] = cheb_coeff(p, Lambda, K, k);
+    return CPA_OK;
+}
+
+cpa_status cpa_spectral_bound(cpa_ctx* ctx, void* stream, int m, int n, const float* X_dev, int64_t ldx,
+                              const cpa_opts* opts, double* Lambda_host, cpa_info* info_host) {
+    cpa_status s;
+    if ((s = check_dense_args(ctx, m, n, X_dev, ldx)) != CPA_OK) return s;
+    if ((s = check_opts(opts)) != CPA_OK) return s;
+    if (!Lambda_host) return fail(CPA_ERR_ARG, "Lambda_host is NULL");
+    if (m == 0 || n == 0) {
+        *Lambda_host = 0.0;
+        if (info_host) std::memset(info_host, 0, sizeof(*info_host));
+        return CPA_OK;
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Work w;
+    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    if ((s = ensure_ws(ctx, m, n, opts->K, maxit, false, w)) != CPA_OK) return s;
+    cpa_shrinkage soft0 = {CPA_SOFT, 0, 0.0, 0.0, 0.0, 1.0};
+    if ((s = fill_scalars(st, w)) != CPA_OK) return s;
+    if ((s = enqueue_gram(ctx, st, m, n, X_dev, ldx, w)) != CPA_OK) return s;
+    if ((s = enqueue_bound(ctx, st, std::min(m, n), &soft0, opts, w, -1)) != CPA_OK) return s;
+    cpa_info tmp;
+    if ((s = read_info(st, w, 1, m, n, &tmp, nullptr)) != CPA_OK) return s;
+    *Lambda_host = tmp.Lambda;
+    if (info_host) *info_host = tmp;
+    return CPA_OK;
+}
+
+cpa_status cpa_shrink_dense(cpa_ctx* ctx, void* stream, int m, int n, const float* X_dev, int64_t ldx, float* Y_dev,
+                            int64_t ldy, const cpa_shrinkage* shrink, const cpa_opts* opts, cpa_info* info_host) {
+    cpa_status s;
+    if ((s = check_dense_args(ctx, m, n, X_dev, ldx)) != CPA_OK) return s;
+    if ((s = check_shrinkage(shrink)) != CPA_OK) return s;
+    if ((s = check_opts(opts)) != CPA_OK) return s;
+    if (m == 0 || n == 0) {
+        if (info_host) std::memset(info_host, 0, sizeof(*info_host));
+        return CPA_OK;
+    }
+    if (!Y_dev) return fail(CPA_ERR_ARG, "Y is NULL");
+    if (ldy < n) return fail(CPA_ERR_SHAPE, "ldy %lld < n %d", (long long)ldy, n);
+    const size_t xb = sizeof(float) * ((size_t)(m - 1) * ldx + n);
+    const size_t yb = sizeof(float) * ((size_t)(m - 1) * ldy + n);
+    if (overlaps(X_dev, xb, Y_dev, yb)) return fail(CPA_ERR_ARG, "Y overlaps X");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Work w;
+    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    if ((s = ensure_ws(ctx, m, n, opts->K, maxit, false, w)) != CPA_OK) return s;
+    return shrink_impl(ctx, st, m, n, X_dev, ldx, Y_dev, ldy, shrink, opts, info_host, w);
+}
+
+cpa_status cpa_timing_enable(cpa_ctx* ctx, int enable) {
+    if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
+    ctx->timing = enable ? 1 : 0;
+    for (auto& L : ctx->tlog) L.used = 0;
+    return CPA_OK;
+}
+
+cpa_status cpa_timing_read(cpa_ctx* ctx, int which, double* total_ms_host, int64_t* launches_host) {
+    if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
+    if (which < 0 || which > 1) return fail(CPA_ERR_ARG, "unknown kernel family %d", which);
+    if (!total_ms_host || !launches_host) return fail(CPA_ERR_ARG, "output pointer is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    TimingLog& L = ctx->tlog[which];
+    double tot = 0.0;
+    for (size_t i = 0; i < L.used; ++i) {
+        HIP_TRY(hipEventSynchronize(L.ev[2 * i + 1]));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, L.ev[2 * i], L.ev[2 * i + 1]));
+        tot += ms;
+    }
+    *total_ms_host = tot;
+    *launches_host = (int64_t)L.used;
+    return CPA_OK;
+}
+
+int64_t cpa_rpca_state_floats(int m, int n) {
+    if (m < 0 || n < 0) return 0;
+    return 7 * (int64_t)m * n;
+}
+
+cpa_status cpa_rpca_init(cpa_ctx* ctx, void* stream, int m, int n, float* state_dev) {
+    if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
+    if (m < 0 || n < 0) return fail(CPA_ERR_SHAPE, "negative size");
+    if (m == 0 || n == 0) return CPA_OK;
+    if (!state_dev) return fail(CPA_ERR_ARG, "state is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int64_t total = cpa_rpca_state_floats(m, n);
+    hipLaunchKernelGGL(fill_f32_kernel, dim3(2048), dim3(256), 0, static_cast<hipStream_t>(stream), state_dev, total, 1.f);
+    HIP_TRY(hipGetLastError());
+    ctx->warm_d = -1;
+    return CPA_OK;
+}
+
+cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const float* I_dev, float* state_dev, int iters,
+                            double inv_rho, double eta_over_rho, const cpa_opts* opts, double* Et_dev) {
+    cpa_status s;
+    if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
+    if (m < 0 || n < 0) return fail(CPA_ERR_SHAPE, "negative size");
+    if (iters < 0) return fail(CPA_ERR_ARG, "iters < 0");
+    if ((s = check_opts(opts)) != CPA_OK) return s;
+    if (!(std::isfinite(inv_rho) && inv_rho >= 0.0 && std::isfinite(eta_over_rho) && eta_over_rho >= 0.0))
+        return fail(CPA_ERR_ARG, "inv_rho and eta_over_rho must be finite and >= 0");
+    if (m == 0 || n == 0 || iters == 0) return CPA_OK;
+    if (!I_dev || !state_dev) return fail(CPA_ERR_ARG, "I or state is NULL");
+    const int64_t mn = (int64_t)m * n;
+    if (overlaps(I_dev, sizeof(float) * mn, state_dev, sizeof(float) * 7 * mn))
+        return fail(CPA_ERR_ARG, "I overlaps the state");
+    if (opts->check) return fail(CPA_ERR_UNSUPPORTED, "the growth check is not available inside the ADMM driver");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Work w;
+    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    if ((s = ensure_ws(ctx, m, n, opts->K, maxit, true, w)) != CPA_OK) return s;
+    AdmmPtrs P;
+    P.l = state_dev;
+    P.s = state_dev + mn;
+    P.z1 = state_dev + 2 * mn;
+    P.z2 = state_dev + 3 * mn;
+    P.u1 = state_dev + 4 * mn;
+    P.u2 = state_dev + 5 * mn;
+    P.u3 = state_dev + 6 * mn;
+    P.I = I_dev;
+    P.x = w.x;
+    cpa_shrinkage sh = {CPA_SOFT, 0, inv_rho, 0.0, 0.0, 1.0};
+    const int grid = (int)std::min<int64_t>(2048, (mn + 255) / 256);
+    for (int t = 0; t < iters; ++t) {
+        hipLaunchKernelGGL(fill_f64_kernel, dim3(1), dim3(64), 0, st, w.admm, 16, 0.0);
+        HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(admm_pre_kernel, dim3(grid), dim3(256), 0, st, P, mn, w.admm);
+        HIP_TRY(hipGetLastError());
+        if ((s = shrink_impl(ctx, st, m, n, w.x, n, P.z1, n, &sh, opts, nullptr, w)) != CPA_OK) return s;
+        hipLaunchKernelGGL(admm_post_kernel, dim3(grid), dim3(256), 0, st, P, mn, (float)eta_over_rho,
+                           (const double*)w.admm, Et_dev ? Et_dev + t : nullptr);
+        HIP_TRY(hipGetLastError());
+    }
+    return CPA_OK;
+}
+
+}  // extern "C"

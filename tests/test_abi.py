@@ -1,0 +1,74 @@
+"""The C-ABI library: it builds, loads, exports every symbol include/cpasvt.h
+declares, and its host-only entry points behave (no GPU needed)."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import paper_1705_07112_amd as cpa
+from oracle import chebyshev
+from oracle.shrinkage import Shrinkage
+
+
+def test_library_exports_every_declared_symbol():
+    names = cpa.declared_symbols()
+    assert "cpa_shrink_dense" in names and "cpa_rpca_iterate" in names
+    lib = cpa.lib()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding wraps exactly the declared set
+    assert set(cpa._SIGS) == set(names)
+
+
+def test_status_strings_and_defaults():
+    assert cpa.status_string(0) == "CPA_OK"
+    assert cpa.status_string(6) == "CPA_ERR_BOUND"
+    o = cpa.CpaOpts()
+    cpa.lib().cpa_default_opts(ctypes.byref(o))
+    assert o.K == 16 and o.bound == 0 and o.power_iters == 100
+    assert o.power_tol == 1e-7 and o.margin == 0.01 and o.growth_tol == 1e-3
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(cpa.CpaShrinkage) == 40
+    assert ctypes.sizeof(cpa.CpaOpts) == 64
+    assert ctypes.sizeof(cpa.CpaInfo) == 56
+
+
+@pytest.mark.parametrize("kind,tau", [(0, 1.3), (1, 0.9), (2, 2.0)])
+@pytest.mark.parametrize("K", [1, 2, 5, 16, 30, 64])
+def test_host_coefficients_match_oracle(kind, tau, K):
+    Lam = 9.0
+    got = cpa.chebyshev_coeffs(cpa.CpaShrinkage(kind, 0, tau, 0.0, 0.0, 1.0), Lam, K)
+    ref = chebyshev.coefficients_shifted(Shrinkage(kind, tau), Lam, K)
+    assert np.max(np.abs(got - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+
+
+def test_host_coefficients_weighted_fn_and_edges():
+    sh = cpa.weighted_fn(1.5, 0.4, 1e-3)
+    ref = chebyshev.coefficients_shifted(Shrinkage(3, 0.0, 1.5, 0.4, 1e-3), 7.0, 20)
+    assert np.max(np.abs(cpa.chebyshev_coeffs(sh, 7.0, 20) - ref)) < 1e-13
+    assert np.all(cpa.chebyshev_coeffs(cpa.soft(1.0), 0.0, 8) == 0.0)
+    # tau^2 >= Lambda: every node lies below the threshold
+    assert np.all(cpa.chebyshev_coeffs(cpa.soft(3.0), 9.0, 8) == 0.0)
+
+
+def test_argument_errors_before_any_device_work():
+    lib = cpa.lib()
+    c = (ctypes.c_double * 4)()
+    with pytest.raises(cpa.CpaError) as e:
+        cpa._check(lib.cpa_chebyshev_coeffs(ctypes.byref(cpa.soft(1.0)), 1.0, 0, c))
+    assert e.value.status == 1
+    with pytest.raises(cpa.CpaError):
+        cpa._check(lib.cpa_chebyshev_coeffs(ctypes.byref(cpa.soft(1.0)), float("nan"), 4, c))
+    with pytest.raises(cpa.CpaError):
+        cpa._check(lib.cpa_chebyshev_coeffs(ctypes.byref(cpa.CpaShrinkage(9, 0, 1.0, 0, 0, 1)), 1.0, 4, c))
+    o = cpa.Opts(K=4).to_c()
+    sh = cpa.soft(1.0)
+    # NULL context is rejected without touching the device
+    st = lib.cpa_shrink_dense(None, None, 4, 4, ctypes.c_void_p(16), 4, ctypes.c_void_p(4096), 4,
+                              ctypes.byref(sh), ctypes.byref(o), None)
+    assert st == 1
+    assert b"context" in lib.cpa_last_error()
+    assert lib.cpa_rpca_state_floats(3, 5) == 105

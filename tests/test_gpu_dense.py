@@ -1,0 +1,194 @@
+"""GPU parity of the dense FP32 path against the FP64 oracle (Algorithm 1 with
+T = Id).  Lambda is passed explicitly so parity isolates the polynomial
+evaluation; a separate test compares the device bound with the oracle's.
+Tolerance of the FP32 path: relative Frobenius error <= 1e-5."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import bound as obound
+from oracle import cpa as ocpa
+from oracle import metrics
+from oracle.shrinkage import Shrinkage
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _lib():
+    import paper_1705_07112_amd as cpa
+    return cpa
+
+
+def _gram_lmax(X):
+    G = X.T @ X if X.shape[0] >= X.shape[1] else X @ X.T
+    return float(np.linalg.eigvalsh(G)[-1]) if G.size else 0.0
+
+
+def _run(X64, sh_c, K, Lam, ld=None, offset=0):
+    torch = _torch()
+    cpa = _lib()
+    m, n = X64.shape
+    ld = ld or n
+    buf = torch.zeros(offset + m * ld + 8, dtype=torch.float32)
+    view = buf[offset:offset + m * ld].view(m, ld)[:, :n]
+    view.copy_(torch.from_numpy(X64.astype(np.float32)))
+    bufd = buf.cuda()
+    Xd = bufd[offset:offset + m * ld].view(m, ld)[:, :n]
+    Y, info = cpa.shrink_dense(Xd, sh_c, cpa.Opts(K=K, Lambda=Lam), info=True)
+    torch.cuda.synchronize()
+    return Y.cpu().numpy().astype(np.float64), info
+
+
+def _case(m, n, K, kind, seed, ld=None, offset=0):
+    print(f"case m={m} n={n} K={K} kind={kind} seed={seed} ld={ld} off={offset}", flush=True)
+    X = synth.as_f32_exact(synth.dense_lowrank(m, n, rank=min(4, m, n), noise=0.2, seed=seed))
+    lmax = _gram_lmax(X)
+    Lam = 1.01 * lmax
+    tau = 0.4 * math.sqrt(lmax)
+    cpa = _lib()
+    if kind == 0:
+        sh_o, sh_c = Shrinkage(0, tau), cpa.soft(tau)
+    elif kind == 1:
+        sh_o, sh_c = Shrinkage(1, tau), cpa.hard(tau)
+    else:
+        wc, ws = 0.3 * tau * tau, 0.05 * lmax
+        sh_o, sh_c = Shrinkage(3, 0.0, wc, ws, 1e-3), cpa.weighted_fn(wc, ws, 1e-3)
+    ref = ocpa.cpa_shrink(X, sh_o, Lam, K)
+    got, info = _run(X, sh_c, K, Lam, ld=ld, offset=offset)
+    err = metrics.rel_fro(got, ref, X)
+    print(f"  rel_fro={err:.3e}", flush=True)
+    assert err <= TOL32, (m, n, K, kind, err)
+    assert info["side"] == (0 if m >= n else 1)
+    return err
+
+
+def test_config1_shape_soft():
+    _case(64, 48, 20, 0, synth.BASE_SEED)
+
+
+EDGE = [1, 2, 3, 15, 16, 17, 63, 64, 65, 127, 128, 129]
+
+
+@pytest.mark.parametrize("m", EDGE)
+def test_edge_shapes_tall(m):
+    for n in (1, 3, 16, 17, 65):
+        if n <= m:
+            _case(m, n, 16, 0, 1000 + m * 7 + n)
+
+
+@pytest.mark.parametrize("n", [2, 17, 64, 129])
+def test_edge_shapes_wide(n):
+    for m in (1, 3, 16, 63):
+        if m < n:
+            _case(m, n, 16, 0, 2000 + m * 7 + n)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 16, 30])
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_orders_and_kinds(K, kind):
+    _case(130, 70, K, kind, 3000 + K)
+    _case(70, 130, K, kind, 4000 + K)
+
+
+def test_strided_and_unaligned_input():
+    _case(77, 45, 12, 0, 5001, ld=53)
+    _case(77, 45, 12, 0, 5002, ld=48, offset=1)
+    _case(40, 90, 12, 0, 5003, ld=97, offset=3)
+
+
+def test_multi_tile_ragged_sizes():
+    # several 128-wide tiles plus a ragged tail on both sides
+    _case(1100, 300, 10, 0, 6001)
+    _case(300, 1100, 10, 0, 6002)
+
+
+def test_special_cases():
+    torch = _torch()
+    cpa = _lib()
+    X = synth.as_f32_exact(synth.dense_lowrank(50, 30, rank=3, noise=0.1, seed=7))
+    lmax = _gram_lmax(X)
+    Lam = 1.01 * lmax
+    Xd = torch.from_numpy(X.astype(np.float32)).cuda()
+    # tau = 0: identity
+    Y = cpa.shrink_dense(Xd, cpa.soft(0.0), cpa.Opts(K=9, Lambda=Lam)).cpu().numpy()
+    assert metrics.rel_fro(Y, X) < 1e-5
+    # tau^2 >= Lambda: exact zero
+    Y = cpa.shrink_dense(Xd, cpa.soft(math.sqrt(Lam)), cpa.Opts(K=9, Lambda=Lam)).cpu().numpy()
+    assert np.all(Y == 0.0)
+    # X = 0 with the power bound: Lambda = 0 and Y = 0
+    Z = torch.zeros(20, 10, device="cuda")
+    Y, info = cpa.shrink_dense(Z, cpa.soft(1.0), cpa.Opts(K=5), info=True)
+    assert info["Lambda"] == 0.0 and torch.count_nonzero(Y).item() == 0
+    # empty input: no-op
+    E = torch.zeros(0, 5, device="cuda")
+    assert cpa.shrink_dense(E, cpa.soft(1.0), cpa.Opts(K=5)).shape == (0, 5)
+    # Y aliasing X is rejected
+    with pytest.raises(cpa.CpaError):
+        cpa.shrink_dense(Xd, cpa.soft(1.0), cpa.Opts(K=5), out=Xd)
+    with pytest.raises(cpa.CpaError):
+        cpa.shrink_dense(Xd, cpa.soft(1.0), cpa.Opts(K=0))
+
+
+def test_device_bound_matches_oracle():
+    torch = _torch()
+    cpa = _lib()
+    for seed, (m, n) in enumerate([(64, 48), (200, 120), (90, 300), (1024, 1024)]):
+        X = synth.as_f32_exact(synth.dense_lowrank(m, n, rank=5, noise=0.3, seed=7000 + seed))
+        G = X.T @ X if m >= n else X @ X.T
+        lam_o = obound.power_bound(G, seed=seed, max_iter=200, tol=1e-9)[0]
+        Xd = torch.from_numpy(X.astype(np.float32)).cuda()
+        lam_g, info = cpa.spectral_bound(Xd, cpa.Opts(K=4, power_iters=200, power_tol=1e-9, seed=seed))
+        print(f"bound m={m} n={n} oracle={lam_o:.10g} gpu={lam_g:.10g} iters={info['power_iters_done']}", flush=True)
+        assert abs(lam_g - lam_o) <= 2e-6 * lam_o
+        assert lam_g >= float(np.linalg.eigvalsh(G)[-1]) * (1 - 1e-6)
+
+
+def test_growth_check_falls_back_to_frobenius_bound():
+    torch = _torch()
+    cpa = _lib()
+    X = synth.as_f32_exact(synth.dense_lowrank(96, 64, rank=4, noise=0.1, seed=8))
+    G = X.T @ X
+    lmax = float(np.linalg.eigvalsh(G)[-1])
+    tau = 0.3 * math.sqrt(lmax)
+    Xd = torch.from_numpy(X.astype(np.float32)).cuda()
+    Y, info = cpa.shrink_dense(Xd, cpa.soft(tau), cpa.Opts(K=20, Lambda=0.6 * lmax, check=True), info=True)
+    assert info["fallback"] == 1
+    fro = math.sqrt(float(np.sum(G * G)))
+    assert info["Lambda"] == pytest.approx(fro, rel=1e-5)
+    ref = ocpa.cpa_shrink(X, Shrinkage(0, tau), info["Lambda"], 20)
+    assert metrics.rel_fro(Y.cpu().numpy(), ref) < TOL32
+    # a sound bound passes the check without fallback
+    _, info = cpa.shrink_dense(Xd, cpa.soft(tau), cpa.Opts(K=20, check=True), info=True)
+    assert info["fallback"] == 0 and info["max_growth"] <= 1.0 + 1e-3
+
+
+def test_full_size_rpca_matrix_sampled_rows():
+    """1024 x 1024, K = 30, the shrink of the ADMM workload (tau = 1/rho = 10),
+    checked on sampled output rows (rows of X H depend only on those rows of X)."""
+    torch = _torch()
+    cpa = _lib()
+    I, _, _ = synth.rpca_frames()
+    X = I.astype(np.float64)
+    G = X.T @ X
+    lam_o = obound.power_bound(G, seed=0)[0]
+    K, tau = 30, 10.0
+    Xd = torch.from_numpy(I).cuda()
+    Y = cpa.shrink_dense(Xd, cpa.soft(tau), cpa.Opts(K=K, Lambda=lam_o)).cpu().numpy()
+    rows = np.array([0, 1, 2, 63, 64, 65, 511, 512, 777, 1000, 1022, 1023])
+    ref = ocpa.cpa_rows(X, Shrinkage(0, tau), lam_o, K, rows)
+    err = metrics.rel_fro(Y[rows].astype(np.float64), ref)
+    print(f"full-size sampled rows rel_fro={err:.3e}", flush=True)
+    assert err <= TOL32
+    # the power bound path on the device agrees with the oracle's bound
+    lam_g, _ = cpa.spectral_bound(Xd, cpa.Opts(K=K))
+    assert abs(lam_g - lam_o) <= 2e-6 * lam_o
