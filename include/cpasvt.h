@@ -163,8 +163,10 @@ cpa_status cpa_shrink_dense(cpa_ctx* ctx, void* stream, int m, int n,
  * State: state_dev holds cpa_rpca_state_floats(m, n) floats laid out as seven
  * consecutive m x n row-major blocks [l, s, z1, z2, u1, u2, u3] (z3 = I is not
  * stored).  After any number of iterations L = block 0 and S = block 1.
- * cpa_rpca_init writes the start l = s = u1 = u2 = u3 = 1 and z1 = z2 = 1
- * (z = K [l; s]; the paper leaves z_0 unstated).
+ * cpa_rpca_init writes the start l = s = u1 = u2 = u3 = 1 and z1 = z2 = 1; the
+ * third block of z is I from the start (the paper leaves z_0 unstated; z_0 =
+ * [l_0; s_0; I] is the reading used, since that block is the projection onto
+ * the observed data at every iteration).
  * cpa_rpca_iterate runs `iters` iterations from the given state; the spectral
  * bound of each shrink uses opts (power iteration warm-started across
  * iterations when opts->warm_start == 1).  Et_dev (device, `iters` doubles, may

@@ -13,8 +13,10 @@ K = [[Id, O], [O, Id], [Id, Id]]:
   z3 = Pi_I(l + s + u3) = I            (every pixel observed)
   u  = u + K l' - z
   E_t = ||l_{t+1} - l_t||_2 / ||l_{t+1}||_2   (stopping quantity, Sec. V-B.2)
-Initialisation: l_0 = s_0 = u_0 = all ones (Sec. V-D); z_0 = K [l_0; s_0]
-(the paper leaves z_0 unstated; this reading makes the first l-update consistent).
+Initialisation: l_0 = s_0 = u_0 = all ones (Sec. V-D).  The paper leaves z_0
+unstated; the reading here is z_0 = [l_0; s_0; I]: the first two blocks equal
+K [l_0; s_0], and the third block is the projection onto the observed data,
+which is I at every iteration, so it starts at I as well.
 The spectral bound of each shrink is a power-iteration bound warm-started from
 the previous iteration's vector.
 
@@ -61,7 +63,7 @@ def rpca_admm(I, inv_rho: float, eta_over_rho: float, iters: int, K: int,
     ones = np.ones_like(I)
     l, s = ones.copy(), ones.copy()
     u1, u2, u3 = ones.copy(), ones.copy(), ones.copy()
-    z1, z2, z3 = l.copy(), s.copy(), l + s
+    z1, z2, z3 = l.copy(), s.copy(), I
     v = None
     E = []
     lams = []
