@@ -77,7 +77,7 @@ typedef struct {
  *                        2u - 1, u = (SplitMix64(seed + (i+1)*0x9E3779B97F4A7C15) >> 11) * 2^-53;
  *                        w = Gram v, mu = v.w, stop when |mu_t - mu_{t-1}| <= power_tol * mu_t
  *                        or after power_iters products; ||r|| = sqrt(max(||w||^2 - mu^2, 0));
- *                        Lambda = min(mu + max(margin * mu, ||r||), ||Gram||_F)
+ *                        Lambda = min(mu + max(margin * mu, ||r||), (1 + margin) ||Gram||_F)
  *   CPA_BOUND_GIVEN      Lambda = opts.Lambda (must be >= 0 and finite)
  *   CPA_BOUND_FROBENIUS  Lambda = ||Gram||_F (always an upper bound) */
 typedef enum { CPA_BOUND_POWER = 0, CPA_BOUND_GIVEN = 1, CPA_BOUND_FROBENIUS = 2 } cpa_bound_rule;

@@ -13,8 +13,11 @@ Reading (documented as a project choice):
     |mu_t - mu_{t-1}| <= tol * mu_t (t >= 2) or after max_iter products;
     otherwise v <- w / ||w||;
   * residual norm ||r|| = sqrt(max(||w||^2 - mu^2, 0)) for the last (v, w, mu);
-  * Lambda = min(mu + max(delta * mu, ||r||), ||Phi||_F);  ||Phi||_F is always
-    an upper bound of lambda_max for a PSD matrix;
+  * Lambda = min(mu + max(delta * mu, ||r||), (1 + delta) ||Phi||_F).
+    ||Phi||_F >= lambda_max for a PSD matrix, so the cap never cuts below the
+    largest eigenvalue, and it keeps the relative margin: a bound equal to
+    lambda_max would put the top eigenvalue on the endpoint of [-1, 1], where
+    T_k has slope k^2 and rounding is amplified about K^2-fold;
   * ||Phi||_F == 0 gives Lambda = 0; a vanishing product (w == 0 while
     ||Phi||_F > 0) gives Lambda = ||Phi||_F.
 
@@ -79,5 +82,5 @@ def power_bound(Phi: np.ndarray, seed: int = 0, max_iter: int = 100, tol: float 
         if it < max_iter:
             v = w / math.sqrt(wn2)
     resid = math.sqrt(max(wn2 - mu * mu, 0.0))
-    Lam = min(mu + max(delta * mu, resid), fro)
+    Lam = min(mu + max(delta * mu, resid), (1.0 + delta) * fro)
     return Lam, mu, resid, it, v

@@ -52,43 +52,49 @@ def admm_lsolve(z1, z2, z3, u1, u2, u3):
     return (2.0 * a - b) / 3.0, (2.0 * b - a) / 3.0
 
 
-def rpca_admm(I, inv_rho: float, eta_over_rho: float, iters: int, K: int,
-              seed: int = 0, power_iters: int = 100, warm_power_iters: int = 100,
-              tol_power: float = 1e-7, delta: float = 0.01, record=None):
-    """Runs ``iters`` ADMM iterations; returns (l, s, E_hist, Lambda_hist).
-
-    ``record`` (optional list) receives (t, shrink_input, Lambda) per iteration
-    so tests can check single shrinks on identical inputs."""
+def rpca_step(state, I, inv_rho: float, eta_over_rho: float, K: int, v=None, seed: int = 0,
+              power_iters: int = 100, tol_power: float = 1e-7, delta: float = 0.01):
+    """One ADMM iteration from ``state`` = dict(l, s, z1, z2, u1, u2, u3) (z3 = I).
+    Returns (new_state, info) with info = dict(x, Lambda, v, E)."""
     I = np.asarray(I, dtype=np.float64)
-    ones = np.ones_like(I)
-    l, s = ones.copy(), ones.copy()
-    u1, u2, u3 = ones.copy(), ones.copy(), ones.copy()
-    z1, z2, z3 = l.copy(), s.copy(), I
+    l_new, s_new = admm_lsolve(state["z1"], state["z2"], I, state["u1"], state["u2"], state["u3"])
+    x = l_new + state["u1"]
+    Phi, _ = cpa.gram(x)
+    Lam, _, _, _, v = bound.power_bound(Phi, seed=seed, max_iter=power_iters, tol=tol_power, delta=delta, v0=v)
+    z1 = cpa.cpa_shrink(x, soft(inv_rho), Lam, K)
+    z2 = soft_elementwise(s_new + state["u2"], eta_over_rho)
+    new = {
+        "l": l_new, "s": s_new, "z1": z1, "z2": z2,
+        "u1": state["u1"] + l_new - z1,
+        "u2": state["u2"] + s_new - z2,
+        "u3": state["u3"] + l_new + s_new - I,
+    }
+    num = math.sqrt(float(np.sum((l_new - state["l"]) ** 2)))
+    den = math.sqrt(float(np.sum(l_new ** 2)))
+    return new, {"x": x, "Lambda": Lam, "v": v, "E": (num / den if den > 0 else 0.0)}
+
+
+def rpca_start(I):
+    """l_0 = s_0 = u_0 = 1, z_0 = [l_0; s_0; I] (z3 = I is implicit)."""
+    ones = np.ones(np.shape(I))
+    return {k: ones.copy() for k in ("l", "s", "z1", "z2", "u1", "u2", "u3")}
+
+
+def rpca_admm(I, inv_rho: float, eta_over_rho: float, iters: int, K: int,
+              seed: int = 0, power_iters: int = 100, tol_power: float = 1e-7, delta: float = 0.01):
+    """Runs ``iters`` ADMM iterations from the start state; returns
+    (l, s, E_hist, Lambda_hist).  The power-iteration bound of each shrink is
+    warm-started from the previous iteration's vector."""
+    state = rpca_start(I)
     v = None
-    E = []
-    lams = []
-    sh = soft(inv_rho)
-    for t in range(iters):
-        l_new, s_new = admm_lsolve(z1, z2, z3, u1, u2, u3)
-        x = l_new + u1
-        Phi, _ = cpa.gram(x)
-        Lam, _, _, _, v = bound.power_bound(
-            Phi, seed=seed, max_iter=(power_iters if v is None else warm_power_iters),
-            tol=tol_power, delta=delta, v0=v)
-        if record is not None:
-            record.append((t, x.copy(), Lam))
-        z1 = cpa.cpa_shrink(x, sh, Lam, K)
-        z2 = soft_elementwise(s_new + u2, eta_over_rho)
-        z3 = I
-        u1 = u1 + l_new - z1
-        u2 = u2 + s_new - z2
-        u3 = u3 + l_new + s_new - z3
-        num = math.sqrt(float(np.sum((l_new - l) ** 2)))
-        den = math.sqrt(float(np.sum(l_new ** 2)))
-        E.append(num / den if den > 0 else 0.0)
-        lams.append(Lam)
-        l, s = l_new, s_new
-    return l, s, E, lams
+    E, lams = [], []
+    for _ in range(iters):
+        state, info = rpca_step(state, I, inv_rho, eta_over_rho, K, v=v, seed=seed,
+                                power_iters=power_iters, tol_power=tol_power, delta=delta)
+        v = info["v"]
+        E.append(info["E"])
+        lams.append(info["Lambda"])
+    return state["l"], state["s"], E, lams
 
 
 def svt_complete(m, n, rows, cols, vals, tau: float, step: float, iters: int, K: int,

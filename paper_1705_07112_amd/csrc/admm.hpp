@@ -3,8 +3,9 @@
 // onto the observed data and the dual update, with the stopping quantity
 // E_t = ||l_{t+1} - l_t|| / ||l_{t+1}|| (Sec. V-B.2) reduced in FP64.
 // Arrays are contiguous m*n float blocks processed by grid-stride loops
-// (consecutive lanes touch consecutive elements).  The two E_t sums live in a
-// small scalar area of their own (index SC_ET_NUM / SC_ET_DEN).
+// (consecutive lanes touch consecutive elements).  The two E_t sums are
+// per-workgroup partials (part[2 * block], part[2 * block + 1]) added in a fixed
+// order by the first workgroup of the post kernel.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -41,7 +42,7 @@ __device__ inline void admm_pre_elem(const AdmmPtrs& P, int64_t e, double& dn, d
 }
 
 // l, s <- (K^T K)^{-1} K^T (z - u); x <- l + u1; E_t partial sums.
-__global__ void __launch_bounds__(256) admm_pre_kernel(AdmmPtrs P, int64_t total, double* scal) {
+__global__ void __launch_bounds__(256) admm_pre_kernel(AdmmPtrs P, int64_t total, double* part) {
     __shared__ double red[8];
     double dn = 0.0, dd = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -50,15 +51,16 @@ __global__ void __launch_bounds__(256) admm_pre_kernel(AdmmPtrs P, int64_t total
     dn = block_sum(dn, red);
     dd = block_sum(dd, red);
     if (threadIdx.x == 0) {
-        if (dn != 0.0) atomicAdd(scal + SC_ET_NUM, dn);
-        if (dd != 0.0) atomicAdd(scal + SC_ET_DEN, dd);
+        part[2 * blockIdx.x] = dn;
+        part[2 * blockIdx.x + 1] = dd;
     }
 }
 
 // z1 already holds the shrink of x.  z2 = soft(s + u2); u1 += l - z1; u2 += s - z2;
 // u3 += l + s - I.  The first workgroup also stores E_t (the pre kernel completed).
-__global__ void __launch_bounds__(256) admm_post_kernel(AdmmPtrs P, int64_t total, float t2, const double* scal,
-                                                        double* Et_out) {
+__global__ void __launch_bounds__(256) admm_post_kernel(AdmmPtrs P, int64_t total, float t2, const double* part,
+                                                        int npart, double* Et_out) {
+    __shared__ double red[8];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += stride) {
         const float l = P.l[e], s = P.s[e];
@@ -70,9 +72,15 @@ __global__ void __launch_bounds__(256) admm_post_kernel(AdmmPtrs P, int64_t tota
         P.u2[e] = P.u2[e] + s - z2;
         P.u3[e] = P.u3[e] + l + s - P.I[e];
     }
-    if (Et_out && blockIdx.x == 0 && threadIdx.x == 0) {
-        const double den = scal[SC_ET_DEN];
-        *Et_out = den > 0.0 ? sqrt(scal[SC_ET_NUM] / den) : 0.0;
+    if (Et_out && blockIdx.x == 0) {
+        double num = 0.0, den = 0.0;
+        for (int i = threadIdx.x; i < npart; i += blockDim.x) {
+            num += part[2 * i];
+            den += part[2 * i + 1];
+        }
+        num = block_sum(num, red);
+        den = block_sum(den, red);
+        if (threadIdx.x == 0) *Et_out = den > 0.0 ? sqrt(num / den) : 0.0;
     }
 }
 

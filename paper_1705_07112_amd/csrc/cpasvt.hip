@@ -41,6 +41,7 @@ cpa_status fail(cpa_status s, const char* fmt, ...) {
     } while (0)
 
 constexpr int kMaxPowerIters = 1000;
+constexpr int kAdmmGrid = 2048;   // workgroups of the ADMM elementwise kernels
 constexpr int kMaxK = 4096;
 
 }  // namespace
@@ -61,6 +62,7 @@ struct cpa_ctx {
     double* warm = nullptr;    // warm-start vector for power iteration
     int warm_cap = 0;
     int warm_d = -1;           // length of the stored vector, -1 if none
+    int coop_max = 0;          // co-resident power-iteration workgroups (0: not queried)
 };
 
 namespace {
@@ -89,17 +91,43 @@ struct Work {
     double* w[2];
     double* scal;
     float* x;      // ADMM shrink input
-    double* admm;  // ADMM scalars (E_t sums), separate from the per-shrink block
+    double* admm;  // ADMM E_t partial sums (2 per pre-kernel workgroup)
     ScalarLayout lay;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
+int gram_tile(int d) {
+    const int64_t tiles128 = (int64_t)((d + 127) / 128) * ((d + 127) / 128);
+    return tiles128 >= 512 ? 128 : 64;
+}
+
+int gram_grid(int d) {
+    const int t = gram_tile(d);
+    return ((d + t - 1) / t) * ((d + t - 1) / t);
+}
+
+// Power-iteration workgroups: about 16 rows each, at most 64 (the grid barrier
+// is one counter; few arrivals keep it cheap), never above what is co-resident.
+int power_grid(cpa_ctx* ctx, int d) {
+    int want = std::max(1, std::min(64, (d + 15) / 16));
+    if (ctx->coop_max > 0) want = std::min(want, ctx->coop_max);
+    return want;
+}
+
 cpa_status ensure_ws(cpa_ctx* ctx, int m, int n, int K, int maxit, bool admm, Work& w) {
     const int d = std::min(m, n);
     const int64_t mn = (int64_t)m * n;
+    if (ctx->coop_max == 0) {
+        int per_cu = 0, cus = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, power_coop_kernel, kPowerThreads, 0));
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        ctx->coop_max = std::max(1, per_cu * cus);
+    }
     w.lay.K = K;
     w.lay.maxit = maxit;
+    w.lay.gwg = gram_grid(d);
+    w.lay.pwg = power_grid(ctx, d);
     size_t off = 0;
     const size_t oG = off; off = align_up(off + sizeof(float) * (size_t)d * d);
     const size_t oY0 = off; off = align_up(off + sizeof(float) * (size_t)mn);
@@ -110,7 +138,7 @@ cpa_status ensure_ws(cpa_ctx* ctx, int m, int n, int K, int maxit, bool admm, Wo
     size_t ox = 0, oa = 0;
     if (admm) {
         ox = off; off = align_up(off + sizeof(float) * (size_t)mn);
-        oa = off; off = align_up(off + sizeof(double) * 16);
+        oa = off; off = align_up(off + sizeof(double) * 2 * kAdmmGrid);
     }
     if (off > ctx->ws_bytes) {
         if (ctx->ws) {
@@ -151,13 +179,23 @@ cpa_status ensure_ws(cpa_ctx* ctx, int m, int n, int K, int maxit, bool admm, Wo
     return CPA_OK;
 }
 
+bool aligned16(const float* p, int64_t ld) {
+    return (ld % 4 == 0) && ((reinterpret_cast<uintptr_t>(p) & 15) == 0);
+}
+
 Operand make_op(const float* p, int64_t ld, int xdim) {
     Operand o;
     o.p = p;
     o.ld = ld;
     o.xdim = xdim;
-    o.vec_ok = (ld % 4 == 0) && ((reinterpret_cast<uintptr_t>(p) & 15) == 0);
     return o;
+}
+
+// 16-byte tile loads need an aligned base, ld % 4 == 0, and a vectorised extent
+// (x for XCONTIG, k for KCONTIG) that is a multiple of 4 and at least 4.
+bool vec_operand(const Operand& o, int layout, int Kd) {
+    const int run = layout == XCONTIG ? o.xdim : Kd;
+    return aligned16(o.p, o.ld) && run % 4 == 0 && run >= 4;
 }
 
 template <int BM, int BN, int LA, int LB, class Epi>
@@ -165,15 +203,20 @@ cpa_status launch_gemm(hipStream_t st, const Operand& A, const Operand& B, int M
                        int sc_a1, int sc_a2, int sc_coef) {
     const int ntm = (M + BM - 1) / BM, ntn = (N + BN - 1) / BN;
     const int grid = ntm * ntn;
-    if (grid <= 0) return CPA_OK;
-    hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, LA, LB, Epi>), dim3(grid), dim3(GTHREADS), 0, st, A, B, M, N, Kd,
-                       epi, sc_a1, sc_a2, sc_coef);
+    if (grid <= 0 || Kd <= 0) return CPA_OK;
+    if (vec_operand(A, LA, Kd) && vec_operand(B, LB, Kd))
+        hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, LA, LB, true, Epi>), dim3(grid), dim3(GTHREADS), 0, st, A, B, M,
+                           N, Kd, epi, sc_a1, sc_a2, sc_coef);
+    else
+        hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, LA, LB, false, Epi>), dim3(grid), dim3(GTHREADS), 0, st, A, B,
+                           M, N, Kd, epi, sc_a1, sc_a2, sc_coef);
     HIP_TRY(hipGetLastError());
     return CPA_OK;
 }
 
 // Tile size choice: 64 x 64 tiles keep >= 256 workgroups in flight from 1024 x 1024
 // outputs; larger outputs take 128 x 128 tiles for more reuse per workgroup.
+// (gram_tile() applies the same rule to size the Gram's partial-sum area.)
 template <int LA, int LB, class Epi>
 cpa_status gemm_dispatch(hipStream_t st, const Operand& A, const Operand& B, int M, int N, int Kd, const Epi& epi,
                          int sc_a1, int sc_a2, int sc_coef) {
@@ -250,8 +293,8 @@ cpa_status enqueue_gram_impl(hipStream_t st, int m, int n, const float* X, int64
     const int d = std::min(m, n);
     epi.C = w.G;
     epi.ldc = d;
-    epi.fro2 = w.scal + SC_FRO2;
-    epi.trace = w.scal + SC_TRACE;
+    epi.part = w.scal + w.lay.gpart();
+    epi.vec_ok = aligned16(w.G, d);
     if (m >= n) {
         // G(i, j) = sum_r X[r][i] X[r][j]
         Operand A = make_op(X, ldx, n), B = make_op(X, ldx, n);
@@ -268,21 +311,26 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
     if (mode_override >= 0) mode = mode_override;
     if (mode == 0) {
         const bool warm = o->warm_start && ctx->warm_d == d;
-        const int gi = std::max(1, std::min(64, (d + 255) / 256));
-        hipLaunchKernelGGL(power_init_kernel, dim3(gi), dim3(256), 0, st, d, (uint64_t)o->seed,
+        hipLaunchKernelGGL(power_init_kernel, dim3(1), dim3(256), 0, st, d, (uint64_t)o->seed,
                            warm ? (const double*)ctx->warm : nullptr, w.w[0], w.scal, w.lay.pw_w2());
         HIP_TRY(hipGetLastError());
-        const int gs = std::max(1, std::min(1024, (d + 3) / 4));
-        for (int t = 1; t <= o->power_iters; ++t) {
-            hipLaunchKernelGGL(power_step_kernel, dim3(gs), dim3(256), 0, st, d, (const float*)w.G, (int64_t)d,
-                               (const double*)w.w[(t - 1) & 1], w.w[t & 1], w.scal, t, o->power_tol,
-                               w.lay.pw_mu(), w.lay.pw_w2());
-            HIP_TRY(hipGetLastError());
-        }
+        int d_ = d, maxit_ = o->power_iters, pw_mu = w.lay.pw_mu(), pw_w2 = w.lay.pw_w2();
+        const float* G = w.G;
+        int64_t ldg = d;
+        double* wb0 = w.w[0];
+        double* wb1 = w.w[1];
+        double* part = w.scal + w.lay.ppart();
+        unsigned* counter = reinterpret_cast<unsigned*>(w.scal + SC_BARRIER);
+        double* scal = w.scal;
+        double tol = o->power_tol;
+        void* args[] = {&d_, &G, &ldg, &wb0, &wb1, &part, &counter, &scal, &maxit_, &tol, &pw_mu, &pw_w2};
+        HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(power_coop_kernel), dim3(w.lay.pwg),
+                                           dim3(kPowerThreads), args, 0, st));
     }
     hipLaunchKernelGGL(finish_bound_kernel, dim3(1), dim3(256), 0, st, mode, o->Lambda, d, o->power_iters, o->margin,
                        (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? ctx->warm : nullptr, w.scal,
-                       to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2());
+                       to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)(w.scal + w.lay.gpart()),
+                       w.lay.gwg);
     HIP_TRY(hipGetLastError());
     if (mode == 0) ctx->warm_d = d;
     return CPA_OK;
@@ -290,7 +338,7 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
 
 // K-1 recurrence steps (or the K == 1 scaling), accumulating into Y.
 cpa_status enqueue_recurrence(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* X, int64_t ldx, float* Y, int64_t ldy,
-                              int K, const Work& w) {
+                              int K, const Work& w, bool norms_needed) {
     if (K == 1) {
         const int64_t total = (int64_t)m * n;
         const int grid = (int)std::min<int64_t>(4096, (total + 255) / 256);
@@ -318,7 +366,8 @@ cpa_status enqueue_recurrence(cpa_ctx* ctx, hipStream_t st, int m, int n, const 
         epi.scal = w.scal;
         epi.step = k;
         epi.last = (k + 1 == K - 1) ? 1 : 0;
-        epi.nrm2 = w.scal + norms + k + 1;
+        epi.nrm2 = norms_needed ? w.scal + norms + (k + 1) * kNormSlots : nullptr;
+        epi.vec_ok = aligned16(yk, ldk) && aligned16(yp, ldp) && aligned16(epi.Ydst, n) && aligned16(Y, ldy);
         hipEvent_t ea, eb;
         cpa_status s = timing_pair(ctx, 0, ea, eb);
         if (s != CPA_OK) return s;
@@ -345,7 +394,9 @@ cpa_status read_info(hipStream_t st, const Work& w, int K, int m, int n, cpa_inf
     double g = 0.0;
     const double x2 = h[SC_TRACE];
     for (int k = 1; k < K; ++k) {
-        const double r = x2 > 0.0 ? std::sqrt(h[w.lay.norms() + k] / x2) : 0.0;
+        double nk = 0.0;
+        for (int q = 0; q < kNormSlots; ++q) nk += h[w.lay.norms() + k * kNormSlots + q];
+        const double r = x2 > 0.0 ? std::sqrt(nk / x2) : 0.0;
         g = std::max(g, r);
     }
     if (growth_out) *growth_out = g;
@@ -360,6 +411,7 @@ cpa_status read_info(hipStream_t st, const Work& w, int K, int m, int n, cpa_inf
         info->side = m >= n ? 0 : 1;
         info->reserved = 0;
     }
+    if (h[SC_TIMEOUT] != 0.0) return fail(CPA_ERR_HIP, "power iteration grid barrier timed out");
     if (!std::isfinite(h[SC_LAMBDA])) return fail(CPA_ERR_NONFINITE, "spectral bound is not finite");
     return CPA_OK;
 }
@@ -371,7 +423,7 @@ cpa_status shrink_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* 
     if ((s = fill_scalars(st, w)) != CPA_OK) return s;
     if ((s = enqueue_gram(ctx, st, m, n, X, ldx, w)) != CPA_OK) return s;
     if ((s = enqueue_bound(ctx, st, d, sh, o, w, -1)) != CPA_OK) return s;
-    if ((s = enqueue_recurrence(ctx, st, m, n, X, ldx, Y, ldy, o->K, w)) != CPA_OK) return s;
+    if ((s = enqueue_recurrence(ctx, st, m, n, X, ldx, Y, ldy, o->K, w, info != nullptr || o->check)) != CPA_OK) return s;
     if (!info && !o->check) return CPA_OK;
     double growth = 0.0;
     if ((s = read_info(st, w, o->K, m, n, info, &growth)) != CPA_OK) return s;
@@ -380,7 +432,7 @@ cpa_status shrink_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* 
         if ((s = fill_scalars(st, w)) != CPA_OK) return s;
         if ((s = enqueue_gram(ctx, st, m, n, X, ldx, w)) != CPA_OK) return s;
         if ((s = enqueue_bound(ctx, st, d, sh, o, w, 2)) != CPA_OK) return s;
-        if ((s = enqueue_recurrence(ctx, st, m, n, X, ldx, Y, ldy, o->K, w)) != CPA_OK) return s;
+        if ((s = enqueue_recurrence(ctx, st, m, n, X, ldx, Y, ldy, o->K, w, info != nullptr || o->check)) != CPA_OK) return s;
         if ((s = read_info(st, w, o->K, m, n, info, &growth)) != CPA_OK) return s;
         if (info) info->fallback = 1;
         if (growth > 1.0 + o->growth_tol)
@@ -597,15 +649,13 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
     P.I = I_dev;
     P.x = w.x;
     cpa_shrinkage sh = {CPA_SOFT, 0, inv_rho, 0.0, 0.0, 1.0};
-    const int grid = (int)std::min<int64_t>(2048, (mn + 255) / 256);
+    const int grid = (int)std::min<int64_t>(kAdmmGrid, (mn + 255) / 256);
     for (int t = 0; t < iters; ++t) {
-        hipLaunchKernelGGL(fill_f64_kernel, dim3(1), dim3(64), 0, st, w.admm, 16, 0.0);
-        HIP_TRY(hipGetLastError());
         hipLaunchKernelGGL(admm_pre_kernel, dim3(grid), dim3(256), 0, st, P, mn, w.admm);
         HIP_TRY(hipGetLastError());
         if ((s = shrink_impl(ctx, st, m, n, w.x, n, P.z1, n, &sh, opts, nullptr, w)) != CPA_OK) return s;
         hipLaunchKernelGGL(admm_post_kernel, dim3(grid), dim3(256), 0, st, P, mn, (float)eta_over_rho,
-                           (const double*)w.admm, Et_dev ? Et_dev + t : nullptr);
+                           (const double*)w.admm, grid, Et_dev ? Et_dev + t : nullptr);
         HIP_TRY(hipGetLastError());
     }
     return CPA_OK;

@@ -12,26 +12,40 @@
 // transposition.  The MFMA fragment reader adapts to the LDS layout instead:
 // v_mfma_f32_16x16x4f32 takes A(i = lane%16, k = lane/16) and
 // B(k = lane/16, j = lane%16); the contraction index seen by lane group
-// g = lane/16 at sub-step kk is mapped to tile column k = 4 g + kk for both
+// g = lane/16 at sub-step kk is mapped to tile column k = 8 g + kk for both
 // operands (any bijection is valid as long as A and B agree).  With that map a
-// KCONTIG LDS row yields the four sub-steps of a lane in one 16-byte read.
+// KCONTIG LDS row yields eight sub-steps of a lane in two 16-byte reads.
 //
-// Workgroup: 256 threads = 4 waves in a 2 x 2 arrangement; each wave owns a
-// (BM/2) x (BN/2) sub-tile made of 16 x 16 MFMA blocks.  K-tiles of 16 are
-// double-buffered in LDS with register prefetch of the next tile.
-#pragma once
-
-#include <hip/hip_runtime.h>
-#include <stdint.h>
-
+// Pipeline: K-tiles of 64, LDS double buffer, and global loads issued two
+// tiles ahead into registers, so each load has two tiles of MFMA work to land.
+// Workgroup: 8 waves (two per SIMD) in a 2 x 4 arrangement; each wave owns a
+// (BM/2) x (BN/4) sub-tile of 16 x 16 MFMA blocks.
+//
+// Accuracy: each K-tile is accumulated into a fresh partial sum that is then
+// added to the running sum with an FP32 add, instead of chaining all Kd
+// products through one accumulator.  Chaining 1024 positive products grows the
+// rounding error several-fold; the two-level sum keeps the 1024^3 recurrence
+// inside the FP32 tolerance.  Two partial sets alternate so the add of tile t
+// waits on MFMAs issued a whole tile earlier.
 namespace cpa {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 enum Layout { XCONTIG = 0, KCONTIG = 1 };
 
-constexpr int GBK = 16;          // K-tile depth
-constexpr int GTHREADS = 256;    // threads per workgroup
+#ifndef CPA_GEMM_BK
+#define CPA_GEMM_BK 64
+#endif
+constexpr int GBK = CPA_GEMM_BK; // K-tile depth
+
+// Keeps the compiler's scheduler from sinking the next tiles' global loads below
+// the MFMA block that is meant to hide their latency.
+#ifndef CPA_SCHED_FENCE
+#define CPA_SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
+#endif
+constexpr int GWAVES = 8;        // waves per workgroup (2 x 4)
+constexpr int GTHREADS = 64 * GWAVES;
+constexpr int KG = GBK / 4;      // sub-steps per lane group and K-tile
 
 template <int BX, int L>
 struct TileGeom {
@@ -49,51 +63,55 @@ struct Operand {
     const float* p;
     int64_t ld;
     int xdim;     // M for A, N for B
-    bool vec_ok;  // ld % 4 == 0 and p 16-byte aligned
 };
 
-// Loads the float4 vectors of one tile (x0.., k0..) into registers, zero outside bounds.
-template <int BX, int L>
+// Loads the float4 groups of one tile (x0.., k0..) into registers; elements
+// outside the matrix read as zero.  The instruction stream is the same for
+// every tile: out-of-range groups load from a clamped in-range address and are
+// zeroed by a select, so the K loop has no branches and the compiler can keep
+// the next tiles' loads in flight across the LDS stores.
+//   VEC: 16-byte loads; requires ld % 4 == 0, a 16-byte aligned base, and the
+//        vectorised extent (xdim for XCONTIG, Kd for KCONTIG) % 4 == 0 and >= 4.
+//   otherwise: four 4-byte loads per group with per-element clamping.
+template <int BX, int L, bool VEC>
 __device__ inline void tile_load(const Operand& op, int x0, int k0, int Kd, f32x4 (&r)[TileGeom<BX, L>::per_thread]) {
 #pragma unroll
     for (int q = 0; q < TileGeom<BX, L>::per_thread; ++q) {
         const int f = threadIdx.x + q * GTHREADS;
-        int x, k;
+        int gx, gk;
         if (L == XCONTIG) {
-            k = f / (BX / 4);
-            x = (f % (BX / 4)) * 4;
+            gk = k0 + f / (BX / 4);
+            gx = x0 + (f % (BX / 4)) * 4;
         } else {
-            x = f / (GBK / 4);
-            k = (f % (GBK / 4)) * 4;
+            gx = x0 + f / (GBK / 4);
+            gk = k0 + (f % (GBK / 4)) * 4;
         }
-        const int gx = x0 + x, gk = k0 + k;
-        f32x4 v = {0.f, 0.f, 0.f, 0.f};
-        if (L == XCONTIG) {
-            if (gk < Kd) {
-                const float* src = op.p + (int64_t)gk * op.ld + gx;
-                if (op.vec_ok && gx + 3 < op.xdim) {
-                    v = *reinterpret_cast<const f32x4*>(src);
-                } else {
-                    if (gx + 0 < op.xdim) v[0] = src[0];
-                    if (gx + 1 < op.xdim) v[1] = src[1];
-                    if (gx + 2 < op.xdim) v[2] = src[2];
-                    if (gx + 3 < op.xdim) v[3] = src[3];
-                }
-            }
+        // L == XCONTIG: the group runs along x; KCONTIG: along k
+        const int lim_run = (L == XCONTIG) ? op.xdim : Kd;
+        const int lim_fix = (L == XCONTIG) ? Kd : op.xdim;
+        const int run = (L == XCONTIG) ? gx : gk;
+        const int fix = (L == XCONTIG) ? gk : gx;
+        const int fixc = fix < lim_fix ? fix : lim_fix - 1;
+        const bool fix_ok = fix < lim_fix;
+        if (VEC) {
+            const bool ok = fix_ok && run < lim_run;
+            const int runc = ok ? run : lim_run - 4;
+            const float* src = (L == XCONTIG) ? op.p + (int64_t)fixc * op.ld + runc
+                                              : op.p + (int64_t)fixc * op.ld + runc;
+            const f32x4 v = *reinterpret_cast<const f32x4*>(src);
+            const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+            r[q] = ok ? v : z;
         } else {
-            if (gx < op.xdim) {
-                const float* src = op.p + (int64_t)gx * op.ld + gk;
-                if (op.vec_ok && gk + 3 < Kd) {
-                    v = *reinterpret_cast<const f32x4*>(src);
-                } else {
-                    if (gk + 0 < Kd) v[0] = src[0];
-                    if (gk + 1 < Kd) v[1] = src[1];
-                    if (gk + 2 < Kd) v[2] = src[2];
-                    if (gk + 3 < Kd) v[3] = src[3];
-                }
+            f32x4 v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const bool ok = fix_ok && run + e < lim_run;
+                const int rc = (run + e < lim_run) ? run + e : lim_run - 1;
+                const float t = op.p[(int64_t)fixc * op.ld + rc];
+                v[e] = ok ? t : 0.f;
             }
+            r[q] = v;
         }
-        r[q] = v;
     }
 }
 
@@ -112,21 +130,25 @@ __device__ inline void tile_store(float* lds, const f32x4 (&r)[TileGeom<BX, L>::
     }
 }
 
-// The four sub-step operands of one lane for the 16-row block starting at xb.
+// The KG sub-step operands of one lane for the 16-row block starting at xb.
 template <int BX, int L>
-__device__ inline f32x4 frag_read(const float* lds, int xb, int lane) {
+__device__ inline void frag_read(const float* lds, int xb, int lane, float (&v)[KG]) {
     const int xi = xb + (lane & 15);
     const int g = lane >> 4;
     if (L == XCONTIG) {
         constexpr int P = TileGeom<BX, L>::pitch;
-        f32x4 v;
-        v[0] = lds[(4 * g + 0) * P + xi];
-        v[1] = lds[(4 * g + 1) * P + xi];
-        v[2] = lds[(4 * g + 2) * P + xi];
-        v[3] = lds[(4 * g + 3) * P + xi];
-        return v;
+#pragma unroll
+        for (int q = 0; q < KG; ++q) v[q] = lds[(KG * g + q) * P + xi];
     } else {
-        return *reinterpret_cast<const f32x4*>(lds + xi * TileGeom<BX, L>::pitch + 4 * g);
+        const float* row = lds + xi * TileGeom<BX, L>::pitch + KG * g;
+#pragma unroll
+        for (int q = 0; q < KG; q += 4) {
+            const f32x4 t = *reinterpret_cast<const f32x4*>(row + q);
+            v[q] = t[0];
+            v[q + 1] = t[1];
+            v[q + 2] = t[2];
+            v[q + 3] = t[3];
+        }
     }
 }
 
@@ -153,37 +175,87 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// Epilogue of the Gram: C = acc, with ||C||_F^2 and trace(C) accumulated in FP64.
+// Sum over the workgroup of two values; the result is valid in thread 0.
+__device__ inline void block_sum2(double& a, double& b) {
+    __shared__ double red[2][GWAVES];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = a;
+        red[1][w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = b = 0.0;
+        for (int i = 0; i < GWAVES; ++i) {
+            a += red[0][i];
+            b += red[1][i];
+        }
+    }
+}
+
+// Epilogues run after the K loop on a tile staged in LDS (row-major, pitch
+// BN + 4), so that every thread handles whole float4 groups of a row: all
+// global loads of a thread are issued before any arithmetic, and each wave
+// reads and writes full 256-byte row segments.  `vec` says whether the
+// operands allow 16-byte accesses (row pitches % 4 == 0, aligned bases, and
+// the group lies inside the matrix); otherwise the group is handled per element.
+
+// Gram: C = acc.  Each workgroup also stores its FP64 partial sums of C(i,j)^2
+// and of the diagonal to part[2 * blockIdx.x] and part[2 * blockIdx.x + 1]; the
+// bound kernel adds them in a fixed order (no atomics: a single address hit by
+// every workgroup serialises in the memory system).
 struct EpiGram {
     float* C;
     int64_t ldc;
-    double* fro2;    // += sum C(i,j)^2
-    double* trace;   // += sum C(i,i)
-    __device__ inline void load_scalars(int, int, int) {}
-    __device__ inline void apply(int i, int j, float v, double& s1, double& s2) const {
-        C[(int64_t)i * ldc + j] = v;
-        s1 += (double)v * v;
-        if (i == j) s2 += v;
-    }
-    __device__ inline void finish(double s1, double s2) const {
-        s1 = wave_sum(s1);
-        s2 = wave_sum(s2);
-        if ((threadIdx.x & 63) == 0) {
-            if (s1 != 0.0) atomicAdd(fro2, s1);
-            if (s2 != 0.0) atomicAdd(trace, s2);
+    double* part;
+    bool vec_ok;
+
+    template <int BM, int BN, int NG>
+    __device__ inline void run(const float* tile, int m0, int n0, int M, int N, const double*, int, int, int) const {
+        constexpr int P = BN + 4, GPR = BN / 4;   // float4 groups per tile row
+        double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+            const int g = threadIdx.x + q * GTHREADS;
+            const int r = g / GPR, c = (g % GPR) * 4;
+            const int i = m0 + r, j = n0 + c;
+            const f32x4 v = *reinterpret_cast<const f32x4*>(tile + r * P + c);
+            if (i >= M) continue;
+            if (vec_ok && j + 3 < N) {
+                *reinterpret_cast<f32x4*>(C + (int64_t)i * ldc + j) = v;
+            } else {
+                for (int e = 0; e < 4; ++e)
+                    if (j + e < N) C[(int64_t)i * ldc + j + e] = v[e];
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (j + e < N) {
+                    s1 += (double)v[e] * v[e];
+                    if (i == j + e) s2 += v[e];
+                }
+            }
+        }
+        block_sum2(s1, s2);
+        if (threadIdx.x == 0) {
+            part[2 * blockIdx.x] = s1;
+            part[2 * blockIdx.x + 1] = s2;
         }
     }
 };
 
-// Epilogue of one recurrence step:
+// One recurrence step:
 //   Ynew = a * acc + b * Yk + c * Yprev
 //   first step:  out = c0/2 * Yk + c1 * Ynew      (Yk = X)
 //   later steps: out += c_{k+1} * Ynew
 //   Ynew is stored to Ydst unless this is the last step (Ydst may equal Yprev:
-//   each element is read and then written by the same lane).
-//   ||Ynew||_F^2 is accumulated for the growth check.
-// Scalars come from device memory so that a bound computed on the device is
-// consumed without a host round trip.
+//   each element is read and then written by the same thread).
+//   ||Ynew||_F^2 is accumulated for the growth check only when nrm2 is set: each
+//   workgroup adds its partial to one of 64 slots (blockIdx % 64), which keeps
+//   the atomics uncontended; the host adds the slots.
+// The scalars are read from device memory, so a bound computed on the device
+// is consumed without a host round trip.
 struct EpiCheb {
     const float* Yk;
     int64_t ldk;
@@ -196,49 +268,141 @@ struct EpiCheb {
     const double* scal;   // scalar block
     int step;             // k: this launch produces Y_{k+1}
     int last;
-    double* nrm2;         // slot for ||Y_{k+1}||^2
-    // resolved per launch
-    float a, b, c, ck1, c0h;
+    double* nrm2;         // 64 slots for ||Y_{k+1}||^2, or nullptr
+    bool vec_ok;
 
-    __device__ inline void load_scalars(int sc_a1, int sc_a2, int sc_coef) {
+    template <int BM, int BN, int NG>
+    __device__ inline void run(const float* tile, int m0, int n0, int M, int N, const double* sc, int sc_a1,
+                               int sc_a2, int sc_coef) const {
+        constexpr int P = BN + 4, GPR = BN / 4;
+        float a, b, c, c0h;
         if (step == 0) {
-            a = (float)scal[sc_a1];
+            a = (float)sc[sc_a1];
             b = -1.f;
             c = 0.f;
-            c0h = (float)(0.5 * scal[sc_coef + 0]);
+            c0h = (float)(0.5 * sc[sc_coef]);
         } else {
-            a = (float)scal[sc_a2];
+            a = (float)sc[sc_a2];
             b = -2.f;
             c = -1.f;
             c0h = 0.f;
         }
-        ck1 = (float)scal[sc_coef + step + 1];
-    }
-    __device__ inline void apply(int i, int j, float v, double& s1, double&) const {
-        const float yk = Yk[(int64_t)i * ldk + j];
-        float yn = a * v + b * yk;
-        if (step > 0) yn += c * Yprev[(int64_t)i * ldp + j];
-        float* o = out + (int64_t)i * ldo + j;
-        if (step == 0)
-            *o = c0h * yk + ck1 * yn;
-        else
-            *o += ck1 * yn;
-        if (!last) Ydst[(int64_t)i * ldd + j] = yn;
-        s1 += (double)yn * yn;
-    }
-    __device__ inline void finish(double s1, double) const {
-        s1 = wave_sum(s1);
-        if ((threadIdx.x & 63) == 0 && s1 != 0.0) atomicAdd(nrm2, s1);
+        const float ck1 = (float)sc[sc_coef + step + 1];
+        f32x4 vk[NG], vp[NG], vo[NG];
+        bool full[NG];
+        // issue every load first
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+            const int g = threadIdx.x + q * GTHREADS;
+            const int i = m0 + g / GPR, j = n0 + (g % GPR) * 4;
+            full[q] = vec_ok && i < M && j + 3 < N;
+            vk[q] = vp[q] = vo[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            if (full[q]) {
+                vk[q] = *reinterpret_cast<const f32x4*>(Yk + (int64_t)i * ldk + j);
+                if (step > 0) {
+                    vp[q] = *reinterpret_cast<const f32x4*>(Yprev + (int64_t)i * ldp + j);
+                    vo[q] = *reinterpret_cast<const f32x4*>(out + (int64_t)i * ldo + j);
+                }
+            } else if (i < M) {
+                for (int e = 0; e < 4; ++e) {
+                    if (j + e < N) {
+                        vk[q][e] = Yk[(int64_t)i * ldk + j + e];
+                        if (step > 0) {
+                            vp[q][e] = Yprev[(int64_t)i * ldp + j + e];
+                            vo[q][e] = out[(int64_t)i * ldo + j + e];
+                        }
+                    }
+                }
+            }
+        }
+        double s1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+            const int g = threadIdx.x + q * GTHREADS;
+            const int r = g / GPR, cc = (g % GPR) * 4;
+            const int i = m0 + r, j = n0 + cc;
+            const f32x4 acc = *reinterpret_cast<const f32x4*>(tile + r * P + cc);
+            f32x4 yn, o;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float y = a * acc[e] + b * vk[q][e];
+                if (step > 0) y += c * vp[q][e];
+                yn[e] = y;
+                o[e] = (step == 0) ? c0h * vk[q][e] + ck1 * y : vo[q][e] + ck1 * y;
+            }
+            if (full[q]) {
+                *reinterpret_cast<f32x4*>(out + (int64_t)i * ldo + j) = o;
+                if (!last) *reinterpret_cast<f32x4*>(Ydst + (int64_t)i * ldd + j) = yn;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) s1 += (double)yn[e] * yn[e];
+            } else if (i < M) {
+                for (int e = 0; e < 4; ++e) {
+                    if (j + e < N) {
+                        out[(int64_t)i * ldo + j + e] = o[e];
+                        if (!last) Ydst[(int64_t)i * ldd + j + e] = yn[e];
+                        s1 += (double)yn[e] * yn[e];
+                    }
+                }
+            }
+        }
+        if (nrm2) {
+            double unused = 0.0;
+            block_sum2(s1, unused);
+            if (threadIdx.x == 0 && s1 != 0.0) atomicAdd(nrm2 + (blockIdx.x & 63), s1);
+        }
     }
 };
 
-template <int BM, int BN, int LA, int LB, class Epi>
-__global__ void __launch_bounds__(GTHREADS) gemm_f32_kernel(Operand A, Operand B, int M, int N, int Kd, Epi epi,
-                                                            int sc_a1, int sc_a2, int sc_coef) {
+__device__ inline const double* epi_scal(const EpiGram&) { return nullptr; }
+__device__ inline const double* epi_scal(const EpiCheb& e) { return e.scal; }
+
+template <int BM, int BN, int LA, int LB>
+struct GemmCore {
     using GA = TileGeom<BM, LA>;
     using GB = TileGeom<BN, LB>;
+    static constexpr int WM = 2, WN = 4;
+    static constexpr int MB = BM / WM / 16, NB = BN / WN / 16;   // 16x16 blocks per wave
+    static_assert(MB >= 1 && NB >= 1, "tile too small for 8 waves");
+
+    // One K-tile from LDS buffer `cur` into the fresh partial `part`.
+    static __device__ inline void tile_mfma(const float* la, const float* lb, int wr, int wc, int lane,
+                                            f32x4 (&part)[MB][NB]) {
+        float fa[MB][KG], fb[NB][KG];
+#pragma unroll
+        for (int a = 0; a < MB; ++a) frag_read<BM, LA>(la, wr * (BM / WM) + a * 16, lane, fa[a]);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) frag_read<BN, LB>(lb, wc * (BN / WN) + b * 16, lane, fb[b]);
+#pragma unroll
+        for (int a = 0; a < MB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) part[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+            for (int a = 0; a < MB; ++a)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                    part[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a][kk], fb[b][kk], part[a][b], 0, 0, 0);
+    }
+
+    static __device__ inline void add_into(f32x4 (&acc)[MB][NB], const f32x4 (&part)[MB][NB]) {
+#pragma unroll
+        for (int a = 0; a < MB; ++a)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) acc[a][b] += part[a][b];
+    }
+};
+
+template <int BM, int BN, int LA, int LB, bool VEC, class Epi>
+__global__ void __launch_bounds__(GTHREADS) gemm_f32_kernel(Operand A, Operand B, int M, int N, int Kd, Epi epi,
+                                                            int sc_a1, int sc_a2, int sc_coef) {
+    using C = GemmCore<BM, BN, LA, LB>;
+    using GA = typename C::GA;
+    using GB = typename C::GB;
+    constexpr int MB = C::MB, NB = C::NB;
     __shared__ __attribute__((aligned(16))) float lds_a[2][GA::size];
     __shared__ __attribute__((aligned(16))) float lds_b[2][GB::size];
+    static_assert(BM * (BN + 4) <= 2 * GA::size, "the epilogue tile must fit the A buffers");
 
     const int ntm = (M + BM - 1) / BM;
     const int ntn = (N + BN - 1) / BN;
@@ -248,64 +412,69 @@ __global__ void __launch_bounds__(GTHREADS) gemm_f32_kernel(Operand A, Operand B
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
-    constexpr int MB = BM / 32, NB = BN / 32;   // 16x16 blocks per wave
+    const int wr = wave / C::WN, wc = wave % C::WN;
 
-    f32x4 acc[MB][NB];
+    f32x4 acc[MB][NB], p0[MB][NB], p1[MB][NB];
 #pragma unroll
     for (int a = 0; a < MB; ++a)
 #pragma unroll
-        for (int b = 0; b < NB; ++b) acc[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < NB; ++b) acc[a][b] = p1[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-    f32x4 ra[GA::per_thread], rb[GB::per_thread];
+    // registers for the two tiles in flight; tile indices past the end are
+    // clamped to the last tile (loaded but never used)
+    f32x4 ra0[GA::per_thread], rb0[GB::per_thread], ra1[GA::per_thread], rb1[GB::per_thread];
     const int nkt = (Kd + GBK - 1) / GBK;
-    if (nkt > 0) {
-        tile_load<BM, LA>(A, m0, 0, Kd, ra);
-        tile_load<BN, LB>(B, n0, 0, Kd, rb);
-        tile_store<BM, LA>(lds_a[0], ra);
-        tile_store<BN, LB>(lds_b[0], rb);
-    }
+    const int last = nkt - 1;
+    tile_load<BM, LA, VEC>(A, m0, 0, Kd, ra0);
+    tile_load<BN, LB, VEC>(B, n0, 0, Kd, rb0);
+    tile_load<BM, LA, VEC>(A, m0, min(1, last) * GBK, Kd, ra1);
+    tile_load<BN, LB, VEC>(B, n0, min(1, last) * GBK, Kd, rb1);
+    tile_store<BM, LA>(lds_a[0], ra0);
+    tile_store<BN, LB>(lds_b[0], rb0);
     __syncthreads();
 
-    for (int kt = 0; kt < nkt; ++kt) {
-        const int cur = kt & 1;
-        const bool more = (kt + 1) < nkt;
-        if (more) {
-            tile_load<BM, LA>(A, m0, (kt + 1) * GBK, Kd, ra);
-            tile_load<BN, LB>(B, n0, (kt + 1) * GBK, Kd, rb);
-        }
-        f32x4 fa[MB], fb[NB];
-#pragma unroll
-        for (int a = 0; a < MB; ++a) fa[a] = frag_read<BM, LA>(lds_a[cur], wr * (BM / 2) + a * 16, lane);
-#pragma unroll
-        for (int b = 0; b < NB; ++b) fb[b] = frag_read<BN, LB>(lds_b[cur], wc * (BN / 2) + b * 16, lane);
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-            for (int a = 0; a < MB; ++a)
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a][kk], fb[b][kk], acc[a][b], 0, 0, 0);
-        if (more) {
-            tile_store<BM, LA>(lds_a[cur ^ 1], ra);
-            tile_store<BN, LB>(lds_b[cur ^ 1], rb);
-        }
+    // Even tiles: LDS buffer 0, partial p0, the following tile in register set 1.
+    // Odd tiles:  LDS buffer 1, partial p1, the following tile in register set 0.
+    for (int kt = 0; kt < nkt; kt += 2) {
+        tile_load<BM, LA, VEC>(A, m0, min(kt + 2, last) * GBK, Kd, ra0);
+        tile_load<BN, LB, VEC>(B, n0, min(kt + 2, last) * GBK, Kd, rb0);
+        CPA_SCHED_FENCE();
+        C::tile_mfma(lds_a[0], lds_b[0], wr, wc, lane, p0);
+        C::add_into(acc, p1);
+        tile_store<BM, LA>(lds_a[1], ra1);
+        tile_store<BN, LB>(lds_b[1], rb1);
         __syncthreads();
+        if (kt + 1 >= nkt) {
+            C::add_into(acc, p0);
+            break;
+        }
+        tile_load<BM, LA, VEC>(A, m0, min(kt + 3, last) * GBK, Kd, ra1);
+        tile_load<BN, LB, VEC>(B, n0, min(kt + 3, last) * GBK, Kd, rb1);
+        CPA_SCHED_FENCE();
+        C::tile_mfma(lds_a[1], lds_b[1], wr, wc, lane, p1);
+        C::add_into(acc, p0);
+        tile_store<BM, LA>(lds_a[0], ra0);
+        tile_store<BN, LB>(lds_b[0], rb0);
+        __syncthreads();
+        if (kt + 2 >= nkt) C::add_into(acc, p1);
     }
 
-    epi.load_scalars(sc_a1, sc_a2, sc_coef);
-    double s1 = 0.0, s2 = 0.0;
+    // stage the accumulator tile in LDS (reusing the operand buffers)
+    float* tile = &lds_a[0][0];
 #pragma unroll
     for (int a = 0; a < MB; ++a)
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = m0 + wr * (BM / 2) + a * 16 + 4 * (lane >> 4) + r;
-                const int j = n0 + wc * (BN / 2) + b * 16 + (lane & 15);
-                if (i < M && j < N) epi.apply(i, j, acc[a][b][r], s1, s2);
+                const int i = wr * (BM / C::WM) + a * 16 + 4 * (lane >> 4) + r;
+                const int j = wc * (BN / C::WN) + b * 16 + (lane & 15);
+                tile[i * (BN + 4) + j] = acc[a][b][r];
             }
-    epi.finish(s1, s2);
+    __syncthreads();
+    constexpr int NG = BM * BN / 4 / GTHREADS;   // float4 groups per thread
+    static_assert(NG * 4 * GTHREADS == BM * BN, "tile must split evenly into float4 groups");
+    epi.template run<BM, BN, NG>(tile, m0, n0, M, N, epi_scal(epi), sc_a1, sc_a2, sc_coef);
 }
 
 }  // namespace cpa

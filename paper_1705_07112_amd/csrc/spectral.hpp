@@ -3,15 +3,21 @@
 // rule, and the FP64 Chebyshev coefficients (Sec. III-A,
 // eq. chebychev_coeff_shifted) computed on the device from that bound.
 //
-// Power iteration, one launch per Gram-vector product, so every workgroup sees
-// the previous product complete:
+// Power iteration runs in one cooperative launch (all workgroups co-resident,
+// which the cooperative launch guarantees) with a grid barrier per product:
 //   w_0 = v_0 (SplitMix64 start vector or the warm-start vector)
 //   product t: v_t = w_{t-1} / ||w_{t-1}||, w_t = G v_t,
-//              mu_t = v_t . w_t and ||w_t||^2 accumulated in FP64.
-//   stop before product t when |mu_{t-1} - mu_{t-2}| <= tol mu_{t-1} (t >= 3) or
-//   ||w_{t-1}|| == 0; later launches return at once.
+//              mu_t = v_t . w_t and ||w_t||^2 in FP64: each workgroup stores its
+//              partial sums, and after the barrier every workgroup adds all
+//              partials in the same order, so all of them take the same
+//              stopping decision;
+//   stop after product t when |mu_t - mu_{t-1}| <= tol mu_t (t >= 2) or
+//   ||w_t|| == 0, or after maxit products.
 // The finishing kernel forms ||r|| = sqrt(max(||w_T||^2 - mu_T^2, 0)) and
-//   Lambda = min(mu_T + max(margin mu_T, ||r||), ||G||_F).
+//   Lambda = min(mu_T + max(margin mu_T, ||r||), (1 + margin) ||G||_F).
+// ||G||_F >= lambda_max caps runaway residual terms without removing the
+// margin: a bound equal to lambda_max would place the top eigenvalue on the
+// endpoint of [-1, 1] where T_k has slope k^2 and FP32 rounding is amplified.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,16 +42,22 @@ enum : int {
     SC_A2 = 9,        // 4 / Lambda
     SC_ET_NUM = 10,   // ADMM: ||l_new - l_old||^2
     SC_ET_DEN = 11,   // ADMM: ||l_new||^2
-    SC_COEF = 16      // K coefficients, then K norms, then power slots
+    SC_TIMEOUT = 12,  // 1 if a grid barrier gave up waiting
+    SC_BARRIER = 13,  // grid-barrier arrival counter (first 4 bytes, zeroed with the block)
+    SC_COEF = 16      // K coefficients, then the other regions below
 };
 
+constexpr int kNormSlots = 64;   // partial-sum slots per growth-check norm
+
 struct ScalarLayout {
-    int K, maxit;
+    int K, maxit, gwg, pwg;      // gwg: Gram workgroups, pwg: power-iteration workgroups
     int coef() const { return SC_COEF; }
-    int norms() const { return SC_COEF + K; }              // ||Y_k||^2, k = 0..K-1
-    int pw_mu() const { return SC_COEF + 2 * K; }          // mu_t, t = 0..maxit
-    int pw_w2() const { return SC_COEF + 2 * K + maxit + 1; }  // ||w_t||^2
-    int total() const { return SC_COEF + 2 * K + 2 * (maxit + 1); }
+    int norms() const { return SC_COEF + K; }                          // K x kNormSlots
+    int pw_mu() const { return norms() + K * kNormSlots; }            // mu_t, t = 0..maxit
+    int pw_w2() const { return pw_mu() + maxit + 1; }                 // ||w_t||^2
+    int gpart() const { return pw_w2() + maxit + 1; }                 // 2 per Gram workgroup
+    int ppart() const { return gpart() + 2 * gwg; }                   // 2 x 2 per power workgroup
+    int total() const { return ppart() + 4 * pwg; }
 };
 
 __global__ void fill_f64_kernel(double* p, int n, double v) {
@@ -70,10 +82,11 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 // w0 = start vector; ||w0||^2 into pw_w2[0].  warm != nullptr: copy it.
+// Single workgroup (fixed summation order).
 __global__ void power_init_kernel(int d, uint64_t seed, const double* warm, double* w0, double* scal, int pw_w2) {
     __shared__ double red[16];
     double acc = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < d; i += gridDim.x * blockDim.x) {
+    for (int i = threadIdx.x; i < d; i += blockDim.x) {
         double v;
         if (warm) {
             v = warm[i];
@@ -85,49 +98,112 @@ __global__ void power_init_kernel(int d, uint64_t seed, const double* warm, doub
         acc += v * v;
     }
     acc = block_sum(acc, red);
-    if (threadIdx.x == 0 && acc != 0.0) atomicAdd(scal + pw_w2, acc);
+    if (threadIdx.x == 0) scal[pw_w2] = acc;
 }
 
-// One product w_t = G v_t (G symmetric d x d, row-major, FP32), one wave per row.
-__global__ void __launch_bounds__(256) power_step_kernel(int d, const float* G, int64_t ldg, const double* wprev,
-                                                         double* wnext, double* scal, int t, double tol,
-                                                         int pw_mu, int pw_w2) {
-    if (scal[SC_STOP] != 0.0) return;
-    const double w2p = scal[pw_w2 + t - 1];
-    if (t >= 3) {
-        const double m1 = scal[pw_mu + t - 1], m2 = scal[pw_mu + t - 2];
-        if (fabs(m1 - m2) <= tol * m1) {
-            // all workgroups read the same completed slots and return; one records it
-            if (blockIdx.x == 0 && threadIdx.x == 0) scal[SC_STOP] = t - 1;
-            return;
+constexpr int kPowerThreads = 512;
+
+// Grid barrier for a cooperative launch: a monotonically increasing arrival
+// counter (zeroed before the launch); barrier number b completes when the
+// counter reaches b * gridDim.x.  The wait is bounded: on time-out the
+// workgroup records SC_TIMEOUT and reports failure, so every wave exits.
+__device__ inline bool grid_barrier(unsigned* counter, unsigned target, double* scal) {
+    __shared__ int ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int good = 1;
+        unsigned spins = 0;
+        while (__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > (1u << 22)) {
+                good = 0;
+                scal[SC_TIMEOUT] = 1.0;
+                break;
+            }
         }
+        __threadfence();
+        ok = good;
     }
-    if (!(w2p > 0.0)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            scal[SC_STOP] = t - 1;
-            scal[SC_VANISH] = 1.0;
-        }
-        return;
-    }
-    const double inv = 1.0 / sqrt(w2p);
+    __syncthreads();
+    return ok != 0;
+}
+
+// Sum of part[0..n) in a fixed order (same result in every workgroup).
+__device__ inline double ordered_sum(const double* part, int n, double* red) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) a += part[i];
+    return block_sum(a, red);
+}
+
+// All products of the power iteration in one cooperative launch (see top).
+__global__ void __launch_bounds__(kPowerThreads) power_coop_kernel(int d, const float* G, int64_t ldg, double* wb0,
+                                                                   double* wb1, double* part, unsigned* counter,
+                                                                   double* scal, int maxit, double tol, int pw_mu,
+                                                                   int pw_w2) {
+    __shared__ double red[kPowerThreads / 64];
+    __shared__ double bcast[2];
+    const int P = gridDim.x;
     const int lane = threadIdx.x & 63;
-    const int gw = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int nw = gridDim.x * (blockDim.x >> 6);
-    double mu_part = 0.0, w2_part = 0.0;
-    for (int i = gw; i < d; i += nw) {
-        const float* row = G + (int64_t)i * ldg;
-        double s = 0.0;
-        for (int j = lane; j < d; j += 64) s += (double)row[j] * (wprev[j] * inv);
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        if (lane == 0) {
-            wnext[i] = s;
-            mu_part += (wprev[i] * inv) * s;
-            w2_part += s * s;
+    const int gw = blockIdx.x * (kPowerThreads / 64) + (threadIdx.x >> 6);
+    const int nw = P * (kPowerThreads / 64);
+    double w2prev = scal[pw_w2 + 0];
+    double muprev = 0.0;
+    int stop = 0, vanish = 0;
+    if (!(w2prev > 0.0)) vanish = 1;
+    int t = 1;
+    for (; !vanish && t <= maxit; ++t) {
+        const double* wp = (t & 1) ? wb0 : wb1;   // w_{t-1}
+        double* wn = (t & 1) ? wb1 : wb0;         // w_t
+        const double inv = 1.0 / sqrt(w2prev);
+        double mu_part = 0.0, w2_part = 0.0;
+        for (int i = gw; i < d; i += nw) {
+            const float* row = G + (int64_t)i * ldg;
+            double acc = 0.0;
+            for (int j = lane; j < d; j += 64) acc += (double)row[j] * (wp[j] * inv);
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if (lane == 0) {
+                wn[i] = acc;
+                mu_part += (wp[i] * inv) * acc;
+                w2_part += acc * acc;
+            }
         }
+        mu_part = block_sum(mu_part, red);
+        w2_part = block_sum(w2_part, red);
+        double* pt = part + (t & 1) * 2 * P;
+        if (threadIdx.x == 0) {
+            pt[blockIdx.x] = mu_part;
+            pt[P + blockIdx.x] = w2_part;
+        }
+        if (!grid_barrier(counter, (unsigned)t * P, scal)) return;
+        const double mu = ordered_sum(pt, P, red);
+        const double w2 = ordered_sum(pt + P, P, red);
+        if (threadIdx.x == 0) {
+            bcast[0] = mu;
+            bcast[1] = w2;
+            if (blockIdx.x == 0) {
+                scal[pw_mu + t] = mu;
+                scal[pw_w2 + t] = w2;
+            }
+        }
+        __syncthreads();
+        const double mu_t = bcast[0], w2_t = bcast[1];
+        __syncthreads();
+        if (!(w2_t > 0.0)) {
+            vanish = 1;
+            break;
+        }
+        if (t >= 2 && fabs(mu_t - muprev) <= tol * mu_t) {
+            stop = t;
+            break;
+        }
+        muprev = mu_t;
+        w2prev = w2_t;
     }
-    if (lane == 0) {
-        if (mu_part != 0.0) atomicAdd(scal + pw_mu + t, mu_part);
-        if (w2_part != 0.0) atomicAdd(scal + pw_w2 + t, w2_part);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        scal[SC_STOP] = stop ? stop : (vanish ? 0 : maxit);
+        scal[SC_VANISH] = vanish;
     }
 }
 
@@ -138,11 +214,22 @@ __global__ void __launch_bounds__(256) power_step_kernel(int d, const float* G, 
 // For mode 0 the warm-start buffer receives v_T (the unit vector of the last product).
 __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int maxit, double margin,
                                     const double* wbuf0, const double* wbuf1, double* warm_out, double* scal,
-                                    ShrinkParams sp, int K, int pw_mu, int pw_w2) {
+                                    ShrinkParams sp, int K, int pw_mu, int pw_w2, const double* gpart, int gwg) {
     __shared__ double sLambda;
     __shared__ int sT;
+    __shared__ double red[16];
+    // Gram statistics from the per-workgroup partials, in a fixed order
+    double f2 = 0.0, tr = 0.0;
+    for (int i = threadIdx.x; i < gwg; i += blockDim.x) {
+        f2 += gpart[2 * i];
+        tr += gpart[2 * i + 1];
+    }
+    f2 = block_sum(f2, red);
+    tr = block_sum(tr, red);
     if (threadIdx.x == 0) {
-        const double fro = sqrt(scal[SC_FRO2] > 0.0 ? scal[SC_FRO2] : 0.0);
+        scal[SC_FRO2] = f2;
+        scal[SC_TRACE] = tr;
+        const double fro = sqrt(f2 > 0.0 ? f2 : 0.0);
         double Lam = 0.0;
         int T = 0;
         if (mode == 1) {
@@ -150,8 +237,8 @@ __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int ma
         } else if (mode == 2) {
             Lam = fro;
         } else if (fro > 0.0) {
-            T = (scal[SC_STOP] != 0.0) ? (int)scal[SC_STOP] : maxit;
-            if (scal[SC_VANISH] != 0.0 || T < 1) {
+            T = (int)scal[SC_STOP];
+            if (scal[SC_VANISH] != 0.0 || scal[SC_TIMEOUT] != 0.0 || T < 1) {
                 Lam = fro;
                 T = 0;
             } else {
@@ -161,7 +248,7 @@ __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int ma
                 const double r = sqrt(r2 > 0.0 ? r2 : 0.0);
                 const double add = (margin * mu > r) ? margin * mu : r;
                 Lam = mu + add;
-                if (Lam > fro) Lam = fro;
+                if (Lam > (1.0 + margin) * fro) Lam = (1.0 + margin) * fro;
                 scal[SC_MU] = mu;
                 scal[SC_RESID] = r;
             }

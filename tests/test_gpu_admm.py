@@ -1,7 +1,10 @@
-"""GPU RPCA ADMM driver (Appendix B) against the oracle driver: identical
-start, the same number of iterations, each side with its own power-iteration
-bound.  Per-iteration quantities agree to FP32 rounding; the drift after a few
-iterations is bounded (ADMM is non-expansive)."""
+"""GPU RPCA ADMM driver (Appendix B) against the oracle driver.
+
+Gated: one iteration started from the same state on both sides (the GPU's
+own state, copied to the host) must agree to the FP32 tolerance -- the shrink
+output z1 and the updated l, s, u.  Reported with a loose sanity bound: the
+end-to-end drift after several iterations, where FP32 rounding is amplified
+through the iteration."""
 import numpy as np
 import pytest
 
@@ -10,35 +13,67 @@ from oracle import drivers, metrics
 
 pytestmark = pytest.mark.gpu
 
+NAMES = ("l", "s", "z1", "z2", "u1", "u2", "u3")
 
-def _admm_pair(m, n, iters, K, inv_rho, eta_over_rho, seed):
+
+def _state_host(run):
+    return {k: run.block(i).cpu().numpy().astype(np.float64) for i, k in enumerate(NAMES)}
+
+
+def _check_one_iteration(m, n, K, inv_rho, eta_over_rho, seed, warm_iters):
     import torch
     import paper_1705_07112_amd as cpa
     I, _, _ = synth.rpca_frames(m, n, rank=min(40, m // 4), outlier_frac=0.05, seed=seed)
     Id = torch.from_numpy(I).cuda()
-    opts = cpa.Opts(K=K, warm_start=True, power_iters=100)
-    run = cpa.RpcaAdmm(Id, inv_rho, eta_over_rho, opts)
+    run = cpa.RpcaAdmm(Id, inv_rho, eta_over_rho, cpa.Opts(K=K, warm_start=True, power_iters=100))
+    Et = torch.zeros(warm_iters + 1, dtype=torch.float64, device="cuda")
+    if warm_iters:
+        run.iterate(warm_iters, Et[:warm_iters])
+    before = _state_host(run)
+    run.iterate(1, Et[warm_iters:])
+    torch.cuda.synchronize()
+    after = _state_host(run)
+    ref, info = drivers.rpca_step(before, I.astype(np.float64), inv_rho, eta_over_rho, K)
+    # each dual block is a sum of three terms; its error is measured against the
+    # size of those terms (the sum itself can cancel to much less)
+    scale = {
+        "u1": metrics.fro(before["u1"]) + metrics.fro(ref["l"]) + metrics.fro(ref["z1"]),
+        "u2": metrics.fro(before["u2"]) + metrics.fro(ref["s"]) + metrics.fro(ref["z2"]),
+        "u3": metrics.fro(before["u3"]) + metrics.fro(ref["l"]) + metrics.fro(ref["s"]) + metrics.fro(I),
+    }
+    errs = {k: (metrics.fro(after[k] - ref[k]) / scale[k] if k in scale else metrics.rel_fro(after[k], ref[k]))
+            for k in NAMES}
+    e_gpu = Et[warm_iters].item()
+    print(f"  one iteration after {warm_iters}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items())
+          + f" E gpu={e_gpu:.6g} oracle={info['E']:.6g}", flush=True)
+    for k in NAMES:
+        assert errs[k] <= 1e-5, (k, errs[k])
+    assert abs(e_gpu - info["E"]) <= 1e-5 * max(info["E"], 1e-12)
+
+
+def test_admm_one_iteration_small():
+    print("admm 96x80", flush=True)
+    _check_one_iteration(96, 80, 20, 1.0, 1.0 / np.sqrt(96), 11, warm_iters=0)
+    _check_one_iteration(96, 80, 20, 1.0, 1.0 / np.sqrt(96), 11, warm_iters=6)
+
+
+def test_admm_one_iteration_full_size():
+    """The bench workload (1024 x 1024, K = 30, 1/rho = 10, eta/rho = 10/32)."""
+    print("admm 1024x1024", flush=True)
+    _check_one_iteration(1024, 1024, 30, 10.0, 10.0 / 32.0, synth.BASE_SEED + 1, warm_iters=4)
+
+
+def test_admm_drift_is_small():
+    import torch
+    import paper_1705_07112_amd as cpa
+    m, n, iters = 96, 80, 12
+    I, _, _ = synth.rpca_frames(m, n, rank=24, outlier_frac=0.05, seed=11)
+    run = cpa.RpcaAdmm(torch.from_numpy(I).cuda(), 1.0, 1.0 / np.sqrt(96), cpa.Opts(K=20, warm_start=True))
     Et = torch.zeros(iters, dtype=torch.float64, device="cuda")
     run.iterate(iters, Et)
-    torch.cuda.synchronize()
-    l_o, s_o, E_o, _ = drivers.rpca_admm(I.astype(np.float64), inv_rho, eta_over_rho, iters, K)
-    return run.L.cpu().numpy(), run.S.cpu().numpy(), Et.cpu().numpy(), l_o, s_o, np.array(E_o)
-
-
-def test_admm_small_matches_oracle():
-    print("admm 96x80 12 iterations", flush=True)
-    l, s, E, l_o, s_o, E_o = _admm_pair(96, 80, 12, 20, 1.0, 1.0 / np.sqrt(96), 11)
-    el, es = metrics.rel_fro(l, l_o), metrics.rel_fro(s, s_o)
-    print(f"  l {el:.3e} s {es:.3e} E {E[:4]} vs {E_o[:4]}", flush=True)
-    assert el < 1e-4 and es < 1e-3
-    assert np.max(np.abs(E - E_o) / np.maximum(E_o, 1e-12)) < 1e-3
-
-
-def test_admm_full_size_first_iterations():
-    """The bench workload (1024 x 1024, K = 30, 1/rho = 10, eta = 1/32) for 3 iterations."""
-    print("admm 1024x1024 3 iterations", flush=True)
-    l, s, E, l_o, s_o, E_o = _admm_pair(1024, 1024, 3, 30, 10.0, 10.0 / 32.0, synth.BASE_SEED + 1)
-    el, es = metrics.rel_fro(l, l_o), metrics.rel_fro(s, s_o)
-    print(f"  l {el:.3e} s {es:.3e} E {E} vs {E_o}", flush=True)
-    assert el < 1e-5 and es < 1e-4
-    assert np.max(np.abs(E - E_o) / np.maximum(E_o, 1e-12)) < 1e-4
+    l_o, s_o, E_o, _ = drivers.rpca_admm(I.astype(np.float64), 1.0, 1.0 / np.sqrt(96), iters, 20)
+    el = metrics.rel_fro(run.L.cpu().numpy(), l_o)
+    es = metrics.rel_fro(run.S.cpu().numpy(), s_o)
+    print(f"  drift after {iters}: l {el:.2e} s {es:.2e}", flush=True)
+    assert el < 1e-3 and es < 1e-2
+    assert np.max(np.abs(Et.cpu().numpy() - np.array(E_o)) / np.array(E_o)) < 1e-2

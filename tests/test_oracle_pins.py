@@ -325,12 +325,16 @@ def test_power_bound_is_an_upper_bound():
         Lam, mu, r, it, v = bound.power_bound(G, seed=seed)
         assert Lam >= lam[-1] * (1 - 1e-12)
         assert mu <= lam[-1] * (1 + 1e-12)
-        assert Lam <= math.sqrt(float(np.sum(G * G))) * (1 + 1e-15)
+        assert Lam <= 1.01 * math.sqrt(float(np.sum(G * G))) * (1 + 1e-15)
         assert abs(mu - lam[-1]) < 1e-6 * lam[-1]
     Dg = np.diag([4.0, 1.0, 0.5, 0.25])
     Lam, mu, r, it, v = bound.power_bound(Dg, seed=1)
     assert mu == pytest.approx(4.0, rel=1e-7)
-    assert Lam == pytest.approx(min(4.04, math.sqrt(16 + 1 + 0.25 + 1 / 16)), rel=1e-6)
+    assert Lam == pytest.approx(4.04, rel=1e-6)
+    # rank one: ||G||_F == lambda_max, the cap keeps the margin
+    u = np.array([[1.0], [2.0], [2.0]])
+    Lam1 = bound.power_bound(u @ u.T, seed=3)[0]
+    assert Lam1 == pytest.approx(9.0 * 1.01, rel=1e-9)
     assert bound.power_bound(np.zeros((3, 3)))[0] == 0.0
 
 
