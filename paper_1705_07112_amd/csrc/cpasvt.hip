@@ -97,14 +97,8 @@ struct Work {
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
-int gram_tile(int d) {
-    const int64_t tiles128 = (int64_t)((d + 127) / 128) * ((d + 127) / 128);
-    return tiles128 >= 512 ? 128 : 64;
-}
-
 int gram_grid(int d) {
-    const int t = gram_tile(d);
-    return ((d + t - 1) / t) * ((d + t - 1) / t);
+    return ((d + 63) / 64) * ((d + 63) / 64);
 }
 
 // Power-iteration workgroups: about 16 rows each, at most 64 (the grid barrier
@@ -214,14 +208,11 @@ cpa_status launch_gemm(hipStream_t st, const Operand& A, const Operand& B, int M
     return CPA_OK;
 }
 
-// Tile size choice: 64 x 64 tiles keep >= 256 workgroups in flight from 1024 x 1024
-// outputs; larger outputs take 128 x 128 tiles for more reuse per workgroup.
-// (gram_tile() applies the same rule to size the Gram's partial-sum area.)
+// All products use 64 x 64 output tiles: at 1024 x 1024 that is 256 workgroups,
+// one per CU, and larger outputs simply have more of them.
 template <int LA, int LB, class Epi>
 cpa_status gemm_dispatch(hipStream_t st, const Operand& A, const Operand& B, int M, int N, int Kd, const Epi& epi,
                          int sc_a1, int sc_a2, int sc_coef) {
-    const int64_t tiles128 = (int64_t)((M + 127) / 128) * ((N + 127) / 128);
-    if (tiles128 >= 512) return launch_gemm<128, 128, LA, LB>(st, A, B, M, N, Kd, epi, sc_a1, sc_a2, sc_coef);
     return launch_gemm<64, 64, LA, LB>(st, A, B, M, N, Kd, epi, sc_a1, sc_a2, sc_coef);
 }
 
@@ -373,9 +364,10 @@ cpa_status enqueue_recurrence(cpa_ctx* ctx, hipStream_t st, int m, int n, const 
         if (s != CPA_OK) return s;
         if (ea) HIP_TRY(hipEventRecord(ea, st));
         if (m >= n) {
-            // Y_k G: A = Y_k (k contiguous), B(k, j) = G[k][j] (j contiguous)
+            // Y_k G: A = Y_k (k contiguous); B(k, j) = G[k][j] = G[j][k] (G symmetric),
+            // read along k so both operands take 16-byte LDS fragment reads
             Operand A = make_op(yk, ldk, m), B = make_op(w.G, d, n);
-            s = gemm_dispatch<KCONTIG, XCONTIG>(st, A, B, m, n, n, epi, SC_A1, SC_A2, SC_COEF);
+            s = gemm_dispatch<KCONTIG, KCONTIG>(st, A, B, m, n, n, epi, SC_A1, SC_A2, SC_COEF);
         } else {
             // G Y_k: A(i, k) = G[k][i] (G symmetric; i contiguous), B = Y_k (j contiguous)
             Operand A = make_op(w.G, d, m), B = make_op(yk, ldk, n);

@@ -16,8 +16,9 @@
 // operands (any bijection is valid as long as A and B agree).  With that map a
 // KCONTIG LDS row yields eight sub-steps of a lane in two 16-byte reads.
 //
-// Pipeline: K-tiles of 64, LDS double buffer, and global loads issued two
-// tiles ahead into registers, so each load has two tiles of MFMA work to land.
+// Pipeline: K-tiles of 64, two LDS stages, MFMA fragments double-buffered in
+// registers, global loads issued three tiles ahead (see the step description
+// above the kernel).
 // Workgroup: 8 waves (two per SIMD) in a 2 x 4 arrangement; each wave owns a
 // (BM/2) x (BN/4) sub-tile of 16 x 16 MFMA blocks.
 //
@@ -43,6 +44,35 @@ constexpr int GBK = CPA_GEMM_BK; // K-tile depth
 #ifndef CPA_SCHED_FENCE
 #define CPA_SCHED_FENCE() __builtin_amdgcn_sched_barrier(0)
 #endif
+
+// Instruction-group order for one pipeline step: the LDS fragment reads of the
+// next tile and the LDS stores are spread between the MFMAs of the current tile
+// so the LDS traffic runs under the matrix-core work instead of in a burst
+// before the barrier.  (sched_group_barrier masks: 0x8 MFMA, 0x100 DS read,
+// 0x200 DS write.)
+#ifndef CPA_READ_SHARE
+#define CPA_READ_SHARE 2   // quarters of the step's MFMAs spread over the DS reads
+#endif
+template <int NMFMA, int NREAD, int NWRITE>
+__device__ inline void interleave_step() {
+    constexpr int per_read = (NMFMA * CPA_READ_SHARE / 4) / (NREAD > 0 ? NREAD : 1);
+    constexpr int used_r = per_read * NREAD;
+    constexpr int per_write = (NMFMA - used_r) / (NWRITE + 1);
+#pragma unroll
+    for (int i = 0; i < NREAD; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, per_read, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < NWRITE; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, per_write, 0);
+        __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, NMFMA - used_r - per_write * NWRITE, 0);
+    // the partial-sum adds (VALU, mask 0x2) last: their inputs were produced a
+    // whole step earlier, so they never wait on the matrix cores
+    __builtin_amdgcn_sched_group_barrier(0x002, 1000, 0);
+}
 constexpr int GWAVES = 8;        // waves per workgroup (2 x 4)
 constexpr int GTHREADS = 64 * GWAVES;
 constexpr int KG = GBK / 4;      // sub-steps per lane group and K-tile
@@ -130,19 +160,20 @@ __device__ inline void tile_store(float* lds, const f32x4 (&r)[TileGeom<BX, L>::
     }
 }
 
-// The KG sub-step operands of one lane for the 16-row block starting at xb.
-template <int BX, int L>
-__device__ inline void frag_read(const float* lds, int xb, int lane, float (&v)[KG]) {
+// The Q sub-step operands of one lane for the 16-row block starting at xb,
+// sub-steps kk = koff .. koff + Q - 1 of the tile (tile column k = KG g + kk).
+template <int BX, int L, int Q>
+__device__ inline void frag_read(const float* lds, int xb, int lane, int koff, float (&v)[Q]) {
     const int xi = xb + (lane & 15);
     const int g = lane >> 4;
     if (L == XCONTIG) {
         constexpr int P = TileGeom<BX, L>::pitch;
 #pragma unroll
-        for (int q = 0; q < KG; ++q) v[q] = lds[(KG * g + q) * P + xi];
+        for (int q = 0; q < Q; ++q) v[q] = lds[(KG * g + koff + q) * P + xi];
     } else {
-        const float* row = lds + xi * TileGeom<BX, L>::pitch + KG * g;
+        const float* row = lds + xi * TileGeom<BX, L>::pitch + KG * g + koff;
 #pragma unroll
-        for (int q = 0; q < KG; q += 4) {
+        for (int q = 0; q < Q; q += 4) {
             const f32x4 t = *reinterpret_cast<const f32x4*>(row + q);
             v[q] = t[0];
             v[q + 1] = t[1];
@@ -356,49 +387,87 @@ struct EpiCheb {
 __device__ inline const double* epi_scal(const EpiGram&) { return nullptr; }
 __device__ inline const double* epi_scal(const EpiCheb& e) { return e.scal; }
 
+// Wave layout: WM x WN waves over the output tile, times KS waves that split
+// each K-tile's sub-steps between them (their partial sums are added once,
+// in LDS, before the epilogue).  64 x 64 tiles use 2 x 2 x 2: each wave owns a
+// 32 x 32 output (2 x 2 MFMA blocks, four independent accumulation chains) over
+// half of every K-tile, which reads a third less from LDS than eight waves with
+// 32 x 16 outputs over whole K-tiles.  128 x 128 tiles use 2 x 4 x 1.
+template <int BM, int BN>
+struct WaveLayout {
+    static constexpr int WM = 2;
+    static constexpr int WN = (BM == 64 && BN == 64) ? 2 : 4;
+    static constexpr int KS = GWAVES / (WM * WN);
+};
+
 template <int BM, int BN, int LA, int LB>
 struct GemmCore {
     using GA = TileGeom<BM, LA>;
     using GB = TileGeom<BN, LB>;
-    static constexpr int WM = 2, WN = 4;
+    static constexpr int WM = WaveLayout<BM, BN>::WM, WN = WaveLayout<BM, BN>::WN, KS = WaveLayout<BM, BN>::KS;
     static constexpr int MB = BM / WM / 16, NB = BN / WN / 16;   // 16x16 blocks per wave
-    static_assert(MB >= 1 && NB >= 1, "tile too small for 8 waves");
+    static constexpr int KQ = KG / KS;                            // sub-steps per wave and K-tile
+    static_assert(MB >= 1 && NB >= 1 && KS >= 1 && WM * WN * KS == GWAVES, "bad wave layout");
+    static_assert(KQ % 4 == 0, "sub-steps per wave must be a multiple of 4");
 
-    // One K-tile from LDS buffer `cur` into the fresh partial `part`.
-    static __device__ inline void tile_mfma(const float* la, const float* lb, int wr, int wc, int lane,
-                                            f32x4 (&part)[MB][NB]) {
-        float fa[MB][KG], fb[NB][KG];
+    struct Frags {
+        float a[MB][KQ];
+        float b[NB][KQ];
+    };
+
+    // instruction counts of one pipeline step (per wave)
+    static constexpr int kMfma = MB * NB * KQ;
+    static constexpr int kReads = (LA == KCONTIG ? MB * KQ / 4 : MB * KQ) + (LB == KCONTIG ? NB * KQ / 4 : NB * KQ);
+    static constexpr int kWrites = GA::per_thread + GB::per_thread;
+
+    static __device__ inline void read(const float* la, const float* lb, int wr, int wc, int kh, int lane, Frags& f) {
 #pragma unroll
-        for (int a = 0; a < MB; ++a) frag_read<BM, LA>(la, wr * (BM / WM) + a * 16, lane, fa[a]);
+        for (int i = 0; i < MB; ++i) frag_read<BM, LA, KQ>(la, wr * (BM / WM) + i * 16, lane, kh * KQ, f.a[i]);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) frag_read<BN, LB>(lb, wc * (BN / WN) + b * 16, lane, fb[b]);
+        for (int j = 0; j < NB; ++j) frag_read<BN, LB, KQ>(lb, wc * (BN / WN) + j * 16, lane, kh * KQ, f.b[j]);
+    }
+
+    // One K-tile (this wave's sub-steps) into the fresh partial `part`.
+    static __device__ inline void mfma(const Frags& f, f32x4 (&part)[MB][NB]) {
 #pragma unroll
-        for (int a = 0; a < MB; ++a)
+        for (int i = 0; i < MB; ++i)
 #pragma unroll
-            for (int b = 0; b < NB; ++b) part[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            for (int j = 0; j < NB; ++j) part[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kk = 0; kk < KG; ++kk)
+        for (int kk = 0; kk < KQ; ++kk)
 #pragma unroll
-            for (int a = 0; a < MB; ++a)
+            for (int i = 0; i < MB; ++i)
 #pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    part[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a][kk], fb[b][kk], part[a][b], 0, 0, 0);
+                for (int j = 0; j < NB; ++j)
+                    part[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(f.a[i][kk], f.b[j][kk], part[i][j], 0, 0, 0);
     }
 
     static __device__ inline void add_into(f32x4 (&acc)[MB][NB], const f32x4 (&part)[MB][NB]) {
 #pragma unroll
-        for (int a = 0; a < MB; ++a)
+        for (int i = 0; i < MB; ++i)
 #pragma unroll
-            for (int b = 0; b < NB; ++b) acc[a][b] += part[a][b];
+            for (int j = 0; j < NB; ++j) acc[i][j] += part[i][j];
     }
 };
 
+// Pipeline of step t (tiles past the end are clamped to the last one: loaded,
+// stored and read, never used):
+//   issue the global loads of tile t+3 into register set (t+1)%2
+//   MFMAs of tile t from fragment set t%2 (read during step t-1)
+//   read the fragments of tile t+1 from LDS stage (t+1)%2 into set (t+1)%2
+//   store tile t+2 (register set t%2, loaded during step t-1) to LDS stage t%2
+//   barrier
+// Stage t%2 is free at step t: its last reader was the fragment read of tile t
+// during step t-1 (the prologue for t = 0), which the barrier of step t-1 (the
+// prologue's second barrier) completed.  Every global load
+// has about two steps to land and every LDS read one step of MFMAs to hide.
 template <int BM, int BN, int LA, int LB, bool VEC, class Epi>
 __global__ void __launch_bounds__(GTHREADS) gemm_f32_kernel(Operand A, Operand B, int M, int N, int Kd, Epi epi,
                                                             int sc_a1, int sc_a2, int sc_coef) {
     using C = GemmCore<BM, BN, LA, LB>;
     using GA = typename C::GA;
     using GB = typename C::GB;
+    using Frags = typename C::Frags;
     constexpr int MB = C::MB, NB = C::NB;
     __shared__ __attribute__((aligned(16))) float lds_a[2][GA::size];
     __shared__ __attribute__((aligned(16))) float lds_b[2][GB::size];
@@ -412,49 +481,64 @@ __global__ void __launch_bounds__(GTHREADS) gemm_f32_kernel(Operand A, Operand B
 
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int wr = wave / C::WN, wc = wave % C::WN;
+    const int wo = wave % (C::WM * C::WN);          // output sub-tile of this wave
+    const int kh = wave / (C::WM * C::WN);          // its share of each K-tile
+    const int wr = wo / C::WN, wc = wo % C::WN;
 
     f32x4 acc[MB][NB], p0[MB][NB], p1[MB][NB];
 #pragma unroll
-    for (int a = 0; a < MB; ++a)
+    for (int i = 0; i < MB; ++i)
 #pragma unroll
-        for (int b = 0; b < NB; ++b) acc[a][b] = p1[a][b] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < NB; ++j) acc[i][j] = p1[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-    // registers for the two tiles in flight; tile indices past the end are
-    // clamped to the last tile (loaded but never used)
     f32x4 ra0[GA::per_thread], rb0[GB::per_thread], ra1[GA::per_thread], rb1[GB::per_thread];
+    Frags f0, f1;
     const int nkt = (Kd + GBK - 1) / GBK;
     const int last = nkt - 1;
-    tile_load<BM, LA, VEC>(A, m0, 0, Kd, ra0);
-    tile_load<BN, LB, VEC>(B, n0, 0, Kd, rb0);
-    tile_load<BM, LA, VEC>(A, m0, min(1, last) * GBK, Kd, ra1);
-    tile_load<BN, LB, VEC>(B, n0, min(1, last) * GBK, Kd, rb1);
+    auto kof = [&](int t) { return min(t, last) * GBK; };
+
+    // prologue: tiles 0 and 1 into LDS, tile 2 in flight, fragments of tile 0
+    tile_load<BM, LA, VEC>(A, m0, kof(0), Kd, ra0);
+    tile_load<BN, LB, VEC>(B, n0, kof(0), Kd, rb0);
+    tile_load<BM, LA, VEC>(A, m0, kof(1), Kd, ra1);
+    tile_load<BN, LB, VEC>(B, n0, kof(1), Kd, rb1);
     tile_store<BM, LA>(lds_a[0], ra0);
     tile_store<BN, LB>(lds_b[0], rb0);
+    tile_store<BM, LA>(lds_a[1], ra1);
+    tile_store<BN, LB>(lds_b[1], rb1);
+    __syncthreads();
+    tile_load<BM, LA, VEC>(A, m0, kof(2), Kd, ra0);
+    tile_load<BN, LB, VEC>(B, n0, kof(2), Kd, rb0);
+    C::read(lds_a[0], lds_b[0], wr, wc, kh, lane, f0);
+    // every wave has its tile-0 fragments before step 0 overwrites stage 0
     __syncthreads();
 
-    // Even tiles: LDS buffer 0, partial p0, the following tile in register set 1.
-    // Odd tiles:  LDS buffer 1, partial p1, the following tile in register set 0.
     for (int kt = 0; kt < nkt; kt += 2) {
-        tile_load<BM, LA, VEC>(A, m0, min(kt + 2, last) * GBK, Kd, ra0);
-        tile_load<BN, LB, VEC>(B, n0, min(kt + 2, last) * GBK, Kd, rb0);
+        // ---- step kt (even): fragments f0, partial p0, loads into set 1, store set 0
+        tile_load<BM, LA, VEC>(A, m0, kof(kt + 3), Kd, ra1);
+        tile_load<BN, LB, VEC>(B, n0, kof(kt + 3), Kd, rb1);
         CPA_SCHED_FENCE();
-        C::tile_mfma(lds_a[0], lds_b[0], wr, wc, lane, p0);
+        C::mfma(f0, p0);
         C::add_into(acc, p1);
-        tile_store<BM, LA>(lds_a[1], ra1);
-        tile_store<BN, LB>(lds_b[1], rb1);
+        C::read(lds_a[1], lds_b[1], wr, wc, kh, lane, f1);
+        tile_store<BM, LA>(lds_a[0], ra0);
+        tile_store<BN, LB>(lds_b[0], rb0);
+        interleave_step<C::kMfma, C::kReads, C::kWrites>();
         __syncthreads();
         if (kt + 1 >= nkt) {
             C::add_into(acc, p0);
             break;
         }
-        tile_load<BM, LA, VEC>(A, m0, min(kt + 3, last) * GBK, Kd, ra1);
-        tile_load<BN, LB, VEC>(B, n0, min(kt + 3, last) * GBK, Kd, rb1);
+        // ---- step kt+1 (odd): fragments f1, partial p1, loads into set 0, store set 1
+        tile_load<BM, LA, VEC>(A, m0, kof(kt + 4), Kd, ra0);
+        tile_load<BN, LB, VEC>(B, n0, kof(kt + 4), Kd, rb0);
         CPA_SCHED_FENCE();
-        C::tile_mfma(lds_a[1], lds_b[1], wr, wc, lane, p1);
+        C::mfma(f1, p1);
         C::add_into(acc, p0);
-        tile_store<BM, LA>(lds_a[0], ra0);
-        tile_store<BN, LB>(lds_b[0], rb0);
+        C::read(lds_a[0], lds_b[0], wr, wc, kh, lane, f0);
+        tile_store<BM, LA>(lds_a[1], ra1);
+        tile_store<BN, LB>(lds_b[1], rb1);
+        interleave_step<C::kMfma, C::kReads, C::kWrites>();
         __syncthreads();
         if (kt + 2 >= nkt) C::add_into(acc, p1);
     }
@@ -462,15 +546,22 @@ __global__ void __launch_bounds__(GTHREADS) gemm_f32_kernel(Operand A, Operand B
     // stage the accumulator tile in LDS (reusing the operand buffers)
     float* tile = &lds_a[0][0];
 #pragma unroll
-    for (int a = 0; a < MB; ++a)
+    for (int h = 0; h < C::KS; ++h) {
+        if (kh == h) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
+            for (int a = 0; a < MB; ++a)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = wr * (BM / C::WM) + a * 16 + 4 * (lane >> 4) + r;
-                const int j = wc * (BN / C::WN) + b * 16 + (lane & 15);
-                tile[i * (BN + 4) + j] = acc[a][b][r];
-            }
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = wr * (BM / C::WM) + a * 16 + 4 * (lane >> 4) + r;
+                        const int j = wc * (BN / C::WN) + b * 16 + (lane & 15);
+                        float* t = tile + i * (BN + 4) + j;
+                        *t = (h == 0) ? acc[a][b][r] : *t + acc[a][b][r];
+                    }
+        }
+        if (C::KS > 1) __syncthreads();
+    }
     __syncthreads();
     constexpr int NG = BM * BN / 4 / GTHREADS;   // float4 groups per thread
     static_assert(NG * 4 * GTHREADS == BM * BN, "tile must split evenly into float4 groups");
