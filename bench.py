@@ -132,6 +132,22 @@ def main():
                      "gram_avg_us": round(1e3 * gram_ms / max(gram_n, 1), 3)},
     }
 
+    # the same workload with the split-precision recurrence (bf16 hi + lo)
+    run2 = cpa.RpcaAdmm(Id, INV_RHO, ETA_OVER_RHO, cpa.Opts(K=K, warm_start=True, power_iters=100, precision="bf16x3"))
+    run2.iterate(args.warmup)
+    torch.cuda.synchronize()
+    cpa.timing_enable(True)
+    t0.record()
+    run2.iterate(args.steps)
+    t1.record()
+    torch.cuda.synchronize()
+    ms2 = t0.elapsed_time(t1)
+    rec2_ms, rec2_n = cpa.timing_read("recurrence")
+    cpa.timing_enable(False)
+    out["bf16x3"] = {"value": round(args.steps / (ms2 / 1e3), 3), "ms_per_step": round(ms2 / args.steps, 4),
+                     "recurrence_avg_us": round(1e3 * rec2_ms / max(rec2_n, 1), 3),
+                     "note": "same ADMM workload; recurrence products as bf16 hi/lo x3 on the BF16 matrix cores"}
+
     if not args.no_accuracy:
         # errors of one shrink of the current ADMM iterate (L + U1) on the device
         from oracle import cpa as ocpa
@@ -144,6 +160,9 @@ def main():
         sh = Shrinkage(0, INV_RHO)
         out["err_vs_fp64_cpa"] = float("%.3e" % metrics.rel_fro(Y, ocpa.cpa_shrink(X64, sh, info["Lambda"], K), X64))
         out["err_vs_fp64_svt"] = float("%.3e" % metrics.rel_fro(Y, exact.svt_svd(X64, sh), X64))
+        Y2 = cpa.shrink_dense(Xd, cpa.soft(INV_RHO), cpa.Opts(K=K, Lambda=info["Lambda"], precision="bf16x3"))
+        out["bf16x3"]["err_vs_fp64_cpa"] = float("%.3e" % metrics.rel_fro(
+            Y2.cpu().numpy().astype(np.float64), ocpa.cpa_shrink(X64, sh, info["Lambda"], K), X64))
         out["E_t_last"] = float("%.3e" % Et[-1].item())
 
     if not args.no_cpu_baseline:

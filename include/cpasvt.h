@@ -82,9 +82,14 @@ typedef struct {
  *   CPA_BOUND_FROBENIUS  Lambda = ||Gram||_F (always an upper bound) */
 typedef enum { CPA_BOUND_POWER = 0, CPA_BOUND_GIVEN = 1, CPA_BOUND_FROBENIUS = 2 } cpa_bound_rule;
 
-/* Arithmetic of the Gram and recurrence products.
- *   CPA_PREC_FP32   FP32 MFMA with FP32 accumulation. */
-typedef enum { CPA_PREC_FP32 = 0 } cpa_precision;
+/* Arithmetic of the recurrence products (the Gram and the bound are always FP32
+ * MFMA with FP64 reductions).
+ *   CPA_PREC_FP32    FP32 MFMA with FP32 accumulation.
+ *   CPA_PREC_BF16X3  each FP32 operand split into bf16 hi + lo (round to nearest
+ *                    even); A_hi B_hi + A_hi B_lo + A_lo B_hi on the BF16 matrix
+ *                    cores with FP32 accumulation.  Y_k, the accumulator and the
+ *                    coefficients stay FP32 / FP64. */
+typedef enum { CPA_PREC_FP32 = 0, CPA_PREC_BF16X3 = 1 } cpa_precision;
 
 typedef struct {
     int32_t K;            /* number of Chebyshev coefficients (the paper's order alpha), >= 1 */

@@ -27,7 +27,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "cpasvt.h")
 
 SOFT, HARD, WEIGHTED_CONST, WEIGHTED_FN = 0, 1, 2, 3
 BOUND_POWER, BOUND_GIVEN, BOUND_FROBENIUS = 0, 1, 2
-PREC_FP32 = 0
+PREC_FP32, PREC_BF16X3 = 0, 1
 
 
 class CpaShrinkage(ctypes.Structure):
@@ -146,6 +146,7 @@ class Opts:
     seed: int = 0
     check: bool = False
     growth_tol: float = 1e-3
+    precision: str = "fp32"      # "fp32" | "bf16x3"
 
     def to_c(self) -> CpaOpts:
         o = CpaOpts()
@@ -162,7 +163,7 @@ class Opts:
         o.margin = float(self.margin)
         o.seed = int(self.seed)
         o.check = int(bool(self.check))
-        o.precision = PREC_FP32
+        o.precision = {"fp32": PREC_FP32, "bf16x3": PREC_BF16X3}[self.precision]
         o.growth_tol = float(self.growth_tol)
         return o
 

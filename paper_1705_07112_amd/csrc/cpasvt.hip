@@ -16,6 +16,7 @@
 
 #include "../../include/cpasvt.h"
 #include "admm.hpp"
+#include "gemm_bf16x3.hpp"
 #include "gemm_f32.hpp"
 #include "shrink_fn.hpp"
 #include "spectral.hpp"
@@ -208,6 +209,21 @@ cpa_status launch_gemm(hipStream_t st, const Operand& A, const Operand& B, int M
     return CPA_OK;
 }
 
+template <int LA, int LB, class Epi>
+cpa_status launch_gemm_split(hipStream_t st, const Operand& A, const Operand& B, int M, int N, int Kd,
+                             const Epi& epi, int sc_a1, int sc_a2, int sc_coef) {
+    const int grid = ((M + 63) / 64) * ((N + 63) / 64);
+    if (grid <= 0 || Kd <= 0) return CPA_OK;
+    if (vec_operand(A, LA, Kd) && vec_operand(B, LB, Kd))
+        hipLaunchKernelGGL((gemm_bf16x3_kernel<64, 64, LA, LB, true, Epi>), dim3(grid), dim3(GTHREADS), 0, st, A, B,
+                           M, N, Kd, epi, sc_a1, sc_a2, sc_coef);
+    else
+        hipLaunchKernelGGL((gemm_bf16x3_kernel<64, 64, LA, LB, false, Epi>), dim3(grid), dim3(GTHREADS), 0, st, A, B,
+                           M, N, Kd, epi, sc_a1, sc_a2, sc_coef);
+    HIP_TRY(hipGetLastError());
+    return CPA_OK;
+}
+
 // All products use 64 x 64 output tiles: at 1024 x 1024 that is 256 workgroups,
 // one per CU, and larger outputs simply have more of them.
 template <int LA, int LB, class Epi>
@@ -248,7 +264,8 @@ cpa_status check_opts(const cpa_opts* o) {
             return fail(CPA_ERR_ARG, "power_iters must be in [1, %d]", kMaxPowerIters);
         if (!(o->power_tol >= 0.0) || !(o->margin >= 0.0)) return fail(CPA_ERR_ARG, "power_tol and margin must be >= 0");
     }
-    if (o->precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "precision %d not supported", o->precision);
+    if (o->precision != CPA_PREC_FP32 && o->precision != CPA_PREC_BF16X3)
+        return fail(CPA_ERR_UNSUPPORTED, "precision %d not supported", o->precision);
     return CPA_OK;
 }
 
@@ -329,7 +346,7 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
 
 // K-1 recurrence steps (or the K == 1 scaling), accumulating into Y.
 cpa_status enqueue_recurrence(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* X, int64_t ldx, float* Y, int64_t ldy,
-                              int K, const Work& w, bool norms_needed) {
+                              int K, const Work& w, bool norms_needed, int precision) {
     if (K == 1) {
         const int64_t total = (int64_t)m * n;
         const int grid = (int)std::min<int64_t>(4096, (total + 255) / 256);
@@ -367,11 +384,15 @@ cpa_status enqueue_recurrence(cpa_ctx* ctx, hipStream_t st, int m, int n, const 
             // Y_k G: A = Y_k (k contiguous); B(k, j) = G[k][j] = G[j][k] (G symmetric),
             // read along k so both operands take 16-byte LDS fragment reads
             Operand A = make_op(yk, ldk, m), B = make_op(w.G, d, n);
-            s = gemm_dispatch<KCONTIG, KCONTIG>(st, A, B, m, n, n, epi, SC_A1, SC_A2, SC_COEF);
+            s = precision == CPA_PREC_BF16X3
+                    ? launch_gemm_split<KCONTIG, KCONTIG>(st, A, B, m, n, n, epi, SC_A1, SC_A2, SC_COEF)
+                    : gemm_dispatch<KCONTIG, KCONTIG>(st, A, B, m, n, n, epi, SC_A1, SC_A2, SC_COEF);
         } else {
             // G Y_k: A(i, k) = G[k][i] (G symmetric; i contiguous), B = Y_k (j contiguous)
             Operand A = make_op(w.G, d, m), B = make_op(yk, ldk, n);
-            s = gemm_dispatch<XCONTIG, XCONTIG>(st, A, B, m, n, m, epi, SC_A1, SC_A2, SC_COEF);
+            s = precision == CPA_PREC_BF16X3
+                    ? launch_gemm_split<XCONTIG, XCONTIG>(st, A, B, m, n, m, epi, SC_A1, SC_A2, SC_COEF)
+                    : gemm_dispatch<XCONTIG, XCONTIG>(st, A, B, m, n, m, epi, SC_A1, SC_A2, SC_COEF);
         }
         if (s != CPA_OK) return s;
         if (eb) HIP_TRY(hipEventRecord(eb, st));
@@ -415,7 +436,7 @@ cpa_status shrink_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* 
     if ((s = fill_scalars(st, w)) != CPA_OK) return s;
     if ((s = enqueue_gram(ctx, st, m, n, X, ldx, w)) != CPA_OK) return s;
     if ((s = enqueue_bound(ctx, st, d, sh, o, w, -1)) != CPA_OK) return s;
-    if ((s = enqueue_recurrence(ctx, st, m, n, X, ldx, Y, ldy, o->K, w, info != nullptr || o->check)) != CPA_OK) return s;
+    if ((s = enqueue_recurrence(ctx, st, m, n, X, ldx, Y, ldy, o->K, w, info != nullptr || o->check, o->precision)) != CPA_OK) return s;
     if (!info && !o->check) return CPA_OK;
     double growth = 0.0;
     if ((s = read_info(st, w, o->K, m, n, info, &growth)) != CPA_OK) return s;
@@ -424,7 +445,7 @@ cpa_status shrink_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* 
         if ((s = fill_scalars(st, w)) != CPA_OK) return s;
         if ((s = enqueue_gram(ctx, st, m, n, X, ldx, w)) != CPA_OK) return s;
         if ((s = enqueue_bound(ctx, st, d, sh, o, w, 2)) != CPA_OK) return s;
-        if ((s = enqueue_recurrence(ctx, st, m, n, X, ldx, Y, ldy, o->K, w, info != nullptr || o->check)) != CPA_OK) return s;
+        if ((s = enqueue_recurrence(ctx, st, m, n, X, ldx, Y, ldy, o->K, w, info != nullptr || o->check, o->precision)) != CPA_OK) return s;
         if ((s = read_info(st, w, o->K, m, n, info, &growth)) != CPA_OK) return s;
         if (info) info->fallback = 1;
         if (growth > 1.0 + o->growth_tol)

@@ -28,6 +28,11 @@
 // rounding error several-fold; the two-level sum keeps the 1024^3 recurrence
 // inside the FP32 tolerance.  Two partial sets alternate so the add of tile t
 // waits on MFMAs issued a whole tile earlier.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
 namespace cpa {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
