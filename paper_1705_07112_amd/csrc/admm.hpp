@@ -58,8 +58,10 @@ __global__ void __launch_bounds__(256) admm_pre_kernel(AdmmPtrs P, int64_t total
 
 // z1 already holds the shrink of x.  z2 = soft(s + u2); u1 += l - z1; u2 += s - z2;
 // u3 += l + s - I.  The first workgroup also stores E_t (the pre kernel completed).
+// E_t goes to Et_base[*counter] and the counter advances, so the same launch
+// (or a replayed graph of it) fills consecutive entries.
 __global__ void __launch_bounds__(256) admm_post_kernel(AdmmPtrs P, int64_t total, float t2, const double* part,
-                                                        int npart, double* Et_out) {
+                                                        int npart, double* Et_base, int* counter) {
     __shared__ double red[8];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += stride) {
@@ -72,7 +74,7 @@ __global__ void __launch_bounds__(256) admm_post_kernel(AdmmPtrs P, int64_t tota
         P.u2[e] = P.u2[e] + s - z2;
         P.u3[e] = P.u3[e] + l + s - P.I[e];
     }
-    if (Et_out && blockIdx.x == 0) {
+    if (Et_base && blockIdx.x == 0) {
         double num = 0.0, den = 0.0;
         for (int i = threadIdx.x; i < npart; i += blockDim.x) {
             num += part[2 * i];
@@ -80,8 +82,16 @@ __global__ void __launch_bounds__(256) admm_post_kernel(AdmmPtrs P, int64_t tota
         }
         num = block_sum(num, red);
         den = block_sum(den, red);
-        if (threadIdx.x == 0) *Et_out = den > 0.0 ? sqrt(num / den) : 0.0;
+        if (threadIdx.x == 0) {
+            const int t = *counter;
+            Et_base[t] = den > 0.0 ? sqrt(num / den) : 0.0;
+            *counter = t + 1;
+        }
     }
+}
+
+__global__ void fill_i32_kernel(int* p, int n, int v) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
 }
 
 __global__ void fill_f32_kernel(float* p, int64_t n, float v) {

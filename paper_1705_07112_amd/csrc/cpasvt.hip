@@ -64,6 +64,10 @@ struct cpa_ctx {
     int warm_cap = 0;
     int warm_d = -1;           // length of the stored vector, -1 if none
     int coop_max = 0;          // co-resident power-iteration workgroups (0: not queried)
+    // captured ADMM iteration, replayed while its key matches
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t admm_exec = nullptr;
+    std::vector<char> admm_key;
 };
 
 namespace {
@@ -93,6 +97,7 @@ struct Work {
     double* scal;
     float* x;      // ADMM shrink input
     double* admm;  // ADMM E_t partial sums (2 per pre-kernel workgroup)
+    int* et_counter;  // next E_t slot
     ScalarLayout lay;
 };
 
@@ -133,7 +138,7 @@ cpa_status ensure_ws(cpa_ctx* ctx, int m, int n, int K, int maxit, bool admm, Wo
     size_t ox = 0, oa = 0;
     if (admm) {
         ox = off; off = align_up(off + sizeof(float) * (size_t)mn);
-        oa = off; off = align_up(off + sizeof(double) * 2 * kAdmmGrid);
+        oa = off; off = align_up(off + sizeof(double) * 2 * kAdmmGrid + 256);
     }
     if (off > ctx->ws_bytes) {
         if (ctx->ws) {
@@ -157,6 +162,7 @@ cpa_status ensure_ws(cpa_ctx* ctx, int m, int n, int K, int maxit, bool admm, Wo
     w.scal = reinterpret_cast<double*>(b + os);
     w.x = admm ? reinterpret_cast<float*>(b + ox) : nullptr;
     w.admm = admm ? reinterpret_cast<double*>(b + oa) : nullptr;
+    w.et_counter = admm ? reinterpret_cast<int*>(b + oa + sizeof(double) * 2 * kAdmmGrid) : nullptr;
     if (d > ctx->warm_cap) {
         if (ctx->warm) {
             HIP_TRY(hipDeviceSynchronize());
@@ -491,6 +497,8 @@ cpa_status cpa_destroy(cpa_ctx* ctx) {
     if (ctx->warm) (void)hipFree(ctx->warm);
     for (auto& L : ctx->tlog)
         for (hipEvent_t e : L.ev) (void)hipEventDestroy(e);
+    if (ctx->admm_exec) (void)hipGraphExecDestroy(ctx->admm_exec);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return CPA_OK;
 }
@@ -663,14 +671,66 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
     P.x = w.x;
     cpa_shrinkage sh = {CPA_SOFT, 0, inv_rho, 0.0, 0.0, 1.0};
     const int grid = (int)std::min<int64_t>(kAdmmGrid, (mn + 255) / 256);
-    for (int t = 0; t < iters; ++t) {
-        hipLaunchKernelGGL(admm_pre_kernel, dim3(grid), dim3(256), 0, st, P, mn, w.admm);
+    auto one_iteration = [&](hipStream_t q) -> cpa_status {
+        cpa_status r;
+        hipLaunchKernelGGL(admm_pre_kernel, dim3(grid), dim3(256), 0, q, P, mn, w.admm);
         HIP_TRY(hipGetLastError());
-        if ((s = shrink_impl(ctx, st, m, n, w.x, n, P.z1, n, &sh, opts, nullptr, w)) != CPA_OK) return s;
-        hipLaunchKernelGGL(admm_post_kernel, dim3(grid), dim3(256), 0, st, P, mn, (float)eta_over_rho,
-                           (const double*)w.admm, grid, Et_dev ? Et_dev + t : nullptr);
+        if ((r = shrink_impl(ctx, q, m, n, w.x, n, P.z1, n, &sh, opts, nullptr, w)) != CPA_OK) return r;
+        hipLaunchKernelGGL(admm_post_kernel, dim3(grid), dim3(256), 0, q, P, mn, (float)eta_over_rho,
+                           (const double*)w.admm, grid, Et_dev, w.et_counter);
         HIP_TRY(hipGetLastError());
+        return CPA_OK;
+    };
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, st, w.et_counter, 1, 0);
+    HIP_TRY(hipGetLastError());
+    int t = 0;
+    // A cold power-iteration start is run directly; the captured graph always
+    // takes the warm start (or the seeded start when warm starts are off).
+    const int d = std::min(m, n);
+    if (opts->bound == CPA_BOUND_POWER && opts->warm_start && ctx->warm_d != d) {
+        if ((s = one_iteration(st)) != CPA_OK) return s;
+        ++t;
     }
+    if (t == iters) return CPA_OK;
+    if (ctx->timing) {
+        // per-launch event timing needs direct launches
+        for (; t < iters; ++t)
+            if ((s = one_iteration(st)) != CPA_OK) return s;
+        return CPA_OK;
+    }
+    // key of the captured iteration: every pointer and scalar its launches bake in
+    std::vector<char> key;
+    auto put = [&](const void* p, size_t nb) {
+        const char* c = static_cast<const char*>(p);
+        key.insert(key.end(), c, c + nb);
+    };
+    put(&m, sizeof m); put(&n, sizeof n); put(&I_dev, sizeof I_dev); put(&state_dev, sizeof state_dev);
+    put(&Et_dev, sizeof Et_dev); put(&ctx->ws, sizeof ctx->ws); put(&ctx->warm, sizeof ctx->warm);
+    put(opts, sizeof *opts); put(&inv_rho, sizeof inv_rho); put(&eta_over_rho, sizeof eta_over_rho);
+    if (!ctx->admm_exec || key != ctx->admm_key) {
+        if (ctx->admm_exec) {
+            HIP_TRY(hipGraphExecDestroy(ctx->admm_exec));
+            ctx->admm_exec = nullptr;
+        }
+        if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        hipGraph_t g;
+        HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        const cpa_status cs = one_iteration(ctx->cap_stream);
+        const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &g);
+        if (cs != CPA_OK) {
+            if (ce == hipSuccess) (void)hipGraphDestroy(g);
+            return cs;
+        }
+        if (ce != hipSuccess) return fail(CPA_ERR_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+        const hipError_t ie = hipGraphInstantiate(&ctx->admm_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            ctx->admm_exec = nullptr;
+            return fail(CPA_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ie));
+        }
+        ctx->admm_key = key;
+    }
+    for (; t < iters; ++t) HIP_TRY(hipGraphLaunch(ctx->admm_exec, st));
     return CPA_OK;
 }
 
