@@ -182,6 +182,28 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
                             float* state_dev, int iters, double inv_rho, double eta_over_rho,
                             const cpa_opts* opts, double* Et_dev);
 
+/* Batched shrinkage of many small matrices in one persistent launch (each
+ * matrix: Algorithm 1 with T = Id, evaluated as in cpa_shrink_dense, inside one
+ * workgroup; workgroups take matrices from an atomic queue).
+ *   m_dev, n_dev, off_dev: device arrays of `batch` entries; matrix j is row-major
+ *     m_j x n_j (leading dimension n_j) at X_dev + off_j, and its result is written
+ *     at Y_dev + off_j (same shape).  X and Y must not overlap.
+ *   Limits per matrix: min(m_j, n_j) <= 64, max(m_j, n_j) <= 128; other matrices
+ *     are skipped with status 2.
+ *   shrink_dev: device array of `batch` cpa_shrinkage records, or NULL to apply
+ *     *shrink_host to every matrix.
+ *   opts: K <= 64; bound CPA_BOUND_POWER (per-matrix power iteration, as in the
+ *     dense path), CPA_BOUND_GIVEN (Lambda_dev[j]), CPA_BOUND_FROBENIUS; precision
+ *     CPA_PREC_FP32; warm_start and check are not used.
+ *   Lambda_out_dev, status_dev: optional device arrays of `batch` entries
+ *     (bound used; 0 = done, 2 = shape outside the limits).
+ * Asynchronous. */
+cpa_status cpa_shrink_batched(cpa_ctx* ctx, void* stream, int batch, const int32_t* m_dev, const int32_t* n_dev,
+                              const int64_t* off_dev, const float* X_dev, float* Y_dev,
+                              const cpa_shrinkage* shrink_dev, const cpa_shrinkage* shrink_host,
+                              const cpa_opts* opts, const double* Lambda_dev, double* Lambda_out_dev,
+                              int32_t* status_dev);
+
 /* Instrumentation: per-launch timing with HIP events.  While enabled, every
  * launch of the recurrence GEMM (which = 0) and of the Gram GEMM (which = 1) is
  * bracketed by a pair of events recorded on the caller's stream.

@@ -79,6 +79,8 @@ _SIGS = {
     "cpa_timing_read": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]),
     "cpa_rpca_init": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P]),
+    "cpa_shrink_batched": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.POINTER(CpaShrinkage),
+                                          ctypes.POINTER(CpaOpts), _P, _P, _P]),
     "cpa_rpca_iterate": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _P, ctypes.c_int, ctypes.c_double,
                                         ctypes.c_double, ctypes.POINTER(CpaOpts), _P]),
 }
@@ -229,6 +231,34 @@ def spectral_bound(X, opts: Opts):
                                     ctypes.c_void_p(X.data_ptr()), ldx, ctypes.byref(co), ctypes.byref(lam),
                                     ctypes.byref(ci)))
     return lam.value, ci.as_dict()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def shrink_batched(X, m, n, off, shrink, opts: Opts, shrink_per_matrix=None, Lambda=None, out=None,
+                   lambda_out=None, status=None):
+    """Shrinks every matrix of a packed batch (see cpa_shrink_batched).
+
+    X: 1-D float32 CUDA tensor; m, n: int32 CUDA tensors; off: int64 CUDA tensor.
+    shrink_per_matrix: optional uint8 CUDA tensor holding `batch` packed
+    cpa_shrinkage records (see shrinkage_records).  Returns Y."""
+    import torch
+    batch = int(m.numel())
+    if out is None:
+        out = torch.empty_like(X)
+    co = opts.to_c()
+    _check(lib().cpa_shrink_batched(ctypes.c_void_p(context(X.device.index or 0)), _stream(X), batch, _ptr(m),
+                                    _ptr(n), _ptr(off), _ptr(X), _ptr(out), _ptr(shrink_per_matrix),
+                                    ctypes.byref(shrink), ctypes.byref(co), _ptr(Lambda), _ptr(lambda_out),
+                                    _ptr(status)))
+    return out
+
+
+def shrinkage_records(records) -> bytes:
+    """Packs a list of CpaShrinkage into the byte layout of a cpa_shrinkage array."""
+    return b"".join(bytes(r) for r in records)
 
 
 def timing_enable(enable: bool = True, device: int = 0):

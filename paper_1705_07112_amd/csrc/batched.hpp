@@ -1,0 +1,290 @@
+// Batched shrinkage of many small matrices in one persistent launch.
+//
+// Each matrix X_j (m_j x n_j, row-major at X + off_j) is shrunk by Algorithm 1
+// (T = Id) in the Y-form, entirely inside one workgroup:
+//   Z = X_j viewed so that its short side is first: Z = X_j when m_j <= n_j,
+//       Z = X_j^T otherwise (d = min(m_j, n_j) <= 64 rows, e = max <= 128 columns);
+//   Gram G = Z Z^T (d x d) with MFMA, ||G||_F^2 in FP64;
+//   bound: power iteration on G in LDS (FP64), Lambda given, or (1+delta)||G||_F;
+//   coefficients c_k in FP64 (eq. chebychev_coeff_shifted);
+//   Y_0 = Z, Y_1 = Ghat Y_0, Y_{k+1} = 2 Ghat Y_k - Y_{k-1}, out = sum c_k Y_k with
+//   Ghat = (2/Lambda) G - I fused as (2/Lambda) G Y - Y.
+// Workgroups take matrix indices from an atomic counter until the batch is
+// exhausted (every wave reaches the exit).
+//
+// LDS: Y_k is kept transposed, YT[j][i] (j < e, i < d, k contiguous), so that
+// both MFMA operands (G rows and YT rows) are 16-byte reads along the
+// contraction index and a thread's own output positions are contiguous.  Y_{k-1}
+// and the accumulator live in the registers of the thread that owns the
+// positions (the MFMA output layout is the same at every step).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gemm_f32.hpp"
+#include "shrink_fn.hpp"
+
+namespace cpa {
+
+constexpr int BT_THREADS = 256;       // 4 waves
+constexpr int BT_DMAX = 64;           // short side
+constexpr int BT_EMAX = 128;          // long side
+constexpr int BT_DP = BT_DMAX + 4;    // LDS pitch (floats) of G and YT rows
+constexpr int BT_JB = BT_EMAX / 16;   // column blocks per wave (each wave owns one row block)
+
+// Device mirror of cpa_shrinkage (same layout).
+struct ShrinkRec {
+    int32_t kind;
+    int32_t reserved;
+    double tau, w_c, w_sigma, w_eps;
+};
+
+struct BatchArgs {
+    int batch;
+    const int32_t* m;
+    const int32_t* n;
+    const int64_t* off;
+    const float* X;
+    float* Y;
+    const ShrinkRec* shrink;   // per matrix, or nullptr
+    ShrinkParams shrink0;      // used when shrink == nullptr
+    int K;
+    int mode;                  // 0 power, 1 given, 2 Frobenius
+    const double* lambda_in;   // mode 1
+    double* lambda_out;        // nullable
+    int32_t* status;           // nullable: 0 done, 2 shape unsupported
+    int power_iters;
+    double tol, margin;
+    uint64_t seed;
+    int* queue;                // next matrix index (zeroed before launch)
+};
+
+__device__ inline double bt_block_sum(double v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(BT_THREADS) batched_kernel(BatchArgs a) {
+    __shared__ __attribute__((aligned(16))) float YT[BT_EMAX * BT_DP];
+    __shared__ __attribute__((aligned(16))) float Gs[BT_DMAX * BT_DP];
+    __shared__ double vv[BT_DMAX], ww[BT_DMAX], coef[64], red[4];
+    __shared__ int s_idx;
+    __shared__ double s_scal[4];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;   // = row block of this wave
+    const int g = lane >> 4;
+
+    for (;;) {
+        if (threadIdx.x == 0) s_idx = atomicAdd(a.queue, 1);
+        __syncthreads();
+        const int idx = s_idx;
+        __syncthreads();
+        if (idx >= a.batch) break;
+
+        const int mj = a.m[idx], nj = a.n[idx];
+        const bool trans = mj > nj;              // Z = X^T
+        const int d = trans ? nj : mj, e = trans ? mj : nj;
+        if (d < 1 || d > BT_DMAX || e > BT_EMAX) {
+            if (threadIdx.x == 0 && a.status) a.status[idx] = 2;
+            continue;
+        }
+        const float* X = a.X + a.off[idx];
+        float* Yo = a.Y + a.off[idx];
+        ShrinkParams sp = a.shrink0;
+        if (a.shrink) {
+            const ShrinkRec r = a.shrink[idx];
+            sp.kind = r.kind;
+            sp.tau = r.tau;
+            sp.w_c = r.w_c;
+            sp.w_sigma = r.w_sigma;
+            sp.w_eps = r.w_eps;
+        }
+
+        // ---- load: YT[j][i] = Z[i][j]; zero padding up to 64 x 128
+        for (int p = threadIdx.x; p < BT_EMAX * BT_DMAX; p += BT_THREADS) {
+            const int j = p / BT_DMAX, i = p % BT_DMAX;
+            float v = 0.f;
+            if (i < d && j < e) v = trans ? X[(int64_t)j * nj + i] : X[(int64_t)i * nj + j];
+            YT[j * BT_DP + i] = v;
+        }
+        __syncthreads();
+
+        // ---- Gram G[i][i'] = sum_j YT[j][i] YT[j][i'] (MFMA, k = j), wave = row block
+        const int ib = wave * 16;
+        double fro2 = 0.0;
+        {
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) {
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                for (int k0 = 0; k0 < BT_EMAX; k0 += 4) {
+                    const int k = k0 + g;
+                    const float av = YT[k * BT_DP + ib + (lane & 15)];
+                    const float bv = YT[k * BT_DP + jb * 16 + (lane & 15)];
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = ib + 4 * g + r, j = jb * 16 + (lane & 15);
+                    Gs[i * BT_DP + j] = acc[r];
+                    fro2 += (double)acc[r] * acc[r];
+                }
+            }
+        }
+        fro2 = bt_block_sum(fro2, red);
+        const double fro = sqrt(fro2);
+
+        // ---- bound
+        double Lam;
+        if (a.mode == 1) {
+            Lam = a.lambda_in[idx];
+        } else if (a.mode == 2 || !(fro > 0.0)) {
+            Lam = (1.0 + a.margin) * fro;
+        } else {
+            // power iteration on G (d x d) in LDS, FP64; start vector as in the dense path
+            if (threadIdx.x < d) {
+                const uint64_t z = a.seed + (uint64_t)(threadIdx.x + 1) * 0x9E3779B97F4A7C15ull;
+                uint64_t o = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+                o = (o ^ (o >> 27)) * 0x94D049BB133111EBull;
+                o ^= o >> 31;
+                vv[threadIdx.x] = 2.0 * ((double)(o >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+            }
+            __syncthreads();
+            double nv = bt_block_sum(threadIdx.x < d ? vv[threadIdx.x] * vv[threadIdx.x] : 0.0, red);
+            double mu = 0.0, w2 = 0.0, muprev = 0.0;
+            bool vanish = !(nv > 0.0);
+            for (int t = 1; !vanish && t <= a.power_iters; ++t) {
+                const double inv = 1.0 / sqrt(nv);
+                double wi = 0.0;
+                if (threadIdx.x < d) {
+                    for (int j = 0; j < d; ++j) wi += (double)Gs[threadIdx.x * BT_DP + j] * (vv[j] * inv);
+                    ww[threadIdx.x] = wi;
+                }
+                const double m_part = threadIdx.x < d ? vv[threadIdx.x] * inv * wi : 0.0;
+                mu = bt_block_sum(m_part, red);
+                w2 = bt_block_sum(threadIdx.x < d ? wi * wi : 0.0, red);
+                if (!(w2 > 0.0)) {
+                    vanish = true;
+                    break;
+                }
+                if (t >= 2 && fabs(mu - muprev) <= a.tol * mu) break;
+                muprev = mu;
+                if (threadIdx.x < d) vv[threadIdx.x] = ww[threadIdx.x];
+                nv = w2;
+                __syncthreads();
+            }
+            if (vanish) {
+                Lam = (1.0 + a.margin) * fro;
+            } else {
+                const double r2 = w2 - mu * mu;
+                const double r = sqrt(r2 > 0.0 ? r2 : 0.0);
+                Lam = mu + (a.margin * mu > r ? a.margin * mu : r);
+                if (Lam > (1.0 + a.margin) * fro) Lam = (1.0 + a.margin) * fro;
+            }
+        }
+        if (threadIdx.x == 0) {
+            if (a.lambda_out) a.lambda_out[idx] = Lam;
+            if (a.status) a.status[idx] = 0;
+        }
+
+        // ---- coefficients (FP64, l ascending per k)
+        for (int k = threadIdx.x; k < a.K; k += BT_THREADS) coef[k] = cheb_coeff(sp, Lam, a.K, k);
+        __syncthreads();
+        const float a1 = Lam > 0.0 ? (float)(2.0 / Lam) : 0.f;
+        const float a2 = Lam > 0.0 ? (float)(4.0 / Lam) : 0.f;
+
+        // ---- recurrence: this wave owns row block ib and every column block jb
+        f32x4 yprev[BT_JB], outv[BT_JB];
+        const int nb = (e + 15) / 16;
+        const float c0h = (float)(0.5 * coef[0]);
+#pragma unroll
+        for (int jb = 0; jb < BT_JB; ++jb) {
+            // own positions (i = ib + 4g + r, j = jb*16 + lane%16): YT[j][ib + 4g .. +3]
+            const int j = jb * 16 + (lane & 15);
+            const f32x4 y0 = *reinterpret_cast<const f32x4*>(&YT[j * BT_DP + ib + 4 * g]);
+            yprev[jb] = y0;
+            outv[jb] = c0h * y0;
+        }
+        for (int step = 0; step + 1 < a.K; ++step) {
+            const float aa = step == 0 ? a1 : a2;
+            const float bb = step == 0 ? -1.f : -2.f;
+            const float cc = step == 0 ? 0.f : -1.f;
+            const float ck = (float)coef[step + 1];
+            // A fragments: G rows ib + lane%16, k = 16 g + kk
+            float fa[16];
+            {
+                const float* row = &Gs[(ib + (lane & 15)) * BT_DP + 16 * g];
+#pragma unroll
+                for (int q = 0; q < 16; q += 4) {
+                    const f32x4 t = *reinterpret_cast<const f32x4*>(row + q);
+                    fa[q] = t[0];
+                    fa[q + 1] = t[1];
+                    fa[q + 2] = t[2];
+                    fa[q + 3] = t[3];
+                }
+            }
+            f32x4 ynew[BT_JB];
+#pragma unroll
+            for (int jb = 0; jb < BT_JB; ++jb) {
+                if (jb < nb) {
+                    const float* row = &YT[(jb * 16 + (lane & 15)) * BT_DP + 16 * g];
+                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int q = 0; q < 16; q += 4) {
+                        const f32x4 b = *reinterpret_cast<const f32x4*>(row + q);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q], b[0], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + 1], b[1], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + 2], b[2], acc, 0, 0, 0);
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + 3], b[3], acc, 0, 0, 0);
+                    }
+                    const int j = jb * 16 + (lane & 15);
+                    const f32x4 yk = *reinterpret_cast<const f32x4*>(&YT[j * BT_DP + ib + 4 * g]);
+                    f32x4 yn;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        float y = aa * acc[r] + bb * yk[r];
+                        if (step > 0) y += cc * yprev[jb][r];
+                        yn[r] = y;
+                        outv[jb][r] += ck * y;
+                    }
+                    ynew[jb] = yn;
+                    yprev[jb] = yk;
+                }
+            }
+            __syncthreads();   // every wave has read Y_k
+#pragma unroll
+            for (int jb = 0; jb < BT_JB; ++jb) {
+                if (jb < nb) {
+                    const int j = jb * 16 + (lane & 15);
+                    *reinterpret_cast<f32x4*>(&YT[j * BT_DP + ib + 4 * g]) = ynew[jb];
+                }
+            }
+            __syncthreads();
+        }
+
+        // ---- store the accumulator (out(i, j) = Y_j[i][j], or Y_j[j][i] when transposed)
+#pragma unroll
+        for (int jb = 0; jb < BT_JB; ++jb) {
+            if (jb < nb) {
+                const int j = jb * 16 + (lane & 15);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = ib + 4 * g + r;
+                    if (i < d && j < e) {
+                        if (trans)
+                            Yo[(int64_t)j * nj + i] = outv[jb][r];
+                        else
+                            Yo[(int64_t)i * nj + j] = outv[jb][r];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace cpa

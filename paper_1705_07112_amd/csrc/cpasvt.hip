@@ -16,6 +16,7 @@
 
 #include "../../include/cpasvt.h"
 #include "admm.hpp"
+#include "batched.hpp"
 #include "gemm_bf16x3.hpp"
 #include "gemm_f32.hpp"
 #include "shrink_fn.hpp"
@@ -64,6 +65,8 @@ struct cpa_ctx {
     int warm_cap = 0;
     int warm_d = -1;           // length of the stored vector, -1 if none
     int coop_max = 0;          // co-resident power-iteration workgroups (0: not queried)
+    int batch_grid = 0;        // persistent workgroups of the batched kernel (0: not queried)
+    int* queue = nullptr;      // work-queue counter of the batched kernel
     // captured ADMM iteration, replayed while its key matches
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t admm_exec = nullptr;
@@ -498,6 +501,7 @@ cpa_status cpa_destroy(cpa_ctx* ctx) {
     for (auto& L : ctx->tlog)
         for (hipEvent_t e : L.ev) (void)hipEventDestroy(e);
     if (ctx->admm_exec) (void)hipGraphExecDestroy(ctx->admm_exec);
+    if (ctx->queue) (void)hipFree(ctx->queue);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return CPA_OK;
@@ -618,6 +622,61 @@ cpa_status cpa_timing_read(cpa_ctx* ctx, int which, double* total_ms_host, int64
     }
     *total_ms_host = tot;
     *launches_host = (int64_t)L.used;
+    return CPA_OK;
+}
+
+cpa_status cpa_shrink_batched(cpa_ctx* ctx, void* stream, int batch, const int32_t* m_dev, const int32_t* n_dev,
+                              const int64_t* off_dev, const float* X_dev, float* Y_dev,
+                              const cpa_shrinkage* shrink_dev, const cpa_shrinkage* shrink_host,
+                              const cpa_opts* opts, const double* Lambda_dev, double* Lambda_out_dev,
+                              int32_t* status_dev) {
+    cpa_status s;
+    if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
+    if (batch < 0) return fail(CPA_ERR_SHAPE, "batch < 0");
+    if ((s = check_opts(opts)) != CPA_OK) return s;
+    if (opts->K > 64) return fail(CPA_ERR_ARG, "batched shrinkage supports K <= 64");
+    if (opts->precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "batched shrinkage is FP32");
+    if (batch == 0) return CPA_OK;
+    if (!m_dev || !n_dev || !off_dev || !X_dev || !Y_dev) return fail(CPA_ERR_ARG, "NULL array");
+    if (X_dev == Y_dev) return fail(CPA_ERR_ARG, "Y aliases X");
+    if (!shrink_dev && (s = check_shrinkage(shrink_host)) != CPA_OK) return s;
+    if (opts->bound == CPA_BOUND_GIVEN && !Lambda_dev) return fail(CPA_ERR_ARG, "Lambda_dev is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (ctx->batch_grid == 0) {
+        int per_cu = 0, cus = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel, BT_THREADS, 0));
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        ctx->batch_grid = std::max(1, per_cu * cus);
+    }
+    if (!ctx->queue && hipMalloc(&ctx->queue, 256) != hipSuccess) {
+        ctx->queue = nullptr;
+        return fail(CPA_ERR_ALLOC, "queue allocation failed");
+    }
+    BatchArgs a;
+    a.batch = batch;
+    a.m = m_dev;
+    a.n = n_dev;
+    a.off = off_dev;
+    a.X = X_dev;
+    a.Y = Y_dev;
+    a.shrink = reinterpret_cast<const ShrinkRec*>(shrink_dev);
+    a.shrink0 = shrink_dev ? ShrinkParams{0, 0.0, 0.0, 0.0, 1.0} : to_params(shrink_host);
+    a.K = opts->K;
+    a.mode = opts->bound == CPA_BOUND_POWER ? 0 : (opts->bound == CPA_BOUND_GIVEN ? 1 : 2);
+    a.lambda_in = Lambda_dev;
+    a.lambda_out = Lambda_out_dev;
+    a.status = status_dev;
+    a.power_iters = opts->power_iters;
+    a.tol = opts->power_tol;
+    a.margin = opts->margin;
+    a.seed = opts->seed;
+    a.queue = ctx->queue;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, st, ctx->queue, 1, 0);
+    HIP_TRY(hipGetLastError());
+    const int grid = std::min(batch, ctx->batch_grid);
+    hipLaunchKernelGGL(batched_kernel, dim3(grid), dim3(BT_THREADS), 0, st, a);
+    HIP_TRY(hipGetLastError());
     return CPA_OK;
 }
 

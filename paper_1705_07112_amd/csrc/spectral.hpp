@@ -207,6 +207,8 @@ __global__ void __launch_bounds__(kPowerThreads) power_coop_kernel(int d, const 
     }
 }
 
+constexpr int kCoefLds = 64;   // orders up to this use the parallel coefficient path
+
 // Bound rule + coefficients + recurrence scalars.  Single workgroup.
 //   mode 0: power iteration result (products 1..maxit in the slots)
 //   mode 1: Lambda given
@@ -262,7 +264,30 @@ __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int ma
     }
     __syncthreads();
     const double Lam = sLambda;
-    for (int k = threadIdx.x; k < K; k += blockDim.x) scal[SC_COEF + k] = cheb_coeff(sp, Lam, K, k);
+    if (K <= kCoefLds) {
+        // the K x K terms cos(k theta_l) h(x_l) in parallel, then each c_k sums its
+        // row with l ascending (the order of the definition)
+        __shared__ double hval[kCoefLds];
+        __shared__ double term[kCoefLds * kCoefLds];
+        const double pi = 3.14159265358979323846;
+        for (int l = threadIdx.x; l < K; l += blockDim.x) {
+            const double th = pi * (l + 0.5) / K;
+            hval[l] = Lam > 0.0 ? shrink_h(sp, 0.5 * Lam * (cos(th) + 1.0)) : 0.0;
+        }
+        __syncthreads();
+        for (int p = threadIdx.x; p < K * K; p += blockDim.x) {
+            const int k = p / K, l = p % K;
+            term[p] = cos(k * (pi * (l + 0.5) / K)) * hval[l];
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < K; k += blockDim.x) {
+            double acc = 0.0;
+            for (int l = 0; l < K; ++l) acc += term[k * K + l];
+            scal[SC_COEF + k] = Lam > 0.0 ? 2.0 / K * acc : 0.0;
+        }
+    } else {
+        for (int k = threadIdx.x; k < K; k += blockDim.x) scal[SC_COEF + k] = cheb_coeff(sp, Lam, K, k);
+    }
     if (mode == 0 && warm_out && sT >= 1) {
         // v_T = w_{T-1} / ||w_{T-1}||; w_{T-1} sits in buffer (T-1) % 2
         const double* src = ((sT - 1) & 1) ? wbuf1 : wbuf0;

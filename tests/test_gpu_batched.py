@@ -1,0 +1,124 @@
+"""Batched persistent shrinkage (one workgroup per small matrix) against the
+FP64 oracle, matrix by matrix.  Lambda is passed per matrix for parity; a
+separate test compares the in-kernel power-iteration bound with the oracle's."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import bound as obound
+from oracle import cpa as ocpa
+from oracle import metrics
+from oracle.shrinkage import Shrinkage
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+
+def _pack(mats):
+    ms = np.array([a.shape[0] for a in mats], dtype=np.int32)
+    ns = np.array([a.shape[1] for a in mats], dtype=np.int32)
+    offs = np.zeros(len(mats), dtype=np.int64)
+    offs[1:] = np.cumsum([a.size for a in mats])[:-1]
+    flat = np.concatenate([a.astype(np.float32).ravel() for a in mats]) if mats else np.zeros(0, np.float32)
+    return flat, ms, ns, offs
+
+
+def _gram(X):
+    return X.T @ X if X.shape[0] >= X.shape[1] else X @ X.T
+
+
+def _run(mats, shr, K, mode="given", lams=None, power_kw=None):
+    import torch
+    import paper_1705_07112_amd as cpa
+    flat, ms, ns, offs = _pack(mats)
+    dev = "cuda"
+    X = torch.from_numpy(flat).to(dev)
+    m = torch.from_numpy(ms).to(dev)
+    n = torch.from_numpy(ns).to(dev)
+    off = torch.from_numpy(offs).to(dev)
+    recs = torch.frombuffer(bytearray(cpa.shrinkage_records(shr)), dtype=torch.uint8).to(dev)
+    lam_in = torch.from_numpy(np.array(lams, dtype=np.float64)).to(dev) if lams is not None else None
+    lam_out = torch.zeros(len(mats), dtype=torch.float64, device=dev)
+    status = torch.full((len(mats),), -1, dtype=torch.int32, device=dev)
+    opts = cpa.Opts(K=K, bound=mode, **(power_kw or {}))
+    if mode == "given":
+        opts.Lambda = 0.0
+    Y = cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), opts, shrink_per_matrix=recs, Lambda=lam_in,
+                           lambda_out=lam_out, status=status)
+    torch.cuda.synchronize()
+    Yh = Y.cpu().numpy()
+    outs = [Yh[offs[i]:offs[i] + mats[i].size].reshape(mats[i].shape).astype(np.float64) for i in range(len(mats))]
+    return outs, lam_out.cpu().numpy(), status.cpu().numpy()
+
+
+def _mats_and_params(shapes, seed):
+    import paper_1705_07112_amd as cpa
+    mats, shr_c, shr_o, lams = [], [], [], []
+    for i, (mm, nn) in enumerate(shapes):
+        X = synth.as_f32_exact(synth.dense_lowrank(mm, nn, rank=min(4, mm, nn), noise=0.2, seed=seed + i))
+        lmax = float(np.linalg.eigvalsh(_gram(X))[-1]) if X.size else 0.0
+        tau = 0.4 * math.sqrt(lmax)
+        if i % 3 == 0:
+            shr_c.append(cpa.soft(tau)); shr_o.append(Shrinkage(0, tau))
+        elif i % 3 == 1:
+            shr_c.append(cpa.hard(tau)); shr_o.append(Shrinkage(1, tau))
+        else:
+            wc, ws = 0.3 * tau * tau, 0.05 * lmax
+            shr_c.append(cpa.weighted_fn(wc, ws, 1e-3)); shr_o.append(Shrinkage(3, 0.0, wc, ws, 1e-3))
+        mats.append(X)
+        lams.append(1.01 * lmax)
+    return mats, shr_c, shr_o, lams
+
+
+SHAPES = [(64, 40), (64, 120), (64, 64), (64, 63), (64, 65), (40, 64), (120, 64), (1, 1), (3, 5), (5, 3),
+          (16, 17), (17, 16), (64, 128), (128, 64), (33, 100), (100, 33), (2, 128), (128, 2)]
+
+
+@pytest.mark.parametrize("K", [1, 2, 16, 30])
+def test_batched_matches_oracle_given_lambda(K):
+    mats, shr_c, shr_o, lams = _mats_and_params(SHAPES, 11000 + K)
+    outs, lam_out, status = _run(mats, shr_c, K, "given", lams)
+    assert np.all(status == 0)
+    worst = 0.0
+    for X, Y, sh, lam in zip(mats, outs, shr_o, lams):
+        ref = ocpa.cpa_shrink(X, sh, lam, K)
+        err = metrics.rel_fro(Y, ref, X)
+        worst = max(worst, err)
+        assert err <= TOL32, (X.shape, K, err)
+    print(f"batched K={K}: worst rel_fro {worst:.3e} over {len(mats)} matrices", flush=True)
+    assert np.allclose(lam_out, lams)
+
+
+def test_batched_patch_groups_and_power_bound():
+    flat, ms, ns, offs, ranks, noises = synth.patch_groups(batch=96, seed=12000)
+    mats = [flat[offs[i]:offs[i] + ms[i] * ns[i]].reshape(ms[i], ns[i]).astype(np.float64) for i in range(96)]
+    import paper_1705_07112_amd as cpa
+    sig = 0.2
+    shr_c, shr_o = [], []
+    for X in mats:
+        nj = X.shape[1]
+        wc, ws = 2 * math.sqrt(2) * sig * sig * math.sqrt(nj), (8 + math.sqrt(nj)) ** 2 * sig * sig
+        shr_c.append(cpa.weighted_fn(wc, ws, 1e-6))
+        shr_o.append(Shrinkage(3, 0.0, wc, ws, 1e-6))
+    outs, lam_out, status = _run(mats, shr_c, 16, "power", None, {"power_iters": 200, "power_tol": 1e-9})
+    assert np.all(status == 0)
+    worst_l = worst_y = 0.0
+    for X, Y, sh, lam_g in zip(mats, outs, shr_o, lam_out):
+        lam_o = obound.power_bound(_gram(X), seed=0, max_iter=200, tol=1e-9)[0]
+        worst_l = max(worst_l, abs(lam_g - lam_o) / lam_o)
+        # parity of the shrink at the device's bound
+        ref = ocpa.cpa_shrink(X, sh, lam_g, 16)
+        worst_y = max(worst_y, metrics.rel_fro(Y, ref, X))
+    print(f"patch groups: bound rel diff {worst_l:.2e}, shrink rel_fro {worst_y:.2e}", flush=True)
+    assert worst_l <= 2e-6
+    assert worst_y <= TOL32
+
+
+def test_batched_rejects_out_of_range_shapes():
+    mats, shr_c, _, lams = _mats_and_params([(65, 70), (64, 129), (64, 40)], 13000)
+    outs, _, status = _run(mats, shr_c, 8, "given", lams)
+    assert list(status) == [2, 2, 0]
