@@ -54,6 +54,79 @@ def cpu_baseline(I, budget_s: float = 15.0):
                       f"K={K}, 1024x1024) in {el:.1f} s"}
 
 
+def bench_batched(cpa, torch, np, synth, timed_runs: int = 5):
+    """Batched weighted soft shrinkage of 8192 patch-group matrices (64 x U{40..120},
+    rank 4 + N(0, 0.2^2)), K = 16, per-matrix power bound, one persistent launch."""
+    import math
+    flat, ms, ns, offs, _, _ = synth.patch_groups(batch=8192)
+    dev = torch.device("cuda:0")
+    sig = 0.2
+    recs = []
+    for nj in ns:
+        wc = 2 * math.sqrt(2) * sig * sig * math.sqrt(float(nj))
+        wsg = (8.0 + math.sqrt(float(nj))) ** 2 * sig * sig
+        recs.append(cpa.weighted_fn(wc, wsg, 1e-6))
+    rec_t = torch.frombuffer(bytearray(cpa.shrinkage_records(recs)), dtype=torch.uint8).to(dev)
+    X = torch.from_numpy(flat).to(dev)
+    m = torch.from_numpy(ms).to(dev)
+    n = torch.from_numpy(ns).to(dev)
+    off = torch.from_numpy(offs).to(dev)
+    lam = torch.zeros(len(ms), dtype=torch.float64, device=dev)
+    opts = cpa.Opts(K=16)
+    Y = torch.empty_like(X)
+    for _ in range(2):
+        cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), opts, shrink_per_matrix=rec_t, out=Y, lambda_out=lam)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(timed_runs):
+        cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), opts, shrink_per_matrix=rec_t, out=Y, lambda_out=lam)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_batch = e0.elapsed_time(e1) / timed_runs
+    d = np.minimum(ms, ns).astype(np.float64)
+    e = np.maximum(ms, ns).astype(np.float64)
+    flop = float(np.sum(16 * 2.0 * d * d * e))
+    # baseline: the same matrices through per-matrix dense calls (first 128, FP32, power bound)
+    nb = 128
+    Xs = [X[int(offs[i]):int(offs[i]) + int(ms[i] * ns[i])].view(int(ms[i]), int(ns[i])) for i in range(nb)]
+    outs = [torch.empty_like(x) for x in Xs]
+    for i in range(8):
+        cpa.shrink_dense(Xs[i], recs[i], opts, out=outs[i])
+    torch.cuda.synchronize()
+    e0.record()
+    for i in range(nb):
+        cpa.shrink_dense(Xs[i], recs[i], opts, out=outs[i])
+    e1.record()
+    torch.cuda.synchronize()
+    ms_single = e0.elapsed_time(e1) / nb
+    # accuracy on a sample: vs the FP64 CPA at the device bound, and vs exact SVT
+    from oracle import cpa as ocpa
+    from oracle import exact, metrics
+    from oracle.shrinkage import Shrinkage
+    Yh = Y.cpu().numpy()
+    lamh = lam.cpu().numpy()
+    e_cpa, e_svt = [], []
+    for i in range(0, 8192, 256):
+        Xi = flat[offs[i]:offs[i] + ms[i] * ns[i]].reshape(ms[i], ns[i]).astype(np.float64)
+        Yi = Yh[offs[i]:offs[i] + ms[i] * ns[i]].reshape(ms[i], ns[i]).astype(np.float64)
+        r = recs[i]
+        sh = Shrinkage(3, 0.0, r.w_c, r.w_sigma, r.w_eps)
+        e_cpa.append(metrics.rel_fro(Yi, ocpa.cpa_shrink(Xi, sh, float(lamh[i]), 16), Xi))
+        e_svt.append(metrics.rel_fro(Yi, exact.svt_svd(Xi, sh), Xi))
+    return {
+        "workload": "8192 patch groups 64 x U{40..120}, rank 4 + N(0,0.2^2), weighted soft, K=16, power bound",
+        "value": round(8192 / (ms_batch / 1e3), 1), "unit": "matrices/s", "ms_per_batch": round(ms_batch, 4),
+        "tflops": round(flop / (ms_batch * 1e-3) / 1e12, 3),
+        "baseline_per_matrix_dense_fp32": {"value": round(1e3 / ms_single, 1), "unit": "matrices/s",
+                                           "sample": f"{nb} matrices, one cpa_shrink_dense call each"},
+        "err_vs_fp64_cpa_max": float("%.3e" % max(e_cpa)),
+        "err_vs_fp64_svt_median": float("%.3e" % float(np.median(e_svt))),
+        "err_vs_fp64_svt_max": float("%.3e" % max(e_svt)),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +134,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
@@ -172,6 +246,9 @@ def main():
         out["bf16x3"]["err_vs_fp64_cpa"] = float("%.3e" % metrics.rel_fro(
             Y2.cpu().numpy().astype(np.float64), ocpa.cpa_shrink(X64, sh, info["Lambda"], K), X64))
         out["E_t_last"] = float("%.3e" % Et[-1].item())
+
+    if not args.no_batched:
+        out["batched"] = bench_batched(cpa, torch, np, synth)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(I)
