@@ -21,6 +21,9 @@ Reading (documented as a project choice):
   * ||Phi||_F == 0 gives Lambda = 0; a vanishing product (w == 0 while
     ||Phi||_F > 0) gives Lambda = ||Phi||_F.
 
+For a sparse S the operator form caps with tr(Phi) = ||S||_F^2 instead of
+||Phi||_F (both bound lambda_max of a PSD matrix).
+
 Pins: the bound is >= the true largest eigenvalue (from eigh) on seeded
 matrices; on diagonal matrices it converges to the known maximum; the start
 vector reproduces SplitMix64's published first outputs for seed 0.
@@ -54,11 +57,14 @@ def start_vector(d: int, seed: int) -> np.ndarray:
 
 
 def power_bound(Phi: np.ndarray, seed: int = 0, max_iter: int = 100, tol: float = 1e-7,
-                delta: float = 0.01, v0=None):
-    """Returns (Lambda, mu, resid, iters, v_last)."""
+                delta: float = 0.01, v0=None, cap=None):
+    """Returns (Lambda, mu, resid, iters, v_last).
+
+    ``cap`` replaces ||Phi||_F as the guaranteed upper bound when given (the
+    operator form knows only tr(Phi) = ||S||_F^2, which is also >= lambda_max)."""
     Phi = np.asarray(Phi, dtype=np.float64)
     d = Phi.shape[0]
-    fro = math.sqrt(float(np.sum(Phi * Phi)))
+    fro = math.sqrt(float(np.sum(Phi * Phi))) if cap is None else float(cap)
     if d == 0 or fro == 0.0:
         return 0.0, 0.0, 0.0, 0, np.zeros(d)
     v = start_vector(d, seed) if v0 is None else np.asarray(v0, dtype=np.float64).copy()

@@ -163,6 +163,29 @@ def cpa_shrink_operator(B: np.ndarray, shrink, Lambda: float, K: int) -> np.ndar
     return acc
 
 
+def cpa_rows_yform(Phi: np.ndarray, Brows: np.ndarray, shrink, Lambda: float, K: int) -> np.ndarray:
+    """Rows of the m >= n Y-form result from the full Gram Phi = B^T B and the
+    selected rows of B (row r of Y_{k+1} = 2 Y_k[r] hat B - Y_{k-1}[r] needs only
+    row r).  For inputs whose Gram is cheap to form but whose H-form is not."""
+    Phi = np.asarray(Phi, dtype=np.float64)
+    Brows = np.asarray(Brows, dtype=np.float64)
+    if Lambda <= 0.0:
+        return np.zeros(Brows.shape)
+    c = chebyshev.coefficients_shifted(shrink, Lambda, K)
+    Bh = (2.0 / Lambda) * Phi - np.eye(Phi.shape[0])
+    y_prev = Brows
+    acc = 0.5 * c[0] * y_prev
+    if K == 1:
+        return acc
+    y = Brows @ Bh
+    acc = acc + c[1] * y
+    for k in range(2, K):
+        y_next = 2.0 * (y @ Bh) - y_prev
+        acc = acc + c[k] * y_next
+        y_prev, y = y, y_next
+    return acc
+
+
 def cpa_rows(B: np.ndarray, shrink, Lambda: float, K: int, rows) -> np.ndarray:
     """Selected output rows of ``cpa_shrink`` for the m >= n side: hat H is
     formed once (Algorithm 1 steps 1-10) and only B[rows] H is multiplied out

@@ -98,21 +98,34 @@ def rpca_admm(I, inv_rho: float, eta_over_rho: float, iters: int, K: int,
 
 
 def svt_complete(m, n, rows, cols, vals, tau: float, step: float, iters: int, K: int,
-                 k0: int = 1, seed: int = 0, power_iters: int = 100):
+                 seed: int = 0, power_iters: int = 100, tol_power: float = 1e-7, delta_bound: float = 0.01):
     """SVT completion with CPA shrinkage on the dense iterate (small sizes only).
-    Returns (X, residual history)."""
+
+    k0 = ceil(tau / (step ||P_Omega M||_2)) with the norm from a converged power
+    iteration (200 products, tol 1e-9); Y^0 = k0 step P_Omega(M).  Each shrink's
+    bound is a power bound capped by tr(Y^T Y) = ||Y||_F^2 (the operator-form cap),
+    warm-started from the previous vector (the first from the k0 iteration).
+    Returns (X, residual history, k0)."""
+    vals = np.asarray(vals, dtype=np.float64)
+    P = np.zeros((m, n))
+    P[rows, cols] = vals
+    G0 = P.T @ P if m >= n else P @ P.T
+    _, mu0, _, _, v = bound.power_bound(G0, seed=seed, max_iter=200, tol=1e-9, delta=delta_bound,
+                                        cap=float(np.trace(G0)))
+    nrm2 = math.sqrt(max(mu0, 0.0))
+    k0 = math.ceil(tau / (step * nrm2)) if nrm2 > 0 else 1
     Y = np.zeros((m, n))
-    Y[rows, cols] = k0 * step * np.asarray(vals, dtype=np.float64)
+    Y[rows, cols] = k0 * step * vals
     sh = soft(tau)
     X = np.zeros((m, n))
     res = []
-    nrm = math.sqrt(float(np.sum(np.asarray(vals, dtype=np.float64) ** 2)))
-    v = None
+    nrm = math.sqrt(float(vals @ vals))
     for _ in range(iters):
         Phi, _ = cpa.gram(Y)
-        Lam, _, _, _, v = bound.power_bound(Phi, seed=seed, max_iter=power_iters, v0=v)
+        Lam, _, _, _, v = bound.power_bound(Phi, seed=seed, max_iter=power_iters, tol=tol_power,
+                                            delta=delta_bound, v0=v, cap=float(np.trace(Phi)))
         X = cpa.cpa_shrink(Y, sh, Lam, K)
-        r = np.asarray(vals, dtype=np.float64) - X[rows, cols]
+        r = vals - X[rows, cols]
         Y[rows, cols] += step * r
         res.append(math.sqrt(float(r @ r)) / nrm)
-    return X, res
+    return X, res, k0

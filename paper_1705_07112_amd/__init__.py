@@ -79,6 +79,11 @@ _SIGS = {
     "cpa_timing_read": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]),
     "cpa_rpca_init": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P]),
+    "cpa_shrink_csr": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _P, _P, _P, _P, _I64,
+                                      ctypes.POINTER(CpaShrinkage), ctypes.POINTER(CpaOpts), ctypes.POINTER(CpaInfo)]),
+    "cpa_svt_complete": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _P, _P, _P, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_int, _P, _I64, ctypes.POINTER(CpaOpts), _P,
+                                        ctypes.POINTER(ctypes.c_double)]),
     "cpa_shrink_batched": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.POINTER(CpaShrinkage),
                                           ctypes.POINTER(CpaOpts), _P, _P, _P]),
     "cpa_rpca_iterate": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _P, ctypes.c_int, ctypes.c_double,
@@ -254,6 +259,36 @@ def shrink_batched(X, m, n, off, shrink, opts: Opts, shrink_per_matrix=None, Lam
                                     ctypes.byref(shrink), ctypes.byref(co), _ptr(Lambda), _ptr(lambda_out),
                                     _ptr(status)))
     return out
+
+
+def shrink_csr(m, n, rowptr, colidx, vals, shrink, opts: Opts, out=None, info: bool = False):
+    """Dense hat G(S) of a CSR matrix (int32 rowptr/colidx, float32 vals, CUDA tensors)."""
+    import torch
+    if out is None:
+        out = torch.empty((m, n), device=vals.device, dtype=torch.float32)
+    _, _, ldy = _mat(out, "out")
+    ci = CpaInfo()
+    co = opts.to_c()
+    _check(lib().cpa_shrink_csr(ctypes.c_void_p(context(vals.device.index or 0)), _stream(vals), int(m), int(n),
+                                int(vals.numel()), _ptr(rowptr), _ptr(colidx), _ptr(vals), _ptr(out), ldy,
+                                ctypes.byref(shrink), ctypes.byref(co), ctypes.byref(ci) if info else None))
+    return (out, ci.as_dict()) if info else out
+
+
+def svt_complete(m, n, rowptr, colidx, mvals, tau: float, delta: float, iters: int, opts: Opts, out=None,
+                 resid=None):
+    """SVT matrix completion on the observed CSR entries; returns (X, k0)."""
+    import torch
+    if out is None:
+        out = torch.empty((m, n), device=mvals.device, dtype=torch.float32)
+    _, _, ldx = _mat(out, "out")
+    k0 = ctypes.c_double()
+    co = opts.to_c()
+    _check(lib().cpa_svt_complete(ctypes.c_void_p(context(mvals.device.index or 0)), _stream(mvals), int(m), int(n),
+                                  int(mvals.numel()), _ptr(rowptr), _ptr(colidx), _ptr(mvals), float(tau),
+                                  float(delta), int(iters), _ptr(out), ldx, ctypes.byref(co), _ptr(resid),
+                                  ctypes.byref(k0)))
+    return out, k0.value
 
 
 def shrinkage_records(records) -> bytes:

@@ -17,6 +17,7 @@
 #include "../../include/cpasvt.h"
 #include "admm.hpp"
 #include "batched.hpp"
+#include "sparse.hpp"
 #include "gemm_bf16x3.hpp"
 #include "gemm_f32.hpp"
 #include "shrink_fn.hpp"
@@ -67,6 +68,15 @@ struct cpa_ctx {
     int coop_max = 0;          // co-resident power-iteration workgroups (0: not queried)
     int batch_grid = 0;        // persistent workgroups of the batched kernel (0: not queried)
     int* queue = nullptr;      // work-queue counter of the batched kernel
+    // sparse path: its own workspace and the cached transposed pattern
+    void* sws = nullptr;
+    size_t sws_bytes = 0;
+    int32_t* csc = nullptr;    // colptr[n+1] | crow[nnz] | csrc[nnz] | scratch[max(n, 2 nnz)]
+    size_t csc_bytes = 0;
+    const int32_t* csc_rowptr = nullptr;
+    const int32_t* csc_colidx = nullptr;
+    int csc_m = -1, csc_n = -1;
+    int64_t csc_nnz = -1;
     // captured ADMM iteration, replayed while its key matches
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t admm_exec = nullptr;
@@ -347,7 +357,7 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
     hipLaunchKernelGGL(finish_bound_kernel, dim3(1), dim3(256), 0, st, mode, o->Lambda, d, o->power_iters, o->margin,
                        (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? ctx->warm : nullptr, w.scal,
                        to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)(w.scal + w.lay.gpart()),
-                       w.lay.gwg);
+                       w.lay.gwg, 0);
     HIP_TRY(hipGetLastError());
     if (mode == 0) ctx->warm_d = d;
     return CPA_OK;
@@ -463,6 +473,224 @@ cpa_status shrink_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* 
     return CPA_OK;
 }
 
+// ---- sparse path ----------------------------------------------------------------
+
+constexpr int kSqGrid = 512;   // workgroups of the ||S||_F^2 reduction
+
+struct SpWork {
+    float* Y[2];
+    float* W;
+    int64_t ld;        // row pitch of Y and W (n rounded up to 4)
+    double* tvec;
+    double* w[2];
+    double* scal;
+    float* yv;         // SVT iterate values (nnz), when requested
+    ScalarLayout lay;
+};
+
+cpa_status ensure_sparse_ws(cpa_ctx* ctx, int m, int n, int64_t nnz, int K, int maxit, bool svt, SpWork& w) {
+    if (ctx->coop_max == 0) {
+        int per_cu = 0, cus = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, power_coop_kernel, kPowerThreads, 0));
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        ctx->coop_max = std::max(1, per_cu * cus);
+    }
+    w.ld = (n + 3) & ~int64_t(3);
+    w.lay.K = K;
+    w.lay.maxit = maxit;
+    w.lay.gwg = kSqGrid;
+    w.lay.pwg = std::max(1, std::min({64, (m + 63) / 64, ctx->coop_max}));
+    size_t off = 0;
+    const size_t oY0 = off; off = align_up(off + sizeof(float) * (size_t)m * w.ld);
+    const size_t oY1 = off; off = align_up(off + sizeof(float) * (size_t)m * w.ld);
+    const size_t oW = off; off = align_up(off + sizeof(float) * (size_t)n * w.ld);
+    const size_t oT = off; off = align_up(off + sizeof(double) * (size_t)std::max(m, 1));
+    const size_t ow0 = off; off = align_up(off + sizeof(double) * (size_t)std::max(n, 1));
+    const size_t ow1 = off; off = align_up(off + sizeof(double) * (size_t)std::max(n, 1));
+    const size_t os = off; off = align_up(off + sizeof(double) * (size_t)w.lay.total());
+    size_t oy = 0;
+    if (svt) { oy = off; off = align_up(off + sizeof(float) * (size_t)std::max<int64_t>(nnz, 1)); }
+    if (off > ctx->sws_bytes) {
+        if (ctx->sws) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipFree(ctx->sws));
+            ctx->sws = nullptr;
+            ctx->sws_bytes = 0;
+        }
+        if (hipMalloc(&ctx->sws, off) != hipSuccess) {
+            ctx->sws = nullptr;
+            return fail(CPA_ERR_ALLOC, "sparse workspace allocation of %zu bytes failed", off);
+        }
+        ctx->sws_bytes = off;
+    }
+    char* b = static_cast<char*>(ctx->sws);
+    w.Y[0] = reinterpret_cast<float*>(b + oY0);
+    w.Y[1] = reinterpret_cast<float*>(b + oY1);
+    w.W = reinterpret_cast<float*>(b + oW);
+    w.tvec = reinterpret_cast<double*>(b + oT);
+    w.w[0] = reinterpret_cast<double*>(b + ow0);
+    w.w[1] = reinterpret_cast<double*>(b + ow1);
+    w.scal = reinterpret_cast<double*>(b + os);
+    w.yv = svt ? reinterpret_cast<float*>(b + oy) : nullptr;
+    if (n > ctx->warm_cap) {
+        if (ctx->warm) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipFree(ctx->warm));
+        }
+        ctx->warm = nullptr;
+        if (hipMalloc(&ctx->warm, sizeof(double) * (size_t)std::max(n, 1)) != hipSuccess) {
+            ctx->warm_cap = 0;
+            ctx->warm_d = -1;
+            return fail(CPA_ERR_ALLOC, "warm-start vector allocation failed");
+        }
+        ctx->warm_cap = std::max(n, 1);
+        ctx->warm_d = -1;
+    }
+    return CPA_OK;
+}
+
+// The transposed pattern, rebuilt only when the CSR arrays or sizes change.
+cpa_status ensure_csc(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t nnz, const int32_t* rowptr,
+                      const int32_t* colidx) {
+    if (ctx->csc && ctx->csc_rowptr == rowptr && ctx->csc_colidx == colidx && ctx->csc_m == m && ctx->csc_n == n &&
+        ctx->csc_nnz == nnz)
+        return CPA_OK;
+    const size_t need = sizeof(int32_t) * ((size_t)n + 1 + 2 * (size_t)nnz + std::max<size_t>(n, 2 * (size_t)nnz));
+    if (need > ctx->csc_bytes) {
+        if (ctx->csc) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipFree(ctx->csc));
+            ctx->csc = nullptr;
+            ctx->csc_bytes = 0;
+        }
+        if (hipMalloc(&ctx->csc, need) != hipSuccess) {
+            ctx->csc = nullptr;
+            return fail(CPA_ERR_ALLOC, "pattern transpose allocation failed");
+        }
+        ctx->csc_bytes = need;
+    }
+    int32_t* colptr = ctx->csc;
+    int32_t* crow = colptr + n + 1;
+    int32_t* csrc = crow + nnz;
+    int32_t* scratch = csrc + nnz;   // counts, then the unsorted (row, src) pairs
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(std::max(1, std::min(1024, (n + 255) / 256))), dim3(256), 0, st, scratch,
+                       n, 0);
+    HIP_TRY(hipGetLastError());
+    const int ge = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (nnz + 255) / 256));
+    if (nnz > 0) hipLaunchKernelGGL(csc_count_kernel, dim3(ge), dim3(256), 0, st, nnz, colidx, scratch);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(csc_scan_kernel, dim3(1), dim3(SP_THREADS), 0, st, n, (const int32_t*)scratch, colptr);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(std::max(1, std::min(1024, (n + 255) / 256))), dim3(256), 0, st, scratch,
+                       n, 0);
+    HIP_TRY(hipGetLastError());
+    // unsorted pairs go to crow/csrc first, then sorted into scratch, then copied back
+    hipLaunchKernelGGL(csc_scatter_kernel, dim3(std::max(1, std::min(4096, (m + 255) / 256))), dim3(256), 0, st, m,
+                       rowptr, colidx, (const int32_t*)colptr, scratch, crow, csrc);
+    HIP_TRY(hipGetLastError());
+    int32_t* srow = scratch;
+    int32_t* ssrc = scratch + nnz;
+    hipLaunchKernelGGL(csc_sort_kernel, dim3(std::max(1, (n + 3) / 4)), dim3(256), 0, st, n, (const int32_t*)colptr,
+                       (const int32_t*)crow, (const int32_t*)csrc, srow, ssrc);
+    HIP_TRY(hipGetLastError());
+    if (nnz > 0) {
+        HIP_TRY(hipMemcpyAsync(crow, srow, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(csrc, ssrc, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, st));
+    }
+    ctx->csc_rowptr = rowptr;
+    ctx->csc_colidx = colidx;
+    ctx->csc_m = m;
+    ctx->csc_n = n;
+    ctx->csc_nnz = nnz;
+    return CPA_OK;
+}
+
+// One sparse shrink, Y = hat G(S) (dense m x n at Y, ldy), everything enqueued.
+cpa_status shrink_csr_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t nnz, const int32_t* rowptr,
+                           const int32_t* colidx, const float* val, float* Y, int64_t ldy,
+                           const cpa_shrinkage* sh, const cpa_opts* o, const SpWork& w) {
+    const int32_t* colptr = ctx->csc;
+    const int32_t* crow = colptr + n + 1;
+    const int32_t* csrc = crow + nnz;
+    const int n_tot = w.lay.total();
+    hipLaunchKernelGGL(fill_f64_kernel, dim3((n_tot + 255) / 256), dim3(256), 0, st, w.scal, n_tot, 0.0);
+    HIP_TRY(hipGetLastError());
+    // tr(S^T S) = ||S||_F^2 into the odd partial slots (even slots stay zero)
+    double* gpart = w.scal + w.lay.gpart();
+    hipLaunchKernelGGL(sq_norm_kernel, dim3(kSqGrid), dim3(256), 0, st, nnz, val, gpart);
+    HIP_TRY(hipGetLastError());
+    int mode = o->bound == CPA_BOUND_POWER ? 0 : (o->bound == CPA_BOUND_GIVEN ? 1 : 2);
+    if (mode == 0) {
+        const bool warm = o->warm_start && ctx->warm_d == n;
+        hipLaunchKernelGGL(power_init_kernel, dim3(1), dim3(256), 0, st, n, (uint64_t)o->seed,
+                           warm ? (const double*)ctx->warm : nullptr, w.w[0], w.scal, w.lay.pw_w2());
+        HIP_TRY(hipGetLastError());
+        int m_ = m, n_ = n, maxit_ = o->power_iters, pw_mu = w.lay.pw_mu(), pw_w2 = w.lay.pw_w2();
+        double* tvec = w.tvec;
+        double* wb0 = w.w[0];
+        double* wb1 = w.w[1];
+        double* part = w.scal + w.lay.ppart();
+        unsigned* counter = reinterpret_cast<unsigned*>(w.scal + SC_BARRIER);
+        double* scal = w.scal;
+        double tol = o->power_tol;
+        void* args[] = {&m_, &n_, &rowptr, &colidx, &val, &colptr, &crow, &csrc, &tvec, &wb0, &wb1,
+                        &part, &counter, &scal, &maxit_, &tol, &pw_mu, &pw_w2};
+        HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(power_op_kernel), dim3(w.lay.pwg),
+                                           dim3(kPowerThreads), args, 0, st));
+    }
+    hipLaunchKernelGGL(finish_bound_kernel, dim3(1), dim3(256), 0, st, mode, o->Lambda, n, o->power_iters, o->margin,
+                       (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? ctx->warm : nullptr, w.scal,
+                       to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)gpart, kSqGrid, 1);
+    HIP_TRY(hipGetLastError());
+    if (mode == 0) ctx->warm_d = n;
+    // Y_0 = S densified
+    const int64_t total = (int64_t)m * w.ld;
+    hipLaunchKernelGGL(fill_f32_kernel, dim3((int)std::min<int64_t>(8192, (total + 255) / 256)), dim3(256), 0, st,
+                       w.Y[0], total, 0.f);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(densify_kernel, dim3(std::min(m, 8192)), dim3(256), 0, st, m, rowptr, colidx, val, w.Y[0],
+                       w.ld);
+    HIP_TRY(hipGetLastError());
+    const int panels = (n + SP_PANEL - 1) / SP_PANEL;
+    if (o->K == 1) {
+        hipLaunchKernelGGL(scale_copy_kernel, dim3((int)std::min<int64_t>(4096, (total + 255) / 256)), dim3(256), 0,
+                           st, m, n, (const float*)w.Y[0], w.ld, Y, ldy, (const double*)w.scal);
+        HIP_TRY(hipGetLastError());
+        return CPA_OK;
+    }
+    for (int k = 0; k + 1 <= o->K - 1; ++k) {
+        const float* yk = w.Y[k & 1];
+        const float* yp = w.Y[(k + 1) & 1];
+        float* ydst = w.Y[(k + 1) & 1];
+        hipEvent_t ea, eb;
+        cpa_status s = timing_pair(ctx, 0, ea, eb);
+        if (s != CPA_OK) return s;
+        if (ea) HIP_TRY(hipEventRecord(ea, st));
+        hipLaunchKernelGGL(spmm_t_kernel, dim3(n * panels), dim3(SP_THREADS), 0, st, n, n, colptr, crow, csrc, val,
+                           yk, w.ld, w.W, w.ld);
+        HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(spmm_cheb_kernel, dim3(m * panels), dim3(SP_THREADS), 0, st, m, n, rowptr, colidx, val,
+                           (const float*)w.W, w.ld, yk, yp, ydst, w.ld, Y, ldy, (const double*)w.scal, k,
+                           (k + 1 == o->K - 1) ? 1 : 0);
+        HIP_TRY(hipGetLastError());
+        if (eb) HIP_TRY(hipEventRecord(eb, st));
+    }
+    return CPA_OK;
+}
+
+cpa_status check_csr_args(cpa_ctx* ctx, int m, int n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx,
+                          const float* val, float* Y, int64_t ldy) {
+    if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
+    if (m < 0 || n < 0 || nnz < 0) return fail(CPA_ERR_SHAPE, "negative size");
+    if (m < n) return fail(CPA_ERR_UNSUPPORTED, "sparse path needs m >= n; shrink the transpose (CSC) instead");
+    if (nnz > INT32_MAX || (int64_t)m * n > ((int64_t)1 << 33)) return fail(CPA_ERR_SHAPE, "sparse matrix too large");
+    if (m == 0 || n == 0) return CPA_OK;
+    if (!rowptr || (nnz > 0 && (!colidx || !val)) || !Y) return fail(CPA_ERR_ARG, "NULL array");
+    if (ldy < n) return fail(CPA_ERR_SHAPE, "ldy < n");
+    if (!aligned16(Y, ldy)) return fail(CPA_ERR_UNSUPPORTED, "sparse path needs a 16-byte aligned Y with ldy % 4 == 0");
+    return CPA_OK;
+}
+
 cpa_status check_dense_args(cpa_ctx* ctx, int m, int n, const float* X, int64_t ldx) {
     if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
     if (m < 0 || n < 0) return fail(CPA_ERR_SHAPE, "negative size %d x %d", m, n);
@@ -502,6 +730,8 @@ cpa_status cpa_destroy(cpa_ctx* ctx) {
         for (hipEvent_t e : L.ev) (void)hipEventDestroy(e);
     if (ctx->admm_exec) (void)hipGraphExecDestroy(ctx->admm_exec);
     if (ctx->queue) (void)hipFree(ctx->queue);
+    if (ctx->sws) (void)hipFree(ctx->sws);
+    if (ctx->csc) (void)hipFree(ctx->csc);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return CPA_OK;
@@ -677,6 +907,101 @@ cpa_status cpa_shrink_batched(cpa_ctx* ctx, void* stream, int batch, const int32
     const int grid = std::min(batch, ctx->batch_grid);
     hipLaunchKernelGGL(batched_kernel, dim3(grid), dim3(BT_THREADS), 0, st, a);
     HIP_TRY(hipGetLastError());
+    return CPA_OK;
+}
+
+cpa_status cpa_shrink_csr(cpa_ctx* ctx, void* stream, int m, int n, int64_t nnz, const int32_t* rowptr_dev,
+                          const int32_t* colidx_dev, const float* val_dev, float* Y_dev, int64_t ldy,
+                          const cpa_shrinkage* shrink, const cpa_opts* opts, cpa_info* info_host) {
+    cpa_status s;
+    if ((s = check_csr_args(ctx, m, n, nnz, rowptr_dev, colidx_dev, val_dev, Y_dev, ldy)) != CPA_OK) return s;
+    if ((s = check_shrinkage(shrink)) != CPA_OK) return s;
+    if ((s = check_opts(opts)) != CPA_OK) return s;
+    if (opts->precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "sparse path is FP32");
+    if (opts->check) return fail(CPA_ERR_UNSUPPORTED, "the growth check is not available on the sparse path");
+    if (m == 0 || n == 0) {
+        if (info_host) std::memset(info_host, 0, sizeof(*info_host));
+        return CPA_OK;
+    }
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    SpWork w;
+    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    if ((s = ensure_sparse_ws(ctx, m, n, nnz, opts->K, maxit, false, w)) != CPA_OK) return s;
+    if ((s = ensure_csc(ctx, st, m, n, nnz, rowptr_dev, colidx_dev)) != CPA_OK) return s;
+    if ((s = shrink_csr_impl(ctx, st, m, n, nnz, rowptr_dev, colidx_dev, val_dev, Y_dev, ldy, shrink, opts, w)) != CPA_OK)
+        return s;
+    if (info_host) {
+        std::vector<double> h(w.lay.total());
+        HIP_TRY(hipMemcpyAsync(h.data(), w.scal, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        std::memset(info_host, 0, sizeof(*info_host));
+        info_host->Lambda = h[SC_LAMBDA];
+        info_host->mu = h[SC_MU];
+        info_host->resid = h[SC_RESID];
+        info_host->fro_gram = h[SC_TRACE];
+        info_host->power_iters_done = (int)h[SC_ITERS];
+        if (h[SC_TIMEOUT] != 0.0) return fail(CPA_ERR_HIP, "power iteration grid barrier timed out");
+        if (!std::isfinite(h[SC_LAMBDA])) return fail(CPA_ERR_NONFINITE, "spectral bound is not finite");
+    }
+    return CPA_OK;
+}
+
+cpa_status cpa_svt_complete(cpa_ctx* ctx, void* stream, int m, int n, int64_t nnz, const int32_t* rowptr_dev,
+                            const int32_t* colidx_dev, const float* Mobs_dev, double tau, double delta, int iters,
+                            float* X_dev, int64_t ldx, const cpa_opts* opts, double* resid_dev, double* k0_host) {
+    cpa_status s;
+    if ((s = check_csr_args(ctx, m, n, nnz, rowptr_dev, colidx_dev, Mobs_dev, X_dev, ldx)) != CPA_OK) return s;
+    if ((s = check_opts(opts)) != CPA_OK) return s;
+    if (opts->precision != CPA_PREC_FP32 || opts->check) return fail(CPA_ERR_UNSUPPORTED, "unsupported option");
+    if (!(std::isfinite(tau) && tau >= 0.0 && std::isfinite(delta) && delta > 0.0) || iters < 0)
+        return fail(CPA_ERR_ARG, "tau >= 0, delta > 0 and iters >= 0 required");
+    if (m == 0 || n == 0 || iters == 0) return CPA_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    SpWork w;
+    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    if ((s = ensure_sparse_ws(ctx, m, n, nnz, opts->K, std::max(maxit, 200), true, w)) != CPA_OK) return s;
+    if ((s = ensure_csc(ctx, st, m, n, nnz, rowptr_dev, colidx_dev)) != CPA_OK) return s;
+    // k0 = ceil(tau / (delta ||P_Omega M||_2)) from a converged power iteration (one sync)
+    cpa_opts ob = *opts;
+    ob.bound = CPA_BOUND_POWER;
+    ob.power_iters = 200;
+    ob.power_tol = 1e-9;
+    ob.warm_start = 0;
+    ob.K = 1;
+    cpa_shrinkage s0 = {CPA_SOFT, 0, 0.0, 0.0, 0.0, 1.0};
+    if ((s = shrink_csr_impl(ctx, st, m, n, nnz, rowptr_dev, colidx_dev, Mobs_dev, X_dev, ldx, &s0, &ob, w)) != CPA_OK)
+        return s;
+    double mu = 0.0;
+    HIP_TRY(hipMemcpyAsync(&mu, w.scal + SC_MU, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double nrm2 = std::sqrt(std::max(mu, 0.0));
+    const double k0 = nrm2 > 0.0 ? std::ceil(tau / (delta * nrm2)) : 1.0;
+    if (k0_host) *k0_host = k0;
+    const int gv = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (nnz + 255) / 256));
+    hipLaunchKernelGGL(scale_vals_kernel, dim3(gv), dim3(256), 0, st, nnz, Mobs_dev, w.yv, (float)(k0 * delta));
+    HIP_TRY(hipGetLastError());
+    // ||P_Omega M||_F for the residual normalisation (host, once)
+    std::vector<float> hv(nnz);
+    HIP_TRY(hipMemcpyAsync(hv.data(), Mobs_dev, sizeof(float) * nnz, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    double nm = 0.0;
+    for (float v : hv) nm += (double)v * v;
+    nm = std::sqrt(nm);
+    cpa_shrinkage sh = {CPA_SOFT, 0, tau, 0.0, 0.0, 1.0};
+    const int gu = std::min(m, 4096);
+    for (int t = 0; t < iters; ++t) {
+        if ((s = shrink_csr_impl(ctx, st, m, n, nnz, rowptr_dev, colidx_dev, w.yv, X_dev, ldx, &sh, opts, w)) != CPA_OK)
+            return s;
+        // residual partials reuse the power-iteration vector buffer (m doubles >= gu)
+        hipLaunchKernelGGL(svt_update_kernel, dim3(gu), dim3(256), 0, st, m, rowptr_dev, colidx_dev, Mobs_dev,
+                           (const float*)X_dev, ldx, w.yv, (float)delta, w.tvec);
+        HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(svt_resid_kernel, dim3(1), dim3(256), 0, st, (const double*)w.tvec, gu, nm,
+                           resid_dev ? resid_dev + t : nullptr);
+        HIP_TRY(hipGetLastError());
+    }
     return CPA_OK;
 }
 

@@ -1,0 +1,341 @@
+// Sparse X: the shrinkage of a CSR matrix S (m x n, m >= n) in operator form.
+//
+// The identity X p(X^T X) = p(X X^T) X (from eq. sing_shrink_from_eig_shrink)
+// gives Y_k = T_k(Ghat_L) S with Ghat_L = (2/Lambda) S S^T - I, so one
+// recurrence step is
+//   W = S^T Y_k            (n x n, SpMM with the transposed pattern)
+//   Y_{k+1} = 2 ((2/Lambda) S W - Y_k) - Y_{k-1}   (SpMM + fused Chebyshev epilogue)
+// and neither S^T S nor S S^T is ever formed.  Y_0 = S (densified).
+//
+// Kernels
+//   csc_*            the transposed pattern (column pointers, row indices and the
+//                    CSR position of each entry, rows ascending within a column),
+//                    built once per pattern on the device;
+//   spmm_t_kernel    W[c][:] = sum_{(r,c) in S} s_rc Y[r][:], one workgroup per
+//                    (column, 1024-wide panel), panels outermost so the gathered rows of
+//                    one panel of Y stay in the Infinity Cache; rows ascending (fixed
+//                    order);
+//   spmm_cheb_kernel Z[r][:] = sum_{(r,c)} s_rc W[c][:] with the recurrence epilogue.
+//   power_op_kernel  power iteration on S^T S through two sparse products per step,
+//                    one cooperative launch (two grid barriers per product).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spectral.hpp"
+
+namespace cpa {
+
+constexpr int SP_THREADS = 256;
+constexpr int SP_PANEL = 4 * SP_THREADS;   // columns of Y / W per workgroup (float4 per thread)
+
+__global__ void csc_count_kernel(int64_t nnz, const int32_t* colidx, int32_t* cnt) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(cnt + colidx[e], 1);
+}
+
+// Exclusive scan of cnt[0..n) into colptr[0..n], single workgroup.
+__global__ void csc_scan_kernel(int n, const int32_t* cnt, int32_t* colptr) {
+    __shared__ int32_t part[SP_THREADS];
+    const int per = (n + SP_THREADS - 1) / SP_THREADS;
+    const int lo = threadIdx.x * per, hi = min(n, lo + per);
+    int32_t s = 0;
+    for (int i = lo; i < hi; ++i) s += cnt[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t run = 0;
+        for (int t = 0; t < SP_THREADS; ++t) {
+            const int32_t v = part[t];
+            part[t] = run;
+            run += v;
+        }
+        colptr[n] = run;
+    }
+    __syncthreads();
+    int32_t run = part[threadIdx.x];
+    for (int i = lo; i < hi; ++i) {
+        colptr[i] = run;
+        run += cnt[i];
+    }
+}
+
+// Places every entry in its column (order within a column arbitrary here).
+__global__ void csc_scatter_kernel(int m, const int32_t* rowptr, const int32_t* colidx, const int32_t* colptr,
+                                   int32_t* fill, int32_t* crow, int32_t* csrc) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < m; r += gridDim.x * blockDim.x) {
+        for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+            const int32_t c = colidx[e];
+            const int32_t p = colptr[c] + atomicAdd(fill + c, 1);
+            crow[p] = r;
+            csrc[p] = e;
+        }
+    }
+}
+
+// Sorts each column by row: the rank of an entry is the number of entries of
+// its column with a smaller row (rows are distinct within a column).  One wave
+// per column; results go to the second pair of arrays.
+__global__ void csc_sort_kernel(int n, const int32_t* colptr, const int32_t* crow_in, const int32_t* csrc_in,
+                                int32_t* crow, int32_t* csrc) {
+    const int lane = threadIdx.x & 63;
+    const int c = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (c >= n) return;
+    const int32_t b = colptr[c], len = colptr[c + 1] - b;
+    for (int32_t i = lane; i < len; i += 64) {
+        const int32_t r = crow_in[b + i];
+        int32_t rank = 0;
+        for (int32_t j = 0; j < len; ++j) rank += crow_in[b + j] < r ? 1 : 0;
+        crow[b + rank] = r;
+        csrc[b + rank] = csrc_in[b + i];
+    }
+}
+
+// Y0 = S (dense m x n, ld = ldy), the buffer already zeroed.
+__global__ void densify_kernel(int m, const int32_t* rowptr, const int32_t* colidx, const float* val, float* Y,
+                               int64_t ldy) {
+    for (int r = blockIdx.x; r < m; r += gridDim.x)
+        for (int32_t e = rowptr[r] + threadIdx.x; e < rowptr[r + 1]; e += blockDim.x)
+            Y[(int64_t)r * ldy + colidx[e]] = val[e];
+}
+
+__device__ inline void panel_of(int nrows, int& row, int& col0) {
+    // panels outermost: all rows of panel 0, then panel 1, ...
+    row = blockIdx.x % nrows;
+    col0 = (blockIdx.x / nrows) * SP_PANEL;
+}
+
+// W[c][j] = sum over column c of S of s_rc * Y[r][j], j in this workgroup's panel.
+__global__ void __launch_bounds__(SP_THREADS) spmm_t_kernel(int n, int ncols, const int32_t* colptr,
+                                                            const int32_t* crow, const int32_t* csrc,
+                                                            const float* val, const float* Y, int64_t ldy,
+                                                            float* W, int64_t ldw) {
+    int c, col0;
+    panel_of(n, c, col0);
+    const int j = col0 + 4 * threadIdx.x;
+    if (j >= ncols) return;
+    const bool full = j + 3 < ncols;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int32_t p = colptr[c]; p < colptr[c + 1]; ++p) {
+        const float s = val[csrc[p]];
+        const float* yr = Y + (int64_t)crow[p] * ldy + j;
+        if (full) {
+            const f32x4 y = *reinterpret_cast<const f32x4*>(yr);
+            acc += s * y;
+        } else {
+            for (int q = 0; q < 4 && j + q < ncols; ++q) acc[q] += s * yr[q];
+        }
+    }
+    float* wr = W + (int64_t)c * ldw + j;
+    if (full) {
+        *reinterpret_cast<f32x4*>(wr) = acc;
+    } else {
+        for (int q = 0; q < 4 && j + q < ncols; ++q) wr[q] = acc[q];
+    }
+}
+
+// Z[r][j] = sum over row r of S of s_rc W[c][j], then the recurrence epilogue:
+//   first step: Ynew = a1 Z - Yk,  out = c0/2 Yk + c1 Ynew
+//   later:      Ynew = a2 Z - 2 Yk - Yprev,  out += c_{k+1} Ynew
+// Ynew goes to Ydst (may equal Yprev) unless this is the last step.
+// Requires ldy, ldw, ldo % 4 == 0 and 16-byte aligned bases (checked by the host).
+__global__ void __launch_bounds__(SP_THREADS) spmm_cheb_kernel(int m, int ncols, const int32_t* rowptr,
+                                                               const int32_t* colidx, const float* val,
+                                                               const float* W, int64_t ldw, const float* Yk,
+                                                               const float* Yprev, float* Ydst, int64_t ldy,
+                                                               float* out, int64_t ldo, const double* scal,
+                                                               int step, int last) {
+    int r, col0;
+    panel_of(m, r, col0);
+    const int j = col0 + 4 * threadIdx.x;
+    if (j >= ncols) return;
+    const bool full = j + 3 < ncols;
+    f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+        const float s = val[e];
+        const float* wr = W + (int64_t)colidx[e] * ldw + j;
+        if (full) {
+            z += s * *reinterpret_cast<const f32x4*>(wr);
+        } else {
+            for (int q = 0; q < 4 && j + q < ncols; ++q) z[q] += s * wr[q];
+        }
+    }
+    float a, b, cc;
+    if (step == 0) {
+        a = (float)scal[SC_A1];
+        b = -1.f;
+        cc = 0.f;
+    } else {
+        a = (float)scal[SC_A2];
+        b = -2.f;
+        cc = -1.f;
+    }
+    const float ck = (float)scal[SC_COEF + step + 1];
+    const float c0h = (float)(0.5 * scal[SC_COEF]);
+    const int64_t oy = (int64_t)r * ldy + j, oo = (int64_t)r * ldo + j;
+    const int cnt = full ? 4 : ncols - j;
+    f32x4 yk = {0.f, 0.f, 0.f, 0.f}, yp = {0.f, 0.f, 0.f, 0.f}, o = {0.f, 0.f, 0.f, 0.f};
+    if (full) {
+        yk = *reinterpret_cast<const f32x4*>(Yk + oy);
+        if (step > 0) {
+            yp = *reinterpret_cast<const f32x4*>(Yprev + oy);
+            o = *reinterpret_cast<const f32x4*>(out + oo);
+        }
+    } else {
+        for (int q = 0; q < cnt; ++q) {
+            yk[q] = Yk[oy + q];
+            if (step > 0) {
+                yp[q] = Yprev[oy + q];
+                o[q] = out[oo + q];
+            }
+        }
+    }
+    f32x4 yn;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        float y = a * z[q] + b * yk[q];
+        if (step > 0) y += cc * yp[q];
+        yn[q] = y;
+        o[q] = step == 0 ? c0h * yk[q] + ck * y : o[q] + ck * y;
+    }
+    if (full) {
+        *reinterpret_cast<f32x4*>(out + oo) = o;
+        if (!last) *reinterpret_cast<f32x4*>(Ydst + oy) = yn;
+    } else {
+        for (int q = 0; q < cnt; ++q) {
+            out[oo + q] = o[q];
+            if (!last) Ydst[oy + q] = yn[q];
+        }
+    }
+}
+
+// ||S||_F^2 (= trace of S^T S) as per-workgroup partials in the trace slots of the
+// Gram-partial layout: part[2 b] = 0, part[2 b + 1] = partial of workgroup b.
+__global__ void sq_norm_kernel(int64_t nnz, const float* val, double* part) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
+        s += (double)val[e] * val[e];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = 0.0;
+        part[2 * blockIdx.x + 1] = s;
+    }
+}
+
+// Power iteration on G = S^T S without forming it: t = S v, w = S^T t.
+// Same stopping rule and partial-sum scheme as power_coop_kernel; the cap of
+// the bound uses tr(G) = ||S||_F^2 >= ||G||_F (written to SC_FRO2 as its square
+// by the caller's reduction: SC_FRO2 holds tr(G)^2).
+__global__ void __launch_bounds__(kPowerThreads) power_op_kernel(int m, int n, const int32_t* rowptr,
+                                                                 const int32_t* colidx, const float* val,
+                                                                 const int32_t* colptr, const int32_t* crow,
+                                                                 const int32_t* csrc, double* tvec, double* wb0,
+                                                                 double* wb1, double* part, unsigned* counter,
+                                                                 double* scal, int maxit, double tol, int pw_mu,
+                                                                 int pw_w2) {
+    __shared__ double red[kPowerThreads / 64];
+    __shared__ double bcast[2];
+    const int P = gridDim.x;
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * (kPowerThreads / 64) + (threadIdx.x >> 6);
+    const int nw = P * (kPowerThreads / 64);
+    double w2prev = scal[pw_w2 + 0];
+    double muprev = 0.0;
+    int stop = 0, vanish = !(w2prev > 0.0);
+    unsigned bar = 0;
+    int t = 1;
+    for (; !vanish && t <= maxit; ++t) {
+        const double* wp = (t & 1) ? wb0 : wb1;
+        double* wn = (t & 1) ? wb1 : wb0;
+        const double inv = 1.0 / sqrt(w2prev);
+        // t = S v   (rows over waves)
+        for (int r = gw; r < m; r += nw) {
+            double acc = 0.0;
+            for (int32_t e = rowptr[r] + lane; e < rowptr[r + 1]; e += 64) acc += (double)val[e] * (wp[colidx[e]] * inv);
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if (lane == 0) tvec[r] = acc;
+        }
+        if (!grid_barrier(counter, (++bar) * P, scal)) return;
+        // w = S^T t  (columns over waves), rows ascending within a column
+        double mu_part = 0.0, w2_part = 0.0;
+        for (int c = gw; c < n; c += nw) {
+            double acc = 0.0;
+            for (int32_t p = colptr[c] + lane; p < colptr[c + 1]; p += 64) acc += (double)val[csrc[p]] * tvec[crow[p]];
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if (lane == 0) {
+                wn[c] = acc;
+                mu_part += (wp[c] * inv) * acc;
+                w2_part += acc * acc;
+            }
+        }
+        mu_part = block_sum(mu_part, red);
+        w2_part = block_sum(w2_part, red);
+        double* pt = part + (t & 1) * 2 * P;
+        if (threadIdx.x == 0) {
+            pt[blockIdx.x] = mu_part;
+            pt[P + blockIdx.x] = w2_part;
+        }
+        if (!grid_barrier(counter, (++bar) * P, scal)) return;
+        const double mu = ordered_sum(pt, P, red);
+        const double w2 = ordered_sum(pt + P, P, red);
+        if (threadIdx.x == 0) {
+            bcast[0] = mu;
+            bcast[1] = w2;
+            if (blockIdx.x == 0) {
+                scal[pw_mu + t] = mu;
+                scal[pw_w2 + t] = w2;
+            }
+        }
+        __syncthreads();
+        const double mu_t = bcast[0], w2_t = bcast[1];
+        __syncthreads();
+        if (!(w2_t > 0.0)) {
+            vanish = 1;
+            break;
+        }
+        if (t >= 2 && fabs(mu_t - muprev) <= tol * mu_t) {
+            stop = t;
+            break;
+        }
+        muprev = mu_t;
+        w2prev = w2_t;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        scal[SC_STOP] = stop ? stop : (vanish ? 0 : maxit);
+        scal[SC_VANISH] = vanish;
+    }
+}
+
+// SVT update on the observed set (values in CSR order):
+//   r_e = M_e - X[row(e)][col(e)],  Yv_e += delta r_e,  partial sums of r^2.
+__global__ void svt_update_kernel(int m, const int32_t* rowptr, const int32_t* colidx, const float* Mv,
+                                  const float* X, int64_t ldx, float* Yv, float delta, double* part) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int r = blockIdx.x; r < m; r += gridDim.x)
+        for (int32_t e = rowptr[r] + threadIdx.x; e < rowptr[r + 1]; e += blockDim.x) {
+            const float res = Mv[e] - X[(int64_t)r * ldx + colidx[e]];
+            Yv[e] += delta * res;
+            s += (double)res * res;
+        }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// resid[t] = sqrt(sum part) / norm_M (fixed order), single workgroup.
+__global__ void svt_resid_kernel(const double* part, int np, double normM, double* resid_out) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0 && resid_out) *resid_out = normM > 0.0 ? sqrt(s) / normM : 0.0;
+}
+
+__global__ void scale_vals_kernel(int64_t nnz, const float* src, float* dst, float f) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = f * src[e];
+}
+
+}  // namespace cpa

@@ -212,11 +212,12 @@ constexpr int kCoefLds = 64;   // orders up to this use the parallel coefficient
 // Bound rule + coefficients + recurrence scalars.  Single workgroup.
 //   mode 0: power iteration result (products 1..maxit in the slots)
 //   mode 1: Lambda given
-//   mode 2: Lambda = ||G||_F
+//   mode 2: Lambda = ||G||_F (tr G when cap_trace)
 // For mode 0 the warm-start buffer receives v_T (the unit vector of the last product).
 __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int maxit, double margin,
                                     const double* wbuf0, const double* wbuf1, double* warm_out, double* scal,
-                                    ShrinkParams sp, int K, int pw_mu, int pw_w2, const double* gpart, int gwg) {
+                                    ShrinkParams sp, int K, int pw_mu, int pw_w2, const double* gpart, int gwg,
+                                    int cap_trace) {
     __shared__ double sLambda;
     __shared__ int sT;
     __shared__ double red[16];
@@ -231,7 +232,8 @@ __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int ma
     if (threadIdx.x == 0) {
         scal[SC_FRO2] = f2;
         scal[SC_TRACE] = tr;
-        const double fro = sqrt(f2 > 0.0 ? f2 : 0.0);
+        // cap_trace: only tr(G) is known (operator form); tr(G) >= ||G||_F >= lambda_max
+        const double fro = cap_trace ? tr : sqrt(f2 > 0.0 ? f2 : 0.0);
         double Lam = 0.0;
         int T = 0;
         if (mode == 1) {

@@ -369,3 +369,32 @@ def test_rpca_admm_converges_on_small_input():
     assert E[-1] < E[2]
     assert E[-1] < 2e-2
     assert all(x > 0 for x in lams)
+
+
+def test_rows_yform_matches_full():
+    X = synth.dense_lowrank(40, 12, rank=3, noise=0.2, seed=31)
+    Phi = X.T @ X
+    Lam = 1.02 * np.linalg.eigvalsh(Phi)[-1]
+    sh = soft(0.3 * math.sqrt(Lam))
+    full = cpa.cpa_shrink(X, sh, Lam, 17)
+    rows = [0, 5, 39]
+    assert np.max(np.abs(cpa.cpa_rows_yform(Phi, X[rows], sh, Lam, 17) - full[rows])) < 1e-11
+
+
+def test_power_bound_trace_cap():
+    X = synth.dense_lowrank(30, 10, rank=1, noise=0.0, seed=32)
+    Phi = X.T @ X
+    lam, mu, _, _, _ = bound.power_bound(Phi, cap=float(np.trace(Phi)))
+    # rank one: trace == lambda_max, so the trace cap still keeps the margin
+    assert lam == pytest.approx(1.01 * np.trace(Phi), rel=1e-9)
+
+
+def test_svt_reduces_residual():
+    g = synth.rng(40)
+    m, n, r = 60, 30, 2
+    M = g.standard_normal((m, r)) @ g.standard_normal((r, n))
+    idx = np.sort(g.choice(m * n, size=900, replace=False))
+    rows, cols = idx // n, idx % n
+    tau, step = 5 * math.sqrt(m * n), 1.2 * m * n / len(idx)
+    X, res, k0 = drivers.svt_complete(m, n, rows, cols, M[rows, cols], tau, step, 30, 25)
+    assert k0 >= 1 and res[-1] < res[0]
