@@ -185,13 +185,16 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
 /* Sparse shrinkage, CSR input (row pointers int32[m+1], sorted column indices
  * int32[nnz], FP32 values), m >= n (for m < n shrink the transpose, i.e. pass the
  * CSC arrays as CSR of S^T, and transpose the result).  The result is dense:
- * Y_dev (m x n, ldy, 16-byte aligned, ldy % 4 == 0) = hat G(S), evaluated in
+ * Y_dev (m x n, ldy) = hat G(S), evaluated in
  * operator form (Algorithm 1 with T = Id, sum distributed over S, and
  * X p(X^T X) = p(X X^T) X from eq. sing_shrink_from_eig_shrink):
  *   W = S^T Y_k (n x n),  Y_{k+1} = 2((2/Lambda) S W - Y_k) - Y_{k-1},  Y_0 = S,
  * so S^T S is never formed.  The power bound iterates v <- S^T (S v) and caps at
  * (1 + margin) tr(S^T S) = (1 + margin) ||S||_F^2.  The transposed pattern is built
- * on the device and cached in the context until the CSR pointers or sizes change.
+ * on the device and cached in the context until the CSR pointers or sizes change;
+ * a new pattern is first validated on the device (rowptr[0] = 0, rowptr[m] = nnz,
+ * nondecreasing, 0 <= colidx < n), which synchronises once, and a malformed one
+ * returns CPA_ERR_ARG before any kernel indexes with it.
  * FP32 only; opts->check must be 0.  Fills *info_host (synchronising) if non-null. */
 cpa_status cpa_shrink_csr(cpa_ctx* ctx, void* stream, int m, int n, int64_t nnz, const int32_t* rowptr_dev,
                           const int32_t* colidx_dev, const float* val_dev, float* Y_dev, int64_t ldy,
@@ -203,7 +206,7 @@ cpa_status cpa_shrink_csr(cpa_ctx* ctx, void* stream, int m, int n, int64_t nnz,
  *   Y^0 = k0 delta P_Omega(M), k0 = ceil(tau / (delta ||P_Omega(M)||_2)),
  *   X^t = shrink_tau(Y^{t-1})  (cpa_shrink_csr, soft threshold tau),
  *   Y^t = Y^{t-1} + delta P_Omega(M - X^t).
- * X_dev (m x n dense, ldx as for cpa_shrink_csr) receives X^iters.  resid_dev
+ * X_dev (m x n dense, ldx >= n) receives X^iters.  resid_dev
  * (device, iters doubles, nullable) receives ||P_Omega(M - X^t)||_F / ||P_Omega M||_F.
  * *k0_host (nullable) receives k0.  Synchronises once (for k0). */
 cpa_status cpa_svt_complete(cpa_ctx* ctx, void* stream, int m, int n, int64_t nnz, const int32_t* rowptr_dev,

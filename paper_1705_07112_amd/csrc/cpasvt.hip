@@ -573,6 +573,15 @@ cpa_status ensure_csc(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t nnz, c
     int32_t* crow = colptr + n + 1;
     int32_t* csrc = crow + nnz;
     int32_t* scratch = csrc + nnz;   // counts, then the unsorted (row, src) pairs
+    // a new pattern is validated once (one synchronisation) before any kernel indexes with it
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, st, scratch, 1, 0);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(csr_validate_kernel, dim3(1024), dim3(256), 0, st, m, n, nnz, rowptr, colidx, scratch);
+    HIP_TRY(hipGetLastError());
+    int bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, scratch, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (bad) return fail(CPA_ERR_ARG, "malformed CSR (row pointers or column indices)");
     hipLaunchKernelGGL(fill_i32_kernel, dim3(std::max(1, std::min(1024, (n + 255) / 256))), dim3(256), 0, st, scratch,
                        n, 0);
     HIP_TRY(hipGetLastError());
@@ -671,7 +680,7 @@ cpa_status shrink_csr_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t n
         HIP_TRY(hipGetLastError());
         hipLaunchKernelGGL(spmm_cheb_kernel, dim3(m * panels), dim3(SP_THREADS), 0, st, m, n, rowptr, colidx, val,
                            (const float*)w.W, w.ld, yk, yp, ydst, w.ld, Y, ldy, (const double*)w.scal, k,
-                           (k + 1 == o->K - 1) ? 1 : 0);
+                           (k + 1 == o->K - 1) ? 1 : 0, aligned16(Y, ldy) ? 1 : 0);
         HIP_TRY(hipGetLastError());
         if (eb) HIP_TRY(hipEventRecord(eb, st));
     }
@@ -687,7 +696,6 @@ cpa_status check_csr_args(cpa_ctx* ctx, int m, int n, int64_t nnz, const int32_t
     if (m == 0 || n == 0) return CPA_OK;
     if (!rowptr || (nnz > 0 && (!colidx || !val)) || !Y) return fail(CPA_ERR_ARG, "NULL array");
     if (ldy < n) return fail(CPA_ERR_SHAPE, "ldy < n");
-    if (!aligned16(Y, ldy)) return fail(CPA_ERR_UNSUPPORTED, "sparse path needs a 16-byte aligned Y with ldy % 4 == 0");
     return CPA_OK;
 }
 

@@ -30,6 +30,20 @@ namespace cpa {
 constexpr int SP_THREADS = 256;
 constexpr int SP_PANEL = 4 * SP_THREADS;   // columns of Y / W per workgroup (float4 per thread)
 
+// Flags a malformed CSR (rowptr[0] != 0, rowptr[m] != nnz, decreasing row
+// pointers, or a column index outside [0, n)).  Reads only rowptr[0..m] and
+// colidx[0..nnz).
+__global__ void csr_validate_kernel(int m, int n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx,
+                                    int* bad) {
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (tid == 0 && (rowptr[0] != 0 || rowptr[m] != nnz)) atomicOr(bad, 1);
+    for (int64_t r = tid; r < m; r += stride)
+        if (rowptr[r] > rowptr[r + 1]) atomicOr(bad, 1);
+    for (int64_t e = tid; e < nnz; e += stride)
+        if (colidx[e] < 0 || colidx[e] >= n) atomicOr(bad, 1);
+}
+
 __global__ void csc_count_kernel(int64_t nnz, const int32_t* colidx, int32_t* cnt) {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
         atomicAdd(cnt + colidx[e], 1);
@@ -139,13 +153,14 @@ __global__ void __launch_bounds__(SP_THREADS) spmm_t_kernel(int n, int ncols, co
 //   first step: Ynew = a1 Z - Yk,  out = c0/2 Yk + c1 Ynew
 //   later:      Ynew = a2 Z - 2 Yk - Yprev,  out += c_{k+1} Ynew
 // Ynew goes to Ydst (may equal Yprev) unless this is the last step.
-// Requires ldy, ldw, ldo % 4 == 0 and 16-byte aligned bases (checked by the host).
+// The workspace buffers (W, Y*) have row pitches % 4 == 0 and aligned bases;
+// `out_vec` says whether the caller's output allows 16-byte accesses too.
 __global__ void __launch_bounds__(SP_THREADS) spmm_cheb_kernel(int m, int ncols, const int32_t* rowptr,
                                                                const int32_t* colidx, const float* val,
                                                                const float* W, int64_t ldw, const float* Yk,
                                                                const float* Yprev, float* Ydst, int64_t ldy,
                                                                float* out, int64_t ldo, const double* scal,
-                                                               int step, int last) {
+                                                               int step, int last, int out_vec) {
     int r, col0;
     panel_of(m, r, col0);
     const int j = col0 + 4 * threadIdx.x;
@@ -178,17 +193,18 @@ __global__ void __launch_bounds__(SP_THREADS) spmm_cheb_kernel(int m, int ncols,
     f32x4 yk = {0.f, 0.f, 0.f, 0.f}, yp = {0.f, 0.f, 0.f, 0.f}, o = {0.f, 0.f, 0.f, 0.f};
     if (full) {
         yk = *reinterpret_cast<const f32x4*>(Yk + oy);
-        if (step > 0) {
-            yp = *reinterpret_cast<const f32x4*>(Yprev + oy);
-            o = *reinterpret_cast<const f32x4*>(out + oo);
-        }
+        if (step > 0) yp = *reinterpret_cast<const f32x4*>(Yprev + oy);
     } else {
         for (int q = 0; q < cnt; ++q) {
             yk[q] = Yk[oy + q];
-            if (step > 0) {
-                yp[q] = Yprev[oy + q];
-                o[q] = out[oo + q];
-            }
+            if (step > 0) yp[q] = Yprev[oy + q];
+        }
+    }
+    if (step > 0) {
+        if (full && out_vec) {
+            o = *reinterpret_cast<const f32x4*>(out + oo);
+        } else {
+            for (int q = 0; q < cnt; ++q) o[q] = out[oo + q];
         }
     }
     f32x4 yn;
@@ -199,13 +215,16 @@ __global__ void __launch_bounds__(SP_THREADS) spmm_cheb_kernel(int m, int ncols,
         yn[q] = y;
         o[q] = step == 0 ? c0h * yk[q] + ck * y : o[q] + ck * y;
     }
-    if (full) {
+    if (full && out_vec) {
         *reinterpret_cast<f32x4*>(out + oo) = o;
-        if (!last) *reinterpret_cast<f32x4*>(Ydst + oy) = yn;
     } else {
-        for (int q = 0; q < cnt; ++q) {
-            out[oo + q] = o[q];
-            if (!last) Ydst[oy + q] = yn[q];
+        for (int q = 0; q < cnt; ++q) out[oo + q] = o[q];
+    }
+    if (!last) {
+        if (full) {
+            *reinterpret_cast<f32x4*>(Ydst + oy) = yn;
+        } else {
+            for (int q = 0; q < cnt; ++q) Ydst[oy + q] = yn[q];
         }
     }
 }
