@@ -225,15 +225,89 @@ cpa_status cpa_svt_complete(cpa_ctx* ctx, void* stream, int m, int n, int64_t nn
  *     *shrink_host to every matrix.
  *   opts: K <= 64; bound CPA_BOUND_POWER (per-matrix power iteration, as in the
  *     dense path), CPA_BOUND_GIVEN (Lambda_dev[j]), CPA_BOUND_FROBENIUS; precision
- *     CPA_PREC_FP32; warm_start and check are not used.
+ *     CPA_PREC_FP32; warm_start is not used.  With check = 1 every matrix is
+ *     tested after its recurrence: ||Y_{K-1}||_F <= (1 + growth_tol) ||X_j||_F
+ *     (inside [0, Lambda] every |T_k| <= 1; above it T_k grows with k, so the
+ *     last term is the largest); a failing matrix is redone once with
+ *     Lambda = (1 + margin) ||Gram||_F.  No synchronisation.
  *   Lambda_out_dev, status_dev: optional device arrays of `batch` entries
- *     (bound used; 0 = done, 2 = shape outside the limits).
+ *     (bound used; status 0 = done, 1 = redone with the fallback bound,
+ *     2 = shape outside the limits, 3 = growth check failed at the last bound).
  * Asynchronous. */
 cpa_status cpa_shrink_batched(cpa_ctx* ctx, void* stream, int batch, const int32_t* m_dev, const int32_t* n_dev,
                               const int64_t* off_dev, const float* X_dev, float* Y_dev,
                               const cpa_shrinkage* shrink_dev, const cpa_shrinkage* shrink_host,
                               const cpa_opts* opts, const double* Lambda_dev, double* Lambda_out_dev,
                               int32_t* status_dev);
+
+/* ---- Learned bound and order predictor (not in the paper).  It stands in for
+ * the maximum-eigenvalue step of Algorithm 1 and chooses the order alpha per
+ * matrix, for the batched path.
+ *
+ * Model: a perceptron 3 -> 64 -> 64 -> 2 with tanh hidden units, stored as
+ * CPA_PRED_MODEL_FLOATS floats (device memory, 16-byte aligned):
+ *   W1[64][3] | b1[64] | W2[64][64] | b2[64] | W3[2][64] | b3[2]   (out x in, row-major;
+ *   CPA_PRED_PARAMS trainable parameters) | mean[3] | inv_std[3] | 2 unused.
+ * Features of a matrix X (m x n, Gram G): f = (log ||X||_F, log ||G||_F^2, log(m n));
+ * the network sees x = (f - mean) * inv_std and returns y = (y0, y1), read as
+ *   Lambda = (1 + margin) ||G||_F exp(min(y0, 0))      (never above the Frobenius bound)
+ *   K_j    = clamp(ceil(exp(y1)), K_min, opts.K).
+ * Training loss: pinball (quantile) loss, mean over samples and both outputs of
+ * max(q_o r, (q_o - 1) r), r = target - y; a high q_0 makes y0 err on the side
+ * of a larger Lambda.  Optimiser: Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias
+ * corrected). */
+#define CPA_PRED_PARAMS 4546
+#define CPA_PRED_MODEL_FLOATS 4554
+
+/* Features of every matrix of a batch (layout as in cpa_shrink_batched):
+ * feat_dev receives batch x 3 floats, computed exactly as the predicted path
+ * computes them (FP32 MFMA Gram, FP64 sums).  A zero matrix gives -inf for the
+ * first two.  status_dev (nullable): 0, or 2 for a shape outside the limits
+ * (its features are not written).  Asynchronous. */
+cpa_status cpa_batched_features(cpa_ctx* ctx, void* stream, int batch, const int32_t* m_dev, const int32_t* n_dev,
+                                const int64_t* off_dev, const float* X_dev, float* feat_dev, int32_t* status_dev);
+
+/* cpa_shrink_batched with the bound and the order taken from the predictor
+ * model_dev (see above) instead of a power iteration: per matrix the Gram, its
+ * features, the network, then the coefficients and the recurrence at
+ * (Lambda, K_j).  opts.K is the largest order (<= 64), K_min the smallest.
+ * With opts.check = 1, a matrix whose growth test fails is redone once with the
+ * power-iteration bound of opts (status 1).  K_out_dev (nullable, int32 per
+ * matrix) receives K_j; Lambda_out_dev and status_dev as in cpa_shrink_batched.
+ * Asynchronous. */
+cpa_status cpa_shrink_batched_predicted(cpa_ctx* ctx, void* stream, int batch, const int32_t* m_dev,
+                                        const int32_t* n_dev, const int64_t* off_dev, const float* X_dev,
+                                        float* Y_dev, const cpa_shrinkage* shrink_dev,
+                                        const cpa_shrinkage* shrink_host, const cpa_opts* opts,
+                                        const float* model_dev, int32_t K_min, double* Lambda_out_dev,
+                                        int32_t* K_out_dev, int32_t* status_dev);
+
+/* Network outputs for n feature rows: y_dev (n x 2) = net(feat_dev (n x 3)).
+ * Asynchronous. */
+cpa_status cpa_predictor_forward(cpa_ctx* ctx, void* stream, int64_t n, const float* feat_dev,
+                                 const float* model_dev, float* y_dev);
+
+/* Gradient of the pinball loss over all n samples (targets targ_dev, n x 2;
+ * quantiles_host[2] in (0, 1)) with respect to the CPA_PRED_PARAMS parameters:
+ * grad_dev receives CPA_PRED_PARAMS floats; loss_dev (nullable, one double)
+ * receives the loss.  Per-workgroup partials are summed in a fixed order, so
+ * the result does not depend on scheduling.  Asynchronous. */
+cpa_status cpa_predictor_grad(cpa_ctx* ctx, void* stream, int64_t n, const float* feat_dev, const float* targ_dev,
+                              const float* quantiles_host, const float* model_dev, float* grad_dev,
+                              double* loss_dev);
+
+/* Minibatch training: `epochs` passes over the n samples in their stored order,
+ * minibatches of batch_size (<= 16384; the last one of a pass may be smaller),
+ * one Adam step per minibatch on the parameters of model_dev (updated in place;
+ * the normalisation entries are not trained).  adam_dev holds 2 x CPA_PRED_PARAMS
+ * floats (first moments, then second moments), zero before the first call;
+ * *step_io_host is the Adam step count, 0 before the first call, advanced by
+ * the steps taken.  epoch_loss_dev (nullable, `epochs` doubles) receives the
+ * mean minibatch loss of every pass, measured before each step's update.
+ * Asynchronous (the host only enqueues). */
+cpa_status cpa_predictor_train(cpa_ctx* ctx, void* stream, int64_t n, const float* feat_dev, const float* targ_dev,
+                               const float* quantiles_host, int32_t batch_size, int32_t epochs, float lr,
+                               float* model_dev, float* adam_dev, int64_t* step_io_host, double* epoch_loss_dev);
 
 /* Instrumentation: per-launch timing with HIP events.  While enabled, every
  * launch of the recurrence GEMM (which = 0) and of the Gram GEMM (which = 1) is

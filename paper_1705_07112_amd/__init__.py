@@ -86,6 +86,16 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_double)]),
     "cpa_shrink_batched": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.POINTER(CpaShrinkage),
                                           ctypes.POINTER(CpaOpts), _P, _P, _P]),
+    "cpa_batched_features": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P]),
+    "cpa_shrink_batched_predicted": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P,
+                                                    ctypes.POINTER(CpaShrinkage), ctypes.POINTER(CpaOpts), _P,
+                                                    ctypes.c_int32, _P, _P, _P]),
+    "cpa_predictor_forward": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P, _P]),
+    "cpa_predictor_grad": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P, ctypes.POINTER(ctypes.c_float), _P, _P,
+                                          _P]),
+    "cpa_predictor_train": (ctypes.c_int, [_P, _P, ctypes.c_int64, _P, _P, ctypes.POINTER(ctypes.c_float),
+                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_float, _P, _P,
+                                           ctypes.POINTER(ctypes.c_int64), _P]),
     "cpa_rpca_iterate": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _P, ctypes.c_int, ctypes.c_double,
                                         ctypes.c_double, ctypes.POINTER(CpaOpts), _P]),
 }
@@ -259,6 +269,78 @@ def shrink_batched(X, m, n, off, shrink, opts: Opts, shrink_per_matrix=None, Lam
                                     ctypes.byref(shrink), ctypes.byref(co), _ptr(Lambda), _ptr(lambda_out),
                                     _ptr(status)))
     return out
+
+
+PRED_PARAMS = 4546
+PRED_MODEL_FLOATS = 4554
+
+
+def batched_features(X, m, n, off, out=None, status=None):
+    """Predictor features (batch x 3 float32) of every matrix of a packed batch."""
+    import torch
+    batch = int(m.numel())
+    if out is None:
+        out = torch.empty((batch, 3), device=X.device, dtype=torch.float32)
+    _check(lib().cpa_batched_features(ctypes.c_void_p(context(X.device.index or 0)), _stream(X), batch, _ptr(m),
+                                      _ptr(n), _ptr(off), _ptr(X), _ptr(out), _ptr(status)))
+    return out
+
+
+def shrink_batched_predicted(X, m, n, off, shrink, opts: Opts, model, K_min: int = 2, shrink_per_matrix=None,
+                             out=None, lambda_out=None, K_out=None, status=None):
+    """Batched shrinkage with Lambda and K_j from the predictor `model` (float32 CUDA
+    tensor of PRED_MODEL_FLOATS entries); opts.K is the largest order."""
+    import torch
+    batch = int(m.numel())
+    if out is None:
+        out = torch.empty_like(X)
+    if model.dtype != torch.float32 or model.numel() != PRED_MODEL_FLOATS or not model.is_contiguous():
+        raise ValueError("model must be a contiguous float32 tensor of %d entries" % PRED_MODEL_FLOATS)
+    co = opts.to_c()
+    _check(lib().cpa_shrink_batched_predicted(ctypes.c_void_p(context(X.device.index or 0)), _stream(X), batch,
+                                              _ptr(m), _ptr(n), _ptr(off), _ptr(X), _ptr(out),
+                                              _ptr(shrink_per_matrix), ctypes.byref(shrink), ctypes.byref(co),
+                                              _ptr(model), int(K_min), _ptr(lambda_out), _ptr(K_out), _ptr(status)))
+    return out
+
+
+def _quantiles(q):
+    return (ctypes.c_float * 2)(float(q[0]), float(q[1]))
+
+
+def predictor_forward(feat, model, out=None):
+    """Network outputs (n x 2) for feature rows feat (n x 3), both float32 CUDA tensors."""
+    import torch
+    n = int(feat.shape[0])
+    if out is None:
+        out = torch.empty((n, 2), device=feat.device, dtype=torch.float32)
+    _check(lib().cpa_predictor_forward(ctypes.c_void_p(context(feat.device.index or 0)), _stream(feat), n,
+                                       _ptr(feat.contiguous()), _ptr(model), _ptr(out)))
+    return out
+
+
+def predictor_grad(feat, targ, model, quantiles=(0.99, 0.9)):
+    """(gradient (PRED_PARAMS float32), loss (float64 tensor of 1)) of the pinball loss."""
+    import torch
+    n = int(feat.shape[0])
+    grad = torch.empty(PRED_PARAMS, device=feat.device, dtype=torch.float32)
+    loss = torch.empty(1, device=feat.device, dtype=torch.float64)
+    _check(lib().cpa_predictor_grad(ctypes.c_void_p(context(feat.device.index or 0)), _stream(feat), n,
+                                    _ptr(feat), _ptr(targ), _quantiles(quantiles), _ptr(model), _ptr(grad),
+                                    _ptr(loss)))
+    return grad, loss
+
+
+def predictor_train(feat, targ, model, adam_state, step: int, quantiles=(0.99, 0.9), batch_size: int = 1024,
+                    epochs: int = 1, lr: float = 1e-3, epoch_loss=None):
+    """Runs `epochs` passes of minibatch Adam on `model` in place; returns the new step count."""
+    n = int(feat.shape[0])
+    st = ctypes.c_int64(int(step))
+    _check(lib().cpa_predictor_train(ctypes.c_void_p(context(feat.device.index or 0)), _stream(feat), n,
+                                     _ptr(feat), _ptr(targ), _quantiles(quantiles), int(batch_size), int(epochs),
+                                     float(lr), _ptr(model), _ptr(adam_state), ctypes.byref(st),
+                                     _ptr(epoch_loss)))
+    return int(st.value)
 
 
 def shrink_csr(m, n, rowptr, colidx, vals, shrink, opts: Opts, out=None, info: bool = False):

@@ -5,10 +5,16 @@
 //   Z = X_j viewed so that its short side is first: Z = X_j when m_j <= n_j,
 //       Z = X_j^T otherwise (d = min(m_j, n_j) <= 64 rows, e = max <= 128 columns);
 //   Gram G = Z Z^T (d x d) with MFMA, ||G||_F^2 in FP64;
-//   bound: power iteration on G in LDS (FP64), Lambda given, or (1+delta)||G||_F;
+//   bound: power iteration on G in LDS (FP64), Lambda given, (1+delta)||G||_F, or
+//       the learned predictor (features of G -> perceptron -> Lambda and K_j);
 //   coefficients c_k in FP64 (eq. chebychev_coeff_shifted);
 //   Y_0 = Z, Y_1 = Ghat Y_0, Y_{k+1} = 2 Ghat Y_k - Y_{k-1}, out = sum c_k Y_k with
 //   Ghat = (2/Lambda) G - I fused as (2/Lambda) G Y - Y.
+// With the growth check on, ||Y_{K-1}||_F <= (1 + tol) ||X||_F is tested after
+// the recurrence (for eigenvalues inside [0, Lambda] every |T_k| <= 1, and above
+// Lambda T_k grows with k, so the last Y_k is the largest); on failure the
+// matrix is redone once with a safer bound (predictor -> power iteration,
+// power or given -> Frobenius).
 // Workgroups take matrix indices from an atomic counter until the batch is
 // exhausted (every wave reaches the exit).
 //
@@ -23,6 +29,7 @@
 #include <stdint.h>
 
 #include "gemm_f32.hpp"
+#include "mlp.hpp"
 #include "shrink_fn.hpp"
 
 namespace cpa {
@@ -49,11 +56,18 @@ struct BatchArgs {
     float* Y;
     const ShrinkRec* shrink;   // per matrix, or nullptr
     ShrinkParams shrink0;      // used when shrink == nullptr
-    int K;
-    int mode;                  // 0 power, 1 given, 2 Frobenius
+    int K;                     // order (the maximum order in mode 3)
+    int mode;                  // 0 power, 1 given, 2 Frobenius, 3 predictor, 4 features only
     const double* lambda_in;   // mode 1
     double* lambda_out;        // nullable
-    int32_t* status;           // nullable: 0 done, 2 shape unsupported
+    int32_t* status;           // nullable: 0 done, 1 redone with the fallback bound,
+                               //           2 shape unsupported, 3 growth check failed at the last bound
+    float* feat_out;           // nullable: 3 features per matrix
+    const float* model;        // mode 3: predictor model
+    int K_min;                 // mode 3: smallest order
+    int32_t* K_out;            // nullable: order used
+    int check;                 // growth check on/off
+    double growth_tol;
     int power_iters;
     double tol, margin;
     uint64_t seed;
@@ -78,6 +92,7 @@ __global__ void __launch_bounds__(BT_THREADS) batched_kernel(BatchArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;   // = row block of this wave
     const int g = lane >> 4;
+    f32x4 yprev[BT_JB], outv[BT_JB];
 
     for (;;) {
         if (threadIdx.x == 0) s_idx = atomicAdd(a.queue, 1);
@@ -105,18 +120,21 @@ __global__ void __launch_bounds__(BT_THREADS) batched_kernel(BatchArgs a) {
             sp.w_eps = r.w_eps;
         }
 
-        // ---- load: YT[j][i] = Z[i][j]; zero padding up to 64 x 128
-        for (int p = threadIdx.x; p < BT_EMAX * BT_DMAX; p += BT_THREADS) {
-            const int j = p / BT_DMAX, i = p % BT_DMAX;
-            float v = 0.f;
-            if (i < d && j < e) v = trans ? X[(int64_t)j * nj + i] : X[(int64_t)i * nj + j];
-            YT[j * BT_DP + i] = v;
-        }
-        __syncthreads();
+        auto load_z = [&]() {
+            // YT[j][i] = Z[i][j]; zero padding up to 64 x 128
+            for (int p = threadIdx.x; p < BT_EMAX * BT_DMAX; p += BT_THREADS) {
+                const int j = p / BT_DMAX, i = p % BT_DMAX;
+                float v = 0.f;
+                if (i < d && j < e) v = trans ? X[(int64_t)j * nj + i] : X[(int64_t)i * nj + j];
+                YT[j * BT_DP + i] = v;
+            }
+            __syncthreads();
+        };
+        load_z();
 
         // ---- Gram G[i][i'] = sum_j YT[j][i] YT[j][i'] (MFMA, k = j), wave = row block
         const int ib = wave * 16;
-        double fro2 = 0.0;
+        double fro2 = 0.0, tr = 0.0;
         {
 #pragma unroll
             for (int jb = 0; jb < 4; ++jb) {
@@ -132,153 +150,201 @@ __global__ void __launch_bounds__(BT_THREADS) batched_kernel(BatchArgs a) {
                     const int i = ib + 4 * g + r, j = jb * 16 + (lane & 15);
                     Gs[i * BT_DP + j] = acc[r];
                     fro2 += (double)acc[r] * acc[r];
+                    if (i == j) tr += (double)acc[r];
                 }
             }
         }
         fro2 = bt_block_sum(fro2, red);
+        tr = bt_block_sum(tr, red);
         const double fro = sqrt(fro2);
+        // features: log ||X||_F (= log sqrt(tr Gram)), log ||Gram||_F^2, log(m n)
+        const float f0 = (float)(0.5 * log(tr)), f1 = (float)log(fro2), f2 = (float)log((double)mj * (double)nj);
+        if (a.feat_out && threadIdx.x == 0) {
+            a.feat_out[3 * (int64_t)idx] = f0;
+            a.feat_out[3 * (int64_t)idx + 1] = f1;
+            a.feat_out[3 * (int64_t)idx + 2] = f2;
+        }
+        if (a.mode == 4) {
+            if (threadIdx.x == 0 && a.status) a.status[idx] = 0;
+            continue;
+        }
 
-        // ---- bound
-        double Lam;
-        if (a.mode == 1) {
-            Lam = a.lambda_in[idx];
-        } else if (a.mode == 2 || !(fro > 0.0)) {
-            Lam = (1.0 + a.margin) * fro;
-        } else {
-            // power iteration on G (d x d) in LDS, FP64; start vector as in the dense path
-            if (threadIdx.x < d) {
-                const uint64_t z = a.seed + (uint64_t)(threadIdx.x + 1) * 0x9E3779B97F4A7C15ull;
-                uint64_t o = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-                o = (o ^ (o >> 27)) * 0x94D049BB133111EBull;
-                o ^= o >> 31;
-                vv[threadIdx.x] = 2.0 * ((double)(o >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+        int mode = a.mode;
+        int Kj = a.K;
+        double Lam = 0.0;
+        if (mode == 3) {
+            if (fro > 0.0) {
+                float y0, y1;
+                mlp_infer_wg(a.model, f0, f1, f2, reinterpret_cast<float*>(vv), reinterpret_cast<float*>(s_scal), y0, y1);
+                const double r = exp((double)(y0 < 0.f ? y0 : 0.f));   // Lambda <= (1 + margin) ||G||_F
+                Lam = (1.0 + a.margin) * fro * r;
+                const double kf = ceil(exp((double)y1));
+                Kj = kf > (double)a.K ? a.K : (kf < (double)a.K_min ? a.K_min : (int)kf);
+            } else {
+                Kj = a.K_min;
             }
-            __syncthreads();
-            double nv = bt_block_sum(threadIdx.x < d ? vv[threadIdx.x] * vv[threadIdx.x] : 0.0, red);
-            double mu = 0.0, w2 = 0.0, muprev = 0.0;
-            bool vanish = !(nv > 0.0);
-            for (int t = 1; !vanish && t <= a.power_iters; ++t) {
-                const double inv = 1.0 / sqrt(nv);
-                double wi = 0.0;
+        }
+        int status = 0;
+        for (int attempt = 0;; ++attempt) {
+            if (attempt > 0) load_z();
+            // ---- bound
+            if (mode == 1) {
+                Lam = a.lambda_in[idx];
+            } else if (mode == 2 || !(fro > 0.0)) {
+                Lam = (1.0 + a.margin) * fro;
+            } else if (mode == 0) {
+                // power iteration on G (d x d) in LDS, FP64; start vector as in the dense path
                 if (threadIdx.x < d) {
-                    for (int j = 0; j < d; ++j) wi += (double)Gs[threadIdx.x * BT_DP + j] * (vv[j] * inv);
-                    ww[threadIdx.x] = wi;
+                    const uint64_t z = a.seed + (uint64_t)(threadIdx.x + 1) * 0x9E3779B97F4A7C15ull;
+                    uint64_t o = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+                    o = (o ^ (o >> 27)) * 0x94D049BB133111EBull;
+                    o ^= o >> 31;
+                    vv[threadIdx.x] = 2.0 * ((double)(o >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
                 }
-                const double m_part = threadIdx.x < d ? vv[threadIdx.x] * inv * wi : 0.0;
-                mu = bt_block_sum(m_part, red);
-                w2 = bt_block_sum(threadIdx.x < d ? wi * wi : 0.0, red);
-                if (!(w2 > 0.0)) {
-                    vanish = true;
-                    break;
+                __syncthreads();
+                double nv = bt_block_sum(threadIdx.x < d ? vv[threadIdx.x] * vv[threadIdx.x] : 0.0, red);
+                double mu = 0.0, w2 = 0.0, muprev = 0.0;
+                bool vanish = !(nv > 0.0);
+                for (int t = 1; !vanish && t <= a.power_iters; ++t) {
+                    const double inv = 1.0 / sqrt(nv);
+                    double wi = 0.0;
+                    if (threadIdx.x < d) {
+                        for (int j = 0; j < d; ++j) wi += (double)Gs[threadIdx.x * BT_DP + j] * (vv[j] * inv);
+                        ww[threadIdx.x] = wi;
+                    }
+                    const double m_part = threadIdx.x < d ? vv[threadIdx.x] * inv * wi : 0.0;
+                    mu = bt_block_sum(m_part, red);
+                    w2 = bt_block_sum(threadIdx.x < d ? wi * wi : 0.0, red);
+                    if (!(w2 > 0.0)) {
+                        vanish = true;
+                        break;
+                    }
+                    if (t >= 2 && fabs(mu - muprev) <= a.tol * mu) break;
+                    muprev = mu;
+                    if (threadIdx.x < d) vv[threadIdx.x] = ww[threadIdx.x];
+                    nv = w2;
+                    __syncthreads();
                 }
-                if (t >= 2 && fabs(mu - muprev) <= a.tol * mu) break;
-                muprev = mu;
-                if (threadIdx.x < d) vv[threadIdx.x] = ww[threadIdx.x];
-                nv = w2;
+                if (vanish) {
+                    Lam = (1.0 + a.margin) * fro;
+                } else {
+                    const double r2 = w2 - mu * mu;
+                    const double r = sqrt(r2 > 0.0 ? r2 : 0.0);
+                    Lam = mu + (a.margin * mu > r ? a.margin * mu : r);
+                    if (Lam > (1.0 + a.margin) * fro) Lam = (1.0 + a.margin) * fro;
+                }
+            }
+
+            // ---- coefficients (FP64, l ascending per k)
+            __syncthreads();   // coef is rewritten on a second attempt
+            for (int k = threadIdx.x; k < Kj; k += BT_THREADS) coef[k] = cheb_coeff(sp, Lam, Kj, k);
+            __syncthreads();
+            const float a1 = Lam > 0.0 ? (float)(2.0 / Lam) : 0.f;
+            const float a2 = Lam > 0.0 ? (float)(4.0 / Lam) : 0.f;
+
+            // ---- recurrence: this wave owns row block ib and every column block jb
+            const int nb = (e + 15) / 16;
+            const float c0h = (float)(0.5 * coef[0]);
+#pragma unroll
+            for (int jb = 0; jb < BT_JB; ++jb) {
+                // own positions (i = ib + 4g + r, j = jb*16 + lane%16): YT[j][ib + 4g .. +3]
+                const int j = jb * 16 + (lane & 15);
+                const f32x4 y0 = *reinterpret_cast<const f32x4*>(&YT[j * BT_DP + ib + 4 * g]);
+                yprev[jb] = y0;
+                outv[jb] = c0h * y0;
+            }
+            float last2 = 0.f;   // ||Y_{K-1}||^2 over this thread's positions
+            for (int step = 0; step + 1 < Kj; ++step) {
+                const float aa = step == 0 ? a1 : a2;
+                const float bb = step == 0 ? -1.f : -2.f;
+                const float cc = step == 0 ? 0.f : -1.f;
+                const float ck = (float)coef[step + 1];
+                const bool final_step = step + 2 == Kj;
+                // A fragments: G rows ib + lane%16, k = 16 g + kk
+                float fa[16];
+                {
+                    const float* row = &Gs[(ib + (lane & 15)) * BT_DP + 16 * g];
+#pragma unroll
+                    for (int q = 0; q < 16; q += 4) {
+                        const f32x4 t = *reinterpret_cast<const f32x4*>(row + q);
+                        fa[q] = t[0];
+                        fa[q + 1] = t[1];
+                        fa[q + 2] = t[2];
+                        fa[q + 3] = t[3];
+                    }
+                }
+                f32x4 ynew[BT_JB];
+#pragma unroll
+                for (int jb = 0; jb < BT_JB; ++jb) {
+                    if (jb < nb) {
+                        const float* row = &YT[(jb * 16 + (lane & 15)) * BT_DP + 16 * g];
+                        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int q = 0; q < 16; q += 4) {
+                            const f32x4 b = *reinterpret_cast<const f32x4*>(row + q);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q], b[0], acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + 1], b[1], acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + 2], b[2], acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + 3], b[3], acc, 0, 0, 0);
+                        }
+                        const int j = jb * 16 + (lane & 15);
+                        const f32x4 yk = *reinterpret_cast<const f32x4*>(&YT[j * BT_DP + ib + 4 * g]);
+                        f32x4 yn;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            float y = aa * acc[r] + bb * yk[r];
+                            if (step > 0) y += cc * yprev[jb][r];
+                            yn[r] = y;
+                            outv[jb][r] += ck * y;
+                            if (final_step) last2 += y * y;
+                        }
+                        ynew[jb] = yn;
+                        yprev[jb] = yk;
+                    }
+                }
+                __syncthreads();   // every wave has read Y_k
+#pragma unroll
+                for (int jb = 0; jb < BT_JB; ++jb) {
+                    if (jb < nb) {
+                        const int j = jb * 16 + (lane & 15);
+                        *reinterpret_cast<f32x4*>(&YT[j * BT_DP + ib + 4 * g]) = ynew[jb];
+                    }
+                }
                 __syncthreads();
             }
-            if (vanish) {
-                Lam = (1.0 + a.margin) * fro;
-            } else {
-                const double r2 = w2 - mu * mu;
-                const double r = sqrt(r2 > 0.0 ? r2 : 0.0);
-                Lam = mu + (a.margin * mu > r ? a.margin * mu : r);
-                if (Lam > (1.0 + a.margin) * fro) Lam = (1.0 + a.margin) * fro;
+            if (!a.check || Kj < 2) break;
+            const double grow2 = bt_block_sum((double)last2, red);
+            const double lim = (1.0 + a.growth_tol) * (1.0 + a.growth_tol) * tr;
+            if (grow2 <= lim) break;
+            if (attempt > 0 || mode == 2) {
+                status = 3;
+                break;
             }
+            mode = mode == 3 ? 0 : 2;
+            status = 1;
         }
         if (threadIdx.x == 0) {
             if (a.lambda_out) a.lambda_out[idx] = Lam;
-            if (a.status) a.status[idx] = 0;
-        }
-
-        // ---- coefficients (FP64, l ascending per k)
-        for (int k = threadIdx.x; k < a.K; k += BT_THREADS) coef[k] = cheb_coeff(sp, Lam, a.K, k);
-        __syncthreads();
-        const float a1 = Lam > 0.0 ? (float)(2.0 / Lam) : 0.f;
-        const float a2 = Lam > 0.0 ? (float)(4.0 / Lam) : 0.f;
-
-        // ---- recurrence: this wave owns row block ib and every column block jb
-        f32x4 yprev[BT_JB], outv[BT_JB];
-        const int nb = (e + 15) / 16;
-        const float c0h = (float)(0.5 * coef[0]);
-#pragma unroll
-        for (int jb = 0; jb < BT_JB; ++jb) {
-            // own positions (i = ib + 4g + r, j = jb*16 + lane%16): YT[j][ib + 4g .. +3]
-            const int j = jb * 16 + (lane & 15);
-            const f32x4 y0 = *reinterpret_cast<const f32x4*>(&YT[j * BT_DP + ib + 4 * g]);
-            yprev[jb] = y0;
-            outv[jb] = c0h * y0;
-        }
-        for (int step = 0; step + 1 < a.K; ++step) {
-            const float aa = step == 0 ? a1 : a2;
-            const float bb = step == 0 ? -1.f : -2.f;
-            const float cc = step == 0 ? 0.f : -1.f;
-            const float ck = (float)coef[step + 1];
-            // A fragments: G rows ib + lane%16, k = 16 g + kk
-            float fa[16];
-            {
-                const float* row = &Gs[(ib + (lane & 15)) * BT_DP + 16 * g];
-#pragma unroll
-                for (int q = 0; q < 16; q += 4) {
-                    const f32x4 t = *reinterpret_cast<const f32x4*>(row + q);
-                    fa[q] = t[0];
-                    fa[q + 1] = t[1];
-                    fa[q + 2] = t[2];
-                    fa[q + 3] = t[3];
-                }
-            }
-            f32x4 ynew[BT_JB];
-#pragma unroll
-            for (int jb = 0; jb < BT_JB; ++jb) {
-                if (jb < nb) {
-                    const float* row = &YT[(jb * 16 + (lane & 15)) * BT_DP + 16 * g];
-                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int q = 0; q < 16; q += 4) {
-                        const f32x4 b = *reinterpret_cast<const f32x4*>(row + q);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q], b[0], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + 1], b[1], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + 2], b[2], acc, 0, 0, 0);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + 3], b[3], acc, 0, 0, 0);
-                    }
-                    const int j = jb * 16 + (lane & 15);
-                    const f32x4 yk = *reinterpret_cast<const f32x4*>(&YT[j * BT_DP + ib + 4 * g]);
-                    f32x4 yn;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        float y = aa * acc[r] + bb * yk[r];
-                        if (step > 0) y += cc * yprev[jb][r];
-                        yn[r] = y;
-                        outv[jb][r] += ck * y;
-                    }
-                    ynew[jb] = yn;
-                    yprev[jb] = yk;
-                }
-            }
-            __syncthreads();   // every wave has read Y_k
-#pragma unroll
-            for (int jb = 0; jb < BT_JB; ++jb) {
-                if (jb < nb) {
-                    const int j = jb * 16 + (lane & 15);
-                    *reinterpret_cast<f32x4*>(&YT[j * BT_DP + ib + 4 * g]) = ynew[jb];
-                }
-            }
-            __syncthreads();
+            if (a.K_out) a.K_out[idx] = Kj;
+            if (a.status) a.status[idx] = status;
         }
 
         // ---- store the accumulator (out(i, j) = Y_j[i][j], or Y_j[j][i] when transposed)
+        {
+            const int nb = (e + 15) / 16;
 #pragma unroll
-        for (int jb = 0; jb < BT_JB; ++jb) {
-            if (jb < nb) {
-                const int j = jb * 16 + (lane & 15);
+            for (int jb = 0; jb < BT_JB; ++jb) {
+                if (jb < nb) {
+                    const int j = jb * 16 + (lane & 15);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int i = ib + 4 * g + r;
-                    if (i < d && j < e) {
-                        if (trans)
-                            Yo[(int64_t)j * nj + i] = outv[jb][r];
-                        else
-                            Yo[(int64_t)i * nj + j] = outv[jb][r];
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = ib + 4 * g + r;
+                        if (i < d && j < e) {
+                            if (trans)
+                                Yo[(int64_t)j * nj + i] = outv[jb][r];
+                            else
+                                Yo[(int64_t)i * nj + j] = outv[jb][r];
+                        }
                     }
                 }
             }

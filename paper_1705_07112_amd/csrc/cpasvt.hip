@@ -68,6 +68,7 @@ struct cpa_ctx {
     int coop_max = 0;          // co-resident power-iteration workgroups (0: not queried)
     int batch_grid = 0;        // persistent workgroups of the batched kernel (0: not queried)
     int* queue = nullptr;      // work-queue counter of the batched kernel
+    void* mlp_ws = nullptr;    // predictor training: gradient partials | loss partials
     // sparse path: its own workspace and the cached transposed pattern
     void* sws = nullptr;
     size_t sws_bytes = 0;
@@ -731,13 +732,14 @@ cpa_status cpa_create(cpa_ctx** ctx_out, int device) {
 cpa_status cpa_destroy(cpa_ctx* ctx) {
     if (!ctx) return CPA_OK;
     (void)hipSetDevice(ctx->device);
-    if (ctx->ws || ctx->warm) (void)hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->warm) (void)hipFree(ctx->warm);
     for (auto& L : ctx->tlog)
         for (hipEvent_t e : L.ev) (void)hipEventDestroy(e);
     if (ctx->admm_exec) (void)hipGraphExecDestroy(ctx->admm_exec);
     if (ctx->queue) (void)hipFree(ctx->queue);
+    if (ctx->mlp_ws) (void)hipFree(ctx->mlp_ws);
     if (ctx->sws) (void)hipFree(ctx->sws);
     if (ctx->csc) (void)hipFree(ctx->csc);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -863,22 +865,27 @@ cpa_status cpa_timing_read(cpa_ctx* ctx, int which, double* total_ms_host, int64
     return CPA_OK;
 }
 
-cpa_status cpa_shrink_batched(cpa_ctx* ctx, void* stream, int batch, const int32_t* m_dev, const int32_t* n_dev,
-                              const int64_t* off_dev, const float* X_dev, float* Y_dev,
-                              const cpa_shrinkage* shrink_dev, const cpa_shrinkage* shrink_host,
-                              const cpa_opts* opts, const double* Lambda_dev, double* Lambda_out_dev,
-                              int32_t* status_dev) {
-    cpa_status s;
+namespace {
+
+// Checks shared by the batched entry points; fills the common kernel arguments.
+cpa_status batched_prepare(cpa_ctx* ctx, int batch, const int32_t* m_dev, const int32_t* n_dev,
+                           const int64_t* off_dev, const float* X_dev, BatchArgs& a) {
     if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
     if (batch < 0) return fail(CPA_ERR_SHAPE, "batch < 0");
-    if ((s = check_opts(opts)) != CPA_OK) return s;
-    if (opts->K > 64) return fail(CPA_ERR_ARG, "batched shrinkage supports K <= 64");
-    if (opts->precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "batched shrinkage is FP32");
-    if (batch == 0) return CPA_OK;
-    if (!m_dev || !n_dev || !off_dev || !X_dev || !Y_dev) return fail(CPA_ERR_ARG, "NULL array");
-    if (X_dev == Y_dev) return fail(CPA_ERR_ARG, "Y aliases X");
-    if (!shrink_dev && (s = check_shrinkage(shrink_host)) != CPA_OK) return s;
-    if (opts->bound == CPA_BOUND_GIVEN && !Lambda_dev) return fail(CPA_ERR_ARG, "Lambda_dev is NULL");
+    if (batch > 0 && (!m_dev || !n_dev || !off_dev || !X_dev)) return fail(CPA_ERR_ARG, "NULL array");
+    std::memset(&a, 0, sizeof(a));
+    a.batch = batch;
+    a.m = m_dev;
+    a.n = n_dev;
+    a.off = off_dev;
+    a.X = X_dev;
+    a.K = 1;
+    a.K_min = 1;
+    a.shrink0 = ShrinkParams{0, 0.0, 0.0, 0.0, 1.0};
+    return CPA_OK;
+}
+
+cpa_status batched_launch(cpa_ctx* ctx, void* stream, BatchArgs& a) {
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
     if (ctx->batch_grid == 0) {
@@ -891,30 +898,268 @@ cpa_status cpa_shrink_batched(cpa_ctx* ctx, void* stream, int batch, const int32
         ctx->queue = nullptr;
         return fail(CPA_ERR_ALLOC, "queue allocation failed");
     }
-    BatchArgs a;
-    a.batch = batch;
-    a.m = m_dev;
-    a.n = n_dev;
-    a.off = off_dev;
-    a.X = X_dev;
+    a.queue = ctx->queue;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, st, ctx->queue, 1, 0);
+    HIP_TRY(hipGetLastError());
+    const int grid = std::min(a.batch, ctx->batch_grid);
+    hipLaunchKernelGGL(batched_kernel, dim3(grid), dim3(BT_THREADS), 0, st, a);
+    HIP_TRY(hipGetLastError());
+    return CPA_OK;
+}
+
+cpa_status batched_shrink_args(const cpa_opts* opts, const float* X_dev, float* Y_dev,
+                               const cpa_shrinkage* shrink_dev, const cpa_shrinkage* shrink_host, BatchArgs& a) {
+    cpa_status s;
+    if ((s = check_opts(opts)) != CPA_OK) return s;
+    if (opts->K > 64) return fail(CPA_ERR_ARG, "batched shrinkage supports K <= 64");
+    if (opts->precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "batched shrinkage is FP32");
+    if (opts->check && !(opts->growth_tol >= 0.0)) return fail(CPA_ERR_ARG, "growth_tol must be >= 0");
+    if (a.batch > 0 && !Y_dev) return fail(CPA_ERR_ARG, "NULL array");
+    if (a.batch > 0 && X_dev == Y_dev) return fail(CPA_ERR_ARG, "Y aliases X");
+    if (!shrink_dev && (s = check_shrinkage(shrink_host)) != CPA_OK) return s;
     a.Y = Y_dev;
     a.shrink = reinterpret_cast<const ShrinkRec*>(shrink_dev);
-    a.shrink0 = shrink_dev ? ShrinkParams{0, 0.0, 0.0, 0.0, 1.0} : to_params(shrink_host);
+    if (!shrink_dev) a.shrink0 = to_params(shrink_host);
     a.K = opts->K;
-    a.mode = opts->bound == CPA_BOUND_POWER ? 0 : (opts->bound == CPA_BOUND_GIVEN ? 1 : 2);
-    a.lambda_in = Lambda_dev;
-    a.lambda_out = Lambda_out_dev;
-    a.status = status_dev;
     a.power_iters = opts->power_iters;
     a.tol = opts->power_tol;
     a.margin = opts->margin;
     a.seed = opts->seed;
-    a.queue = ctx->queue;
-    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, st, ctx->queue, 1, 0);
+    a.check = opts->check ? 1 : 0;
+    a.growth_tol = opts->growth_tol;
+    return CPA_OK;
+}
+
+}  // namespace
+
+cpa_status cpa_shrink_batched(cpa_ctx* ctx, void* stream, int batch, const int32_t* m_dev, const int32_t* n_dev,
+                              const int64_t* off_dev, const float* X_dev, float* Y_dev,
+                              const cpa_shrinkage* shrink_dev, const cpa_shrinkage* shrink_host,
+                              const cpa_opts* opts, const double* Lambda_dev, double* Lambda_out_dev,
+                              int32_t* status_dev) {
+    cpa_status s;
+    BatchArgs a;
+    if ((s = batched_prepare(ctx, batch, m_dev, n_dev, off_dev, X_dev, a)) != CPA_OK) return s;
+    if ((s = batched_shrink_args(opts, X_dev, Y_dev, shrink_dev, shrink_host, a)) != CPA_OK) return s;
+    if (opts->bound == CPA_BOUND_GIVEN && !Lambda_dev) return fail(CPA_ERR_ARG, "Lambda_dev is NULL");
+    if (batch == 0) return CPA_OK;
+    a.mode = opts->bound == CPA_BOUND_POWER ? 0 : (opts->bound == CPA_BOUND_GIVEN ? 1 : 2);
+    a.lambda_in = Lambda_dev;
+    a.lambda_out = Lambda_out_dev;
+    a.status = status_dev;
+    return batched_launch(ctx, stream, a);
+}
+
+cpa_status cpa_batched_features(cpa_ctx* ctx, void* stream, int batch, const int32_t* m_dev, const int32_t* n_dev,
+                                const int64_t* off_dev, const float* X_dev, float* feat_dev, int32_t* status_dev) {
+    cpa_status s;
+    BatchArgs a;
+    if ((s = batched_prepare(ctx, batch, m_dev, n_dev, off_dev, X_dev, a)) != CPA_OK) return s;
+    if (batch > 0 && !feat_dev) return fail(CPA_ERR_ARG, "feat_dev is NULL");
+    if (batch == 0) return CPA_OK;
+    a.mode = 4;
+    a.feat_out = feat_dev;
+    a.status = status_dev;
+    return batched_launch(ctx, stream, a);
+}
+
+cpa_status cpa_shrink_batched_predicted(cpa_ctx* ctx, void* stream, int batch, const int32_t* m_dev,
+                                        const int32_t* n_dev, const int64_t* off_dev, const float* X_dev,
+                                        float* Y_dev, const cpa_shrinkage* shrink_dev,
+                                        const cpa_shrinkage* shrink_host, const cpa_opts* opts,
+                                        const float* model_dev, int32_t K_min, double* Lambda_out_dev,
+                                        int32_t* K_out_dev, int32_t* status_dev) {
+    cpa_status s;
+    BatchArgs a;
+    if ((s = batched_prepare(ctx, batch, m_dev, n_dev, off_dev, X_dev, a)) != CPA_OK) return s;
+    if ((s = batched_shrink_args(opts, X_dev, Y_dev, shrink_dev, shrink_host, a)) != CPA_OK) return s;
+    if (!model_dev) return fail(CPA_ERR_ARG, "model_dev is NULL");
+    if (reinterpret_cast<uintptr_t>(model_dev) % 16 != 0) return fail(CPA_ERR_ARG, "model_dev must be 16-byte aligned");
+    if (K_min < 1 || K_min > opts->K) return fail(CPA_ERR_ARG, "K_min must be in [1, opts->K]");
+    if (opts->power_iters < 1 || opts->power_iters > kMaxPowerIters)
+        return fail(CPA_ERR_ARG, "power_iters must be in [1, %d] (used by the fallback)", kMaxPowerIters);
+    if (!(opts->power_tol >= 0.0) || !(opts->margin >= 0.0)) return fail(CPA_ERR_ARG, "power_tol and margin must be >= 0");
+    if (batch == 0) return CPA_OK;
+    a.mode = 3;
+    a.model = model_dev;
+    a.K_min = K_min;
+    a.lambda_out = Lambda_out_dev;
+    a.K_out = K_out_dev;
+    a.status = status_dev;
+    return batched_launch(ctx, stream, a);
+}
+
+namespace {
+
+cpa_status ensure_mlp_ws(cpa_ctx* ctx, float*& part, double*& lpart) {
+    const size_t pbytes = align_up(sizeof(float) * (size_t)kMlpMaxWg * kMlpParams);
+    if (!ctx->mlp_ws) {
+        if (hipMalloc(&ctx->mlp_ws, pbytes + sizeof(double) * kMlpMaxWg) != hipSuccess) {
+            ctx->mlp_ws = nullptr;
+            return fail(CPA_ERR_ALLOC, "predictor workspace allocation failed");
+        }
+    }
+    part = static_cast<float*>(ctx->mlp_ws);
+    lpart = reinterpret_cast<double*>(static_cast<char*>(ctx->mlp_ws) + pbytes);
+    return CPA_OK;
+}
+
+cpa_status check_model(const float* model_dev) {
+    if (!model_dev) return fail(CPA_ERR_ARG, "model_dev is NULL");
+    if (reinterpret_cast<uintptr_t>(model_dev) % 16 != 0) return fail(CPA_ERR_ARG, "model_dev must be 16-byte aligned");
+    return CPA_OK;
+}
+
+cpa_status check_quantiles(const float* q) {
+    if (!q) return fail(CPA_ERR_ARG, "quantiles_host is NULL");
+    for (int o = 0; o < 2; ++o)
+        if (!(q[o] > 0.f && q[o] < 1.f)) return fail(CPA_ERR_ARG, "quantiles must lie in (0, 1)");
+    return CPA_OK;
+}
+
+}  // namespace
+
+cpa_status cpa_predictor_forward(cpa_ctx* ctx, void* stream, int64_t n, const float* feat_dev,
+                                 const float* model_dev, float* y_dev) {
+    cpa_status s;
+    if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
+    if (n < 0) return fail(CPA_ERR_SHAPE, "n < 0");
+    if ((s = check_model(model_dev)) != CPA_OK) return s;
+    if (n == 0) return CPA_OK;
+    if (!feat_dev || !y_dev) return fail(CPA_ERR_ARG, "NULL array");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    MlpArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.feat = feat_dev;
+    a.model = model_dev;
+    a.y = y_dev;
+    a.s0 = 0;
+    a.count = n;
+    const int64_t tiles = (n + kMlpH - 1) / kMlpH;
+    const int grid = (int)std::min<int64_t>(tiles, 2048);
+    hipLaunchKernelGGL(mlp_tile_kernel<false>, dim3(grid), dim3(kMlpThreads), 0, st, a);
     HIP_TRY(hipGetLastError());
-    const int grid = std::min(batch, ctx->batch_grid);
-    hipLaunchKernelGGL(batched_kernel, dim3(grid), dim3(BT_THREADS), 0, st, a);
+    return CPA_OK;
+}
+
+cpa_status cpa_predictor_grad(cpa_ctx* ctx, void* stream, int64_t n, const float* feat_dev, const float* targ_dev,
+                              const float* quantiles_host, const float* model_dev, float* grad_dev,
+                              double* loss_dev) {
+    cpa_status s;
+    if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
+    if (n < 1) return fail(CPA_ERR_SHAPE, "n must be >= 1");
+    if ((s = check_model(model_dev)) != CPA_OK) return s;
+    if ((s = check_quantiles(quantiles_host)) != CPA_OK) return s;
+    if (!feat_dev || !targ_dev || !grad_dev) return fail(CPA_ERR_ARG, "NULL array");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float* part;
+    double* lpart;
+    if ((s = ensure_mlp_ws(ctx, part, lpart)) != CPA_OK) return s;
+    MlpArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.feat = feat_dev;
+    a.targ = targ_dev;
+    a.model = model_dev;
+    a.part = part;
+    a.lpart = lpart;
+    a.s0 = 0;
+    a.count = n;
+    a.q0 = quantiles_host[0];
+    a.q1 = quantiles_host[1];
+    a.dscale = (float)(1.0 / (2.0 * (double)n));
+    const int64_t tiles = (n + kMlpH - 1) / kMlpH;
+    const int grid = (int)std::min<int64_t>(tiles, kMlpMaxWg);
+    hipLaunchKernelGGL(mlp_tile_kernel<true>, dim3(grid), dim3(kMlpThreads), 0, st, a);
     HIP_TRY(hipGetLastError());
+    if (loss_dev) {
+        hipLaunchKernelGGL(fill_f64_kernel, dim3(1), dim3(64), 0, st, loss_dev, 1, 0.0);
+        HIP_TRY(hipGetLastError());
+    }
+    AdamArgs r;
+    std::memset(&r, 0, sizeof(r));
+    r.part = part;
+    r.nwg = grid;
+    r.lpart = lpart;
+    r.grad_out = grad_dev;
+    r.loss_dst = loss_dev;
+    r.loss_mul = 1.0 / (2.0 * (double)n);
+    r.adam = 0;
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, r);
+    HIP_TRY(hipGetLastError());
+    return CPA_OK;
+}
+
+cpa_status cpa_predictor_train(cpa_ctx* ctx, void* stream, int64_t n, const float* feat_dev, const float* targ_dev,
+                               const float* quantiles_host, int32_t batch_size, int32_t epochs, float lr,
+                               float* model_dev, float* adam_dev, int64_t* step_io_host, double* epoch_loss_dev) {
+    cpa_status s;
+    if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
+    if (n < 1) return fail(CPA_ERR_SHAPE, "n must be >= 1");
+    if ((s = check_model(model_dev)) != CPA_OK) return s;
+    if ((s = check_quantiles(quantiles_host)) != CPA_OK) return s;
+    if (!feat_dev || !targ_dev || !adam_dev || !step_io_host) return fail(CPA_ERR_ARG, "NULL argument");
+    if (batch_size < 1 || batch_size > kMlpH * kMlpMaxWg)
+        return fail(CPA_ERR_ARG, "batch_size must be in [1, %d]", kMlpH * kMlpMaxWg);
+    if (epochs < 0) return fail(CPA_ERR_ARG, "epochs < 0");
+    if (!(lr >= 0.f) || !std::isfinite(lr)) return fail(CPA_ERR_ARG, "lr must be finite and >= 0");
+    if (*step_io_host < 0) return fail(CPA_ERR_ARG, "*step_io_host < 0");
+    if (epochs == 0) return CPA_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    float* part;
+    double* lpart;
+    if ((s = ensure_mlp_ws(ctx, part, lpart)) != CPA_OK) return s;
+    if (epoch_loss_dev) {
+        hipLaunchKernelGGL(fill_f64_kernel, dim3(1), dim3(256), 0, st, epoch_loss_dev, epochs, 0.0);
+        HIP_TRY(hipGetLastError());
+    }
+    const int64_t steps = (n + batch_size - 1) / batch_size;
+    const double beta1 = 0.9, beta2 = 0.999;
+    int64_t t = *step_io_host;
+    for (int ep = 0; ep < epochs; ++ep) {
+        for (int64_t b = 0; b < steps; ++b) {
+            const int64_t s0 = b * batch_size;
+            const int64_t cnt = std::min<int64_t>(batch_size, n - s0);
+            MlpArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.feat = feat_dev;
+            a.targ = targ_dev;
+            a.model = model_dev;
+            a.part = part;
+            a.lpart = lpart;
+            a.s0 = s0;
+            a.count = cnt;
+            a.q0 = quantiles_host[0];
+            a.q1 = quantiles_host[1];
+            a.dscale = (float)(1.0 / (2.0 * (double)cnt));
+            const int grid = (int)((cnt + kMlpH - 1) / kMlpH);
+            hipLaunchKernelGGL(mlp_tile_kernel<true>, dim3(grid), dim3(kMlpThreads), 0, st, a);
+            HIP_TRY(hipGetLastError());
+            ++t;
+            AdamArgs r;
+            std::memset(&r, 0, sizeof(r));
+            r.part = part;
+            r.nwg = grid;
+            r.lpart = lpart;
+            r.model = model_dev;
+            r.m = adam_dev;
+            r.v = adam_dev + kMlpParams;
+            r.lr = lr;
+            r.beta1 = (float)beta1;
+            r.beta2 = (float)beta2;
+            r.eps = 1e-8f;
+            r.bc1 = 1.0 - std::pow(beta1, (double)t);
+            r.bc2 = 1.0 - std::pow(beta2, (double)t);
+            r.loss_dst = epoch_loss_dev ? epoch_loss_dev + ep : nullptr;
+            r.loss_mul = 1.0 / (2.0 * (double)cnt * (double)steps);
+            r.adam = 1;
+            hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, r);
+            HIP_TRY(hipGetLastError());
+        }
+    }
+    *step_io_host = t;
     return CPA_OK;
 }
 

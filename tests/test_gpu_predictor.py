@@ -1,0 +1,302 @@
+"""Learned bound / order predictor on the GPU against the FP64 oracle network:
+forward, loss gradient, Adam step, features, and the predicted batched
+shrinkage (decisions and result), plus the growth-check fallback."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cpa as ocpa
+from oracle import metrics
+from oracle import mlp as omlp
+from oracle.shrinkage import Shrinkage
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+Q = (0.99, 0.9)
+
+
+def _model(seed, scale=1.0):
+    """A model buffer drawn by the test (the network's weights are test inputs)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    p = omlp.init_params(seed) + 0.05 * g.standard_normal(omlp.N_PARAMS)
+    p[omlp.N_PARAMS - 2:] = g.standard_normal(2)
+    mean = g.standard_normal(3)
+    inv = g.uniform(0.3, 2.0, 3) * scale
+    return np.concatenate([p, mean, inv, [0.0, 0.0]]).astype(np.float32)
+
+
+def _dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    return t.to("cuda") if dtype is None else t.to("cuda", dtype)
+
+
+@pytest.mark.parametrize("n", [1, 63, 1000, 16401])
+def test_forward_matches_oracle(n):
+    import paper_1705_07112_amd as cpa
+    g = np.random.Generator(np.random.PCG64(100 + n))
+    model = _model(3)
+    F = g.normal(0.0, 2.0, (n, 3)).astype(np.float32)
+    y = cpa.predictor_forward(_dev(F), _dev(model)).cpu().numpy()
+    ref = omlp.forward_model(model, F.astype(np.float64))
+    assert np.max(np.abs(y - ref)) <= TOL32 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("n", [1, 1000, 16401])
+def test_gradient_matches_oracle(n):
+    import paper_1705_07112_amd as cpa
+    g = np.random.Generator(np.random.PCG64(200 + n))
+    model = _model(4)
+    F = g.normal(0.0, 2.0, (n, 3)).astype(np.float32)
+    T = g.normal(0.0, 1.0, (n, 2)).astype(np.float32)
+    grad, loss = cpa.predictor_grad(_dev(F), _dev(T), _dev(model), Q)
+    p, mean, inv = omlp.split_model(model)
+    lref, gref = omlp.loss_and_grad(p, (F.astype(np.float64) - mean) * inv, T.astype(np.float64), np.array(Q))
+    gd = grad.cpu().numpy().astype(np.float64)
+    assert metrics.rel_fro(gd, gref, gref) <= TOL32
+    assert abs(float(loss.cpu().numpy()[0]) - lref) <= TOL32 * abs(lref)
+
+
+def test_gradient_is_deterministic():
+    import paper_1705_07112_amd as cpa
+    g = np.random.Generator(np.random.PCG64(7))
+    F = _dev(g.normal(0.0, 2.0, (5000, 3)).astype(np.float32))
+    T = _dev(g.normal(0.0, 1.0, (5000, 2)).astype(np.float32))
+    M = _dev(_model(5))
+    g1, l1 = cpa.predictor_grad(F, T, M, Q)
+    g2, l2 = cpa.predictor_grad(F, T, M, Q)
+    assert bool((g1 == g2).all()) and bool((l1 == l2).all())
+
+
+def test_adam_step_matches_oracle():
+    import torch
+    import paper_1705_07112_amd as cpa
+    g = np.random.Generator(np.random.PCG64(8))
+    n = 700
+    model = _model(6)
+    F = g.normal(0.0, 2.0, (n, 3)).astype(np.float32)
+    T = g.normal(0.0, 1.0, (n, 2)).astype(np.float32)
+    M = _dev(model.copy())
+    adam = torch.zeros(2 * cpa.PRED_PARAMS, dtype=torch.float32, device="cuda")
+    lr = 1e-3
+    losses = torch.zeros(2, dtype=torch.float64, device="cuda")
+    step = cpa.predictor_train(_dev(F), _dev(T), M, adam, 0, Q, batch_size=n, epochs=2, lr=lr, epoch_loss=losses)
+    assert step == 2
+    # oracle: two full-batch Adam steps from the same start
+    p, mean, inv = omlp.split_model(model)
+    X = (F.astype(np.float64) - mean) * inv
+    m = np.zeros(omlp.N_PARAMS)
+    v = np.zeros(omlp.N_PARAMS)
+    lref = []
+    grads = []
+    for t in (1, 2):
+        l, gr = omlp.loss_and_grad(p, X, T.astype(np.float64), np.array(Q))
+        lref.append(l)
+        grads.append(gr)
+        p, m, v = omlp.adam_step(p, gr, m, v, t, lr)
+    got = M.cpu().numpy()
+    # parameters whose gradient is far from zero move exactly as the oracle's;
+    # the others (where m / sqrt(v) hinges on a near-zero gradient) move no further
+    # than the oracle's largest move
+    big = np.minimum(np.abs(grads[0]), np.abs(grads[1])) > 1e-3 * np.max(np.abs(grads[0]))
+    assert big.sum() > omlp.N_PARAMS // 2
+    assert np.max(np.abs(got[:omlp.N_PARAMS][big] - p[big])) <= 1e-3 * lr + 1e-6
+    moved = np.abs(got[:omlp.N_PARAMS] - model[:omlp.N_PARAMS])
+    assert np.max(moved) <= 1.001 * np.max(np.abs(p - model[:omlp.N_PARAMS].astype(np.float64))) + 1e-6
+    assert np.array_equal(got[omlp.N_PARAMS:], model[omlp.N_PARAMS:])   # normalisation untouched
+    lg = losses.cpu().numpy()
+    assert abs(lg[0] - lref[0]) <= 1e-5 * lref[0] and abs(lg[1] - lref[1]) <= 1e-5 * lref[1]
+
+
+def test_training_reduces_loss_and_is_reproducible():
+    import torch
+    import paper_1705_07112_amd as cpa
+    g = np.random.Generator(np.random.PCG64(9))
+    n = 20000
+    F = g.normal(0.0, 1.0, (n, 3)).astype(np.float32)
+    T = np.stack([np.tanh(F[:, 0] - 0.5 * F[:, 1]), 0.3 * F[:, 2] ** 2], axis=1).astype(np.float32)
+    model = _model(10)
+    model[omlp.N_PARAMS:omlp.N_PARAMS + 3] = 0.0
+    model[omlp.N_PARAMS + 3:omlp.N_PARAMS + 6] = 1.0
+    outs = []
+    for _ in range(2):
+        M = _dev(model.copy())
+        adam = torch.zeros(2 * cpa.PRED_PARAMS, dtype=torch.float32, device="cuda")
+        losses = torch.zeros(15, dtype=torch.float64, device="cuda")
+        cpa.predictor_train(_dev(F), _dev(T), M, adam, 0, (0.5, 0.5), batch_size=512, epochs=15, lr=3e-3,
+                            epoch_loss=losses)
+        outs.append((M.cpu().numpy(), losses.cpu().numpy()))
+    (m1, l1), (m2, l2) = outs
+    assert np.array_equal(m1, m2) and np.array_equal(l1, l2)
+    assert l1[-1] < 0.5 * l1[0]
+
+
+def _family(batch, seed, extra_shapes=()):
+    flat, ms, ns, offs, ranks, noises = synth.patch_groups(batch=batch, rank_range=(1, 16),
+                                                           noise_range=(0.05, 0.5), seed=seed)
+    mats = [flat[offs[j]:offs[j] + ms[j] * ns[j]].reshape(ms[j], ns[j]) for j in range(batch)]
+    taus = [noises[j] * (math.sqrt(ms[j]) + math.sqrt(ns[j])) for j in range(batch)]
+    g = np.random.Generator(np.random.PCG64(seed + 1))
+    for (a, b) in extra_shapes:
+        mats.append(g.standard_normal((a, b)).astype(np.float32))
+        taus.append(0.5 * (math.sqrt(a) + math.sqrt(b)))
+    return mats, taus
+
+
+def _pack(mats):
+    ms = np.array([a.shape[0] for a in mats], dtype=np.int32)
+    ns = np.array([a.shape[1] for a in mats], dtype=np.int32)
+    offs = np.zeros(len(mats), dtype=np.int64)
+    offs[1:] = np.cumsum([a.size for a in mats])[:-1]
+    flat = np.concatenate([a.astype(np.float32).ravel() for a in mats])
+    return flat, ms, ns, offs
+
+
+def _upload(mats, taus):
+    import torch
+    import paper_1705_07112_amd as cpa
+    flat, ms, ns, offs = _pack(mats)
+    recs = torch.frombuffer(bytearray(cpa.shrinkage_records([cpa.soft(t) for t in taus])),
+                            dtype=torch.uint8).to("cuda")
+    return _dev(flat), _dev(ms), _dev(ns), _dev(offs), recs, offs
+
+
+EXTRA = ((1, 1), (1, 128), (128, 1), (64, 64), (100, 30), (17, 5), (128, 64))
+
+
+def test_features_match_oracle():
+    import paper_1705_07112_amd as cpa
+    mats, _ = _family(300, 31, EXTRA)
+    X, m, n, off, _, _ = _upload(mats, [0.0] * len(mats))
+    status = _dev(np.full(len(mats), -1, np.int32))
+    F = cpa.batched_features(X, m, n, off, status=status).cpu().numpy()
+    assert np.all(status.cpu().numpy() == 0)
+    for j, A in enumerate(mats):
+        ref = omlp.features(A.astype(np.float64))
+        # logs: absolute error ~ relative error of the sums
+        assert np.max(np.abs(F[j] - ref)) <= TOL32 * max(1.0, np.max(np.abs(ref))), j
+
+
+def _predicted(mats, taus, model, K_max, K_min, check):
+    import torch
+    import paper_1705_07112_amd as cpa
+    X, m, n, off, recs, offs = _upload(mats, taus)
+    nb = len(mats)
+    lam = torch.zeros(nb, dtype=torch.float64, device="cuda")
+    K = torch.zeros(nb, dtype=torch.int32, device="cuda")
+    st = torch.full((nb,), -1, dtype=torch.int32, device="cuda")
+    opts = cpa.Opts(K=K_max, check=check)
+    Y = cpa.shrink_batched_predicted(X, m, n, off, cpa.soft(0.0), opts, _dev(model), K_min=K_min,
+                                     shrink_per_matrix=recs, lambda_out=lam, K_out=K, status=st)
+    F = cpa.batched_features(X, m, n, off).cpu().numpy()
+    Yh = Y.cpu().numpy()
+    outs = [Yh[offs[j]:offs[j] + mats[j].size].reshape(mats[j].shape).astype(np.float64) for j in range(nb)]
+    return outs, lam.cpu().numpy(), K.cpu().numpy(), st.cpu().numpy(), F, (X, m, n, off, recs, offs)
+
+
+def _predict_model(seed):
+    """A network with sensible outputs for the family: y0 ~ log(0.9), y1 ~ log(20) plus
+    small input-dependent terms."""
+    model = _model(seed, scale=0.3)
+    model[omlp.N_PARAMS - 130:omlp.N_PARAMS - 2] *= 0.3    # W3 small
+    model[omlp.N_PARAMS - 2] = math.log(0.9)
+    model[omlp.N_PARAMS - 1] = math.log(20.0)
+    return model
+
+
+def test_predicted_batched_matches_oracle():
+    mats, taus = _family(200, 41, EXTRA)
+    model = _predict_model(12)
+    outs, lam, K, st, F, _ = _predicted(mats, taus, model, 64, 4, check=False)
+    assert np.all(st == 0)
+    y = omlp.forward_model(model, F.astype(np.float64))
+    margin = 0.01
+    compared = 0
+    for j, A in enumerate(mats):
+        A64 = A.astype(np.float64)
+        G = A64.T @ A64 if A.shape[0] >= A.shape[1] else A64 @ A64.T
+        fro = np.sqrt(np.sum(G * G))
+        Lref, Kref = omlp.decide(y[j], fro, margin, 4, 64)
+        assert abs(lam[j] - Lref) <= TOL32 * Lref, j
+        kf = math.exp(float(y[j][1]))
+        if abs(kf - round(kf)) > 1e-4 * kf:
+            assert K[j] == Kref, j
+        assert 4 <= K[j] <= 64
+        # results are compared where the predicted bound covers the spectrum; below
+        # lambda_max the recurrence leaves [-1, 1] and amplifies rounding in both
+        if lam[j] >= np.linalg.eigvalsh(G)[-1]:
+            compared += 1
+            ref = ocpa.cpa_shrink(A64, Shrinkage(0, taus[j], 0, 0, 0), float(lam[j]), int(K[j]))
+            assert metrics.rel_fro(outs[j], ref, A64) <= TOL32, j
+    assert compared >= len(mats) // 2
+
+
+def test_growth_check_falls_back_to_power_bound():
+    """A model whose Lambda is far below lambda_max: with the check on, every such
+    matrix is redone with the power-iteration bound and equals the plain power path."""
+    import torch
+    import paper_1705_07112_amd as cpa
+    mats, taus = _family(64, 51)
+    model = _model(13)
+    model[omlp.N_PARAMS - 130:omlp.N_PARAMS - 2] = 0.0     # W3 = 0: constant outputs
+    model[omlp.N_PARAMS - 2] = math.log(0.05)
+    model[omlp.N_PARAMS - 1] = math.log(15.5)   # ceil(15.5) = 16, away from a rounding edge
+    outs, lam, K, st, F, (X, m, n, off, recs, offs) = _predicted(mats, taus, model, 64, 2, check=True)
+    assert np.all(K == 16)
+    assert np.all(st == 1)
+    lam_p = torch.zeros(len(mats), dtype=torch.float64, device="cuda")
+    Yp = cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), cpa.Opts(K=16), shrink_per_matrix=recs,
+                            lambda_out=lam_p).cpu().numpy()
+    assert np.array_equal(lam, lam_p.cpu().numpy())
+    for j, A in enumerate(mats):
+        assert np.array_equal(outs[j], Yp[offs[j]:offs[j] + A.size].reshape(A.shape).astype(np.float64)), j
+
+
+def test_growth_check_given_bound_falls_back_to_frobenius():
+    import torch
+    import paper_1705_07112_amd as cpa
+    mats, taus = _family(32, 61)
+    X, m, n, off, recs, offs = _upload(mats, taus)
+    nb = len(mats)
+    tiny = _dev(np.full(nb, 1e-3, np.float64))
+    lam = torch.zeros(nb, dtype=torch.float64, device="cuda")
+    st = torch.full((nb,), -1, dtype=torch.int32, device="cuda")
+    Y = cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), cpa.Opts(K=12, bound="given", check=True),
+                           shrink_per_matrix=recs, Lambda=tiny, lambda_out=lam, status=st).cpu().numpy()
+    assert np.all(st.cpu().numpy() == 1)
+    lam_f = torch.zeros(nb, dtype=torch.float64, device="cuda")
+    Yf = cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), cpa.Opts(K=12, bound="frobenius"),
+                            shrink_per_matrix=recs, lambda_out=lam_f).cpu().numpy()
+    assert np.array_equal(lam.cpu().numpy(), lam_f.cpu().numpy())
+    assert np.array_equal(Y, Yf)
+    # check on with a valid bound changes nothing
+    st2 = torch.full((nb,), -1, dtype=torch.int32, device="cuda")
+    Y2 = cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), cpa.Opts(K=12, check=True), shrink_per_matrix=recs,
+                            status=st2).cpu().numpy()
+    Y3 = cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), cpa.Opts(K=12), shrink_per_matrix=recs).cpu().numpy()
+    assert np.all(st2.cpu().numpy() == 0)
+    assert np.array_equal(Y2, Y3)
+
+
+def test_predictor_argument_errors():
+    import torch
+    import paper_1705_07112_amd as cpa
+    mats, taus = _family(4, 71)
+    X, m, n, off, recs, offs = _upload(mats, taus)
+    model = _dev(_predict_model(1))
+    with pytest.raises(cpa.CpaError):
+        cpa.shrink_batched_predicted(X, m, n, off, cpa.soft(0.0), cpa.Opts(K=80), model, K_min=2,
+                                     shrink_per_matrix=recs)
+    with pytest.raises(cpa.CpaError):
+        cpa.shrink_batched_predicted(X, m, n, off, cpa.soft(0.0), cpa.Opts(K=16), model, K_min=20,
+                                     shrink_per_matrix=recs)
+    F = torch.zeros((10, 3), device="cuda")
+    T = torch.zeros((10, 2), device="cuda")
+    with pytest.raises(cpa.CpaError):
+        cpa.predictor_grad(F, T, model, (1.0, 0.5))
+    adam = torch.zeros(2 * cpa.PRED_PARAMS, device="cuda")
+    with pytest.raises(cpa.CpaError):
+        cpa.predictor_train(F, T, model, adam, 0, Q, batch_size=20000)

@@ -124,3 +124,56 @@ def test_planted_mistake_is_caught(monkeypatch, name, mod, attr, fn):
         # cpa imported the module, so patching the module attribute is enough
         pass
     assert _any_pin_fails(), f"planted mistake not detected: {name}"
+
+
+# ---- predictor network: slips in the backward pass or the loss derivative
+
+import tests.test_oracle_mlp as mlp_pins
+from oracle import mlp as mlp_mod
+
+MLP_PINS = [mlp_pins.test_gradient_matches_central_differences, mlp_pins.test_linear_closed_form]
+
+
+def _mlp_pin_fails():
+    for f in MLP_PINS:
+        try:
+            f()
+        except AssertionError:
+            return True
+    return False
+
+
+def _backward_no_tanh_derivative(p, cache, dy):
+    W1, b1, W2, b2, W3, b3 = mlp_mod.unpack(p)
+    F, a1, a2 = cache
+    dz2 = dy @ W3                       # (1 - a2^2) dropped
+    da1 = dz2 @ W2
+    dz1 = da1 * (1.0 - a1 * a1)
+    return mlp_mod.pack([dz1.T @ F, dz1.sum(0), dz2.T @ a1, dz2.sum(0), dy.T @ a2, dy.sum(0)])
+
+
+def _backward_transposed_w2(p, cache, dy):
+    W1, b1, W2, b2, W3, b3 = mlp_mod.unpack(p)
+    F, a1, a2 = cache
+    dz2 = (dy @ W3) * (1.0 - a2 * a2)
+    da1 = dz2 @ W2.T                    # should be dz2 @ W2
+    dz1 = da1 * (1.0 - a1 * a1)
+    return mlp_mod.pack([dz1.T @ F, dz1.sum(0), dz2.T @ a1, dz2.sum(0), dy.T @ a2, dy.sum(0)])
+
+
+def _pinball_sign_flipped(y, t, q):
+    loss, dy = mlp_orig_pinball(y, t, q)
+    return loss, -dy
+
+
+mlp_orig_pinball = mlp_mod.pinball
+
+
+@pytest.mark.parametrize("name,fn", [
+    ("backward", _backward_no_tanh_derivative),
+    ("backward", _backward_transposed_w2),
+    ("pinball", _pinball_sign_flipped),
+])
+def test_mlp_planted_mistake_is_caught(name, fn, monkeypatch):
+    monkeypatch.setattr(mlp_mod, name, fn)
+    assert _mlp_pin_fails()
