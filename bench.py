@@ -30,8 +30,12 @@ MFMA_FP32_PEAK_TFLOPS = 157.3
 METRIC = "shrunk matrices/sec & TFLOP/s at rel. Frobenius err ≤1e-3 vs FP64 SVT"
 
 
-def cpu_baseline(I, budget_s: float = 15.0):
-    """The FP64 oracle's ADMM iterations on the host, for about budget_s seconds."""
+def cpu_baseline(I, budget_s: float = 15.0, check=None):
+    """The FP64 oracle's ADMM iterations on the host, for about budget_s seconds.
+
+    check: optional (X, {name: Y_gpu}, Lambda) -- one shrink input, GPU results
+    and the bound they used; the oracle's CPA of X at that bound (untimed) gives
+    each result's relative Frobenius error against FP64 Algorithm 1."""
     import numpy as np
     from oracle import drivers
     try:
@@ -49,9 +53,30 @@ def cpu_baseline(I, budget_s: float = 15.0):
         el = time.perf_counter() - t0
         if el >= budget_s or done >= 50:
             break
-    return {"value": done / el, "unit": "matrices/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{done} FP64 oracle ADMM iterations (one shrink each: Algorithm 1 H-form, "
-                      f"K={K}, 1024x1024) in {el:.1f} s"}
+    res = {"value": done / el, "unit": "matrices/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"{done} FP64 oracle ADMM iterations (one shrink each: Algorithm 1 H-form, "
+                     f"K={K}, 1024x1024) in {el:.1f} s"}
+    if check is not None:
+        from oracle import cpa as ocpa
+        from oracle import metrics
+        from oracle.shrinkage import Shrinkage
+        Xc, outs, lam = check
+        ref = ocpa.cpa_shrink(Xc, Shrinkage(0, INV_RHO), lam, K)
+        res["err_vs_fp64_cpa"] = {k: float("%.3e" % metrics.rel_fro(v, ref, Xc)) for k, v in outs.items()}
+    return res
+
+
+def exact_shrink(X, g):
+    """U g(Sigma) V^T by LAPACK's SVD in FP64 (the definition of singular value shrinkage)."""
+    import numpy as np
+    U, sv, Vt = np.linalg.svd(X, full_matrices=False)
+    return (U * g(sv)) @ Vt
+
+
+def rel_fro(A, B, scale):
+    import numpy as np
+    d = float(np.linalg.norm(scale))
+    return float(np.linalg.norm(A - B)) / (d if d > 0 else 1.0)
 
 
 def bench_batched(cpa, torch, np, synth, timed_runs: int = 5):
@@ -101,27 +126,25 @@ def bench_batched(cpa, torch, np, synth, timed_runs: int = 5):
     e1.record()
     torch.cuda.synchronize()
     ms_single = e0.elapsed_time(e1) / nb
-    # accuracy on a sample: vs the FP64 CPA at the device bound, and vs exact SVT
-    from oracle import cpa as ocpa
-    from oracle import exact, metrics
-    from oracle.shrinkage import Shrinkage
+    # accuracy on a sample against the exact weighted shrinkage (LAPACK SVD):
+    # g(s) = s - w(s^2) when s > w(s^2), w(x) = w_c / (sqrt(max(x - w_sigma, 0)) + w_eps)
     Yh = Y.cpu().numpy()
-    lamh = lam.cpu().numpy()
-    e_cpa, e_svt = [], []
+    e_svt = []
     for i in range(0, 8192, 256):
         Xi = flat[offs[i]:offs[i] + ms[i] * ns[i]].reshape(ms[i], ns[i]).astype(np.float64)
         Yi = Yh[offs[i]:offs[i] + ms[i] * ns[i]].reshape(ms[i], ns[i]).astype(np.float64)
         r = recs[i]
-        sh = Shrinkage(3, 0.0, r.w_c, r.w_sigma, r.w_eps)
-        e_cpa.append(metrics.rel_fro(Yi, ocpa.cpa_shrink(Xi, sh, float(lamh[i]), 16), Xi))
-        e_svt.append(metrics.rel_fro(Yi, exact.svt_svd(Xi, sh), Xi))
+
+        def g(sv, r=r):
+            w = r.w_c / (np.sqrt(np.maximum(sv * sv - r.w_sigma, 0.0)) + r.w_eps)
+            return np.where(sv > w, sv - w, 0.0)
+        e_svt.append(rel_fro(Yi, exact_shrink(Xi, g), Xi))
     return {
         "workload": "8192 patch groups 64 x U{40..120}, rank 4 + N(0,0.2^2), weighted soft, K=16, power bound",
         "value": round(8192 / (ms_batch / 1e3), 1), "unit": "matrices/s", "ms_per_batch": round(ms_batch, 4),
         "tflops": round(flop / (ms_batch * 1e-3) / 1e12, 3),
         "baseline_per_matrix_dense_fp32": {"value": round(1e3 / ms_single, 1), "unit": "matrices/s",
                                            "sample": f"{nb} matrices, one cpa_shrink_dense call each"},
-        "err_vs_fp64_cpa_max": float("%.3e" % max(e_cpa)),
         "err_vs_fp64_svt_median": float("%.3e" % float(np.median(e_svt))),
         "err_vs_fp64_svt_max": float("%.3e" % max(e_svt)),
     }
@@ -175,6 +198,120 @@ def bench_sparse(cpa, torch, np, synth):
     }
 
 
+def bench_predictor(cpa, torch, np, synth, n_train: int = 32768, n_eval: int = 8192, epochs: int = 40,
+                    gate: float = 1e-2, lr: float = 2e-3, quantiles=(0.99, 0.9)):
+    """Learned bound / order predictor on patch groups 64 x U{40..120} with rank
+    U{1..16} and noise sigma U[0.05, 0.5] (soft tau_j = sigma_j (sqrt(64) + sqrt(n_j))).
+    Labels come from the method on the GPU (converged power bound; smallest K of
+    {4, 6, .., 64} whose result is within `gate` of the exact shrinkage), training
+    from the library's kernels.  Gain: matrices/s of the predicted path (no power
+    iteration, per-matrix K, growth check on) over plain CPA (power bound, one K for
+    all: the smallest whose pass rate of the gate reaches the predicted path's), on
+    a held-out batch."""
+    from paper_1705_07112_amd import predictor as P
+    dev = torch.device("cuda:0")
+
+    def make(batch, seed):
+        flat, ms, ns, offs, _, noises = synth.patch_groups(batch=batch, rank_range=(1, 16),
+                                                           noise_range=(0.05, 0.5), seed=seed)
+        taus = noises * (np.sqrt(ms) + np.sqrt(ns))
+        t = time.perf_counter()
+        ex = P.exact_soft_batch(flat, ms, ns, offs, taus)
+        return {"ms": ms, "ns": ns, "offs": offs, "X": torch.from_numpy(flat).to(dev), "m": torch.from_numpy(ms).to(dev),
+                "n": torch.from_numpy(ns).to(dev), "off": torch.from_numpy(offs).to(dev),
+                "recs": P.soft_records(torch, taus, dev), "Yex": torch.from_numpy(ex).to(dev),
+                "t_exact": time.perf_counter() - t}
+
+    tr = make(n_train, synth.BASE_SEED + 4)
+    ev = make(n_eval, synth.BASE_SEED + 5)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    feat, targ, kstar, miss = P.make_labels(torch, tr["X"], tr["m"], tr["n"], tr["off"], tr["recs"], tr["ms"],
+                                            tr["ns"], tr["offs"], tr["Yex"], gate=gate)
+    torch.cuda.synchronize()
+    t_label = time.perf_counter() - t
+    ok = torch.isfinite(targ).all(dim=1)
+    gen = torch.Generator().manual_seed(0)
+    idx = torch.nonzero(ok).flatten().cpu()
+    idx = idx[torch.randperm(idx.numel(), generator=gen)].to(dev)
+    feat, targ = feat[idx].contiguous(), targ[idx].contiguous()
+    mean = feat.double().mean(0).cpu().numpy()
+    std = feat.double().std(0).cpu().numpy()
+    model = torch.from_numpy(P.init_model(0, mean, std)).to(dev)
+    adam = torch.zeros(2 * cpa.PRED_PARAMS, dtype=torch.float32, device=dev)
+    losses = torch.zeros(epochs, dtype=torch.float64, device=dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    cpa.predictor_train(feat, targ, model, adam, 0, quantiles, batch_size=1024, epochs=epochs, lr=lr,
+                        epoch_loss=losses)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_train = e0.elapsed_time(e1)
+    lh = losses.cpu().numpy()
+
+    nb = int(ev["m"].numel())
+    bounds = P.segment_bounds(torch, ev["ms"], ev["ns"], ev["offs"], dev)
+    Y = torch.empty_like(ev["X"])
+    lam = torch.zeros(nb, dtype=torch.float64, device=dev)
+    kout = torch.zeros(nb, dtype=torch.int32, device=dev)
+    st = torch.zeros(nb, dtype=torch.int32, device=dev)
+    popts = cpa.Opts(K=64, check=True)
+
+    def predicted():
+        cpa.shrink_batched_predicted(ev["X"], ev["m"], ev["n"], ev["off"], cpa.soft(0.0), popts, model, K_min=4,
+                                     shrink_per_matrix=ev["recs"], out=Y, lambda_out=lam, K_out=kout, status=st)
+
+    def plain(Kc):
+        cpa.shrink_batched(ev["X"], ev["m"], ev["n"], ev["off"], cpa.soft(0.0), cpa.Opts(K=Kc),
+                           shrink_per_matrix=ev["recs"], out=Y)
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_pred = timed(predicted)
+    err, ref2 = P.rel_errors(torch, Y, ev["Yex"], bounds)
+    pass_pred = float((err <= gate).double().mean())
+    k_mean = float(kout.double().mean())
+    fb = float((st == 1).double().mean())
+    plain_rows = []
+    chosen = None
+    for Kc in P.K_GRID:
+        plain(Kc)
+        e, _ = P.rel_errors(torch, Y, ev["Yex"], bounds, ref2)
+        pr = float((e <= gate).double().mean())
+        plain_rows.append((Kc, pr))
+        if pr >= pass_pred:
+            chosen = (Kc, pr)
+            break
+    if chosen is None:
+        chosen = plain_rows[-1]
+    ms_plain = timed(lambda: plain(chosen[0]))
+    return {
+        "workload": f"train {n_train} / held-out {n_eval} patch groups 64 x U{{40..120}}, rank U{{1..16}}, "
+                    f"sigma U[0.05,0.5], soft tau = sigma (sqrt m + sqrt n); gate: rel. err <= {gate:g} vs exact",
+        "labels": {"seconds_gpu_method_runs": round(t_label, 2),
+                   "seconds_exact_svd_host": round(tr["t_exact"] + ev["t_exact"], 2),
+                   "K_star_mean": round(float(kstar.double().mean()), 2),
+                   "miss_frac": round(float(miss.double().mean()), 4)},
+        "train": {"epochs": epochs, "batch": 1024, "lr": lr, "quantiles": list(quantiles),
+                  "ms_per_epoch": round(ms_train / epochs, 3), "loss_first": round(float(lh[0]), 5),
+                  "loss_last": round(float(lh[-1]), 5)},
+        "predicted": {"pass_rate": round(pass_pred, 4), "matrices_per_s": round(nb / (ms_pred / 1e3), 1),
+                      "ms_per_batch": round(ms_pred, 4), "K_mean": round(k_mean, 2), "fallback_frac": round(fb, 4)},
+        "plain_cpa": {"K": chosen[0], "pass_rate": round(chosen[1], 4),
+                      "matrices_per_s": round(nb / (ms_plain / 1e3), 1), "ms_per_batch": round(ms_plain, 4)},
+        "gain": round(ms_plain / ms_pred, 3),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +321,9 @@ def main():
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-sparse", action="store_true")
+    ap.add_argument("--no-predictor", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
@@ -193,8 +333,21 @@ def main():
     import numpy as np
     import torch
 
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
+                          "launches": 3}), flush=True)
+        return
+
     import paper_1705_07112_amd as cpa
     import synth
+
+    def progress(msg):
+        print(f"bench: {msg}", file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
     I, _, _ = synth.rpca_frames(M, N)
@@ -279,31 +432,39 @@ def main():
                      "recurrence_avg_us": round(1e3 * rec2_ms / max(rec2_n, 1), 3),
                      "note": "same ADMM workload; recurrence products as bf16 hi/lo x3 on the BF16 matrix cores"}
 
+    check = None
     if not args.no_accuracy:
-        # errors of one shrink of the current ADMM iterate (L + U1) on the device
-        from oracle import cpa as ocpa
-        from oracle import exact, metrics
-        from oracle.shrinkage import Shrinkage
+        # one shrink of the current ADMM iterate (L + U1) on the device, against the
+        # exact soft shrinkage (LAPACK SVD); the FP64 CPA comparison is made in the
+        # oracle leg below
         Xd = (run.block(0) + run.block(4)).contiguous()
         Yd, info = cpa.shrink_dense(Xd, cpa.soft(INV_RHO), cpa.Opts(K=K), info=True)
         X64 = Xd.cpu().numpy().astype(np.float64)
         Y = Yd.cpu().numpy().astype(np.float64)
-        sh = Shrinkage(0, INV_RHO)
-        out["err_vs_fp64_cpa"] = float("%.3e" % metrics.rel_fro(Y, ocpa.cpa_shrink(X64, sh, info["Lambda"], K), X64))
-        out["err_vs_fp64_svt"] = float("%.3e" % metrics.rel_fro(Y, exact.svt_svd(X64, sh), X64))
+        ex = exact_shrink(X64, lambda sv: np.maximum(sv - INV_RHO, 0.0))
+        out["err_vs_fp64_svt"] = float("%.3e" % rel_fro(Y, ex, X64))
         Y2 = cpa.shrink_dense(Xd, cpa.soft(INV_RHO), cpa.Opts(K=K, Lambda=info["Lambda"], precision="bf16x3"))
-        out["bf16x3"]["err_vs_fp64_cpa"] = float("%.3e" % metrics.rel_fro(
-            Y2.cpu().numpy().astype(np.float64), ocpa.cpa_shrink(X64, sh, info["Lambda"], K), X64))
+        Y2 = Y2.cpu().numpy().astype(np.float64)
+        out["bf16x3"]["err_vs_fp64_svt"] = float("%.3e" % rel_fro(Y2, ex, X64))
         out["E_t_last"] = float("%.3e" % Et[-1].item())
+        check = (X64, {"fp32": Y, "bf16x3": Y2}, info["Lambda"])
 
+    progress("dense RPCA legs done")
     if not args.no_batched:
         out["batched"] = bench_batched(cpa, torch, np, synth)
+        progress("batched leg done")
 
     if not args.no_sparse:
         out["sparse"] = bench_sparse(cpa, torch, np, synth)
+        progress("sparse leg done")
+
+    if not args.no_predictor:
+        out["predictor"] = bench_predictor(cpa, torch, np, synth)
+        progress("predictor leg done")
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(I)
+        out["cpu_baseline"] = cpu_baseline(I, check=check)
+        progress("oracle leg done")
     print(json.dumps(out), flush=True)
 
 

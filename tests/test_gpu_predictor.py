@@ -300,3 +300,57 @@ def test_predictor_argument_errors():
     adam = torch.zeros(2 * cpa.PRED_PARAMS, device="cuda")
     with pytest.raises(cpa.CpaError):
         cpa.predictor_train(F, T, model, adam, 0, Q, batch_size=20000)
+
+
+def test_predictor_pipeline_small():
+    """Labels from the method, training by the library, predicted shrinkage on a
+    held-out batch: decisions stay in range, few fallbacks, results match the
+    oracle CPA at the kernel's own (Lambda, K) on a sample."""
+    import torch
+    import paper_1705_07112_amd as cpa
+    from paper_1705_07112_amd import predictor as P
+    dev = torch.device("cuda:0")
+
+    def make(batch, seed):
+        flat, ms, ns, offs, _, noises = synth.patch_groups(batch=batch, rank_range=(1, 16),
+                                                           noise_range=(0.05, 0.5), seed=seed)
+        taus = noises * (np.sqrt(ms) + np.sqrt(ns))
+        ex = P.exact_soft_batch(flat, ms, ns, offs, taus)
+        return (flat, ms, ns, offs, taus, torch.from_numpy(flat).to(dev), torch.from_numpy(ms).to(dev),
+                torch.from_numpy(ns).to(dev), torch.from_numpy(offs).to(dev), P.soft_records(torch, taus, dev),
+                torch.from_numpy(ex).to(dev))
+
+    flat, ms, ns, offs, taus, X, m, n, off, recs, Yex = make(3000, 901)
+    feat, targ, kstar, miss = P.make_labels(torch, X, m, n, off, recs, ms, ns, offs, Yex, gate=1e-2)
+    assert bool(torch.isfinite(targ).all())
+    assert float(miss.double().mean()) < 0.05
+    assert int(kstar.min()) >= 4 and int(kstar.max()) <= 64
+    mean = feat.double().mean(0).cpu().numpy()
+    std = feat.double().std(0).cpu().numpy()
+    model = torch.from_numpy(P.init_model(0, mean, std)).to(dev)
+    adam = torch.zeros(2 * cpa.PRED_PARAMS, dtype=torch.float32, device=dev)
+    losses = torch.zeros(30, dtype=torch.float64, device=dev)
+    cpa.predictor_train(feat, targ, model, adam, 0, (0.99, 0.9), batch_size=256, epochs=30, lr=2e-3,
+                        epoch_loss=losses)
+    lh = losses.cpu().numpy()
+    assert lh[-1] < 0.5 * lh[0]
+
+    flat, ms, ns, offs, taus, X, m, n, off, recs, Yex = make(512, 902)
+    nb = 512
+    lam = torch.zeros(nb, dtype=torch.float64, device=dev)
+    kout = torch.zeros(nb, dtype=torch.int32, device=dev)
+    st = torch.full((nb,), -1, dtype=torch.int32, device=dev)
+    Y = cpa.shrink_batched_predicted(X, m, n, off, cpa.soft(0.0), cpa.Opts(K=64, check=True), model, K_min=4,
+                                     shrink_per_matrix=recs, lambda_out=lam, K_out=kout, status=st)
+    sth = st.cpu().numpy()
+    assert np.all((sth == 0) | (sth == 1))
+    assert np.mean(sth == 1) < 0.1
+    kh = kout.cpu().numpy()
+    assert kh.min() >= 4 and kh.max() <= 64
+    Yh = Y.cpu().numpy()
+    lamh = lam.cpu().numpy()
+    for j in range(0, nb, 16):
+        A = flat[offs[j]:offs[j] + ms[j] * ns[j]].reshape(ms[j], ns[j]).astype(np.float64)
+        got = Yh[offs[j]:offs[j] + A.size].reshape(A.shape).astype(np.float64)
+        ref = ocpa.cpa_shrink(A, Shrinkage(0, float(taus[j]), 0, 0, 0), float(lamh[j]), int(kh[j]))
+        assert metrics.rel_fro(got, ref, A) <= TOL32, j
