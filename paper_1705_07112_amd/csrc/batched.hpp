@@ -74,6 +74,19 @@ struct BatchArgs {
     int* queue;                // next matrix index (zeroed before launch)
 };
 
+__device__ inline double bt_wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Value of v held by lane l (l uniform across the wave).
+__device__ inline double bt_readlane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ inline double bt_block_sum(double v, double* red) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     __syncthreads();
@@ -82,10 +95,12 @@ __device__ inline double bt_block_sum(double v, double* red) {
     return red[0] + red[1] + red[2] + red[3];
 }
 
-__global__ void __launch_bounds__(BT_THREADS) batched_kernel(BatchArgs a) {
+// Two workgroups per CU (the register budget is capped accordingly): one
+// matrix's barriers and power iteration overlap another's recurrence.
+__global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
     __shared__ __attribute__((aligned(16))) float YT[BT_EMAX * BT_DP];
     __shared__ __attribute__((aligned(16))) float Gs[BT_DMAX * BT_DP];
-    __shared__ double vv[BT_DMAX], ww[BT_DMAX], coef[64], red[4];
+    __shared__ double vv[BT_DMAX], coef[64], red[4];   // vv: scratch of the predictor network
     __shared__ int s_idx;
     __shared__ double s_scal[4];
 
@@ -193,46 +208,58 @@ __global__ void __launch_bounds__(BT_THREADS) batched_kernel(BatchArgs a) {
             } else if (mode == 2 || !(fro > 0.0)) {
                 Lam = (1.0 + a.margin) * fro;
             } else if (mode == 0) {
-                // power iteration on G (d x d) in LDS, FP64; start vector as in the dense path
-                if (threadIdx.x < d) {
-                    const uint64_t z = a.seed + (uint64_t)(threadIdx.x + 1) * 0x9E3779B97F4A7C15ull;
-                    uint64_t o = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-                    o = (o ^ (o >> 27)) * 0x94D049BB133111EBull;
-                    o ^= o >> 31;
-                    vv[threadIdx.x] = 2.0 * ((double)(o >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+                // power iteration on G (d x d), FP64, start vector as in the dense path.
+                // One wave: lane i owns row i (G is symmetric, so it reads column i,
+                // which is free of bank conflicts), v_j is broadcast with readlane and
+                // the sums are in-wave shuffles: no workgroup barrier per iteration.
+                if (wave == 0) {
+                    double v = 0.0;
+                    if (lane < d) {
+                        const uint64_t z = a.seed + (uint64_t)(lane + 1) * 0x9E3779B97F4A7C15ull;
+                        uint64_t o = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+                        o = (o ^ (o >> 27)) * 0x94D049BB133111EBull;
+                        o ^= o >> 31;
+                        v = 2.0 * ((double)(o >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+                    }
+                    double nv = bt_wave_sum(v * v);
+                    double mu = 0.0, w2 = 0.0, muprev = 0.0;
+                    bool vanish = !(nv > 0.0);
+                    for (int t = 1; !vanish && t <= a.power_iters; ++t) {
+                        const double vs = v * (1.0 / sqrt(nv));
+                        // four independent partial sums (j mod 4) shorten the FMA chain
+                        double w4[4] = {0.0, 0.0, 0.0, 0.0};
+                        int j = 0;
+                        for (; j + 4 <= d; j += 4) {
+#pragma unroll
+                            for (int q = 0; q < 4; ++q)
+                                w4[q] += (double)Gs[(j + q) * BT_DP + lane] * bt_readlane(vs, j + q);
+                        }
+                        for (; j < d; ++j) w4[j & 3] += (double)Gs[j * BT_DP + lane] * bt_readlane(vs, j);
+                        const double wi = (w4[0] + w4[1]) + (w4[2] + w4[3]);
+                        mu = bt_wave_sum(vs * wi);
+                        w2 = bt_wave_sum(wi * wi);
+                        if (!(w2 > 0.0)) {
+                            vanish = true;
+                            break;
+                        }
+                        if (t >= 2 && fabs(mu - muprev) <= a.tol * mu) break;
+                        muprev = mu;
+                        v = wi;
+                        nv = w2;
+                    }
+                    double L;
+                    if (vanish) {
+                        L = (1.0 + a.margin) * fro;
+                    } else {
+                        const double r2 = w2 - mu * mu;
+                        const double r = sqrt(r2 > 0.0 ? r2 : 0.0);
+                        L = mu + (a.margin * mu > r ? a.margin * mu : r);
+                        if (L > (1.0 + a.margin) * fro) L = (1.0 + a.margin) * fro;
+                    }
+                    if (lane == 0) s_scal[3] = L;
                 }
                 __syncthreads();
-                double nv = bt_block_sum(threadIdx.x < d ? vv[threadIdx.x] * vv[threadIdx.x] : 0.0, red);
-                double mu = 0.0, w2 = 0.0, muprev = 0.0;
-                bool vanish = !(nv > 0.0);
-                for (int t = 1; !vanish && t <= a.power_iters; ++t) {
-                    const double inv = 1.0 / sqrt(nv);
-                    double wi = 0.0;
-                    if (threadIdx.x < d) {
-                        for (int j = 0; j < d; ++j) wi += (double)Gs[threadIdx.x * BT_DP + j] * (vv[j] * inv);
-                        ww[threadIdx.x] = wi;
-                    }
-                    const double m_part = threadIdx.x < d ? vv[threadIdx.x] * inv * wi : 0.0;
-                    mu = bt_block_sum(m_part, red);
-                    w2 = bt_block_sum(threadIdx.x < d ? wi * wi : 0.0, red);
-                    if (!(w2 > 0.0)) {
-                        vanish = true;
-                        break;
-                    }
-                    if (t >= 2 && fabs(mu - muprev) <= a.tol * mu) break;
-                    muprev = mu;
-                    if (threadIdx.x < d) vv[threadIdx.x] = ww[threadIdx.x];
-                    nv = w2;
-                    __syncthreads();
-                }
-                if (vanish) {
-                    Lam = (1.0 + a.margin) * fro;
-                } else {
-                    const double r2 = w2 - mu * mu;
-                    const double r = sqrt(r2 > 0.0 ? r2 : 0.0);
-                    Lam = mu + (a.margin * mu > r ? a.margin * mu : r);
-                    if (Lam > (1.0 + a.margin) * fro) Lam = (1.0 + a.margin) * fro;
-                }
+                Lam = s_scal[3];
             }
 
             // ---- coefficients (FP64, l ascending per k)
