@@ -238,11 +238,16 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
                         const double wi = (w4[0] + w4[1]) + (w4[2] + w4[3]);
                         mu = bt_wave_sum(vs * wi);
                         w2 = bt_wave_sum(wi * wi);
-                        if (!(w2 > 0.0)) {
+                        // the sums are bitwise equal in every lane (xor butterfly), so
+                        // the exit is taken by the whole wave; readfirstlane states
+                        // that to the compiler, which then branches on a scalar
+                        int stop = !(w2 > 0.0) ? 2 : ((t >= 2 && fabs(mu - muprev) <= a.tol * mu) ? 1 : 0);
+                        stop = __builtin_amdgcn_readfirstlane(stop);
+                        if (stop == 2) {
                             vanish = true;
                             break;
                         }
-                        if (t >= 2 && fabs(mu - muprev) <= a.tol * mu) break;
+                        if (stop == 1) break;
                         muprev = mu;
                         v = wi;
                         nv = w2;

@@ -122,3 +122,24 @@ def test_batched_rejects_out_of_range_shapes():
     mats, shr_c, _, lams = _mats_and_params([(65, 70), (64, 129), (64, 40)], 13000)
     outs, _, status = _run(mats, shr_c, 8, "given", lams)
     assert list(status) == [2, 2, 0]
+
+
+def test_converged_power_bound_matches_oracle_on_hard_cases():
+    """Converged power bounds (tol 1e-12) on matrices whose iteration stops on the
+    tolerance late, including one whose top two eigenvalues nearly coincide; the
+    wave that runs the iteration must leave the loop together (regression: a
+    per-lane exit once returned about half of lambda_max here)."""
+    import paper_1705_07112_amd as cpa
+    flat, ms, ns, offs, _, _ = synth.patch_groups(batch=32768, rank_range=(1, 16), noise_range=(0.05, 0.5),
+                                                  seed=synth.BASE_SEED + 4)
+    g = np.random.Generator(np.random.PCG64(5))
+    pick = [10625, 628, 1000, 1079, 2065] + sorted(g.choice(32768, size=120, replace=False).tolist())
+    mats = [flat[offs[i]:offs[i] + ms[i] * ns[i]].reshape(ms[i], ns[i]).astype(np.float64) for i in pick]
+    shr = [cpa.soft(0.0)] * len(mats)
+    for batch in (mats, mats[:1]):
+        _, lam_out, status = _run(batch, shr[:len(batch)], 2, "power", None,
+                                  {"power_iters": 1000, "power_tol": 1e-12, "margin": 0.0})
+        assert np.all(status == 0)
+        for X, lg in zip(batch, lam_out):
+            lo = obound.power_bound(_gram(X), seed=0, max_iter=1000, tol=1e-12, delta=0.0)[0]
+            assert abs(lg - lo) <= 1e-4 * lo, (lg, lo)
