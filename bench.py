@@ -66,6 +66,24 @@ def cpu_baseline(I, budget_s: float = 15.0, check=None):
     return res
 
 
+def measured_traffic(path: str = os.path.join(ROOT, "profiles", "recurrence_gemm_f32_1024_K30_pmc_traffic.md")):
+    """HBM bytes per launch of the recurrence GEMM from its committed counter summary,
+    or None when the summary is missing or the kernel source changed since."""
+    import hashlib
+    try:
+        fields = {}
+        for line in open(path):
+            if ":" in line and line.startswith("    ") and not line.strip().startswith("rocprofv3"):
+                k, v = line.strip().split(":", 1)
+                fields[k.strip()] = v.strip()
+        src = os.path.join(ROOT, fields["kernel_source"])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != fields["kernel_source_sha256"]:
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def exact_shrink(X, g):
     """U g(Sigma) V^T by LAPACK's SVD in FP64 (the definition of singular value shrinkage)."""
     import numpy as np
@@ -407,7 +425,8 @@ def main():
         "wall_s_timed": round(wall, 4),
         "roofline": {"bound": "mfma", "kernel": "recurrence GEMM (FP32 MFMA, fused Chebyshev epilogue)",
                      "achieved": round(achieved, 3), "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / MFMA_FP32_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(achieved / MFMA_FP32_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
+                     "traffic_unit": "bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, copy-calibrated)",
                      "avg_launch_us": round(rec_avg_us, 3), "launches": rec_n,
                      "flop_per_launch": flop_gemm,
                      "timing": "HIP events around each launch, same workload, pass right after the timed region",
