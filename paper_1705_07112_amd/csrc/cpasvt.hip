@@ -481,7 +481,8 @@ constexpr int kSqGrid = 512;   // workgroups of the ||S||_F^2 reduction
 struct SpWork {
     float* Y[2];
     float* W;
-    int64_t ld;        // row pitch of Y and W (n rounded up to 4)
+    int64_t ld;        // row pitch of Y and W (n rounded up to 32: 128-byte rows)
+    float* cval;       // values of S in column order (nnz)
     double* tvec;
     double* w[2];
     double* scal;
@@ -496,7 +497,7 @@ cpa_status ensure_sparse_ws(cpa_ctx* ctx, int m, int n, int64_t nnz, int K, int 
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
         ctx->coop_max = std::max(1, per_cu * cus);
     }
-    w.ld = (n + 3) & ~int64_t(3);
+    w.ld = (n + 31) & ~int64_t(31);
     w.lay.K = K;
     w.lay.maxit = maxit;
     w.lay.gwg = kSqGrid;
@@ -509,6 +510,7 @@ cpa_status ensure_sparse_ws(cpa_ctx* ctx, int m, int n, int64_t nnz, int K, int 
     const size_t ow0 = off; off = align_up(off + sizeof(double) * (size_t)std::max(n, 1));
     const size_t ow1 = off; off = align_up(off + sizeof(double) * (size_t)std::max(n, 1));
     const size_t os = off; off = align_up(off + sizeof(double) * (size_t)w.lay.total());
+    const size_t ocv = off; off = align_up(off + sizeof(float) * (size_t)std::max<int64_t>(nnz, 1));
     size_t oy = 0;
     if (svt) { oy = off; off = align_up(off + sizeof(float) * (size_t)std::max<int64_t>(nnz, 1)); }
     if (off > ctx->sws_bytes) {
@@ -528,6 +530,7 @@ cpa_status ensure_sparse_ws(cpa_ctx* ctx, int m, int n, int64_t nnz, int K, int 
     w.Y[0] = reinterpret_cast<float*>(b + oY0);
     w.Y[1] = reinterpret_cast<float*>(b + oY1);
     w.W = reinterpret_cast<float*>(b + oW);
+    w.cval = reinterpret_cast<float*>(b + ocv);
     w.tvec = reinterpret_cast<double*>(b + oT);
     w.w[0] = reinterpret_cast<double*>(b + ow0);
     w.w[1] = reinterpret_cast<double*>(b + ow1);
@@ -661,13 +664,19 @@ cpa_status shrink_csr_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t n
     hipLaunchKernelGGL(densify_kernel, dim3(std::min(m, 8192)), dim3(256), 0, st, m, rowptr, colidx, val, w.Y[0],
                        w.ld);
     HIP_TRY(hipGetLastError());
-    const int panels = (n + SP_PANEL - 1) / SP_PANEL;
     if (o->K == 1) {
         hipLaunchKernelGGL(scale_copy_kernel, dim3((int)std::min<int64_t>(4096, (total + 255) / 256)), dim3(256), 0,
                            st, m, n, (const float*)w.Y[0], w.ld, Y, ldy, (const double*)w.scal);
         HIP_TRY(hipGetLastError());
         return CPA_OK;
     }
+    if (nnz > 0) {
+        hipLaunchKernelGGL(csc_values_kernel, dim3((int)std::min<int64_t>(4096, (nnz + 255) / 256)), dim3(256), 0, st,
+                           nnz, csrc, val, w.cval);
+        HIP_TRY(hipGetLastError());
+    }
+    const int grid_t = ((n + SP_WAVES - 1) / SP_WAVES) * ((n + SPT_J - 1) / SPT_J);
+    const int grid_c = ((m + SP_WAVES - 1) / SP_WAVES) * ((n + SPC_J - 1) / SPC_J);
     for (int k = 0; k + 1 <= o->K - 1; ++k) {
         const float* yk = w.Y[k & 1];
         const float* yp = w.Y[(k + 1) & 1];
@@ -676,10 +685,10 @@ cpa_status shrink_csr_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t n
         cpa_status s = timing_pair(ctx, 0, ea, eb);
         if (s != CPA_OK) return s;
         if (ea) HIP_TRY(hipEventRecord(ea, st));
-        hipLaunchKernelGGL(spmm_t_kernel, dim3(n * panels), dim3(SP_THREADS), 0, st, n, n, colptr, crow, csrc, val,
-                           yk, w.ld, w.W, w.ld);
+        hipLaunchKernelGGL(spmm_t_kernel, dim3(grid_t), dim3(SP_THREADS), 0, st, n, n, colptr, crow,
+                           (const float*)w.cval, yk, w.ld, w.W, w.ld);
         HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(spmm_cheb_kernel, dim3(m * panels), dim3(SP_THREADS), 0, st, m, n, rowptr, colidx, val,
+        hipLaunchKernelGGL(spmm_cheb_kernel, dim3(grid_c), dim3(SP_THREADS), 0, st, m, n, rowptr, colidx, val,
                            (const float*)w.W, w.ld, yk, yp, ydst, w.ld, Y, ldy, (const double*)w.scal, k,
                            (k + 1 == o->K - 1) ? 1 : 0, aligned16(Y, ldy) ? 1 : 0);
         HIP_TRY(hipGetLastError());

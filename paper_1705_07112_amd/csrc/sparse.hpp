@@ -11,11 +11,18 @@
 //   csc_*            the transposed pattern (column pointers, row indices and the
 //                    CSR position of each entry, rows ascending within a column),
 //                    built once per pattern on the device;
-//   spmm_t_kernel    W[c][:] = sum_{(r,c) in S} s_rc Y[r][:], one workgroup per
-//                    (column, 1024-wide panel), panels outermost so the gathered rows of
-//                    one panel of Y stay in the Infinity Cache; rows ascending (fixed
-//                    order);
-//   spmm_cheb_kernel Z[r][:] = sum_{(r,c)} s_rc W[c][:] with the recurrence epilogue.
+//   spmm_t_kernel    W[c][:] = sum_{(r,c) in S} s_rc Y[r][:], one wave per output
+//                    column c and 32-column panel of Y, panels outermost: a panel of
+//                    Y (m x 32 floats, 2.5 MB at m = 20000) stays in each XCD's 4 MB
+//                    L2 while every wave gathers from it; 8 nonzeros in flight per
+//                    wave (8 lanes x float4 per gathered 128-byte row segment);
+//   spmm_cheb_kernel Z[r][:] = sum_{(r,c)} s_rc W[c][:] with the recurrence epilogue,
+//                    one wave per output row and 128-column panel of W (n x 128
+//                    floats, 2 MB at n = 4000), 2 nonzeros in flight per wave.
+// Both kernels read the pattern and the streamed operands with non-temporal
+// loads and stores so that they do not evict the gathered panel; partial sums
+// are combined in a fixed order (xor shuffles), so results do not depend on
+// scheduling.
 //   power_op_kernel  power iteration on S^T S through two sparse products per step,
 //                    one cooperative launch (two grid barriers per product).
 #pragma once
@@ -28,7 +35,9 @@
 namespace cpa {
 
 constexpr int SP_THREADS = 256;
-constexpr int SP_PANEL = 4 * SP_THREADS;   // columns of Y / W per workgroup (float4 per thread)
+constexpr int SP_WAVES = SP_THREADS / 64;   // output rows (or columns) per workgroup, one per wave
+constexpr int SPT_J = 32;                   // panel width of S^T Y_k
+constexpr int SPC_J = 128;                  // panel width of S W
 
 // Flags a malformed CSR (rowptr[0] != 0, rowptr[m] != nnz, decreasing row
 // pointers, or a column index outside [0, n)).  Reads only rowptr[0..m] and
@@ -114,38 +123,78 @@ __global__ void densify_kernel(int m, const int32_t* rowptr, const int32_t* coli
             Y[(int64_t)r * ldy + colidx[e]] = val[e];
 }
 
-__device__ inline void panel_of(int nrows, int& row, int& col0) {
-    // panels outermost: all rows of panel 0, then panel 1, ...
-    row = blockIdx.x % nrows;
-    col0 = (blockIdx.x / nrows) * SP_PANEL;
+// cval[p] = val[csrc[p]]: the values in column order, gathered once per shrink.
+__global__ void csc_values_kernel(int64_t nnz, const int32_t* csrc, const float* val, float* cval) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x)
+        cval[p] = val[csrc[p]];
 }
 
-// W[c][j] = sum over column c of S of s_rc * Y[r][j], j in this workgroup's panel.
+__device__ inline f32x4 sp_shfl_xor4(f32x4 v, int off) {
+    f32x4 r;
+    r[0] = __shfl_xor(v[0], off, 64);
+    r[1] = __shfl_xor(v[1], off, 64);
+    r[2] = __shfl_xor(v[2], off, 64);
+    r[3] = __shfl_xor(v[3], off, 64);
+    return r;
+}
+
+// W[c][j] = sum over column c of S of s_rc * Y[r][j], j in this wave's 32-column
+// panel.  Lane = 8 * g + q: row group g and float4 q of the panel.  Grid: ceil(n / 4) x ceil(ncols / 32) workgroups,
+// panels outermost.
 __global__ void __launch_bounds__(SP_THREADS) spmm_t_kernel(int n, int ncols, const int32_t* colptr,
-                                                            const int32_t* crow, const int32_t* csrc,
-                                                            const float* val, const float* Y, int64_t ldy,
-                                                            float* W, int64_t ldw) {
-    int c, col0;
-    panel_of(n, c, col0);
-    const int j = col0 + 4 * threadIdx.x;
-    if (j >= ncols) return;
+                                                            const int32_t* crow, const float* cval,
+                                                            const float* Y, int64_t ldy, float* W, int64_t ldw) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int groups = (n + SP_WAVES - 1) / SP_WAVES;
+    const int panel = blockIdx.x / groups;
+    const int c = (blockIdx.x - panel * groups) * SP_WAVES + wave;
+    if (c >= n) return;
+    const int g = lane >> 3;
+    const int j = panel * SPT_J + 4 * (lane & 7);
     const bool full = j + 3 < ncols;
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int32_t p = colptr[c]; p < colptr[c + 1]; ++p) {
-        const float s = val[csrc[p]];
-        const float* yr = Y + (int64_t)crow[p] * ldy + j;
-        if (full) {
-            const f32x4 y = *reinterpret_cast<const f32x4*>(yr);
-            acc += s * y;
-        } else {
-            for (int q = 0; q < 4 && j + q < ncols; ++q) acc[q] += s * yr[q];
+    const int32_t p0 = colptr[c], p1 = colptr[c + 1];
+    // chunks of 64 entries: one coalesced load of (row, value) per lane, then
+    // row group g gathers entries g, g + 8, ..., g + 56 with all eight in flight
+    for (int32_t base = p0; base < p1; base += 64) {
+        const int cnt = p1 - base < 64 ? (int)(p1 - base) : 64;
+        int32_t rl = 0;
+        float sl = 0.f;
+        if (lane < cnt) {
+            rl = __builtin_nontemporal_load(crow + base + lane);
+            sl = __builtin_nontemporal_load(cval + base + lane);
         }
+        f32x4 y[8];
+        float sv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = g + 8 * u;
+            const int32_t r = __shfl(rl, i, 64);
+            sv[u] = __shfl(sl, i, 64);
+            y[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+            if (i < cnt) {
+                const float* yr = Y + (int64_t)r * ldy + j;
+                if (full) {
+                    y[u] = *reinterpret_cast<const f32x4*>(yr);
+                } else {
+                    for (int q = 0; q < 4; ++q)
+                        if (j + q < ncols) y[u][q] = yr[q];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += sv[u] * y[u];
     }
+    acc += sp_shfl_xor4(acc, 8);
+    acc += sp_shfl_xor4(acc, 16);
+    acc += sp_shfl_xor4(acc, 32);
+    if (g != 0 || j >= ncols) return;
     float* wr = W + (int64_t)c * ldw + j;
     if (full) {
         *reinterpret_cast<f32x4*>(wr) = acc;
     } else {
-        for (int q = 0; q < 4 && j + q < ncols; ++q) wr[q] = acc[q];
+        for (int q = 0; q < 4; ++q)
+            if (j + q < ncols) wr[q] = acc[q];
     }
 }
 
@@ -153,29 +202,62 @@ __global__ void __launch_bounds__(SP_THREADS) spmm_t_kernel(int n, int ncols, co
 //   first step: Ynew = a1 Z - Yk,  out = c0/2 Yk + c1 Ynew
 //   later:      Ynew = a2 Z - 2 Yk - Yprev,  out += c_{k+1} Ynew
 // Ynew goes to Ydst (may equal Yprev) unless this is the last step.
-// The workspace buffers (W, Y*) have row pitches % 4 == 0 and aligned bases;
-// `out_vec` says whether the caller's output allows 16-byte accesses too.
+// Lane = 32 * g + q: entry group g and float4 q of the 128-column panel.  Grid: ceil(m / 4) x ceil(ncols / 128), panels
+// outermost.  The workspace buffers (W, Y*) have row pitches % 32 == 0 and
+// aligned bases; `out_vec` says whether the caller's output allows 16-byte
+// accesses too.
 __global__ void __launch_bounds__(SP_THREADS) spmm_cheb_kernel(int m, int ncols, const int32_t* rowptr,
                                                                const int32_t* colidx, const float* val,
                                                                const float* W, int64_t ldw, const float* Yk,
                                                                const float* Yprev, float* Ydst, int64_t ldy,
                                                                float* out, int64_t ldo, const double* scal,
                                                                int step, int last, int out_vec) {
-    int r, col0;
-    panel_of(m, r, col0);
-    const int j = col0 + 4 * threadIdx.x;
-    if (j >= ncols) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int groups = (m + SP_WAVES - 1) / SP_WAVES;
+    const int panel = blockIdx.x / groups;
+    const int r = (blockIdx.x - panel * groups) * SP_WAVES + wave;
+    if (r >= m) return;
+    const int g = lane >> 5;
+    const int j = panel * SPC_J + 4 * (lane & 31);
     const bool full = j + 3 < ncols;
     f32x4 z = {0.f, 0.f, 0.f, 0.f};
-    for (int32_t e = rowptr[r]; e < rowptr[r + 1]; ++e) {
-        const float s = val[e];
-        const float* wr = W + (int64_t)colidx[e] * ldw + j;
-        if (full) {
-            z += s * *reinterpret_cast<const f32x4*>(wr);
-        } else {
-            for (int q = 0; q < 4 && j + q < ncols; ++q) z[q] += s * wr[q];
+    const int32_t e0 = rowptr[r], e1 = rowptr[r + 1];
+    // chunks of 64 entries: one coalesced load of (column, value) per lane, then
+    // entry group g gathers entries g, g + 2, ..., eight at a time in flight
+    for (int32_t base = e0; base < e1; base += 64) {
+        const int cnt = e1 - base < 64 ? (int)(e1 - base) : 64;
+        int32_t cl = 0;
+        float sl = 0.f;
+        if (lane < cnt) {
+            cl = __builtin_nontemporal_load(colidx + base + lane);
+            sl = __builtin_nontemporal_load(val + base + lane);
+        }
+        // the trip count is uniform across the wave (shuffles read every lane)
+        for (int u0 = 0; u0 < 32 && 2 * u0 < cnt; u0 += 8) {
+            f32x4 w[8];
+            float sv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = g + 2 * (u0 + u);
+                const int32_t c = __shfl(cl, i, 64);
+                sv[u] = __shfl(sl, i, 64);
+                w[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+                if (i < cnt) {
+                    const float* wr = W + (int64_t)c * ldw + j;
+                    if (full) {
+                        w[u] = *reinterpret_cast<const f32x4*>(wr);
+                    } else {
+                        for (int q = 0; q < 4; ++q)
+                            if (j + q < ncols) w[u][q] = wr[q];
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) z += sv[u] * w[u];
         }
     }
+    z += sp_shfl_xor4(z, 32);
+    if (g != 0 || j >= ncols) return;
     float a, b, cc;
     if (step == 0) {
         a = (float)scal[SC_A1];
@@ -192,8 +274,8 @@ __global__ void __launch_bounds__(SP_THREADS) spmm_cheb_kernel(int m, int ncols,
     const int cnt = full ? 4 : ncols - j;
     f32x4 yk = {0.f, 0.f, 0.f, 0.f}, yp = {0.f, 0.f, 0.f, 0.f}, o = {0.f, 0.f, 0.f, 0.f};
     if (full) {
-        yk = *reinterpret_cast<const f32x4*>(Yk + oy);
-        if (step > 0) yp = *reinterpret_cast<const f32x4*>(Yprev + oy);
+        yk = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(Yk + oy));
+        if (step > 0) yp = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(Yprev + oy));
     } else {
         for (int q = 0; q < cnt; ++q) {
             yk[q] = Yk[oy + q];
@@ -202,7 +284,7 @@ __global__ void __launch_bounds__(SP_THREADS) spmm_cheb_kernel(int m, int ncols,
     }
     if (step > 0) {
         if (full && out_vec) {
-            o = *reinterpret_cast<const f32x4*>(out + oo);
+            o = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(out + oo));
         } else {
             for (int q = 0; q < cnt; ++q) o[q] = out[oo + q];
         }
@@ -216,13 +298,13 @@ __global__ void __launch_bounds__(SP_THREADS) spmm_cheb_kernel(int m, int ncols,
         o[q] = step == 0 ? c0h * yk[q] + ck * y : o[q] + ck * y;
     }
     if (full && out_vec) {
-        *reinterpret_cast<f32x4*>(out + oo) = o;
+        __builtin_nontemporal_store(o, reinterpret_cast<f32x4*>(out + oo));
     } else {
         for (int q = 0; q < cnt; ++q) out[oo + q] = o[q];
     }
     if (!last) {
         if (full) {
-            *reinterpret_cast<f32x4*>(Ydst + oy) = yn;
+            __builtin_nontemporal_store(yn, reinterpret_cast<f32x4*>(Ydst + oy));
         } else {
             for (int q = 0; q < cnt; ++q) Ydst[oy + q] = yn[q];
         }
