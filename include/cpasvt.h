@@ -91,6 +91,21 @@ typedef enum { CPA_BOUND_POWER = 0, CPA_BOUND_GIVEN = 1, CPA_BOUND_FROBENIUS = 2
  *                    coefficients stay FP32 / FP64. */
 typedef enum { CPA_PREC_FP32 = 0, CPA_PREC_BF16X3 = 1 } cpa_precision;
 
+/* How the polynomial hat H(Gram) = c_0/2 I + sum_k c_k T_k(hat B) reaches X (dense path).
+ *   CPA_EVAL_RECURRENCE  the three-term recurrence distributed over X (Algorithm 1's
+ *                        loop applied to Y_k = X T_k(hat B)): K - 1 products of size
+ *                        max(m,n) x d x d, d = min(m, n).
+ *   CPA_EVAL_POLYNOMIAL  the matrix polynomial on the d x d side first (Algorithm 1's
+ *                        H), then one product with X.  The polynomial is formed with
+ *                        baby steps / giant steps in the Chebyshev basis: T_1..T_s by
+ *                        the recurrence (s = ceil(sqrt K), at most 16), then
+ *                        p = sum_j R_j T_j(T_s) by Clenshaw's recurrence, using
+ *                        T_j(T_s(x)) = T_{js}(x): about 2 sqrt(K) products of d x d x d.
+ *                        Same polynomial; rounding differs.  K <= 256; not with check = 1.
+ *   CPA_EVAL_AUTO        POLYNOMIAL when check = 0, K <= 256 and it costs fewer flops,
+ *                        otherwise RECURRENCE. */
+typedef enum { CPA_EVAL_AUTO = 0, CPA_EVAL_RECURRENCE = 1, CPA_EVAL_POLYNOMIAL = 2 } cpa_eval;
+
 typedef struct {
     int32_t K;            /* number of Chebyshev coefficients (the paper's order alpha), >= 1 */
     int32_t bound;        /* cpa_bound_rule */
@@ -104,6 +119,8 @@ typedef struct {
                              recompute at Lambda = ||Gram||_F on failure (synchronises the stream) */
     int32_t precision;    /* cpa_precision */
     double growth_tol;    /* tolerance of the growth check */
+    int32_t eval;         /* cpa_eval (dense path; the sparse and batched paths use the recurrence) */
+    int32_t reserved;     /* must be 0 */
 } cpa_opts;
 
 /* Per-call report (host struct).  Filling it synchronises the stream. */
@@ -112,7 +129,8 @@ typedef struct {
     double mu;            /* last Rayleigh quotient (0 unless CPA_BOUND_POWER) */
     double resid;         /* last residual norm ||Gram v - mu v|| */
     double fro_gram;      /* ||Gram||_F */
-    double max_growth;    /* max_k ||Y_k||_F / ||X||_F over k = 1..K-1 (0 if K == 1) */
+    double max_growth;    /* max_k ||Y_k||_F / ||X||_F over k = 1..K-1 (0 if K == 1 or when the
+                             matrix-polynomial route ran: it never forms Y_k) */
     int32_t power_iters_done;
     int32_t fallback;     /* 1 when the growth check forced Lambda = ||Gram||_F */
     int32_t side;         /* 0: Gram = X^T X (m >= n), 1: Gram = X X^T (m < n) */
@@ -131,7 +149,8 @@ const char* cpa_status_string(cpa_status s);
 const char* cpa_last_error(void);
 
 /* Fills opts with defaults: K = 16, POWER bound, power_iters = 100, power_tol = 1e-7,
- * margin = 0.01, seed = 0, warm_start = 0, check = 0, FP32, growth_tol = 1e-3. */
+ * margin = 0.01, seed = 0, warm_start = 0, check = 0, FP32, growth_tol = 1e-3,
+ * eval = CPA_EVAL_AUTO. */
 void cpa_default_opts(cpa_opts* opts);
 
 /* Chebyshev coefficients on the host in FP64 (Sec. III-A, eq. chebychev_coeff_shifted;

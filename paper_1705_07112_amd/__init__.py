@@ -39,7 +39,8 @@ class CpaOpts(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("bound", ctypes.c_int32), ("Lambda", ctypes.c_double),
                 ("power_iters", ctypes.c_int32), ("warm_start", ctypes.c_int32),
                 ("power_tol", ctypes.c_double), ("margin", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("check", ctypes.c_int32), ("precision", ctypes.c_int32), ("growth_tol", ctypes.c_double)]
+                ("check", ctypes.c_int32), ("precision", ctypes.c_int32), ("growth_tol", ctypes.c_double),
+                ("eval", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class CpaInfo(ctypes.Structure):
@@ -164,6 +165,7 @@ class Opts:
     check: bool = False
     growth_tol: float = 1e-3
     precision: str = "fp32"      # "fp32" | "bf16x3"
+    eval: str = "auto"           # "auto" | "recurrence" | "polynomial"
 
     def to_c(self) -> CpaOpts:
         o = CpaOpts()
@@ -182,6 +184,7 @@ class Opts:
         o.check = int(bool(self.check))
         o.precision = {"fp32": PREC_FP32, "bf16x3": PREC_BF16X3}[self.precision]
         o.growth_tol = float(self.growth_tol)
+        o.eval = {"auto": 0, "recurrence": 1, "polynomial": 2}[self.eval]
         return o
 
 

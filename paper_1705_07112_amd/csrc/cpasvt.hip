@@ -112,6 +112,8 @@ struct Work {
     float* x;      // ADMM shrink input
     double* admm;  // ADMM E_t partial sums (2 per pre-kernel workgroup)
     int* et_counter;  // next E_t slot
+    float* poly;      // matrix-polynomial route: T_1..T_s and three Clenshaw buffers (d x d each)
+    int poly_s;       // s of that route (0: not allocated)
     ScalarLayout lay;
 };
 
@@ -129,7 +131,7 @@ int power_grid(cpa_ctx* ctx, int d) {
     return want;
 }
 
-cpa_status ensure_ws(cpa_ctx* ctx, int m, int n, int K, int maxit, bool admm, Work& w) {
+cpa_status ensure_ws(cpa_ctx* ctx, int m, int n, int K, int maxit, bool admm, Work& w, int poly_s = 0) {
     const int d = std::min(m, n);
     const int64_t mn = (int64_t)m * n;
     if (ctx->coop_max == 0) {
@@ -149,6 +151,8 @@ cpa_status ensure_ws(cpa_ctx* ctx, int m, int n, int K, int maxit, bool admm, Wo
     const size_t ow0 = off; off = align_up(off + sizeof(double) * (size_t)d);
     const size_t ow1 = off; off = align_up(off + sizeof(double) * (size_t)d);
     const size_t os = off; off = align_up(off + sizeof(double) * (size_t)w.lay.total());
+    size_t opl = 0;
+    if (poly_s > 0) { opl = off; off = align_up(off + sizeof(float) * (size_t)(poly_s + 3) * d * d); }
     size_t ox = 0, oa = 0;
     if (admm) {
         ox = off; off = align_up(off + sizeof(float) * (size_t)mn);
@@ -177,6 +181,8 @@ cpa_status ensure_ws(cpa_ctx* ctx, int m, int n, int K, int maxit, bool admm, Wo
     w.x = admm ? reinterpret_cast<float*>(b + ox) : nullptr;
     w.admm = admm ? reinterpret_cast<double*>(b + oa) : nullptr;
     w.et_counter = admm ? reinterpret_cast<int*>(b + oa + sizeof(double) * 2 * kAdmmGrid) : nullptr;
+    w.poly = poly_s > 0 ? reinterpret_cast<float*>(b + opl) : nullptr;
+    w.poly_s = poly_s;
     if (d > ctx->warm_cap) {
         if (ctx->warm) {
             HIP_TRY(hipDeviceSynchronize());
@@ -286,6 +292,12 @@ cpa_status check_opts(const cpa_opts* o) {
     }
     if (o->precision != CPA_PREC_FP32 && o->precision != CPA_PREC_BF16X3)
         return fail(CPA_ERR_UNSUPPORTED, "precision %d not supported", o->precision);
+    if (o->eval < CPA_EVAL_AUTO || o->eval > CPA_EVAL_POLYNOMIAL) return fail(CPA_ERR_ARG, "unknown eval %d", o->eval);
+    if (o->eval == CPA_EVAL_POLYNOMIAL && o->check)
+        return fail(CPA_ERR_UNSUPPORTED, "the growth check needs the recurrence (eval AUTO or RECURRENCE)");
+    if (o->eval == CPA_EVAL_POLYNOMIAL && o->K > 256)
+        return fail(CPA_ERR_UNSUPPORTED, "the matrix-polynomial route supports K <= 256");
+    if (o->reserved != 0) return fail(CPA_ERR_ARG, "opts.reserved must be 0");
     return CPA_OK;
 }
 
@@ -420,6 +432,133 @@ cpa_status enqueue_recurrence(cpa_ctx* ctx, hipStream_t st, int m, int n, const 
     return CPA_OK;
 }
 
+// ---- matrix-polynomial route ---------------------------------------------------
+//
+// The same polynomial as the recurrence, p(Ghat) = c_0/2 I + sum_k c_k T_k(Ghat), is
+// formed on the d x d side (as Algorithm 1's H = sum c_k Psi_k) with baby steps and
+// giant steps in the Chebyshev basis:
+//   T_1 = Ghat, T_{i+1} = 2 T_1 T_i - T_{i-1}            (i < s: s - 1 products)
+//   p = sum_j R_j T_j(y), y = T_s, R_j = sum_i r_{j,i} T_i   (Clenshaw in y: J - 1 products)
+//   Y = X p (m >= n) or p X (m < n)                         (one product)
+// with s = ceil(sqrt(K)) and J = ceil(K / s) (K <= 256, so s, J <= 16): about
+// 2 sqrt(K) products instead of K - 1.  All matrices of the route are polynomials
+// in Ghat, hence symmetric in exact arithmetic, and the engine reads the second
+// operand along k, i.e. transposed.  Only the fixed operands (T_1 in the baby
+// steps, y in the giant steps) are taken that way: a transposed T_1 or y is one
+// fixed, slightly different operator for the whole chain, whereas transposing
+// the operand that changes from step to step lets its rounding asymmetry grow
+// (about 3e-5 at s = 10 in FP32, and relative errors near 1e-3 at K = 144).
+
+constexpr int kPolyMaxK = kPsMaxS * kPsMaxS;   // 256
+
+int poly_s_of(int K) {
+    int s = 1;
+    while (s * s < K) ++s;
+    return std::min(s, kPsMaxS);
+}
+
+// s of the matrix-polynomial route when `o` selects it for an m x n input, else 0.
+int poly_choice(const cpa_opts* o, int m, int n) {
+    if (o->K < 2 || o->K > kPolyMaxK || o->eval == CPA_EVAL_RECURRENCE) return 0;
+    const int s = poly_s_of(o->K), J = (o->K + s - 1) / s;
+    if (o->eval == CPA_EVAL_POLYNOMIAL) return s;
+    if (o->check) return 0;   // the growth check needs every ||Y_k||
+    const double d = std::min(m, n), e = std::max(m, n);
+    const double cost_poly = (double)(s - 1 + J - 1) * d * d * d + e * d * d;
+    const double cost_rec = (double)(o->K - 1) * e * d * d;
+    return cost_poly < cost_rec ? s : 0;
+}
+
+template <class Epi>
+cpa_status poly_gemm(cpa_ctx* ctx, hipStream_t st, const Operand& A, const Operand& B, int M, int N, int Kd,
+                     const Epi& epi, int precision, bool kk) {
+    hipEvent_t ea, eb;
+    cpa_status s = timing_pair(ctx, 0, ea, eb);
+    if (s != CPA_OK) return s;
+    if (ea) HIP_TRY(hipEventRecord(ea, st));
+    if (kk)
+        s = precision == CPA_PREC_BF16X3 ? launch_gemm_split<KCONTIG, KCONTIG>(st, A, B, M, N, Kd, epi, SC_A1, SC_A2, SC_COEF)
+                                         : gemm_dispatch<KCONTIG, KCONTIG>(st, A, B, M, N, Kd, epi, SC_A1, SC_A2, SC_COEF);
+    else
+        s = precision == CPA_PREC_BF16X3 ? launch_gemm_split<XCONTIG, XCONTIG>(st, A, B, M, N, Kd, epi, SC_A1, SC_A2, SC_COEF)
+                                         : gemm_dispatch<XCONTIG, XCONTIG>(st, A, B, M, N, Kd, epi, SC_A1, SC_A2, SC_COEF);
+    if (s != CPA_OK) return s;
+    if (eb) HIP_TRY(hipEventRecord(eb, st));
+    return CPA_OK;
+}
+
+EpiLin lin_epi(float* D, int64_t ldd, const float* Mx, int64_t ldm, float alpha, float beta, float gamma, float delta) {
+    EpiLin e;
+    e.D = D;
+    e.ldd = ldd;
+    e.Mx = Mx;
+    e.ldm = ldm;
+    e.alpha = alpha;
+    e.beta = beta;
+    e.gamma = gamma;
+    e.delta = delta;
+    e.vec_ok = aligned16(D, ldd) && (gamma == 0.f || aligned16(Mx, ldm));
+    return e;
+}
+
+cpa_status enqueue_poly(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* X, int64_t ldx, float* Y,
+                        int64_t ldy, int K, const Work& w, int precision) {
+    const int d = std::min(m, n);
+    const int s = w.poly_s, J = (K + s - 1) / s;
+    const int64_t dd = (int64_t)d * d;
+    float* T1 = w.poly;                       // T_q at T1 + (q - 1) dd, q = 1..s
+    float* Bf[3] = {w.poly + s * dd, w.poly + (s + 1) * dd, w.poly + (s + 2) * dd};
+    const int roff = w.lay.ps();
+    const int ge = (int)std::min<int64_t>(4096, (dd + 255) / 256);
+    hipLaunchKernelGGL(ps_coeff_kernel, dim3(1), dim3(64), 0, st, K, s, J, w.scal, roff);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(ps_shift_kernel, dim3(ge), dim3(256), 0, st, d, (const float*)w.G, T1, (const double*)w.scal);
+    HIP_TRY(hipGetLastError());
+    cpa_status r;
+    auto Tq = [&](int q) { return T1 + (int64_t)(q - 1) * dd; };
+    // baby steps: T_{i+1} = 2 T_i T_1 - T_{i-1}, T_0 = I (T_1 is the operand read transposed)
+    for (int i = 1; i < s; ++i) {
+        const EpiLin e = lin_epi(Tq(i + 1), d, i > 1 ? Tq(i - 1) : nullptr, d, 2.f, 0.f, i > 1 ? -1.f : 0.f,
+                                 i > 1 ? 0.f : -1.f);
+        if ((r = poly_gemm(ctx, st, make_op(Tq(i), d, d), make_op(T1, d, d), d, d, d, e, precision, true)) != CPA_OK)
+            return r;
+    }
+    // giant steps (Clenshaw in y = T_s): b_{J-1} = R_{J-1}; b_j = R_j + 2 y b_{j+1} - b_{j+2}; p = R_0 + y b_1 - b_2
+    float* F = Bf[0];
+    if (J == 1) {
+        hipLaunchKernelGGL(ps_lincomb_kernel, dim3(ge), dim3(256), 0, st, d, s, (const float*)T1,
+                           (const double*)w.scal, roff, F);
+        HIP_TRY(hipGetLastError());
+    } else {
+        const float* y = Tq(s);
+        int cur = 0;          // buffer holding b_{j+1}
+        int prev = -1;        // buffer holding b_{j+2} (none yet)
+        hipLaunchKernelGGL(ps_lincomb_kernel, dim3(ge), dim3(256), 0, st, d, s, (const float*)T1,
+                           (const double*)w.scal, roff + (J - 1) * s, Bf[cur]);
+        HIP_TRY(hipGetLastError());
+        for (int j = J - 2; j >= 0; --j) {
+            int dst = 0;
+            while (dst == cur || dst == prev) ++dst;
+            hipLaunchKernelGGL(ps_lincomb_kernel, dim3(ge), dim3(256), 0, st, d, s, (const float*)T1,
+                               (const double*)w.scal, roff + j * s, Bf[dst]);
+            HIP_TRY(hipGetLastError());
+            const float* b2 = prev >= 0 ? Bf[prev] : nullptr;
+            const EpiLin e = lin_epi(Bf[dst], d, b2, d, j > 0 ? 2.f : 1.f, 1.f, b2 ? -1.f : 0.f, 0.f);
+            // b_{j+1} y with y read transposed
+            if ((r = poly_gemm(ctx, st, make_op(Bf[cur], d, d), make_op(y, d, d), d, d, d, e, precision, true)) != CPA_OK)
+                return r;
+            prev = cur;
+            cur = dst;
+        }
+        F = Bf[cur];
+    }
+    // Y = X p (right) or p X (left)
+    const EpiLin e = lin_epi(Y, ldy, nullptr, 0, 1.f, 0.f, 0.f, 0.f);
+    if (m >= n)
+        return poly_gemm(ctx, st, make_op(X, ldx, m), make_op(F, d, n), m, n, n, e, precision, true);
+    return poly_gemm(ctx, st, make_op(F, d, m), make_op(X, ldx, n), m, n, m, e, precision, false);
+}
+
 cpa_status read_info(hipStream_t st, const Work& w, int K, int m, int n, cpa_info* info, double* growth_out) {
     std::vector<double> h(w.lay.total());
     HIP_TRY(hipMemcpyAsync(h.data(), w.scal, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
@@ -456,7 +595,12 @@ cpa_status shrink_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* 
     if ((s = fill_scalars(st, w)) != CPA_OK) return s;
     if ((s = enqueue_gram(ctx, st, m, n, X, ldx, w)) != CPA_OK) return s;
     if ((s = enqueue_bound(ctx, st, d, sh, o, w, -1)) != CPA_OK) return s;
-    if ((s = enqueue_recurrence(ctx, st, m, n, X, ldx, Y, ldy, o->K, w, info != nullptr || o->check, o->precision)) != CPA_OK) return s;
+    if (w.poly_s > 0 && o->K >= 2) {
+        if ((s = enqueue_poly(ctx, st, m, n, X, ldx, Y, ldy, o->K, w, o->precision)) != CPA_OK) return s;
+    } else if ((s = enqueue_recurrence(ctx, st, m, n, X, ldx, Y, ldy, o->K, w, info != nullptr || o->check,
+                                       o->precision)) != CPA_OK) {
+        return s;
+    }
     if (!info && !o->check) return CPA_OK;
     double growth = 0.0;
     if ((s = read_info(st, w, o->K, m, n, info, &growth)) != CPA_OK) return s;
@@ -786,6 +930,8 @@ void cpa_default_opts(cpa_opts* o) {
     o->check = 0;
     o->precision = CPA_PREC_FP32;
     o->growth_tol = 1e-3;
+    o->eval = CPA_EVAL_AUTO;
+    o->reserved = 0;
 }
 
 cpa_status cpa_chebyshev_coeffs(const cpa_shrinkage* shrink, double Lambda, int K, double* c_host) {
@@ -845,7 +991,7 @@ cpa_status cpa_shrink_dense(cpa_ctx* ctx, void* stream, int m, int n, const floa
     hipStream_t st = static_cast<hipStream_t>(stream);
     Work w;
     const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
-    if ((s = ensure_ws(ctx, m, n, opts->K, maxit, false, w)) != CPA_OK) return s;
+    if ((s = ensure_ws(ctx, m, n, opts->K, maxit, false, w, poly_choice(opts, m, n))) != CPA_OK) return s;
     return shrink_impl(ctx, st, m, n, X_dev, ldx, Y_dev, ldy, shrink, opts, info_host, w);
 }
 
@@ -1304,7 +1450,7 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
     hipStream_t st = static_cast<hipStream_t>(stream);
     Work w;
     const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
-    if ((s = ensure_ws(ctx, m, n, opts->K, maxit, true, w)) != CPA_OK) return s;
+    if ((s = ensure_ws(ctx, m, n, opts->K, maxit, true, w, poly_choice(opts, m, n))) != CPA_OK) return s;
     AdmmPtrs P;
     P.l = state_dev;
     P.s = state_dev + mn;

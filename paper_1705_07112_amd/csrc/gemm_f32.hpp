@@ -389,6 +389,64 @@ struct EpiCheb {
     }
 };
 
+// D = alpha acc + beta D + gamma Mx + delta I (the matrix polynomial steps):
+// D row-major with pitch ldd (read when beta != 0), Mx with pitch ldm (read when
+// gamma != 0), I the identity (delta added where row == column).
+struct EpiLin {
+    float* D;
+    int64_t ldd;
+    const float* Mx;
+    int64_t ldm;
+    float alpha, beta, gamma, delta;
+    bool vec_ok;
+
+    template <int BM, int BN, int NG>
+    __device__ inline void run(const float* tile, int m0, int n0, int M, int N, const double*, int, int, int) const {
+        constexpr int P = BN + 4, GPR = BN / 4;
+        f32x4 vd[NG], vm[NG];
+        bool full[NG];
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+            const int g = threadIdx.x + q * GTHREADS;
+            const int i = m0 + g / GPR, j = n0 + (g % GPR) * 4;
+            full[q] = vec_ok && i < M && j + 3 < N;
+            vd[q] = vm[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            if (full[q]) {
+                if (beta != 0.f) vd[q] = *reinterpret_cast<const f32x4*>(D + (int64_t)i * ldd + j);
+                if (gamma != 0.f) vm[q] = *reinterpret_cast<const f32x4*>(Mx + (int64_t)i * ldm + j);
+            } else if (i < M) {
+                for (int e = 0; e < 4; ++e) {
+                    if (j + e < N) {
+                        if (beta != 0.f) vd[q][e] = D[(int64_t)i * ldd + j + e];
+                        if (gamma != 0.f) vm[q][e] = Mx[(int64_t)i * ldm + j + e];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+            const int g = threadIdx.x + q * GTHREADS;
+            const int r = g / GPR, cc = (g % GPR) * 4;
+            const int i = m0 + r, j = n0 + cc;
+            const f32x4 acc = *reinterpret_cast<const f32x4*>(tile + r * P + cc);
+            f32x4 o;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float v = alpha * acc[e] + beta * vd[q][e] + gamma * vm[q][e];
+                if (i == j + e) v += delta;
+                o[e] = v;
+            }
+            if (full[q]) {
+                *reinterpret_cast<f32x4*>(D + (int64_t)i * ldd + j) = o;
+            } else if (i < M) {
+                for (int e = 0; e < 4; ++e)
+                    if (j + e < N) D[(int64_t)i * ldd + j + e] = o[e];
+            }
+        }
+    }
+};
+
+__device__ inline const double* epi_scal(const EpiLin&) { return nullptr; }
 __device__ inline const double* epi_scal(const EpiGram&) { return nullptr; }
 __device__ inline const double* epi_scal(const EpiCheb& e) { return e.scal; }
 

@@ -49,6 +49,8 @@ enum : int {
 
 constexpr int kNormSlots = 64;   // partial-sum slots per growth-check norm
 
+constexpr int kPsMaxS = 16;   // largest baby-step count of the matrix-polynomial route
+
 struct ScalarLayout {
     int K, maxit, gwg, pwg;      // gwg: Gram workgroups, pwg: power-iteration workgroups
     int coef() const { return SC_COEF; }
@@ -57,7 +59,8 @@ struct ScalarLayout {
     int pw_w2() const { return pw_mu() + maxit + 1; }                 // ||w_t||^2
     int gpart() const { return pw_w2() + maxit + 1; }                 // 2 per Gram workgroup
     int ppart() const { return gpart() + 2 * gwg; }                   // 2 x 2 per power workgroup
-    int total() const { return ppart() + 4 * pwg; }
+    int ps() const { return ppart() + 4 * pwg; }                       // matrix-polynomial coefficients
+    int total() const { return ps() + K + kPsMaxS; }
 };
 
 __global__ void fill_f64_kernel(double* p, int n, double v) {
@@ -306,6 +309,53 @@ __global__ void scale_copy_kernel(int m, int n, const float* X, int64_t ldx, flo
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = e / n, j = e % n;
         Y[i * ldy + j] = c * X[i * ldx + j];
+    }
+}
+
+// Matrix-polynomial route (baby steps / giant steps in the Chebyshev basis).
+// p(x) = c_0/2 + sum_{k>=1} c_k T_k(x) is rewritten as
+//   p(x) = sum_{j<J} R_j(x) T_j(y),  y = T_s(x),  R_j = sum_{i<s} r_{j,i} T_i(x),
+// using T_j(T_s(x)) = T_{js}(x) and T_i T_{js} = (T_{js+i} + T_{js-i}) / 2: from
+// the highest degree down, r_{j,i} = 2 w_{js+i} and w_{js-i} -= w_{js+i} (i >= 1),
+// r_{j,0} = w_{js}, r_{0,i} = w_i.  One thread, FP64; r is written row by row.
+__global__ void ps_coeff_kernel(int K, int s, int J, double* scal, int out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double* w = scal + out;   // the output area doubles as the working copy
+    for (int k = 0; k < J * s; ++k) w[k] = k < K ? scal[SC_COEF + k] * (k == 0 ? 0.5 : 1.0) : 0.0;
+    // in place: entry (j, i) of r lives at w[j s + i]
+    for (int j = J - 1; j >= 1; --j) {
+        for (int i = s - 1; i >= 1; --i) {
+            const int k = j * s + i;
+            const double v = w[k];
+            w[k] = 2.0 * v;
+            w[j * s - i] -= v;
+        }
+    }
+}
+
+// T1 = (2 / Lambda) G - I, d x d, pitch d.
+__global__ void ps_shift_kernel(int d, const float* G, float* T1, const double* scal) {
+    const float a1 = (float)scal[SC_A1];
+    const int64_t total = (int64_t)d * d;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = p / d, j = p - i * d;
+        T1[p] = a1 * G[p] - (i == j ? 1.f : 0.f);
+    }
+}
+
+// dst = r[0] I + sum_{q=1}^{s-1} r[q] T_q, with T_q at T1 + (q - 1) d^2 (pitch d).
+__global__ void ps_lincomb_kernel(int d, int s, const float* T1, const double* scal, int roff, float* dst) {
+    const int64_t dd = (int64_t)d * d;
+    float r[kPsMaxS];
+#pragma unroll
+    for (int q = 0; q < kPsMaxS; ++q) r[q] = q < s ? (float)scal[roff + q] : 0.f;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < dd; p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = p / d, j = p - i * d;
+        float v = i == j ? r[0] : 0.f;
+#pragma unroll
+        for (int q = 1; q < kPsMaxS; ++q)
+            if (q < s) v += r[q] * T1[(q - 1) * dd + p];
+        dst[p] = v;
     }
 }
 

@@ -32,7 +32,7 @@ def test_status_strings_and_defaults():
 
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(cpa.CpaShrinkage) == 40
-    assert ctypes.sizeof(cpa.CpaOpts) == 64
+    assert ctypes.sizeof(cpa.CpaOpts) == 72
     assert ctypes.sizeof(cpa.CpaInfo) == 56
 
 

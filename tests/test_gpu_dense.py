@@ -34,7 +34,7 @@ def _gram_lmax(X):
     return float(np.linalg.eigvalsh(G)[-1]) if G.size else 0.0
 
 
-def _run(X64, sh_c, K, Lam, ld=None, offset=0):
+def _run(X64, sh_c, K, Lam, ld=None, offset=0, ev="auto"):
     torch = _torch()
     cpa = _lib()
     m, n = X64.shape
@@ -44,13 +44,13 @@ def _run(X64, sh_c, K, Lam, ld=None, offset=0):
     view.copy_(torch.from_numpy(X64.astype(np.float32)))
     bufd = buf.cuda()
     Xd = bufd[offset:offset + m * ld].view(m, ld)[:, :n]
-    Y, info = cpa.shrink_dense(Xd, sh_c, cpa.Opts(K=K, Lambda=Lam), info=True)
+    Y, info = cpa.shrink_dense(Xd, sh_c, cpa.Opts(K=K, Lambda=Lam, eval=ev), info=True)
     torch.cuda.synchronize()
     return Y.cpu().numpy().astype(np.float64), info
 
 
-def _case(m, n, K, kind, seed, ld=None, offset=0):
-    print(f"case m={m} n={n} K={K} kind={kind} seed={seed} ld={ld} off={offset}", flush=True)
+def _case(m, n, K, kind, seed, ld=None, offset=0, ev="auto"):
+    print(f"case m={m} n={n} K={K} kind={kind} seed={seed} ld={ld} off={offset} eval={ev}", flush=True)
     X = synth.as_f32_exact(synth.dense_lowrank(m, n, rank=min(4, m, n), noise=0.2, seed=seed))
     lmax = _gram_lmax(X)
     Lam = 1.01 * lmax
@@ -64,7 +64,7 @@ def _case(m, n, K, kind, seed, ld=None, offset=0):
         wc, ws = 0.3 * tau * tau, 0.05 * lmax
         sh_o, sh_c = Shrinkage(3, 0.0, wc, ws, 1e-3), cpa.weighted_fn(wc, ws, 1e-3)
     ref = ocpa.cpa_shrink(X, sh_o, Lam, K)
-    got, info = _run(X, sh_c, K, Lam, ld=ld, offset=offset)
+    got, info = _run(X, sh_c, K, Lam, ld=ld, offset=offset, ev=ev)
     err = metrics.rel_fro(got, ref, X)
     print(f"  rel_fro={err:.3e}", flush=True)
     assert err <= TOL32, (m, n, K, kind, err)
@@ -192,3 +192,48 @@ def test_full_size_rpca_matrix_sampled_rows():
     # the power bound path on the device agrees with the oracle's bound
     lam_g, _ = cpa.spectral_bound(Xd, cpa.Opts(K=K))
     assert abs(lam_g - lam_o) <= 2e-6 * lam_o
+
+
+@pytest.mark.parametrize("ev", ["recurrence", "polynomial"])
+@pytest.mark.parametrize("shape,K", [((64, 48), 20), ((130, 70), 30), ((70, 130), 30), ((129, 129), 7),
+                                     ((300, 1100), 16), ((1, 5), 9), ((5, 1), 9), ((200, 3), 64),
+                                     ((64, 64), 100), ((64, 64), 144), ((97, 33), 2), ((97, 33), 3),
+                                     ((40, 30), 256)])
+def test_both_evaluation_routes(ev, shape, K):
+    """The recurrence over X and the matrix polynomial on the d x d side (baby
+    steps / giant steps) against the same oracle."""
+    m, n = shape
+    for kind in (0, 1, 2):
+        _case(m, n, K, kind, seed=7000 + m + n + K, ev=ev)
+
+
+def test_polynomial_route_full_size_and_unaligned():
+    torch = _torch()
+    cpa = _lib()
+    I, _, _ = synth.rpca_frames()
+    X = I.astype(np.float64)
+    lam_o = obound.power_bound(X.T @ X, seed=0)[0]
+    Xd = torch.from_numpy(I).cuda()
+    rows = np.array([0, 5, 64, 511, 777, 1023])
+    for K in (16, 30, 64):
+        Y = cpa.shrink_dense(Xd, cpa.soft(10.0), cpa.Opts(K=K, Lambda=lam_o, eval="polynomial")).cpu().numpy()
+        ref = ocpa.cpa_rows(X, Shrinkage(0, 10.0), lam_o, K, rows)
+        err = metrics.rel_fro(Y[rows].astype(np.float64), ref)
+        print(f"polynomial route 1024^2 K={K} sampled rel_fro={err:.3e}", flush=True)
+        assert err <= TOL32
+    # odd d (no 16-byte rows) and a strided input
+    _case(131, 77, 25, 0, seed=91, ev="polynomial")
+    _case(77, 131, 25, 0, seed=92, ev="polynomial", ld=140, offset=3)
+
+
+def test_polynomial_route_rejects_growth_check():
+    torch = _torch()
+    cpa = _lib()
+    Xd = torch.ones((8, 4), device="cuda")
+    with pytest.raises(cpa.CpaError):
+        cpa.shrink_dense(Xd, cpa.soft(0.1), cpa.Opts(K=9, eval="polynomial", check=True))
+    with pytest.raises(cpa.CpaError):
+        cpa.shrink_dense(Xd, cpa.soft(0.1), cpa.Opts(K=257, eval="polynomial"))
+    # auto with the check takes the recurrence and reports its growth
+    _, info = cpa.shrink_dense(Xd, cpa.soft(0.1), cpa.Opts(K=9, check=True), info=True)
+    assert info["max_growth"] > 0.0

@@ -18,7 +18,7 @@ pytestmark = pytest.mark.gpu
 TOL_SPLIT = 1e-3
 
 
-def _case(m, n, K, kind, seed, ld=None):
+def _case(m, n, K, kind, seed, ld=None, ev="auto"):
     import torch
     import paper_1705_07112_amd as cpa
     X = synth.as_f32_exact(synth.dense_lowrank(m, n, rank=min(4, m, n), noise=0.2, seed=seed))
@@ -36,9 +36,9 @@ def _case(m, n, K, kind, seed, ld=None):
     buf = torch.zeros(m * ld, dtype=torch.float32)
     buf.view(m, ld)[:, :n] = torch.from_numpy(X.astype(np.float32))
     Xd = buf.cuda().view(m, ld)[:, :n]
-    Y = cpa.shrink_dense(Xd, sh_c, cpa.Opts(K=K, Lambda=Lam, precision="bf16x3")).cpu().numpy()
+    Y = cpa.shrink_dense(Xd, sh_c, cpa.Opts(K=K, Lambda=Lam, precision="bf16x3", eval=ev)).cpu().numpy()
     err = metrics.rel_fro(Y, ocpa.cpa_shrink(X, sh_o, Lam, K), X)
-    print(f"bf16x3 m={m} n={n} K={K} kind={kind} rel_fro={err:.3e}", flush=True)
+    print(f"bf16x3 m={m} n={n} K={K} kind={kind} eval={ev} rel_fro={err:.3e}", flush=True)
     assert err <= TOL_SPLIT
     return err
 
@@ -70,3 +70,9 @@ def test_split_full_size_rpca_matrix():
     err = metrics.rel_fro(Y[rows].astype(np.float64), ocpa.cpa_rows(X, Shrinkage(0, 10.0), lam, 30, rows))
     print(f"bf16x3 full size sampled rows rel_fro={err:.3e}", flush=True)
     assert err <= TOL_SPLIT
+
+
+@pytest.mark.parametrize("ev", ["recurrence", "polynomial"])
+@pytest.mark.parametrize("shape", [(130, 70), (70, 130), (129, 129)])
+def test_split_both_evaluation_routes(ev, shape):
+    _case(*shape, 30, 0, 9300 + shape[0] + shape[1], ev=ev)
