@@ -170,8 +170,10 @@ def bench_batched(cpa, torch, np, synth, timed_runs: int = 5):
 
 def bench_sparse(cpa, torch, np, synth):
     """Sparse completion-shaped shrink: S 20000 x 4000 with 2% observed entries (CSR,
-    1.6M nonzeros) of a rank-10 N(0,1) product, K = 25, soft tau = 0.5 sqrt(Lambda),
-    operator form (W = S^T Y_k, then S W with the fused recurrence update)."""
+    1.6M nonzeros) of a rank-10 N(0,1) product, K = 25, soft tau = 0.5 sqrt(Lambda).
+    Main figure: the default route (matrix polynomial: Gram S^T S by one sparse
+    product, the polynomial on the 4000 x 4000 side, one product S p).  Beside it:
+    the operator-form recurrence (W = S^T Y_k, then S W with the fused update)."""
     m, n, K = 20000, 4000, 25
     _, _, rowptr, cols, vals = synth.completion()
     dev = torch.device("cuda:0")
@@ -181,38 +183,49 @@ def bench_sparse(cpa, torch, np, synth):
     out = torch.empty((m, n), device=dev, dtype=torch.float32)
     _, info = cpa.shrink_csr(m, n, r, c, v, cpa.soft(1.0), cpa.Opts(K=2), out=out, info=True)
     tau = 0.5 * (info["Lambda"] / 1.01) ** 0.5
-    opts = cpa.Opts(K=K, warm_start=True)
-    cpa.shrink_csr(m, n, r, c, v, cpa.soft(tau), opts, out=out)
-    torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    reps = 3
-    e0.record()
-    for _ in range(reps):
+    res = {}
+    for ev in ("auto", "recurrence"):
+        opts = cpa.Opts(K=K, warm_start=True, eval=ev)
         cpa.shrink_csr(m, n, r, c, v, cpa.soft(tau), opts, out=out)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_shrink = e0.elapsed_time(e1) / reps
-    cpa.timing_enable(True)
-    cpa.shrink_csr(m, n, r, c, v, cpa.soft(tau), opts, out=out)
-    torch.cuda.synchronize()
-    step_ms, steps = cpa.timing_read("recurrence")
-    cpa.timing_enable(False)
+        torch.cuda.synchronize()
+        reps = 3
+        e0.record()
+        for _ in range(reps):
+            cpa.shrink_csr(m, n, r, c, v, cpa.soft(tau), opts, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_shrink = e0.elapsed_time(e1) / reps
+        cpa.timing_enable(True)
+        cpa.shrink_csr(m, n, r, c, v, cpa.soft(tau), opts, out=out)
+        torch.cuda.synchronize()
+        tot_ms, launches = cpa.timing_read("recurrence")
+        cpa.timing_enable(False)
+        res[ev] = (ms_shrink, 1e3 * tot_ms / max(launches, 1), launches)
     nnz = int(vals.size)
     dense = 4.0 * m * n
-    # algorithmic bytes of a middle step: S^T Y_k reads Y_k and the transposed pattern
-    # (row, source position, value), writes W; S W reads the CSR pattern and W, reads
+    # operator form, algorithmic bytes of a middle step: S^T Y_k reads Y_k and the
+    # transposed pattern (row, value), writes W; S W reads the CSR pattern and W, reads
     # Y_k, Y_{k-1} and the accumulator, writes the accumulator and Y_{k+1}
-    step_bytes = (dense + 12.0 * nnz + 4.0 * n * n) + (8.0 * nnz + 4.0 * n * n + 5 * dense)
-    avg_step_us = 1e3 * step_ms / max(steps, 1)
+    step_bytes = (dense + 8.0 * nnz + 4.0 * n * n) + (8.0 * nnz + 4.0 * n * n + 5 * dense)
+    ms_p, us_p, l_p = res["auto"]
+    ms_r, us_r, l_r = res["recurrence"]
+    flop_gemm = 2.0 * n * n * n
     return {
-        "workload": "CSR 20000 x 4000, 1.6M nonzeros (2%), rank-10 N(0,1) values, soft, K=25, operator form",
-        "ms_per_shrink": round(ms_shrink, 3), "shrinks_per_s": round(1e3 / ms_shrink, 2),
-        "spmm_pair_avg_us": round(avg_step_us, 1),
-        "roofline": {"bound": "hbm", "achieved": round(step_bytes / (avg_step_us * 1e-6) / 1e9, 1),
-                     "peak": 8000.0, "unit": "GB/s",
-                     "frac": round(step_bytes / (avg_step_us * 1e-6) / 1e9 / 8000.0, 4),
-                     "bytes_per_step": step_bytes, "traffic": None},
+        "workload": "CSR 20000 x 4000, 1.6M nonzeros (2%), rank-10 N(0,1) values, soft, K=25",
+        "route": "matrix polynomial: Gram S^T S (sparse), polynomial on 4000 x 4000 (FP32 MFMA), Y = S p (sparse)",
+        "ms_per_shrink": round(ms_p, 3), "shrinks_per_s": round(1e3 / ms_p, 2),
+        "roofline": {"bound": "mfma", "kernel": "4000^3 polynomial GEMM", "achieved": round(flop_gemm / (us_p * 1e-6) / 1e12, 2),
+                     "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(flop_gemm / (us_p * 1e-6) / 1e12 / MFMA_FP32_PEAK_TFLOPS, 4),
+                     "avg_launch_us": round(us_p, 1), "launches": l_p, "traffic": None},
+        "operator_form": {"ms_per_shrink": round(ms_r, 3), "shrinks_per_s": round(1e3 / ms_r, 2),
+                          "spmm_pair_avg_us": round(us_r, 1),
+                          "roofline": {"bound": "hbm", "achieved": round(step_bytes / (us_r * 1e-6) / 1e9, 1),
+                                       "peak": 8000.0, "unit": "GB/s",
+                                       "frac": round(step_bytes / (us_r * 1e-6) / 1e9 / 8000.0, 4),
+                                       "bytes_per_step": step_bytes, "traffic": None}},
     }
 
 

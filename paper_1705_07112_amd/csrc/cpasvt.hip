@@ -501,18 +501,18 @@ EpiLin lin_epi(float* D, int64_t ldd, const float* Mx, int64_t ldm, float alpha,
     return e;
 }
 
-cpa_status enqueue_poly(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* X, int64_t ldx, float* Y,
-                        int64_t ldy, int K, const Work& w, int precision) {
-    const int d = std::min(m, n);
-    const int s = w.poly_s, J = (K + s - 1) / s;
+// The polynomial p(Ghat) (d x d, pitch d) from the Gram G (pitch ldg) and the
+// coefficients in scal; `poly` holds s + 3 matrices of d x d.  Returns p's buffer.
+cpa_status enqueue_poly_core(cpa_ctx* ctx, hipStream_t st, int d, const float* G, int64_t ldg, double* scal,
+                             int roff, float* poly, int s, int K, int precision, float** F_out) {
+    const int J = (K + s - 1) / s;
     const int64_t dd = (int64_t)d * d;
-    float* T1 = w.poly;                       // T_q at T1 + (q - 1) dd, q = 1..s
-    float* Bf[3] = {w.poly + s * dd, w.poly + (s + 1) * dd, w.poly + (s + 2) * dd};
-    const int roff = w.lay.ps();
+    float* T1 = poly;                         // T_q at T1 + (q - 1) dd, q = 1..s
+    float* Bf[3] = {poly + s * dd, poly + (s + 1) * dd, poly + (s + 2) * dd};
     const int ge = (int)std::min<int64_t>(4096, (dd + 255) / 256);
-    hipLaunchKernelGGL(ps_coeff_kernel, dim3(1), dim3(64), 0, st, K, s, J, w.scal, roff);
+    hipLaunchKernelGGL(ps_coeff_kernel, dim3(1), dim3(64), 0, st, K, s, J, scal, roff);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(ps_shift_kernel, dim3(ge), dim3(256), 0, st, d, (const float*)w.G, T1, (const double*)w.scal);
+    hipLaunchKernelGGL(ps_shift_kernel, dim3(ge), dim3(256), 0, st, d, G, ldg, T1, (const double*)scal);
     HIP_TRY(hipGetLastError());
     cpa_status r;
     auto Tq = [&](int q) { return T1 + (int64_t)(q - 1) * dd; };
@@ -523,36 +523,46 @@ cpa_status enqueue_poly(cpa_ctx* ctx, hipStream_t st, int m, int n, const float*
         if ((r = poly_gemm(ctx, st, make_op(Tq(i), d, d), make_op(T1, d, d), d, d, d, e, precision, true)) != CPA_OK)
             return r;
     }
-    // giant steps (Clenshaw in y = T_s): b_{J-1} = R_{J-1}; b_j = R_j + 2 y b_{j+1} - b_{j+2}; p = R_0 + y b_1 - b_2
-    float* F = Bf[0];
+    // giant steps (Clenshaw in y = T_s): b_{J-1} = R_{J-1}; b_j = R_j + 2 b_{j+1} y - b_{j+2};
+    // p = R_0 + b_1 y - b_2
     if (J == 1) {
         hipLaunchKernelGGL(ps_lincomb_kernel, dim3(ge), dim3(256), 0, st, d, s, (const float*)T1,
-                           (const double*)w.scal, roff, F);
+                           (const double*)scal, roff, Bf[0]);
         HIP_TRY(hipGetLastError());
-    } else {
-        const float* y = Tq(s);
-        int cur = 0;          // buffer holding b_{j+1}
-        int prev = -1;        // buffer holding b_{j+2} (none yet)
-        hipLaunchKernelGGL(ps_lincomb_kernel, dim3(ge), dim3(256), 0, st, d, s, (const float*)T1,
-                           (const double*)w.scal, roff + (J - 1) * s, Bf[cur]);
-        HIP_TRY(hipGetLastError());
-        for (int j = J - 2; j >= 0; --j) {
-            int dst = 0;
-            while (dst == cur || dst == prev) ++dst;
-            hipLaunchKernelGGL(ps_lincomb_kernel, dim3(ge), dim3(256), 0, st, d, s, (const float*)T1,
-                               (const double*)w.scal, roff + j * s, Bf[dst]);
-            HIP_TRY(hipGetLastError());
-            const float* b2 = prev >= 0 ? Bf[prev] : nullptr;
-            const EpiLin e = lin_epi(Bf[dst], d, b2, d, j > 0 ? 2.f : 1.f, 1.f, b2 ? -1.f : 0.f, 0.f);
-            // b_{j+1} y with y read transposed
-            if ((r = poly_gemm(ctx, st, make_op(Bf[cur], d, d), make_op(y, d, d), d, d, d, e, precision, true)) != CPA_OK)
-                return r;
-            prev = cur;
-            cur = dst;
-        }
-        F = Bf[cur];
+        *F_out = Bf[0];
+        return CPA_OK;
     }
-    // Y = X p (right) or p X (left)
+    const float* y = Tq(s);
+    int cur = 0;          // buffer holding b_{j+1}
+    int prev = -1;        // buffer holding b_{j+2} (none yet)
+    hipLaunchKernelGGL(ps_lincomb_kernel, dim3(ge), dim3(256), 0, st, d, s, (const float*)T1, (const double*)scal,
+                       roff + (J - 1) * s, Bf[cur]);
+    HIP_TRY(hipGetLastError());
+    for (int j = J - 2; j >= 0; --j) {
+        int dst = 0;
+        while (dst == cur || dst == prev) ++dst;
+        hipLaunchKernelGGL(ps_lincomb_kernel, dim3(ge), dim3(256), 0, st, d, s, (const float*)T1,
+                           (const double*)scal, roff + j * s, Bf[dst]);
+        HIP_TRY(hipGetLastError());
+        const float* b2 = prev >= 0 ? Bf[prev] : nullptr;
+        const EpiLin e = lin_epi(Bf[dst], d, b2, d, j > 0 ? 2.f : 1.f, 1.f, b2 ? -1.f : 0.f, 0.f);
+        // b_{j+1} y with y read transposed
+        if ((r = poly_gemm(ctx, st, make_op(Bf[cur], d, d), make_op(y, d, d), d, d, d, e, precision, true)) != CPA_OK)
+            return r;
+        prev = cur;
+        cur = dst;
+    }
+    *F_out = Bf[cur];
+    return CPA_OK;
+}
+
+cpa_status enqueue_poly(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* X, int64_t ldx, float* Y,
+                        int64_t ldy, int K, const Work& w, int precision) {
+    const int d = std::min(m, n);
+    float* F = nullptr;
+    cpa_status r = enqueue_poly_core(ctx, st, d, w.G, d, w.scal, w.lay.ps(), w.poly, w.poly_s, K, precision, &F);
+    if (r != CPA_OK) return r;
+    // Y = X p (right) or p X (left); p read transposed (it is the fixed operand)
     const EpiLin e = lin_epi(Y, ldy, nullptr, 0, 1.f, 0.f, 0.f, 0.f);
     if (m >= n)
         return poly_gemm(ctx, st, make_op(X, ldx, m), make_op(F, d, n), m, n, n, e, precision, true);
@@ -631,10 +641,13 @@ struct SpWork {
     double* w[2];
     double* scal;
     float* yv;         // SVT iterate values (nnz), when requested
+    float* poly;       // matrix-polynomial route: s + 3 matrices of n x n (or nullptr)
+    int poly_s;
     ScalarLayout lay;
 };
 
-cpa_status ensure_sparse_ws(cpa_ctx* ctx, int m, int n, int64_t nnz, int K, int maxit, bool svt, SpWork& w) {
+cpa_status ensure_sparse_ws(cpa_ctx* ctx, int m, int n, int64_t nnz, int K, int maxit, bool svt, SpWork& w,
+                            int poly_s = 0) {
     if (ctx->coop_max == 0) {
         int per_cu = 0, cus = 0;
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, power_coop_kernel, kPowerThreads, 0));
@@ -657,6 +670,8 @@ cpa_status ensure_sparse_ws(cpa_ctx* ctx, int m, int n, int64_t nnz, int K, int 
     const size_t ocv = off; off = align_up(off + sizeof(float) * (size_t)std::max<int64_t>(nnz, 1));
     size_t oy = 0;
     if (svt) { oy = off; off = align_up(off + sizeof(float) * (size_t)std::max<int64_t>(nnz, 1)); }
+    size_t opl = 0;
+    if (poly_s > 0) { opl = off; off = align_up(off + sizeof(float) * (size_t)(poly_s + 3) * n * n); }
     if (off > ctx->sws_bytes) {
         if (ctx->sws) {
             HIP_TRY(hipDeviceSynchronize());
@@ -675,6 +690,8 @@ cpa_status ensure_sparse_ws(cpa_ctx* ctx, int m, int n, int64_t nnz, int K, int 
     w.Y[1] = reinterpret_cast<float*>(b + oY1);
     w.W = reinterpret_cast<float*>(b + oW);
     w.cval = reinterpret_cast<float*>(b + ocv);
+    w.poly = poly_s > 0 ? reinterpret_cast<float*>(b + opl) : nullptr;
+    w.poly_s = poly_s;
     w.tvec = reinterpret_cast<double*>(b + oT);
     w.w[0] = reinterpret_cast<double*>(b + ow0);
     w.w[1] = reinterpret_cast<double*>(b + ow1);
@@ -763,6 +780,20 @@ cpa_status ensure_csc(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t nnz, c
 }
 
 // One sparse shrink, Y = hat G(S) (dense m x n at Y, ldy), everything enqueued.
+// s of the matrix-polynomial route for a CSR input (0: operator-form recurrence).
+// The route costs one sparse product for the Gram S^T S, s - 1 + J - 1 dense n x n
+// products and one sparse product S p; the recurrence costs two sparse products per
+// step.  AUTO takes the route when it has fewer products and its n x n buffers fit
+// in 16 GiB.
+int sparse_poly_choice(const cpa_opts* o, int n) {
+    if (o->K < 2 || o->K > kPolyMaxK || o->eval == CPA_EVAL_RECURRENCE) return 0;
+    const int s = poly_s_of(o->K), J = (o->K + s - 1) / s;
+    if (o->eval == CPA_EVAL_POLYNOMIAL) return s;
+    const double bytes = 4.0 * (s + 3) * (double)n * n;
+    if (bytes > 16.0 * (1 << 30)) return 0;
+    return (s - 1 + J - 1 + 2) < 2 * (o->K - 1) ? s : 0;
+}
+
 cpa_status shrink_csr_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t nnz, const int32_t* rowptr,
                            const int32_t* colidx, const float* val, float* Y, int64_t ldy,
                            const cpa_shrinkage* sh, const cpa_opts* o, const SpWork& w) {
@@ -818,6 +849,23 @@ cpa_status shrink_csr_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t n
         hipLaunchKernelGGL(csc_values_kernel, dim3((int)std::min<int64_t>(4096, (nnz + 255) / 256)), dim3(256), 0, st,
                            nnz, csrc, val, w.cval);
         HIP_TRY(hipGetLastError());
+    }
+    if (w.poly_s > 0) {
+        // matrix-polynomial route: Gram S^T S (one sparse product with the densified S),
+        // the polynomial on the n x n side, then Y = S p
+        hipLaunchKernelGGL(spmm_t_kernel, dim3(((n + SP_WAVES - 1) / SP_WAVES) * ((n + SPT_J - 1) / SPT_J)),
+                           dim3(SP_THREADS), 0, st, n, n, colptr, crow, (const float*)w.cval, (const float*)w.Y[0],
+                           w.ld, w.W, w.ld);
+        HIP_TRY(hipGetLastError());
+        float* F = nullptr;
+        cpa_status r = enqueue_poly_core(ctx, st, n, w.W, w.ld, w.scal, w.lay.ps(), w.poly, w.poly_s, o->K,
+                                         CPA_PREC_FP32, &F);
+        if (r != CPA_OK) return r;
+        hipLaunchKernelGGL(spmm_out_kernel, dim3(((m + SP_WAVES - 1) / SP_WAVES) * ((n + SPC_J - 1) / SPC_J)),
+                           dim3(SP_THREADS), 0, st, m, n, rowptr, colidx, val, (const float*)F, (int64_t)n, Y, ldy,
+                           aligned16(F, n) ? 1 : 0, aligned16(Y, ldy) ? 1 : 0);
+        HIP_TRY(hipGetLastError());
+        return CPA_OK;
     }
     const int grid_t = ((n + SP_WAVES - 1) / SP_WAVES) * ((n + SPT_J - 1) / SPT_J);
     const int grid_c = ((m + SP_WAVES - 1) / SP_WAVES) * ((n + SPC_J - 1) / SPC_J);
@@ -1335,7 +1383,8 @@ cpa_status cpa_shrink_csr(cpa_ctx* ctx, void* stream, int m, int n, int64_t nnz,
     hipStream_t st = static_cast<hipStream_t>(stream);
     SpWork w;
     const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
-    if ((s = ensure_sparse_ws(ctx, m, n, nnz, opts->K, maxit, false, w)) != CPA_OK) return s;
+    if ((s = ensure_sparse_ws(ctx, m, n, nnz, opts->K, maxit, false, w, sparse_poly_choice(opts, n))) != CPA_OK)
+        return s;
     if ((s = ensure_csc(ctx, st, m, n, nnz, rowptr_dev, colidx_dev)) != CPA_OK) return s;
     if ((s = shrink_csr_impl(ctx, st, m, n, nnz, rowptr_dev, colidx_dev, val_dev, Y_dev, ldy, shrink, opts, w)) != CPA_OK)
         return s;
@@ -1369,7 +1418,9 @@ cpa_status cpa_svt_complete(cpa_ctx* ctx, void* stream, int m, int n, int64_t nn
     hipStream_t st = static_cast<hipStream_t>(stream);
     SpWork w;
     const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
-    if ((s = ensure_sparse_ws(ctx, m, n, nnz, opts->K, std::max(maxit, 200), true, w)) != CPA_OK) return s;
+    if ((s = ensure_sparse_ws(ctx, m, n, nnz, opts->K, std::max(maxit, 200), true, w, sparse_poly_choice(opts, n))) !=
+        CPA_OK)
+        return s;
     if ((s = ensure_csc(ctx, st, m, n, nnz, rowptr_dev, colidx_dev)) != CPA_OK) return s;
     // k0 = ceil(tau / (delta ||P_Omega M||_2)) from a converged power iteration (one sync)
     cpa_opts ob = *opts;

@@ -198,28 +198,11 @@ __global__ void __launch_bounds__(SP_THREADS) spmm_t_kernel(int n, int ncols, co
     }
 }
 
-// Z[r][j] = sum over row r of S of s_rc W[c][j], then the recurrence epilogue:
-//   first step: Ynew = a1 Z - Yk,  out = c0/2 Yk + c1 Ynew
-//   later:      Ynew = a2 Z - 2 Yk - Yprev,  out += c_{k+1} Ynew
-// Ynew goes to Ydst (may equal Yprev) unless this is the last step.
-// Lane = 32 * g + q: entry group g and float4 q of the 128-column panel.  Grid: ceil(m / 4) x ceil(ncols / 128), panels
-// outermost.  The workspace buffers (W, Y*) have row pitches % 32 == 0 and
-// aligned bases; `out_vec` says whether the caller's output allows 16-byte
-// accesses too.
-__global__ void __launch_bounds__(SP_THREADS) spmm_cheb_kernel(int m, int ncols, const int32_t* rowptr,
-                                                               const int32_t* colidx, const float* val,
-                                                               const float* W, int64_t ldw, const float* Yk,
-                                                               const float* Yprev, float* Ydst, int64_t ldy,
-                                                               float* out, int64_t ldo, const double* scal,
-                                                               int step, int last, int out_vec) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int groups = (m + SP_WAVES - 1) / SP_WAVES;
-    const int panel = blockIdx.x / groups;
-    const int r = (blockIdx.x - panel * groups) * SP_WAVES + wave;
-    if (r >= m) return;
-    const int g = lane >> 5;
-    const int j = panel * SPC_J + 4 * (lane & 31);
-    const bool full = j + 3 < ncols;
+// sum over row r of S of s_rc B[c][j..j+3] for entry group g (entries g, g + 2, ...
+// of every 64-entry chunk); the caller adds the two groups with one shuffle.
+__device__ inline f32x4 sp_row_gather(int r, int g, int j, bool full, int ncols, const int32_t* rowptr,
+                                      const int32_t* colidx, const float* val, const float* W, int64_t ldw) {
+    const int lane = threadIdx.x & 63;
     f32x4 z = {0.f, 0.f, 0.f, 0.f};
     const int32_t e0 = rowptr[r], e1 = rowptr[r + 1];
     // chunks of 64 entries: one coalesced load of (column, value) per lane, then
@@ -256,6 +239,32 @@ __global__ void __launch_bounds__(SP_THREADS) spmm_cheb_kernel(int m, int ncols,
             for (int u = 0; u < 8; ++u) z += sv[u] * w[u];
         }
     }
+    return z;
+}
+
+// Z[r][j] = sum over row r of S of s_rc W[c][j], then the recurrence epilogue:
+//   first step: Ynew = a1 Z - Yk,  out = c0/2 Yk + c1 Ynew
+//   later:      Ynew = a2 Z - 2 Yk - Yprev,  out += c_{k+1} Ynew
+// Ynew goes to Ydst (may equal Yprev) unless this is the last step.
+// Lane = 32 * g + q: entry group g and float4 q of the 128-column panel.  Grid: ceil(m / 4) x ceil(ncols / 128), panels
+// outermost.  The workspace buffers (W, Y*) have row pitches % 32 == 0 and
+// aligned bases; `out_vec` says whether the caller's output allows 16-byte
+// accesses too.
+__global__ void __launch_bounds__(SP_THREADS) spmm_cheb_kernel(int m, int ncols, const int32_t* rowptr,
+                                                               const int32_t* colidx, const float* val,
+                                                               const float* W, int64_t ldw, const float* Yk,
+                                                               const float* Yprev, float* Ydst, int64_t ldy,
+                                                               float* out, int64_t ldo, const double* scal,
+                                                               int step, int last, int out_vec) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int groups = (m + SP_WAVES - 1) / SP_WAVES;
+    const int panel = blockIdx.x / groups;
+    const int r = (blockIdx.x - panel * groups) * SP_WAVES + wave;
+    if (r >= m) return;
+    const int g = lane >> 5;
+    const int j = panel * SPC_J + 4 * (lane & 31);
+    const bool full = j + 3 < ncols;
+    f32x4 z = sp_row_gather(r, g, j, full, ncols, rowptr, colidx, val, W, ldw);
     z += sp_shfl_xor4(z, 32);
     if (g != 0 || j >= ncols) return;
     float a, b, cc;
@@ -308,6 +317,33 @@ __global__ void __launch_bounds__(SP_THREADS) spmm_cheb_kernel(int m, int ncols,
         } else {
             for (int q = 0; q < cnt; ++q) Ydst[oy + q] = yn[q];
         }
+    }
+}
+
+// Y[r][j] = sum over row r of S of s_rc F[c][j] (the matrix-polynomial route's
+// final product S p).  Same decomposition as spmm_cheb_kernel.
+__global__ void __launch_bounds__(SP_THREADS) spmm_out_kernel(int m, int ncols, const int32_t* rowptr,
+                                                              const int32_t* colidx, const float* val,
+                                                              const float* F, int64_t ldf, float* Y, int64_t ldy,
+                                                              int f_vec, int out_vec) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int groups = (m + SP_WAVES - 1) / SP_WAVES;
+    const int panel = blockIdx.x / groups;
+    const int r = (blockIdx.x - panel * groups) * SP_WAVES + wave;
+    if (r >= m) return;
+    const int g = lane >> 5;
+    const int j = panel * SPC_J + 4 * (lane & 31);
+    // 16-byte loads of F need ldf % 4 == 0 (f_vec); otherwise element loads
+    const bool full = f_vec && j + 3 < ncols;
+    f32x4 z = sp_row_gather(r, g, j, full, ncols, rowptr, colidx, val, F, ldf);
+    z += sp_shfl_xor4(z, 32);
+    if (g != 0 || j >= ncols) return;
+    float* yr = Y + (int64_t)r * ldy + j;
+    if (full && out_vec) {
+        __builtin_nontemporal_store(z, reinterpret_cast<f32x4*>(yr));
+    } else {
+        for (int q = 0; q < 4; ++q)
+            if (j + q < ncols) yr[q] = z[q];
     }
 }
 

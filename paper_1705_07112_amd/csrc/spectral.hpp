@@ -333,13 +333,13 @@ __global__ void ps_coeff_kernel(int K, int s, int J, double* scal, int out) {
     }
 }
 
-// T1 = (2 / Lambda) G - I, d x d, pitch d.
-__global__ void ps_shift_kernel(int d, const float* G, float* T1, const double* scal) {
+// T1 = (2 / Lambda) G - I, d x d (G with pitch ldg, T1 with pitch d).
+__global__ void ps_shift_kernel(int d, const float* G, int64_t ldg, float* T1, const double* scal) {
     const float a1 = (float)scal[SC_A1];
     const int64_t total = (int64_t)d * d;
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = p / d, j = p - i * d;
-        T1[p] = a1 * G[p] - (i == j ? 1.f : 0.f);
+        T1[p] = a1 * G[i * ldg + j] - (i == j ? 1.f : 0.f);
     }
 }
 

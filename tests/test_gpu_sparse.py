@@ -134,3 +134,22 @@ def test_svt_completion_matches_oracle():
     assert k0 == k0_o
     assert e < 1e-3
     assert np.max(np.abs(res.cpu().numpy() - np.array(res_o))) < 1e-3
+
+
+@pytest.mark.parametrize("ev", ["recurrence", "polynomial"])
+@pytest.mark.parametrize("m,n,frac,K", [(300, 120, 0.05, 25), (257, 131, 0.03, 9), (64, 63, 0.2, 64),
+                                        (500, 37, 0.02, 2), (129, 129, 0.1, 100)])
+def test_csr_both_evaluation_routes(ev, m, n, frac, K):
+    """The operator-form recurrence and the matrix-polynomial route (Gram S^T S,
+    polynomial on the n x n side, one product S p) against the same oracle; odd n
+    exercises the element-wise loads of p."""
+    import paper_1705_07112_amd as cpa
+    rowptr, cols, vals, S = _random_csr(m, n, frac, 4400 + m + n + K)
+    G = S.T @ S
+    lmax = float(np.linalg.eigvalsh(G)[-1])
+    Lam, tau = 1.01 * lmax, 0.3 * math.sqrt(lmax)
+    Y = _gpu_csr(m, n, rowptr, cols, vals, cpa.soft(tau), cpa.Opts(K=K, Lambda=Lam, eval=ev)).cpu().numpy()
+    ref = ocpa.cpa_shrink(S, Shrinkage(0, tau), Lam, K)
+    err = metrics.rel_fro(Y.astype(np.float64), ref, S)
+    print(f"csr {m}x{n} K={K} eval={ev} rel_fro={err:.3e}", flush=True)
+    assert err <= TOL32
