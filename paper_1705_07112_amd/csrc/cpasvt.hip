@@ -112,12 +112,16 @@ struct Work {
     float* x;      // ADMM shrink input
     double* admm;  // ADMM E_t partial sums (2 per pre-kernel workgroup)
     int* et_counter;  // next E_t slot
-    float* poly;      // matrix-polynomial route: T_1..T_s and three Clenshaw buffers (d x d each)
+    float* poly;      // matrix-polynomial route: T_1..T_s, R_0..R_{J-1}, three Clenshaw buffers (d x d each)
     int poly_s;       // s of that route (0: not allocated)
     ScalarLayout lay;
 };
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Matrices of d x d held by the matrix-polynomial route: T_1..T_s, R_0..R_{J-1},
+// three Clenshaw buffers.
+int poly_mats(int K, int s) { return s + (K + s - 1) / s + 3; }
 
 int gram_grid(int d) {
     return ((d + 63) / 64) * ((d + 63) / 64);
@@ -152,7 +156,7 @@ cpa_status ensure_ws(cpa_ctx* ctx, int m, int n, int K, int maxit, bool admm, Wo
     const size_t ow1 = off; off = align_up(off + sizeof(double) * (size_t)d);
     const size_t os = off; off = align_up(off + sizeof(double) * (size_t)w.lay.total());
     size_t opl = 0;
-    if (poly_s > 0) { opl = off; off = align_up(off + sizeof(float) * (size_t)(poly_s + 3) * d * d); }
+    if (poly_s > 0) { opl = off; off = align_up(off + sizeof(float) * (size_t)poly_mats(K, poly_s) * d * d); }
     size_t ox = 0, oa = 0;
     if (admm) {
         ox = off; off = align_up(off + sizeof(float) * (size_t)mn);
@@ -491,6 +495,8 @@ EpiLin lin_epi(float* D, int64_t ldd, const float* Mx, int64_t ldm, float alpha,
     EpiLin e;
     e.D = D;
     e.ldd = ldd;
+    e.C = D;
+    e.ldc = ldd;
     e.Mx = Mx;
     e.ldm = ldm;
     e.alpha = alpha;
@@ -502,15 +508,16 @@ EpiLin lin_epi(float* D, int64_t ldd, const float* Mx, int64_t ldm, float alpha,
 }
 
 // The polynomial p(Ghat) (d x d, pitch d) from the Gram G (pitch ldg) and the
-// coefficients in scal; `poly` holds s + 3 matrices of d x d.  Returns p's buffer.
+// coefficients in scal; `poly` holds poly_mats(K, s) matrices of d x d.  Returns p's buffer.
 cpa_status enqueue_poly_core(cpa_ctx* ctx, hipStream_t st, int d, const float* G, int64_t ldg, double* scal,
                              int roff, float* poly, int s, int K, int precision, float** F_out) {
     const int J = (K + s - 1) / s;
     const int64_t dd = (int64_t)d * d;
     float* T1 = poly;                         // T_q at T1 + (q - 1) dd, q = 1..s
-    float* Bf[3] = {poly + s * dd, poly + (s + 1) * dd, poly + (s + 2) * dd};
+    float* R = poly + (int64_t)s * dd;        // R_j at R + j dd
+    float* Bf[3] = {R + (int64_t)J * dd, R + (int64_t)(J + 1) * dd, R + (int64_t)(J + 2) * dd};
     const int ge = (int)std::min<int64_t>(4096, (dd + 255) / 256);
-    hipLaunchKernelGGL(ps_coeff_kernel, dim3(1), dim3(64), 0, st, K, s, J, scal, roff);
+    hipLaunchKernelGGL(ps_coeff_kernel, dim3(1), dim3(256), 0, st, K, s, J, scal, roff);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(ps_shift_kernel, dim3(ge), dim3(256), 0, st, d, G, ldg, T1, (const double*)scal);
     HIP_TRY(hipGetLastError());
@@ -518,41 +525,42 @@ cpa_status enqueue_poly_core(cpa_ctx* ctx, hipStream_t st, int d, const float* G
     auto Tq = [&](int q) { return T1 + (int64_t)(q - 1) * dd; };
     // baby steps: T_{i+1} = 2 T_i T_1 - T_{i-1}, T_0 = I (T_1 is the operand read transposed)
     for (int i = 1; i < s; ++i) {
-        const EpiLin e = lin_epi(Tq(i + 1), d, i > 1 ? Tq(i - 1) : nullptr, d, 2.f, 0.f, i > 1 ? -1.f : 0.f,
-                                 i > 1 ? 0.f : -1.f);
+        EpiLin e = lin_epi(Tq(i + 1), d, i > 1 ? Tq(i - 1) : nullptr, d, 2.f, 0.f, i > 1 ? -1.f : 0.f,
+                           i > 1 ? 0.f : -1.f);
         if ((r = poly_gemm(ctx, st, make_op(Tq(i), d, d), make_op(T1, d, d), d, d, d, e, precision, true)) != CPA_OK)
             return r;
     }
-    // giant steps (Clenshaw in y = T_s): b_{J-1} = R_{J-1}; b_j = R_j + 2 b_{j+1} y - b_{j+2};
-    // p = R_0 + b_1 y - b_2
+    // every R_j = sum_i r_{j,i} T_i in one pass
+    hipLaunchKernelGGL(ps_lincomb_kernel, dim3((int)std::min<int64_t>(4096, (dd / 4 + 255) / 256 + 1)), dim3(256), 0,
+                       st, d, s, J, (const float*)T1, (const double*)scal, roff, R);
+    HIP_TRY(hipGetLastError());
     if (J == 1) {
-        hipLaunchKernelGGL(ps_lincomb_kernel, dim3(ge), dim3(256), 0, st, d, s, (const float*)T1,
-                           (const double*)scal, roff, Bf[0]);
-        HIP_TRY(hipGetLastError());
-        *F_out = Bf[0];
+        *F_out = R;
         return CPA_OK;
     }
+    // giant steps (Clenshaw in y = T_s): b_{J-1} = R_{J-1}; b_j = R_j + 2 b_{j+1} y - b_{j+2};
+    // p = R_0 + b_1 y - b_2
     const float* y = Tq(s);
-    int cur = 0;          // buffer holding b_{j+1}
-    int prev = -1;        // buffer holding b_{j+2} (none yet)
-    hipLaunchKernelGGL(ps_lincomb_kernel, dim3(ge), dim3(256), 0, st, d, s, (const float*)T1, (const double*)scal,
-                       roff + (J - 1) * s, Bf[cur]);
-    HIP_TRY(hipGetLastError());
+    const float* cur = R + (int64_t)(J - 1) * dd;   // b_{j+1}
+    const float* prev = nullptr;                     // b_{j+2}
     for (int j = J - 2; j >= 0; --j) {
-        int dst = 0;
-        while (dst == cur || dst == prev) ++dst;
-        hipLaunchKernelGGL(ps_lincomb_kernel, dim3(ge), dim3(256), 0, st, d, s, (const float*)T1,
-                           (const double*)scal, roff + j * s, Bf[dst]);
-        HIP_TRY(hipGetLastError());
-        const float* b2 = prev >= 0 ? Bf[prev] : nullptr;
-        const EpiLin e = lin_epi(Bf[dst], d, b2, d, j > 0 ? 2.f : 1.f, 1.f, b2 ? -1.f : 0.f, 0.f);
+        float* dst = Bf[0];
+        for (int q = 0; q < 3; ++q)
+            if (Bf[q] != cur && Bf[q] != prev) {
+                dst = Bf[q];
+                break;
+            }
+        EpiLin e = lin_epi(dst, d, prev, d, j > 0 ? 2.f : 1.f, 1.f, prev ? -1.f : 0.f, 0.f);
+        e.C = R + (int64_t)j * dd;
+        e.ldc = d;
+        e.vec_ok = e.vec_ok && aligned16(e.C, d);
         // b_{j+1} y with y read transposed
-        if ((r = poly_gemm(ctx, st, make_op(Bf[cur], d, d), make_op(y, d, d), d, d, d, e, precision, true)) != CPA_OK)
+        if ((r = poly_gemm(ctx, st, make_op(cur, d, d), make_op(y, d, d), d, d, d, e, precision, true)) != CPA_OK)
             return r;
         prev = cur;
         cur = dst;
     }
-    *F_out = Bf[cur];
+    *F_out = const_cast<float*>(cur);
     return CPA_OK;
 }
 
@@ -641,7 +649,7 @@ struct SpWork {
     double* w[2];
     double* scal;
     float* yv;         // SVT iterate values (nnz), when requested
-    float* poly;       // matrix-polynomial route: s + 3 matrices of n x n (or nullptr)
+    float* poly;       // matrix-polynomial route: poly_mats(K, s) matrices of n x n (or nullptr)
     int poly_s;
     ScalarLayout lay;
 };
@@ -671,7 +679,7 @@ cpa_status ensure_sparse_ws(cpa_ctx* ctx, int m, int n, int64_t nnz, int K, int 
     size_t oy = 0;
     if (svt) { oy = off; off = align_up(off + sizeof(float) * (size_t)std::max<int64_t>(nnz, 1)); }
     size_t opl = 0;
-    if (poly_s > 0) { opl = off; off = align_up(off + sizeof(float) * (size_t)(poly_s + 3) * n * n); }
+    if (poly_s > 0) { opl = off; off = align_up(off + sizeof(float) * (size_t)poly_mats(K, poly_s) * n * n); }
     if (off > ctx->sws_bytes) {
         if (ctx->sws) {
             HIP_TRY(hipDeviceSynchronize());
@@ -789,7 +797,7 @@ int sparse_poly_choice(const cpa_opts* o, int n) {
     if (o->K < 2 || o->K > kPolyMaxK || o->eval == CPA_EVAL_RECURRENCE) return 0;
     const int s = poly_s_of(o->K), J = (o->K + s - 1) / s;
     if (o->eval == CPA_EVAL_POLYNOMIAL) return s;
-    const double bytes = 4.0 * (s + 3) * (double)n * n;
+    const double bytes = 4.0 * poly_mats(o->K, s) * (double)n * n;
     if (bytes > 16.0 * (1 << 30)) return 0;
     return (s - 1 + J - 1 + 2) < 2 * (o->K - 1) ? s : 0;
 }

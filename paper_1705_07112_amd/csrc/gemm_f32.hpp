@@ -389,12 +389,14 @@ struct EpiCheb {
     }
 };
 
-// D = alpha acc + beta D + gamma Mx + delta I (the matrix polynomial steps):
-// D row-major with pitch ldd (read when beta != 0), Mx with pitch ldm (read when
-// gamma != 0), I the identity (delta added where row == column).
+// D = alpha acc + beta C + gamma Mx + delta I (the matrix polynomial steps):
+// row-major D (pitch ldd), C (pitch ldc, read when beta != 0; may be D), Mx (pitch
+// ldm, read when gamma != 0), I the identity (delta added where row == column).
 struct EpiLin {
     float* D;
     int64_t ldd;
+    const float* C;
+    int64_t ldc;
     const float* Mx;
     int64_t ldm;
     float alpha, beta, gamma, delta;
@@ -412,12 +414,12 @@ struct EpiLin {
             full[q] = vec_ok && i < M && j + 3 < N;
             vd[q] = vm[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
             if (full[q]) {
-                if (beta != 0.f) vd[q] = *reinterpret_cast<const f32x4*>(D + (int64_t)i * ldd + j);
+                if (beta != 0.f) vd[q] = *reinterpret_cast<const f32x4*>(C + (int64_t)i * ldc + j);
                 if (gamma != 0.f) vm[q] = *reinterpret_cast<const f32x4*>(Mx + (int64_t)i * ldm + j);
             } else if (i < M) {
                 for (int e = 0; e < 4; ++e) {
                     if (j + e < N) {
-                        if (beta != 0.f) vd[q][e] = D[(int64_t)i * ldd + j + e];
+                        if (beta != 0.f) vd[q][e] = C[(int64_t)i * ldc + j + e];
                         if (gamma != 0.f) vm[q][e] = Mx[(int64_t)i * ldm + j + e];
                     }
                 }

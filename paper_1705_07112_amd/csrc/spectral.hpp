@@ -49,6 +49,8 @@ enum : int {
 
 constexpr int kNormSlots = 64;   // partial-sum slots per growth-check norm
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 constexpr int kPsMaxS = 16;   // largest baby-step count of the matrix-polynomial route
 
 struct ScalarLayout {
@@ -319,18 +321,24 @@ __global__ void scale_copy_kernel(int m, int n, const float* X, int64_t ldx, flo
 // the highest degree down, r_{j,i} = 2 w_{js+i} and w_{js-i} -= w_{js+i} (i >= 1),
 // r_{j,0} = w_{js}, r_{0,i} = w_i.  One thread, FP64; r is written row by row.
 __global__ void ps_coeff_kernel(int K, int s, int J, double* scal, int out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double* w = scal + out;   // the output area doubles as the working copy
-    for (int k = 0; k < J * s; ++k) w[k] = k < K ? scal[SC_COEF + k] * (k == 0 ? 0.5 : 1.0) : 0.0;
-    // in place: entry (j, i) of r lives at w[j s + i]
-    for (int j = J - 1; j >= 1; --j) {
-        for (int i = s - 1; i >= 1; --i) {
-            const int k = j * s + i;
-            const double v = w[k];
-            w[k] = 2.0 * v;
-            w[j * s - i] -= v;
+    __shared__ double w[kPsMaxS * kPsMaxS + kPsMaxS];
+    const int n = J * s;   // <= K + s - 1 <= 271
+    for (int k = threadIdx.x; k < n; k += blockDim.x)
+        w[k] = k < K ? scal[SC_COEF + k] * (k == 0 ? 0.5 : 1.0) : 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // in place: entry (j, i) of r lives at w[j s + i]
+        for (int j = J - 1; j >= 1; --j) {
+            for (int i = s - 1; i >= 1; --i) {
+                const int k = j * s + i;
+                const double v = w[k];
+                w[k] = 2.0 * v;
+                w[j * s - i] -= v;
+            }
         }
     }
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += blockDim.x) scal[out + k] = w[k];
 }
 
 // T1 = (2 / Lambda) G - I, d x d (G with pitch ldg, T1 with pitch d).
@@ -343,19 +351,51 @@ __global__ void ps_shift_kernel(int d, const float* G, int64_t ldg, float* T1, c
     }
 }
 
-// dst = r[0] I + sum_{q=1}^{s-1} r[q] T_q, with T_q at T1 + (q - 1) d^2 (pitch d).
-__global__ void ps_lincomb_kernel(int d, int s, const float* T1, const double* scal, int roff, float* dst) {
+// R_j = r_{j,0} I + sum_{q=1}^{s-1} r_{j,q} T_q for every j < J in one pass: each
+// element of T_1..T_{s-1} is read once (T_q at T1 + (q - 1) d^2, pitch d) and R_j
+// goes to R + j d^2.  Four consecutive elements per thread (16-byte accesses when
+// d % 4 == 0).
+__global__ void ps_lincomb_kernel(int d, int s, int J, const float* T1, const double* scal, int roff, float* R) {
+    __shared__ float rc[kPsMaxS * kPsMaxS];
+    for (int k = threadIdx.x; k < J * s; k += blockDim.x) rc[k] = (float)scal[roff + k];
+    __syncthreads();
     const int64_t dd = (int64_t)d * d;
-    float r[kPsMaxS];
+    const bool vec = (d & 3) == 0;
+    const int64_t nq = (dd + 3) / 4;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < nq; g += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p0 = 4 * g;
+        f32x4 t[kPsMaxS];
 #pragma unroll
-    for (int q = 0; q < kPsMaxS; ++q) r[q] = q < s ? (float)scal[roff + q] : 0.f;
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < dd; p += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = p / d, j = p - i * d;
-        float v = i == j ? r[0] : 0.f;
+        for (int q = 1; q < kPsMaxS; ++q) {
+            t[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            if (q < s) {
+                const float* src = T1 + (int64_t)(q - 1) * dd + p0;
+                if (vec) {
+                    t[q] = *reinterpret_cast<const f32x4*>(src);
+                } else {
+                    for (int e = 0; e < 4; ++e)
+                        if (p0 + e < dd) t[q][e] = src[e];
+                }
+            }
+        }
+        for (int j = 0; j < J; ++j) {
+            f32x4 v;
 #pragma unroll
-        for (int q = 1; q < kPsMaxS; ++q)
-            if (q < s) v += r[q] * T1[(q - 1) * dd + p];
-        dst[p] = v;
+            for (int e = 0; e < 4; ++e) {
+                const int64_t p = p0 + e;
+                v[e] = (p / d == p % d) ? rc[j * s] : 0.f;
+            }
+#pragma unroll
+            for (int q = 1; q < kPsMaxS; ++q)
+                if (q < s) v += rc[j * s + q] * t[q];
+            float* dst = R + (int64_t)j * dd + p0;
+            if (vec) {
+                *reinterpret_cast<f32x4*>(dst) = v;
+            } else {
+                for (int e = 0; e < 4; ++e)
+                    if (p0 + e < dd) dst[e] = v[e];
+            }
+        }
     }
 }
 
