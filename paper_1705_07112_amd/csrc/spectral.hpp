@@ -163,11 +163,31 @@ __global__ void __launch_bounds__(kPowerThreads) power_coop_kernel(int d, const 
         double* wn = (t & 1) ? wb1 : wb0;         // w_t
         const double inv = 1.0 / sqrt(w2prev);
         double mu_part = 0.0, w2_part = 0.0;
+        const bool vec = ((ldg & 3) == 0) && ((reinterpret_cast<uintptr_t>(G) & 15) == 0);
         for (int i = gw; i < d; i += nw) {
             const float* row = G + (int64_t)i * ldg;
-            double acc = 0.0;
-            for (int j = lane; j < d; j += 64) acc += (double)row[j] * (wp[j] * inv);
+            // four independent partial sums, 16-byte loads of G when rows are aligned,
+            // several loads in flight per lane (the sum is scaled by 1/||w|| at the end)
+            double a[4] = {0.0, 0.0, 0.0, 0.0};
+            int j = 4 * lane;
+            if (vec) {
+#pragma unroll 4
+                for (; j + 3 < d; j += 256) {
+                    const f32x4 g = *reinterpret_cast<const f32x4*>(row + j);
+                    const double2 v01 = *reinterpret_cast<const double2*>(wp + j);
+                    const double2 v23 = *reinterpret_cast<const double2*>(wp + j + 2);
+                    a[0] += (double)g[0] * v01.x;
+                    a[1] += (double)g[1] * v01.y;
+                    a[2] += (double)g[2] * v23.x;
+                    a[3] += (double)g[3] * v23.y;
+                }
+            }
+            for (; j < d; j += 256)
+                for (int e = 0; e < 4; ++e)
+                    if (j + e < d) a[e] += (double)row[j + e] * wp[j + e];
+            double acc = (a[0] + a[1]) + (a[2] + a[3]);
             for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            acc *= inv;
             if (lane == 0) {
                 wn[i] = acc;
                 mu_part += (wp[i] * inv) * acc;
