@@ -175,7 +175,7 @@ def bench_sparse(cpa, torch, np, synth):
     product, the polynomial on the 4000 x 4000 side, one product S p).  Beside it:
     the operator-form recurrence (W = S^T Y_k, then S W with the fused update)."""
     m, n, K = 20000, 4000, 25
-    _, _, rowptr, cols, vals = synth.completion()
+    u_f, v_f, rowptr, cols, vals = synth.completion()
     dev = torch.device("cuda:0")
     r = torch.from_numpy(rowptr).to(dev)
     c = torch.from_numpy(cols).to(dev)
@@ -212,6 +212,27 @@ def bench_sparse(cpa, torch, np, synth):
     ms_p, us_p, l_p = res["auto"]
     ms_r, us_r, l_r = res["recurrence"]
     flop_gemm = 2.0 * n * n * n
+    # the whole completion: 100 SVT iterations (Cai, Candes, Shen: tau = 5 sqrt(m n),
+    # delta = 1.2 m n / |Omega|), each a K = 25 shrink on the default route
+    iters = 100
+    tau_svt = 5.0 * math.sqrt(m * n)
+    delta = 1.2 * m * n / nnz
+    resid = torch.zeros(iters, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t_svt = time.perf_counter()
+    e0.record()
+    X, k0 = cpa.svt_complete(m, n, r, c, v, tau_svt, delta, iters, cpa.Opts(K=K, warm_start=True), out=out,
+                             resid=resid)
+    e1.record()
+    torch.cuda.synchronize()
+    wall_svt = time.perf_counter() - t_svt
+    ms_svt = e0.elapsed_time(e1)
+    Mt = torch.from_numpy(u_f).to(dev) @ torch.from_numpy(v_f).to(dev).T
+    rel_m = float(torch.linalg.norm(X - Mt) / torch.linalg.norm(Mt))
+    del Mt
+    svt = {"iterations": iters, "K": K, "tau": round(tau_svt, 1), "delta": round(delta, 2), "k0": k0,
+           "ms_total": round(ms_svt, 1), "wall_s": round(wall_svt, 3), "iterations_per_s": round(iters / (ms_svt / 1e3), 2),
+           "final_observed_residual": float("%.3e" % float(resid[-1])), "rel_err_vs_ground_truth": float("%.3e" % rel_m)}
     return {
         "workload": "CSR 20000 x 4000, 1.6M nonzeros (2%), rank-10 N(0,1) values, soft, K=25",
         "route": "matrix polynomial: Gram S^T S (sparse), polynomial on 4000 x 4000 (FP32 MFMA), Y = S p (sparse)",
@@ -220,6 +241,7 @@ def bench_sparse(cpa, torch, np, synth):
                      "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(flop_gemm / (us_p * 1e-6) / 1e12 / MFMA_FP32_PEAK_TFLOPS, 4),
                      "avg_launch_us": round(us_p, 1), "launches": l_p, "traffic": None},
+        "svt_completion": svt,
         "operator_form": {"ms_per_shrink": round(ms_r, 3), "shrinks_per_s": round(1e3 / ms_r, 2),
                           "spmm_pair_avg_us": round(us_r, 1),
                           "roofline": {"bound": "hbm", "achieved": round(step_bytes / (us_r * 1e-6) / 1e9, 1),
