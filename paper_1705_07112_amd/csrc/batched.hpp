@@ -74,17 +74,34 @@ struct BatchArgs {
     int* queue;                // next matrix index (zeroed before launch)
 };
 
-__device__ inline double bt_wave_sum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 // Value of v held by lane l (l uniform across the wave).
 __device__ inline double bt_readlane(double v, int l) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane((int)b, l);
     const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// v of the lane selected by the DPP pattern CTRL (within rows of 16 lanes).
+template <int CTRL>
+__device__ inline double bt_dpp(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes, equal in every lane.  Within each row of 16 lanes:
+// swap neighbours, swap pairs, mirror halves of 8, mirror the row -- each step
+// adds the same two values in either order, so all lanes of a row end with the
+// same bits; the four row sums are then read from lanes 0, 16, 32, 48 and added
+// in a fixed order.  VALU data movement only (no LDS round trips).
+__device__ inline double bt_wave_sum(double v) {
+    v += bt_dpp<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += bt_dpp<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += bt_dpp<0x141>(v);   // row_half_mirror
+    v += bt_dpp<0x140>(v);   // row_mirror
+    return (bt_readlane(v, 0) + bt_readlane(v, 16)) + (bt_readlane(v, 32) + bt_readlane(v, 48));
 }
 
 __device__ inline double bt_block_sum(double v, double* red) {
@@ -101,6 +118,7 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
     __shared__ __attribute__((aligned(16))) float YT[BT_EMAX * BT_DP];
     __shared__ __attribute__((aligned(16))) float Gs[BT_DMAX * BT_DP];
     __shared__ double vv[BT_DMAX], coef[64], red[4];   // vv: scratch of the predictor network
+    __shared__ double pw[2 * BT_THREADS];                 // power iteration: partial rows, by parity
     __shared__ int s_idx;
     __shared__ double s_scal[4];
 
@@ -209,62 +227,59 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
                 Lam = (1.0 + a.margin) * fro;
             } else if (mode == 0) {
                 // power iteration on G (d x d), FP64, start vector as in the dense path.
-                // One wave: lane i owns row i (G is symmetric, so it reads column i,
-                // which is free of bank conflicts), v_j is broadcast with readlane and
-                // the sums are in-wave shuffles: no workgroup barrier per iteration.
-                if (wave == 0) {
-                    double v = 0.0;
-                    if (lane < d) {
-                        const uint64_t z = a.seed + (uint64_t)(lane + 1) * 0x9E3779B97F4A7C15ull;
-                        uint64_t o = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-                        o = (o ^ (o >> 27)) * 0x94D049BB133111EBull;
-                        o ^= o >> 31;
-                        v = 2.0 * ((double)(o >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
-                    }
-                    double nv = bt_wave_sum(v * v);
-                    double mu = 0.0, w2 = 0.0, muprev = 0.0;
-                    bool vanish = !(nv > 0.0);
-                    for (int t = 1; !vanish && t <= a.power_iters; ++t) {
-                        const double vs = v * (1.0 / sqrt(nv));
-                        // four independent partial sums (j mod 4) shorten the FMA chain
-                        double w4[4] = {0.0, 0.0, 0.0, 0.0};
-                        int j = 0;
-                        for (; j + 4 <= d; j += 4) {
-#pragma unroll
-                            for (int q = 0; q < 4; ++q)
-                                w4[q] += (double)Gs[(j + q) * BT_DP + lane] * bt_readlane(vs, j + q);
-                        }
-                        for (; j < d; ++j) w4[j & 3] += (double)Gs[j * BT_DP + lane] * bt_readlane(vs, j);
-                        const double wi = (w4[0] + w4[1]) + (w4[2] + w4[3]);
-                        mu = bt_wave_sum(vs * wi);
-                        w2 = bt_wave_sum(wi * wi);
-                        // the sums are bitwise equal in every lane (xor butterfly), so
-                        // the exit is taken by the whole wave; readfirstlane states
-                        // that to the compiler, which then branches on a scalar
-                        int stop = !(w2 > 0.0) ? 2 : ((t >= 2 && fabs(mu - muprev) <= a.tol * mu) ? 1 : 0);
-                        stop = __builtin_amdgcn_readfirstlane(stop);
-                        if (stop == 2) {
-                            vanish = true;
-                            break;
-                        }
-                        if (stop == 1) break;
-                        muprev = mu;
-                        v = wi;
-                        nv = w2;
-                    }
-                    double L;
-                    if (vanish) {
-                        L = (1.0 + a.margin) * fro;
-                    } else {
-                        const double r2 = w2 - mu * mu;
-                        const double r = sqrt(r2 > 0.0 ? r2 : 0.0);
-                        L = mu + (a.margin * mu > r ? a.margin * mu : r);
-                        if (L > (1.0 + a.margin) * fro) L = (1.0 + a.margin) * fro;
-                    }
-                    if (lane == 0) s_scal[3] = L;
+                // Lane i owns row i (G is symmetric, so it reads column i, which is
+                // free of bank conflicts); wave w adds the columns j in [16 w, 16 w + 16)
+                // with v_j broadcast by readlane, the four partial rows meet in LDS
+                // (one barrier per product, buffers alternating by parity), and every
+                // wave then forms the same w, mu, ||w||^2 and stop decision: the
+                // values are bitwise equal across lanes and waves (same operations on
+                // the same data), and the stop flag goes through readfirstlane so the
+                // loop exit is a scalar branch.
+                double v = 0.0;
+                if (lane < d) {
+                    const uint64_t z = a.seed + (uint64_t)(lane + 1) * 0x9E3779B97F4A7C15ull;
+                    uint64_t o = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+                    o = (o ^ (o >> 27)) * 0x94D049BB133111EBull;
+                    o ^= o >> 31;
+                    v = 2.0 * ((double)(o >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
                 }
-                __syncthreads();
-                Lam = s_scal[3];
+                double nv = bt_wave_sum(v * v);
+                double mu = 0.0, w2 = 0.0, muprev = 0.0;
+                bool vanish = !(nv > 0.0);
+                const int j0 = 16 * wave, j1 = d < j0 + 16 ? d : j0 + 16;
+                for (int t = 1; !vanish && t <= a.power_iters; ++t) {
+                    const double vs = v * (1.0 / sqrt(nv));
+                    double q[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) {
+                        const int j = j0 + u;
+                        if (j < j1) q[u & 3] += (double)Gs[j * BT_DP + lane] * bt_readlane(vs, j);
+                    }
+                    double* pb = pw + (t & 1) * BT_THREADS;
+                    pb[threadIdx.x] = (q[0] + q[1]) + (q[2] + q[3]);
+                    __syncthreads();
+                    const double wi = (pb[lane] + pb[64 + lane]) + (pb[128 + lane] + pb[192 + lane]);
+                    mu = bt_wave_sum(vs * wi);
+                    w2 = bt_wave_sum(wi * wi);
+                    int stop = !(w2 > 0.0) ? 2 : ((t >= 2 && fabs(mu - muprev) <= a.tol * mu) ? 1 : 0);
+                    stop = __builtin_amdgcn_readfirstlane(stop);
+                    if (stop == 2) {
+                        vanish = true;
+                        break;
+                    }
+                    if (stop == 1) break;
+                    muprev = mu;
+                    v = wi;
+                    nv = w2;
+                }
+                if (vanish) {
+                    Lam = (1.0 + a.margin) * fro;
+                } else {
+                    const double r2 = w2 - mu * mu;
+                    const double r = sqrt(r2 > 0.0 ? r2 : 0.0);
+                    Lam = mu + (a.margin * mu > r ? a.margin * mu : r);
+                    if (Lam > (1.0 + a.margin) * fro) Lam = (1.0 + a.margin) * fro;
+                }
             }
 
             // ---- coefficients (FP64, l ascending per k)
