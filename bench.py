@@ -28,14 +28,17 @@ INV_RHO = 10.0
 ETA_OVER_RHO = 10.0 / 32.0
 MFMA_FP32_PEAK_TFLOPS = 157.3
 METRIC = "shrunk matrices/sec & TFLOP/s at rel. Frobenius err ≤1e-3 vs FP64 SVT"
+SAMPLES = {}   # GPU results of the other legs kept for the oracle leg's FP64 CPA comparison
 
 
-def cpu_baseline(I, budget_s: float = 15.0, check=None):
+def cpu_baseline(I, budget_s: float = 15.0, check=None, samples=None):
     """The FP64 oracle's ADMM iterations on the host, for about budget_s seconds.
 
     check: optional (X, {name: Y_gpu}, Lambda) -- one shrink input, GPU results
     and the bound they used; the oracle's CPA of X at that bound (untimed) gives
-    each result's relative Frobenius error against FP64 Algorithm 1."""
+    each result's relative Frobenius error against FP64 Algorithm 1.
+    samples: optional {leg: [(X, Y_gpu, (kind, tau, w_c, w_sigma, w_eps), Lambda, K), ...]};
+    the largest such error over each leg's sample is reported as well."""
     import numpy as np
     from oracle import drivers
     try:
@@ -63,6 +66,18 @@ def cpu_baseline(I, budget_s: float = 15.0, check=None):
         Xc, outs, lam = check
         ref = ocpa.cpa_shrink(Xc, Shrinkage(0, INV_RHO), lam, K)
         res["err_vs_fp64_cpa"] = {k: float("%.3e" % metrics.rel_fro(v, ref, Xc)) for k, v in outs.items()}
+    if samples:
+        from oracle import cpa as ocpa
+        from oracle import metrics
+        from oracle.shrinkage import Shrinkage
+        worst = {}
+        for leg, items in samples.items():
+            e = 0.0
+            for Xs, Ys, sh, lam_s, K_s in items:
+                ref = ocpa.cpa_shrink(Xs, Shrinkage(*sh), lam_s, K_s)
+                e = max(e, metrics.rel_fro(Ys, ref, Xs))
+            worst[leg] = {"max": float("%.3e" % e), "matrices": len(items)}
+        res["err_vs_fp64_cpa_samples"] = worst
     return res
 
 
@@ -116,18 +131,24 @@ def bench_batched(cpa, torch, np, synth, timed_runs: int = 5):
     off = torch.from_numpy(offs).to(dev)
     lam = torch.zeros(len(ms), dtype=torch.float64, device=dev)
     opts = cpa.Opts(K=16)
-    Y = torch.empty_like(X)
-    for _ in range(2):
-        cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), opts, shrink_per_matrix=rec_t, out=Y, lambda_out=lam)
-    torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(timed_runs):
-        cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), opts, shrink_per_matrix=rec_t, out=Y, lambda_out=lam)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_batch = e0.elapsed_time(e1) / timed_runs
+
+    def timed(o, Yo):
+        for _ in range(2):
+            cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), o, shrink_per_matrix=rec_t, out=Yo, lambda_out=lam)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(timed_runs):
+            cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), o, shrink_per_matrix=rec_t, out=Yo, lambda_out=lam)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / timed_runs
+
+    Ysp = torch.empty_like(X)
+    ms_split = timed(cpa.Opts(K=16, precision="bf16x3"), Ysp)
+    Y = torch.empty_like(X)
+    ms_batch = timed(opts, Y)
     d = np.minimum(ms, ns).astype(np.float64)
     e = np.maximum(ms, ns).astype(np.float64)
     flop = float(np.sum(16 * 2.0 * d * d * e))
@@ -147,16 +168,22 @@ def bench_batched(cpa, torch, np, synth, timed_runs: int = 5):
     # accuracy on a sample against the exact weighted shrinkage (LAPACK SVD):
     # g(s) = s - w(s^2) when s > w(s^2), w(x) = w_c / (sqrt(max(x - w_sigma, 0)) + w_eps)
     Yh = Y.cpu().numpy()
-    e_svt = []
+    Ysh = Ysp.cpu().numpy()
+    e_svt, e_svt_split = [], []
     for i in range(0, 8192, 256):
         Xi = flat[offs[i]:offs[i] + ms[i] * ns[i]].reshape(ms[i], ns[i]).astype(np.float64)
         Yi = Yh[offs[i]:offs[i] + ms[i] * ns[i]].reshape(ms[i], ns[i]).astype(np.float64)
+        Ys = Ysh[offs[i]:offs[i] + ms[i] * ns[i]].reshape(ms[i], ns[i]).astype(np.float64)
         r = recs[i]
 
         def g(sv, r=r):
             w = r.w_c / (np.sqrt(np.maximum(sv * sv - r.w_sigma, 0.0)) + r.w_eps)
             return np.where(sv > w, sv - w, 0.0)
-        e_svt.append(rel_fro(Yi, exact_shrink(Xi, g), Xi))
+        ex = exact_shrink(Xi, g)
+        e_svt.append(rel_fro(Yi, ex, Xi))
+        e_svt_split.append(rel_fro(Ys, ex, Xi))
+        SAMPLES.setdefault("batched", []).append((Xi, Yi, (3, 0.0, r.w_c, r.w_sigma, r.w_eps),
+                                                  float(lam[i].item()), 16))
     return {
         "workload": "8192 patch groups 64 x U{40..120}, rank 4 + N(0,0.2^2), weighted soft, K=16, power bound",
         "value": round(8192 / (ms_batch / 1e3), 1), "unit": "matrices/s", "ms_per_batch": round(ms_batch, 4),
@@ -165,6 +192,10 @@ def bench_batched(cpa, torch, np, synth, timed_runs: int = 5):
                                            "sample": f"{nb} matrices, one cpa_shrink_dense call each"},
         "err_vs_fp64_svt_median": float("%.3e" % float(np.median(e_svt))),
         "err_vs_fp64_svt_max": float("%.3e" % max(e_svt)),
+        "bf16x3": {"value": round(8192 / (ms_split / 1e3), 1), "unit": "matrices/s",
+                   "ms_per_batch": round(ms_split, 4),
+                   "err_vs_fp64_svt_median": float("%.3e" % float(np.median(e_svt_split))),
+                   "err_vs_fp64_svt_max": float("%.3e" % max(e_svt_split))},
     }
 
 
@@ -270,7 +301,7 @@ def bench_predictor(cpa, torch, np, synth, n_train: int = 32768, n_eval: int = 8
         taus = noises * (np.sqrt(ms) + np.sqrt(ns))
         t = time.perf_counter()
         ex = P.exact_soft_batch(flat, ms, ns, offs, taus)
-        return {"ms": ms, "ns": ns, "offs": offs, "X": torch.from_numpy(flat).to(dev), "m": torch.from_numpy(ms).to(dev),
+        return {"ms": ms, "ns": ns, "offs": offs, "taus": taus, "X": torch.from_numpy(flat).to(dev), "m": torch.from_numpy(ms).to(dev),
                 "n": torch.from_numpy(ns).to(dev), "off": torch.from_numpy(offs).to(dev),
                 "recs": P.soft_records(torch, taus, dev), "Yex": torch.from_numpy(ex).to(dev),
                 "t_exact": time.perf_counter() - t}
@@ -330,6 +361,15 @@ def bench_predictor(cpa, torch, np, synth, n_train: int = 32768, n_eval: int = 8
         return e0.elapsed_time(e1) / reps
 
     ms_pred = timed(predicted)
+    Yh, lamh, kh = Y.cpu().numpy(), lam.cpu().numpy(), kout.cpu().numpy()
+    Xh = ev["X"].cpu().numpy()
+    for i in range(0, nb, 256):
+        o, sz = int(ev["offs"][i]), int(ev["ms"][i]) * int(ev["ns"][i])
+        shp = (int(ev["ms"][i]), int(ev["ns"][i]))
+        SAMPLES.setdefault("predicted", []).append((Xh[o:o + sz].reshape(shp).astype(np.float64),
+                                                    Yh[o:o + sz].reshape(shp).astype(np.float64),
+                                                    (0, float(ev["taus"][i]), 0.0, 0.0, 0.0), float(lamh[i]),
+                                                    int(kh[i])))
     err, ref2 = P.rel_errors(torch, Y, ev["Yex"], bounds)
     pass_pred = float((err <= gate).double().mean())
     k_mean = float(kout.double().mean())
@@ -492,6 +532,28 @@ def main():
     torch.cuda.synchronize()
     rec2_ms, rec2_n = cpa.timing_read("recurrence")
     cpa.timing_enable(False)
+    # the same workload with the three-term recurrence over X (the paper's evaluation order)
+    run3 = cpa.RpcaAdmm(Id, INV_RHO, ETA_OVER_RHO, cpa.Opts(K=K, warm_start=True, power_iters=100, eval="recurrence"))
+    run3.iterate(args.warmup)
+    torch.cuda.synchronize()
+    t0.record()
+    run3.iterate(args.steps)
+    t1.record()
+    torch.cuda.synchronize()
+    ms3 = t0.elapsed_time(t1)
+    cpa.timing_enable(True)
+    run3.iterate(args.steps)
+    torch.cuda.synchronize()
+    rec3_ms, rec3_n = cpa.timing_read("recurrence")
+    cpa.timing_enable(False)
+    rec3_us = 1e3 * rec3_ms / max(rec3_n, 1)
+    out["recurrence_route"] = {
+        "value": round(args.steps / (ms3 / 1e3), 3), "ms_per_step": round(ms3 / args.steps, 4),
+        "note": "same ADMM workload, eval='recurrence': K-1 = 29 products Y_{k+1} = 2 Y_k Ghat - Y_{k-1} over X",
+        "roofline": {"bound": "mfma", "kernel": "recurrence GEMM 1024^3 (FP32 MFMA, fused Chebyshev epilogue)",
+                     "achieved": round(flop_gemm / (rec3_us * 1e-6) / 1e12, 3), "peak": MFMA_FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(flop_gemm / (rec3_us * 1e-6) / 1e12 / MFMA_FP32_PEAK_TFLOPS, 4),
+                     "avg_launch_us": round(rec3_us, 3), "launches": rec3_n}}
     out["bf16x3"] = {"value": round(args.steps / (ms2 / 1e3), 3), "ms_per_step": round(ms2 / args.steps, 4),
                      "recurrence_avg_us": round(1e3 * rec2_ms / max(rec2_n, 1), 3),
                      "note": "same ADMM workload; recurrence products as bf16 hi/lo x3 on the BF16 matrix cores"}
@@ -527,7 +589,7 @@ def main():
         progress("predictor leg done")
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(I, check=check)
+        out["cpu_baseline"] = cpu_baseline(I, check=check, samples=SAMPLES)
         progress("oracle leg done")
     print(json.dumps(out), flush=True)
 

@@ -244,7 +244,9 @@ cpa_status cpa_svt_complete(cpa_ctx* ctx, void* stream, int m, int n, int64_t nn
  *     *shrink_host to every matrix.
  *   opts: K <= 64; bound CPA_BOUND_POWER (per-matrix power iteration, as in the
  *     dense path), CPA_BOUND_GIVEN (Lambda_dev[j]), CPA_BOUND_FROBENIUS; precision
- *     CPA_PREC_FP32; warm_start is not used.  With check = 1 every matrix is
+ *     CPA_PREC_FP32, or CPA_PREC_BF16X3 (each recurrence product as three BF16
+ *     matrix-core products of hi/lo parts with FP32 accumulation, as in
+ *     cpa_shrink_dense; the Gram and the bound stay FP32); warm_start is not used.  With check = 1 every matrix is
  *     tested after its recurrence: ||Y_{K-1}||_F <= (1 + growth_tol) ||X_j||_F
  *     (inside [0, Lambda] every |T_k| <= 1; above it T_k grows with k, so the
  *     last term is the largest); a failing matrix is redone once with

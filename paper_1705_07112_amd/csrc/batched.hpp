@@ -18,6 +18,13 @@
 // Workgroups take matrix indices from an atomic counter until the batch is
 // exhausted (every wave reaches the exit).
 //
+// Split-precision variant (SPLIT = true): each recurrence product G Y_k runs as
+// G_hi Y_hi + G_hi Y_lo + G_lo Y_hi on the BF16 matrix cores (16x16x32, FP32
+// accumulation, hi = bf16(x), lo = bf16(x - hi) rounded to nearest even); the
+// rows of G this lane supplies are split once per matrix and kept in registers,
+// the Y_k fragments are split as they are read.  The Gram, the bound and the
+// coefficients stay FP32 / FP64.
+//
 // LDS: Y_k is kept transposed, YT[j][i] (j < e, i < d, k contiguous), so that
 // both MFMA operands (G rows and YT rows) are 16-byte reads along the
 // contraction index and a thread's own output positions are contiguous.  Y_{k-1}
@@ -28,6 +35,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gemm_bf16x3.hpp"
 #include "gemm_f32.hpp"
 #include "mlp.hpp"
 #include "shrink_fn.hpp"
@@ -74,6 +82,27 @@ struct BatchArgs {
     int* queue;                // next matrix index (zeroed before launch)
 };
 
+typedef unsigned short bt_u16x8 __attribute__((ext_vector_type(8)));
+
+// Eight consecutive floats -> bf16 hi and lo parts (round to nearest even).
+__device__ inline void bt_split8(const float* p, bf16x8& hi, bf16x8& lo) {
+    const f32x4 a = *reinterpret_cast<const f32x4*>(p);
+    const f32x4 b = *reinterpret_cast<const f32x4*>(p + 4);
+    bt_u16x8 h, l;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        unsigned short x, y;
+        split2(a[e], x, y);
+        h[e] = x;
+        l[e] = y;
+        split2(b[e], x, y);
+        h[e + 4] = x;
+        l[e + 4] = y;
+    }
+    hi = __builtin_bit_cast(bf16x8, h);
+    lo = __builtin_bit_cast(bf16x8, l);
+}
+
 // Value of v held by lane l (l uniform across the wave).
 __device__ inline double bt_readlane(double v, int l) {
     const long long b = __double_as_longlong(v);
@@ -114,6 +143,7 @@ __device__ inline double bt_block_sum(double v, double* red) {
 
 // Two workgroups per CU (the register budget is capped accordingly): one
 // matrix's barriers and power iteration overlap another's recurrence.
+template <bool SPLIT>
 __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
     __shared__ __attribute__((aligned(16))) float YT[BT_EMAX * BT_DP];
     __shared__ __attribute__((aligned(16))) float Gs[BT_DMAX * BT_DP];
@@ -301,6 +331,12 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
                 outv[jb] = c0h * y0;
             }
             float last2 = 0.f;   // ||Y_{K-1}||^2 over this thread's positions
+            // split precision: rows ib + lane%16 of G, k = 16 g + 8 b + 0..7, split once per matrix
+            bf16x8 gah[2], gal[2];
+            if (SPLIT) {
+#pragma unroll
+                for (int b = 0; b < 2; ++b) bt_split8(&Gs[(ib + (lane & 15)) * BT_DP + 16 * g + 8 * b], gah[b], gal[b]);
+            }
             for (int step = 0; step + 1 < Kj; ++step) {
                 const float aa = step == 0 ? a1 : a2;
                 const float bb = step == 0 ? -1.f : -2.f;
@@ -309,7 +345,7 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
                 const bool final_step = step + 2 == Kj;
                 // A fragments: G rows ib + lane%16, k = 16 g + kk
                 float fa[16];
-                {
+                if (!SPLIT) {
                     const float* row = &Gs[(ib + (lane & 15)) * BT_DP + 16 * g];
 #pragma unroll
                     for (int q = 0; q < 16; q += 4) {
@@ -326,13 +362,24 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
                     if (jb < nb) {
                         const float* row = &YT[(jb * 16 + (lane & 15)) * BT_DP + 16 * g];
                         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                        if (SPLIT) {
 #pragma unroll
-                        for (int q = 0; q < 16; q += 4) {
-                            const f32x4 b = *reinterpret_cast<const f32x4*>(row + q);
-                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q], b[0], acc, 0, 0, 0);
-                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + 1], b[1], acc, 0, 0, 0);
-                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + 2], b[2], acc, 0, 0, 0);
-                            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + 3], b[3], acc, 0, 0, 0);
+                            for (int b = 0; b < 2; ++b) {
+                                bf16x8 yh, yl;
+                                bt_split8(row + 8 * b, yh, yl);
+                                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gal[b], yh, acc, 0, 0, 0);
+                                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gah[b], yl, acc, 0, 0, 0);
+                                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gah[b], yh, acc, 0, 0, 0);
+                            }
+                        } else {
+#pragma unroll
+                            for (int q = 0; q < 16; q += 4) {
+                                const f32x4 b = *reinterpret_cast<const f32x4*>(row + q);
+                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q], b[0], acc, 0, 0, 0);
+                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + 1], b[1], acc, 0, 0, 0);
+                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + 2], b[2], acc, 0, 0, 0);
+                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + 3], b[3], acc, 0, 0, 0);
+                            }
                         }
                         const int j = jb * 16 + (lane & 15);
                         const f32x4 yk = *reinterpret_cast<const f32x4*>(&YT[j * BT_DP + ib + 4 * g]);

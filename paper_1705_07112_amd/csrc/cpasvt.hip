@@ -66,7 +66,7 @@ struct cpa_ctx {
     int warm_cap = 0;
     int warm_d = -1;           // length of the stored vector, -1 if none
     int coop_max = 0;          // co-resident power-iteration workgroups (0: not queried)
-    int batch_grid = 0;        // persistent workgroups of the batched kernel (0: not queried)
+    int batch_grid[2] = {0, 0};   // persistent workgroups of the batched kernel (FP32, split; 0: not queried)
     int* queue = nullptr;      // work-queue counter of the batched kernel
     void* mlp_ws = nullptr;    // predictor training: gradient partials | loss partials
     // sparse path: its own workspace and the cached transposed pattern
@@ -1096,14 +1096,18 @@ cpa_status batched_prepare(cpa_ctx* ctx, int batch, const int32_t* m_dev, const 
     return CPA_OK;
 }
 
-cpa_status batched_launch(cpa_ctx* ctx, void* stream, BatchArgs& a) {
+cpa_status batched_launch(cpa_ctx* ctx, void* stream, BatchArgs& a, bool split = false) {
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    if (ctx->batch_grid == 0) {
+    int& bg = ctx->batch_grid[split ? 1 : 0];
+    if (bg == 0) {
         int per_cu = 0, cus = 0;
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel, BT_THREADS, 0));
+        if (split)
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel<true>, BT_THREADS, 0));
+        else
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel<false>, BT_THREADS, 0));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
-        ctx->batch_grid = std::max(1, per_cu * cus);
+        bg = std::max(1, per_cu * cus);
     }
     if (!ctx->queue && hipMalloc(&ctx->queue, 256) != hipSuccess) {
         ctx->queue = nullptr;
@@ -1112,8 +1116,11 @@ cpa_status batched_launch(cpa_ctx* ctx, void* stream, BatchArgs& a) {
     a.queue = ctx->queue;
     hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, st, ctx->queue, 1, 0);
     HIP_TRY(hipGetLastError());
-    const int grid = std::min(a.batch, ctx->batch_grid);
-    hipLaunchKernelGGL(batched_kernel, dim3(grid), dim3(BT_THREADS), 0, st, a);
+    const int grid = std::min(a.batch, bg);
+    if (split)
+        hipLaunchKernelGGL(batched_kernel<true>, dim3(grid), dim3(BT_THREADS), 0, st, a);
+    else
+        hipLaunchKernelGGL(batched_kernel<false>, dim3(grid), dim3(BT_THREADS), 0, st, a);
     HIP_TRY(hipGetLastError());
     return CPA_OK;
 }
@@ -1123,7 +1130,7 @@ cpa_status batched_shrink_args(const cpa_opts* opts, const float* X_dev, float* 
     cpa_status s;
     if ((s = check_opts(opts)) != CPA_OK) return s;
     if (opts->K > 64) return fail(CPA_ERR_ARG, "batched shrinkage supports K <= 64");
-    if (opts->precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "batched shrinkage is FP32");
+
     if (opts->check && !(opts->growth_tol >= 0.0)) return fail(CPA_ERR_ARG, "growth_tol must be >= 0");
     if (a.batch > 0 && !Y_dev) return fail(CPA_ERR_ARG, "NULL array");
     if (a.batch > 0 && X_dev == Y_dev) return fail(CPA_ERR_ARG, "Y aliases X");
@@ -1158,7 +1165,7 @@ cpa_status cpa_shrink_batched(cpa_ctx* ctx, void* stream, int batch, const int32
     a.lambda_in = Lambda_dev;
     a.lambda_out = Lambda_out_dev;
     a.status = status_dev;
-    return batched_launch(ctx, stream, a);
+    return batched_launch(ctx, stream, a, opts->precision == CPA_PREC_BF16X3);
 }
 
 cpa_status cpa_batched_features(cpa_ctx* ctx, void* stream, int batch, const int32_t* m_dev, const int32_t* n_dev,
@@ -1197,7 +1204,7 @@ cpa_status cpa_shrink_batched_predicted(cpa_ctx* ctx, void* stream, int batch, c
     a.lambda_out = Lambda_out_dev;
     a.K_out = K_out_dev;
     a.status = status_dev;
-    return batched_launch(ctx, stream, a);
+    return batched_launch(ctx, stream, a, opts->precision == CPA_PREC_BF16X3);
 }
 
 namespace {

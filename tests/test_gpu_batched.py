@@ -16,6 +16,7 @@ from oracle.shrinkage import Shrinkage
 pytestmark = pytest.mark.gpu
 
 TOL32 = 1e-5
+TOL_SPLIT = 1e-3   # split-precision products (bf16 hi/lo, FP32 accumulation)
 
 
 def _pack(mats):
@@ -31,7 +32,7 @@ def _gram(X):
     return X.T @ X if X.shape[0] >= X.shape[1] else X @ X.T
 
 
-def _run(mats, shr, K, mode="given", lams=None, power_kw=None):
+def _run(mats, shr, K, mode="given", lams=None, power_kw=None, precision="fp32"):
     import torch
     import paper_1705_07112_amd as cpa
     flat, ms, ns, offs = _pack(mats)
@@ -44,7 +45,7 @@ def _run(mats, shr, K, mode="given", lams=None, power_kw=None):
     lam_in = torch.from_numpy(np.array(lams, dtype=np.float64)).to(dev) if lams is not None else None
     lam_out = torch.zeros(len(mats), dtype=torch.float64, device=dev)
     status = torch.full((len(mats),), -1, dtype=torch.int32, device=dev)
-    opts = cpa.Opts(K=K, bound=mode, **(power_kw or {}))
+    opts = cpa.Opts(K=K, bound=mode, precision=precision, **(power_kw or {}))
     if mode == "given":
         opts.Lambda = 0.0
     Y = cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), opts, shrink_per_matrix=recs, Lambda=lam_in,
@@ -91,6 +92,45 @@ def test_batched_matches_oracle_given_lambda(K):
         assert err <= TOL32, (X.shape, K, err)
     print(f"batched K={K}: worst rel_fro {worst:.3e} over {len(mats)} matrices", flush=True)
     assert np.allclose(lam_out, lams)
+
+
+@pytest.mark.parametrize("K", [1, 2, 16, 30])
+def test_batched_split_precision_matches_oracle(K):
+    """Split-precision recurrence (bf16 hi/lo products with FP32 accumulation) on
+    the same shapes and shrinkages, within the split-precision bar."""
+    mats, shr_c, shr_o, lams = _mats_and_params(SHAPES, 11500 + K)
+    outs, lam_out, status = _run(mats, shr_c, K, "given", lams, precision="bf16x3")
+    assert np.all(status == 0)
+    worst = 0.0
+    for X, Y, sh, lam in zip(mats, outs, shr_o, lams):
+        ref = ocpa.cpa_shrink(X, sh, lam, K)
+        err = metrics.rel_fro(Y, ref, X)
+        worst = max(worst, err)
+        assert err <= TOL_SPLIT, (X.shape, K, err)
+    print(f"batched split K={K}: worst rel_fro {worst:.3e} over {len(mats)} matrices", flush=True)
+    assert np.allclose(lam_out, lams)
+
+
+def test_batched_split_precision_power_bound_and_growth_check():
+    """Split precision with the in-kernel power bound and the growth check on
+    patch groups: the bound equals the FP32 path's (the Gram and the iteration
+    do not depend on the product precision) and the shrink is within the bar."""
+    flat, ms, ns, offs, ranks, noises = synth.patch_groups(batch=64, seed=12500)
+    mats = [flat[offs[i]:offs[i] + ms[i] * ns[i]].reshape(ms[i], ns[i]).astype(np.float64) for i in range(64)]
+    import paper_1705_07112_amd as cpa
+    shr_c = [cpa.soft(0.3 * math.sqrt(float(np.linalg.eigvalsh(_gram(X))[-1]))) for X in mats]
+    taus = [r.tau for r in shr_c]
+    kw = {"power_iters": 200, "power_tol": 1e-9, "check": 1}
+    o32, l32, s32 = _run(mats, shr_c, 16, "power", None, kw)
+    osp, lsp, ssp = _run(mats, shr_c, 16, "power", None, kw, precision="bf16x3")
+    assert np.all(ssp == 0) and np.all(s32 == 0)
+    assert np.array_equal(l32, lsp)
+    worst = 0.0
+    for X, Y, tau, lam in zip(mats, osp, taus, lsp):
+        ref = ocpa.cpa_shrink(X, Shrinkage(0, tau), lam, 16)
+        worst = max(worst, metrics.rel_fro(Y, ref, X))
+    print(f"patch groups split: shrink rel_fro {worst:.2e}", flush=True)
+    assert worst <= TOL_SPLIT
 
 
 def test_batched_patch_groups_and_power_bound():
