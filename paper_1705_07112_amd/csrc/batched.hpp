@@ -22,14 +22,17 @@
 // G_hi Y_hi + G_hi Y_lo + G_lo Y_hi on the BF16 matrix cores (16x16x32, FP32
 // accumulation, hi = bf16(x), lo = bf16(x - hi) rounded to nearest even); the
 // rows of G this lane supplies are split once per matrix and kept in registers,
-// the Y_k fragments are split as they are read.  The Gram, the bound and the
-// coefficients stay FP32 / FP64.
+// and every element of Y_k is split once, by the thread that produced it, into
+// bf16 hi / lo planes that replace the FP32 copy in LDS (row j: hi of the 64
+// contraction entries, then lo).  The Gram, the bound and the coefficients stay
+// FP32 / FP64, and the recurrence values themselves stay FP32 in registers.
 //
 // LDS: Y_k is kept transposed, YT[j][i] (j < e, i < d, k contiguous), so that
 // both MFMA operands (G rows and YT rows) are 16-byte reads along the
-// contraction index and a thread's own output positions are contiguous.  Y_{k-1}
-// and the accumulator live in the registers of the thread that owns the
-// positions (the MFMA output layout is the same at every step).
+// contraction index and a thread's own output positions are contiguous.  Y_k,
+// Y_{k-1} and the accumulator also live in the registers of the thread that owns
+// the positions (the MFMA output layout is the same at every step); the LDS
+// copy of Y_k is only the operand of the next product.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -103,6 +106,23 @@ __device__ inline void bt_split8(const float* p, bf16x8& hi, bf16x8& lo) {
     lo = __builtin_bit_cast(bf16x8, l);
 }
 
+// Split rows of the bf16 planes: row j holds hi of entries 0..63, then lo.
+constexpr int BT_BP = 2 * BT_DP;   // row pitch in bf16 elements (same bytes as an FP32 row)
+
+// Four consecutive entries (i0 .. i0 + 3 of row j) -> the hi and lo planes.
+__device__ inline void bt_store_split4(unsigned short* YB, int j, int i0, const f32x4& v) {
+    unsigned short h[4], l[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) split2(v[r], h[r], l[r]);
+    uint2 hh, ll;
+    hh.x = (unsigned)h[0] | ((unsigned)h[1] << 16);
+    hh.y = (unsigned)h[2] | ((unsigned)h[3] << 16);
+    ll.x = (unsigned)l[0] | ((unsigned)l[1] << 16);
+    ll.y = (unsigned)l[2] | ((unsigned)l[3] << 16);
+    *reinterpret_cast<uint2*>(YB + j * BT_BP + i0) = hh;
+    *reinterpret_cast<uint2*>(YB + j * BT_BP + BT_DMAX + i0) = ll;
+}
+
 // Value of v held by lane l (l uniform across the wave).
 __device__ inline double bt_readlane(double v, int l) {
     const long long b = __double_as_longlong(v);
@@ -133,12 +153,90 @@ __device__ inline double bt_wave_sum(double v) {
     return (bt_readlane(v, 0) + bt_readlane(v, 16)) + (bt_readlane(v, 32) + bt_readlane(v, 48));
 }
 
+// Two independent wave sums with their steps interleaved (same operations and
+// order as bt_wave_sum on each value).
+__device__ inline void bt_wave_sum2(double& a, double& b) {
+    a += bt_dpp<0xB1>(a);
+    b += bt_dpp<0xB1>(b);
+    a += bt_dpp<0x4E>(a);
+    b += bt_dpp<0x4E>(b);
+    a += bt_dpp<0x141>(a);
+    b += bt_dpp<0x141>(b);
+    a += bt_dpp<0x140>(a);
+    b += bt_dpp<0x140>(b);
+    a = (bt_readlane(a, 0) + bt_readlane(a, 16)) + (bt_readlane(a, 32) + bt_readlane(a, 48));
+    b = (bt_readlane(b, 0) + bt_readlane(b, 16)) + (bt_readlane(b, 32) + bt_readlane(b, 48));
+}
+
+// 1 / sqrt(x) for a positive FP64 x: the hardware estimate refined by two
+// Newton steps y <- y (3 - x y^2) / 2 (a few ulp) inside [2^-1000, 2^1000], the
+// correctly rounded quotient outside that range.  Only the length of the
+// normalised iterate depends on it, never its direction.
+__device__ inline double bt_rsqrt(double x) {
+    if (x > 0x1p-1000 && x < 0x1p1000) {
+        double y = __builtin_amdgcn_rsq(x);
+        const double hx = 0.5 * x;
+        y = y * (1.5 - hx * y * y);
+        y = y * (1.5 - hx * y * y);
+        return y;
+    }
+    return 1.0 / sqrt(x);
+}
+
 __device__ inline double bt_block_sum(double v, double* red) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
     return red[0] + red[1] + red[2] + red[3];
+}
+
+// Recurrence product of NBLK adjacent 16 x 16 output blocks (column blocks
+// jb0 .. jb0 + NBLK - 1 of this wave's row block): the blocks' MFMA chains are
+// independent and issued interleaved, so one block's LDS reads and MFMA latency
+// overlap the others' work.  Blocks past the matrix's last column read the zero
+// padding of YT and produce zeros.
+template <bool SPLIT, int NBLK>
+__device__ inline void bt_product(const float* YT, int jb0, int lane, const float (&fa)[16], const bf16x8 (&gah)[2],
+                                  const bf16x8 (&gal)[2], f32x4 (&acc)[NBLK]) {
+    const int g = lane >> 4;
+    const float* row[NBLK];
+#pragma unroll
+    for (int u = 0; u < NBLK; ++u) {
+        row[u] = &YT[((jb0 + u) * 16 + (lane & 15)) * BT_DP + 16 * g];
+        acc[u] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    }
+    if (SPLIT) {
+        const unsigned short* YB = reinterpret_cast<const unsigned short*>(YT);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            bf16x8 yh[NBLK], yl[NBLK];
+#pragma unroll
+            for (int u = 0; u < NBLK; ++u) {
+                const unsigned short* rb = YB + ((jb0 + u) * 16 + (lane & 15)) * BT_BP + 16 * g + 8 * b;
+                yh[u] = *reinterpret_cast<const bf16x8*>(rb);
+                yl[u] = *reinterpret_cast<const bf16x8*>(rb + BT_DMAX);
+            }
+#pragma unroll
+            for (int u = 0; u < NBLK; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gal[b], yh[u], acc[u], 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < NBLK; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gah[b], yl[u], acc[u], 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < NBLK; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gah[b], yh[u], acc[u], 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 16; q += 4) {
+            f32x4 bv[NBLK];
+#pragma unroll
+            for (int u = 0; u < NBLK; ++u) bv[u] = *reinterpret_cast<const f32x4*>(row[u] + q);
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int u = 0; u < NBLK; ++u)
+                    acc[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + r], bv[u][r], acc[u], 0, 0, 0);
+        }
+    }
 }
 
 // Two workgroups per CU (the register budget is capped accordingly): one
@@ -155,7 +253,7 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;   // = row block of this wave
     const int g = lane >> 4;
-    f32x4 yprev[BT_JB], outv[BT_JB];
+    f32x4 yprev[BT_JB], ycur[BT_JB], outv[BT_JB];
 
     for (;;) {
         if (threadIdx.x == 0) s_idx = atomicAdd(a.queue, 1);
@@ -199,21 +297,26 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
         const int ib = wave * 16;
         double fro2 = 0.0, tr = 0.0;
         {
+            // the four column blocks as independent chains; the contraction stops at e
+            // rounded up to 4 (YT rows past e are zero)
+            f32x4 acc[4];
+#pragma unroll
+            for (int jb = 0; jb < 4; ++jb) acc[jb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            const int kend = (e + 3) & ~3;
+            for (int k0 = 0; k0 < kend; k0 += 4) {
+                const float* yr = &YT[(k0 + g) * BT_DP + (lane & 15)];
+                const float av = yr[ib];
+#pragma unroll
+                for (int jb = 0; jb < 4; ++jb) acc[jb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, yr[jb * 16], acc[jb], 0, 0, 0);
+            }
 #pragma unroll
             for (int jb = 0; jb < 4; ++jb) {
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-                for (int k0 = 0; k0 < BT_EMAX; k0 += 4) {
-                    const int k = k0 + g;
-                    const float av = YT[k * BT_DP + ib + (lane & 15)];
-                    const float bv = YT[k * BT_DP + jb * 16 + (lane & 15)];
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, acc, 0, 0, 0);
-                }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int i = ib + 4 * g + r, j = jb * 16 + (lane & 15);
-                    Gs[i * BT_DP + j] = acc[r];
-                    fro2 += (double)acc[r] * acc[r];
-                    if (i == j) tr += (double)acc[r];
+                    Gs[i * BT_DP + j] = acc[jb][r];
+                    fro2 += (double)acc[jb][r] * acc[jb][r];
+                    if (i == j) tr += (double)acc[jb][r];
                 }
             }
         }
@@ -257,9 +360,12 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
                 Lam = (1.0 + a.margin) * fro;
             } else if (mode == 0) {
                 // power iteration on G (d x d), FP64, start vector as in the dense path.
-                // Lane i owns row i (G is symmetric, so it reads column i, which is
-                // free of bank conflicts); wave w adds the columns j in [16 w, 16 w + 16)
-                // with v_j broadcast by readlane, the four partial rows meet in LDS
+                // Lane i owns row i; wave w adds the columns j in [16 w, 16 w + 16)
+                // (four 16-byte reads of row i, conflict-free at pitch 68) with v_j
+                // broadcast by readlane.  Rows and columns of G past d and entries of v
+                // past d are zero, so every wave takes all 16 columns without a
+                // bound test (the zero terms leave the sums unchanged); the four
+                // partial rows meet in LDS
                 // (one barrier per product, buffers alternating by parity), and every
                 // wave then forms the same w, mu, ||w||^2 and stop decision: the
                 // values are bitwise equal across lanes and waves (same operations on
@@ -276,21 +382,22 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
                 double nv = bt_wave_sum(v * v);
                 double mu = 0.0, w2 = 0.0, muprev = 0.0;
                 bool vanish = !(nv > 0.0);
-                const int j0 = 16 * wave, j1 = d < j0 + 16 ? d : j0 + 16;
+                const int j0 = __builtin_amdgcn_readfirstlane(16 * wave);   // scalar lane base
+                f32x4 grow[4];   // G[lane][j0 .. j0 + 15], fixed for the whole iteration
+#pragma unroll
+                for (int t = 0; t < 4; ++t) grow[t] = *reinterpret_cast<const f32x4*>(&Gs[lane * BT_DP + j0 + 4 * t]);
                 for (int t = 1; !vanish && t <= a.power_iters; ++t) {
-                    const double vs = v * (1.0 / sqrt(nv));
+                    const double vs = v * bt_rsqrt(nv);
                     double q[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                    for (int u = 0; u < 16; ++u) {
-                        const int j = j0 + u;
-                        if (j < j1) q[u & 3] += (double)Gs[j * BT_DP + lane] * bt_readlane(vs, j);
-                    }
+                    for (int u = 0; u < 16; ++u) q[u & 3] += (double)grow[u >> 2][u & 3] * bt_readlane(vs, j0 + u);
                     double* pb = pw + (t & 1) * BT_THREADS;
                     pb[threadIdx.x] = (q[0] + q[1]) + (q[2] + q[3]);
                     __syncthreads();
                     const double wi = (pb[lane] + pb[64 + lane]) + (pb[128 + lane] + pb[192 + lane]);
-                    mu = bt_wave_sum(vs * wi);
-                    w2 = bt_wave_sum(wi * wi);
+                    mu = vs * wi;
+                    w2 = wi * wi;
+                    bt_wave_sum2(mu, w2);
                     int stop = !(w2 > 0.0) ? 2 : ((t >= 2 && fabs(mu - muprev) <= a.tol * mu) ? 1 : 0);
                     stop = __builtin_amdgcn_readfirstlane(stop);
                     if (stop == 2) {
@@ -327,8 +434,17 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
                 // own positions (i = ib + 4g + r, j = jb*16 + lane%16): YT[j][ib + 4g .. +3]
                 const int j = jb * 16 + (lane & 15);
                 const f32x4 y0 = *reinterpret_cast<const f32x4*>(&YT[j * BT_DP + ib + 4 * g]);
-                yprev[jb] = y0;
+                ycur[jb] = y0;
                 outv[jb] = c0h * y0;
+            }
+            if (SPLIT) {
+                // Y_0 into the bf16 planes (every FP32 entry has been read)
+                __syncthreads();
+#pragma unroll
+                for (int jb = 0; jb < BT_JB; ++jb)
+                    if (jb < nb)
+                        bt_store_split4(reinterpret_cast<unsigned short*>(YT), jb * 16 + (lane & 15), ib + 4 * g, ycur[jb]);
+                __syncthreads();
             }
             float last2 = 0.f;   // ||Y_{K-1}||^2 over this thread's positions
             // split precision: rows ib + lane%16 of G, k = 16 g + 8 b + 0..7, split once per matrix
@@ -356,52 +472,45 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
                         fa[q + 3] = t[3];
                     }
                 }
-                f32x4 ynew[BT_JB];
+                // three-term update of this thread's positions in block jb
+                auto update = [&](int jb, const f32x4& acc) {
+                    const f32x4 yk = ycur[jb];
+                    f32x4 yn;
 #pragma unroll
-                for (int jb = 0; jb < BT_JB; ++jb) {
-                    if (jb < nb) {
-                        const float* row = &YT[(jb * 16 + (lane & 15)) * BT_DP + 16 * g];
-                        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-                        if (SPLIT) {
+                    for (int r = 0; r < 4; ++r) {
+                        float y = aa * acc[r] + bb * yk[r];
+                        if (step > 0) y += cc * yprev[jb][r];
+                        yn[r] = y;
+                        outv[jb][r] += ck * y;
+                        if (final_step) last2 += y * y;
+                    }
+                    ycur[jb] = yn;
+                    yprev[jb] = yk;
+                };
+                // column blocks in pairs (two interleaved chains), a lone last block alone
 #pragma unroll
-                            for (int b = 0; b < 2; ++b) {
-                                bf16x8 yh, yl;
-                                bt_split8(row + 8 * b, yh, yl);
-                                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gal[b], yh, acc, 0, 0, 0);
-                                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gah[b], yl, acc, 0, 0, 0);
-                                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(gah[b], yh, acc, 0, 0, 0);
-                            }
-                        } else {
-#pragma unroll
-                            for (int q = 0; q < 16; q += 4) {
-                                const f32x4 b = *reinterpret_cast<const f32x4*>(row + q);
-                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q], b[0], acc, 0, 0, 0);
-                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + 1], b[1], acc, 0, 0, 0);
-                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + 2], b[2], acc, 0, 0, 0);
-                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[q + 3], b[3], acc, 0, 0, 0);
-                            }
-                        }
-                        const int j = jb * 16 + (lane & 15);
-                        const f32x4 yk = *reinterpret_cast<const f32x4*>(&YT[j * BT_DP + ib + 4 * g]);
-                        f32x4 yn;
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            float y = aa * acc[r] + bb * yk[r];
-                            if (step > 0) y += cc * yprev[jb][r];
-                            yn[r] = y;
-                            outv[jb][r] += ck * y;
-                            if (final_step) last2 += y * y;
-                        }
-                        ynew[jb] = yn;
-                        yprev[jb] = yk;
+                for (int jb = 0; jb < BT_JB; jb += 2) {
+                    if (jb + 1 < nb) {
+                        f32x4 acc[2];
+                        bt_product<SPLIT, 2>(YT, jb, lane, fa, gah, gal, acc);
+                        update(jb, acc[0]);
+                        update(jb + 1, acc[1]);
+                    } else if (jb < nb) {
+                        f32x4 acc[1];
+                        bt_product<SPLIT, 1>(YT, jb, lane, fa, gah, gal, acc);
+                        update(jb, acc[0]);
                     }
                 }
-                __syncthreads();   // every wave has read Y_k
+                if (final_step) break;   // Y_{K-1} is not an operand
+                __syncthreads();         // every wave has read Y_k
 #pragma unroll
                 for (int jb = 0; jb < BT_JB; ++jb) {
                     if (jb < nb) {
                         const int j = jb * 16 + (lane & 15);
-                        *reinterpret_cast<f32x4*>(&YT[j * BT_DP + ib + 4 * g]) = ynew[jb];
+                        if (SPLIT)
+                            bt_store_split4(reinterpret_cast<unsigned short*>(YT), j, ib + 4 * g, ycur[jb]);
+                        else
+                            *reinterpret_cast<f32x4*>(&YT[j * BT_DP + ib + 4 * g]) = ycur[jb];
                     }
                 }
                 __syncthreads();
