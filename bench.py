@@ -112,9 +112,12 @@ def rel_fro(A, B, scale):
     return float(np.linalg.norm(A - B)) / (d if d > 0 else 1.0)
 
 
-def bench_batched(cpa, torch, np, synth, timed_runs: int = 5):
+def bench_batched(cpa, torch, np, synth, timed_runs: int = 10):
     """Batched weighted soft shrinkage of 8192 patch-group matrices (64 x U{40..120},
-    rank 4 + N(0, 0.2^2)), K = 16, per-matrix power bound, one persistent launch."""
+    rank 4 + N(0, 0.2^2)), K = 16, per-matrix power bound: one persistent launch,
+    captured in a graph after the autotuner picked its configuration.  Main figure:
+    split-precision products (bf16 hi/lo x3, FP32 accumulation); beside it the
+    same plan with FP32 products."""
     import math
     flat, ms, ns, offs, _, _ = synth.patch_groups(batch=8192)
     dev = torch.device("cuda:0")
@@ -129,30 +132,33 @@ def bench_batched(cpa, torch, np, synth, timed_runs: int = 5):
     m = torch.from_numpy(ms).to(dev)
     n = torch.from_numpy(ns).to(dev)
     off = torch.from_numpy(offs).to(dev)
-    lam = torch.zeros(len(ms), dtype=torch.float64, device=dev)
-    opts = cpa.Opts(K=16)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
 
-    def timed(o, Yo):
-        for _ in range(2):
-            cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), o, shrink_per_matrix=rec_t, out=Yo, lambda_out=lam)
+    def run_plan(precision):
+        lam = torch.zeros(len(ms), dtype=torch.float64, device=dev)
+        plan = cpa.BatchedPlan(X, m, n, off, cpa.soft(0.0), cpa.Opts(K=16, precision=precision),
+                               shrink_per_matrix=rec_t, lambda_out=lam)
+        plan.run()
         torch.cuda.synchronize()
         e0.record()
         for _ in range(timed_runs):
-            cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), o, shrink_per_matrix=rec_t, out=Yo, lambda_out=lam)
+            plan.run()
         e1.record()
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / timed_runs
+        ms_b = e0.elapsed_time(e1) / timed_runs
+        tun = plan.tuning
+        Yh = plan.out.cpu().numpy()
+        plan.close()
+        return ms_b, tun, Yh, lam
 
-    Ysp = torch.empty_like(X)
-    ms_split = timed(cpa.Opts(K=16, precision="bf16x3"), Ysp)
-    Y = torch.empty_like(X)
-    ms_batch = timed(opts, Y)
+    ms_split, tun_split, Ysh, lam_sp = run_plan("bf16x3")
+    ms_32, tun_32, Yh, lam = run_plan("fp32")
     d = np.minimum(ms, ns).astype(np.float64)
     e = np.maximum(ms, ns).astype(np.float64)
     flop = float(np.sum(16 * 2.0 * d * d * e))
     # baseline: the same matrices through per-matrix dense calls (first 128, FP32, power bound)
+    opts = cpa.Opts(K=16)
     nb = 128
     Xs = [X[int(offs[i]):int(offs[i]) + int(ms[i] * ns[i])].view(int(ms[i]), int(ns[i])) for i in range(nb)]
     outs = [torch.empty_like(x) for x in Xs]
@@ -167,8 +173,6 @@ def bench_batched(cpa, torch, np, synth, timed_runs: int = 5):
     ms_single = e0.elapsed_time(e1) / nb
     # accuracy on a sample against the exact weighted shrinkage (LAPACK SVD):
     # g(s) = s - w(s^2) when s > w(s^2), w(x) = w_c / (sqrt(max(x - w_sigma, 0)) + w_eps)
-    Yh = Y.cpu().numpy()
-    Ysh = Ysp.cpu().numpy()
     e_svt, e_svt_split = [], []
     for i in range(0, 8192, 256):
         Xi = flat[offs[i]:offs[i] + ms[i] * ns[i]].reshape(ms[i], ns[i]).astype(np.float64)
@@ -182,20 +186,28 @@ def bench_batched(cpa, torch, np, synth, timed_runs: int = 5):
         ex = exact_shrink(Xi, g)
         e_svt.append(rel_fro(Yi, ex, Xi))
         e_svt_split.append(rel_fro(Ys, ex, Xi))
-        SAMPLES.setdefault("batched", []).append((Xi, Yi, (3, 0.0, r.w_c, r.w_sigma, r.w_eps),
-                                                  float(lam[i].item()), 16))
+        rec = (3, 0.0, r.w_c, r.w_sigma, r.w_eps)
+        SAMPLES.setdefault("batched_fp32", []).append((Xi, Yi, rec, float(lam[i].item()), 16))
+        SAMPLES.setdefault("batched_bf16x3", []).append((Xi, Ys, rec, float(lam_sp[i].item()), 16))
+
+    def tun_rec(t):
+        return {"grid": t["grid"], "pair": t["pair"], "order": t["order"], "candidates": t["candidates"],
+                "tuned_us": round(t["best_us"], 1), "untuned_us": round(t["default_us"], 1)}
     return {
         "workload": "8192 patch groups 64 x U{40..120}, rank 4 + N(0,0.2^2), weighted soft, K=16, power bound",
-        "value": round(8192 / (ms_batch / 1e3), 1), "unit": "matrices/s", "ms_per_batch": round(ms_batch, 4),
-        "tflops": round(flop / (ms_batch * 1e-3) / 1e12, 3),
+        "precision": "bf16x3 (split products, FP32 accumulation)",
+        "value": round(8192 / (ms_split / 1e3), 1), "unit": "matrices/s", "ms_per_batch": round(ms_split, 4),
+        "tflops": round(flop / (ms_split * 1e-3) / 1e12, 3),
+        "launch": "one persistent launch per batch, replayed from a captured graph",
+        "autotuner": tun_rec(tun_split),
+        "err_vs_fp64_svt_median": float("%.3e" % float(np.median(e_svt_split))),
+        "err_vs_fp64_svt_max": float("%.3e" % max(e_svt_split)),
+        "fp32": {"value": round(8192 / (ms_32 / 1e3), 1), "unit": "matrices/s", "ms_per_batch": round(ms_32, 4),
+                 "tflops": round(flop / (ms_32 * 1e-3) / 1e12, 3), "autotuner": tun_rec(tun_32),
+                 "err_vs_fp64_svt_median": float("%.3e" % float(np.median(e_svt))),
+                 "err_vs_fp64_svt_max": float("%.3e" % max(e_svt))},
         "baseline_per_matrix_dense_fp32": {"value": round(1e3 / ms_single, 1), "unit": "matrices/s",
                                            "sample": f"{nb} matrices, one cpa_shrink_dense call each"},
-        "err_vs_fp64_svt_median": float("%.3e" % float(np.median(e_svt))),
-        "err_vs_fp64_svt_max": float("%.3e" % max(e_svt)),
-        "bf16x3": {"value": round(8192 / (ms_split / 1e3), 1), "unit": "matrices/s",
-                   "ms_per_batch": round(ms_split, 4),
-                   "err_vs_fp64_svt_median": float("%.3e" % float(np.median(e_svt_split))),
-                   "err_vs_fp64_svt_max": float("%.3e" % max(e_svt_split))},
     }
 
 

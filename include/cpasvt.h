@@ -261,6 +261,46 @@ cpa_status cpa_shrink_batched(cpa_ctx* ctx, void* stream, int batch, const int32
                               const cpa_opts* opts, const double* Lambda_dev, double* Lambda_out_dev,
                               int32_t* status_dev);
 
+/* ---- Batched plans: the batched shrink as one captured graph, tuned once.
+ * Not in the paper (it shrinks one matrix at a time); the per-matrix
+ * computation is exactly that of cpa_shrink_batched.
+ *
+ * cpa_batched_plan_create binds every argument of cpa_shrink_batched (same
+ * meaning, layout and limits; the arrays must stay allocated, and m_dev, n_dev,
+ * off_dev unchanged, for the plan's lifetime), picks a launch configuration and
+ * captures the launch (queue reset + kernel) in a HIP graph.  With tune = 1 it
+ * runs the batch under every configuration of the search space (persistent
+ * workgroups per CU: 1 or the occupancy limit; recurrence output blocks per MFMA
+ * group: 1 or 2; queue order: by index, or largest d^2 e first), four times
+ * each, on `stream`, writing Y_dev and the optional outputs, and keeps the
+ * fastest; with tune = 0 it takes the configuration cpa_shrink_batched uses.
+ * Every configuration yields the same bits.  Creation synchronises `stream`
+ * (the shapes are read to build the largest-first order).
+ * cpa_batched_plan_execute replays the graph on `stream` (asynchronous; reads
+ * the current contents of X_dev, Lambda_dev and shrink_dev).  Replays of one
+ * plan must not overlap (they share its queue counter).
+ * cpa_batched_plan_tuning reports the choice; cpa_batched_plan_destroy
+ * synchronises the device and frees the plan (NULL is accepted). */
+typedef struct cpa_batched_plan cpa_batched_plan;
+
+typedef struct {
+    int32_t grid;         /* workgroups launched */
+    int32_t pair;         /* recurrence output blocks per MFMA group */
+    int32_t order;        /* 0: queue by index, 1: largest first */
+    int32_t candidates;   /* configurations timed (0: not tuned) */
+    double best_us;       /* mean launch time of the chosen configuration (0 if not tuned) */
+    double default_us;    /* mean launch time of cpa_shrink_batched's configuration (0 if not tuned) */
+} cpa_batched_tuning;
+
+cpa_status cpa_batched_plan_create(cpa_ctx* ctx, void* stream, int batch, const int32_t* m_dev, const int32_t* n_dev,
+                                   const int64_t* off_dev, const float* X_dev, float* Y_dev,
+                                   const cpa_shrinkage* shrink_dev, const cpa_shrinkage* shrink_host,
+                                   const cpa_opts* opts, const double* Lambda_dev, double* Lambda_out_dev,
+                                   int32_t* status_dev, int32_t tune, cpa_batched_plan** plan_out);
+cpa_status cpa_batched_plan_execute(cpa_batched_plan* plan, void* stream);
+cpa_status cpa_batched_plan_tuning(const cpa_batched_plan* plan, cpa_batched_tuning* out);
+cpa_status cpa_batched_plan_destroy(cpa_batched_plan* plan);
+
 /* ---- Learned bound and order predictor (not in the paper).  It stands in for
  * the maximum-eigenvalue step of Algorithm 1 and chooses the order alpha per
  * matrix, for the batched path.

@@ -59,6 +59,11 @@ class CpaError(RuntimeError):
         self.status = status
 
 
+class CpaBatchedTuning(ctypes.Structure):
+    _fields_ = [("grid", ctypes.c_int32), ("pair", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("best_us", ctypes.c_double), ("default_us", ctypes.c_double)]
+
+
 _lib = None
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -88,6 +93,12 @@ _SIGS = {
     "cpa_shrink_batched": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.POINTER(CpaShrinkage),
                                           ctypes.POINTER(CpaOpts), _P, _P, _P]),
     "cpa_batched_features": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P]),
+    "cpa_batched_plan_create": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P,
+                                               ctypes.POINTER(CpaShrinkage), ctypes.POINTER(CpaOpts), _P, _P, _P,
+                                               ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "cpa_batched_plan_execute": (ctypes.c_int, [_P, _P]),
+    "cpa_batched_plan_tuning": (ctypes.c_int, [_P, ctypes.POINTER(CpaBatchedTuning)]),
+    "cpa_batched_plan_destroy": (ctypes.c_int, [_P]),
     "cpa_shrink_batched_predicted": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P,
                                                     ctypes.POINTER(CpaShrinkage), ctypes.POINTER(CpaOpts), _P,
                                                     ctypes.c_int32, _P, _P, _P]),
@@ -272,6 +283,56 @@ def shrink_batched(X, m, n, off, shrink, opts: Opts, shrink_per_matrix=None, Lam
                                     ctypes.byref(shrink), ctypes.byref(co), _ptr(Lambda), _ptr(lambda_out),
                                     _ptr(status)))
     return out
+
+
+class BatchedPlan:
+    """A packed batch bound to one captured, tuned launch (see cpa_batched_plan_create).
+
+    Takes the arguments of shrink_batched and keeps references to every tensor;
+    `run()` replays the graph on the current stream and returns `out`.  The
+    shapes (m, n, off) must not change; X, Lambda and the per-matrix records may."""
+
+    def __init__(self, X, m, n, off, shrink, opts: Opts, shrink_per_matrix=None, Lambda=None, out=None,
+                 lambda_out=None, status=None, tune: bool = True):
+        import torch
+        if out is None:
+            out = torch.empty_like(X)
+        self._keep = (X, m, n, off, shrink_per_matrix, Lambda, out, lambda_out, status)
+        self._shrink = shrink
+        self._co = opts.to_c()
+        self.out = out
+        self.device = X.device
+        h = ctypes.c_void_p()
+        _check(lib().cpa_batched_plan_create(ctypes.c_void_p(context(X.device.index or 0)), _stream(X),
+                                             int(m.numel()), _ptr(m), _ptr(n), _ptr(off), _ptr(X), _ptr(out),
+                                             _ptr(shrink_per_matrix), ctypes.byref(self._shrink),
+                                             ctypes.byref(self._co), _ptr(Lambda), _ptr(lambda_out), _ptr(status),
+                                             1 if tune else 0, ctypes.byref(h)))
+        self._h = h.value
+
+    def run(self):
+        if self._h is None:
+            raise RuntimeError("plan is closed")
+        _check(lib().cpa_batched_plan_execute(ctypes.c_void_p(self._h), _stream(self.out)))
+        return self.out
+
+    @property
+    def tuning(self) -> dict:
+        t = CpaBatchedTuning()
+        _check(lib().cpa_batched_plan_tuning(ctypes.c_void_p(self._h), ctypes.byref(t)))
+        return {"grid": t.grid, "pair": t.pair, "order": ("index", "largest_first")[t.order],
+                "candidates": t.candidates, "best_us": t.best_us, "default_us": t.default_us}
+
+    def close(self):
+        if self._h is not None:
+            _check(lib().cpa_batched_plan_destroy(ctypes.c_void_p(self._h)))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 PRED_PARAMS = 4546

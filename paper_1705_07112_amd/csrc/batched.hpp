@@ -82,7 +82,8 @@ struct BatchArgs {
     int power_iters;
     double tol, margin;
     uint64_t seed;
-    int* queue;                // next matrix index (zeroed before launch)
+    int* queue;                // next queue position (zeroed before launch)
+    const int32_t* order;      // nullable: matrix index of every queue position
 };
 
 typedef unsigned short bt_u16x8 __attribute__((ext_vector_type(8)));
@@ -241,7 +242,10 @@ __device__ inline void bt_product(const float* YT, int jb0, int lane, const floa
 
 // Two workgroups per CU (the register budget is capped accordingly): one
 // matrix's barriers and power iteration overlap another's recurrence.
-template <bool SPLIT>
+// PAIR: recurrence output blocks per MFMA group (1 or 2; a tuning choice, the
+// results are the same bits either way: every block's products and adds run
+// in the same order).
+template <bool SPLIT, int PAIR>
 __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
     __shared__ __attribute__((aligned(16))) float YT[BT_EMAX * BT_DP];
     __shared__ __attribute__((aligned(16))) float Gs[BT_DMAX * BT_DP];
@@ -258,9 +262,10 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
     for (;;) {
         if (threadIdx.x == 0) s_idx = atomicAdd(a.queue, 1);
         __syncthreads();
-        const int idx = s_idx;
+        const int qpos = s_idx;
         __syncthreads();
-        if (idx >= a.batch) break;
+        if (qpos >= a.batch) break;
+        const int idx = a.order ? a.order[qpos] : qpos;
 
         const int mj = a.m[idx], nj = a.n[idx];
         const bool trans = mj > nj;              // Z = X^T
@@ -487,10 +492,10 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
                     ycur[jb] = yn;
                     yprev[jb] = yk;
                 };
-                // column blocks in pairs (two interleaved chains), a lone last block alone
+                // column blocks in groups of PAIR (interleaved chains), a lone last block alone
 #pragma unroll
-                for (int jb = 0; jb < BT_JB; jb += 2) {
-                    if (jb + 1 < nb) {
+                for (int jb = 0; jb < BT_JB; jb += PAIR) {
+                    if (PAIR == 2 && jb + 1 < nb) {
                         f32x4 acc[2];
                         bt_product<SPLIT, 2>(YT, jb, lane, fa, gah, gal, acc);
                         update(jb, acc[0]);

@@ -66,7 +66,8 @@ struct cpa_ctx {
     int warm_cap = 0;
     int warm_d = -1;           // length of the stored vector, -1 if none
     int coop_max = 0;          // co-resident power-iteration workgroups (0: not queried)
-    int batch_grid[2] = {0, 0};   // persistent workgroups of the batched kernel (FP32, split; 0: not queried)
+    int batch_per_cu = 0;      // co-resident workgroups of the batched kernel per CU (0: not queried)
+    int cus = 0;
     int* queue = nullptr;      // work-queue counter of the batched kernel
     void* mlp_ws = nullptr;    // predictor training: gradient partials | loss partials
     // sparse path: its own workspace and the cached transposed pattern
@@ -1096,33 +1097,54 @@ cpa_status batched_prepare(cpa_ctx* ctx, int batch, const int32_t* m_dev, const 
     return CPA_OK;
 }
 
+// Launch shape of the batched kernel (the autotuner's search space).
+struct BatchConfig {
+    int per_cu;   // persistent workgroups per CU (1 or the occupancy limit)
+    int pair;     // recurrence output blocks per MFMA group (1 or 2)
+    int order;    // 0: queue in index order, 1: largest d^2 e first
+};
+
+cpa_status batched_query(cpa_ctx* ctx) {
+    if (ctx->batch_per_cu == 0) {
+        int per_cu = 0, cus = 0;
+        // every instantiation has the same LDS and the same register cap
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel<false, 2>, BT_THREADS, 0));
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        ctx->batch_per_cu = std::max(1, per_cu);
+        ctx->cus = std::max(1, cus);
+    }
+    return CPA_OK;
+}
+
+// Queue reset (a fill kernel, so the pair can be captured in a graph) and the kernel.
+cpa_status batched_enqueue(hipStream_t st, const BatchArgs& a, bool split, int pair, int grid) {
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, st, a.queue, 1, 0);
+    HIP_TRY(hipGetLastError());
+    grid = std::max(1, std::min(a.batch, grid));
+    if (split && pair == 2)
+        hipLaunchKernelGGL((batched_kernel<true, 2>), dim3(grid), dim3(BT_THREADS), 0, st, a);
+    else if (split)
+        hipLaunchKernelGGL((batched_kernel<true, 1>), dim3(grid), dim3(BT_THREADS), 0, st, a);
+    else if (pair == 2)
+        hipLaunchKernelGGL((batched_kernel<false, 2>), dim3(grid), dim3(BT_THREADS), 0, st, a);
+    else
+        hipLaunchKernelGGL((batched_kernel<false, 1>), dim3(grid), dim3(BT_THREADS), 0, st, a);
+    HIP_TRY(hipGetLastError());
+    return CPA_OK;
+}
+
+// Direct calls: the default configuration (occupancy-limit grid, pairs, index order).
 cpa_status batched_launch(cpa_ctx* ctx, void* stream, BatchArgs& a, bool split = false) {
     HIP_TRY(hipSetDevice(ctx->device));
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    int& bg = ctx->batch_grid[split ? 1 : 0];
-    if (bg == 0) {
-        int per_cu = 0, cus = 0;
-        if (split)
-            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel<true>, BT_THREADS, 0));
-        else
-            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batched_kernel<false>, BT_THREADS, 0));
-        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
-        bg = std::max(1, per_cu * cus);
-    }
+    cpa_status s;
+    if ((s = batched_query(ctx)) != CPA_OK) return s;
     if (!ctx->queue && hipMalloc(&ctx->queue, 256) != hipSuccess) {
         ctx->queue = nullptr;
         return fail(CPA_ERR_ALLOC, "queue allocation failed");
     }
     a.queue = ctx->queue;
-    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, st, ctx->queue, 1, 0);
-    HIP_TRY(hipGetLastError());
-    const int grid = std::min(a.batch, bg);
-    if (split)
-        hipLaunchKernelGGL(batched_kernel<true>, dim3(grid), dim3(BT_THREADS), 0, st, a);
-    else
-        hipLaunchKernelGGL(batched_kernel<false>, dim3(grid), dim3(BT_THREADS), 0, st, a);
-    HIP_TRY(hipGetLastError());
-    return CPA_OK;
+    a.order = nullptr;
+    return batched_enqueue(static_cast<hipStream_t>(stream), a, split, 2, ctx->batch_per_cu * ctx->cus);
 }
 
 cpa_status batched_shrink_args(const cpa_opts* opts, const float* X_dev, float* Y_dev,
@@ -1205,6 +1227,208 @@ cpa_status cpa_shrink_batched_predicted(cpa_ctx* ctx, void* stream, int batch, c
     a.K_out = K_out_dev;
     a.status = status_dev;
     return batched_launch(ctx, stream, a, opts->precision == CPA_PREC_BF16X3);
+}
+
+}  // extern "C"
+
+struct cpa_batched_plan {
+    int device = 0;
+    BatchArgs a;                  // bound buffers; queue and order are the plan's own
+    bool split = false;
+    BatchConfig cfg{2, 2, 0};
+    int grid = 1;
+    int* queue = nullptr;
+    int32_t* order = nullptr;     // largest-first queue order (used when cfg.order == 1)
+    hipGraphExec_t exec = nullptr;
+    cpa_batched_tuning tun{};
+};
+
+namespace {
+
+void plan_free(cpa_batched_plan* p) {
+    if (!p) return;
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->queue) (void)hipFree(p->queue);
+    if (p->order) (void)hipFree(p->order);
+    delete p;
+}
+
+// Largest-first queue order by the recurrence work d^2 e of every matrix (stable;
+// shapes outside the limits last).
+cpa_status plan_order(cpa_batched_plan* p, hipStream_t st) {
+    const int b = p->a.batch;
+    std::vector<int32_t> m(b), n(b);
+    HIP_TRY(hipMemcpyAsync(m.data(), p->a.m, sizeof(int32_t) * b, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(n.data(), p->a.n, sizeof(int32_t) * b, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<int64_t> cost(b);
+    for (int j = 0; j < b; ++j) {
+        const int64_t d = std::min(m[j], n[j]), e = std::max(m[j], n[j]);
+        cost[j] = (d >= 1 && d <= BT_DMAX && e <= BT_EMAX) ? d * d * e : -1;
+    }
+    std::vector<int32_t> ord(b);
+    for (int j = 0; j < b; ++j) ord[j] = j;
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
+    HIP_TRY(hipMemcpyAsync(p->order, ord.data(), sizeof(int32_t) * b, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return CPA_OK;
+}
+
+cpa_status plan_enqueue(cpa_batched_plan* p, hipStream_t st, const BatchConfig& c, int per_cu_max, int cus) {
+    BatchArgs a = p->a;
+    a.queue = p->queue;
+    a.order = c.order ? p->order : nullptr;
+    return batched_enqueue(st, a, p->split, c.pair, std::min(c.per_cu, per_cu_max) * cus);
+}
+
+// Mean time of `reps` launches of configuration c (after one untimed launch), in us.
+cpa_status plan_time(cpa_batched_plan* p, hipStream_t st, const BatchConfig& c, int per_cu_max, int cus, int reps,
+                     double& us) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(CPA_ERR_HIP, "event creation failed");
+    }
+    cpa_status s = plan_enqueue(p, st, c, per_cu_max, cus);
+    if (s == CPA_OK && hipEventRecord(e0, st) != hipSuccess) s = fail(CPA_ERR_HIP, "event record failed");
+    for (int r = 0; s == CPA_OK && r < reps; ++r) s = plan_enqueue(p, st, c, per_cu_max, cus);
+    if (s == CPA_OK && hipEventRecord(e1, st) != hipSuccess) s = fail(CPA_ERR_HIP, "event record failed");
+    if (s == CPA_OK && hipEventSynchronize(e1) != hipSuccess) s = fail(CPA_ERR_HIP, "event wait failed");
+    float ms = 0.f;
+    if (s == CPA_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) s = fail(CPA_ERR_HIP, "event timing failed");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    us = 1e3 * (double)ms / reps;
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+cpa_status cpa_batched_plan_create(cpa_ctx* ctx, void* stream, int batch, const int32_t* m_dev, const int32_t* n_dev,
+                                   const int64_t* off_dev, const float* X_dev, float* Y_dev,
+                                   const cpa_shrinkage* shrink_dev, const cpa_shrinkage* shrink_host,
+                                   const cpa_opts* opts, const double* Lambda_dev, double* Lambda_out_dev,
+                                   int32_t* status_dev, int32_t tune, cpa_batched_plan** plan_out) {
+    if (!plan_out) return fail(CPA_ERR_ARG, "plan_out is NULL");
+    *plan_out = nullptr;
+    cpa_status s;
+    BatchArgs a;
+    if ((s = batched_prepare(ctx, batch, m_dev, n_dev, off_dev, X_dev, a)) != CPA_OK) return s;
+    if ((s = batched_shrink_args(opts, X_dev, Y_dev, shrink_dev, shrink_host, a)) != CPA_OK) return s;
+    if (opts->bound == CPA_BOUND_GIVEN && !Lambda_dev) return fail(CPA_ERR_ARG, "Lambda_dev is NULL");
+    if (tune != 0 && tune != 1) return fail(CPA_ERR_ARG, "tune must be 0 or 1");
+    a.mode = opts->bound == CPA_BOUND_POWER ? 0 : (opts->bound == CPA_BOUND_GIVEN ? 1 : 2);
+    a.lambda_in = Lambda_dev;
+    a.lambda_out = Lambda_out_dev;
+    a.status = status_dev;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if ((s = batched_query(ctx)) != CPA_OK) return s;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+
+    cpa_batched_plan* p = new (std::nothrow) cpa_batched_plan();
+    if (!p) return fail(CPA_ERR_ALLOC, "plan allocation failed");
+    p->device = ctx->device;
+    p->a = a;
+    p->split = opts->precision == CPA_PREC_BF16X3;
+    const BatchConfig dflt{ctx->batch_per_cu, 2, 0};
+    p->cfg = dflt;
+    if (hipMalloc(&p->queue, 256) != hipSuccess) {
+        p->queue = nullptr;
+        plan_free(p);
+        return fail(CPA_ERR_ALLOC, "queue allocation failed");
+    }
+    if (batch > 0) {
+        if (hipMalloc(&p->order, sizeof(int32_t) * (size_t)batch) != hipSuccess) {
+            p->order = nullptr;
+            plan_free(p);
+            return fail(CPA_ERR_ALLOC, "order allocation failed");
+        }
+        if ((s = plan_order(p, st)) != CPA_OK) {
+            plan_free(p);
+            return s;
+        }
+    }
+    if (tune && batch > 0) {
+        // every configuration computes the same results; keep the fastest
+        double best = 0.0;
+        int ncand = 0;
+        for (int per_cu = 1; per_cu <= std::min(2, ctx->batch_per_cu); ++per_cu)
+            for (int pair = 1; pair <= 2; ++pair)
+                for (int ord = 0; ord <= 1; ++ord) {
+                    const BatchConfig c{per_cu, pair, ord};
+                    double us = 0.0;
+                    if ((s = plan_time(p, st, c, ctx->batch_per_cu, ctx->cus, 3, us)) != CPA_OK) {
+                        plan_free(p);
+                        return s;
+                    }
+                    ++ncand;
+                    if (per_cu == dflt.per_cu && pair == dflt.pair && ord == dflt.order) p->tun.default_us = us;
+                    if (ncand == 1 || us < best) {
+                        best = us;
+                        p->cfg = c;
+                    }
+                }
+        p->tun.candidates = ncand;
+        p->tun.best_us = best;
+    }
+    p->grid = std::max(1, std::min(batch, p->cfg.per_cu * ctx->cus));
+    p->tun.grid = p->grid;
+    p->tun.pair = p->cfg.pair;
+    p->tun.order = p->cfg.order;
+
+    // capture the chosen launch (queue reset + kernel) once; replays bake in every argument
+    if (!ctx->cap_stream && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        ctx->cap_stream = nullptr;
+        plan_free(p);
+        return fail(CPA_ERR_HIP, "capture stream creation failed");
+    }
+    if (batch > 0) {
+        hipGraph_t g;
+        if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            plan_free(p);
+            return fail(CPA_ERR_HIP, "graph capture could not start");
+        }
+        const cpa_status cs = plan_enqueue(p, ctx->cap_stream, p->cfg, ctx->batch_per_cu, ctx->cus);
+        const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &g);
+        if (cs != CPA_OK || ce != hipSuccess) {
+            if (ce == hipSuccess) (void)hipGraphDestroy(g);
+            plan_free(p);
+            return cs != CPA_OK ? cs : fail(CPA_ERR_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+        }
+        const hipError_t ie = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ie != hipSuccess) {
+            p->exec = nullptr;
+            plan_free(p);
+            return fail(CPA_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ie));
+        }
+    }
+    *plan_out = p;
+    return CPA_OK;
+}
+
+cpa_status cpa_batched_plan_execute(cpa_batched_plan* plan, void* stream) {
+    if (!plan) return fail(CPA_ERR_ARG, "plan is NULL");
+    if (!plan->exec) return CPA_OK;   // empty batch
+    HIP_TRY(hipSetDevice(plan->device));
+    HIP_TRY(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)));
+    return CPA_OK;
+}
+
+cpa_status cpa_batched_plan_tuning(const cpa_batched_plan* plan, cpa_batched_tuning* out) {
+    if (!plan || !out) return fail(CPA_ERR_ARG, "NULL argument");
+    *out = plan->tun;
+    return CPA_OK;
+}
+
+cpa_status cpa_batched_plan_destroy(cpa_batched_plan* plan) {
+    plan_free(plan);
+    return CPA_OK;
 }
 
 namespace {

@@ -34,6 +34,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(cpa.CpaShrinkage) == 40
     assert ctypes.sizeof(cpa.CpaOpts) == 72
     assert ctypes.sizeof(cpa.CpaInfo) == 56
+    assert ctypes.sizeof(cpa.CpaBatchedTuning) == 32
 
 
 @pytest.mark.parametrize("kind,tau", [(0, 1.3), (1, 0.9), (2, 2.0)])

@@ -183,3 +183,78 @@ def test_converged_power_bound_matches_oracle_on_hard_cases():
         for X, lg in zip(batch, lam_out):
             lo = obound.power_bound(_gram(X), seed=0, max_iter=1000, tol=1e-12, delta=0.0)[0]
             assert abs(lg - lo) <= 1e-4 * lo, (lg, lo)
+
+
+def _patch_batch(batch, seed, extra_shapes=()):
+    import torch
+    import paper_1705_07112_amd as cpa
+    flat, ms, ns, offs, _, _ = synth.patch_groups(batch=batch, seed=seed)
+    mats = [flat[offs[i]:offs[i] + ms[i] * ns[i]].reshape(ms[i], ns[i]) for i in range(batch)]
+    for k, (mm, nn) in enumerate(extra_shapes):
+        mats.append(synth.as_f32_exact(synth.dense_lowrank(mm, nn, rank=2, noise=0.1, seed=seed + 100 + k)))
+    flat, ms, ns, offs = _pack(mats)
+    dev = "cuda"
+    t = lambda a: torch.from_numpy(a).to(dev)
+    sig = 0.2
+    recs = [cpa.weighted_fn(2 * math.sqrt(2) * sig * sig * math.sqrt(float(nj)), (8 + math.sqrt(float(nj))) ** 2 * sig * sig,
+                            1e-6) for nj in ns]
+    rec_t = torch.frombuffer(bytearray(cpa.shrinkage_records(recs)), dtype=torch.uint8).to(dev)
+    return t(flat), t(ms), t(ns), t(offs), rec_t
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_plan_replays_match_direct_calls_bitwise(precision):
+    """A tuned plan (captured graph) gives the same bits as cpa_shrink_batched on
+    the same inputs, on every replay, also after X changes between replays."""
+    import torch
+    import paper_1705_07112_amd as cpa
+    X, m, n, off, rec_t = _patch_batch(700, 12600, extra_shapes=[(70, 70), (5, 3), (64, 130)])
+    batch = int(m.numel())
+    opts = cpa.Opts(K=16, precision=precision, check=True)
+    lam_p = torch.zeros(batch, dtype=torch.float64, device="cuda")
+    st_p = torch.full((batch,), -1, dtype=torch.int32, device="cuda")
+    # skipped matrices (shapes outside the limits) are never written: start both outputs at zero
+    plan = cpa.BatchedPlan(X, m, n, off, cpa.soft(0.0), opts, shrink_per_matrix=rec_t, out=torch.zeros_like(X),
+                           lambda_out=lam_p, status=st_p)
+    tun = plan.tuning
+    print(f"plan {precision}: {tun}", flush=True)
+    assert tun["candidates"] >= 4 and tun["best_us"] > 0 and tun["default_us"] > 0
+    assert tun["best_us"] <= tun["default_us"] * 1.0000001
+    for rep in range(3):
+        if rep == 2:
+            X.mul_(0.5).add_(0.01)   # new contents, same shapes
+        Yp = plan.run().clone()
+        lp, sp = lam_p.clone(), st_p.clone()
+        torch.cuda.synchronize()
+        lam_d = torch.zeros_like(lam_p)
+        st_d = torch.full_like(st_p, -1)
+        Yd = cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), opts, shrink_per_matrix=rec_t, out=torch.zeros_like(X),
+                                lambda_out=lam_d, status=st_d)
+        torch.cuda.synchronize()
+        assert torch.equal(Yp, Yd), rep
+        assert torch.equal(lp, lam_d), rep
+        assert torch.equal(sp, st_d), rep
+        assert int((sp == 2).sum()) == 2 and int((sp == 0).sum()) + int((sp == 1).sum()) == batch - 2
+    plan.close()
+
+
+def test_untuned_plan_and_empty_batch():
+    import torch
+    import paper_1705_07112_amd as cpa
+    X, m, n, off, rec_t = _patch_batch(50, 12700)
+    plan = cpa.BatchedPlan(X, m, n, off, cpa.soft(0.0), cpa.Opts(K=8), shrink_per_matrix=rec_t, tune=False)
+    tun = plan.tuning
+    assert tun["candidates"] == 0 and tun["best_us"] == 0.0 and tun["pair"] == 2 and tun["order"] == "index"
+    Yp = plan.run().clone()
+    Yd = cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), cpa.Opts(K=8), shrink_per_matrix=rec_t)
+    torch.cuda.synchronize()
+    assert torch.equal(Yp, Yd)
+    plan.close()
+    e32 = torch.zeros(0, dtype=torch.int32, device="cuda")
+    e64 = torch.zeros(0, dtype=torch.int64, device="cuda")
+    ef = torch.zeros(0, dtype=torch.float32, device="cuda")
+    empty = cpa.BatchedPlan(ef, e32, e32, e64, cpa.soft(1.0), cpa.Opts(K=8))
+    empty.run()
+    torch.cuda.synchronize()
+    assert empty.tuning["candidates"] == 0
+    empty.close()
