@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/cpasvt.h"
@@ -20,6 +21,7 @@
 #include "sparse.hpp"
 #include "gemm_bf16x3.hpp"
 #include "gemm_f32.hpp"
+#include "gemm_lds.hpp"
 #include "shrink_fn.hpp"
 #include "spectral.hpp"
 
@@ -255,11 +257,30 @@ cpa_status launch_gemm_split(hipStream_t st, const Operand& A, const Operand& B,
     return CPA_OK;
 }
 
+// Full 64 x 64 tiles of two k-contiguous operands: the direct global-to-LDS
+// pipeline applies.
+bool lds_pipeline_ok(const Operand& A, const Operand& B, int M, int N, int Kd) {
+    return M > 0 && N > 0 && Kd > 0 && M % 64 == 0 && N % 64 == 0 && Kd % GBK == 0 && aligned16(A.p, A.ld) &&
+           aligned16(B.p, B.ld);
+}
+
 // All products use 64 x 64 output tiles: at 1024 x 1024 that is 256 workgroups,
 // one per CU, and larger outputs simply have more of them.
 template <int LA, int LB, class Epi>
 cpa_status gemm_dispatch(hipStream_t st, const Operand& A, const Operand& B, int M, int N, int Kd, const Epi& epi,
                          int sc_a1, int sc_a2, int sc_coef) {
+    // the linear-epilogue products of the matrix-polynomial route: direct
+    // global-to-LDS copies, 16 waves (measured: 27.2 us vs 27.8 us at 1024^3;
+    // the Chebyshev and Gram epilogues run faster on the register-staged kernel)
+    if constexpr (LA == KCONTIG && LB == KCONTIG && std::is_same<Epi, EpiLin>::value) {
+        if (lds_pipeline_ok(A, B, M, N, Kd)) {
+            const int grid = (M / 64) * (N / 64);
+            hipLaunchKernelGGL((gemm_f32_lds_kernel<64, 64, Epi, 16>), dim3(grid), dim3(1024), 0, st, A, B, M, N, Kd,
+                               epi, sc_a1, sc_a2, sc_coef);
+            HIP_TRY(hipGetLastError());
+            return CPA_OK;
+        }
+    }
     return launch_gemm<64, 64, LA, LB>(st, A, B, M, N, Kd, epi, sc_a1, sc_a2, sc_coef);
 }
 

@@ -465,14 +465,15 @@ struct WaveLayout {
     static constexpr int KS = GWAVES / (WM * WN);
 };
 
-template <int BM, int BN, int LA, int LB>
+// NWAVES: waves of the workgroup (the K-split KS takes the waves beyond WM x WN).
+template <int BM, int BN, int LA, int LB, int NWAVES = GWAVES>
 struct GemmCore {
     using GA = TileGeom<BM, LA>;
     using GB = TileGeom<BN, LB>;
-    static constexpr int WM = WaveLayout<BM, BN>::WM, WN = WaveLayout<BM, BN>::WN, KS = WaveLayout<BM, BN>::KS;
+    static constexpr int WM = WaveLayout<BM, BN>::WM, WN = WaveLayout<BM, BN>::WN, KS = NWAVES / (WM * WN);
     static constexpr int MB = BM / WM / 16, NB = BN / WN / 16;   // 16x16 blocks per wave
     static constexpr int KQ = KG / KS;                            // sub-steps per wave and K-tile
-    static_assert(MB >= 1 && NB >= 1 && KS >= 1 && WM * WN * KS == GWAVES, "bad wave layout");
+    static_assert(MB >= 1 && NB >= 1 && KS >= 1 && WM * WN * KS == NWAVES, "bad wave layout");
     static_assert(KQ % 4 == 0, "sub-steps per wave must be a multiple of 4");
 
     struct Frags {

@@ -1,0 +1,209 @@
+// FP32 MFMA GEMM for full tiles of two k-contiguous operands, with the operand
+// tiles moved from global memory to LDS by the load unit itself
+// (global_load_lds_dwordx4: each lane's 16 bytes land at a consecutive LDS
+// address, no staging registers, no LDS store instructions).  Used for the
+// linear-epilogue products of the matrix-polynomial route.
+//
+// Same product, MFMA sequence, two-level partial sums and epilogues as
+// gemm_f32_kernel (gemm_f32.hpp) for A and B in the KCONTIG layout; it differs
+// in how tiles reach LDS and in the wave count:
+//   * four LDS stages (tile i in stage i % 4, 32 KB each) and the copy of tile
+//     t + 3 issued at step t, so a copy has two whole steps to land -- the
+//     operand panels are first touched by all workgroups of an XCD at about the
+//     same time, so many copies come from the MALL or HBM;
+//   * rows are stored unpadded (64 floats, 16 chunks of 16 bytes) with chunk c
+//     of row r at position c ^ (r % 16): a 16-byte fragment read by 16 lanes of
+//     16 consecutive rows then touches 16 different chunk positions, i.e. all
+//     64 banks once, and each lane's copy address is still a permutation of
+//     its row's 256 bytes (coalesced);
+//   * the waits are explicit: at the end of step t each wave waits until only
+//     its copies of tile t + 3 are outstanding (vmcnt), then the workgroup
+//     barrier makes tile t + 2 visible to every wave before step t + 1 reads it.
+//     The barrier is the bare s_barrier: a fence would wait for every
+//     outstanding copy, including the ones meant to stay in flight;
+//   * NW = 16 waves (four per SIMD, K-split 4) hide more of the LDS and MFMA
+//     latency than eight, at 110 registers per wave.
+// Requirements (checked by the host): M % 64 == 0, N % 64 == 0, Kd % 64 == 0,
+// 16-byte aligned bases, leading dimensions % 4 == 0.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gemm_f32.hpp"
+
+namespace cpa {
+
+constexpr int LDS_STAGES = 4;
+// copy instructions per wave for one K-tile of both operands (four rows each)
+template <int NW>
+constexpr int dma_per_tile() { return 2 * (64 / NW / 4); }
+constexpr int kDmaPerTile = dma_per_tile<GWAVES>();
+
+// Waits until at most N of this wave's vector-memory operations are outstanding
+// (N: the copies of one K-tile), optionally with all LDS operations done.
+template <int N>
+__device__ inline void wait_vm();
+template <>
+__device__ inline void wait_vm<2>() { asm volatile("s_waitcnt vmcnt(2)" ::: "memory"); }
+template <>
+__device__ inline void wait_vm<4>() { asm volatile("s_waitcnt vmcnt(4)" ::: "memory"); }
+template <int N>
+__device__ inline void wait_vm_lds();
+template <>
+__device__ inline void wait_vm_lds<2>() { asm volatile("s_waitcnt vmcnt(2) lgkmcnt(0)" ::: "memory"); }
+template <>
+__device__ inline void wait_vm_lds<4>() { asm volatile("s_waitcnt vmcnt(4) lgkmcnt(0)" ::: "memory"); }
+constexpr int LDS_TILE = 64 * GBK;   // floats per operand tile (64 rows x 64 k, unpadded)
+static_assert(GBK == 64, "the swizzled LDS layout assumes K-tiles of 64");
+
+// Copy of one 64 x 64 k-contiguous tile (rows x0.., k0..) into an LDS stage:
+// wave w copies rows 8 w .. 8 w + 7, four rows (64 lanes x 16 bytes) per
+// instruction; lane L takes row R = R0 + L / 16 and stores its chunk at
+// position L % 16, so it reads logical chunk (L % 16) ^ (R % 16).
+template <int NW = GWAVES>
+__device__ inline void tile_dma(const Operand& op, int x0, int k0, float* stage, int wave, int lane) {
+    constexpr int ROWS_PER_WAVE = 64 / NW;
+    static_assert(ROWS_PER_WAVE % 4 == 0, "four rows per copy instruction");
+#pragma unroll
+    for (int i = 0; i < ROWS_PER_WAVE / 4; ++i) {
+        const int R0 = wave * ROWS_PER_WAVE + 4 * i;
+        const int R = R0 + (lane >> 4);
+        const int c = (lane & 15) ^ (R & 15);
+        const float* src = op.p + (int64_t)(x0 + R) * op.ld + k0 + 4 * c;
+        __builtin_amdgcn_global_load_lds(src, stage + R0 * GBK, 16, 0, 0);
+    }
+}
+
+// Fragments of one lane for the 16-row block at xb (tile column k = KG g + kk,
+// kk = koff .. koff + Q - 1), from a swizzled stage.
+template <int Q>
+__device__ inline void frag_read_swz(const float* stage, int xb, int lane, int koff, float (&v)[Q]) {
+    const int xi = xb + (lane & 15);
+    const int g = lane >> 4;
+    const float* row = stage + xi * GBK;
+#pragma unroll
+    for (int q = 0; q < Q; q += 4) {
+        const int c = (KG * g + koff + q) >> 2;
+        const f32x4 t = *reinterpret_cast<const f32x4*>(row + ((c ^ (xi & 15)) << 2));
+        v[q] = t[0];
+        v[q + 1] = t[1];
+        v[q + 2] = t[2];
+        v[q + 3] = t[3];
+    }
+}
+
+// NW: waves per workgroup (8: K-split 2, two waves per SIMD; 16: K-split 4,
+// four waves per SIMD, half the fragment registers per wave).
+template <int BM, int BN, class Epi, int NW = GWAVES>
+__global__ void __launch_bounds__(64 * NW) gemm_f32_lds_kernel(Operand A, Operand B, int M, int N, int Kd, Epi epi,
+                                                               int sc_a1, int sc_a2, int sc_coef) {
+    static_assert(BM == 64 && BN == 64, "64 x 64 output tiles");
+    constexpr int NT = 64 * NW;
+    constexpr int DMA = dma_per_tile<NW>();
+    using C = GemmCore<BM, BN, KCONTIG, KCONTIG, NW>;
+    using Frags = typename C::Frags;
+    constexpr int MB = C::MB, NB = C::NB;
+    // stage s: A tile at lds + 2 s LDS_TILE, B tile right after it
+    __shared__ __attribute__((aligned(16))) float lds[LDS_STAGES * 2 * LDS_TILE];
+    static_assert(BM * (BN + 4) <= LDS_STAGES * 2 * LDS_TILE, "the epilogue tile must fit");
+
+    const int ntm = M / BM;
+    const int ntn = N / BN;
+    int tm, tn;
+    tile_coords(ntm, ntn, tm, tn);
+    const int m0 = tm * BM, n0 = tn * BN;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wo = wave % (C::WM * C::WN);
+    const int kh = wave / (C::WM * C::WN);
+    const int wr = wo / C::WN, wc = wo % C::WN;
+
+    f32x4 acc[MB][NB], p0[MB][NB], p1[MB][NB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[i][j] = p1[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+    Frags f0, f1;
+    const int nkt = Kd / GBK;
+    const int last = nkt - 1;
+    auto kof = [&](int t) { return min(t, last) * GBK; };
+    auto sa = [&](int t) { return lds + (t % LDS_STAGES) * 2 * LDS_TILE; };
+    auto sb = [&](int t) { return lds + (t % LDS_STAGES) * 2 * LDS_TILE + LDS_TILE; };
+    auto copy = [&](int t) {
+        tile_dma<NW>(A, m0, kof(t), sa(t), wave, lane);
+        tile_dma<NW>(B, n0, kof(t), sb(t), wave, lane);
+    };
+    auto read = [&](int t, Frags& f) {
+#pragma unroll
+        for (int i = 0; i < MB; ++i) frag_read_swz<C::KQ>(sa(t), wr * (BM / C::WM) + i * 16, lane, kh * C::KQ, f.a[i]);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) frag_read_swz<C::KQ>(sb(t), wc * (BN / C::WN) + j * 16, lane, kh * C::KQ, f.b[j]);
+    };
+
+    // prologue: tiles 0, 1, 2 in flight; wait for 0 and 1 (4 copies per tile and wave)
+    copy(0);
+    copy(1);
+    copy(2);
+    wait_vm<DMA>();
+    __builtin_amdgcn_s_barrier();
+    read(0, f0);
+
+    // step t: copy tile t+3 into the stage tile t-1 used (its fragments were read
+    // during step t-2), MFMAs of tile t, fragments of tile t+1, wait for tile t+2
+    for (int kt = 0; kt < nkt; kt += 2) {
+        copy(kt + 3);
+        CPA_SCHED_FENCE();
+        C::mfma(f0, p0);
+        C::add_into(acc, p1);
+        read(kt + 1, f1);
+        interleave_step<C::kMfma, C::kReads, 0>();
+        wait_vm_lds<DMA>();
+        __builtin_amdgcn_s_barrier();
+        if (kt + 1 >= nkt) {
+            C::add_into(acc, p0);
+            break;
+        }
+        copy(kt + 4);
+        CPA_SCHED_FENCE();
+        C::mfma(f1, p1);
+        C::add_into(acc, p0);
+        read(kt + 2, f0);
+        interleave_step<C::kMfma, C::kReads, 0>();
+        wait_vm_lds<DMA>();
+        __builtin_amdgcn_s_barrier();
+        if (kt + 2 >= nkt) C::add_into(acc, p1);
+    }
+    // the clamped copies past the last tile may still be landing: drain them
+    // before the stages are reused for the epilogue tile
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    __syncthreads();
+
+    float* tile = lds;
+#pragma unroll
+    for (int h = 0; h < C::KS; ++h) {
+        if (kh == h) {
+#pragma unroll
+            for (int a = 0; a < MB; ++a)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = wr * (BM / C::WM) + a * 16 + 4 * (lane >> 4) + r;
+                        const int j = wc * (BN / C::WN) + b * 16 + (lane & 15);
+                        float* t = tile + i * (BN + 4) + j;
+                        *t = (h == 0) ? acc[a][b][r] : *t + acc[a][b][r];
+                    }
+        }
+        if (C::KS > 1) __syncthreads();
+    }
+    __syncthreads();
+    constexpr int NG = BM * BN / 4 / NT;
+    static_assert(NG * 4 * NT == BM * BN, "tile must split evenly into float4 groups");
+    static_assert(NG == 1 || NT == GTHREADS, "epilogues index float4 groups in steps of GTHREADS");
+    epi.template run<BM, BN, NG>(tile, m0, n0, M, N, epi_scal(epi), sc_a1, sc_a2, sc_coef);
+}
+
+}  // namespace cpa

@@ -198,7 +198,8 @@ def test_full_size_rpca_matrix_sampled_rows():
 @pytest.mark.parametrize("shape,K", [((64, 48), 20), ((130, 70), 30), ((70, 130), 30), ((129, 129), 7),
                                      ((300, 1100), 16), ((1, 5), 9), ((5, 1), 9), ((200, 3), 64),
                                      ((64, 64), 100), ((64, 64), 144), ((97, 33), 2), ((97, 33), 3),
-                                     ((40, 30), 256)])
+                                     ((40, 30), 256), ((192, 320), 30), ((320, 192), 25), ((128, 128), 40),
+                                     ((256, 320), 30), ((640, 320), 25), ((512, 512), 16)])
 def test_both_evaluation_routes(ev, shape, K):
     """The recurrence over X and the matrix polynomial on the d x d side (baby
     steps / giant steps) against the same oracle."""
@@ -224,6 +225,20 @@ def test_polynomial_route_full_size_and_unaligned():
     # odd d (no 16-byte rows) and a strided input
     _case(131, 77, 25, 0, seed=91, ev="polynomial")
     _case(77, 131, 25, 0, seed=92, ev="polynomial", ld=140, offset=3)
+
+
+def test_polynomial_route_is_deterministic():
+    """The polynomial route (direct global-to-LDS products at these sizes) gives
+    the same bits on every call."""
+    torch = _torch()
+    cpa = _lib()
+    for d, K in ((256, 30), (512, 25), (1024, 30)):
+        X = torch.from_numpy(synth.dense_lowrank(d, d, rank=8, noise=0.1, seed=d).astype(np.float32)).cuda()
+        o = cpa.Opts(K=K, eval="polynomial", bound="frobenius")
+        Y1 = cpa.shrink_dense(X, cpa.soft(0.5), o).clone()
+        Y2 = cpa.shrink_dense(X, cpa.soft(0.5), o).clone()
+        torch.cuda.synchronize()
+        assert torch.equal(Y1, Y2), d
 
 
 def test_polynomial_route_rejects_growth_check():
