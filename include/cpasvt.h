@@ -379,6 +379,14 @@ cpa_status cpa_predictor_train(cpa_ctx* ctx, void* stream, int64_t n, const floa
 cpa_status cpa_timing_enable(cpa_ctx* ctx, int enable);
 cpa_status cpa_timing_read(cpa_ctx* ctx, int which, double* total_ms_host, int64_t* launches_host);
 
+/* Achievable matrix-core throughput (measurement support for roofline figures,
+ * not part of the method): launches a kernel whose waves issue `iters` rounds
+ * of eight independent MFMAs on register operands (kind 0:
+ * v_mfma_f32_16x16x4f32, 1: v_mfma_f32_16x16x32_bf16; four waves per SIMD, no
+ * memory traffic), twice, and returns the second launch's rate in TFLOP/s
+ * (dense flops).  Synchronises `stream`. */
+cpa_status cpa_peak_mfma(cpa_ctx* ctx, void* stream, int kind, int iters, double* tflops_host);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,6 +82,7 @@ _SIGS = {
                                         ctypes.POINTER(CpaInfo)]),
     "cpa_rpca_state_floats": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int]),
     "cpa_timing_enable": (ctypes.c_int, [_P, ctypes.c_int]),
+    "cpa_peak_mfma": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
     "cpa_timing_read": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]),
     "cpa_rpca_init": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P]),
@@ -440,6 +441,16 @@ def svt_complete(m, n, rowptr, colidx, mvals, tau: float, delta: float, iters: i
 def shrinkage_records(records) -> bytes:
     """Packs a list of CpaShrinkage into the byte layout of a cpa_shrinkage array."""
     return b"".join(bytes(r) for r in records)
+
+
+def peak_mfma(kind: str = "fp32", iters: int = 4000, device: int = 0) -> float:
+    """Achievable dense MFMA rate of the device in TFLOP/s (see cpa_peak_mfma)."""
+    import torch
+    out = ctypes.c_double()
+    _check(lib().cpa_peak_mfma(ctypes.c_void_p(context(device)),
+                               ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream),
+                               {"fp32": 0, "bf16": 1}[kind], int(iters), ctypes.byref(out)))
+    return out.value
 
 
 def timing_enable(enable: bool = True, device: int = 0):

@@ -22,6 +22,7 @@
 #include "gemm_bf16x3.hpp"
 #include "gemm_f32.hpp"
 #include "gemm_lds.hpp"
+#include "peak.hpp"
 #include "shrink_fn.hpp"
 #include "spectral.hpp"
 
@@ -1834,6 +1835,45 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
         ctx->admm_key = key;
     }
     for (; t < iters; ++t) HIP_TRY(hipGraphLaunch(ctx->admm_exec, st));
+    return CPA_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+cpa_status cpa_peak_mfma(cpa_ctx* ctx, void* stream, int kind, int iters, double* tflops_host) {
+    if (!ctx || !tflops_host) return fail(CPA_ERR_ARG, "NULL argument");
+    if (kind != 0 && kind != 1) return fail(CPA_ERR_ARG, "kind must be 0 (FP32) or 1 (BF16)");
+    if (iters < 1 || iters > (1 << 20)) return fail(CPA_ERR_ARG, "iters must be in [1, 2^20]");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    const int grid = 4 * cus;   // four 4-wave workgroups per CU: four waves per SIMD
+    float* out = nullptr;
+    if (hipMalloc(&out, sizeof(float) * (size_t)grid * 256) != hipSuccess) return fail(CPA_ERR_ALLOC, "allocation failed");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    cpa_status s = CPA_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) s = fail(CPA_ERR_HIP, "event creation failed");
+    float ms = 0.f;
+    for (int r = 0; s == CPA_OK && r < 2; ++r) {   // the first launch warms the clocks up
+        if (hipEventRecord(e0, st) != hipSuccess) s = fail(CPA_ERR_HIP, "event record failed");
+        if (kind == 0)
+            hipLaunchKernelGGL(peak_mfma_kernel<0>, dim3(grid), dim3(256), 0, st, iters, out);
+        else
+            hipLaunchKernelGGL(peak_mfma_kernel<1>, dim3(grid), dim3(256), 0, st, iters, out);
+        if (s == CPA_OK && hipGetLastError() != hipSuccess) s = fail(CPA_ERR_HIP, "launch failed");
+        if (s == CPA_OK && hipEventRecord(e1, st) != hipSuccess) s = fail(CPA_ERR_HIP, "event record failed");
+        if (s == CPA_OK && hipEventSynchronize(e1) != hipSuccess) s = fail(CPA_ERR_HIP, "event wait failed");
+        if (s == CPA_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) s = fail(CPA_ERR_HIP, "event timing failed");
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(out);
+    if (s != CPA_OK) return s;
+    const double flop = (double)grid * 4 /* waves */ * iters * kPeakChains * (kind == 0 ? 2048.0 : 16384.0);
+    *tflops_host = flop / (1e-3 * ms) / 1e12;
     return CPA_OK;
 }
 
