@@ -135,6 +135,36 @@ __device__ inline bool grid_barrier(unsigned* counter, unsigned target, double* 
     return ok != 0;
 }
 
+// Grid barrier for kernels that exchange data only through agent-scope atomic
+// accesses (coherent across the XCDs' L2 caches without flushing them): each
+// thread's stores have completed (vmcnt) before its workgroup arrives, and the
+// spin reads the counter with relaxed loads.  Unlike grid_barrier it writes back
+// and invalidates no cache, so G stays in L2 from one product to the next.
+__device__ inline bool grid_barrier_coherent(unsigned* counter, unsigned target, double* scal) {
+    __shared__ int ok;
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int good = 1;
+        unsigned spins = 0;
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > (1u << 22)) {
+                good = 0;
+                scal[SC_TIMEOUT] = 1.0;
+                break;
+            }
+        }
+        ok = good;
+    }
+    __syncthreads();
+    return ok != 0;
+}
+
+__device__ inline double ld_agent(const double* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline void st_agent(double* p, double v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
 // Sum of part[0..n) in a fixed order (same result in every workgroup).
 __device__ inline double ordered_sum(const double* part, int n, double* red) {
     double a = 0.0;
@@ -143,16 +173,24 @@ __device__ inline double ordered_sum(const double* part, int n, double* red) {
 }
 
 // All products of the power iteration in one cooperative launch (see top).
+// The iterate and the partial sums written during the launch are exchanged
+// through agent-scope atomic stores and loads (grid_barrier_coherent); each
+// workgroup copies w_{t-1} into LDS once per product (d <= kPowerVecLds; above
+// that the matvec reads it with agent-scope loads).
+constexpr int kPowerVecLds = 4096;
+
 __global__ void __launch_bounds__(kPowerThreads) power_coop_kernel(int d, const float* G, int64_t ldg, double* wb0,
                                                                    double* wb1, double* part, unsigned* counter,
                                                                    double* scal, int maxit, double tol, int pw_mu,
                                                                    int pw_w2) {
     __shared__ double red[kPowerThreads / 64];
     __shared__ double bcast[2];
+    __shared__ __attribute__((aligned(16))) double vl[kPowerVecLds];
     const int P = gridDim.x;
     const int lane = threadIdx.x & 63;
     const int gw = blockIdx.x * (kPowerThreads / 64) + (threadIdx.x >> 6);
     const int nw = P * (kPowerThreads / 64);
+    const bool in_lds = d <= kPowerVecLds;
     double w2prev = scal[pw_w2 + 0];
     double muprev = 0.0;
     int stop = 0, vanish = 0;
@@ -161,9 +199,13 @@ __global__ void __launch_bounds__(kPowerThreads) power_coop_kernel(int d, const 
     for (; !vanish && t <= maxit; ++t) {
         const double* wp = (t & 1) ? wb0 : wb1;   // w_{t-1}
         double* wn = (t & 1) ? wb1 : wb0;         // w_t
+        if (in_lds) {
+            for (int j = threadIdx.x; j < d; j += kPowerThreads) vl[j] = ld_agent(wp + j);
+            __syncthreads();
+        }
         const double inv = 1.0 / sqrt(w2prev);
         double mu_part = 0.0, w2_part = 0.0;
-        const bool vec = ((ldg & 3) == 0) && ((reinterpret_cast<uintptr_t>(G) & 15) == 0);
+        const bool vec = ((ldg & 3) == 0) && ((reinterpret_cast<uintptr_t>(G) & 15) == 0) && in_lds;
         for (int i = gw; i < d; i += nw) {
             const float* row = G + (int64_t)i * ldg;
             // four independent partial sums, 16-byte loads of G when rows are aligned,
@@ -174,8 +216,8 @@ __global__ void __launch_bounds__(kPowerThreads) power_coop_kernel(int d, const 
 #pragma unroll 4
                 for (; j + 3 < d; j += 256) {
                     const f32x4 g = *reinterpret_cast<const f32x4*>(row + j);
-                    const double2 v01 = *reinterpret_cast<const double2*>(wp + j);
-                    const double2 v23 = *reinterpret_cast<const double2*>(wp + j + 2);
+                    const double2 v01 = *reinterpret_cast<const double2*>(vl + j);
+                    const double2 v23 = *reinterpret_cast<const double2*>(vl + j + 2);
                     a[0] += (double)g[0] * v01.x;
                     a[1] += (double)g[1] * v01.y;
                     a[2] += (double)g[2] * v23.x;
@@ -184,13 +226,13 @@ __global__ void __launch_bounds__(kPowerThreads) power_coop_kernel(int d, const 
             }
             for (; j < d; j += 256)
                 for (int e = 0; e < 4; ++e)
-                    if (j + e < d) a[e] += (double)row[j + e] * wp[j + e];
+                    if (j + e < d) a[e] += (double)row[j + e] * (in_lds ? vl[j + e] : ld_agent(wp + j + e));
             double acc = (a[0] + a[1]) + (a[2] + a[3]);
             for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
             acc *= inv;
             if (lane == 0) {
-                wn[i] = acc;
-                mu_part += (wp[i] * inv) * acc;
+                st_agent(wn + i, acc);
+                mu_part += ((in_lds ? vl[i] : ld_agent(wp + i)) * inv) * acc;
                 w2_part += acc * acc;
             }
         }
@@ -198,12 +240,17 @@ __global__ void __launch_bounds__(kPowerThreads) power_coop_kernel(int d, const 
         w2_part = block_sum(w2_part, red);
         double* pt = part + (t & 1) * 2 * P;
         if (threadIdx.x == 0) {
-            pt[blockIdx.x] = mu_part;
-            pt[P + blockIdx.x] = w2_part;
+            st_agent(pt + blockIdx.x, mu_part);
+            st_agent(pt + P + blockIdx.x, w2_part);
         }
-        if (!grid_barrier(counter, (unsigned)t * P, scal)) return;
-        const double mu = ordered_sum(pt, P, red);
-        const double w2 = ordered_sum(pt + P, P, red);
+        if (!grid_barrier_coherent(counter, (unsigned)t * P, scal)) return;
+        double smu = 0.0, sw2 = 0.0;
+        for (int i = threadIdx.x; i < P; i += kPowerThreads) {
+            smu += ld_agent(pt + i);
+            sw2 += ld_agent(pt + P + i);
+        }
+        const double mu = block_sum(smu, red);
+        const double w2 = block_sum(sw2, red);
         if (threadIdx.x == 0) {
             bcast[0] = mu;
             bcast[1] = w2;

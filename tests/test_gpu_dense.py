@@ -252,3 +252,16 @@ def test_polynomial_route_rejects_growth_check():
     # auto with the check takes the recurrence and reports its growth
     _, info = cpa.shrink_dense(Xd, cpa.soft(0.1), cpa.Opts(K=9, check=True), info=True)
     assert info["max_growth"] > 0.0
+
+
+def test_power_bound_large_d_reads_iterate_from_global():
+    """d above the LDS copy of the iterate (4096): the cooperative power iteration
+    reads w_{t-1} with agent-scope loads; its bound matches the oracle's."""
+    torch = _torch()
+    cpa = _lib()
+    X = synth.dense_lowrank(4160, 4160, rank=12, noise=0.05, seed=4160).astype(np.float32)
+    G = X.astype(np.float64).T @ X.astype(np.float64)
+    lam_o = obound.power_bound(G, seed=0, max_iter=100, tol=1e-7)[0]
+    lam_g, _ = cpa.spectral_bound(torch.from_numpy(X).cuda(), cpa.Opts(K=8))
+    print(f"d=4160 power bound: gpu {lam_g:.9e} oracle {lam_o:.9e}", flush=True)
+    assert abs(lam_g - lam_o) <= 2e-6 * lam_o
