@@ -24,7 +24,10 @@
 // are combined in a fixed order (xor shuffles), so results do not depend on
 // scheduling.
 //   power_op_kernel  power iteration on S^T S through two sparse products per step,
-//                    one cooperative launch (two grid barriers per product).
+//                    one cooperative launch (two grid barriers per product); the
+//                    vectors and partial sums go through agent-scope atomic
+//                    accesses, so the barriers flush no cache and the pattern
+//                    stays in L2 from one product to the next.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -362,7 +365,8 @@ __global__ void sq_norm_kernel(int64_t nnz, const float* val, double* part) {
 }
 
 // Power iteration on G = S^T S without forming it: t = S v, w = S^T t.
-// Same stopping rule and partial-sum scheme as power_coop_kernel; the cap of
+// Same stopping rule, partial-sum scheme and data exchange (agent-scope atomic
+// accesses, v staged in LDS when n <= kPowerVecLds) as power_coop_kernel; the cap of
 // the bound uses tr(G) = ||S||_F^2 >= ||G||_F (written to SC_FRO2 as its square
 // by the caller's reduction: SC_FRO2 holds tr(G)^2).
 __global__ void __launch_bounds__(kPowerThreads) power_op_kernel(int m, int n, const int32_t* rowptr,
@@ -374,6 +378,8 @@ __global__ void __launch_bounds__(kPowerThreads) power_op_kernel(int m, int n, c
                                                                  int pw_w2) {
     __shared__ double red[kPowerThreads / 64];
     __shared__ double bcast[2];
+    __shared__ __attribute__((aligned(16))) double vl[kPowerVecLds];
+    const bool in_lds = n <= kPowerVecLds;
     const int P = gridDim.x;
     const int lane = threadIdx.x & 63;
     const int gw = blockIdx.x * (kPowerThreads / 64) + (threadIdx.x >> 6);
@@ -386,24 +392,31 @@ __global__ void __launch_bounds__(kPowerThreads) power_op_kernel(int m, int n, c
     for (; !vanish && t <= maxit; ++t) {
         const double* wp = (t & 1) ? wb0 : wb1;
         double* wn = (t & 1) ? wb1 : wb0;
+        if (in_lds) {
+            for (int j = threadIdx.x; j < n; j += kPowerThreads) vl[j] = ld_agent(wp + j);
+            __syncthreads();
+        }
         const double inv = 1.0 / sqrt(w2prev);
         // t = S v   (rows over waves)
         for (int r = gw; r < m; r += nw) {
             double acc = 0.0;
-            for (int32_t e = rowptr[r] + lane; e < rowptr[r + 1]; e += 64) acc += (double)val[e] * (wp[colidx[e]] * inv);
+            for (int32_t e = rowptr[r] + lane; e < rowptr[r + 1]; e += 64) {
+                const int32_t c = colidx[e];
+                acc += (double)val[e] * ((in_lds ? vl[c] : ld_agent(wp + c)) * inv);
+            }
             for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-            if (lane == 0) tvec[r] = acc;
+            if (lane == 0) st_agent(tvec + r, acc);
         }
-        if (!grid_barrier(counter, (++bar) * P, scal)) return;
+        if (!grid_barrier_coherent(counter, (++bar) * P, scal)) return;
         // w = S^T t  (columns over waves), rows ascending within a column
         double mu_part = 0.0, w2_part = 0.0;
         for (int c = gw; c < n; c += nw) {
             double acc = 0.0;
-            for (int32_t p = colptr[c] + lane; p < colptr[c + 1]; p += 64) acc += (double)val[csrc[p]] * tvec[crow[p]];
+            for (int32_t p = colptr[c] + lane; p < colptr[c + 1]; p += 64) acc += (double)val[csrc[p]] * ld_agent(tvec + crow[p]);
             for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
             if (lane == 0) {
-                wn[c] = acc;
-                mu_part += (wp[c] * inv) * acc;
+                st_agent(wn + c, acc);
+                mu_part += ((in_lds ? vl[c] : ld_agent(wp + c)) * inv) * acc;
                 w2_part += acc * acc;
             }
         }
@@ -411,12 +424,17 @@ __global__ void __launch_bounds__(kPowerThreads) power_op_kernel(int m, int n, c
         w2_part = block_sum(w2_part, red);
         double* pt = part + (t & 1) * 2 * P;
         if (threadIdx.x == 0) {
-            pt[blockIdx.x] = mu_part;
-            pt[P + blockIdx.x] = w2_part;
+            st_agent(pt + blockIdx.x, mu_part);
+            st_agent(pt + P + blockIdx.x, w2_part);
         }
-        if (!grid_barrier(counter, (++bar) * P, scal)) return;
-        const double mu = ordered_sum(pt, P, red);
-        const double w2 = ordered_sum(pt + P, P, red);
+        if (!grid_barrier_coherent(counter, (++bar) * P, scal)) return;
+        double smu = 0.0, sw2 = 0.0;
+        for (int i = threadIdx.x; i < P; i += kPowerThreads) {
+            smu += ld_agent(pt + i);
+            sw2 += ld_agent(pt + P + i);
+        }
+        const double mu = block_sum(smu, red);
+        const double w2 = block_sum(sw2, red);
         if (threadIdx.x == 0) {
             bcast[0] = mu;
             bcast[1] = w2;
