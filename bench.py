@@ -293,7 +293,13 @@ def bench_sparse(cpa, torch, np, synth):
                           "roofline": {"bound": "hbm", "achieved": round(step_bytes / (us_r * 1e-6) / 1e9, 1),
                                        "peak": 8000.0, "unit": "GB/s",
                                        "frac": round(step_bytes / (us_r * 1e-6) / 1e9 / 8000.0, 4),
-                                       "bytes_per_step": step_bytes, "traffic": None}},
+                                       "bytes_per_step": step_bytes, "traffic": None},
+                          # what actually bounds it: every nonzero gathers a whole row of the
+                          # dense operand (Y_k in S^T Y_k, W in S W), served from L2 / MALL
+                          "gathers": {"bytes_per_step": 2.0 * nnz * n * 4,
+                                      "achieved_TBps": round(2.0 * nnz * n * 4 / (us_r * 1e-6) / 1e12, 2),
+                                      "note": "2 nnz n 4 bytes of row gathers per step, "
+                                              "25x the algorithmic HBM bytes"}},
     }
 
 

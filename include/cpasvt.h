@@ -106,6 +106,15 @@ typedef enum { CPA_PREC_FP32 = 0, CPA_PREC_BF16X3 = 1 } cpa_precision;
  *                        otherwise RECURRENCE. */
 typedef enum { CPA_EVAL_AUTO = 0, CPA_EVAL_RECURRENCE = 1, CPA_EVAL_POLYNOMIAL = 2 } cpa_eval;
 
+/* Which Gram the bound and the polynomial use (eq. sing_shrink_from_eig_shrink:
+ * X h(X^T X) = h(X X^T) X, so both give the same matrix; they differ in cost
+ * and rounding).
+ *   CPA_SIDE_AUTO   the smaller one: X^T X (n x n) when m >= n, else X X^T
+ *   CPA_SIDE_RIGHT  X^T X, products with X on the right (Y_k Ghat)
+ *   CPA_SIDE_LEFT   X X^T, products on the left (Ghat Y_k)
+ * The sparse path forms S^T S (AUTO or RIGHT); the batched path takes AUTO. */
+typedef enum { CPA_SIDE_AUTO = 0, CPA_SIDE_RIGHT = 1, CPA_SIDE_LEFT = 2 } cpa_side;
+
 typedef struct {
     int32_t K;            /* number of Chebyshev coefficients (the paper's order alpha), >= 1 */
     int32_t bound;        /* cpa_bound_rule */
@@ -119,8 +128,8 @@ typedef struct {
                              recompute at Lambda = ||Gram||_F on failure (synchronises the stream) */
     int32_t precision;    /* cpa_precision */
     double growth_tol;    /* tolerance of the growth check */
-    int32_t eval;         /* cpa_eval (dense path; the sparse and batched paths use the recurrence) */
-    int32_t reserved;     /* must be 0 */
+    int32_t eval;         /* cpa_eval (dense and sparse paths; the batched path uses the recurrence) */
+    int32_t side;         /* cpa_side */
 } cpa_opts;
 
 /* Per-call report (host struct).  Filling it synchronises the stream. */
@@ -133,7 +142,7 @@ typedef struct {
                              matrix-polynomial route ran: it never forms Y_k) */
     int32_t power_iters_done;
     int32_t fallback;     /* 1 when the growth check forced Lambda = ||Gram||_F */
-    int32_t side;         /* 0: Gram = X^T X (m >= n), 1: Gram = X X^T (m < n) */
+    int32_t side;         /* 0: Gram = X^T X (right side), 1: Gram = X X^T (left side) */
     int32_t reserved;
 } cpa_info;
 
@@ -166,6 +175,14 @@ cpa_status cpa_chebyshev_coeffs(const cpa_shrinkage* shrink, double Lambda, int 
 cpa_status cpa_spectral_bound(cpa_ctx* ctx, void* stream, int m, int n,
                               const float* X_dev, int64_t ldx, const cpa_opts* opts,
                               double* Lambda_host, cpa_info* info_host);
+
+/* Device bytes the context's workspace grows to for cpa_shrink_dense (and
+ * cpa_spectral_bound) on an m x n input with these options: the Gram, two Y
+ * buffers, the power vectors, the scalar block, the matrix-polynomial buffers
+ * when that route runs, and the warm-start vector.  The context allocates them
+ * on first use and keeps them (a larger call grows them); nothing is allocated
+ * by this query.  (The RPCA driver adds one m x n buffer and its E_t partials.) */
+cpa_status cpa_workspace_bytes(cpa_ctx* ctx, int m, int n, const cpa_opts* opts, size_t* bytes_host);
 
 /* Dense shrinkage Y = hat G(X) of Algorithm 1 (T = Id), FP32 in and out.
  * X_dev (m x n, ldx) is read only; Y_dev (m x n, ldy) is written and must not

@@ -40,7 +40,7 @@ class CpaOpts(ctypes.Structure):
                 ("power_iters", ctypes.c_int32), ("warm_start", ctypes.c_int32),
                 ("power_tol", ctypes.c_double), ("margin", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("check", ctypes.c_int32), ("precision", ctypes.c_int32), ("growth_tol", ctypes.c_double),
-                ("eval", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("eval", ctypes.c_int32), ("side", ctypes.c_int32)]
 
 
 class CpaInfo(ctypes.Structure):
@@ -83,6 +83,8 @@ _SIGS = {
     "cpa_rpca_state_floats": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int]),
     "cpa_timing_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "cpa_peak_mfma": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+    "cpa_workspace_bytes": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(CpaOpts),
+                                           ctypes.POINTER(ctypes.c_size_t)]),
     "cpa_timing_read": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]),
     "cpa_rpca_init": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P]),
@@ -178,6 +180,7 @@ class Opts:
     growth_tol: float = 1e-3
     precision: str = "fp32"      # "fp32" | "bf16x3"
     eval: str = "auto"           # "auto" | "recurrence" | "polynomial"
+    side: str = "auto"           # "auto" | "right" (Gram X^T X) | "left" (Gram X X^T)
 
     def to_c(self) -> CpaOpts:
         o = CpaOpts()
@@ -197,6 +200,7 @@ class Opts:
         o.precision = {"fp32": PREC_FP32, "bf16x3": PREC_BF16X3}[self.precision]
         o.growth_tol = float(self.growth_tol)
         o.eval = {"auto": 0, "recurrence": 1, "polynomial": 2}[self.eval]
+        o.side = {"auto": 0, "right": 1, "left": 2}[self.side]
         return o
 
 
@@ -441,6 +445,15 @@ def svt_complete(m, n, rowptr, colidx, mvals, tau: float, delta: float, iters: i
 def shrinkage_records(records) -> bytes:
     """Packs a list of CpaShrinkage into the byte layout of a cpa_shrinkage array."""
     return b"".join(bytes(r) for r in records)
+
+
+def workspace_bytes(m: int, n: int, opts: Opts, device: int = 0) -> int:
+    """Device bytes the dense shrink of an m x n input needs (see cpa_workspace_bytes)."""
+    out = ctypes.c_size_t()
+    co = opts.to_c()
+    _check(lib().cpa_workspace_bytes(ctypes.c_void_p(context(device)), int(m), int(n), ctypes.byref(co),
+                                     ctypes.byref(out)))
+    return int(out.value)
 
 
 def peak_mfma(kind: str = "fp32", iters: int = 4000, device: int = 0) -> float:

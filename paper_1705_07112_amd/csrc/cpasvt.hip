@@ -118,8 +118,15 @@ struct Work {
     int* et_counter;  // next E_t slot
     float* poly;      // matrix-polynomial route: T_1..T_s, R_0..R_{J-1}, three Clenshaw buffers (d x d each)
     int poly_s;       // s of that route (0: not allocated)
+    bool right;       // Gram = X^T X (n x n) and products on the right; else X X^T (m x m), on the left
+    int d;            // side of the Gram
     ScalarLayout lay;
 };
+
+// The Gram side: CPA_SIDE_AUTO takes the smaller one (X^T X when m >= n).
+bool right_side(const cpa_opts* o, int m, int n) {
+    return o->side == CPA_SIDE_AUTO ? m >= n : o->side == CPA_SIDE_RIGHT;
+}
 
 size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -139,8 +146,13 @@ int power_grid(cpa_ctx* ctx, int d) {
     return want;
 }
 
-cpa_status ensure_ws(cpa_ctx* ctx, int m, int n, int K, int maxit, bool admm, Work& w, int poly_s = 0) {
-    const int d = std::min(m, n);
+// size_only != nullptr: report the bytes of the main workspace and the power
+// vector this call needs and allocate nothing.
+cpa_status ensure_ws(cpa_ctx* ctx, int m, int n, int K, int maxit, bool admm, Work& w, bool right, int poly_s = 0,
+                     size_t* size_only = nullptr) {
+    const int d = right ? n : m;
+    w.right = right;
+    w.d = d;
     const int64_t mn = (int64_t)m * n;
     if (ctx->coop_max == 0) {
         int per_cu = 0, cus = 0;
@@ -165,6 +177,10 @@ cpa_status ensure_ws(cpa_ctx* ctx, int m, int n, int K, int maxit, bool admm, Wo
     if (admm) {
         ox = off; off = align_up(off + sizeof(float) * (size_t)mn);
         oa = off; off = align_up(off + sizeof(double) * 2 * kAdmmGrid + 256);
+    }
+    if (size_only) {
+        *size_only = off + sizeof(double) * (size_t)std::max(d, 1);
+        return CPA_OK;
     }
     if (off > ctx->ws_bytes) {
         if (ctx->ws) {
@@ -324,7 +340,7 @@ cpa_status check_opts(const cpa_opts* o) {
         return fail(CPA_ERR_UNSUPPORTED, "the growth check needs the recurrence (eval AUTO or RECURRENCE)");
     if (o->eval == CPA_EVAL_POLYNOMIAL && o->K > 256)
         return fail(CPA_ERR_UNSUPPORTED, "the matrix-polynomial route supports K <= 256");
-    if (o->reserved != 0) return fail(CPA_ERR_ARG, "opts.reserved must be 0");
+    if (o->side < CPA_SIDE_AUTO || o->side > CPA_SIDE_LEFT) return fail(CPA_ERR_ARG, "unknown side %d", o->side);
     return CPA_OK;
 }
 
@@ -357,12 +373,12 @@ cpa_status enqueue_gram(cpa_ctx* ctx, hipStream_t st, int m, int n, const float*
 
 cpa_status enqueue_gram_impl(hipStream_t st, int m, int n, const float* X, int64_t ldx, const Work& w) {
     EpiGram epi;
-    const int d = std::min(m, n);
+    const int d = w.d;
     epi.C = w.G;
     epi.ldc = d;
     epi.part = w.scal + w.lay.gpart();
     epi.vec_ok = aligned16(w.G, d);
-    if (m >= n) {
+    if (w.right) {
         // G(i, j) = sum_r X[r][i] X[r][j]
         Operand A = make_op(X, ldx, n), B = make_op(X, ldx, n);
         return gemm_dispatch<XCONTIG, XCONTIG>(st, A, B, n, n, m, epi, 0, 0, 0);
@@ -414,7 +430,7 @@ cpa_status enqueue_recurrence(cpa_ctx* ctx, hipStream_t st, int m, int n, const 
         HIP_TRY(hipGetLastError());
         return CPA_OK;
     }
-    const int d = std::min(m, n);
+    const int d = w.d;
     const int norms = w.lay.norms();
     for (int k = 0; k + 1 <= K - 1; ++k) {
         EpiCheb epi;
@@ -439,7 +455,7 @@ cpa_status enqueue_recurrence(cpa_ctx* ctx, hipStream_t st, int m, int n, const 
         cpa_status s = timing_pair(ctx, 0, ea, eb);
         if (s != CPA_OK) return s;
         if (ea) HIP_TRY(hipEventRecord(ea, st));
-        if (m >= n) {
+        if (w.right) {
             // Y_k G: A = Y_k (k contiguous); B(k, j) = G[k][j] = G[j][k] (G symmetric),
             // read along k so both operands take 16-byte LDS fragment reads
             Operand A = make_op(yk, ldk, m), B = make_op(w.G, d, n);
@@ -466,7 +482,7 @@ cpa_status enqueue_recurrence(cpa_ctx* ctx, hipStream_t st, int m, int n, const 
 // giant steps in the Chebyshev basis:
 //   T_1 = Ghat, T_{i+1} = 2 T_1 T_i - T_{i-1}            (i < s: s - 1 products)
 //   p = sum_j R_j T_j(y), y = T_s, R_j = sum_i r_{j,i} T_i   (Clenshaw in y: J - 1 products)
-//   Y = X p (m >= n) or p X (m < n)                         (one product)
+//   Y = X p (right side) or p X (left side)                 (one product)
 // with s = ceil(sqrt(K)) and J = ceil(K / s) (K <= 256, so s, J <= 16): about
 // 2 sqrt(K) products instead of K - 1.  All matrices of the route are polynomials
 // in Ghat, hence symmetric in exact arithmetic, and the engine reads the second
@@ -490,7 +506,8 @@ int poly_choice(const cpa_opts* o, int m, int n) {
     const int s = poly_s_of(o->K), J = (o->K + s - 1) / s;
     if (o->eval == CPA_EVAL_POLYNOMIAL) return s;
     if (o->check) return 0;   // the growth check needs every ||Y_k||
-    const double d = std::min(m, n), e = std::max(m, n);
+    const bool right = right_side(o, m, n);
+    const double d = right ? n : m, e = right ? m : n;
     const double cost_poly = (double)(s - 1 + J - 1) * d * d * d + e * d * d;
     const double cost_rec = (double)(o->K - 1) * e * d * d;
     return cost_poly < cost_rec ? s : 0;
@@ -589,13 +606,13 @@ cpa_status enqueue_poly_core(cpa_ctx* ctx, hipStream_t st, int d, const float* G
 
 cpa_status enqueue_poly(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* X, int64_t ldx, float* Y,
                         int64_t ldy, int K, const Work& w, int precision) {
-    const int d = std::min(m, n);
+    const int d = w.d;
     float* F = nullptr;
     cpa_status r = enqueue_poly_core(ctx, st, d, w.G, d, w.scal, w.lay.ps(), w.poly, w.poly_s, K, precision, &F);
     if (r != CPA_OK) return r;
     // Y = X p (right) or p X (left); p read transposed (it is the fixed operand)
     const EpiLin e = lin_epi(Y, ldy, nullptr, 0, 1.f, 0.f, 0.f, 0.f);
-    if (m >= n)
+    if (w.right)
         return poly_gemm(ctx, st, make_op(X, ldx, m), make_op(F, d, n), m, n, n, e, precision, true);
     return poly_gemm(ctx, st, make_op(F, d, m), make_op(X, ldx, n), m, n, m, e, precision, false);
 }
@@ -621,7 +638,7 @@ cpa_status read_info(hipStream_t st, const Work& w, int K, int m, int n, cpa_inf
         info->max_growth = g;
         info->power_iters_done = (int)h[SC_ITERS];
         info->fallback = 0;
-        info->side = m >= n ? 0 : 1;
+        info->side = w.right ? 0 : 1;
         info->reserved = 0;
     }
     if (h[SC_TIMEOUT] != 0.0) return fail(CPA_ERR_HIP, "power iteration grid barrier timed out");
@@ -631,7 +648,7 @@ cpa_status read_info(hipStream_t st, const Work& w, int K, int m, int n, cpa_inf
 
 cpa_status shrink_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* X, int64_t ldx, float* Y,
                        int64_t ldy, const cpa_shrinkage* sh, const cpa_opts* o, cpa_info* info, const Work& w) {
-    const int d = std::min(m, n);
+    const int d = w.d;
     cpa_status s;
     if ((s = fill_scalars(st, w)) != CPA_OK) return s;
     if ((s = enqueue_gram(ctx, st, m, n, X, ldx, w)) != CPA_OK) return s;
@@ -995,6 +1012,19 @@ const char* cpa_status_string(cpa_status s) {
 
 const char* cpa_last_error(void) { return g_err; }
 
+cpa_status cpa_workspace_bytes(cpa_ctx* ctx, int m, int n, const cpa_opts* opts, size_t* bytes_host) {
+    cpa_status s;
+    if (!ctx || !bytes_host) return fail(CPA_ERR_ARG, "NULL argument");
+    if ((s = check_opts(opts)) != CPA_OK) return s;
+    if (m < 0 || n < 0) return fail(CPA_ERR_SHAPE, "negative size");
+    *bytes_host = 0;
+    if (m == 0 || n == 0) return CPA_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    Work w;
+    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    return ensure_ws(ctx, m, n, opts->K, maxit, false, w, right_side(opts, m, n), poly_choice(opts, m, n), bytes_host);
+}
+
 void cpa_default_opts(cpa_opts* o) {
     if (!o) return;
     std::memset(o, 0, sizeof(*o));
@@ -1010,7 +1040,7 @@ void cpa_default_opts(cpa_opts* o) {
     o->precision = CPA_PREC_FP32;
     o->growth_tol = 1e-3;
     o->eval = CPA_EVAL_AUTO;
-    o->reserved = 0;
+    o->side = CPA_SIDE_AUTO;
 }
 
 cpa_status cpa_chebyshev_coeffs(const cpa_shrinkage* shrink, double Lambda, int K, double* c_host) {
@@ -1039,11 +1069,11 @@ cpa_status cpa_spectral_bound(cpa_ctx* ctx, void* stream, int m, int n, const fl
     hipStream_t st = static_cast<hipStream_t>(stream);
     Work w;
     const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
-    if ((s = ensure_ws(ctx, m, n, opts->K, maxit, false, w)) != CPA_OK) return s;
+    if ((s = ensure_ws(ctx, m, n, opts->K, maxit, false, w, right_side(opts, m, n))) != CPA_OK) return s;
     cpa_shrinkage soft0 = {CPA_SOFT, 0, 0.0, 0.0, 0.0, 1.0};
     if ((s = fill_scalars(st, w)) != CPA_OK) return s;
     if ((s = enqueue_gram(ctx, st, m, n, X_dev, ldx, w)) != CPA_OK) return s;
-    if ((s = enqueue_bound(ctx, st, std::min(m, n), &soft0, opts, w, -1)) != CPA_OK) return s;
+    if ((s = enqueue_bound(ctx, st, w.d, &soft0, opts, w, -1)) != CPA_OK) return s;
     cpa_info tmp;
     if ((s = read_info(st, w, 1, m, n, &tmp, nullptr)) != CPA_OK) return s;
     *Lambda_host = tmp.Lambda;
@@ -1070,7 +1100,8 @@ cpa_status cpa_shrink_dense(cpa_ctx* ctx, void* stream, int m, int n, const floa
     hipStream_t st = static_cast<hipStream_t>(stream);
     Work w;
     const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
-    if ((s = ensure_ws(ctx, m, n, opts->K, maxit, false, w, poly_choice(opts, m, n))) != CPA_OK) return s;
+    if ((s = ensure_ws(ctx, m, n, opts->K, maxit, false, w, right_side(opts, m, n), poly_choice(opts, m, n))) != CPA_OK)
+        return s;
     return shrink_impl(ctx, st, m, n, X_dev, ldx, Y_dev, ldy, shrink, opts, info_host, w);
 }
 
@@ -1174,6 +1205,7 @@ cpa_status batched_shrink_args(const cpa_opts* opts, const float* X_dev, float* 
     cpa_status s;
     if ((s = check_opts(opts)) != CPA_OK) return s;
     if (opts->K > 64) return fail(CPA_ERR_ARG, "batched shrinkage supports K <= 64");
+    if (opts->side != CPA_SIDE_AUTO) return fail(CPA_ERR_UNSUPPORTED, "batched shrinkage takes the smaller Gram (side auto)");
 
     if (opts->check && !(opts->growth_tol >= 0.0)) return fail(CPA_ERR_ARG, "growth_tol must be >= 0");
     if (a.batch > 0 && !Y_dev) return fail(CPA_ERR_ARG, "NULL array");
@@ -1632,6 +1664,7 @@ cpa_status cpa_shrink_csr(cpa_ctx* ctx, void* stream, int m, int n, int64_t nnz,
                           const cpa_shrinkage* shrink, const cpa_opts* opts, cpa_info* info_host) {
     cpa_status s;
     if ((s = check_csr_args(ctx, m, n, nnz, rowptr_dev, colidx_dev, val_dev, Y_dev, ldy)) != CPA_OK) return s;
+    if (opts && opts->side == CPA_SIDE_LEFT) return fail(CPA_ERR_UNSUPPORTED, "sparse path forms S^T S (side right)");
     if ((s = check_shrinkage(shrink)) != CPA_OK) return s;
     if ((s = check_opts(opts)) != CPA_OK) return s;
     if (opts->precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "sparse path is FP32");
@@ -1670,6 +1703,7 @@ cpa_status cpa_svt_complete(cpa_ctx* ctx, void* stream, int m, int n, int64_t nn
                             float* X_dev, int64_t ldx, const cpa_opts* opts, double* resid_dev, double* k0_host) {
     cpa_status s;
     if ((s = check_csr_args(ctx, m, n, nnz, rowptr_dev, colidx_dev, Mobs_dev, X_dev, ldx)) != CPA_OK) return s;
+    if (opts && opts->side == CPA_SIDE_LEFT) return fail(CPA_ERR_UNSUPPORTED, "sparse path forms S^T S (side right)");
     if ((s = check_opts(opts)) != CPA_OK) return s;
     if (opts->precision != CPA_PREC_FP32 || opts->check) return fail(CPA_ERR_UNSUPPORTED, "unsupported option");
     if (!(std::isfinite(tau) && tau >= 0.0 && std::isfinite(delta) && delta > 0.0) || iters < 0)
@@ -1762,7 +1796,8 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
     hipStream_t st = static_cast<hipStream_t>(stream);
     Work w;
     const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
-    if ((s = ensure_ws(ctx, m, n, opts->K, maxit, true, w, poly_choice(opts, m, n))) != CPA_OK) return s;
+    if ((s = ensure_ws(ctx, m, n, opts->K, maxit, true, w, right_side(opts, m, n), poly_choice(opts, m, n))) != CPA_OK)
+        return s;
     AdmmPtrs P;
     P.l = state_dev;
     P.s = state_dev + mn;
@@ -1790,7 +1825,7 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
     int t = 0;
     // A cold power-iteration start is run directly; the captured graph always
     // takes the warm start (or the seeded start when warm starts are off).
-    const int d = std::min(m, n);
+    const int d = w.d;
     if (opts->bound == CPA_BOUND_POWER && opts->warm_start && ctx->warm_d != d) {
         if ((s = one_iteration(st)) != CPA_OK) return s;
         ++t;

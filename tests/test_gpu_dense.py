@@ -34,7 +34,7 @@ def _gram_lmax(X):
     return float(np.linalg.eigvalsh(G)[-1]) if G.size else 0.0
 
 
-def _run(X64, sh_c, K, Lam, ld=None, offset=0, ev="auto"):
+def _run(X64, sh_c, K, Lam, ld=None, offset=0, ev="auto", side="auto"):
     torch = _torch()
     cpa = _lib()
     m, n = X64.shape
@@ -44,13 +44,13 @@ def _run(X64, sh_c, K, Lam, ld=None, offset=0, ev="auto"):
     view.copy_(torch.from_numpy(X64.astype(np.float32)))
     bufd = buf.cuda()
     Xd = bufd[offset:offset + m * ld].view(m, ld)[:, :n]
-    Y, info = cpa.shrink_dense(Xd, sh_c, cpa.Opts(K=K, Lambda=Lam, eval=ev), info=True)
+    Y, info = cpa.shrink_dense(Xd, sh_c, cpa.Opts(K=K, Lambda=Lam, eval=ev, side=side), info=True)
     torch.cuda.synchronize()
     return Y.cpu().numpy().astype(np.float64), info
 
 
-def _case(m, n, K, kind, seed, ld=None, offset=0, ev="auto"):
-    print(f"case m={m} n={n} K={K} kind={kind} seed={seed} ld={ld} off={offset} eval={ev}", flush=True)
+def _case(m, n, K, kind, seed, ld=None, offset=0, ev="auto", side="auto"):
+    print(f"case m={m} n={n} K={K} kind={kind} seed={seed} ld={ld} off={offset} eval={ev} side={side}", flush=True)
     X = synth.as_f32_exact(synth.dense_lowrank(m, n, rank=min(4, m, n), noise=0.2, seed=seed))
     lmax = _gram_lmax(X)
     Lam = 1.01 * lmax
@@ -64,11 +64,11 @@ def _case(m, n, K, kind, seed, ld=None, offset=0, ev="auto"):
         wc, ws = 0.3 * tau * tau, 0.05 * lmax
         sh_o, sh_c = Shrinkage(3, 0.0, wc, ws, 1e-3), cpa.weighted_fn(wc, ws, 1e-3)
     ref = ocpa.cpa_shrink(X, sh_o, Lam, K)
-    got, info = _run(X, sh_c, K, Lam, ld=ld, offset=offset, ev=ev)
+    got, info = _run(X, sh_c, K, Lam, ld=ld, offset=offset, ev=ev, side=side)
     err = metrics.rel_fro(got, ref, X)
     print(f"  rel_fro={err:.3e}", flush=True)
     assert err <= TOL32, (m, n, K, kind, err)
-    assert info["side"] == (0 if m >= n else 1)
+    assert info["side"] == {"auto": 0 if m >= n else 1, "right": 0, "left": 1}[side]
     return err
 
 
@@ -265,3 +265,47 @@ def test_power_bound_large_d_reads_iterate_from_global():
     lam_g, _ = cpa.spectral_bound(torch.from_numpy(X).cuda(), cpa.Opts(K=8))
     print(f"d=4160 power bound: gpu {lam_g:.9e} oracle {lam_o:.9e}", flush=True)
     assert abs(lam_g - lam_o) <= 2e-6 * lam_o
+
+
+@pytest.mark.parametrize("ev", ["recurrence", "polynomial"])
+@pytest.mark.parametrize("shape,side", [((130, 70), "left"), ((70, 130), "right"), ((130, 70), "right"),
+                                        ((70, 130), "left"), ((64, 64), "left"), ((128, 192), "right")])
+def test_explicit_gram_side(ev, shape, side):
+    """X h(X^T X) = h(X X^T) X: forcing the larger Gram gives the same shrinkage
+    (within the FP32 bar) on both evaluation routes."""
+    m, n = shape
+    for kind in (0, 2):
+        _case(m, n, 20, kind, seed=8800 + m + 3 * n, ev=ev, side=side)
+
+
+def test_side_rejections():
+    torch = _torch()
+    cpa = _lib()
+    X = torch.ones((8, 4), device="cuda")
+    bad = cpa.Opts(K=4).to_c()
+    bad.side = 3
+    import ctypes
+    Y = torch.empty_like(X)
+    st = cpa.lib().cpa_shrink_dense(ctypes.c_void_p(cpa.context(0)), cpa._stream(X), 8, 4, ctypes.c_void_p(X.data_ptr()), 4,
+                                    ctypes.c_void_p(Y.data_ptr()), 4, ctypes.byref(cpa.soft(0.5)), ctypes.byref(bad), None)
+    assert st == 1   # CPA_ERR_ARG
+
+
+def test_workspace_bytes_query():
+    """The workspace query covers the Gram, both Y buffers and the polynomial
+    buffers of the route that runs, grows with the shape, and allocates nothing
+    the following shrink would not reuse."""
+    cpa = _lib()
+    rec = cpa.workspace_bytes(1024, 1024, cpa.Opts(K=30, eval="recurrence"))
+    poly = cpa.workspace_bytes(1024, 1024, cpa.Opts(K=30, eval="polynomial"))
+    small = cpa.workspace_bytes(256, 128, cpa.Opts(K=30))
+    d, mn = 1024, 1024 * 1024
+    assert rec >= 4 * (d * d + 2 * mn) + 8 * d
+    # s = 6, J = 5: T_1..T_6, R_0..R_4 and three Clenshaw buffers of d x d
+    assert poly >= rec + 4 * 14 * d * d
+    assert 4 * (128 * 128 + 2 * 256 * 128) <= small < rec
+    assert cpa.workspace_bytes(0, 5, cpa.Opts(K=4)) == 0
+    # the larger Gram (300 x 300 instead of 100 x 100) on the same route
+    left = cpa.workspace_bytes(300, 100, cpa.Opts(K=8, side="left", eval="recurrence"))
+    right = cpa.workspace_bytes(300, 100, cpa.Opts(K=8, eval="recurrence"))
+    assert left - right >= 4 * (300 * 300 - 100 * 100)
