@@ -1,0 +1,109 @@
+"""Sparsifying transform and component truncation of Algorithm 1 (oracle; test
+infrastructure only).
+
+Sec. III-B writes the shrinkage with an orthogonal forward transform T:
+  Phi = T B^T B T^T                                   (eq. sing_shrink_exact_sparse)
+  underline Phi_ij = Phi_ij if |Phi_ij| >= eps, else 0 (eq. threshold_components)
+  hat G(B) = B T^T hat H(underline Phi) T             (Algorithm 1, last step)
+with hat H by Algorithm 1's three-term recurrence (oracle.cpa.chebyshev_matrix_sum).
+The threshold is eps = K(|Phi|, k), the k-th largest entry of |Phi|
+(Sec. V, eq. recommendation_epsilon, where k is a fraction of n^2).
+
+Readings where the paper is silent:
+  * K(|underline Phi|, k) in eq. (recommendation_epsilon) is read as K(|Phi|, k):
+    the threshold is taken on the transformed Gram before truncation (the
+    truncated matrix cannot define its own threshold).
+  * entries equal to eps are kept (>=), so ties at the k-th value keep more
+    than k entries -- Phi is symmetric, so an off-diagonal k-th value always
+    brings its mirror entry (k or k + 1 entries are kept when no other values tie);
+  * m < n uses the transposed identity, hat G(B) = T^T hat H(T B B^T T^T) T B.
+  * the computed product T G T^T is symmetrised, (Phi + Phi^T)/2, before the
+    threshold: rounding makes it slightly asymmetric, and an entry and its mirror
+    could then land on different sides of eps and give a non-symmetric matrix.
+
+Transforms (forward, orthonormal rows):
+  dct_matrix(n)    D[k, j] = s_k cos(pi (2 j + 1) k / (2 n)), s_0 = sqrt(1/n),
+                   s_k = sqrt(2/n) (DCT-II)
+  block_dct(n, b)  kron(I_{n/b}, dct_matrix(b)): the b x b block DCT, b = 8 in the paper
+
+Pins (tests/test_oracle_sparsify.py): the DCT matrix equals scipy's orthonormal
+DCT-II and is orthogonal; without truncation (k = n^2) the result equals the
+T = Id shrinkage for every orthogonal T (an orthogonal similarity); with
+truncation it equals the spectral form built from an eigendecomposition of the
+truncated matrix; eps equals the k-th value of a full sort.  Parity: pinned.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import chebyshev
+from .cpa import chebyshev_matrix_sum
+
+
+def dct_matrix(n: int) -> np.ndarray:
+    """Orthonormal DCT-II matrix (rows are the basis functions; D @ x transforms x)."""
+    k = np.arange(n)[:, None]
+    j = np.arange(n)[None, :]
+    D = np.cos(math.pi * (2 * j + 1) * k / (2.0 * n))
+    D[0, :] *= math.sqrt(1.0 / n)
+    D[1:, :] *= math.sqrt(2.0 / n)
+    return D
+
+
+def block_dct(n: int, b: int = 8) -> np.ndarray:
+    """kron(I_{n/b}, D_b): the b x b block DCT of length-n vectors (n a multiple of b)."""
+    if n % b:
+        raise ValueError("n must be a multiple of the block size")
+    return np.kron(np.eye(n // b), dct_matrix(b))
+
+
+def transformed_gram(B: np.ndarray, T: np.ndarray):
+    """Algorithm 1 step 1: (Phi, side) with Phi = T B^T B T^T (m >= n, 'right') or
+    T B B^T T^T (m < n, 'left')."""
+    B = np.asarray(B, dtype=np.float64)
+    m, n = B.shape
+    G = B.T @ B if m >= n else B @ B.T
+    Phi = T @ G @ T.T
+    # exactly symmetric, like the true Phi: otherwise an entry and its mirror can
+    # fall on different sides of the threshold
+    return 0.5 * (Phi + Phi.T), ("right" if m >= n else "left")
+
+
+def kth_largest_abs(Phi: np.ndarray, k: int) -> float:
+    """K(|Phi|, k): the k-th largest entry of |Phi| (1 <= k <= Phi.size)."""
+    a = np.abs(np.asarray(Phi, dtype=np.float64)).ravel()
+    if not 1 <= k <= a.size:
+        raise ValueError("k out of range")
+    return float(np.partition(a, a.size - k)[a.size - k])
+
+
+def truncate(Phi: np.ndarray, eps: float) -> np.ndarray:
+    """eq. (threshold_components): keep the entries with |Phi_ij| >= eps."""
+    Phi = np.asarray(Phi, dtype=np.float64)
+    return np.where(np.abs(Phi) >= eps, Phi, 0.0)
+
+
+def keep_count(n: int, fraction: float) -> int:
+    """k for a kept fraction of the n x n entries (eq. recommendation_epsilon writes
+    k = f n^2): ceil(f n^2), at least 1."""
+    return max(1, int(math.ceil(fraction * n * n)))
+
+
+def cpa_shrink_sparsified(B: np.ndarray, shrink, Lambda: float, K: int, T: np.ndarray, k: int):
+    """hat G(B) by Algorithm 1 with transform T and threshold eps = K(|Phi|, k).
+    Lambda must bound the largest eigenvalue of the truncated matrix; it is taken
+    as given.  Returns (result, eps, kept entries)."""
+    B = np.asarray(B, dtype=np.float64)
+    m, n = B.shape
+    Phi, side = transformed_gram(B, T)
+    eps = kth_largest_abs(Phi, k)
+    Phil = truncate(Phi, eps)
+    nnz = int(np.count_nonzero(np.abs(Phi) >= eps))
+    if Lambda <= 0.0:
+        return np.zeros((m, n)), eps, nnz
+    c = chebyshev.coefficients_shifted(shrink, Lambda, K)
+    H = chebyshev_matrix_sum(Phil, c, Lambda)
+    M = T.T @ H @ T
+    return (B @ M if side == "right" else M @ B), eps, nnz

@@ -1,0 +1,125 @@
+"""Pins for the oracle's sparsified Algorithm 1 (transform T, truncation eps):
+each check compares it with something fixed independently of its own code --
+scipy's DCT, the T = Id shrinkage (an orthogonal similarity leaves the result
+unchanged), an eigendecomposition of the truncated matrix, a full sort."""
+import math
+
+import numpy as np
+import pytest
+import scipy.fft
+
+import synth
+from oracle import chebyshev, cpa, sparsify
+from oracle.shrinkage import Shrinkage
+
+
+@pytest.mark.parametrize("n", [1, 2, 8, 16, 40])
+def test_dct_matrix_is_scipys_orthonormal_dct2(n):
+    D = sparsify.dct_matrix(n)
+    ref = scipy.fft.dct(np.eye(n), type=2, norm="ortho", axis=0)
+    assert np.allclose(D, ref, atol=1e-14)
+    assert np.allclose(D @ D.T, np.eye(n), atol=1e-13)
+
+
+def test_block_dct_transforms_each_block():
+    n = 48
+    T = sparsify.block_dct(n, 8)
+    x = np.random.default_rng(3).standard_normal(n)
+    ref = np.concatenate([scipy.fft.dct(x[i:i + 8], type=2, norm="ortho") for i in range(0, n, 8)])
+    assert np.allclose(T @ x, ref, atol=1e-13)
+    assert np.allclose(T @ T.T, np.eye(n), atol=1e-13)
+    with pytest.raises(ValueError):
+        sparsify.block_dct(20, 8)
+
+
+def test_kth_largest_matches_a_full_sort():
+    A = np.random.default_rng(4).standard_normal((13, 11))
+    s = np.sort(np.abs(A).ravel())[::-1]
+    for k in (1, 2, 7, 50, A.size):
+        assert sparsify.kth_largest_abs(A, k) == s[k - 1]
+    assert sparsify.keep_count(1000, 0.5e-4) == 50
+    assert sparsify.keep_count(10, 1e-9) == 1
+
+
+@pytest.mark.parametrize("shape", [(40, 24), (24, 40)])
+@pytest.mark.parametrize("which", ["dct", "block"])
+def test_without_truncation_any_orthogonal_transform_gives_the_plain_shrinkage(shape, which):
+    m, n = shape
+    B = synth.dense_lowrank(m, n, rank=4, noise=0.1, seed=5 + m)
+    d = min(m, n)
+    T = sparsify.dct_matrix(d) if which == "dct" else sparsify.block_dct(d, 8)
+    G = B.T @ B if m >= n else B @ B.T
+    lam = 1.01 * float(np.linalg.eigvalsh(G)[-1])
+    sh = Shrinkage(0, 0.3 * math.sqrt(lam))
+    Y, eps, nnz = sparsify.cpa_shrink_sparsified(B, sh, lam, 12, T, d * d)
+    ref = cpa.cpa_shrink(B, sh, lam, 12)
+    assert nnz == d * d
+    assert np.abs(Y - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def _spectral_reference(B, T, k, sh, K):
+    """The same result from an eigendecomposition of the truncated matrix:
+    B T^T V diag(hat h(lambda)) V^T T (right side), hat h evaluated by the scalar
+    recurrence at 2 lambda / Lambda - 1."""
+    m, n = B.shape
+    G = B.T @ B if m >= n else B @ B.T
+    Phi = T @ G @ T.T
+    Phi = 0.5 * (Phi + Phi.T)
+    a = np.sort(np.abs(Phi).ravel())[::-1]
+    eps = a[k - 1]
+    Phil = np.where(np.abs(Phi) >= eps, Phi, 0.0)
+    lam, V = np.linalg.eigh(Phil)
+    Lam = 1.01 * float(lam[-1])
+    c = chebyshev.coefficients_shifted(sh, Lam, K)
+    x = 2.0 * lam / Lam - 1.0
+    hh = 0.5 * c[0] + sum(c[j] * chebyshev.cheb_recurrence(j, x) for j in range(1, K))
+    M = T.T @ (V * hh) @ V.T @ T
+    return (B @ M if m >= n else M @ B), Lam, eps, int(np.count_nonzero(np.abs(Phi) >= eps))
+
+
+def block_smooth(m, n, rank, noise, seed):
+    """m x n data whose Gram side varies only between 8-blocks (plus noise): its
+    block-DCT transformed Gram is concentrated on the blocks' DC entries, the
+    kind of input the truncation is meant for."""
+    g = np.random.default_rng(seed)
+    d = min(m, n)
+    smooth = np.repeat(g.standard_normal((d // 8, rank)), 8, axis=0)      # d x rank
+    other = g.standard_normal((rank, max(m, n)))
+    B = (smooth @ other).T if m >= n else smooth @ other
+    return B + noise * g.standard_normal((m, n))
+
+
+@pytest.mark.parametrize("shape", [(64, 32), (32, 64)])
+@pytest.mark.parametrize("frac", [0.02, 0.1, 0.4])
+def test_truncated_shrinkage_matches_spectral_form(shape, frac):
+    m, n = shape
+    B = block_smooth(m, n, rank=3, noise=1e-3, seed=17 + m)
+    d = min(m, n)
+    T = sparsify.block_dct(d, 8)
+    k = sparsify.keep_count(d, frac)
+    sh = Shrinkage(3, 0.0, 2.0, 0.5, 1e-3)
+    ref, Lam, eps_ref, nnz_ref = _spectral_reference(B, T, k, sh, 16)
+    Y, eps, nnz = sparsify.cpa_shrink_sparsified(B, sh, Lam, 16, T, k)
+    # Phi is symmetric: the k-th value's mirror entry ties with it and is kept too
+    assert eps == eps_ref and nnz == nnz_ref and k <= nnz <= k + 1
+    # the truncated spectrum stays (up to the dropped noise) inside [0, Lambda]
+    G = B.T @ B if m >= n else B @ B.T
+    Phil = sparsify.truncate(0.5 * (T @ G @ T.T + (T @ G @ T.T).T), eps)
+    assert np.array_equal(Phil, Phil.T)
+    lam = np.linalg.eigvalsh(Phil)
+    assert lam[0] >= -1e-3 * lam[-1]
+    assert np.abs(Y - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_transform_order_matters_under_truncation():
+    """With truncation the result depends on applying T (not T^T) to the Gram:
+    swapping them changes it, so the pins above see that order."""
+    B = synth.dense_lowrank(64, 32, rank=3, noise=0.05, seed=99)
+    T = sparsify.dct_matrix(32)
+    k = sparsify.keep_count(32, 0.05)
+    G = B.T @ B
+    Lam = 1.01 * float(np.linalg.eigvalsh(G)[-1])
+    sh = Shrinkage(0, 0.2 * math.sqrt(Lam))
+    Y1, _, _ = sparsify.cpa_shrink_sparsified(B, sh, Lam, 10, T, k)
+    Y2, _, _ = sparsify.cpa_shrink_sparsified(B, sh, Lam, 10, T.T.copy(), k)
+    assert np.abs(Y1 - Y2).max() > 1e-3 * np.abs(Y1).max()
