@@ -278,6 +278,37 @@ cpa_status cpa_shrink_batched(cpa_ctx* ctx, void* stream, int batch, const int32
                               const cpa_opts* opts, const double* Lambda_dev, double* Lambda_out_dev,
                               int32_t* status_dev);
 
+/* ---- Sparsified shrinkage (Sec. III-B, Algorithm 1 with a transform and
+ * truncation).  The Gram G (side as opts->side) is transformed,
+ * Phi = T G T^T (eq. sing_shrink_exact_sparse), its entries below
+ * eps = the keep-th largest |Phi_ij| are set to zero (eq. threshold_components;
+ * entries equal to eps are kept, so an off-diagonal keep-th value also keeps its
+ * mirror), the bound and the coefficients are taken from the truncated matrix,
+ * hat H is formed by Algorithm 1's recurrence with the truncated matrix stored
+ * sparse (one sparse-dense product per step), and Y = X T^T hat H T (or
+ * T^T hat H T X on the left side).  Phi is formed exactly symmetric (FP64
+ * transform of the FP32 Gram, upper tiles mirrored).
+ *   transform: CPA_TRANSFORM_BLOCK_DCT8 (the 8 x 8 block DCT, T = kron(I, D_8)) or
+ *              CPA_TRANSFORM_IDENTITY (truncation of the Gram itself).
+ *   keep: 1 <= keep <= d^2 (d: the Gram side, a multiple of 8).
+ * FP32, check = 0 only; eval is not used.  eps_host and nnz_host (nullable)
+ * receive the threshold and the number of kept entries (synchronising).
+ * The truncated matrix need not be positive semidefinite: its spectrum can leave
+ * [0, Lambda] on the negative side, where Chebyshev series grow, so the keep
+ * count must retain the transform's significant entries. */
+typedef enum { CPA_TRANSFORM_IDENTITY = 0, CPA_TRANSFORM_BLOCK_DCT8 = 1 } cpa_transform;
+
+typedef struct {
+    int32_t transform;  /* cpa_transform */
+    int32_t reserved;   /* must be 0 */
+    int64_t keep;       /* entries of |Phi| at or above the threshold: eps = keep-th largest */
+} cpa_sparsify;
+
+cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n, const float* X_dev, int64_t ldx,
+                                       float* Y_dev, int64_t ldy, const cpa_shrinkage* shrink, const cpa_opts* opts,
+                                       const cpa_sparsify* sparsify, cpa_info* info_host, double* eps_host,
+                                       int64_t* nnz_host);
+
 /* ---- Batched plans: the batched shrink as one captured graph, tuned once.
  * Not in the paper (it shrinks one matrix at a time); the per-matrix
  * computation is exactly that of cpa_shrink_batched.

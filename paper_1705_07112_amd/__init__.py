@@ -59,6 +59,13 @@ class CpaError(RuntimeError):
         self.status = status
 
 
+class CpaSparsify(ctypes.Structure):
+    _fields_ = [("transform", ctypes.c_int32), ("reserved", ctypes.c_int32), ("keep", ctypes.c_int64)]
+
+
+TRANSFORM_IDENTITY, TRANSFORM_BLOCK_DCT8 = 0, 1
+
+
 class CpaBatchedTuning(ctypes.Structure):
     _fields_ = [("grid", ctypes.c_int32), ("pair", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("candidates", ctypes.c_int32), ("best_us", ctypes.c_double), ("default_us", ctypes.c_double)]
@@ -96,6 +103,10 @@ _SIGS = {
     "cpa_shrink_batched": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.POINTER(CpaShrinkage),
                                           ctypes.POINTER(CpaOpts), _P, _P, _P]),
     "cpa_batched_features": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P]),
+    "cpa_shrink_dense_sparsified": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _I64, _P, _I64,
+                                                   ctypes.POINTER(CpaShrinkage), ctypes.POINTER(CpaOpts),
+                                                   ctypes.POINTER(CpaSparsify), ctypes.POINTER(CpaInfo),
+                                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     "cpa_batched_plan_create": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P,
                                                ctypes.POINTER(CpaShrinkage), ctypes.POINTER(CpaOpts), _P, _P, _P,
                                                ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
@@ -269,6 +280,36 @@ def spectral_bound(X, opts: Opts):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def shrink_dense_sparsified(X, shrink: CpaShrinkage, opts: Opts, keep: int, transform: str = "block_dct8",
+                            out=None, info: bool = False):
+    """Algorithm 1 with a transform and truncation (see cpa_shrink_dense_sparsified):
+    Phi = T G T^T, entries below the keep-th largest |Phi| dropped.  Returns Y, or
+    (Y, info dict with 'eps' and 'nnz' added)."""
+    import torch
+    m, n, ldx = _mat(X, "X")
+    if out is None:
+        out = torch.empty((m, n), device=X.device, dtype=torch.float32)
+    _, _, ldy = _mat(out, "out")
+    if tuple(out.shape) != (m, n):
+        raise ValueError("out has the wrong shape")
+    sp = CpaSparsify({"identity": TRANSFORM_IDENTITY, "block_dct8": TRANSFORM_BLOCK_DCT8}[transform], 0, int(keep))
+    ci = CpaInfo()
+    eps = ctypes.c_double()
+    nnz = ctypes.c_int64()
+    co = opts.to_c()
+    _check(lib().cpa_shrink_dense_sparsified(ctypes.c_void_p(context(X.device.index or 0)), _stream(X), m, n,
+                                             ctypes.c_void_p(X.data_ptr()), ldx, ctypes.c_void_p(out.data_ptr()), ldy,
+                                             ctypes.byref(shrink), ctypes.byref(co), ctypes.byref(sp),
+                                             ctypes.byref(ci) if info else None, ctypes.byref(eps) if info else None,
+                                             ctypes.byref(nnz) if info else None))
+    if not info:
+        return out
+    d = ci.as_dict()
+    d["eps"] = eps.value
+    d["nnz"] = nnz.value
+    return out, d
 
 
 def shrink_batched(X, m, n, off, shrink, opts: Opts, shrink_per_matrix=None, Lambda=None, out=None,

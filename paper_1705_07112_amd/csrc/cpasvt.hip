@@ -19,6 +19,7 @@
 #include "admm.hpp"
 #include "batched.hpp"
 #include "sparse.hpp"
+#include "sparsify.hpp"
 #include "gemm_bf16x3.hpp"
 #include "gemm_f32.hpp"
 #include "gemm_lds.hpp"
@@ -69,6 +70,8 @@ struct cpa_ctx {
     int warm_cap = 0;
     int warm_d = -1;           // length of the stored vector, -1 if none
     int coop_max = 0;          // co-resident power-iteration workgroups (0: not queried)
+    void* spf = nullptr;       // sparsified path: Phi, CSR of the truncated matrix, Psi buffers, H, M, selection state
+    size_t spf_bytes = 0;
     int batch_per_cu = 0;      // co-resident workgroups of the batched kernel per CU (0: not queried)
     int cus = 0;
     int* queue = nullptr;      // work-queue counter of the batched kernel
@@ -988,6 +991,7 @@ cpa_status cpa_destroy(cpa_ctx* ctx) {
         for (hipEvent_t e : L.ev) (void)hipEventDestroy(e);
     if (ctx->admm_exec) (void)hipGraphExecDestroy(ctx->admm_exec);
     if (ctx->queue) (void)hipFree(ctx->queue);
+    if (ctx->spf) (void)hipFree(ctx->spf);
     if (ctx->mlp_ws) (void)hipFree(ctx->mlp_ws);
     if (ctx->sws) (void)hipFree(ctx->sws);
     if (ctx->csc) (void)hipFree(ctx->csc);
@@ -1909,6 +1913,203 @@ cpa_status cpa_peak_mfma(cpa_ctx* ctx, void* stream, int kind, int iters, double
     if (s != CPA_OK) return s;
     const double flop = (double)grid * 4 /* waves */ * iters * kPeakChains * (kind == 0 ? 2048.0 : 16384.0);
     *tflops_host = flop / (1e-3 * ms) / 1e12;
+    return CPA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// 8 x 8 transform table: the orthonormal DCT-II, D[a][i] = s_a cos(pi (2i + 1) a / 16),
+// s_0 = sqrt(1/8), s_a = 1/2; or the identity.
+Dct8 transform_table(int transform) {
+    Dct8 t;
+    for (int a = 0; a < 8; ++a)
+        for (int i = 0; i < 8; ++i) {
+            if (transform == CPA_TRANSFORM_BLOCK_DCT8)
+                t.d[8 * a + i] = (a == 0 ? std::sqrt(1.0 / 8.0) : 0.5) * std::cos(M_PI * (2 * i + 1) * a / 16.0);
+            else
+                t.d[8 * a + i] = (a == i) ? 1.0 : 0.0;
+        }
+    return t;
+}
+
+struct SpfWork {
+    float* Phi;      // d x d: Phi, then the dense truncated matrix
+    int32_t* cnt;    // d
+    int32_t* rowptr; // d + 1
+    int32_t* colidx; // d^2 (capacity)
+    float* val;      // d^2
+    float* P[2];     // Psi ping-pong, d x d
+    float* H;        // d x d
+    float* M;        // d x d
+    unsigned* hist;  // kSelBins
+    SelState* sel;
+};
+
+cpa_status ensure_spf(cpa_ctx* ctx, int d, SpfWork& s) {
+    const size_t dd = (size_t)d * d;
+    size_t off = 0;
+    const size_t oPhi = off; off = align_up(off + sizeof(float) * dd);
+    const size_t oC = off; off = align_up(off + sizeof(int32_t) * d);
+    const size_t oR = off; off = align_up(off + sizeof(int32_t) * (d + 1));
+    const size_t oI = off; off = align_up(off + sizeof(int32_t) * dd);
+    const size_t oV = off; off = align_up(off + sizeof(float) * dd);
+    const size_t oP0 = off; off = align_up(off + sizeof(float) * dd);
+    const size_t oP1 = off; off = align_up(off + sizeof(float) * dd);
+    const size_t oH = off; off = align_up(off + sizeof(float) * dd);
+    const size_t oM = off; off = align_up(off + sizeof(float) * dd);
+    const size_t oHi = off; off = align_up(off + sizeof(unsigned) * kSelBins);
+    const size_t oS = off; off = align_up(off + sizeof(SelState));
+    if (off > ctx->spf_bytes) {
+        if (ctx->spf) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipFree(ctx->spf));
+            ctx->spf = nullptr;
+            ctx->spf_bytes = 0;
+        }
+        if (hipMalloc(&ctx->spf, off) != hipSuccess) {
+            ctx->spf = nullptr;
+            return fail(CPA_ERR_ALLOC, "sparsified-path workspace allocation of %zu bytes failed", off);
+        }
+        ctx->spf_bytes = off;
+    }
+    char* b = static_cast<char*>(ctx->spf);
+    s.Phi = reinterpret_cast<float*>(b + oPhi);
+    s.cnt = reinterpret_cast<int32_t*>(b + oC);
+    s.rowptr = reinterpret_cast<int32_t*>(b + oR);
+    s.colidx = reinterpret_cast<int32_t*>(b + oI);
+    s.val = reinterpret_cast<float*>(b + oV);
+    s.P[0] = reinterpret_cast<float*>(b + oP0);
+    s.P[1] = reinterpret_cast<float*>(b + oP1);
+    s.H = reinterpret_cast<float*>(b + oH);
+    s.M = reinterpret_cast<float*>(b + oM);
+    s.hist = reinterpret_cast<unsigned*>(b + oHi);
+    s.sel = reinterpret_cast<SelState*>(b + oS);
+    return CPA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n, const float* X_dev, int64_t ldx,
+                                       float* Y_dev, int64_t ldy, const cpa_shrinkage* shrink, const cpa_opts* opts,
+                                       const cpa_sparsify* sp, cpa_info* info_host, double* eps_host,
+                                       int64_t* nnz_host) {
+    cpa_status s;
+    if ((s = check_dense_args(ctx, m, n, X_dev, ldx)) != CPA_OK) return s;
+    if ((s = check_opts(opts)) != CPA_OK) return s;
+    if ((s = check_shrinkage(shrink)) != CPA_OK) return s;
+    if (!sp) return fail(CPA_ERR_ARG, "sparsify is NULL");
+    if (sp->transform != CPA_TRANSFORM_IDENTITY && sp->transform != CPA_TRANSFORM_BLOCK_DCT8)
+        return fail(CPA_ERR_ARG, "unknown transform %d", sp->transform);
+    if (sp->reserved != 0) return fail(CPA_ERR_ARG, "sparsify.reserved must be 0");
+    if (opts->check) return fail(CPA_ERR_UNSUPPORTED, "the growth check is not available on the sparsified path");
+    if (opts->precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "the sparsified path is FP32");
+    if (m == 0 || n == 0) {
+        if (info_host) std::memset(info_host, 0, sizeof(*info_host));
+        if (eps_host) *eps_host = 0.0;
+        if (nnz_host) *nnz_host = 0;
+        return CPA_OK;
+    }
+    if (!Y_dev) return fail(CPA_ERR_ARG, "Y is NULL");
+    if (ldy < n) return fail(CPA_ERR_SHAPE, "ldy < n");
+    const bool right = right_side(opts, m, n);
+    const int d = right ? n : m;
+    if (d % 8 != 0) return fail(CPA_ERR_SHAPE, "the Gram side (%d) must be a multiple of 8 (8 x 8 tiles)", d);
+    if (sp->keep < 1 || sp->keep > (int64_t)d * d) return fail(CPA_ERR_ARG, "keep must be in [1, d^2]");
+    if ((int64_t)d * d > INT32_MAX) return fail(CPA_ERR_SHAPE, "Gram too large for 32-bit indices");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Work w;
+    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    if ((s = ensure_ws(ctx, m, n, opts->K, maxit, false, w, right, 0)) != CPA_OK) return s;
+    SpfWork f;
+    if ((s = ensure_spf(ctx, d, f)) != CPA_OK) return s;
+    const Dct8 D = transform_table(sp->transform);
+    const int nt = d / 8;
+
+    if ((s = fill_scalars(st, w)) != CPA_OK) return s;
+    if ((s = enqueue_gram(ctx, st, m, n, X_dev, ldx, w)) != CPA_OK) return s;
+    // Phi = T G T^T (exactly symmetric)
+    hipLaunchKernelGGL(bt_forward_kernel, dim3(nt * (nt + 1) / 2), dim3(64), 0, st, d, (const float*)w.G,
+                       (int64_t)d, f.Phi, (int64_t)d, D);
+    HIP_TRY(hipGetLastError());
+    // eps = the keep-th largest |Phi|
+    hipLaunchKernelGGL(sel_init_kernel, dim3(1), dim3(256), 0, st, f.sel, (uint32_t)sp->keep, f.hist);
+    HIP_TRY(hipGetLastError());
+    const int gh = (int)std::min<int64_t>(1024, ((int64_t)d * d + 255) / 256);
+    for (int pass = 0; pass < 3; ++pass) {
+        hipLaunchKernelGGL(sel_hist_kernel, dim3(gh), dim3(256), 0, st, d, (const float*)f.Phi, (int64_t)d, pass,
+                           (const SelState*)f.sel, f.hist);
+        HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(sel_pick_kernel, dim3(1), dim3(256), 0, st, pass, f.sel, f.hist);
+        HIP_TRY(hipGetLastError());
+    }
+    // the truncated matrix: CSR, and dense in place
+    const int gr = (d + 3) / 4;
+    hipLaunchKernelGGL(trunc_count_kernel, dim3(gr), dim3(256), 0, st, d, (const float*)f.Phi, (int64_t)d,
+                       (const SelState*)f.sel, f.cnt);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(csc_scan_kernel, dim3(1), dim3(SP_THREADS), 0, st, d, (const int32_t*)f.cnt, f.rowptr);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(trunc_fill_kernel, dim3(gr), dim3(256), 0, st, d, f.Phi, (int64_t)d, (const SelState*)f.sel,
+                       (const int32_t*)f.rowptr, f.colidx, f.val);
+    HIP_TRY(hipGetLastError());
+
+    // bound and coefficients from the (dense) truncated matrix
+    Work wb = w;
+    wb.G = f.Phi;
+    if ((s = enqueue_bound(ctx, st, d, shrink, opts, wb, -1)) != CPA_OK) return s;
+    if (opts->K == 1) {
+        // hat H = c_0/2 I, and T^T (c_0/2 I) T = c_0/2 I: Y = c_0/2 X
+        if ((s = enqueue_recurrence(ctx, st, m, n, X_dev, ldx, Y_dev, ldy, 1, w, false, CPA_PREC_FP32)) != CPA_OK)
+            return s;
+    } else {
+        // hat H: Psi_0 = I, Psi_{k+1} = 2 ((2/Lambda) Phi_ Psi_k - Psi_k) - Psi_{k-1}, H = sum c_k Psi_k
+        const int ge = (int)std::min<int64_t>(4096, ((int64_t)d * d + 255) / 256);
+        hipLaunchKernelGGL(eye_kernel, dim3(ge), dim3(256), 0, st, d, f.P[0], (int64_t)d);
+        HIP_TRY(hipGetLastError());
+        const int grid_c = ((d + SP_WAVES - 1) / SP_WAVES) * ((d + SPC_J - 1) / SPC_J);
+        int cur = 0;
+        for (int k = 0; k + 1 <= opts->K - 1; ++k) {
+            const float* yk = f.P[cur];
+            float* yo = f.P[cur ^ 1];   // Psi_{k-1} (unused at k = 0), overwritten by Psi_{k+1}
+            hipLaunchKernelGGL(spmm_cheb_kernel, dim3(grid_c), dim3(SP_THREADS), 0, st, d, d,
+                               (const int32_t*)f.rowptr, (const int32_t*)f.colidx, (const float*)f.val, yk, (int64_t)d,
+                               yk, (const float*)yo, yo, (int64_t)d, f.H, (int64_t)d, (const double*)w.scal, k,
+                               (k + 1 == opts->K - 1) ? 1 : 0, 1);
+            HIP_TRY(hipGetLastError());
+            cur ^= 1;
+        }
+        // M = T^T hat H T, then Y = X M (right) or M X (left)
+        hipLaunchKernelGGL(bt_inverse_kernel, dim3(nt * nt), dim3(64), 0, st, d, (const float*)f.H, (int64_t)d,
+                           f.M, (int64_t)d, D);
+        HIP_TRY(hipGetLastError());
+        const EpiLin e = lin_epi(Y_dev, ldy, nullptr, 0, 1.f, 0.f, 0.f, 0.f);
+        if (right)
+            s = poly_gemm(ctx, st, make_op(X_dev, ldx, m), make_op(f.M, d, n), m, n, n, e, CPA_PREC_FP32, true);
+        else
+            s = poly_gemm(ctx, st, make_op(f.M, d, m), make_op(X_dev, ldx, n), m, n, m, e, CPA_PREC_FP32, false);
+        if (s != CPA_OK) return s;
+    }
+    if (info_host) {
+        if ((s = read_info(st, w, opts->K, m, n, info_host, nullptr)) != CPA_OK) return s;
+    }
+    if (eps_host || nnz_host) {
+        SelState hs;
+        int32_t nnz = 0;
+        HIP_TRY(hipMemcpyAsync(&hs, f.sel, sizeof(hs), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(&nnz, f.rowptr + d, sizeof(nnz), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (eps_host) {
+            float e;
+            std::memcpy(&e, &hs.prefix, sizeof(e));
+            *eps_host = (double)e;
+        }
+        if (nnz_host) *nnz_host = nnz;
+    }
     return CPA_OK;
 }
 

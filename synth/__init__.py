@@ -115,6 +115,20 @@ def patch_groups(batch: int = 8192, rows: int = 64, ncol_lo: int = 40, ncol_hi: 
     return out, ms, ncols, offsets[:-1].copy(), ranks, noises
 
 
+def block_smooth(m: int, n: int, rank: int = 3, noise: float = 1e-3, seed: int = BASE_SEED) -> np.ndarray:
+    """m x n data that varies only between 8-blocks along its shorter side (the
+    side of its Gram), plus N(0, noise^2): a rank-`rank` product whose factor on
+    that side is piecewise constant over 8 entries.  Its 8 x 8 block-DCT
+    transformed Gram is concentrated on the blocks' DC entries -- the kind of
+    input the transform-and-truncate form of the shrinkage is meant for.  FP64."""
+    g = rng(seed)
+    d = min(m, n)
+    smooth = np.repeat(g.standard_normal((max(d // 8, 1), rank)), 8, axis=0)[:d]   # d x rank
+    other = g.standard_normal((rank, max(m, n)))
+    B = (smooth @ other).T if m >= n else smooth @ other
+    return B + noise * g.standard_normal((m, n))
+
+
 def block_matrix_D(size: int = 1000, nblocks: int = 10) -> np.ndarray:
     """D = J - blkdiag(0.5 * 1_b 1_b^T, repeated nblocks times), b = size / nblocks."""
     b = size // nblocks

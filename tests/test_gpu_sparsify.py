@@ -1,0 +1,147 @@
+"""Sparsified shrinkage (Algorithm 1 with the 8 x 8 block DCT or the identity and
+component truncation) against the FP64 oracle.  The keep counts sit at a clear
+gap in |Phi| (the kept and the first dropped magnitude differ by more than 2%),
+so the truncation keeps the same entries in the kernel's FP32 and the oracle's
+FP64; the threshold and the kept count are compared, then the result."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import bound as obound
+from oracle import cpa as ocpa
+from oracle import metrics, sparsify
+from oracle.shrinkage import Shrinkage
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+
+def _lib():
+    import paper_1705_07112_amd as cpa
+    return cpa
+
+
+def _gap_keep(Phi, frac):
+    """A keep count near frac * d^2 at a gap of more than 2% in the sorted |Phi|."""
+    a = np.sort(np.abs(Phi).ravel())[::-1]
+    target = max(1, int(frac * a.size))
+    ratio = a[:-1] / np.maximum(a[1:], 1e-300)
+    cand = np.nonzero(ratio > 1.02)[0]
+    j = cand[np.argmin(np.abs(cand + 1 - target))]
+    return int(j + 1)
+
+
+def _case(X, T, transform, frac, K, sh_o, sh_c, side_right=True):
+    import torch
+    cpa = _lib()
+    m, n = X.shape
+    Phi, _ = sparsify.transformed_gram(X, T)
+    keep = _gap_keep(Phi, frac) if frac < 1.0 else Phi.size
+    eps_o = sparsify.kth_largest_abs(Phi, keep)
+    Phil = sparsify.truncate(Phi, eps_o)
+    lam = 1.01 * float(np.linalg.eigvalsh(Phil)[-1])
+    ref, _, nnz_o = sparsify.cpa_shrink_sparsified(X, sh_o, lam, K, T, keep)
+    Xd = torch.from_numpy(X.astype(np.float32)).cuda()
+    Y, info = cpa.shrink_dense_sparsified(Xd, sh_c, cpa.Opts(K=K, Lambda=lam), keep=keep, transform=transform,
+                                          info=True)
+    torch.cuda.synchronize()
+    err = metrics.rel_fro(Y.cpu().numpy().astype(np.float64), ref, X)
+    print(f"sparsified {transform} {m}x{n} K={K} keep={keep} nnz={info['nnz']} (oracle {nnz_o}) "
+          f"eps={info['eps']:.6e} (oracle {eps_o:.6e}) rel_fro={err:.3e}", flush=True)
+    assert info["nnz"] == nnz_o
+    # FP32 Gram: absolute rounding on the scale of the largest entry of Phi
+    assert abs(info["eps"] - eps_o) <= 1e-6 * float(np.abs(Phi).max())
+    assert info["side"] == (0 if side_right else 1)
+    assert err <= TOL32
+    return Y
+
+
+@pytest.mark.parametrize("shape,frac,K,kind", [((256, 128), 0.02, 20, 0), ((128, 256), 0.02, 20, 0),
+                                               ((512, 512), 0.01, 30, 3), ((320, 64), 0.1, 16, 1),
+                                               ((64, 192), 0.05, 8, 0)])
+def test_block_dct_truncated_matches_oracle(shape, frac, K, kind):
+    cpa = _lib()
+    m, n = shape
+    X = synth.as_f32_exact(synth.block_smooth(m, n, rank=4, noise=1e-3, seed=9100 + m + n))
+    d = min(m, n)
+    T = sparsify.block_dct(d, 8)
+    G = X.T @ X if m >= n else X @ X.T
+    s1 = math.sqrt(float(np.linalg.eigvalsh(G)[-1]))
+    if kind == 0:
+        sh_o, sh_c = Shrinkage(0, 0.2 * s1), cpa.soft(0.2 * s1)
+    elif kind == 1:
+        sh_o, sh_c = Shrinkage(1, 0.2 * s1), cpa.hard(0.2 * s1)
+    else:
+        wc, ws = 0.05 * s1 * s1, 0.01 * s1 * s1
+        sh_o, sh_c = Shrinkage(3, 0.0, wc, ws, 1e-3), cpa.weighted_fn(wc, ws, 1e-3)
+    _case(X, T, "block_dct8", frac, K, sh_o, sh_c, side_right=m >= n)
+
+
+@pytest.mark.parametrize("transform", ["block_dct8", "identity"])
+def test_no_truncation_equals_plain_shrinkage(transform):
+    """keep = d^2: T^T hat H(T G T^T) T = hat H(G) for orthogonal T."""
+    import torch
+    cpa = _lib()
+    X = synth.as_f32_exact(synth.dense_lowrank(200, 96, rank=5, noise=0.2, seed=9300))
+    G = X.T @ X
+    lam = 1.01 * float(np.linalg.eigvalsh(G)[-1])
+    tau = 0.3 * math.sqrt(lam)
+    ref = ocpa.cpa_shrink(X, Shrinkage(0, tau), lam, 24)
+    Y, info = cpa.shrink_dense_sparsified(torch.from_numpy(X.astype(np.float32)).cuda(), cpa.soft(tau),
+                                          cpa.Opts(K=24, Lambda=lam), keep=96 * 96, transform=transform, info=True)
+    torch.cuda.synchronize()
+    err = metrics.rel_fro(Y.cpu().numpy().astype(np.float64), ref, X)
+    print(f"no truncation {transform}: nnz {info['nnz']} rel_fro {err:.3e}", flush=True)
+    assert info["nnz"] == 96 * 96
+    assert err <= TOL32
+
+
+def test_identity_transform_truncates_a_nearly_diagonal_gram():
+    """Nearly orthogonal columns: the Gram is sparse in the identity basis."""
+    cpa = _lib()
+    m, n = 256, 64
+    Q = synth.random_orthogonal(m, seed=9400)[:, :n]
+    s = np.linspace(1.0, 8.0, n)
+    X = synth.as_f32_exact(Q * s + 1e-3 * synth.dense_lowrank(m, n, rank=n, noise=0.0, seed=9401) / 8.0)
+    T = np.eye(n)
+    _case(X, T, "identity", 0.02, 16, Shrinkage(0, 3.0), cpa.soft(3.0))
+
+
+def test_power_bound_of_the_truncated_matrix():
+    import torch
+    cpa = _lib()
+    X = synth.as_f32_exact(synth.block_smooth(256, 128, rank=4, noise=1e-3, seed=9500))
+    T = sparsify.block_dct(128, 8)
+    Phi, _ = sparsify.transformed_gram(X, T)
+    keep = _gap_keep(Phi, 0.02)
+    Phil = sparsify.truncate(Phi, sparsify.kth_largest_abs(Phi, keep))
+    lam_o = obound.power_bound(Phil, seed=0, max_iter=200, tol=1e-9)[0]
+    _, info = cpa.shrink_dense_sparsified(torch.from_numpy(X.astype(np.float32)).cuda(), cpa.soft(1.0),
+                                          cpa.Opts(K=8, power_iters=200, power_tol=1e-9), keep=keep, info=True)
+    print(f"truncated power bound: gpu {info['Lambda']:.8e} oracle {lam_o:.8e}", flush=True)
+    assert abs(info["Lambda"] - lam_o) <= 1e-5 * lam_o
+
+
+def test_sparsified_is_deterministic_and_rejects_bad_arguments():
+    import torch
+    cpa = _lib()
+    X = torch.from_numpy(synth.block_smooth(128, 64, rank=3, noise=1e-3, seed=9600).astype(np.float32)).cuda()
+    o = cpa.Opts(K=12, bound="frobenius")
+    Y1 = cpa.shrink_dense_sparsified(X, cpa.soft(1.0), o, keep=100).clone()
+    Y2 = cpa.shrink_dense_sparsified(X, cpa.soft(1.0), o, keep=100).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(Y1, Y2)
+    with pytest.raises(cpa.CpaError):
+        cpa.shrink_dense_sparsified(X, cpa.soft(1.0), o, keep=0)
+    with pytest.raises(cpa.CpaError):
+        cpa.shrink_dense_sparsified(X, cpa.soft(1.0), o, keep=64 * 64 + 1)
+    with pytest.raises(cpa.CpaError):
+        cpa.shrink_dense_sparsified(X, cpa.soft(1.0), cpa.Opts(K=12, precision="bf16x3"), keep=100)
+    with pytest.raises(cpa.CpaError):
+        cpa.shrink_dense_sparsified(X, cpa.soft(1.0), cpa.Opts(K=12, check=True), keep=100)
+    X2 = torch.ones((40, 36), device="cuda")
+    with pytest.raises(cpa.CpaError):
+        cpa.shrink_dense_sparsified(X2, cpa.soft(1.0), o, keep=10)

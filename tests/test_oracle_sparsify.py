@@ -77,23 +77,11 @@ def _spectral_reference(B, T, k, sh, K):
     return (B @ M if m >= n else M @ B), Lam, eps, int(np.count_nonzero(np.abs(Phi) >= eps))
 
 
-def block_smooth(m, n, rank, noise, seed):
-    """m x n data whose Gram side varies only between 8-blocks (plus noise): its
-    block-DCT transformed Gram is concentrated on the blocks' DC entries, the
-    kind of input the truncation is meant for."""
-    g = np.random.default_rng(seed)
-    d = min(m, n)
-    smooth = np.repeat(g.standard_normal((d // 8, rank)), 8, axis=0)      # d x rank
-    other = g.standard_normal((rank, max(m, n)))
-    B = (smooth @ other).T if m >= n else smooth @ other
-    return B + noise * g.standard_normal((m, n))
-
-
 @pytest.mark.parametrize("shape", [(64, 32), (32, 64)])
 @pytest.mark.parametrize("frac", [0.02, 0.1, 0.4])
 def test_truncated_shrinkage_matches_spectral_form(shape, frac):
     m, n = shape
-    B = block_smooth(m, n, rank=3, noise=1e-3, seed=17 + m)
+    B = synth.block_smooth(m, n, rank=3, noise=1e-3, seed=17 + m)
     d = min(m, n)
     T = sparsify.block_dct(d, 8)
     k = sparsify.keep_count(d, frac)
