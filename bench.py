@@ -303,6 +303,54 @@ def bench_sparse(cpa, torch, np, synth):
     }
 
 
+def bench_sparsified(cpa, torch, np, synth, reps: int = 10):
+    """Algorithm 1 with the 8 x 8 block DCT and truncation on a 1024 x 1024 input
+    that is sparse in that transform (block-smooth, rank 4, N(0, 1e-3^2) noise;
+    its transformed Gram is concentrated on the (1024/8)^2 block DC entries),
+    K = 30, soft tau = 0.2 sigma_1, keeping 1.6% and 3% of the entries; beside it
+    the dense matrix-polynomial route on the same input."""
+    n, K = 1024, 30
+    X64 = synth.block_smooth(n, n, rank=4, noise=1e-3, seed=synth.BASE_SEED + 6)
+    X = torch.from_numpy(X64.astype(np.float32)).cuda()
+    s1 = float(np.linalg.svd(X64, compute_uv=False)[0])
+    tau = 0.2 * s1
+    g = lambda sv: np.maximum(sv - tau, 0.0)
+    ex = exact_shrink(X64, g)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    opts = cpa.Opts(K=K)
+    Yd = torch.empty_like(X)
+    ms_dense = timed(lambda: cpa.shrink_dense(X, cpa.soft(tau), opts, out=Yd))
+    dense_err = rel_fro(Yd.cpu().numpy().astype(np.float64), ex, X64)
+    out = {"workload": "1024 x 1024 block-smooth (rank 4, 8-blocks) + N(0,1e-3^2), block DCT 8x8, K=30, soft "
+                       "tau = 0.2 sigma_1, power bound",
+           "dense_polynomial_route": {"ms_per_shrink": round(ms_dense, 4), "err_vs_fp64_svt": float("%.3e" % dense_err)},
+           "keep": []}
+    Ys = torch.empty_like(X)
+    for frac in (0.016, 0.03):
+        keep = int(frac * n * n)
+        ms_s = timed(lambda: cpa.shrink_dense_sparsified(X, cpa.soft(tau), opts, keep=keep, out=Ys))
+        _, info = cpa.shrink_dense_sparsified(X, cpa.soft(tau), opts, keep=keep, out=Ys, info=True)
+        Yh = Ys.cpu().numpy().astype(np.float64)
+        out["keep"].append({"fraction": frac, "keep": keep, "nnz": info["nnz"], "eps": float("%.5e" % info["eps"]),
+                            "ms_per_shrink": round(ms_s, 4), "speedup_vs_dense": round(ms_dense / ms_s, 3),
+                            "err_vs_fp64_svt": float("%.3e" % rel_fro(Yh, ex, X64)),
+                            "err_vs_dense_route": float("%.3e" % rel_fro(Yh, Yd.cpu().numpy().astype(np.float64),
+                                                                         X64))})
+    return out
+
+
 def bench_predictor(cpa, torch, np, synth, n_train: int = 32768, n_eval: int = 8192, epochs: int = 40,
                     gate: float = 1e-2, lr: float = 2e-3, quantiles=(0.99, 0.9)):
     """Learned bound / order predictor on patch groups 64 x U{40..120} with rank
@@ -436,6 +484,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-sparse", action="store_true")
     ap.add_argument("--no-predictor", action="store_true")
+    ap.add_argument("--no-sparsified", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -627,6 +676,9 @@ def main():
         out["sparse"] = bench_sparse(cpa, torch, np, synth)
         progress("sparse leg done")
 
+    if not args.no_sparsified:
+        out["sparsified"] = bench_sparsified(cpa, torch, np, synth)
+        progress("sparsified leg done")
     if not args.no_predictor:
         out["predictor"] = bench_predictor(cpa, torch, np, synth)
         progress("predictor leg done")

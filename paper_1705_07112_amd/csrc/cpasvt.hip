@@ -2071,15 +2071,14 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
         const int ge = (int)std::min<int64_t>(4096, ((int64_t)d * d + 255) / 256);
         hipLaunchKernelGGL(eye_kernel, dim3(ge), dim3(256), 0, st, d, f.P[0], (int64_t)d);
         HIP_TRY(hipGetLastError());
-        const int grid_c = ((d + SP_WAVES - 1) / SP_WAVES) * ((d + SPC_J - 1) / SPC_J);
+        const int grid_c = d * ((d + kPsiJ - 1) / kPsiJ);   // a workgroup per row and 128-column panel
         int cur = 0;
         for (int k = 0; k + 1 <= opts->K - 1; ++k) {
             const float* yk = f.P[cur];
             float* yo = f.P[cur ^ 1];   // Psi_{k-1} (unused at k = 0), overwritten by Psi_{k+1}
-            hipLaunchKernelGGL(spmm_cheb_kernel, dim3(grid_c), dim3(SP_THREADS), 0, st, d, d,
-                               (const int32_t*)f.rowptr, (const int32_t*)f.colidx, (const float*)f.val, yk, (int64_t)d,
-                               yk, (const float*)yo, yo, (int64_t)d, f.H, (int64_t)d, (const double*)w.scal, k,
-                               (k + 1 == opts->K - 1) ? 1 : 0, 1);
+            hipLaunchKernelGGL(psi_step_kernel, dim3(grid_c), dim3(256), 0, st, d, (const int32_t*)f.rowptr,
+                               (const int32_t*)f.colidx, (const float*)f.val, yk, (const float*)yo, yo, (int64_t)d,
+                               f.H, (const double*)w.scal, k, (k + 1 == opts->K - 1) ? 1 : 0);
             HIP_TRY(hipGetLastError());
             cur ^= 1;
         }

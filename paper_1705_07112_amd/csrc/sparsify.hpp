@@ -4,7 +4,7 @@
 //   underline Phi_ij = Phi_ij if |Phi_ij| >= eps (eq. threshold_components), with
 //         eps = the k-th largest |Phi_ij| (the threshold rule of eq. recommendation_epsilon),
 //   hat H(underline Phi) by the three-term recurrence with underline Phi in CSR
-//         (spmm_cheb_kernel, one sparse product per step),
+//         (psi_step_kernel, one sparse product per step),
 //   M = T^T hat H T, then hat G = X M (or M X).
 //
 // Kernels:
@@ -17,17 +17,24 @@
 //   sel_hist_kernel /   radix selection of the k-th largest |Phi| on the FP32 bit
 //   sel_pick_kernel     patterns of |Phi| (monotone as unsigned integers): three
 //                       passes of 11, 11 and 9 bits; exact integer histograms, so
-//                       the threshold is the same on every run.
+//                       the threshold is the same on every run.  The pick finds the
+//                       digit with a suffix scan over the bins (one workgroup).
 //   trunc_count_kernel, one wave per row: counts the kept entries; after an
 //   trunc_fill_kernel   exclusive scan, writes (column, value) in column order
 //                       (ballot + prefix popcount) and zeroes the dropped entries of
 //                       Phi in place (the dense underline Phi feeds the power
 //                       iteration).
+//   psi_step_kernel     one recurrence step on the CSR matrix: a workgroup per row
+//                       and 128-column panel, the row's entries spread over its
+//                       8 lane groups (the kept rows are very uneven).
 //   bt_inverse_kernel   M_IJ = D^T H_IJ D for every tile, FP64 inside.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "gemm_f32.hpp"
+#include "spectral.hpp"
 
 namespace cpa {
 
@@ -132,27 +139,47 @@ __global__ void __launch_bounds__(256) sel_hist_kernel(int d, const float* Phi, 
 // the prefix; clears the histogram for the next pass.  One workgroup.
 __global__ void __launch_bounds__(256) sel_pick_kernel(int pass, SelState* st, unsigned* hist) {
     __shared__ unsigned h[kSelBins];
+    __shared__ uint32_t part[256];
     __shared__ uint32_t s_bin, s_above;
-    for (int i = threadIdx.x; i < kSelBins; i += 256) {
+    const int t = threadIdx.x;
+    const int nbin = 1 << sel_bits(pass), per = nbin / 256;
+    for (int i = t; i < kSelBins; i += 256) {
         h[i] = hist[i];
         hist[i] = 0u;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const int nbin = 1 << sel_bits(pass);
-        uint32_t above = 0, bin = 0;
-        for (int i = nbin - 1; i >= 0; --i) {
-            if (above + h[i] >= st->krem) {
-                bin = (uint32_t)i;
+    // thread t owns bins [hi - per, hi): thread 0 the largest digits
+    const int hi = nbin - per * t;
+    uint32_t sum = 0;
+    for (int u = 1; u <= per; ++u) sum += h[hi - u];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    // entries above thread t's bins: excl; the digit is in the one thread where the
+    // count reaches krem (1 <= krem <= the entries matching the prefix)
+    const uint32_t krem = st->krem;
+    const uint32_t incl = part[t], excl = incl - sum;
+    if (excl < krem && incl >= krem) {
+        uint32_t above = excl;
+        int bin = hi - 1;
+        for (int u = 1; u <= per; ++u) {
+            const int i = hi - u;
+            if (above + h[i] >= krem) {
+                bin = i;
                 break;
             }
             above += h[i];
         }
-        s_bin = bin;
+        s_bin = (uint32_t)bin;
         s_above = above;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         const int shift = sel_shift(pass);
         st->prefix |= s_bin << shift;
         st->mask |= (uint32_t)((1 << sel_bits(pass)) - 1) << shift;
@@ -208,6 +235,91 @@ __global__ void sel_init_kernel(SelState* st, uint32_t k, unsigned* hist) {
         st->krem = k;
         st->pad = 0u;
     }
+}
+
+// One step of the recurrence on the truncated matrix (CSR, d x d):
+//   Z = underline Phi Psi_k,  Psi_{k+1} = a Z + b Psi_k + c Psi_{k-1},
+//   out = c_0/2 Psi_0 + c_1 Psi_1 (step 0) or out += c_{k+1} Psi_{k+1}
+// with a, b, c = 2/Lambda, -1, 0 (step 0) or 4/Lambda, -2, -1 and the coefficients
+// from the scalar block.  The rows of the truncated matrix are very uneven (under
+// the block DCT the kept entries gather on the block-DC rows), so one workgroup
+// takes one row and 128-column panel and spreads the row's entries over its 8
+// groups of 32 lanes (entry e to group e mod 8); the 8 partial sums are added in
+// LDS in a fixed order.  Pprev and Pdst may alias (same element, same thread).
+// Rows start 16-byte aligned and d % 4 == 0.
+constexpr int kPsiJ = 128;
+
+__global__ void __launch_bounds__(256) psi_step_kernel(int d, const int32_t* rowptr, const int32_t* colidx,
+                                                       const float* val, const float* Pk, const float* Pprev,
+                                                       float* Pdst, int64_t ld, float* out, const double* scal, int step,
+                                                       int last) {
+    __shared__ f32x4 red[8][32];
+    const int panels = (d + kPsiJ - 1) / kPsiJ;
+    const int r = blockIdx.x / panels, panel = blockIdx.x - r * panels;
+    const int g = threadIdx.x >> 5, q = threadIdx.x & 31;
+    const int j = panel * kPsiJ + 4 * q;
+    const bool in = j < d;
+    const int e0 = rowptr[r], e1 = rowptr[r + 1];
+    f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    if (e1 > e0) {   // the same for the whole workgroup
+        if (in) {
+            f32x4 acc[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] = (f32x4){0.f, 0.f, 0.f, 0.f};
+            int e = e0 + g;
+            for (; e + 24 < e1; e += 32) {
+                f32x4 w[4];
+                float sv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    sv[u] = val[e + 8 * u];
+                    w[u] = *reinterpret_cast<const f32x4*>(Pk + (int64_t)colidx[e + 8 * u] * ld + j);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[u] += sv[u] * w[u];
+            }
+            for (; e < e1; e += 8) acc[0] += val[e] * *reinterpret_cast<const f32x4*>(Pk + (int64_t)colidx[e] * ld + j);
+            z = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        }
+        red[g][q] = z;
+        __syncthreads();
+        if (g != 0) return;
+        z = red[0][q];
+#pragma unroll
+        for (int u = 1; u < 8; ++u) z += red[u][q];
+    } else if (g != 0) {
+        return;
+    }
+    if (!in) return;
+    float a, b, cc;
+    if (step == 0) {
+        a = (float)scal[SC_A1];
+        b = -1.f;
+        cc = 0.f;
+    } else {
+        a = (float)scal[SC_A2];
+        b = -2.f;
+        cc = -1.f;
+    }
+    const float ck = (float)scal[SC_COEF + step + 1];
+    const float c0h = (float)(0.5 * scal[SC_COEF]);
+    const int64_t o = (int64_t)r * ld + j;
+    const f32x4 yk = *reinterpret_cast<const f32x4*>(Pk + o);
+    f32x4 yp = {0.f, 0.f, 0.f, 0.f}, ov = {0.f, 0.f, 0.f, 0.f};
+    if (step > 0) {
+        yp = *reinterpret_cast<const f32x4*>(Pprev + o);
+        ov = *reinterpret_cast<const f32x4*>(out + o);
+    }
+    f32x4 yn, on;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        float y = a * z[t] + b * yk[t];
+        if (step > 0) y += cc * yp[t];
+        yn[t] = y;
+        on[t] = step == 0 ? c0h * yk[t] + ck * y : ov[t] + ck * y;
+    }
+    *reinterpret_cast<f32x4*>(out + o) = on;
+    if (!last) *reinterpret_cast<f32x4*>(Pdst + o) = yn;
 }
 
 // Dense identity (pitch ld) for Psi_0.
