@@ -307,8 +307,9 @@ def bench_sparsified(cpa, torch, np, synth, reps: int = 10):
     """Algorithm 1 with the 8 x 8 block DCT and truncation on a 1024 x 1024 input
     that is sparse in that transform (block-smooth, rank 4, N(0, 1e-3^2) noise;
     its transformed Gram is concentrated on the (1024/8)^2 block DC entries),
-    K = 30, soft tau = 0.2 sigma_1, keeping 1.6% and 3% of the entries; beside it
-    the dense matrix-polynomial route on the same input."""
+    K = 30, soft tau = 0.2 sigma_1, keeping 1.6% and 3% of the entries: hat H by
+    the matrix polynomial on the nonempty block (the default) and by the sparse
+    recurrence; beside them the dense matrix-polynomial route on the same input."""
     n, K = 1024, 30
     X64 = synth.block_smooth(n, n, rank=4, noise=1e-3, seed=synth.BASE_SEED + 6)
     X = torch.from_numpy(X64.astype(np.float32)).cuda()
@@ -338,13 +339,16 @@ def bench_sparsified(cpa, torch, np, synth, reps: int = 10):
            "dense_polynomial_route": {"ms_per_shrink": round(ms_dense, 4), "err_vs_fp64_svt": float("%.3e" % dense_err)},
            "keep": []}
     Ys = torch.empty_like(X)
+    opts_rec = cpa.Opts(K=K, eval="recurrence")
     for frac in (0.016, 0.03):
         keep = int(frac * n * n)
         ms_s = timed(lambda: cpa.shrink_dense_sparsified(X, cpa.soft(tau), opts, keep=keep, out=Ys))
+        ms_r = timed(lambda: cpa.shrink_dense_sparsified(X, cpa.soft(tau), opts_rec, keep=keep, out=Ys))
         _, info = cpa.shrink_dense_sparsified(X, cpa.soft(tau), opts, keep=keep, out=Ys, info=True)
         Yh = Ys.cpu().numpy().astype(np.float64)
         out["keep"].append({"fraction": frac, "keep": keep, "nnz": info["nnz"], "eps": float("%.5e" % info["eps"]),
                             "ms_per_shrink": round(ms_s, 4), "speedup_vs_dense": round(ms_dense / ms_s, 3),
+                            "sparse_recurrence_ms_per_shrink": round(ms_r, 4),
                             "err_vs_fp64_svt": float("%.3e" % rel_fro(Yh, ex, X64)),
                             "err_vs_dense_route": float("%.3e" % rel_fro(Yh, Yd.cpu().numpy().astype(np.float64),
                                                                          X64))})

@@ -1945,6 +1945,9 @@ struct SpfWork {
     float* M;        // d x d
     unsigned* hist;  // kSelBins
     SelState* sel;
+    int32_t* pos;    // d: compact index of a nonempty row, -1 for an empty one
+    int32_t* rows;   // d: the nonempty rows
+    int32_t* nrows;  // 1
 };
 
 cpa_status ensure_spf(cpa_ctx* ctx, int d, SpfWork& s) {
@@ -1961,6 +1964,9 @@ cpa_status ensure_spf(cpa_ctx* ctx, int d, SpfWork& s) {
     const size_t oM = off; off = align_up(off + sizeof(float) * dd);
     const size_t oHi = off; off = align_up(off + sizeof(unsigned) * kSelBins);
     const size_t oS = off; off = align_up(off + sizeof(SelState));
+    const size_t oPos = off; off = align_up(off + sizeof(int32_t) * d);
+    const size_t oRows = off; off = align_up(off + sizeof(int32_t) * d);
+    const size_t oN = off; off = align_up(off + sizeof(int32_t));
     if (off > ctx->spf_bytes) {
         if (ctx->spf) {
             HIP_TRY(hipDeviceSynchronize());
@@ -1986,6 +1992,9 @@ cpa_status ensure_spf(cpa_ctx* ctx, int d, SpfWork& s) {
     s.M = reinterpret_cast<float*>(b + oM);
     s.hist = reinterpret_cast<unsigned*>(b + oHi);
     s.sel = reinterpret_cast<SelState*>(b + oS);
+    s.pos = reinterpret_cast<int32_t*>(b + oPos);
+    s.rows = reinterpret_cast<int32_t*>(b + oRows);
+    s.nrows = reinterpret_cast<int32_t*>(b + oN);
     return CPA_OK;
 }
 
@@ -2024,7 +2033,10 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
     hipStream_t st = static_cast<hipStream_t>(stream);
     Work w;
     const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
-    if ((s = ensure_ws(ctx, m, n, opts->K, maxit, false, w, right, 0)) != CPA_OK) return s;
+    // hat H by the matrix polynomial on the compact block, or by the sparse recurrence
+    const bool poly = opts->K >= 2 && opts->K <= kPolyMaxK && opts->eval != CPA_EVAL_RECURRENCE;
+    const int ps = poly ? poly_s_of(opts->K) : 0;
+    if ((s = ensure_ws(ctx, m, n, opts->K, maxit, false, w, right, ps)) != CPA_OK) return s;
     SpfWork f;
     if ((s = ensure_spf(ctx, d, f)) != CPA_OK) return s;
     const Dct8 D = transform_table(sp->transform);
@@ -2057,44 +2069,91 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
     hipLaunchKernelGGL(trunc_fill_kernel, dim3(gr), dim3(256), 0, st, d, f.Phi, (int64_t)d, (const SelState*)f.sel,
                        (const int32_t*)f.rowptr, f.colidx, f.val);
     HIP_TRY(hipGetLastError());
-
-    // bound and coefficients from the (dense) truncated matrix
-    Work wb = w;
-    wb.G = f.Phi;
-    if ((s = enqueue_bound(ctx, st, d, shrink, opts, wb, -1)) != CPA_OK) return s;
-    if (opts->K == 1) {
-        // hat H = c_0/2 I, and T^T (c_0/2 I) T = c_0/2 I: Y = c_0/2 X
-        if ((s = enqueue_recurrence(ctx, st, m, n, X_dev, ldx, Y_dev, ldy, 1, w, false, CPA_PREC_FP32)) != CPA_OK)
+    // hat H is computed on the nonempty rows and columns only
+    hipLaunchKernelGGL(compact_rows_kernel, dim3(1), dim3(256), 0, st, d, (const int32_t*)f.cnt, f.pos, f.rows,
+                       f.nrows);
+    HIP_TRY(hipGetLastError());
+    const EpiLin ey = lin_epi(Y_dev, ldy, nullptr, 0, 1.f, 0.f, 0.f, 0.f);
+    Work wi = w;   // the layout read_info uses
+    if (poly) {
+        // the block's size sets every launch below: one wait for the stream
+        int32_t ns = 0;
+        HIP_TRY(hipMemcpyAsync(&ns, f.nrows, sizeof(ns), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (ns < 1 || ns > d) return fail(CPA_ERR_HIP, "compact block size %d read back out of range", ns);
+        // zero rows and columns appended to the block are empty ones too (eigenvalue 0,
+        // never read back): a multiple of 64 gives full tiles to every product
+        int nb = (ns + 63) / 64 * 64;
+        if (nb > d) nb = (ns + 3) / 4 * 4;   // d % 8 == 0, so this fits
+        const int gg = (int)std::min<int64_t>(4096, ((int64_t)nb * nb + 255) / 256);
+        hipLaunchKernelGGL(gather_compact_kernel, dim3(gg), dim3(256), 0, st, ns, nb, (const int32_t*)f.rows,
+                           (const float*)f.Phi, (int64_t)d, w.G);
+        HIP_TRY(hipGetLastError());
+        // bound, coefficients and p(Phi_S) on the nb x nb block (pitch nb, in the Gram's buffer);
+        // the Gram partials keep their place (they depend on K and maxit only)
+        Work wc = w;
+        wc.d = nb;
+        wc.lay.pwg = power_grid(ctx, nb);
+        if ((s = enqueue_bound(ctx, st, nb, shrink, opts, wc, -1)) != CPA_OK) return s;
+        float* F = nullptr;
+        if ((s = enqueue_poly_core(ctx, st, nb, w.G, nb, w.scal, wc.lay.ps(), w.poly, ps, opts->K, CPA_PREC_FP32,
+                                   &F)) != CPA_OK)
             return s;
-    } else {
-        // hat H: Psi_0 = I, Psi_{k+1} = 2 ((2/Lambda) Phi_ Psi_k - Psi_k) - Psi_{k-1}, H = sum c_k Psi_k
-        const int ge = (int)std::min<int64_t>(4096, ((int64_t)d * d + 255) / 256);
-        hipLaunchKernelGGL(eye_kernel, dim3(ge), dim3(256), 0, st, d, f.P[0], (int64_t)d);
+        // M = T^T hat H T (hat h(0) on the empty diagonal), then Y = X M (right) or M X (left)
+        hipLaunchKernelGGL(bt_inverse_kernel, dim3(nt * nt), dim3(64), 0, st, d, (const float*)F, (int64_t)nb, f.M,
+                           (int64_t)d, D, (const int32_t*)f.pos, (const double*)w.scal, opts->K);
         HIP_TRY(hipGetLastError());
-        const int grid_c = d * ((d + kPsiJ - 1) / kPsiJ);   // a workgroup per row and 128-column panel
-        int cur = 0;
-        for (int k = 0; k + 1 <= opts->K - 1; ++k) {
-            const float* yk = f.P[cur];
-            float* yo = f.P[cur ^ 1];   // Psi_{k-1} (unused at k = 0), overwritten by Psi_{k+1}
-            hipLaunchKernelGGL(psi_step_kernel, dim3(grid_c), dim3(256), 0, st, d, (const int32_t*)f.rowptr,
-                               (const int32_t*)f.colidx, (const float*)f.val, yk, (const float*)yo, yo, (int64_t)d,
-                               f.H, (const double*)w.scal, k, (k + 1 == opts->K - 1) ? 1 : 0);
-            HIP_TRY(hipGetLastError());
-            cur ^= 1;
-        }
-        // M = T^T hat H T, then Y = X M (right) or M X (left)
-        hipLaunchKernelGGL(bt_inverse_kernel, dim3(nt * nt), dim3(64), 0, st, d, (const float*)f.H, (int64_t)d,
-                           f.M, (int64_t)d, D);
-        HIP_TRY(hipGetLastError());
-        const EpiLin e = lin_epi(Y_dev, ldy, nullptr, 0, 1.f, 0.f, 0.f, 0.f);
         if (right)
-            s = poly_gemm(ctx, st, make_op(X_dev, ldx, m), make_op(f.M, d, n), m, n, n, e, CPA_PREC_FP32, true);
+            s = poly_gemm(ctx, st, make_op(X_dev, ldx, m), make_op(f.M, d, n), m, n, n, ey, CPA_PREC_FP32, true);
         else
-            s = poly_gemm(ctx, st, make_op(f.M, d, m), make_op(X_dev, ldx, n), m, n, m, e, CPA_PREC_FP32, false);
+            s = poly_gemm(ctx, st, make_op(f.M, d, m), make_op(X_dev, ldx, n), m, n, m, ey, CPA_PREC_FP32, false);
         if (s != CPA_OK) return s;
+        wi = wc;
+    } else {
+        hipLaunchKernelGGL(remap_cols_kernel, dim3(1024), dim3(256), 0, st, d, (const int32_t*)f.rowptr, f.colidx,
+                           (const int32_t*)f.pos);
+        HIP_TRY(hipGetLastError());
+
+        // bound and coefficients from the (dense) truncated matrix
+        Work wb = w;
+        wb.G = f.Phi;
+        if ((s = enqueue_bound(ctx, st, d, shrink, opts, wb, -1)) != CPA_OK) return s;
+        if (opts->K == 1) {
+            // hat H = c_0/2 I, and T^T (c_0/2 I) T = c_0/2 I: Y = c_0/2 X
+            if ((s = enqueue_recurrence(ctx, st, m, n, X_dev, ldx, Y_dev, ldy, 1, w, false, CPA_PREC_FP32)) != CPA_OK)
+                return s;
+        } else {
+            // compact hat H: Psi_0 = I, Psi_{k+1} = 2 ((2/Lambda) Phi_ Psi_k - Psi_k) - Psi_{k-1}, H = sum c_k Psi_k
+            const int ge = (int)std::min<int64_t>(4096, ((int64_t)d * d + 255) / 256);
+            hipLaunchKernelGGL(eye_compact_kernel, dim3(ge), dim3(256), 0, st, (const int32_t*)f.nrows, f.P[0],
+                               (int64_t)d);
+            HIP_TRY(hipGetLastError());
+            // row-and-panel items loop over a grid of at most 2048 workgroups
+            const int grid_c = (int)std::min<int64_t>(2048, (int64_t)d * ((d + kPsiJ - 1) / kPsiJ));
+            int cur = 0;
+            for (int k = 0; k + 1 <= opts->K - 1; ++k) {
+                const float* yk = f.P[cur];
+                float* yo = f.P[cur ^ 1];   // Psi_{k-1} (unused at k = 0), overwritten by Psi_{k+1}
+                hipLaunchKernelGGL(psi_step_kernel, dim3(grid_c), dim3(256), 0, st, d, (const int32_t*)f.rows,
+                                   (const int32_t*)f.nrows, (const int32_t*)f.rowptr,
+                                   (const int32_t*)f.colidx, (const float*)f.val, yk, (const float*)yo, yo, (int64_t)d,
+                                   f.H, (const double*)w.scal, k, (k + 1 == opts->K - 1) ? 1 : 0);
+                HIP_TRY(hipGetLastError());
+                cur ^= 1;
+            }
+            // M = T^T hat H T, then Y = X M (right) or M X (left)
+            hipLaunchKernelGGL(bt_inverse_kernel, dim3(nt * nt), dim3(64), 0, st, d, (const float*)f.H, (int64_t)d,
+                               f.M, (int64_t)d, D, (const int32_t*)f.pos, (const double*)w.scal, opts->K);
+            HIP_TRY(hipGetLastError());
+            if (right)
+                s = poly_gemm(ctx, st, make_op(X_dev, ldx, m), make_op(f.M, d, n), m, n, n, ey, CPA_PREC_FP32, true);
+            else
+                s = poly_gemm(ctx, st, make_op(f.M, d, m), make_op(X_dev, ldx, n), m, n, m, ey, CPA_PREC_FP32, false);
+            if (s != CPA_OK) return s;
+        }
     }
     if (info_host) {
-        if ((s = read_info(st, w, opts->K, m, n, info_host, nullptr)) != CPA_OK) return s;
+        if ((s = read_info(st, wi, opts->K, m, n, info_host, nullptr)) != CPA_OK) return s;
     }
     if (eps_host || nnz_host) {
         SelState hs;

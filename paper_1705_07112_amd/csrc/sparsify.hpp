@@ -24,10 +24,14 @@
 //                       (ballot + prefix popcount) and zeroes the dropped entries of
 //                       Phi in place (the dense underline Phi feeds the power
 //                       iteration).
+//   compact_rows_kernel the rows with kept entries; the recurrence runs on that
+//   remap_cols_kernel   block only (an empty row of the symmetric truncated matrix
+//   eye_compact_kernel  is an empty column too: an eigenvector with eigenvalue 0).
 //   psi_step_kernel     one recurrence step on the CSR matrix: a workgroup per row
 //                       and 128-column panel, the row's entries spread over its
 //                       8 lane groups (the kept rows are very uneven).
-//   bt_inverse_kernel   M_IJ = D^T H_IJ D for every tile, FP64 inside.
+//   bt_inverse_kernel   M_IJ = D^T H_IJ D for every tile, FP64 inside; expands the
+//                       compact hat H (hat h(0) on the empty diagonal entries).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -94,14 +98,46 @@ __global__ void __launch_bounds__(64) bt_forward_kernel(int d, const float* G, i
     }
 }
 
+// hat h(0) with the arithmetic of the recurrence on a row with no kept entries
+// (Z = 0, Psi_0 = 1): Psi_k = (-1)^k exactly, summed in FP32 in step order.
+__device__ inline float hhat_at_zero(const double* scal, int K) {
+    const float c0h = (float)(0.5 * scal[SC_COEF]);
+    if (K < 2) return c0h;
+    float yp = 1.f, yk = -1.f;
+    float out = c0h + (float)scal[SC_COEF + 1] * yk;
+    for (int k = 1; k + 1 <= K - 1; ++k) {
+        const float y = -2.f * yk - yp;
+        out += (float)scal[SC_COEF + k + 1] * y;
+        yp = yk;
+        yk = y;
+    }
+    return out;
+}
+
+// M_IJ = D^T H_IJ D.  With pos != nullptr, H holds hat H of the nonempty rows and
+// columns only (row r of the full matrix is row pos[r] there, pos[r] < 0 for an
+// empty row): an empty row r of the truncated matrix is an eigenvector with
+// eigenvalue 0, so the full hat H is the compact one on the nonempty indices and
+// hat h(0) on the diagonal of the empty ones.
 __global__ void __launch_bounds__(64) bt_inverse_kernel(int d, const float* H, int64_t ldh, float* M, int64_t ldm,
-                                                        Dct8 D) {
+                                                        Dct8 D, const int32_t* pos, const double* scal, int K) {
     __shared__ double h[8][9];
     __shared__ double t[8][9];
     const int nt = d / 8;
     const int I = blockIdx.x / nt, J = blockIdx.x % nt;
     const int a = threadIdx.x >> 3, b = threadIdx.x & 7;
-    h[a][b] = (double)H[(int64_t)(8 * I + a) * ldh + 8 * J + b];
+    const int r = 8 * I + a, c = 8 * J + b;
+    float hv;
+    if (pos) {
+        const int pr = pos[r], pc = pos[c];
+        if (pr >= 0 && pc >= 0)
+            hv = H[(int64_t)pr * ldh + pc];
+        else
+            hv = r == c ? hhat_at_zero(scal, K) : 0.f;
+    } else {
+        hv = H[(int64_t)r * ldh + c];
+    }
+    h[a][b] = (double)hv;
     __syncthreads();
     // t = H_IJ D: t[a][b] = sum_j h[a][j] D[j][b]
     double s = 0.0;
@@ -113,7 +149,7 @@ __global__ void __launch_bounds__(64) bt_inverse_kernel(int d, const float* H, i
     double v = 0.0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) v += D.d[8 * i + a] * t[i][b];
-    M[(int64_t)(8 * I + a) * ldm + 8 * J + b] = (float)v;
+    M[(int64_t)r * ldm + c] = (float)v;
 }
 
 // Histogram of the next digit of |Phi| over the entries matching the prefix.
@@ -237,60 +273,32 @@ __global__ void sel_init_kernel(SelState* st, uint32_t k, unsigned* hist) {
     }
 }
 
-// One step of the recurrence on the truncated matrix (CSR, d x d):
+// One step of the recurrence on the truncated matrix (CSR):
 //   Z = underline Phi Psi_k,  Psi_{k+1} = a Z + b Psi_k + c Psi_{k-1},
 //   out = c_0/2 Psi_0 + c_1 Psi_1 (step 0) or out += c_{k+1} Psi_{k+1}
 // with a, b, c = 2/Lambda, -1, 0 (step 0) or 4/Lambda, -2, -1 and the coefficients
 // from the scalar block.  The rows of the truncated matrix are very uneven (under
-// the block DCT the kept entries gather on the block-DC rows), so one workgroup
-// takes one row and 128-column panel and spreads the row's entries over its 8
-// groups of 32 lanes (entry e to group e mod 8); the 8 partial sums are added in
-// LDS in a fixed order.  Pprev and Pdst may alias (same element, same thread).
-// Rows start 16-byte aligned and d % 4 == 0.
+// the block DCT the kept entries gather on the block-DC rows), so a workgroup
+// takes one row and 128-column panel at a time and spreads the row's entries over
+// its 8 groups of 32 lanes (entry e to group e mod 8); the 8 partial sums are
+// added in LDS in a fixed order.
+// Compact form (rows != nullptr): the matrices are n x n with n = *nrows, row i
+// of the recurrence is CSR row rows[i] and the column indices are compact; the
+// columns up to the next multiple of 4 are computed too (they never mix with the
+// others).  Pprev and Pdst may alias (same element, same thread).  Row pitch ld,
+// rows 16-byte aligned, d % 4 == 0.
 constexpr int kPsiJ = 128;
 
-__global__ void __launch_bounds__(256) psi_step_kernel(int d, const int32_t* rowptr, const int32_t* colidx,
-                                                       const float* val, const float* Pk, const float* Pprev,
-                                                       float* Pdst, int64_t ld, float* out, const double* scal, int step,
-                                                       int last) {
+__global__ void __launch_bounds__(256) psi_step_kernel(int d, const int32_t* rows, const int32_t* nrows,
+                                                       const int32_t* rowptr, const int32_t* colidx, const float* val,
+                                                       const float* Pk, const float* Pprev, float* Pdst, int64_t ld,
+                                                       float* out, const double* scal, int step, int last) {
     __shared__ f32x4 red[8][32];
-    const int panels = (d + kPsiJ - 1) / kPsiJ;
-    const int r = blockIdx.x / panels, panel = blockIdx.x - r * panels;
+    const int n = rows ? *nrows : d;
+    const int w4 = (n + 3) & ~3;
+    const int panels = (w4 + kPsiJ - 1) / kPsiJ;
+    const int items = n * panels;
     const int g = threadIdx.x >> 5, q = threadIdx.x & 31;
-    const int j = panel * kPsiJ + 4 * q;
-    const bool in = j < d;
-    const int e0 = rowptr[r], e1 = rowptr[r + 1];
-    f32x4 z = {0.f, 0.f, 0.f, 0.f};
-    if (e1 > e0) {   // the same for the whole workgroup
-        if (in) {
-            f32x4 acc[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] = (f32x4){0.f, 0.f, 0.f, 0.f};
-            int e = e0 + g;
-            for (; e + 24 < e1; e += 32) {
-                f32x4 w[4];
-                float sv[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    sv[u] = val[e + 8 * u];
-                    w[u] = *reinterpret_cast<const f32x4*>(Pk + (int64_t)colidx[e + 8 * u] * ld + j);
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) acc[u] += sv[u] * w[u];
-            }
-            for (; e < e1; e += 8) acc[0] += val[e] * *reinterpret_cast<const f32x4*>(Pk + (int64_t)colidx[e] * ld + j);
-            z = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-        }
-        red[g][q] = z;
-        __syncthreads();
-        if (g != 0) return;
-        z = red[0][q];
-#pragma unroll
-        for (int u = 1; u < 8; ++u) z += red[u][q];
-    } else if (g != 0) {
-        return;
-    }
-    if (!in) return;
     float a, b, cc;
     if (step == 0) {
         a = (float)scal[SC_A1];
@@ -303,31 +311,122 @@ __global__ void __launch_bounds__(256) psi_step_kernel(int d, const int32_t* row
     }
     const float ck = (float)scal[SC_COEF + step + 1];
     const float c0h = (float)(0.5 * scal[SC_COEF]);
-    const int64_t o = (int64_t)r * ld + j;
-    const f32x4 yk = *reinterpret_cast<const f32x4*>(Pk + o);
-    f32x4 yp = {0.f, 0.f, 0.f, 0.f}, ov = {0.f, 0.f, 0.f, 0.f};
-    if (step > 0) {
-        yp = *reinterpret_cast<const f32x4*>(Pprev + o);
-        ov = *reinterpret_cast<const f32x4*>(out + o);
-    }
-    f32x4 yn, on;
+    for (int it = blockIdx.x; it < items; it += gridDim.x) {
+        const int r = it / panels, panel = it - r * panels;
+        const int j = panel * kPsiJ + 4 * q;
+        const bool in = j < w4;
+        const int rr = rows ? rows[r] : r;
+        const int e0 = rowptr[rr], e1 = rowptr[rr + 1];
+        f32x4 z = {0.f, 0.f, 0.f, 0.f};
+        if (e1 > e0) {   // the same for the whole workgroup
+            if (in) {
+                f32x4 acc[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        float y = a * z[t] + b * yk[t];
-        if (step > 0) y += cc * yp[t];
-        yn[t] = y;
-        on[t] = step == 0 ? c0h * yk[t] + ck * y : ov[t] + ck * y;
+                for (int u = 0; u < 4; ++u) acc[u] = (f32x4){0.f, 0.f, 0.f, 0.f};
+                int e = e0 + g;
+                for (; e + 24 < e1; e += 32) {
+                    f32x4 w[4];
+                    float sv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        sv[u] = val[e + 8 * u];
+                        w[u] = *reinterpret_cast<const f32x4*>(Pk + (int64_t)colidx[e + 8 * u] * ld + j);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) acc[u] += sv[u] * w[u];
+                }
+                for (; e < e1; e += 8)
+                    acc[0] += val[e] * *reinterpret_cast<const f32x4*>(Pk + (int64_t)colidx[e] * ld + j);
+                z = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+            }
+            red[g][q] = z;
+            __syncthreads();
+            if (g == 0) {
+                z = red[0][q];
+#pragma unroll
+                for (int u = 1; u < 8; ++u) z += red[u][q];
+            }
+            __syncthreads();   // red is refilled by the next item
+        }
+        if (g != 0 || !in) continue;
+        const int64_t o = (int64_t)r * ld + j;
+        const f32x4 yk = *reinterpret_cast<const f32x4*>(Pk + o);
+        f32x4 yp = {0.f, 0.f, 0.f, 0.f}, ov = {0.f, 0.f, 0.f, 0.f};
+        if (step > 0) {
+            yp = *reinterpret_cast<const f32x4*>(Pprev + o);
+            ov = *reinterpret_cast<const f32x4*>(out + o);
+        }
+        f32x4 yn, on;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            float y = a * z[t] + b * yk[t];
+            if (step > 0) y += cc * yp[t];
+            yn[t] = y;
+            on[t] = step == 0 ? c0h * yk[t] + ck * y : ov[t] + ck * y;
+        }
+        *reinterpret_cast<f32x4*>(out + o) = on;
+        if (!last) *reinterpret_cast<f32x4*>(Pdst + o) = yn;
     }
-    *reinterpret_cast<f32x4*>(out + o) = on;
-    if (!last) *reinterpret_cast<f32x4*>(Pdst + o) = yn;
 }
 
-// Dense identity (pitch ld) for Psi_0.
-__global__ void eye_kernel(int d, float* P, int64_t ld) {
-    const int64_t total = (int64_t)d * ld;
+// The nonempty rows of the truncated matrix (cnt[r] > 0), single workgroup of
+// 256: pos[r] = compact index or -1, rows[i] = the i-th nonempty row, *nrows.
+__global__ void __launch_bounds__(256) compact_rows_kernel(int d, const int32_t* cnt, int32_t* pos, int32_t* rows,
+                                                           int32_t* nrows) {
+    __shared__ int32_t part[256];
+    const int t = threadIdx.x;
+    const int per = (d + 255) / 256;
+    const int lo = min(d, t * per), hi = min(d, lo + per);
+    int32_t sum = 0;
+    for (int i = lo; i < hi; ++i) sum += cnt[i] > 0 ? 1 : 0;
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int32_t v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int32_t run = part[t] - sum;
+    for (int i = lo; i < hi; ++i) {
+        if (cnt[i] > 0) {
+            pos[i] = run;
+            rows[run] = i;
+            ++run;
+        } else {
+            pos[i] = -1;
+        }
+    }
+    if (t == 255) *nrows = part[255];
+}
+
+// Column indices of the CSR to compact ones (every kept column is a nonempty row:
+// the matrix is symmetric).
+__global__ void remap_cols_kernel(int d, const int32_t* rowptr, int32_t* colidx, const int32_t* pos) {
+    const int32_t nnz = rowptr[d];
+    for (int32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += gridDim.x * blockDim.x)
+        colidx[e] = pos[colidx[e]];
+}
+
+// The compact block Phi_S[i][j] = Phi[rows[i]][rows[j]] for i, j < ns, zero up to
+// nb x nb (pitch nb).
+__global__ void gather_compact_kernel(int ns, int nb, const int32_t* rows, const float* Phi, int64_t ldp,
+                                      float* out) {
+    const int64_t total = (int64_t)nb * nb;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = e / ld, c = e % ld;
-        P[e] = (r == c) ? 1.f : 0.f;
+        const int r = (int)(e / nb), c = (int)(e % nb);
+        out[e] = (r < ns && c < ns) ? Phi[(int64_t)rows[r] * ldp + rows[c]] : 0.f;
+    }
+}
+
+// Compact identity: the leading n x n block (n = *nrows, columns up to the next
+// multiple of 4) of a matrix with pitch ld.
+__global__ void eye_compact_kernel(const int32_t* nrows, float* P, int64_t ld) {
+    const int n = *nrows, w4 = (n + 3) & ~3;
+    const int64_t total = (int64_t)n * w4;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / w4, c = e % w4;
+        P[r * ld + c] = (r == c) ? 1.f : 0.f;
     }
 }
 

@@ -34,7 +34,7 @@ def _gap_keep(Phi, frac):
     return int(j + 1)
 
 
-def _case(X, T, transform, frac, K, sh_o, sh_c, side_right=True):
+def _case(X, T, transform, frac, K, sh_o, sh_c, side_right=True, ev="auto"):
     import torch
     cpa = _lib()
     m, n = X.shape
@@ -45,11 +45,11 @@ def _case(X, T, transform, frac, K, sh_o, sh_c, side_right=True):
     lam = 1.01 * float(np.linalg.eigvalsh(Phil)[-1])
     ref, _, nnz_o = sparsify.cpa_shrink_sparsified(X, sh_o, lam, K, T, keep)
     Xd = torch.from_numpy(X.astype(np.float32)).cuda()
-    Y, info = cpa.shrink_dense_sparsified(Xd, sh_c, cpa.Opts(K=K, Lambda=lam), keep=keep, transform=transform,
-                                          info=True)
+    Y, info = cpa.shrink_dense_sparsified(Xd, sh_c, cpa.Opts(K=K, Lambda=lam, eval=ev), keep=keep,
+                                          transform=transform, info=True)
     torch.cuda.synchronize()
     err = metrics.rel_fro(Y.cpu().numpy().astype(np.float64), ref, X)
-    print(f"sparsified {transform} {m}x{n} K={K} keep={keep} nnz={info['nnz']} (oracle {nnz_o}) "
+    print(f"sparsified {transform} {ev} {m}x{n} K={K} keep={keep} nnz={info['nnz']} (oracle {nnz_o}) "
           f"eps={info['eps']:.6e} (oracle {eps_o:.6e}) rel_fro={err:.3e}", flush=True)
     assert info["nnz"] == nnz_o
     # FP32 Gram: absolute rounding on the scale of the largest entry of Phi
@@ -59,10 +59,11 @@ def _case(X, T, transform, frac, K, sh_o, sh_c, side_right=True):
     return Y
 
 
+@pytest.mark.parametrize("ev", ["auto", "recurrence"])
 @pytest.mark.parametrize("shape,frac,K,kind", [((256, 128), 0.02, 20, 0), ((128, 256), 0.02, 20, 0),
                                                ((512, 512), 0.01, 30, 3), ((320, 64), 0.1, 16, 1),
                                                ((64, 192), 0.05, 8, 0)])
-def test_block_dct_truncated_matches_oracle(shape, frac, K, kind):
+def test_block_dct_truncated_matches_oracle(shape, frac, K, kind, ev):
     cpa = _lib()
     m, n = shape
     X = synth.as_f32_exact(synth.block_smooth(m, n, rank=4, noise=1e-3, seed=9100 + m + n))
@@ -77,11 +78,35 @@ def test_block_dct_truncated_matches_oracle(shape, frac, K, kind):
     else:
         wc, ws = 0.05 * s1 * s1, 0.01 * s1 * s1
         sh_o, sh_c = Shrinkage(3, 0.0, wc, ws, 1e-3), cpa.weighted_fn(wc, ws, 1e-3)
-    _case(X, T, "block_dct8", frac, K, sh_o, sh_c, side_right=m >= n)
+    _case(X, T, "block_dct8", frac, K, sh_o, sh_c, side_right=m >= n, ev=ev)
 
 
+@pytest.mark.parametrize("ev", ["auto", "recurrence"])
+@pytest.mark.parametrize("shape,frac", [((256, 128), 0.02), ((96, 200), 1e-9), ((512, 256), 0.004)])
+def test_empty_rows_are_left_out_of_hat_h(shape, frac, ev):
+    """hat H is computed on the rows with kept entries only (an empty row is an
+    eigenvector with eigenvalue 0, where hat H is hat h(0)), by the matrix
+    polynomial on that block (auto) or by the sparse recurrence; cases with many
+    empty rows, a count of nonempty rows that is not a multiple of 4, and a keep
+    count of a few entries."""
+    cpa = _lib()
+    m, n = shape
+    X = synth.as_f32_exact(synth.block_smooth(m, n, rank=4, noise=1e-3, seed=9150 + m))
+    d = min(m, n)
+    T = sparsify.block_dct(d, 8)
+    Phi, _ = sparsify.transformed_gram(X, T)
+    keep = _gap_keep(Phi, frac)
+    nonempty = int(np.count_nonzero(np.abs(sparsify.truncate(Phi, sparsify.kth_largest_abs(Phi, keep))).sum(1)))
+    print(f"{m}x{n} keep {keep}: {nonempty} of {d} rows nonempty", flush=True)
+    assert nonempty < d
+    G = X.T @ X if m >= n else X @ X.T
+    s1 = math.sqrt(float(np.linalg.eigvalsh(G)[-1]))
+    _case(X, T, "block_dct8", frac, 18, Shrinkage(0, 0.15 * s1), cpa.soft(0.15 * s1), side_right=m >= n, ev=ev)
+
+
+@pytest.mark.parametrize("ev", ["auto", "recurrence"])
 @pytest.mark.parametrize("transform", ["block_dct8", "identity"])
-def test_no_truncation_equals_plain_shrinkage(transform):
+def test_no_truncation_equals_plain_shrinkage(transform, ev):
     """keep = d^2: T^T hat H(T G T^T) T = hat H(G) for orthogonal T."""
     import torch
     cpa = _lib()
@@ -91,7 +116,8 @@ def test_no_truncation_equals_plain_shrinkage(transform):
     tau = 0.3 * math.sqrt(lam)
     ref = ocpa.cpa_shrink(X, Shrinkage(0, tau), lam, 24)
     Y, info = cpa.shrink_dense_sparsified(torch.from_numpy(X.astype(np.float32)).cuda(), cpa.soft(tau),
-                                          cpa.Opts(K=24, Lambda=lam), keep=96 * 96, transform=transform, info=True)
+                                          cpa.Opts(K=24, Lambda=lam, eval=ev), keep=96 * 96, transform=transform,
+                                          info=True)
     torch.cuda.synchronize()
     err = metrics.rel_fro(Y.cpu().numpy().astype(np.float64), ref, X)
     print(f"no truncation {transform}: nnz {info['nnz']} rel_fro {err:.3e}", flush=True)
@@ -99,7 +125,8 @@ def test_no_truncation_equals_plain_shrinkage(transform):
     assert err <= TOL32
 
 
-def test_identity_transform_truncates_a_nearly_diagonal_gram():
+@pytest.mark.parametrize("ev", ["auto", "recurrence"])
+def test_identity_transform_truncates_a_nearly_diagonal_gram(ev):
     """Nearly orthogonal columns: the Gram is sparse in the identity basis."""
     cpa = _lib()
     m, n = 256, 64
@@ -107,10 +134,13 @@ def test_identity_transform_truncates_a_nearly_diagonal_gram():
     s = np.linspace(1.0, 8.0, n)
     X = synth.as_f32_exact(Q * s + 1e-3 * synth.dense_lowrank(m, n, rank=n, noise=0.0, seed=9401) / 8.0)
     T = np.eye(n)
-    _case(X, T, "identity", 0.02, 16, Shrinkage(0, 3.0), cpa.soft(3.0))
+    _case(X, T, "identity", 0.02, 16, Shrinkage(0, 3.0), cpa.soft(3.0), ev=ev)
 
 
-def test_power_bound_of_the_truncated_matrix():
+@pytest.mark.parametrize("ev", ["auto", "recurrence"])
+def test_power_bound_of_the_truncated_matrix(ev):
+    """The bound from the compact block (auto) and from the whole truncated matrix
+    (recurrence) both give the largest eigenvalue of the truncated matrix."""
     import torch
     cpa = _lib()
     X = synth.as_f32_exact(synth.block_smooth(256, 128, rank=4, noise=1e-3, seed=9500))
@@ -120,7 +150,8 @@ def test_power_bound_of_the_truncated_matrix():
     Phil = sparsify.truncate(Phi, sparsify.kth_largest_abs(Phi, keep))
     lam_o = obound.power_bound(Phil, seed=0, max_iter=200, tol=1e-9)[0]
     _, info = cpa.shrink_dense_sparsified(torch.from_numpy(X.astype(np.float32)).cuda(), cpa.soft(1.0),
-                                          cpa.Opts(K=8, power_iters=200, power_tol=1e-9), keep=keep, info=True)
+                                          cpa.Opts(K=8, power_iters=200, power_tol=1e-9, eval=ev), keep=keep,
+                                          info=True)
     print(f"truncated power bound: gpu {info['Lambda']:.8e} oracle {lam_o:.8e}", flush=True)
     assert abs(info["Lambda"] - lam_o) <= 1e-5 * lam_o
 
@@ -130,10 +161,12 @@ def test_sparsified_is_deterministic_and_rejects_bad_arguments():
     cpa = _lib()
     X = torch.from_numpy(synth.block_smooth(128, 64, rank=3, noise=1e-3, seed=9600).astype(np.float32)).cuda()
     o = cpa.Opts(K=12, bound="frobenius")
-    Y1 = cpa.shrink_dense_sparsified(X, cpa.soft(1.0), o, keep=100).clone()
-    Y2 = cpa.shrink_dense_sparsified(X, cpa.soft(1.0), o, keep=100).clone()
-    torch.cuda.synchronize()
-    assert torch.equal(Y1, Y2)
+    for ev in ("auto", "recurrence"):
+        oe = cpa.Opts(K=12, bound="frobenius", eval=ev)
+        Y1 = cpa.shrink_dense_sparsified(X, cpa.soft(1.0), oe, keep=100).clone()
+        Y2 = cpa.shrink_dense_sparsified(X, cpa.soft(1.0), oe, keep=100).clone()
+        torch.cuda.synchronize()
+        assert torch.equal(Y1, Y2)
     with pytest.raises(cpa.CpaError):
         cpa.shrink_dense_sparsified(X, cpa.soft(1.0), o, keep=0)
     with pytest.raises(cpa.CpaError):
