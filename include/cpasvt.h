@@ -284,19 +284,37 @@ cpa_status cpa_shrink_batched(cpa_ctx* ctx, void* stream, int batch, const int32
  * eps = the keep-th largest |Phi_ij| are set to zero (eq. threshold_components;
  * entries equal to eps are kept, so an off-diagonal keep-th value also keeps its
  * mirror), the bound and the coefficients are taken from the truncated matrix,
- * hat H is formed by Algorithm 1's recurrence with the truncated matrix stored
- * sparse (one sparse-dense product per step), and Y = X T^T hat H T (or
+ * hat H = hat h(truncated Phi) is formed, and Y = X T^T hat H T (or
  * T^T hat H T X on the left side).  Phi is formed exactly symmetric (FP64
  * transform of the FP32 Gram, upper tiles mirrored).
- *   transform: CPA_TRANSFORM_BLOCK_DCT8 (the 8 x 8 block DCT, T = kron(I, D_8)) or
+ * hat H is computed on the rows of the truncated matrix that keep an entry: an
+ * empty row (and, by symmetry, column) is an eigenvector with eigenvalue 0, where
+ * hat H is hat h(0).  opts->eval selects how:
+ *   AUTO / POLYNOMIAL (2 <= K <= 256): the bound and the baby-step / giant-step
+ *     matrix polynomial on that block as a dense matrix (zero-padded to full
+ *     64 x 64 tiles).  Its size is read back once: the call waits for the
+ *     stream once, after the truncation.
+ *   RECURRENCE (and K = 1 or K > 256): Algorithm 1's recurrence with the block
+ *     stored sparse (one sparse-dense product per step), the bound on the whole
+ *     truncated matrix; no wait unless info/eps/nnz are requested.
+ *   transform: CPA_TRANSFORM_BLOCK_DCT8 (the 8 x 8 block DCT, T = kron(I, D_8)),
+ *              CPA_TRANSFORM_HAAR1 (the one-level orthonormal Haar DWT),
+ *              CPA_TRANSFORM_HAAR1_LOWPASS (the same, with every entry of Phi in
+ *              a high-frequency row or column set to zero before the threshold,
+ *              as in the experiments of Sec. V), or
  *              CPA_TRANSFORM_IDENTITY (truncation of the Gram itself).
  *   keep: 1 <= keep <= d^2 (d: the Gram side, a multiple of 8).
- * FP32, check = 0 only; eval is not used.  eps_host and nnz_host (nullable)
- * receive the threshold and the number of kept entries (synchronising).
+ * FP32, check = 0 only.  eps_host and nnz_host (nullable) receive the threshold
+ * and the number of kept entries (synchronising).
  * The truncated matrix need not be positive semidefinite: its spectrum can leave
  * [0, Lambda] on the negative side, where Chebyshev series grow, so the keep
  * count must retain the transform's significant entries. */
-typedef enum { CPA_TRANSFORM_IDENTITY = 0, CPA_TRANSFORM_BLOCK_DCT8 = 1 } cpa_transform;
+typedef enum {
+    CPA_TRANSFORM_IDENTITY = 0,
+    CPA_TRANSFORM_BLOCK_DCT8 = 1,
+    CPA_TRANSFORM_HAAR1 = 2,
+    CPA_TRANSFORM_HAAR1_LOWPASS = 3
+} cpa_transform;
 
 typedef struct {
     int32_t transform;  /* cpa_transform */

@@ -25,12 +25,20 @@ Transforms (forward, orthonormal rows):
   dct_matrix(n)    D[k, j] = s_k cos(pi (2 j + 1) k / (2 n)), s_0 = sqrt(1/n),
                    s_k = sqrt(2/n) (DCT-II)
   block_dct(n, b)  kron(I_{n/b}, dct_matrix(b)): the b x b block DCT, b = 8 in the paper
+  haar_matrix(n)   one-level Haar DWT: row q < n/2 is (e_2q + e_2q+1)/sqrt 2 (low
+                   pass), row n/2 + q is (e_2q - e_2q+1)/sqrt 2 (high pass).  The
+                   experiments of Sec. V use it with every high-frequency
+                   component set to zero: `zero` below marks those components,
+                   whose rows and columns of Phi are zeroed before the threshold.
 
 Pins (tests/test_oracle_sparsify.py): the DCT matrix equals scipy's orthonormal
 DCT-II and is orthogonal; without truncation (k = n^2) the result equals the
 T = Id shrinkage for every orthogonal T (an orthogonal similarity); with
 truncation it equals the spectral form built from an eigendecomposition of the
-truncated matrix; eps equals the k-th value of a full sort.  Parity: pinned.
+truncated matrix; eps equals the k-th value of a full sort; the Haar matrix
+maps hand-computed vectors to their sums and differences; with the high
+frequencies zeroed the result equals B T_L^T hat h(Phi_LL) T_L + hat h(0) B T_H^T T_H
+from an eigendecomposition of the low-pass block.  Parity: pinned.
 """
 from __future__ import annotations
 
@@ -57,6 +65,20 @@ def block_dct(n: int, b: int = 8) -> np.ndarray:
     if n % b:
         raise ValueError("n must be a multiple of the block size")
     return np.kron(np.eye(n // b), dct_matrix(b))
+
+
+def haar_matrix(n: int) -> np.ndarray:
+    """One-level orthonormal Haar DWT of length-n vectors (n even): low-pass
+    outputs first, then high-pass."""
+    if n % 2:
+        raise ValueError("n must be even")
+    H = np.zeros((n, n))
+    r = math.sqrt(0.5)
+    for q in range(n // 2):
+        H[q, 2 * q] = H[q, 2 * q + 1] = r
+        H[n // 2 + q, 2 * q] = r
+        H[n // 2 + q, 2 * q + 1] = -r
+    return H
 
 
 def transformed_gram(B: np.ndarray, T: np.ndarray):
@@ -91,13 +113,19 @@ def keep_count(n: int, fraction: float) -> int:
     return max(1, int(math.ceil(fraction * n * n)))
 
 
-def cpa_shrink_sparsified(B: np.ndarray, shrink, Lambda: float, K: int, T: np.ndarray, k: int):
+def cpa_shrink_sparsified(B: np.ndarray, shrink, Lambda: float, K: int, T: np.ndarray, k: int, zero=None):
     """hat G(B) by Algorithm 1 with transform T and threshold eps = K(|Phi|, k).
-    Lambda must bound the largest eigenvalue of the truncated matrix; it is taken
-    as given.  Returns (result, eps, kept entries)."""
+    zero (optional boolean mask over the transform's components): those rows and
+    columns of Phi are set to zero first (the high frequencies of the DWT in
+    Sec. V).  Lambda must bound the largest eigenvalue of the truncated matrix; it
+    is taken as given.  Returns (result, eps, kept entries)."""
     B = np.asarray(B, dtype=np.float64)
     m, n = B.shape
     Phi, side = transformed_gram(B, T)
+    if zero is not None:
+        Phi = Phi.copy()
+        Phi[zero, :] = 0.0
+        Phi[:, zero] = 0.0
     eps = kth_largest_abs(Phi, k)
     Phil = truncate(Phi, eps)
     nnz = int(np.count_nonzero(np.abs(Phi) >= eps))

@@ -63,7 +63,9 @@ class CpaSparsify(ctypes.Structure):
     _fields_ = [("transform", ctypes.c_int32), ("reserved", ctypes.c_int32), ("keep", ctypes.c_int64)]
 
 
-TRANSFORM_IDENTITY, TRANSFORM_BLOCK_DCT8 = 0, 1
+TRANSFORM_IDENTITY, TRANSFORM_BLOCK_DCT8, TRANSFORM_HAAR1, TRANSFORM_HAAR1_LOWPASS = 0, 1, 2, 3
+_TRANSFORMS = {"identity": TRANSFORM_IDENTITY, "block_dct8": TRANSFORM_BLOCK_DCT8, "haar1": TRANSFORM_HAAR1,
+               "haar1_lowpass": TRANSFORM_HAAR1_LOWPASS}
 
 
 class CpaBatchedTuning(ctypes.Structure):
@@ -285,8 +287,9 @@ def _ptr(t):
 def shrink_dense_sparsified(X, shrink: CpaShrinkage, opts: Opts, keep: int, transform: str = "block_dct8",
                             out=None, info: bool = False):
     """Algorithm 1 with a transform and truncation (see cpa_shrink_dense_sparsified):
-    Phi = T G T^T, entries below the keep-th largest |Phi| dropped.  Returns Y, or
-    (Y, info dict with 'eps' and 'nnz' added)."""
+    Phi = T G T^T, entries below the keep-th largest |Phi| dropped.  transform:
+    "block_dct8", "haar1", "haar1_lowpass" (high frequencies set to zero) or
+    "identity".  Returns Y, or (Y, info dict with 'eps' and 'nnz' added)."""
     import torch
     m, n, ldx = _mat(X, "X")
     if out is None:
@@ -294,7 +297,7 @@ def shrink_dense_sparsified(X, shrink: CpaShrinkage, opts: Opts, keep: int, tran
     _, _, ldy = _mat(out, "out")
     if tuple(out.shape) != (m, n):
         raise ValueError("out has the wrong shape")
-    sp = CpaSparsify({"identity": TRANSFORM_IDENTITY, "block_dct8": TRANSFORM_BLOCK_DCT8}[transform], 0, int(keep))
+    sp = CpaSparsify(_TRANSFORMS[transform], 0, int(keep))
     ci = CpaInfo()
     eps = ctypes.c_double()
     nnz = ctypes.c_int64()

@@ -1922,14 +1922,26 @@ namespace {
 
 // 8 x 8 transform table: the orthonormal DCT-II, D[a][i] = s_a cos(pi (2i + 1) a / 16),
 // s_0 = sqrt(1/8), s_a = 1/2; or the identity.
+// Rows of the 8 x 8 transform block.  Haar: one level on the pairs (2q, 2q + 1)
+// of the block, the four low-pass rows (sum / sqrt 2) first, then the four
+// high-pass rows (difference / sqrt 2).  Over the whole vector this is the usual
+// one-level Haar DWT with its outputs permuted; a permutation P of T's rows leaves
+// T^T hat H(T G T^T) T unchanged (hat H(P A P^T) = P hat H(A) P^T, and the kept set
+// is the same), so the block order gives the same result.
 Dct8 transform_table(int transform) {
     Dct8 t;
+    const double r2 = std::sqrt(0.5);
     for (int a = 0; a < 8; ++a)
         for (int i = 0; i < 8; ++i) {
-            if (transform == CPA_TRANSFORM_BLOCK_DCT8)
+            if (transform == CPA_TRANSFORM_BLOCK_DCT8) {
                 t.d[8 * a + i] = (a == 0 ? std::sqrt(1.0 / 8.0) : 0.5) * std::cos(M_PI * (2 * i + 1) * a / 16.0);
-            else
+            } else if (transform == CPA_TRANSFORM_HAAR1 || transform == CPA_TRANSFORM_HAAR1_LOWPASS) {
+                const int q = a & 3;
+                const bool high = a >= 4;
+                t.d[8 * a + i] = (i == 2 * q) ? r2 : (i == 2 * q + 1 ? (high ? -r2 : r2) : 0.0);
+            } else {
                 t.d[8 * a + i] = (a == i) ? 1.0 : 0.0;
+            }
         }
     return t;
 }
@@ -2011,7 +2023,8 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
     if ((s = check_opts(opts)) != CPA_OK) return s;
     if ((s = check_shrinkage(shrink)) != CPA_OK) return s;
     if (!sp) return fail(CPA_ERR_ARG, "sparsify is NULL");
-    if (sp->transform != CPA_TRANSFORM_IDENTITY && sp->transform != CPA_TRANSFORM_BLOCK_DCT8)
+    if (sp->transform != CPA_TRANSFORM_IDENTITY && sp->transform != CPA_TRANSFORM_BLOCK_DCT8 &&
+        sp->transform != CPA_TRANSFORM_HAAR1 && sp->transform != CPA_TRANSFORM_HAAR1_LOWPASS)
         return fail(CPA_ERR_ARG, "unknown transform %d", sp->transform);
     if (sp->reserved != 0) return fail(CPA_ERR_ARG, "sparsify.reserved must be 0");
     if (opts->check) return fail(CPA_ERR_UNSUPPORTED, "the growth check is not available on the sparsified path");
@@ -2046,7 +2059,7 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
     if ((s = enqueue_gram(ctx, st, m, n, X_dev, ldx, w)) != CPA_OK) return s;
     // Phi = T G T^T (exactly symmetric)
     hipLaunchKernelGGL(bt_forward_kernel, dim3(nt * (nt + 1) / 2), dim3(64), 0, st, d, (const float*)w.G,
-                       (int64_t)d, f.Phi, (int64_t)d, D);
+                       (int64_t)d, f.Phi, (int64_t)d, D, sp->transform == CPA_TRANSFORM_HAAR1_LOWPASS ? 1 : 0);
     HIP_TRY(hipGetLastError());
     // eps = the keep-th largest |Phi|
     hipLaunchKernelGGL(sel_init_kernel, dim3(1), dim3(256), 0, st, f.sel, (uint32_t)sp->keep, f.hist);

@@ -1,6 +1,7 @@
 // The sparsifying transform and component truncation of Algorithm 1 (Sec. III-B):
-//   Phi = T G T^T with T the 8 x 8 block DCT (kron(I, D_8), eq. sing_shrink_exact_sparse)
-//         or the identity,
+//   Phi = T G T^T with T the 8 x 8 block DCT (kron(I, D_8), eq. sing_shrink_exact_sparse),
+//         the one-level Haar DWT (optionally with every high-frequency component
+//         set to zero, as in the experiments of Sec. V) or the identity,
 //   underline Phi_ij = Phi_ij if |Phi_ij| >= eps (eq. threshold_components), with
 //         eps = the k-th largest |Phi_ij| (the threshold rule of eq. recommendation_epsilon),
 //   hat H(underline Phi) by the three-term recurrence with underline Phi in CSR
@@ -13,7 +14,10 @@
 //                       (I, J) and transposed to (J, I); diagonal tiles are
 //                       symmetrised ((P + P^T)/2).  Phi is therefore exactly
 //                       symmetric, so an entry and its mirror always fall on the
-//                       same side of eps.  D is passed in (the DCT table, or I).
+//                       same side of eps.  D is passed in (the DCT table, the
+//                       one-level Haar table with the four low-pass rows first,
+//                       or I); with the Haar table the high-frequency rows and
+//                       columns can be zeroed.
 //   sel_hist_kernel /   radix selection of the k-th largest |Phi| on the FP32 bit
 //   sel_pick_kernel     patterns of |Phi| (monotone as unsigned integers): three
 //                       passes of 11, 11 and 9 bits; exact integer histograms, so
@@ -60,8 +64,10 @@ struct SelState {
 
 __device__ inline uint32_t abs_key(float x) { return __float_as_uint(x) & 0x7fffffffu; }
 
+// zero_high: rows 4..7 of the table are high-frequency components (the Haar
+// table); every entry of Phi in such a row or column is set to zero.
 __global__ void __launch_bounds__(64) bt_forward_kernel(int d, const float* G, int64_t ldg, float* Phi, int64_t ldp,
-                                                        Dct8 D) {
+                                                        Dct8 D, int zero_high) {
     __shared__ double g[8][9];
     __shared__ double t[8][9];
     // tile pair index -> (I, J), I <= J, row-major over the upper triangle
@@ -85,6 +91,7 @@ __global__ void __launch_bounds__(64) bt_forward_kernel(int d, const float* G, i
     double v = 0.0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) v += D.d[8 * a + i] * t[i][b];
+    if (zero_high && (a >= 4 || b >= 4)) v = 0.0;
     if (I == J) {
         __syncthreads();
         g[a][b] = v;   // reuse: the tile's P

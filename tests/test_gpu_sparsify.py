@@ -34,16 +34,19 @@ def _gap_keep(Phi, frac):
     return int(j + 1)
 
 
-def _case(X, T, transform, frac, K, sh_o, sh_c, side_right=True, ev="auto"):
+def _case(X, T, transform, frac, K, sh_o, sh_c, side_right=True, ev="auto", zero=None):
     import torch
     cpa = _lib()
     m, n = X.shape
     Phi, _ = sparsify.transformed_gram(X, T)
+    if zero is not None:
+        Phi[zero, :] = 0.0
+        Phi[:, zero] = 0.0
     keep = _gap_keep(Phi, frac) if frac < 1.0 else Phi.size
     eps_o = sparsify.kth_largest_abs(Phi, keep)
     Phil = sparsify.truncate(Phi, eps_o)
     lam = 1.01 * float(np.linalg.eigvalsh(Phil)[-1])
-    ref, _, nnz_o = sparsify.cpa_shrink_sparsified(X, sh_o, lam, K, T, keep)
+    ref, _, nnz_o = sparsify.cpa_shrink_sparsified(X, sh_o, lam, K, T, keep, zero=zero)
     Xd = torch.from_numpy(X.astype(np.float32)).cuda()
     Y, info = cpa.shrink_dense_sparsified(Xd, sh_c, cpa.Opts(K=K, Lambda=lam, eval=ev), keep=keep,
                                           transform=transform, info=True)
@@ -102,6 +105,25 @@ def test_empty_rows_are_left_out_of_hat_h(shape, frac, ev):
     G = X.T @ X if m >= n else X @ X.T
     s1 = math.sqrt(float(np.linalg.eigvalsh(G)[-1]))
     _case(X, T, "block_dct8", frac, 18, Shrinkage(0, 0.15 * s1), cpa.soft(0.15 * s1), side_right=m >= n, ev=ev)
+
+
+@pytest.mark.parametrize("ev", ["auto", "recurrence"])
+@pytest.mark.parametrize("transform", ["haar1", "haar1_lowpass"])
+@pytest.mark.parametrize("shape,frac", [((256, 128), 0.3), ((128, 192), 0.5), ((96, 64), 0.24)])
+def test_haar_matches_oracle(shape, frac, transform, ev):
+    """The one-level Haar DWT (the kernels order each 8-block's low-pass rows
+    first; the oracle uses the global order, a row permutation with the same
+    result), with and without every high-frequency component set to zero."""
+    cpa = _lib()
+    m, n = shape
+    X = synth.as_f32_exact(synth.block_smooth(m, n, rank=4, noise=1e-3, seed=9700 + m + n))
+    d = min(m, n)
+    T = sparsify.haar_matrix(d)
+    zero = (np.arange(d) >= d // 2) if transform == "haar1_lowpass" else None
+    G = X.T @ X if m >= n else X @ X.T
+    s1 = math.sqrt(float(np.linalg.eigvalsh(G)[-1]))
+    _case(X, T, transform, frac, 20, Shrinkage(0, 0.2 * s1), cpa.soft(0.2 * s1), side_right=m >= n, ev=ev,
+          zero=zero)
 
 
 @pytest.mark.parametrize("ev", ["auto", "recurrence"])

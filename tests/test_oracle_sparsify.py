@@ -111,3 +111,69 @@ def test_transform_order_matters_under_truncation():
     Y1, _, _ = sparsify.cpa_shrink_sparsified(B, sh, Lam, 10, T, k)
     Y2, _, _ = sparsify.cpa_shrink_sparsified(B, sh, Lam, 10, T.T.copy(), k)
     assert np.abs(Y1 - Y2).max() > 1e-3 * np.abs(Y1).max()
+
+
+def test_haar_matrix_sums_and_differences():
+    r = math.sqrt(0.5)
+    H = sparsify.haar_matrix(4)
+    assert np.allclose(H @ np.array([1.0, 2.0, 3.0, 5.0]), [3 * r, 8 * r, -1 * r, -2 * r], atol=1e-15)
+    for n in (2, 8, 40):
+        Hn = sparsify.haar_matrix(n)
+        assert np.allclose(Hn @ Hn.T, np.eye(n), atol=1e-15)
+    with pytest.raises(ValueError):
+        sparsify.haar_matrix(7)
+
+
+def _cheb_scalar(sh, Lam, K, lam):
+    c = chebyshev.coefficients_shifted(sh, Lam, K)
+    x = 2.0 * np.asarray(lam, dtype=np.float64) / Lam - 1.0
+    return 0.5 * c[0] + sum(c[j] * chebyshev.cheb_recurrence(j, x) for j in range(1, K))
+
+
+@pytest.mark.parametrize("shape", [(64, 32), (32, 64)])
+@pytest.mark.parametrize("frac", [0.05, 0.25])
+def test_lowpass_haar_equals_the_low_block_spectral_form(shape, frac):
+    """High frequencies set to zero: the truncated matrix lives on the low-pass
+    block, so hat G = B T_L^T V hat h(lambda) V^T T_L + hat h(0) B T_H^T T_H with
+    V, lambda from an eigendecomposition of the truncated low-pass block."""
+    m, n = shape
+    B = synth.block_smooth(m, n, rank=3, noise=1e-3, seed=41 + m)
+    d = min(m, n)
+    T = sparsify.haar_matrix(d)
+    TL, TH = T[: d // 2], T[d // 2:]
+    G = B.T @ B if m >= n else B @ B.T
+    PL = TL @ G @ TL.T
+    PL = 0.5 * (PL + PL.T)
+    k = sparsify.keep_count(d // 2, frac)
+    eps = np.sort(np.abs(PL).ravel())[::-1][k - 1]
+    lam, V = np.linalg.eigh(np.where(np.abs(PL) >= eps, PL, 0.0))
+    Lam = 1.01 * float(lam[-1])
+    sh = Shrinkage(0, 0.2 * math.sqrt(Lam))
+    K = 14
+    M = TL.T @ (V * _cheb_scalar(sh, Lam, K, lam)) @ V.T @ TL + _cheb_scalar(sh, Lam, K, [0.0])[0] * (TH.T @ TH)
+    ref = B @ M if m >= n else M @ B
+    zero = np.arange(d) >= d // 2
+    Y, eps_o, nnz = sparsify.cpa_shrink_sparsified(B, sh, Lam, K, T, k, zero=zero)
+    assert eps_o == eps
+    assert np.abs(Y - ref).max() <= 1e-9 * np.abs(ref).max()
+
+
+def test_block_ordered_haar_gives_the_same_result():
+    """kron(I, haar_matrix(8)) is a row permutation of haar_matrix(n) (the low-pass
+    rows of each 8-block first); the result, eps and the kept count do not change,
+    with or without the high frequencies zeroed."""
+    B = synth.block_smooth(96, 48, rank=3, noise=1e-3, seed=55)
+    d = 48
+    Tg = sparsify.haar_matrix(d)
+    Tb = np.kron(np.eye(d // 8), sparsify.haar_matrix(8))
+    # the two have the same rows
+    assert sorted(map(tuple, np.round(Tg, 12))) == sorted(map(tuple, np.round(Tb, 12)))
+    G = B.T @ B
+    Lam = 1.01 * float(np.linalg.eigvalsh(G)[-1])
+    sh = Shrinkage(0, 0.2 * math.sqrt(Lam))
+    k = sparsify.keep_count(d, 0.05)
+    for zg, zb in ((None, None), (np.arange(d) >= d // 2, np.arange(d) % 8 >= 4)):
+        Y1, e1, n1 = sparsify.cpa_shrink_sparsified(B, sh, Lam, 12, Tg, k, zero=zg)
+        Y2, e2, n2 = sparsify.cpa_shrink_sparsified(B, sh, Lam, 12, Tb, k, zero=zb)
+        assert n1 == n2 and abs(e1 - e2) <= 1e-12 * e1
+        assert np.abs(Y1 - Y2).max() <= 1e-10 * np.abs(Y1).max()
