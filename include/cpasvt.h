@@ -285,8 +285,8 @@ cpa_status cpa_shrink_batched(cpa_ctx* ctx, void* stream, int batch, const int32
  * entries equal to eps are kept, so an off-diagonal keep-th value also keeps its
  * mirror), the bound and the coefficients are taken from the truncated matrix,
  * hat H = hat h(truncated Phi) is formed, and Y = X T^T hat H T (or
- * T^T hat H T X on the left side).  Phi is formed exactly symmetric (FP64
- * transform of the FP32 Gram, upper tiles mirrored).
+ * T^T hat H T X on the left side).  Phi is formed exactly symmetric (block
+ * transforms: FP64 transform of the FP32 Gram, upper tiles mirrored).
  * hat H is computed on the rows of the truncated matrix that keep an entry: an
  * empty row (and, by symmetry, column) is an eigenvector with eigenvalue 0, where
  * hat H is hat h(0).  opts->eval selects how:
@@ -301,7 +301,9 @@ cpa_status cpa_shrink_batched(cpa_ctx* ctx, void* stream, int batch, const int32
  *              CPA_TRANSFORM_HAAR1 (the one-level orthonormal Haar DWT),
  *              CPA_TRANSFORM_HAAR1_LOWPASS (the same, with every entry of Phi in
  *              a high-frequency row or column set to zero before the threshold,
- *              as in the experiments of Sec. V), or
+ *              as in the experiments of Sec. V),
+ *              CPA_TRANSFORM_DCT (the orthonormal DCT-II over the whole side, dense:
+ *              T G T^T and T^T hat H T by FP32 products, Phi then symmetrised), or
  *              CPA_TRANSFORM_IDENTITY (truncation of the Gram itself).
  *   keep: 1 <= keep <= d^2 (d: the Gram side, a multiple of 8).
  * FP32, check = 0 only.  eps_host and nnz_host (nullable) receive the threshold
@@ -313,7 +315,8 @@ typedef enum {
     CPA_TRANSFORM_IDENTITY = 0,
     CPA_TRANSFORM_BLOCK_DCT8 = 1,
     CPA_TRANSFORM_HAAR1 = 2,
-    CPA_TRANSFORM_HAAR1_LOWPASS = 3
+    CPA_TRANSFORM_HAAR1_LOWPASS = 3,
+    CPA_TRANSFORM_DCT = 4
 } cpa_transform;
 
 typedef struct {

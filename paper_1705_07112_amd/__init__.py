@@ -63,9 +63,9 @@ class CpaSparsify(ctypes.Structure):
     _fields_ = [("transform", ctypes.c_int32), ("reserved", ctypes.c_int32), ("keep", ctypes.c_int64)]
 
 
-TRANSFORM_IDENTITY, TRANSFORM_BLOCK_DCT8, TRANSFORM_HAAR1, TRANSFORM_HAAR1_LOWPASS = 0, 1, 2, 3
+TRANSFORM_IDENTITY, TRANSFORM_BLOCK_DCT8, TRANSFORM_HAAR1, TRANSFORM_HAAR1_LOWPASS, TRANSFORM_DCT = 0, 1, 2, 3, 4
 _TRANSFORMS = {"identity": TRANSFORM_IDENTITY, "block_dct8": TRANSFORM_BLOCK_DCT8, "haar1": TRANSFORM_HAAR1,
-               "haar1_lowpass": TRANSFORM_HAAR1_LOWPASS}
+               "haar1_lowpass": TRANSFORM_HAAR1_LOWPASS, "dct": TRANSFORM_DCT}
 
 
 class CpaBatchedTuning(ctypes.Structure):
@@ -288,8 +288,8 @@ def shrink_dense_sparsified(X, shrink: CpaShrinkage, opts: Opts, keep: int, tran
                             out=None, info: bool = False):
     """Algorithm 1 with a transform and truncation (see cpa_shrink_dense_sparsified):
     Phi = T G T^T, entries below the keep-th largest |Phi| dropped.  transform:
-    "block_dct8", "haar1", "haar1_lowpass" (high frequencies set to zero) or
-    "identity".  Returns Y, or (Y, info dict with 'eps' and 'nnz' added)."""
+    "block_dct8", "haar1", "haar1_lowpass" (high frequencies set to zero), "dct"
+    (the full DCT-II) or "identity".  Returns Y, or (Y, info dict with 'eps' and 'nnz' added)."""
     import torch
     m, n, ldx = _mat(X, "X")
     if out is None:

@@ -1960,9 +1960,11 @@ struct SpfWork {
     int32_t* pos;    // d: compact index of a nonempty row, -1 for an empty one
     int32_t* rows;   // d: the nonempty rows
     int32_t* nrows;  // 1
+    float* Dm;       // d x d, the full DCT (dense transform only, else null)
+    float* Dt;       // its transpose
 };
 
-cpa_status ensure_spf(cpa_ctx* ctx, int d, SpfWork& s) {
+cpa_status ensure_spf(cpa_ctx* ctx, int d, bool dense_t, SpfWork& s) {
     const size_t dd = (size_t)d * d;
     size_t off = 0;
     const size_t oPhi = off; off = align_up(off + sizeof(float) * dd);
@@ -1979,6 +1981,11 @@ cpa_status ensure_spf(cpa_ctx* ctx, int d, SpfWork& s) {
     const size_t oPos = off; off = align_up(off + sizeof(int32_t) * d);
     const size_t oRows = off; off = align_up(off + sizeof(int32_t) * d);
     const size_t oN = off; off = align_up(off + sizeof(int32_t));
+    size_t oDm = 0, oDt = 0;
+    if (dense_t) {
+        oDm = off; off = align_up(off + sizeof(float) * dd);
+        oDt = off; off = align_up(off + sizeof(float) * dd);
+    }
     if (off > ctx->spf_bytes) {
         if (ctx->spf) {
             HIP_TRY(hipDeviceSynchronize());
@@ -2007,6 +2014,8 @@ cpa_status ensure_spf(cpa_ctx* ctx, int d, SpfWork& s) {
     s.pos = reinterpret_cast<int32_t*>(b + oPos);
     s.rows = reinterpret_cast<int32_t*>(b + oRows);
     s.nrows = reinterpret_cast<int32_t*>(b + oN);
+    s.Dm = dense_t ? reinterpret_cast<float*>(b + oDm) : nullptr;
+    s.Dt = dense_t ? reinterpret_cast<float*>(b + oDt) : nullptr;
     return CPA_OK;
 }
 
@@ -2024,7 +2033,8 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
     if ((s = check_shrinkage(shrink)) != CPA_OK) return s;
     if (!sp) return fail(CPA_ERR_ARG, "sparsify is NULL");
     if (sp->transform != CPA_TRANSFORM_IDENTITY && sp->transform != CPA_TRANSFORM_BLOCK_DCT8 &&
-        sp->transform != CPA_TRANSFORM_HAAR1 && sp->transform != CPA_TRANSFORM_HAAR1_LOWPASS)
+        sp->transform != CPA_TRANSFORM_HAAR1 && sp->transform != CPA_TRANSFORM_HAAR1_LOWPASS &&
+        sp->transform != CPA_TRANSFORM_DCT)
         return fail(CPA_ERR_ARG, "unknown transform %d", sp->transform);
     if (sp->reserved != 0) return fail(CPA_ERR_ARG, "sparsify.reserved must be 0");
     if (opts->check) return fail(CPA_ERR_UNSUPPORTED, "the growth check is not available on the sparsified path");
@@ -2051,16 +2061,55 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
     const int ps = poly ? poly_s_of(opts->K) : 0;
     if ((s = ensure_ws(ctx, m, n, opts->K, maxit, false, w, right, ps)) != CPA_OK) return s;
     SpfWork f;
-    if ((s = ensure_spf(ctx, d, f)) != CPA_OK) return s;
+    const bool dense_t = sp->transform == CPA_TRANSFORM_DCT;
+    if ((s = ensure_spf(ctx, d, dense_t, f)) != CPA_OK) return s;
     const Dct8 D = transform_table(sp->transform);
     const int nt = d / 8;
 
     if ((s = fill_scalars(st, w)) != CPA_OK) return s;
     if ((s = enqueue_gram(ctx, st, m, n, X_dev, ldx, w)) != CPA_OK) return s;
     // Phi = T G T^T (exactly symmetric)
-    hipLaunchKernelGGL(bt_forward_kernel, dim3(nt * (nt + 1) / 2), dim3(64), 0, st, d, (const float*)w.G,
-                       (int64_t)d, f.Phi, (int64_t)d, D, sp->transform == CPA_TRANSFORM_HAAR1_LOWPASS ? 1 : 0);
-    HIP_TRY(hipGetLastError());
+    const int gd = (int)std::min<int64_t>(4096, ((int64_t)d * d + 255) / 256);
+    if (dense_t) {
+        // full DCT: C = D G, Phi = C D^T (FP32 products), then (Phi + Phi^T)/2
+        const EpiLin ec = lin_epi(f.P[0], d, nullptr, 0, 1.f, 0.f, 0.f, 0.f);
+        const EpiLin ep = lin_epi(f.Phi, d, nullptr, 0, 1.f, 0.f, 0.f, 0.f);
+        hipLaunchKernelGGL(dct_fill_kernel, dim3(gd), dim3(256), 0, st, d, f.Dm, f.Dt);
+        HIP_TRY(hipGetLastError());
+        if ((s = poly_gemm(ctx, st, make_op(f.Dt, d, d), make_op(w.G, d, d), d, d, d, ec, CPA_PREC_FP32, false)) !=
+            CPA_OK)
+            return s;
+        if ((s = poly_gemm(ctx, st, make_op(f.P[0], d, d), make_op(f.Dm, d, d), d, d, d, ep, CPA_PREC_FP32, true)) !=
+            CPA_OK)
+            return s;
+        hipLaunchKernelGGL(symmetrize_kernel, dim3(gd), dim3(256), 0, st, d, f.Phi, (int64_t)d);
+        HIP_TRY(hipGetLastError());
+    } else {
+        hipLaunchKernelGGL(bt_forward_kernel, dim3(nt * (nt + 1) / 2), dim3(64), 0, st, d, (const float*)w.G,
+                           (int64_t)d, f.Phi, (int64_t)d, D, sp->transform == CPA_TRANSFORM_HAAR1_LOWPASS ? 1 : 0);
+        HIP_TRY(hipGetLastError());
+    }
+    // M = T^T hat H T from the compact hat H (pitch ldh; hat h(0) on the empty diagonal)
+    auto inverse = [&](const float* Hc, int64_t ldh) -> cpa_status {
+        if (!dense_t) {
+            hipLaunchKernelGGL(bt_inverse_kernel, dim3(nt * nt), dim3(64), 0, st, d, Hc, ldh, f.M, (int64_t)d, D,
+                               (const int32_t*)f.pos, (const double*)w.scal, opts->K);
+            HIP_TRY(hipGetLastError());
+            return CPA_OK;
+        }
+        // expand to the full hat H (identity table), then C = hat H D, M = D^T C
+        hipLaunchKernelGGL(bt_inverse_kernel, dim3(nt * nt), dim3(64), 0, st, d, Hc, ldh, f.P[0], (int64_t)d,
+                           transform_table(CPA_TRANSFORM_IDENTITY), (const int32_t*)f.pos, (const double*)w.scal,
+                           opts->K);
+        HIP_TRY(hipGetLastError());
+        const EpiLin ec = lin_epi(f.P[1], d, nullptr, 0, 1.f, 0.f, 0.f, 0.f);
+        const EpiLin em = lin_epi(f.M, d, nullptr, 0, 1.f, 0.f, 0.f, 0.f);
+        cpa_status r;
+        if ((r = poly_gemm(ctx, st, make_op(f.P[0], d, d), make_op(f.Dt, d, d), d, d, d, ec, CPA_PREC_FP32, true)) !=
+            CPA_OK)
+            return r;
+        return poly_gemm(ctx, st, make_op(f.Dm, d, d), make_op(f.P[1], d, d), d, d, d, em, CPA_PREC_FP32, false);
+    };
     // eps = the keep-th largest |Phi|
     hipLaunchKernelGGL(sel_init_kernel, dim3(1), dim3(256), 0, st, f.sel, (uint32_t)sp->keep, f.hist);
     HIP_TRY(hipGetLastError());
@@ -2113,9 +2162,7 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
                                    &F)) != CPA_OK)
             return s;
         // M = T^T hat H T (hat h(0) on the empty diagonal), then Y = X M (right) or M X (left)
-        hipLaunchKernelGGL(bt_inverse_kernel, dim3(nt * nt), dim3(64), 0, st, d, (const float*)F, (int64_t)nb, f.M,
-                           (int64_t)d, D, (const int32_t*)f.pos, (const double*)w.scal, opts->K);
-        HIP_TRY(hipGetLastError());
+        if ((s = inverse(F, nb)) != CPA_OK) return s;
         if (right)
             s = poly_gemm(ctx, st, make_op(X_dev, ldx, m), make_op(f.M, d, n), m, n, n, ey, CPA_PREC_FP32, true);
         else
@@ -2155,9 +2202,7 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
                 cur ^= 1;
             }
             // M = T^T hat H T, then Y = X M (right) or M X (left)
-            hipLaunchKernelGGL(bt_inverse_kernel, dim3(nt * nt), dim3(64), 0, st, d, (const float*)f.H, (int64_t)d,
-                               f.M, (int64_t)d, D, (const int32_t*)f.pos, (const double*)w.scal, opts->K);
-            HIP_TRY(hipGetLastError());
+            if ((s = inverse(f.H, d)) != CPA_OK) return s;
             if (right)
                 s = poly_gemm(ctx, st, make_op(X_dev, ldx, m), make_op(f.M, d, n), m, n, n, ey, CPA_PREC_FP32, true);
             else

@@ -1,7 +1,8 @@
 // The sparsifying transform and component truncation of Algorithm 1 (Sec. III-B):
 //   Phi = T G T^T with T the 8 x 8 block DCT (kron(I, D_8), eq. sing_shrink_exact_sparse),
 //         the one-level Haar DWT (optionally with every high-frequency component
-//         set to zero, as in the experiments of Sec. V) or the identity,
+//         set to zero, as in the experiments of Sec. V), the identity, or the
+//         full DCT (dense: two FP32 products each way, see dct_fill_kernel),
 //   underline Phi_ij = Phi_ij if |Phi_ij| >= eps (eq. threshold_components), with
 //         eps = the k-th largest |Phi_ij| (the threshold rule of eq. recommendation_epsilon),
 //   hat H(underline Phi) by the three-term recurrence with underline Phi in CSR
@@ -413,6 +414,34 @@ __global__ void remap_cols_kernel(int d, const int32_t* rowptr, int32_t* colidx,
     const int32_t nnz = rowptr[d];
     for (int32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += gridDim.x * blockDim.x)
         colidx[e] = pos[colidx[e]];
+}
+
+// The orthonormal DCT-II matrix D[k][j] = s_k cos(pi (2 j + 1) k / (2 d)),
+// s_0 = sqrt(1/d), s_k = sqrt(2/d), and its transpose, in FP32 from FP64 values
+// (the angle reduced exactly in integers first).
+__global__ void dct_fill_kernel(int d, float* Dm, float* Dt) {
+    const int64_t total = (int64_t)d * d;
+    const double s0 = sqrt(1.0 / d), s1 = sqrt(2.0 / d);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int k = (int)(e / d), j = (int)(e % d);
+        const int64_t q = ((int64_t)(2 * j + 1) * k) % (4 * (int64_t)d);   // angle = pi q / (2 d)
+        const float v = (float)((k == 0 ? s0 : s1) * cos(M_PI * (double)q / (2.0 * d)));
+        Dm[(int64_t)k * d + j] = v;
+        Dt[(int64_t)j * d + k] = v;
+    }
+}
+
+// P <- (P + P^T) / 2 in place (d x d, pitch ld).
+__global__ void symmetrize_kernel(int d, float* P, int64_t ld) {
+    const int64_t total = (int64_t)d * d;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / d), j = (int)(e % d);
+        if (j <= i) continue;
+        const float a = P[(int64_t)i * ld + j], b = P[(int64_t)j * ld + i];
+        const float v = 0.5f * (a + b);
+        P[(int64_t)i * ld + j] = v;
+        P[(int64_t)j * ld + i] = v;
+    }
 }
 
 // The compact block Phi_S[i][j] = Phi[rows[i]][rows[j]] for i, j < ns, zero up to

@@ -129,6 +129,22 @@ def block_smooth(m: int, n: int, rank: int = 3, noise: float = 1e-3, seed: int =
     return B + noise * g.standard_normal((m, n))
 
 
+def smooth_lowrank(m: int, n: int, rank: int = 3, freqs: int = 4, noise: float = 1e-3,
+                   seed: int = BASE_SEED) -> np.ndarray:
+    """m x n data whose factor along its shorter side (the side of its Gram) is a
+    sum of the `freqs` lowest cosines cos(pi f (i + 1/2) / d) with N(0, 1)
+    weights, times a N(0, 1) factor, plus N(0, noise^2): its DCT-transformed Gram
+    is concentrated on the freqs x freqs low-frequency corner.  FP64."""
+    g = rng(seed)
+    d = min(m, n)
+    i = np.arange(d)[:, None] + 0.5
+    basis = np.cos(np.pi * np.arange(freqs)[None, :] * i / d)          # d x freqs
+    smooth = basis @ g.standard_normal((freqs, rank))                  # d x rank
+    other = g.standard_normal((rank, max(m, n)))
+    B = (smooth @ other).T if m >= n else smooth @ other
+    return B + noise * g.standard_normal((m, n))
+
+
 def block_matrix_D(size: int = 1000, nblocks: int = 10) -> np.ndarray:
     """D = J - blkdiag(0.5 * 1_b 1_b^T, repeated nblocks times), b = size / nblocks."""
     b = size // nblocks

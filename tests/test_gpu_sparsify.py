@@ -34,7 +34,7 @@ def _gap_keep(Phi, frac):
     return int(j + 1)
 
 
-def _case(X, T, transform, frac, K, sh_o, sh_c, side_right=True, ev="auto", zero=None):
+def _case(X, T, transform, frac, K, sh_o, sh_c, side_right=True, ev="auto", zero=None, keep=None, eps_tol=1e-6):
     import torch
     cpa = _lib()
     m, n = X.shape
@@ -42,7 +42,8 @@ def _case(X, T, transform, frac, K, sh_o, sh_c, side_right=True, ev="auto", zero
     if zero is not None:
         Phi[zero, :] = 0.0
         Phi[:, zero] = 0.0
-    keep = _gap_keep(Phi, frac) if frac < 1.0 else Phi.size
+    if keep is None:
+        keep = _gap_keep(Phi, frac) if frac < 1.0 else Phi.size
     eps_o = sparsify.kth_largest_abs(Phi, keep)
     Phil = sparsify.truncate(Phi, eps_o)
     lam = 1.01 * float(np.linalg.eigvalsh(Phil)[-1])
@@ -55,8 +56,9 @@ def _case(X, T, transform, frac, K, sh_o, sh_c, side_right=True, ev="auto", zero
     print(f"sparsified {transform} {ev} {m}x{n} K={K} keep={keep} nnz={info['nnz']} (oracle {nnz_o}) "
           f"eps={info['eps']:.6e} (oracle {eps_o:.6e}) rel_fro={err:.3e}", flush=True)
     assert info["nnz"] == nnz_o
-    # FP32 Gram: absolute rounding on the scale of the largest entry of Phi
-    assert abs(info["eps"] - eps_o) <= 1e-6 * float(np.abs(Phi).max())
+    # FP32 Gram (and FP32 transform products for the full DCT): absolute rounding
+    # on the scale of the largest entry of Phi
+    assert abs(info["eps"] - eps_o) <= eps_tol * float(np.abs(Phi).max())
     assert info["side"] == (0 if side_right else 1)
     assert err <= TOL32
     return Y
@@ -124,6 +126,23 @@ def test_haar_matches_oracle(shape, frac, transform, ev):
     s1 = math.sqrt(float(np.linalg.eigvalsh(G)[-1]))
     _case(X, T, transform, frac, 20, Shrinkage(0, 0.2 * s1), cpa.soft(0.2 * s1), side_right=m >= n, ev=ev,
           zero=zero)
+
+
+@pytest.mark.parametrize("ev", ["auto", "recurrence"])
+@pytest.mark.parametrize("full", [False, True])
+@pytest.mark.parametrize("shape", [(256, 128), (128, 192), (96, 64)])
+def test_full_dct_matches_oracle(shape, full, ev):
+    """The full DCT-II (FP32 transform products): smooth data whose transformed
+    Gram lives on the 6 x 6 low-frequency corner; keep = 36 (that corner, a
+    compact block of 6 rows, the next entry below 1e-5 of the largest) or all."""
+    cpa = _lib()
+    m, n = shape
+    X = synth.as_f32_exact(synth.smooth_lowrank(m, n, rank=4, freqs=6, noise=1e-3, seed=9800 + m + n))
+    d = min(m, n)
+    G = X.T @ X if m >= n else X @ X.T
+    s1 = math.sqrt(float(np.linalg.eigvalsh(G)[-1]))
+    _case(X, sparsify.dct_matrix(d), "dct", 1.0, 20, Shrinkage(0, 0.2 * s1), cpa.soft(0.2 * s1), side_right=m >= n,
+          ev=ev, keep=d * d if full else 36, eps_tol=1e-5)
 
 
 @pytest.mark.parametrize("ev", ["auto", "recurrence"])
