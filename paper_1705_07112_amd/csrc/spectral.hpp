@@ -196,13 +196,15 @@ __global__ void __launch_bounds__(kPowerThreads) power_coop_kernel(int d, const 
     int stop = 0, vanish = 0;
     if (!(w2prev > 0.0)) vanish = 1;
     int t = 1;
+    // the iterate in LDS: w_0 here, then w_t right after each barrier (its loads
+    // overlap the loads of the partial sums)
+    if (in_lds && !vanish) {
+        for (int j = threadIdx.x; j < d; j += kPowerThreads) vl[j] = ld_agent(wb0 + j);
+        __syncthreads();
+    }
     for (; !vanish && t <= maxit; ++t) {
         const double* wp = (t & 1) ? wb0 : wb1;   // w_{t-1}
         double* wn = (t & 1) ? wb1 : wb0;         // w_t
-        if (in_lds) {
-            for (int j = threadIdx.x; j < d; j += kPowerThreads) vl[j] = ld_agent(wp + j);
-            __syncthreads();
-        }
         const double inv = 1.0 / sqrt(w2prev);
         double mu_part = 0.0, w2_part = 0.0;
         const bool vec = ((ldg & 3) == 0) && ((reinterpret_cast<uintptr_t>(G) & 15) == 0) && in_lds;
@@ -249,6 +251,10 @@ __global__ void __launch_bounds__(kPowerThreads) power_coop_kernel(int d, const 
             smu += ld_agent(pt + i);
             sw2 += ld_agent(pt + P + i);
         }
+        // vl (w_{t-1}) was last read before the barrier; the block sums below
+        // synchronise the workgroup before the next product reads w_t
+        if (in_lds)
+            for (int j = threadIdx.x; j < d; j += kPowerThreads) vl[j] = ld_agent(wn + j);
         const double mu = block_sum(smu, red);
         const double w2 = block_sum(sw2, red);
         if (threadIdx.x == 0) {
