@@ -140,9 +140,10 @@ def test_special_cases():
 
 
 def test_device_bound_matches_oracle():
+    """Gram sides from 4 to 1024, aligned and not (90)."""
     torch = _torch()
     cpa = _lib()
-    for seed, (m, n) in enumerate([(64, 48), (200, 120), (90, 300), (1024, 1024)]):
+    for seed, (m, n) in enumerate([(64, 48), (200, 120), (90, 300), (400, 256), (256, 4), (1024, 1024)]):
         X = synth.as_f32_exact(synth.dense_lowrank(m, n, rank=5, noise=0.3, seed=7000 + seed))
         G = X.T @ X if m >= n else X @ X.T
         lam_o = obound.power_bound(G, seed=seed, max_iter=200, tol=1e-9)[0]
