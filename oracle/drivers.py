@@ -24,6 +24,24 @@ SVT matrix completion (Cai, Candes, Shen 2010; the paper cites completion but
 gives no algorithm): X^t = shrink_tau(Y^{t-1}); Y^t = Y^{t-1} + delta P_Omega(M - X^t),
 Y^0 = k0 delta P_Omega(M).
 
+Texture inpainting (Sec. V-C, eq. texture_repaire4; Appendix A, eqs. texture_repaire5,
+z_insert, admm_eq, admm_algorithm_inp): ADMM on z = K l with
+K = [Id; Psi; Omega; Id; Omega_bar], Psi the orthonormal 2-D DCT of the m x n image
+(Psi l = vec(D_m L D_n^T)), Omega the observed-pixel mask and Omega_bar its complement:
+  l = (K^T K)^{-1} K^T (z - u)              K^T K = 4 Id (Psi orthogonal, Omega + Omega_bar = Id)
+  z1 = prox_{(1/rho)||.||_*}(l + u1)        CPA singular value soft shrinkage
+  z2 = soft(Psi l + u2, eta/rho)
+  z3 = Pi_I(Omega l + u3) = Omega i         the observed pixels
+  z4 = Pi_D(l + u4) = clip to [0, 1]
+  z5 = Pi_M(Omega_bar l + u5)               the recovered region shifted to the mean of the
+                                            surrounding observed pixels m_del
+  u += K l - z;   E_t = ||l_{t+1} - l_t|| / ||l_{t+1}||.
+Readings: the start is l_0 = u_0 = 1 (Sec. V-C) and z_0 = K l_0 (unstated); the recovered
+region is the unobserved set (Omega_bar) and the surrounding pixels m_del are a mask the
+caller gives; Pi_M adds (mean of I over m_del) - (mean of y over the region) to y on the
+region and leaves y elsewhere; without the mean term (the random-corruption experiment of
+Sec. V-F) z5 and u5 are dropped and K^T K = 3 Id + Omega.
+
 Pins: (K^T K)^{-1} K^T checked by substitution; l1 prox against its closed
 form; E_t falls on a low-rank-plus-sparse input.  Parity: pinned for the
 closed-form pieces; the ADMM hyper-parameters are project choices (parity
@@ -37,6 +55,7 @@ import numpy as np
 
 from . import bound, cpa
 from .shrinkage import soft
+from .sparsify import dct_matrix
 
 
 def soft_elementwise(x, t):
@@ -129,3 +148,92 @@ def svt_complete(m, n, rows, cols, vals, tau: float, step: float, iters: int, K:
         Y[rows, cols] += step * r
         res.append(math.sqrt(float(r @ r)) / nrm)
     return X, res, k0
+
+
+def dct2(L, Dm=None, Dn=None):
+    """Psi l as a matrix: D_m L D_n^T with the orthonormal DCT-II matrices."""
+    L = np.asarray(L, dtype=np.float64)
+    m, n = L.shape
+    Dm = dct_matrix(m) if Dm is None else Dm
+    Dn = dct_matrix(n) if Dn is None else Dn
+    return Dm @ L @ Dn.T
+
+
+def idct2(S, Dm=None, Dn=None):
+    """Psi^T s as a matrix: D_m^T S D_n."""
+    S = np.asarray(S, dtype=np.float64)
+    m, n = S.shape
+    Dm = dct_matrix(m) if Dm is None else Dm
+    Dn = dct_matrix(n) if Dn is None else Dn
+    return Dm.T @ S @ Dn
+
+
+INPAINT_NAMES = ("l", "z1", "z2", "z3", "z4", "z5", "u1", "u2", "u3", "u4", "u5")
+
+
+def inpaint_start(omega):
+    """l_0 = u_0 = 1 and z_0 = K l_0 (with the mean term; z5, u5 unused without it)."""
+    om = np.asarray(omega, dtype=np.float64)
+    ones = np.ones(om.shape)
+    st = {k: ones.copy() for k in INPAINT_NAMES}
+    st["z2"] = dct2(ones)
+    st["z3"] = om * ones
+    st["z5"] = (1.0 - om) * ones
+    return st
+
+
+def inpaint_step(state, I, omega, border, inv_rho: float, eta_over_rho: float, K: int, v=None, seed: int = 0,
+                 power_iters: int = 100, tol_power: float = 1e-7, delta: float = 0.01):
+    """One ADMM iteration of eq. (admm_algorithm_inp).  omega: observed mask (1/0);
+    border: mask of the surrounding pixels m_del, or None for no mean term.
+    Returns (new_state, info) with info = dict(x, Lambda, v, E)."""
+    I = np.asarray(I, dtype=np.float64)
+    om = np.asarray(omega, dtype=np.float64)
+    ob = 1.0 - om
+    ave = border is not None
+    st = state
+    r = (st["z1"] - st["u1"]) + idct2(st["z2"] - st["u2"]) + om * (st["z3"] - st["u3"]) + (st["z4"] - st["u4"])
+    if ave:
+        r = r + ob * (st["z5"] - st["u5"])
+    diag = 3.0 + om + (ob if ave else 0.0)
+    l_new = r / diag
+    x = l_new + st["u1"]
+    Phi, _ = cpa.gram(x)
+    Lam, _, _, _, v = bound.power_bound(Phi, seed=seed, max_iter=power_iters, tol=tol_power, delta=delta, v0=v)
+    z1 = cpa.cpa_shrink(x, soft(inv_rho), Lam, K)
+    P = dct2(l_new)
+    z2 = soft_elementwise(P + st["u2"], eta_over_rho)
+    z3 = om * I
+    z4 = np.clip(l_new + st["u4"], 0.0, 1.0)
+    new = {"l": l_new, "z1": z1, "z2": z2, "z3": z3, "z4": z4,
+           "u1": st["u1"] + l_new - z1, "u2": st["u2"] + P - z2, "u3": st["u3"] + om * l_new - z3,
+           "u4": st["u4"] + l_new - z4}
+    if ave:
+        bd = np.asarray(border, dtype=bool)
+        reg = om == 0.0
+        y = ob * l_new + st["u5"]
+        z5 = y.copy()
+        z5[reg] += float(np.mean(I[bd])) - float(np.mean(y[reg]))
+        new["z5"] = z5
+        new["u5"] = st["u5"] + ob * l_new - z5
+    else:
+        new["z5"] = st["z5"]
+        new["u5"] = st["u5"]
+    num = math.sqrt(float(np.sum((l_new - st["l"]) ** 2)))
+    den = math.sqrt(float(np.sum(l_new ** 2)))
+    return new, {"x": x, "Lambda": Lam, "v": v, "E": (num / den if den > 0 else 0.0)}
+
+
+def inpaint_admm(I, omega, border, inv_rho: float, eta_over_rho: float, iters: int, K: int, seed: int = 0,
+                 power_iters: int = 100, tol_power: float = 1e-7, delta: float = 0.01):
+    """``iters`` iterations of eq. (admm_algorithm_inp) from inpaint_start; returns
+    (l, E_hist).  The power bound of each shrink is warm-started."""
+    state = inpaint_start(omega)
+    v = None
+    E = []
+    for _ in range(iters):
+        state, info = inpaint_step(state, I, omega, border, inv_rho, eta_over_rho, K, v=v, seed=seed,
+                                   power_iters=power_iters, tol_power=tol_power, delta=delta)
+        v = info["v"]
+        E.append(info["E"])
+    return state["l"], E

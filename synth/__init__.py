@@ -145,6 +145,38 @@ def smooth_lowrank(m: int, n: int, rank: int = 3, freqs: int = 4, noise: float =
     return B + noise * g.standard_normal((m, n))
 
 
+def texture(m: int, n: int, terms: int = 3, noise: float = 0.01, hole=None, border: int = 4,
+            seed: int = BASE_SEED):
+    """A periodic texture stand-in for the inpainting experiment (the paper's
+    images are not available): L0 = minmax(sum of `terms` separable products
+    cos(2 pi f r / m + a) cos(2 pi g c / n + b), integer f, g in 1..8) + N(0,
+    noise^2), clipped to [0, 1] (rank <= 2 terms).  hole = (r0, r1, c0, c1) is the
+    missing rectangle (default: the central quarter of each side); border is the
+    width of the surrounding frame of observed pixels (m_del).  Returns
+    (I, omega, border_mask, L0): I = L0 with the hole set to 0, omega = 1 on the
+    observed pixels, FP64 arrays."""
+    g = rng(seed)
+    r = np.arange(m)[:, None]
+    c = np.arange(n)[None, :]
+    L = np.zeros((m, n))
+    for _ in range(terms):
+        f, h = g.integers(1, 9, size=2)
+        a, b = g.uniform(0, 2 * np.pi, size=2)
+        L += g.uniform(0.5, 1.0) * np.cos(2 * np.pi * f * r / m + a) * np.cos(2 * np.pi * h * c / n + b)
+    L = (L - L.min()) / (L.max() - L.min())
+    L = np.clip(L + noise * g.standard_normal((m, n)), 0.0, 1.0)
+    if hole is None:
+        hole = (3 * m // 8, 5 * m // 8, 3 * n // 8, 5 * n // 8)
+    r0, r1, c0, c1 = hole
+    omega = np.ones((m, n))
+    omega[r0:r1, c0:c1] = 0.0
+    frame = np.zeros((m, n), dtype=bool)
+    frame[max(r0 - border, 0):min(r1 + border, m), max(c0 - border, 0):min(c1 + border, n)] = True
+    frame &= omega > 0
+    I = L * omega
+    return I, omega, frame, L
+
+
 def block_matrix_D(size: int = 1000, nblocks: int = 10) -> np.ndarray:
     """D = J - blkdiag(0.5 * 1_b 1_b^T, repeated nblocks times), b = size / nblocks."""
     b = size // nblocks
