@@ -218,6 +218,37 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
                             float* state_dev, int iters, double inv_rho, double eta_over_rho,
                             const cpa_opts* opts, double* Et_dev);
 
+/* Texture inpainting by ADMM (Sec. V-C, eq. texture_repaire4; Appendix A,
+ * eq. admm_algorithm_inp) for
+ *   min ||L||_* + eta ||Psi l||_1 + iota_I(Omega l) + iota_D(l) + iota_M(Omega_bar l),
+ *   z = K l, K = [Id; Psi; Omega; Id; Omega_bar],
+ * Psi the orthonormal 2-D DCT (Psi l = D_m L D_n^T, DCT-II matrices built on the
+ * device), Omega the observed pixels (omega_dev != 0) and Omega_bar the region to
+ * recover (omega_dev == 0).  One iteration:
+ *   l = (K^T K)^{-1} K^T (z - u)   (K^T K = 4 Id; 3 Id + Omega without the mean term);
+ *   z1 = CPA soft shrinkage of l + u1 with tau = inv_rho;
+ *   z2 = sgn(y) max(|y| - eta_over_rho, 0), y = Psi l + u2;
+ *   z3 = Omega I (the observed pixels);  z4 = clip(l + u4, 0, 1);
+ *   z5 = y5 + (c - mean of y5 over the region) on the region, y5 elsewhere, with
+ *        y5 = Omega_bar l + u5 and c = the mean of I over border_dev != 0 (the
+ *        pixels surrounding the region; the caller chooses them);
+ *   u += K l - z;  E_t = ||l_new - l_old||_2 / ||l_new||_2.
+ * border_dev == NULL drops the mean term (z5, u5 untouched), as in the
+ * random-corruption experiment of Sec. V-F.  An empty border or region makes
+ * the shift 0.
+ * State: cpa_inpaint_state_floats(m, n) floats, eleven consecutive m x n
+ * row-major blocks [l, z1, z2, z3, z4, z5, u1, u2, u3, u4, u5]; L = block 0.
+ * cpa_inpaint_init writes the start l = u = 1 and z = K l (the paper gives
+ * l_0 = u_0 = 1; z_0 = K l_0 is the reading used).  cpa_inpaint_iterate runs
+ * `iters` iterations (launched directly, no graph); Et_dev (device, `iters`
+ * doubles, may be NULL) receives E_t.  I, omega and border (m x n floats, ld = n)
+ * are read only and must not overlap the state.  Asynchronous. */
+int64_t cpa_inpaint_state_floats(int m, int n);
+cpa_status cpa_inpaint_init(cpa_ctx* ctx, void* stream, int m, int n, const float* omega_dev, float* state_dev);
+cpa_status cpa_inpaint_iterate(cpa_ctx* ctx, void* stream, int m, int n, const float* I_dev, const float* omega_dev,
+                               const float* border_dev, float* state_dev, int iters, double inv_rho,
+                               double eta_over_rho, const cpa_opts* opts, double* Et_dev);
+
 /* Sparse shrinkage, CSR input (row pointers int32[m+1], sorted column indices
  * int32[nnz], FP32 values), m >= n (for m < n shrink the transpose, i.e. pass the
  * CSC arrays as CSR of S^T, and transpose the result).  The result is dense:

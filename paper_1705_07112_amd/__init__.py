@@ -90,6 +90,10 @@ _SIGS = {
                                         ctypes.POINTER(CpaShrinkage), ctypes.POINTER(CpaOpts),
                                         ctypes.POINTER(CpaInfo)]),
     "cpa_rpca_state_floats": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int]),
+    "cpa_inpaint_state_floats": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int]),
+    "cpa_inpaint_init": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _P]),
+    "cpa_inpaint_iterate": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, ctypes.c_int,
+                                           ctypes.c_double, ctypes.c_double, ctypes.POINTER(CpaOpts), _P]),
     "cpa_timing_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "cpa_peak_mfma": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
     "cpa_workspace_bytes": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(CpaOpts),
@@ -522,6 +526,52 @@ def timing_read(which: str = "recurrence", device: int = 0):
     _check(lib().cpa_timing_read(ctypes.c_void_p(context(device)), {"recurrence": 0, "gram": 1}[which],
                                  ctypes.byref(ms), ctypes.byref(cnt)))
     return ms.value, cnt.value
+
+
+class Inpaint:
+    """Texture inpainting by ADMM (Appendix A of the paper) with CPA shrinkage,
+    state on the device (see cpa_inpaint_iterate).  ``omega``: 1 on the observed
+    pixels, 0 on the region to recover; ``border``: 1 on the surrounding pixels
+    whose mean the region is held to, or None for no mean term.  ``state`` holds
+    the blocks [l, z1..z5, u1..u5]; ``L`` views the first."""
+
+    NAMES = ("l", "z1", "z2", "z3", "z4", "z5", "u1", "u2", "u3", "u4", "u5")
+
+    def __init__(self, I, omega, inv_rho: float, eta_over_rho: float, opts: Opts, border=None):
+        import torch
+        m, n, ld = _mat(I, "I")
+        if ld != n:
+            raise ValueError("I must be contiguous")
+        self.I, self.m, self.n = I, m, n
+        self.omega = omega.to(device=I.device, dtype=torch.float32).contiguous()
+        self.border = None if border is None else border.to(device=I.device, dtype=torch.float32).contiguous()
+        for t in (self.omega, self.border):
+            if t is not None and tuple(t.shape) != (m, n):
+                raise ValueError("omega and border must have the shape of I")
+        self.inv_rho, self.eta_over_rho, self.opts = float(inv_rho), float(eta_over_rho), opts
+        count = lib().cpa_inpaint_state_floats(m, n)
+        self.state = torch.empty(count, device=I.device, dtype=torch.float32)
+        self.ctx = context(I.device.index or 0)
+        _check(lib().cpa_inpaint_init(ctypes.c_void_p(self.ctx), _stream(I), m, n,
+                                      ctypes.c_void_p(self.omega.data_ptr()), ctypes.c_void_p(self.state.data_ptr())))
+
+    def block(self, i: int):
+        mn = self.m * self.n
+        return self.state[i * mn:(i + 1) * mn].view(self.m, self.n)
+
+    @property
+    def L(self):
+        return self.block(0)
+
+    def iterate(self, iters: int, Et=None):
+        """Runs ``iters`` iterations; ``Et`` (float64 CUDA tensor, >= iters) receives E_t."""
+        co = self.opts.to_c()
+        ptr = ctypes.c_void_p(Et.data_ptr()) if Et is not None else None
+        bptr = ctypes.c_void_p(self.border.data_ptr()) if self.border is not None else None
+        _check(lib().cpa_inpaint_iterate(ctypes.c_void_p(self.ctx), _stream(self.I), self.m, self.n,
+                                         ctypes.c_void_p(self.I.data_ptr()), ctypes.c_void_p(self.omega.data_ptr()),
+                                         bptr, ctypes.c_void_p(self.state.data_ptr()), int(iters), self.inv_rho,
+                                         self.eta_over_rho, ctypes.byref(co), ptr))
 
 
 class RpcaAdmm:

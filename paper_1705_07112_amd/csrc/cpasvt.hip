@@ -20,6 +20,7 @@
 #include "batched.hpp"
 #include "sparse.hpp"
 #include "sparsify.hpp"
+#include "inpaint.hpp"
 #include "gemm_bf16x3.hpp"
 #include "gemm_f32.hpp"
 #include "gemm_lds.hpp"
@@ -72,6 +73,8 @@ struct cpa_ctx {
     int coop_max = 0;          // co-resident power-iteration workgroups (0: not queried)
     void* spf = nullptr;       // sparsified path: Phi, CSR of the truncated matrix, Psi buffers, H, M, selection state
     size_t spf_bytes = 0;
+    void* inp = nullptr;       // inpainting driver: DCT matrices, product scratch, partial sums
+    size_t inp_bytes = 0;
     int batch_per_cu = 0;      // co-resident workgroups of the batched kernel per CU (0: not queried)
     int cus = 0;
     int* queue = nullptr;      // work-queue counter of the batched kernel
@@ -992,6 +995,7 @@ cpa_status cpa_destroy(cpa_ctx* ctx) {
     if (ctx->admm_exec) (void)hipGraphExecDestroy(ctx->admm_exec);
     if (ctx->queue) (void)hipFree(ctx->queue);
     if (ctx->spf) (void)hipFree(ctx->spf);
+    if (ctx->inp) (void)hipFree(ctx->inp);
     if (ctx->mlp_ws) (void)hipFree(ctx->mlp_ws);
     if (ctx->sws) (void)hipFree(ctx->sws);
     if (ctx->csc) (void)hipFree(ctx->csc);
@@ -2225,6 +2229,188 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
             *eps_host = (double)e;
         }
         if (nnz_host) *nnz_host = nnz;
+    }
+    return CPA_OK;
+}
+
+}  // extern "C"
+
+// ---- Texture inpainting (Appendix A) ----
+
+namespace {
+
+struct InpWork {
+    float* Dm;    // m x m DCT-II matrix
+    float* Dtm;   // its transpose
+    float* Dn;    // n x n
+    float* Dtn;
+    float* A;     // m x n product scratch
+    float* B;     // m x n product scratch
+    float* T;     // m x n: Psi^T (z2 - u2), then Psi l
+    float* x;     // m x n shrink input
+    double* part; // 3 per elementwise workgroup
+    double* cst;  // mean over the surrounding pixels, region size
+    int* counter; // next E_t slot
+};
+
+cpa_status ensure_inp(cpa_ctx* ctx, int m, int n, InpWork& s) {
+    const size_t mm = (size_t)m * m, nn = (size_t)n * n, mn = (size_t)m * n;
+    size_t off = 0;
+    const size_t oDm = off; off = align_up(off + sizeof(float) * mm);
+    const size_t oDtm = off; off = align_up(off + sizeof(float) * mm);
+    const size_t oDn = off; off = align_up(off + sizeof(float) * nn);
+    const size_t oDtn = off; off = align_up(off + sizeof(float) * nn);
+    const size_t oA = off; off = align_up(off + sizeof(float) * mn);
+    const size_t oB = off; off = align_up(off + sizeof(float) * mn);
+    const size_t oT = off; off = align_up(off + sizeof(float) * mn);
+    const size_t oX = off; off = align_up(off + sizeof(float) * mn);
+    const size_t oP = off; off = align_up(off + sizeof(double) * 3 * kInpGrid);
+    const size_t oC = off; off = align_up(off + sizeof(double) * 4);
+    const size_t oK = off; off = align_up(off + sizeof(int));
+    if (off > ctx->inp_bytes) {
+        if (ctx->inp) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipFree(ctx->inp));
+            ctx->inp = nullptr;
+            ctx->inp_bytes = 0;
+        }
+        if (hipMalloc(&ctx->inp, off) != hipSuccess) {
+            ctx->inp = nullptr;
+            return fail(CPA_ERR_ALLOC, "inpainting workspace allocation of %zu bytes failed", off);
+        }
+        ctx->inp_bytes = off;
+    }
+    char* b = static_cast<char*>(ctx->inp);
+    s.Dm = reinterpret_cast<float*>(b + oDm);
+    s.Dtm = reinterpret_cast<float*>(b + oDtm);
+    s.Dn = reinterpret_cast<float*>(b + oDn);
+    s.Dtn = reinterpret_cast<float*>(b + oDtn);
+    s.A = reinterpret_cast<float*>(b + oA);
+    s.B = reinterpret_cast<float*>(b + oB);
+    s.T = reinterpret_cast<float*>(b + oT);
+    s.x = reinterpret_cast<float*>(b + oX);
+    s.part = reinterpret_cast<double*>(b + oP);
+    s.cst = reinterpret_cast<double*>(b + oC);
+    s.counter = reinterpret_cast<int*>(b + oK);
+    return CPA_OK;
+}
+
+// The DCT matrices of both sides (D and D^T for m and for n).
+cpa_status inp_dct(hipStream_t st, int m, int n, const InpWork& f) {
+    const int gm = (int)std::min<int64_t>(4096, ((int64_t)m * m + 255) / 256);
+    const int gn = (int)std::min<int64_t>(4096, ((int64_t)n * n + 255) / 256);
+    hipLaunchKernelGGL(dct_fill_kernel, dim3(gm), dim3(256), 0, st, m, f.Dm, f.Dtm);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(dct_fill_kernel, dim3(gn), dim3(256), 0, st, n, f.Dn, f.Dtn);
+    HIP_TRY(hipGetLastError());
+    return CPA_OK;
+}
+
+// out = Psi src = D_m src D_n^T (forward) or Psi^T src = D_m^T src D_n, via f.B.
+cpa_status inp_psi(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* src, float* out, bool forward,
+                   const InpWork& f) {
+    const EpiLin eb = lin_epi(f.B, n, nullptr, 0, 1.f, 0.f, 0.f, 0.f);
+    const EpiLin eo = lin_epi(out, n, nullptr, 0, 1.f, 0.f, 0.f, 0.f);
+    cpa_status s;
+    // B = D_m src (forward: A stored D_m^T, read transposed) or D_m^T src (A stored D_m)
+    if ((s = poly_gemm(ctx, st, make_op(forward ? f.Dtm : f.Dm, m, m), make_op(src, n, n), m, n, m, eb,
+                       CPA_PREC_FP32, false)) != CPA_OK)
+        return s;
+    // out = B D_n^T (B operand stored D_n) or B D_n (stored D_n^T)
+    return poly_gemm(ctx, st, make_op(f.B, n, m), make_op(forward ? f.Dn : f.Dtn, n, n), m, n, n, eo,
+                     CPA_PREC_FP32, true);
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t cpa_inpaint_state_floats(int m, int n) {
+    if (m <= 0 || n <= 0) return 0;
+    return 11 * (int64_t)m * n;
+}
+
+cpa_status cpa_inpaint_init(cpa_ctx* ctx, void* stream, int m, int n, const float* omega_dev, float* state_dev) {
+    if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
+    if (m < 0 || n < 0) return fail(CPA_ERR_SHAPE, "negative size");
+    if (m == 0 || n == 0) return CPA_OK;
+    if (!omega_dev || !state_dev) return fail(CPA_ERR_ARG, "omega or state is NULL");
+    const int64_t mn = (int64_t)m * n;
+    if (overlaps(omega_dev, sizeof(float) * mn, state_dev, sizeof(float) * 11 * mn))
+        return fail(CPA_ERR_ARG, "omega overlaps the state");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    InpWork f;
+    cpa_status s;
+    if ((s = ensure_inp(ctx, m, n, f)) != CPA_OK) return s;
+    const int grid = (int)std::min<int64_t>(kInpGrid, (mn + 255) / 256);
+    hipLaunchKernelGGL(inp_init_kernel, dim3(grid), dim3(256), 0, st, mn, omega_dev, state_dev);
+    HIP_TRY(hipGetLastError());
+    // z2 = Psi 1 (the init kernel left ones in z2; the product reads them from there)
+    if ((s = inp_dct(st, m, n, f)) != CPA_OK) return s;
+    return inp_psi(ctx, st, m, n, state_dev + 2 * mn, state_dev + 2 * mn, true, f);
+}
+
+cpa_status cpa_inpaint_iterate(cpa_ctx* ctx, void* stream, int m, int n, const float* I_dev, const float* omega_dev,
+                               const float* border_dev, float* state_dev, int iters, double inv_rho,
+                               double eta_over_rho, const cpa_opts* opts, double* Et_dev) {
+    cpa_status s;
+    if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
+    if (m < 0 || n < 0) return fail(CPA_ERR_SHAPE, "negative size");
+    if (iters < 0) return fail(CPA_ERR_ARG, "iters < 0");
+    if ((s = check_opts(opts)) != CPA_OK) return s;
+    if (!(std::isfinite(inv_rho) && inv_rho >= 0.0 && std::isfinite(eta_over_rho) && eta_over_rho >= 0.0))
+        return fail(CPA_ERR_ARG, "inv_rho and eta_over_rho must be finite and >= 0");
+    if (m == 0 || n == 0 || iters == 0) return CPA_OK;
+    if (!I_dev || !omega_dev || !state_dev) return fail(CPA_ERR_ARG, "I, omega or state is NULL");
+    if (opts->check) return fail(CPA_ERR_UNSUPPORTED, "the growth check is not available inside the ADMM driver");
+    const int64_t mn = (int64_t)m * n;
+    const size_t sb = sizeof(float) * 11 * mn, ib = sizeof(float) * mn;
+    if (overlaps(I_dev, ib, state_dev, sb) || overlaps(omega_dev, ib, state_dev, sb) ||
+        (border_dev && overlaps(border_dev, ib, state_dev, sb)))
+        return fail(CPA_ERR_ARG, "an input overlaps the state");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Work w;
+    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    if ((s = ensure_ws(ctx, m, n, opts->K, maxit, false, w, right_side(opts, m, n), poly_choice(opts, m, n))) !=
+        CPA_OK)
+        return s;
+    InpWork f;
+    if ((s = ensure_inp(ctx, m, n, f)) != CPA_OK) return s;
+    if ((s = inp_dct(st, m, n, f)) != CPA_OK) return s;
+    hipLaunchKernelGGL(inp_const_kernel, dim3(1), dim3(256), 0, st, mn, I_dev, omega_dev, border_dev, f.cst);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, st, f.counter, 1, 0);
+    HIP_TRY(hipGetLastError());
+    InpPtrs P;
+    P.l = state_dev;
+    for (int k = 0; k < 5; ++k) {
+        P.z[k] = state_dev + (1 + k) * mn;
+        P.u[k] = state_dev + (6 + k) * mn;
+    }
+    P.I = I_dev;
+    P.om = omega_dev;
+    P.x = f.x;
+    P.T = f.T;
+    P.ave = border_dev ? 1 : 0;
+    cpa_shrinkage sh = {CPA_SOFT, 0, inv_rho, 0.0, 0.0, 1.0};
+    const int grid = (int)std::min<int64_t>(kInpGrid, (mn + 255) / 256);
+    for (int t = 0; t < iters; ++t) {
+        // T = Psi^T (z2 - u2)
+        hipLaunchKernelGGL(inp_diff_kernel, dim3(grid), dim3(256), 0, st, mn, (const float*)P.z[1],
+                           (const float*)P.u[1], f.A);
+        HIP_TRY(hipGetLastError());
+        if ((s = inp_psi(ctx, st, m, n, f.A, f.T, false, f)) != CPA_OK) return s;
+        hipLaunchKernelGGL(inp_pre_kernel, dim3(grid), dim3(256), 0, st, P, mn, f.part);
+        HIP_TRY(hipGetLastError());
+        // z1 = the CPA shrink of x = l + u1
+        if ((s = shrink_impl(ctx, st, m, n, f.x, n, P.z[0], n, &sh, opts, nullptr, w)) != CPA_OK) return s;
+        // T = Psi l
+        if ((s = inp_psi(ctx, st, m, n, P.l, f.T, true, f)) != CPA_OK) return s;
+        hipLaunchKernelGGL(inp_post_kernel, dim3(grid), dim3(256), 0, st, P, mn, (float)eta_over_rho,
+                           (const double*)f.part, grid, (const double*)f.cst, Et_dev, f.counter);
+        HIP_TRY(hipGetLastError());
     }
     return CPA_OK;
 }

@@ -1,0 +1,82 @@
+"""GPU texture-inpainting ADMM (Appendix A, eq. admm_algorithm_inp) against the
+oracle driver.
+
+Gated: one iteration started from the same state on both sides (the GPU's own
+state, copied to the host) must agree to the FP32 tolerance, every block of
+[l, z1..z5, u1..u5]; each dual block's error is measured against the size of
+the terms it sums.  Then the recovery of a low-rank texture's missing block
+with the pin's parameters."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import drivers, metrics
+
+pytestmark = pytest.mark.gpu
+
+NAMES = drivers.INPAINT_NAMES
+
+
+def _state_host(run):
+    return {k: run.block(i).cpu().numpy().astype(np.float64) for i, k in enumerate(NAMES)}
+
+
+def _run(m, n, hole, border_w, with_mean, K, inv_rho, eta, seed):
+    import torch
+    import paper_1705_07112_amd as cpa
+    I, om, bd, L0 = synth.texture(m, n, hole=hole, border=border_w, seed=seed)
+    Id = torch.from_numpy(I.astype(np.float32)).cuda()
+    run = cpa.Inpaint(Id, torch.from_numpy(om), inv_rho, eta, cpa.Opts(K=K, warm_start=True, power_iters=100),
+                      border=torch.from_numpy(bd.astype(np.float32)) if with_mean else None)
+    return run, I.astype(np.float32).astype(np.float64), om, bd, L0
+
+
+@pytest.mark.parametrize("with_mean", [True, False])
+@pytest.mark.parametrize("shape,hole", [((96, 80), (30, 60, 20, 44)), ((130, 70), (40, 71, 9, 33))])
+def test_inpaint_one_iteration(shape, hole, with_mean):
+    import torch
+    m, n = shape
+    K, inv_rho, eta = 20, 1.0, 0.01
+    run, I, om, bd, _ = _run(m, n, hole, 3, with_mean, K, inv_rho, eta, 8100 + m)
+    for warm in (0, 6):
+        if warm:
+            run.iterate(warm)
+        before = _state_host(run)
+        Et = torch.zeros(1, dtype=torch.float64, device="cuda")
+        run.iterate(1, Et)
+        torch.cuda.synchronize()
+        after = _state_host(run)
+        ref, info = drivers.inpaint_step(before, I, om, bd if with_mean else None, inv_rho, eta, K)
+        P = drivers.dct2(ref["l"])
+        scale = {"u1": metrics.fro(before["u1"]) + metrics.fro(ref["l"]) + metrics.fro(ref["z1"]),
+                 "u2": metrics.fro(before["u2"]) + metrics.fro(P) + metrics.fro(ref["z2"]),
+                 "u3": metrics.fro(before["u3"]) + metrics.fro(om * ref["l"]) + metrics.fro(ref["z3"]),
+                 "u4": metrics.fro(before["u4"]) + metrics.fro(ref["l"]) + metrics.fro(ref["z4"]),
+                 "u5": metrics.fro(before["u5"]) + metrics.fro((1 - om) * ref["l"]) + metrics.fro(ref["z5"])}
+        errs = {k: (metrics.fro(after[k] - ref[k]) / scale[k] if k in scale else metrics.rel_fro(after[k], ref[k]))
+                for k in NAMES}
+        print(f"inpaint {m}x{n} mean={with_mean} after {warm}: " + " ".join(f"{k}={v:.1e}" for k, v in errs.items())
+              + f" E gpu={Et.item():.6g} oracle={info['E']:.6g}", flush=True)
+        for k in NAMES:
+            assert errs[k] <= 1e-5, (k, errs[k])
+        assert abs(Et.item() - info["E"]) <= 1e-5 * max(info["E"], 1e-12)
+
+
+def test_inpaint_recovers_a_low_rank_texture():
+    """The oracle pin's problem (48 x 40, 12 x 10 hole, 120 iterations): E_t falls
+    below 1e-4 and the hole is recovered to 25%, like the oracle's run."""
+    import torch
+    run, I, om, bd, L0 = _run(48, 40, None, 4, True, 20, 1.0, 0.01, 5)
+    Et = torch.zeros(120, dtype=torch.float64, device="cuda")
+    run.iterate(120, Et)
+    torch.cuda.synchronize()
+    l = run.L.cpu().numpy().astype(np.float64)
+    reg = om == 0.0
+    err = np.linalg.norm((l - L0)[reg]) / np.linalg.norm(L0[reg])
+    l_o, E_o = drivers.inpaint_admm(I, om, bd, 1.0, 0.01, 120, 20)
+    err_o = np.linalg.norm((l_o - L0)[reg]) / np.linalg.norm(L0[reg])
+    print(f"inpaint recovery: hole err gpu {err:.4f} oracle {err_o:.4f}; E_t gpu {Et[-1].item():.2e} "
+          f"oracle {E_o[-1]:.2e}; drift {metrics.rel_fro(l, l_o):.2e}", flush=True)
+    assert Et[-1].item() < 1e-4
+    assert err < 0.25
+    assert abs(err - err_o) <= 0.01
