@@ -2379,7 +2379,11 @@ cpa_status cpa_inpaint_iterate(cpa_ctx* ctx, void* stream, int m, int n, const f
     InpWork f;
     if ((s = ensure_inp(ctx, m, n, f)) != CPA_OK) return s;
     if ((s = inp_dct(st, m, n, f)) != CPA_OK) return s;
-    hipLaunchKernelGGL(inp_const_kernel, dim3(1), dim3(256), 0, st, mn, I_dev, omega_dev, border_dev, f.cst);
+    const int grid = (int)std::min<int64_t>(kInpGrid, (mn + 255) / 256);
+    hipLaunchKernelGGL(inp_const_kernel, dim3(grid), dim3(256), 0, st, mn, I_dev, omega_dev, border_dev, f.part);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(inp_const_finish_kernel, dim3(1), dim3(256), 0, st, (const double*)f.part, grid,
+                       border_dev ? 1 : 0, f.cst);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, st, f.counter, 1, 0);
     HIP_TRY(hipGetLastError());
@@ -2395,7 +2399,6 @@ cpa_status cpa_inpaint_iterate(cpa_ctx* ctx, void* stream, int m, int n, const f
     P.T = f.T;
     P.ave = border_dev ? 1 : 0;
     cpa_shrinkage sh = {CPA_SOFT, 0, inv_rho, 0.0, 0.0, 1.0};
-    const int grid = (int)std::min<int64_t>(kInpGrid, (mn + 255) / 256);
     for (int t = 0; t < iters; ++t) {
         // T = Psi^T (z2 - u2)
         hipLaunchKernelGGL(inp_diff_kernel, dim3(grid), dim3(256), 0, st, mn, (const float*)P.z[1],

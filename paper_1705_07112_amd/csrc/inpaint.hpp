@@ -122,14 +122,15 @@ __global__ void __launch_bounds__(256) inp_post_kernel(InpPtrs P, int64_t total,
     }
 }
 
-// cst[0] = mean of I over the surrounding pixels (border != 0), cst[1] = number of
-// region pixels (om == 0); cst[1] = 0 when either set is empty or border is null.
-// Single workgroup, fixed order.
+// Per-workgroup partials of the constants: [3 b] sum of I over the surrounding
+// pixels (border != 0), [3 b + 1] their number, [3 b + 2] the number of region
+// pixels (om == 0).
 __global__ void __launch_bounds__(256) inp_const_kernel(int64_t total, const float* I, const float* om,
-                                                        const float* border, double* cst) {
+                                                        const float* border, double* part) {
     __shared__ double red[8];
     double sb = 0.0, nb = 0.0, nr = 0.0;
-    for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += stride) {
         if (border && border[e] != 0.f) {
             sb += (double)I[e];
             nb += 1.0;
@@ -140,7 +141,29 @@ __global__ void __launch_bounds__(256) inp_const_kernel(int64_t total, const flo
     nb = block_sum(nb, red);
     nr = block_sum(nr, red);
     if (threadIdx.x == 0) {
-        const bool ok = border && nb > 0.0 && nr > 0.0;
+        part[3 * blockIdx.x] = sb;
+        part[3 * blockIdx.x + 1] = nb;
+        part[3 * blockIdx.x + 2] = nr;
+    }
+}
+
+// cst[0] = mean of I over the surrounding pixels, cst[1] = number of region
+// pixels; cst[1] = 0 when either set is empty or there is no border mask.  The
+// partials are added in a fixed order (one workgroup).
+__global__ void __launch_bounds__(256) inp_const_finish_kernel(const double* part, int npart, int has_border,
+                                                               double* cst) {
+    __shared__ double red[8];
+    double sb = 0.0, nb = 0.0, nr = 0.0;
+    for (int i = threadIdx.x; i < npart; i += blockDim.x) {
+        sb += part[3 * i];
+        nb += part[3 * i + 1];
+        nr += part[3 * i + 2];
+    }
+    sb = block_sum(sb, red);
+    nb = block_sum(nb, red);
+    nr = block_sum(nr, red);
+    if (threadIdx.x == 0) {
+        const bool ok = has_border && nb > 0.0 && nr > 0.0;
         cst[0] = ok ? sb / nb : 0.0;
         cst[1] = ok ? nr : 0.0;
     }
