@@ -73,3 +73,22 @@ def test_argument_errors_before_any_device_work():
     assert st == 1
     assert b"context" in lib.cpa_last_error()
     assert lib.cpa_rpca_state_floats(3, 5) == 105
+
+
+def test_inpaint_and_sparsified_argument_errors_before_any_device_work():
+    lib = cpa.lib()
+    o = cpa.Opts(K=4).to_c()
+    assert lib.cpa_inpaint_state_floats(3, 5) == 165
+    assert lib.cpa_inpaint_state_floats(0, 5) == 0
+    # NULL context
+    st = lib.cpa_inpaint_iterate(None, None, 4, 4, ctypes.c_void_p(16), ctypes.c_void_p(4096), None,
+                                 ctypes.c_void_p(1 << 20), 1, 1.0, 0.1, ctypes.byref(o), None)
+    assert st == 1 and b"context" in lib.cpa_last_error()
+    st = lib.cpa_inpaint_init(None, None, 4, 4, ctypes.c_void_p(16), ctypes.c_void_p(4096))
+    assert st == 1 and b"context" in lib.cpa_last_error()
+    sp = cpa.CpaSparsify(cpa.TRANSFORM_BLOCK_DCT8, 0, 4)
+    info = cpa.CpaInfo()
+    st = lib.cpa_shrink_dense_sparsified(None, None, 8, 8, ctypes.c_void_p(16), 8, ctypes.c_void_p(4096), 8,
+                                         ctypes.byref(cpa.soft(1.0)), ctypes.byref(o), ctypes.byref(sp),
+                                         ctypes.byref(info), None, None)
+    assert st == 1 and b"context" in lib.cpa_last_error()
