@@ -114,6 +114,11 @@ typedef enum { CPA_EVAL_AUTO = 0, CPA_EVAL_RECURRENCE = 1, CPA_EVAL_POLYNOMIAL =
  *   CPA_SIDE_LEFT   X X^T, products on the left (Ghat Y_k)
  * The sparse path forms S^T S (AUTO or RIGHT); the batched path takes AUTO. */
 typedef enum { CPA_SIDE_AUTO = 0, CPA_SIDE_RIGHT = 1, CPA_SIDE_LEFT = 2 } cpa_side;
+/* Damping of the Chebyshev coefficients, g_k for degree N = K - 1 (the kernel
+ * polynomial method's factors):  Jackson ((N - k + 1) cos(pi k/(N+1)) +
+ * sin(pi k/(N+1)) cot(pi/(N+1))) / (N + 1);  Lanczos sin(pi k/(N+1)) / (pi k/(N+1));
+ * g_0 = 1. */
+typedef enum { CPA_DAMP_NONE = 0, CPA_DAMP_JACKSON = 1, CPA_DAMP_LANCZOS = 2 } cpa_damping;
 
 typedef struct {
     int32_t K;            /* number of Chebyshev coefficients (the paper's order alpha), >= 1 */
@@ -130,6 +135,11 @@ typedef struct {
     double growth_tol;    /* tolerance of the growth check */
     int32_t eval;         /* cpa_eval (dense and sparse paths; the batched path uses the recurrence) */
     int32_t side;         /* cpa_side */
+    int32_t damping;      /* cpa_damping: coefficients times Jackson or Lanczos factors (not in the
+                             paper; a ripple reducer for steep responses such as the high-order hard
+                             threshold).  Dense, CSR and sparsified paths and the drivers; the
+                             batched path rejects it */
+    int32_t reserved;     /* must be 0 */
 } cpa_opts;
 
 /* Per-call report (host struct).  Filling it synchronises the stream. */
@@ -168,6 +178,10 @@ void cpa_default_opts(cpa_opts* opts);
  *   theta_l = pi (l - 1/2) / K,  k = 0..K-1.
  * c_host must hold K doubles.  Lambda == 0 gives all zeros.  Pure host code. */
 cpa_status cpa_chebyshev_coeffs(const cpa_shrinkage* shrink, double Lambda, int K, double* c_host);
+
+/* The damping factors g_0..g_{K-1} of the kind (cpa_damping), host FP64; the
+ * shrink uses c_k g_k.  Errors: K outside [1, 4096] or an unknown kind. */
+cpa_status cpa_damping_factors(int K, int kind, double* g_host);
 
 /* The device bound alone: forms the Gram of X (FP32 MFMA) and applies opts->bound
  * to it.  Writes Lambda to *Lambda_host and fills *info_host if non-null.

@@ -72,10 +72,11 @@ def chebyshev_matrix_sum(Phi: np.ndarray, c: np.ndarray, Lambda: float) -> np.nd
     return H
 
 
-def cpa_shrink(B: np.ndarray, shrink, Lambda: float, K: int) -> np.ndarray:
+def cpa_shrink(B: np.ndarray, shrink, Lambda: float, K: int, damping: str = "none") -> np.ndarray:
     """hat G(B) by Algorithm 1 (T = Id, epsilon = 0).  ``shrink`` is a callable h(x)
     (e.g. oracle.shrinkage.Shrinkage).  Lambda must bound the Gram's largest
-    eigenvalue; it is taken as given."""
+    eigenvalue; it is taken as given.  ``damping`` multiplies the coefficients by
+    chebyshev.damping_factors (not in the paper)."""
     B = np.asarray(B, dtype=np.float64)
     if K < 1:
         raise ValueError("K must be >= 1")
@@ -85,7 +86,7 @@ def cpa_shrink(B: np.ndarray, shrink, Lambda: float, K: int) -> np.ndarray:
     if Lambda <= 0.0:
         return np.zeros((m, n))
     Phi, side = gram(B)
-    c = chebyshev.coefficients_shifted(shrink, Lambda, K)
+    c = chebyshev.coefficients_shifted(shrink, Lambda, K) * chebyshev.damping_factors(K, damping)
     H = chebyshev_matrix_sum(Phi, c, Lambda)
     if side == "right":
         return B @ H

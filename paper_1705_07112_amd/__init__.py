@@ -40,7 +40,8 @@ class CpaOpts(ctypes.Structure):
                 ("power_iters", ctypes.c_int32), ("warm_start", ctypes.c_int32),
                 ("power_tol", ctypes.c_double), ("margin", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("check", ctypes.c_int32), ("precision", ctypes.c_int32), ("growth_tol", ctypes.c_double),
-                ("eval", ctypes.c_int32), ("side", ctypes.c_int32)]
+                ("eval", ctypes.c_int32), ("side", ctypes.c_int32), ("damping", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class CpaInfo(ctypes.Structure):
@@ -82,6 +83,7 @@ _SIGS = {
     "cpa_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "cpa_last_error": (ctypes.c_char_p, []),
     "cpa_default_opts": (None, [ctypes.POINTER(CpaOpts)]),
+    "cpa_damping_factors": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P]),
     "cpa_chebyshev_coeffs": (ctypes.c_int, [ctypes.POINTER(CpaShrinkage), ctypes.c_double, ctypes.c_int,
                                             ctypes.POINTER(ctypes.c_double)]),
     "cpa_spectral_bound": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _I64, ctypes.POINTER(CpaOpts),
@@ -198,6 +200,7 @@ class Opts:
     precision: str = "fp32"      # "fp32" | "bf16x3"
     eval: str = "auto"           # "auto" | "recurrence" | "polynomial"
     side: str = "auto"           # "auto" | "right" (Gram X^T X) | "left" (Gram X X^T)
+    damping: str = "none"        # "none" | "jackson" | "lanczos" (coefficient damping; not in the paper)
 
     def to_c(self) -> CpaOpts:
         o = CpaOpts()
@@ -218,6 +221,7 @@ class Opts:
         o.growth_tol = float(self.growth_tol)
         o.eval = {"auto": 0, "recurrence": 1, "polynomial": 2}[self.eval]
         o.side = {"auto": 0, "right": 1, "left": 2}[self.side]
+        o.damping = {"none": 0, "jackson": 1, "lanczos": 2}[self.damping]
         return o
 
 
@@ -253,6 +257,13 @@ def chebyshev_coeffs(shrink: CpaShrinkage, Lambda: float, K: int) -> np.ndarray:
     out = (ctypes.c_double * int(K))()
     _check(lib().cpa_chebyshev_coeffs(ctypes.byref(shrink), float(Lambda), int(K), out))
     return np.array(out[:], dtype=np.float64)
+
+
+def damping_factors(K: int, kind: str = "jackson"):
+    """The coefficient damping factors g_0..g_{K-1} (cpa_damping_factors) as a list."""
+    out = (ctypes.c_double * int(K))()
+    _check(lib().cpa_damping_factors(int(K), {"none": 0, "jackson": 1, "lanczos": 2}[kind], out))
+    return list(out)
 
 
 def shrink_dense(X, shrink: CpaShrinkage, opts: Opts, out=None, info: bool = False):

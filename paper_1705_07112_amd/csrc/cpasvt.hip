@@ -347,6 +347,9 @@ cpa_status check_opts(const cpa_opts* o) {
     if (o->eval == CPA_EVAL_POLYNOMIAL && o->K > 256)
         return fail(CPA_ERR_UNSUPPORTED, "the matrix-polynomial route supports K <= 256");
     if (o->side < CPA_SIDE_AUTO || o->side > CPA_SIDE_LEFT) return fail(CPA_ERR_ARG, "unknown side %d", o->side);
+    if (o->damping < CPA_DAMP_NONE || o->damping > CPA_DAMP_LANCZOS)
+        return fail(CPA_ERR_ARG, "unknown damping %d", o->damping);
+    if (o->reserved != 0) return fail(CPA_ERR_ARG, "opts.reserved must be 0");
     return CPA_OK;
 }
 
@@ -419,7 +422,7 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
     hipLaunchKernelGGL(finish_bound_kernel, dim3(1), dim3(256), 0, st, mode, o->Lambda, d, o->power_iters, o->margin,
                        (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? ctx->warm : nullptr, w.scal,
                        to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)(w.scal + w.lay.gpart()),
-                       w.lay.gwg, 0);
+                       w.lay.gwg, 0, o->damping);
     HIP_TRY(hipGetLastError());
     if (mode == 0) ctx->warm_d = d;
     return CPA_OK;
@@ -882,7 +885,7 @@ cpa_status shrink_csr_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t n
     }
     hipLaunchKernelGGL(finish_bound_kernel, dim3(1), dim3(256), 0, st, mode, o->Lambda, n, o->power_iters, o->margin,
                        (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? ctx->warm : nullptr, w.scal,
-                       to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)gpart, kSqGrid, 1);
+                       to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)gpart, kSqGrid, 1, o->damping);
     HIP_TRY(hipGetLastError());
     if (mode == 0) ctx->warm_d = n;
     // Y_0 = S densified
@@ -1051,6 +1054,14 @@ void cpa_default_opts(cpa_opts* o) {
     o->side = CPA_SIDE_AUTO;
 }
 
+cpa_status cpa_damping_factors(int K, int kind, double* g_host) {
+    if (K < 1 || K > kMaxK) return fail(CPA_ERR_ARG, "K must be in [1, %d], got %d", kMaxK, K);
+    if (kind < CPA_DAMP_NONE || kind > CPA_DAMP_LANCZOS) return fail(CPA_ERR_ARG, "unknown damping %d", kind);
+    if (!g_host) return fail(CPA_ERR_ARG, "output pointer is NULL");
+    for (int k = 0; k < K; ++k) g_host[k] = damping_factor(kind, K, k);
+    return CPA_OK;
+}
+
 cpa_status cpa_chebyshev_coeffs(const cpa_shrinkage* shrink, double Lambda, int K, double* c_host) {
     cpa_status s = check_shrinkage(shrink);
     if (s != CPA_OK) return s;
@@ -1214,6 +1225,7 @@ cpa_status batched_shrink_args(const cpa_opts* opts, const float* X_dev, float* 
     if ((s = check_opts(opts)) != CPA_OK) return s;
     if (opts->K > 64) return fail(CPA_ERR_ARG, "batched shrinkage supports K <= 64");
     if (opts->side != CPA_SIDE_AUTO) return fail(CPA_ERR_UNSUPPORTED, "batched shrinkage takes the smaller Gram (side auto)");
+    if (opts->damping != CPA_DAMP_NONE) return fail(CPA_ERR_UNSUPPORTED, "batched shrinkage takes undamped coefficients");
 
     if (opts->check && !(opts->growth_tol >= 0.0)) return fail(CPA_ERR_ARG, "growth_tol must be >= 0");
     if (a.batch > 0 && !Y_dev) return fail(CPA_ERR_ARG, "NULL array");

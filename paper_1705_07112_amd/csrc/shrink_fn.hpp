@@ -53,4 +53,17 @@ __host__ __device__ inline double cheb_coeff(const ShrinkParams& p, double Lambd
     return 2.0 / K * acc;
 }
 
+// Optional damping factor g_k of c_k (not in the paper; the kernel polynomial
+// method's factors for degree N = K - 1): kind 0 none, 1 Jackson
+// ((N - k + 1) cos(pi k/(N+1)) + sin(pi k/(N+1)) cot(pi/(N+1))) / (N + 1),
+// 2 Lanczos sin(pi k/(N+1)) / (pi k/(N+1)); g_0 = 1.
+__host__ __device__ inline double damping_factor(int kind, int K, int k) {
+    if (kind == 0 || k == 0 || K < 2) return 1.0;
+    const double pi = 3.14159265358979323846;
+    const double n1 = (double)K;   // N + 1
+    const double a = pi * k / n1;
+    if (kind == 1) return ((n1 - k) * cos(a) + sin(a) / tan(pi / n1)) / n1;
+    return sin(a) / a;
+}
+
 }  // namespace cpa

@@ -295,7 +295,7 @@ constexpr int kCoefLds = 64;   // orders up to this use the parallel coefficient
 __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int maxit, double margin,
                                     const double* wbuf0, const double* wbuf1, double* warm_out, double* scal,
                                     ShrinkParams sp, int K, int pw_mu, int pw_w2, const double* gpart, int gwg,
-                                    int cap_trace) {
+                                    int cap_trace, int damping) {
     __shared__ double sLambda;
     __shared__ int sT;
     __shared__ double red[16];
@@ -363,10 +363,11 @@ __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int ma
         for (int k = threadIdx.x; k < K; k += blockDim.x) {
             double acc = 0.0;
             for (int l = 0; l < K; ++l) acc += term[k * K + l];
-            scal[SC_COEF + k] = Lam > 0.0 ? 2.0 / K * acc : 0.0;
+            scal[SC_COEF + k] = Lam > 0.0 ? 2.0 / K * acc * damping_factor(damping, K, k) : 0.0;
         }
     } else {
-        for (int k = threadIdx.x; k < K; k += blockDim.x) scal[SC_COEF + k] = cheb_coeff(sp, Lam, K, k);
+        for (int k = threadIdx.x; k < K; k += blockDim.x)
+            scal[SC_COEF + k] = cheb_coeff(sp, Lam, K, k) * damping_factor(damping, K, k);
     }
     if (mode == 0 && warm_out && sT >= 1) {
         // v_T = w_{T-1} / ||w_{T-1}||; w_{T-1} sits in buffer (T-1) % 2

@@ -32,7 +32,7 @@ def test_status_strings_and_defaults():
 
 def test_struct_layouts_match_header():
     assert ctypes.sizeof(cpa.CpaShrinkage) == 40
-    assert ctypes.sizeof(cpa.CpaOpts) == 72
+    assert ctypes.sizeof(cpa.CpaOpts) == 80
     assert ctypes.sizeof(cpa.CpaInfo) == 56
     assert ctypes.sizeof(cpa.CpaBatchedTuning) == 32
 
@@ -92,3 +92,19 @@ def test_inpaint_and_sparsified_argument_errors_before_any_device_work():
                                          ctypes.byref(cpa.soft(1.0)), ctypes.byref(o), ctypes.byref(sp),
                                          ctypes.byref(info), None, None)
     assert st == 1 and b"context" in lib.cpa_last_error()
+
+
+@pytest.mark.parametrize("K", [1, 2, 7, 30, 256])
+def test_damping_factors_match_oracle(K):
+    import numpy as np
+    from oracle import chebyshev
+    for kind in ("none", "jackson", "lanczos"):
+        g = np.array(cpa.damping_factors(K, kind))
+        assert np.abs(g - chebyshev.damping_factors(K, kind)).max() <= 1e-14
+    with pytest.raises(cpa.CpaError):
+        cpa._check(cpa.lib().cpa_damping_factors(K, 3, ctypes.c_void_p(16)))
+    o = cpa.Opts(K=4).to_c()
+    o.damping = 5
+    st = cpa.lib().cpa_shrink_dense(ctypes.c_void_p(1), None, 4, 4, ctypes.c_void_p(16), 4, ctypes.c_void_p(4096), 4,
+                                    ctypes.byref(cpa.soft(1.0)), ctypes.byref(o), None)
+    assert st != 0

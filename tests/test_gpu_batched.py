@@ -164,6 +164,15 @@ def test_batched_rejects_out_of_range_shapes():
     assert list(status) == [2, 2, 0]
 
 
+def test_batched_rejects_damping():
+    """Coefficient damping is not available on the batched path (checked before
+    any launch)."""
+    import paper_1705_07112_amd as cpa
+    mats, shr_c, _, lams = _mats_and_params([(64, 40)], 13100)
+    with pytest.raises(cpa.CpaError):
+        _run(mats, shr_c, 8, "given", lams, power_kw={"damping": "jackson"})
+
+
 def test_converged_power_bound_matches_oracle_on_hard_cases():
     """Converged power bounds (tol 1e-12) on matrices whose iteration stops on the
     tolerance late, including one whose top two eigenvalues nearly coincide; the

@@ -310,3 +310,27 @@ def test_workspace_bytes_query():
     left = cpa.workspace_bytes(300, 100, cpa.Opts(K=8, side="left", eval="recurrence"))
     right = cpa.workspace_bytes(300, 100, cpa.Opts(K=8, eval="recurrence"))
     assert left - right >= 4 * (300 * 300 - 100 * 100)
+
+
+@pytest.mark.parametrize("damping", ["jackson", "lanczos"])
+@pytest.mark.parametrize("ev", ["recurrence", "polynomial"])
+def test_damped_coefficients_match_oracle(damping, ev):
+    """Coefficients times the Jackson or Lanczos factors (opts.damping; not in the
+    paper), including the high-order hard threshold (K = 64) it is meant for."""
+    torch = _torch()
+    cpa = _lib()
+    for (m, n), K, kind in (((130, 70), 64, 1), ((70, 130), 30, 0), ((256, 192), 64, 1)):
+        X = synth.as_f32_exact(synth.dense_lowrank(m, n, rank=4, noise=0.2, seed=7700 + m + K))
+        lmax = _gram_lmax(X)
+        Lam, tau = 1.01 * lmax, 0.4 * math.sqrt(lmax)
+        sh_o, sh_c = (Shrinkage(1, tau), cpa.hard(tau)) if kind == 1 else (Shrinkage(0, tau), cpa.soft(tau))
+        ref = ocpa.cpa_shrink(X, sh_o, Lam, K, damping=damping)
+        Y = cpa.shrink_dense(torch.from_numpy(X.astype(np.float32)).cuda(), sh_c,
+                             cpa.Opts(K=K, Lambda=Lam, eval=ev, damping=damping))
+        torch.cuda.synchronize()
+        err = metrics.rel_fro(Y.cpu().numpy().astype(np.float64), ref, X)
+        undamped = ocpa.cpa_shrink(X, sh_o, Lam, K)
+        print(f"damping {damping} {ev} {m}x{n} K={K} kind={kind}: rel_fro={err:.3e} "
+              f"(damped vs undamped oracle {metrics.rel_fro(ref, undamped, X):.2e})", flush=True)
+        assert err <= TOL32
+        assert metrics.rel_fro(ref, undamped, X) > 1e-4   # the damping changed the result

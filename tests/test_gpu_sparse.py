@@ -153,3 +153,18 @@ def test_csr_both_evaluation_routes(ev, m, n, frac, K):
     err = metrics.rel_fro(Y.astype(np.float64), ref, S)
     print(f"csr {m}x{n} K={K} eval={ev} rel_fro={err:.3e}", flush=True)
     assert err <= TOL32
+
+
+def test_csr_damped_coefficients_match_oracle():
+    import paper_1705_07112_amd as cpa
+    m, n, K = 300, 120, 40
+    rowptr, cols, vals, S = _random_csr(m, n, 0.05, 20400, empty_rows=(0,), empty_cols=(1,))
+    lmax = float(np.linalg.eigvalsh(S.T @ S)[-1])
+    Lam, tau = 1.01 * lmax, 0.3 * math.sqrt(lmax)
+    for ev in ("recurrence", "polynomial"):
+        Y = _gpu_csr(m, n, rowptr, cols, vals, cpa.hard(tau),
+                     cpa.Opts(K=K, Lambda=Lam, eval=ev, damping="jackson")).cpu().numpy()
+        ref = ocpa.cpa_shrink(S, Shrinkage(1, tau), Lam, K, damping="jackson")
+        err = metrics.rel_fro(Y, ref, S)
+        print(f"csr damped {ev}: rel_fro={err:.3e}", flush=True)
+        assert err <= TOL32
