@@ -89,7 +89,9 @@ typedef enum { CPA_BOUND_POWER = 0, CPA_BOUND_GIVEN = 1, CPA_BOUND_FROBENIUS = 2
  *                    even); A_hi B_hi + A_hi B_lo + A_lo B_hi on the BF16 matrix
  *                    cores with FP32 accumulation.  Y_k, the accumulator and the
  *                    coefficients stay FP32 / FP64. */
-typedef enum { CPA_PREC_FP32 = 0, CPA_PREC_BF16X3 = 1 } cpa_precision;
+typedef enum { CPA_PREC_FP32 = 0, CPA_PREC_BF16X3 = 1, CPA_PREC_FP64 = 2 } cpa_precision;
+/* CPA_PREC_FP64 is accepted by cpa_shrink_dense_f64 only (FP64 inputs and
+ * arithmetic); the FP32 entry points reject it. */
 
 /* How the polynomial hat H(Gram) = c_0/2 I + sum_k c_k T_k(hat B) reaches X (dense path).
  *   CPA_EVAL_RECURRENCE  the three-term recurrence distributed over X (Algorithm 1's
@@ -206,6 +208,20 @@ cpa_status cpa_shrink_dense(cpa_ctx* ctx, void* stream, int m, int n,
                             const float* X_dev, int64_t ldx, float* Y_dev, int64_t ldy,
                             const cpa_shrinkage* shrink, const cpa_opts* opts,
                             cpa_info* info_host);
+
+/* The same shrinkage with FP64 input, output and arithmetic (Algorithm 1, with
+ * the recurrence of eq. recurrence_our_method distributed over X as in the FP32
+ * path): FP64 Gram (side as opts->side), the bound and the coefficients in FP64
+ * (power iteration on the FP64 Gram), K - 1 FP64 products Y_k Gram (or Gram Y_k)
+ * each followed by the three-term update, the sum accumulated in Y_dev.
+ * opts->precision may be CPA_PREC_FP32 or CPA_PREC_FP64 (the arithmetic is FP64
+ * either way); eval RECURRENCE or AUTO (the matrix polynomial is FP32-only);
+ * check = 0.  Layout, aliasing, edge cases and synchronisation as
+ * cpa_shrink_dense.  Workspace: a d x d and three m x n FP64 buffers. */
+cpa_status cpa_shrink_dense_f64(cpa_ctx* ctx, void* stream, int m, int n,
+                                const double* X_dev, int64_t ldx, double* Y_dev, int64_t ldy,
+                                const cpa_shrinkage* shrink, const cpa_opts* opts,
+                                cpa_info* info_host);
 
 /* RPCA background modelling by ADMM (Appendix B, eq. admm_algorithm_mod) for
  *   min ||L||_* + eta ||S||_1  s.t.  I = L + S,   z = K [l; s], K = [[Id,0],[0,Id],[Id,Id]].

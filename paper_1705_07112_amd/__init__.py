@@ -27,7 +27,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "cpasvt.h")
 
 SOFT, HARD, WEIGHTED_CONST, WEIGHTED_FN = 0, 1, 2, 3
 BOUND_POWER, BOUND_GIVEN, BOUND_FROBENIUS = 0, 1, 2
-PREC_FP32, PREC_BF16X3 = 0, 1
+PREC_FP32, PREC_BF16X3, PREC_FP64 = 0, 1, 2
 
 
 class CpaShrinkage(ctypes.Structure):
@@ -89,6 +89,9 @@ _SIGS = {
     "cpa_spectral_bound": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _I64, ctypes.POINTER(CpaOpts),
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(CpaInfo)]),
     "cpa_shrink_dense": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _I64, _P, _I64,
+                                        ctypes.POINTER(CpaShrinkage), ctypes.POINTER(CpaOpts),
+                                        ctypes.POINTER(CpaInfo)]),
+    "cpa_shrink_dense_f64": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _I64, _P, _I64,
                                         ctypes.POINTER(CpaShrinkage), ctypes.POINTER(CpaOpts),
                                         ctypes.POINTER(CpaInfo)]),
     "cpa_rpca_state_floats": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int]),
@@ -197,7 +200,7 @@ class Opts:
     seed: int = 0
     check: bool = False
     growth_tol: float = 1e-3
-    precision: str = "fp32"      # "fp32" | "bf16x3"
+    precision: str = "fp32"      # "fp32" | "bf16x3" | "fp64" (FP64 inputs only)
     eval: str = "auto"           # "auto" | "recurrence" | "polynomial"
     side: str = "auto"           # "auto" | "right" (Gram X^T X) | "left" (Gram X X^T)
     damping: str = "none"        # "none" | "jackson" | "lanczos" (coefficient damping; not in the paper)
@@ -217,7 +220,7 @@ class Opts:
         o.margin = float(self.margin)
         o.seed = int(self.seed)
         o.check = int(bool(self.check))
-        o.precision = {"fp32": PREC_FP32, "bf16x3": PREC_BF16X3}[self.precision]
+        o.precision = {"fp32": PREC_FP32, "bf16x3": PREC_BF16X3, "fp64": PREC_FP64}[self.precision]
         o.growth_tol = float(self.growth_tol)
         o.eval = {"auto": 0, "recurrence": 1, "polynomial": 2}[self.eval]
         o.side = {"auto": 0, "right": 1, "left": 2}[self.side]
@@ -243,10 +246,11 @@ def _stream(t):
     return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
 
 
-def _mat(t, name):
+def _mat(t, name, dtypes=("float32",)):
     import torch
-    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or t.dim() != 2:
-        raise TypeError(f"{name} must be a 2-D float32 CUDA tensor")
+    ok = tuple(getattr(torch, d) for d in dtypes)
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype not in ok or t.dim() != 2:
+        raise TypeError(f"{name} must be a 2-D {' or '.join(dtypes)} CUDA tensor")
     if t.stride(1) != 1:
         raise ValueError(f"{name} must have unit column stride (row-major)")
     return t.shape[0], t.shape[1], max(t.stride(0), t.shape[1])
@@ -267,19 +271,21 @@ def damping_factors(K: int, kind: str = "jackson"):
 
 
 def shrink_dense(X, shrink: CpaShrinkage, opts: Opts, out=None, info: bool = False):
-    """Y = hat G(X) (Algorithm 1 with T = Id).  Returns Y, or (Y, info dict)."""
+    """Y = hat G(X) (Algorithm 1 with T = Id).  float32 X: cpa_shrink_dense;
+    float64 X: cpa_shrink_dense_f64 (FP64 arithmetic).  Returns Y, or (Y, info dict)."""
     import torch
-    m, n, ldx = _mat(X, "X")
+    m, n, ldx = _mat(X, "X", ("float32", "float64"))
     if out is None:
-        out = torch.empty((m, n), device=X.device, dtype=torch.float32)
-    _, _, ldy = _mat(out, "out")
-    if tuple(out.shape) != (m, n):
-        raise ValueError("out has the wrong shape")
+        out = torch.empty((m, n), device=X.device, dtype=X.dtype)
+    _, _, ldy = _mat(out, "out", ("float32", "float64"))
+    if tuple(out.shape) != (m, n) or out.dtype != X.dtype:
+        raise ValueError("out has the wrong shape or dtype")
     ci = CpaInfo()
     co = opts.to_c()
-    _check(lib().cpa_shrink_dense(ctypes.c_void_p(context(X.device.index or 0)), _stream(X), m, n,
-                                  ctypes.c_void_p(X.data_ptr()), ldx, ctypes.c_void_p(out.data_ptr()), ldy,
-                                  ctypes.byref(shrink), ctypes.byref(co), ctypes.byref(ci) if info else None))
+    fn = lib().cpa_shrink_dense_f64 if X.dtype == torch.float64 else lib().cpa_shrink_dense
+    _check(fn(ctypes.c_void_p(context(X.device.index or 0)), _stream(X), m, n, ctypes.c_void_p(X.data_ptr()), ldx,
+              ctypes.c_void_p(out.data_ptr()), ldy, ctypes.byref(shrink), ctypes.byref(co),
+              ctypes.byref(ci) if info else None))
     return (out, ci.as_dict()) if info else out
 
 

@@ -21,6 +21,7 @@
 #include "sparse.hpp"
 #include "sparsify.hpp"
 #include "inpaint.hpp"
+#include "fp64.hpp"
 #include "gemm_bf16x3.hpp"
 #include "gemm_f32.hpp"
 #include "gemm_lds.hpp"
@@ -75,6 +76,8 @@ struct cpa_ctx {
     size_t spf_bytes = 0;
     void* inp = nullptr;       // inpainting driver: DCT matrices, product scratch, partial sums
     size_t inp_bytes = 0;
+    void* f64 = nullptr;       // FP64 shrink: Gram, two Y buffers, product buffer
+    size_t f64_bytes = 0;
     int batch_per_cu = 0;      // co-resident workgroups of the batched kernel per CU (0: not queried)
     int cus = 0;
     int* queue = nullptr;      // work-queue counter of the batched kernel
@@ -162,7 +165,7 @@ cpa_status ensure_ws(cpa_ctx* ctx, int m, int n, int K, int maxit, bool admm, Wo
     const int64_t mn = (int64_t)m * n;
     if (ctx->coop_max == 0) {
         int per_cu = 0, cus = 0;
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, power_coop_kernel, kPowerThreads, 0));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, power_coop_kernel<float>, kPowerThreads, 0));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
         ctx->coop_max = std::max(1, per_cu * cus);
     }
@@ -397,8 +400,9 @@ cpa_status enqueue_gram_impl(hipStream_t st, int m, int n, const float* X, int64
     return gemm_dispatch<KCONTIG, KCONTIG>(st, A, B, m, m, n, epi, 0, 0, 0);
 }
 
+// G64 != nullptr: the power iteration reads that FP64 Gram (pitch d) instead of w.G.
 cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkage* sh, const cpa_opts* o,
-                         const Work& w, int mode_override) {
+                         const Work& w, int mode_override, const double* G64 = nullptr) {
     int mode = o->bound == CPA_BOUND_POWER ? 0 : (o->bound == CPA_BOUND_GIVEN ? 1 : 2);
     if (mode_override >= 0) mode = mode_override;
     if (mode == 0) {
@@ -415,9 +419,15 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
         unsigned* counter = reinterpret_cast<unsigned*>(w.scal + SC_BARRIER);
         double* scal = w.scal;
         double tol = o->power_tol;
-        void* args[] = {&d_, &G, &ldg, &wb0, &wb1, &part, &counter, &scal, &maxit_, &tol, &pw_mu, &pw_w2};
-        HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(power_coop_kernel), dim3(w.lay.pwg),
-                                           dim3(kPowerThreads), args, 0, st));
+        if (G64) {
+            void* args[] = {&d_, &G64, &ldg, &wb0, &wb1, &part, &counter, &scal, &maxit_, &tol, &pw_mu, &pw_w2};
+            HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(power_coop_kernel<double>),
+                                               dim3(w.lay.pwg), dim3(kPowerThreads), args, 0, st));
+        } else {
+            void* args[] = {&d_, &G, &ldg, &wb0, &wb1, &part, &counter, &scal, &maxit_, &tol, &pw_mu, &pw_w2};
+            HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(power_coop_kernel<float>),
+                                               dim3(w.lay.pwg), dim3(kPowerThreads), args, 0, st));
+        }
     }
     hipLaunchKernelGGL(finish_bound_kernel, dim3(1), dim3(256), 0, st, mode, o->Lambda, d, o->power_iters, o->margin,
                        (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? ctx->warm : nullptr, w.scal,
@@ -707,7 +717,7 @@ cpa_status ensure_sparse_ws(cpa_ctx* ctx, int m, int n, int64_t nnz, int K, int 
                             int poly_s = 0) {
     if (ctx->coop_max == 0) {
         int per_cu = 0, cus = 0;
-        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, power_coop_kernel, kPowerThreads, 0));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, power_coop_kernel<float>, kPowerThreads, 0));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
         ctx->coop_max = std::max(1, per_cu * cus);
     }
@@ -999,6 +1009,7 @@ cpa_status cpa_destroy(cpa_ctx* ctx) {
     if (ctx->queue) (void)hipFree(ctx->queue);
     if (ctx->spf) (void)hipFree(ctx->spf);
     if (ctx->inp) (void)hipFree(ctx->inp);
+    if (ctx->f64) (void)hipFree(ctx->f64);
     if (ctx->mlp_ws) (void)hipFree(ctx->mlp_ws);
     if (ctx->sws) (void)hipFree(ctx->sws);
     if (ctx->csc) (void)hipFree(ctx->csc);
@@ -2426,6 +2437,131 @@ cpa_status cpa_inpaint_iterate(cpa_ctx* ctx, void* stream, int m, int n, const f
         hipLaunchKernelGGL(inp_post_kernel, dim3(grid), dim3(256), 0, st, P, mn, (float)eta_over_rho,
                            (const double*)f.part, grid, (const double*)f.cst, Et_dev, f.counter);
         HIP_TRY(hipGetLastError());
+    }
+    return CPA_OK;
+}
+
+}  // extern "C"
+
+// ---- FP64 dense shrinkage ----
+
+namespace {
+
+struct F64Work {
+    double* G;      // d x d
+    double* Yb[2];  // m x n: Y_k ping-pong (Y_0 = a copy of X)
+    double* Z;      // m x n product
+};
+
+cpa_status ensure_f64(cpa_ctx* ctx, int d, int m, int n, F64Work& f) {
+    const size_t dd = (size_t)d * d, mn = (size_t)m * n;
+    size_t off = 0;
+    const size_t oG = off; off = align_up(off + sizeof(double) * dd);
+    const size_t oY0 = off; off = align_up(off + sizeof(double) * mn);
+    const size_t oY1 = off; off = align_up(off + sizeof(double) * mn);
+    const size_t oZ = off; off = align_up(off + sizeof(double) * mn);
+    if (off > ctx->f64_bytes) {
+        if (ctx->f64) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipFree(ctx->f64));
+            ctx->f64 = nullptr;
+            ctx->f64_bytes = 0;
+        }
+        if (hipMalloc(&ctx->f64, off) != hipSuccess) {
+            ctx->f64 = nullptr;
+            return fail(CPA_ERR_ALLOC, "FP64 workspace allocation of %zu bytes failed", off);
+        }
+        ctx->f64_bytes = off;
+    }
+    char* b = static_cast<char*>(ctx->f64);
+    f.G = reinterpret_cast<double*>(b + oG);
+    f.Yb[0] = reinterpret_cast<double*>(b + oY0);
+    f.Yb[1] = reinterpret_cast<double*>(b + oY1);
+    f.Z = reinterpret_cast<double*>(b + oZ);
+    return CPA_OK;
+}
+
+template <bool TA, bool TB>
+cpa_status gemm64(hipStream_t st, int M, int N, int Kd, const double* A, int64_t lda, const double* B, int64_t ldb,
+                  double* C, int64_t ldc) {
+    const dim3 grid((N + F64_BN - 1) / F64_BN, (M + F64_BM - 1) / F64_BM);
+    hipLaunchKernelGGL((gemm_f64_kernel<TA, TB>), grid, dim3(256), 0, st, M, N, Kd, A, lda, B, ldb, C, ldc);
+    HIP_TRY(hipGetLastError());
+    return CPA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cpa_status cpa_shrink_dense_f64(cpa_ctx* ctx, void* stream, int m, int n, const double* X_dev, int64_t ldx,
+                                double* Y_dev, int64_t ldy, const cpa_shrinkage* shrink, const cpa_opts* opts_in,
+                                cpa_info* info_host) {
+    cpa_status s;
+    if ((s = check_dense_args(ctx, m, n, reinterpret_cast<const float*>(X_dev), ldx)) != CPA_OK) return s;
+    if ((s = check_shrinkage(shrink)) != CPA_OK) return s;
+    if (!opts_in) return fail(CPA_ERR_ARG, "opts is NULL");
+    cpa_opts o = *opts_in;
+    if (o.precision == CPA_PREC_FP64) o.precision = CPA_PREC_FP32;   // the arithmetic here is FP64 in any case
+    if ((s = check_opts(&o)) != CPA_OK) return s;
+    if (o.precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "the FP64 path has no split precision");
+    if (o.check) return fail(CPA_ERR_UNSUPPORTED, "the growth check is not available on the FP64 path");
+    if (o.eval == CPA_EVAL_POLYNOMIAL) return fail(CPA_ERR_UNSUPPORTED, "the FP64 path evaluates by the recurrence");
+    if (m == 0 || n == 0) {
+        if (info_host) std::memset(info_host, 0, sizeof(*info_host));
+        return CPA_OK;
+    }
+    if (!Y_dev) return fail(CPA_ERR_ARG, "Y is NULL");
+    if (ldy < n) return fail(CPA_ERR_SHAPE, "ldy < n");
+    if (overlaps(X_dev, sizeof(double) * ((size_t)(m - 1) * ldx + n), Y_dev, sizeof(double) * ((size_t)(m - 1) * ldy + n)))
+        return fail(CPA_ERR_ARG, "Y overlaps X");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool right = right_side(&o, m, n);
+    const int d = right ? n : m;
+    Work w;
+    const int maxit = o.bound == CPA_BOUND_POWER ? o.power_iters : 1;
+    if ((s = ensure_ws(ctx, m, n, o.K, maxit, false, w, right, 0)) != CPA_OK) return s;
+    F64Work f;
+    if ((s = ensure_f64(ctx, d, m, n, f)) != CPA_OK) return s;
+    if ((s = fill_scalars(st, w)) != CPA_OK) return s;
+    // Gram X^T X (n x n) or X X^T (m x m), FP64
+    if (right)
+        s = gemm64<true, false>(st, n, n, m, X_dev, ldx, X_dev, ldx, f.G, n);
+    else
+        s = gemm64<false, true>(st, m, m, n, X_dev, ldx, X_dev, ldx, f.G, m);
+    if (s != CPA_OK) return s;
+    hipLaunchKernelGGL(gram64_stats_kernel, dim3(w.lay.gwg), dim3(256), 0, st, d, (const double*)f.G,
+                       w.scal + w.lay.gpart());
+    HIP_TRY(hipGetLastError());
+    if ((s = enqueue_bound(ctx, st, d, shrink, &o, w, -1, f.G)) != CPA_OK) return s;
+    const int64_t mn = (int64_t)m * n;
+    const int ge = (int)std::min<int64_t>(4096, (mn + 255) / 256);
+    if (o.K == 1) {
+        hipLaunchKernelGGL(scale64_kernel, dim3(ge), dim3(256), 0, st, m, n, X_dev, ldx, Y_dev, ldy,
+                           (const double*)w.scal);
+        HIP_TRY(hipGetLastError());
+    } else {
+        hipLaunchKernelGGL(copy64_kernel, dim3(ge), dim3(256), 0, st, m, n, X_dev, ldx, f.Yb[0]);
+        HIP_TRY(hipGetLastError());
+        int cur = 0;
+        for (int k = 0; k + 1 <= o.K - 1; ++k) {
+            const double* yk = f.Yb[cur];
+            // Z = Y_k G (right) or G Y_k (left)
+            if (right)
+                s = gemm64<false, false>(st, m, n, n, yk, n, f.G, n, f.Z, n);
+            else
+                s = gemm64<false, false>(st, m, n, m, f.G, m, yk, n, f.Z, n);
+            if (s != CPA_OK) return s;
+            hipLaunchKernelGGL(cheb64_step_kernel, dim3(ge), dim3(256), 0, st, m, n, (const double*)f.Z, yk,
+                               (int64_t)n, f.Yb[cur ^ 1], Y_dev, ldy, (const double*)w.scal, k);
+            HIP_TRY(hipGetLastError());
+            cur ^= 1;
+        }
+    }
+    if (info_host) {
+        if ((s = read_info(st, w, o.K, m, n, info_host, nullptr)) != CPA_OK) return s;
+        info_host->side = right ? 0 : 1;
     }
     return CPA_OK;
 }

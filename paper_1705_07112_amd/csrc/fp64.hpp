@@ -1,0 +1,145 @@
+// FP64 shrinkage (the dense path with FP64 inputs, outputs and arithmetic):
+// the Gram, Algorithm 1's recurrence distributed over X (Y_{k+1} = 2 Y_k Ghat -
+// Y_{k-1}, Ghat = (2/Lambda) G - I, out = c_0/2 X + sum c_k Y_k; eq.
+// recurrence_our_method) and the Gram statistics of the Frobenius bound, all in
+// double precision.  The bound and the coefficients come from the same FP64
+// kernels as the FP32 path (power iteration on the FP64 Gram).
+//
+// gemm_f64_kernel: C = op(A) op(B) with 64 x 64 output tiles, K-steps of 16,
+// 256 threads each holding a 4 x 4 block of FP64 accumulators; operand tiles go
+// through LDS with zero fill outside the matrix.  op(A)[i][k] is A[k][i] when TA
+// (the Gram X^T X reads X transposed), op(B)[k][j] is B[j][k] when TB (X X^T).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spectral.hpp"
+
+namespace cpa {
+
+constexpr int F64_BM = 64, F64_BN = 64, F64_BK = 16;
+
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) gemm_f64_kernel(int M, int N, int Kd, const double* A, int64_t lda,
+                                                       const double* B, int64_t ldb, double* C, int64_t ldc) {
+    __shared__ double As[F64_BK][F64_BM + 1];   // [k][i]
+    __shared__ double Bs[F64_BK][F64_BN + 1];   // [k][j]
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+    const int i0 = blockIdx.y * F64_BM, j0 = blockIdx.x * F64_BN;
+    double acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+    for (int k0 = 0; k0 < Kd; k0 += F64_BK) {
+        // consecutive threads read consecutive addresses of each operand
+        for (int e = tid; e < F64_BM * F64_BK; e += 256) {
+            const int ii = TA ? e % F64_BM : e / F64_BK;
+            const int kk = TA ? e / F64_BM : e % F64_BK;
+            const int gi = i0 + ii, gk = k0 + kk;
+            double v = 0.0;
+            if (gi < M && gk < Kd) v = TA ? A[(int64_t)gk * lda + gi] : A[(int64_t)gi * lda + gk];
+            As[kk][ii] = v;
+        }
+        for (int e = tid; e < F64_BN * F64_BK; e += 256) {
+            const int jj = TB ? e / F64_BK : e % F64_BN;
+            const int kk = TB ? e % F64_BK : e / F64_BN;
+            const int gj = j0 + jj, gk = k0 + kk;
+            double v = 0.0;
+            if (gj < N && gk < Kd) v = TB ? B[(int64_t)gj * ldb + gk] : B[(int64_t)gk * ldb + gj];
+            Bs[kk][jj] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < F64_BK; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = As[kk][ty * 4 + r];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx * 4 + c];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = i0 + ty * 4 + r;
+        if (i >= M) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int j = j0 + tx * 4 + c;
+            if (j < N) C[(int64_t)i * ldc + j] = acc[r][c];
+        }
+    }
+}
+
+// One recurrence step on an m x n matrix, element (r, c) per thread:
+//   step 0: Y_1 = a1 Z - X,               out = c_0/2 X + c_1 Y_1
+//   step k: Y_{k+1} = a2 Z - 2 Y_k - Y_{k-1}, out += c_{k+1} Y_{k+1}
+// Z = Y_k G (or G Y_k); Yk has pitch ldk (X at step 0), Yo holds Y_{k-1} and
+// receives Y_{k+1} (pitch n, same element, same thread); out has pitch ldo.
+__global__ void __launch_bounds__(256) cheb64_step_kernel(int m, int n, const double* Z, const double* Yk, int64_t ldk,
+                                                          double* Yo, double* out, int64_t ldo, const double* scal,
+                                                          int step) {
+    const double a = step == 0 ? scal[SC_A1] : scal[SC_A2];
+    const double ck = scal[SC_COEF + step + 1];
+    const double c0h = 0.5 * scal[SC_COEF];
+    const int64_t total = (int64_t)m * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / n, c = e % n;
+        const double yk = Yk[r * ldk + c];
+        double y;
+        if (step == 0) {
+            y = a * Z[e] - yk;
+            out[r * ldo + c] = c0h * yk + ck * y;
+        } else {
+            y = a * Z[e] - 2.0 * yk - Yo[e];
+            out[r * ldo + c] += ck * y;
+        }
+        Yo[e] = y;
+    }
+}
+
+// dst (pitch n) = X (pitch ldx).
+__global__ void __launch_bounds__(256) copy64_kernel(int m, int n, const double* X, int64_t ldx, double* dst) {
+    const int64_t total = (int64_t)m * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+        dst[e] = X[(e / n) * ldx + e % n];
+}
+
+// out = c_0/2 X (K = 1).
+__global__ void __launch_bounds__(256) scale64_kernel(int m, int n, const double* X, int64_t ldx, double* out,
+                                                      int64_t ldo, const double* scal) {
+    const double c0h = 0.5 * scal[SC_COEF];
+    const int64_t total = (int64_t)m * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / n, c = e % n;
+        out[r * ldo + c] = c0h * X[r * ldx + c];
+    }
+}
+
+// Per-workgroup partials of ||G||_F^2 and tr G (d x d, pitch d), 2 per workgroup,
+// in the layout the bound kernel reads.
+__global__ void __launch_bounds__(256) gram64_stats_kernel(int d, const double* G, double* gpart) {
+    __shared__ double red[8];
+    double f2 = 0.0, tr = 0.0;
+    const int64_t total = (int64_t)d * d;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const double g = G[e];
+        f2 += g * g;
+        if (e / d == e % d) tr += g;
+    }
+    f2 = block_sum(f2, red);
+    tr = block_sum(tr, red);
+    if (threadIdx.x == 0) {
+        gpart[2 * blockIdx.x] = f2;
+        gpart[2 * blockIdx.x + 1] = tr;
+    }
+}
+
+}  // namespace cpa

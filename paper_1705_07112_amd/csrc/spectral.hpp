@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "shrink_fn.hpp"
 
 namespace cpa {
@@ -179,7 +181,9 @@ __device__ inline double ordered_sum(const double* part, int n, double* red) {
 // that the matvec reads it with agent-scope loads).
 constexpr int kPowerVecLds = 4096;
 
-__global__ void __launch_bounds__(kPowerThreads) power_coop_kernel(int d, const float* G, int64_t ldg, double* wb0,
+// TG: the Gram's element type (float, or double for the FP64 path).
+template <class TG>
+__global__ void __launch_bounds__(kPowerThreads) power_coop_kernel(int d, const TG* G, int64_t ldg, double* wb0,
                                                                    double* wb1, double* part, unsigned* counter,
                                                                    double* scal, int maxit, double tol, int pw_mu,
                                                                    int pw_w2) {
@@ -207,23 +211,26 @@ __global__ void __launch_bounds__(kPowerThreads) power_coop_kernel(int d, const 
         double* wn = (t & 1) ? wb1 : wb0;         // w_t
         const double inv = 1.0 / sqrt(w2prev);
         double mu_part = 0.0, w2_part = 0.0;
-        const bool vec = ((ldg & 3) == 0) && ((reinterpret_cast<uintptr_t>(G) & 15) == 0) && in_lds;
+        const bool vec = std::is_same<TG, float>::value && ((ldg & 3) == 0) &&
+                         ((reinterpret_cast<uintptr_t>(G) & 15) == 0) && in_lds;
         for (int i = gw; i < d; i += nw) {
-            const float* row = G + (int64_t)i * ldg;
+            const TG* row = G + (int64_t)i * ldg;
             // four independent partial sums, 16-byte loads of G when rows are aligned,
             // several loads in flight per lane (the sum is scaled by 1/||w|| at the end)
             double a[4] = {0.0, 0.0, 0.0, 0.0};
             int j = 4 * lane;
-            if (vec) {
+            if constexpr (std::is_same<TG, float>::value) {
+                if (vec) {
 #pragma unroll 4
-                for (; j + 3 < d; j += 256) {
-                    const f32x4 g = *reinterpret_cast<const f32x4*>(row + j);
-                    const double2 v01 = *reinterpret_cast<const double2*>(vl + j);
-                    const double2 v23 = *reinterpret_cast<const double2*>(vl + j + 2);
-                    a[0] += (double)g[0] * v01.x;
-                    a[1] += (double)g[1] * v01.y;
-                    a[2] += (double)g[2] * v23.x;
-                    a[3] += (double)g[3] * v23.y;
+                    for (; j + 3 < d; j += 256) {
+                        const f32x4 g = *reinterpret_cast<const f32x4*>(row + j);
+                        const double2 v01 = *reinterpret_cast<const double2*>(vl + j);
+                        const double2 v23 = *reinterpret_cast<const double2*>(vl + j + 2);
+                        a[0] += (double)g[0] * v01.x;
+                        a[1] += (double)g[1] * v01.y;
+                        a[2] += (double)g[2] * v23.x;
+                        a[3] += (double)g[3] * v23.y;
+                    }
                 }
             }
             for (; j < d; j += 256)
