@@ -691,6 +691,25 @@ def main():
                      "recurrence_avg_us": round(1e3 * rec2_ms / max(rec2_n, 1), 3),
                      "note": "same ADMM workload; recurrence products as bf16 hi/lo x3 on the BF16 matrix cores"}
 
+    # FP64 path: one shrink of the 1024 x 1024 frames in double precision (recurrence,
+    # K = 30, power bound), timed over a few calls
+    X64d = Id.to(torch.float64)
+    o64 = cpa.Opts(K=K, precision="fp64")
+    cpa.shrink_dense(X64d, cpa.soft(INV_RHO), o64)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(3):
+        cpa.shrink_dense(X64d, cpa.soft(INV_RHO), o64)
+    t1.record()
+    torch.cuda.synchronize()
+    ms64 = t0.elapsed_time(t1) / 3
+    flop64 = K * flop_gemm   # Gram + K - 1 recurrence products
+    out["fp64"] = {"ms_per_shrink": round(ms64, 3), "shrinks_per_s": round(1e3 / ms64, 2),
+                   "tflops": round(flop64 / (ms64 * 1e-3) / 1e12, 2), "peak_fp64_tflops": 78.6,
+                   "note": "cpa_shrink_dense_f64 on the 1024 x 1024 frames: FP64 Gram, power bound and K - 1 = 29 "
+                           "FP64 products (LDS-tiled FP64 FMA kernel)"}
+    del X64d
+
     check = None
     if not args.no_accuracy:
         # one shrink of the current ADMM iterate (L + U1) on the device, against the
