@@ -248,6 +248,17 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
                             float* state_dev, int iters, double inv_rho, double eta_over_rho,
                             const cpa_opts* opts, double* Et_dev);
 
+/* The same ADMM in one call: from the start state, iterations until
+ * E_t <= tol (the paper's stopping rule, Sec. V-B) or max_iters, then L and S
+ * (m x n, contiguous, caller-owned) receive the result.  E_t is checked after
+ * every iteration, so the call synchronises the stream once per iteration and
+ * stops at the first iteration with E_t <= tol; Et_host (max_iters doubles,
+ * nullable) receives E_1, E_2, ... and *iters_done the number of iterations run.
+ * The state lives in the context (7 m n floats).  I, L and S must not overlap. */
+cpa_status cpa_rpca_admm(cpa_ctx* ctx, void* stream, int m, int n, const float* I_dev, float* L_dev,
+                         float* S_dev, double inv_rho, double eta_over_rho, int max_iters, double tol,
+                         const cpa_opts* opts, double* Et_host, int* iters_done);
+
 /* Texture inpainting by ADMM (Sec. V-C, eq. texture_repaire4; Appendix A,
  * eq. admm_algorithm_inp) for
  *   min ||L||_* + eta ||Psi l||_1 + iota_I(Omega l) + iota_D(l) + iota_M(Omega_bar l),

@@ -95,6 +95,9 @@ _SIGS = {
                                         ctypes.POINTER(CpaShrinkage), ctypes.POINTER(CpaOpts),
                                         ctypes.POINTER(CpaInfo)]),
     "cpa_rpca_state_floats": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int]),
+    "cpa_rpca_admm": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _P, _P, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_int, ctypes.c_double, ctypes.POINTER(CpaOpts), _P,
+                                     ctypes.POINTER(ctypes.c_int)]),
     "cpa_inpaint_state_floats": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int]),
     "cpa_inpaint_init": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "cpa_inpaint_iterate": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, ctypes.c_int,
@@ -543,6 +546,24 @@ def timing_read(which: str = "recurrence", device: int = 0):
     _check(lib().cpa_timing_read(ctypes.c_void_p(context(device)), {"recurrence": 0, "gram": 1}[which],
                                  ctypes.byref(ms), ctypes.byref(cnt)))
     return ms.value, cnt.value
+
+
+def rpca_admm(I, inv_rho: float, eta_over_rho: float, max_iters: int, tol: float, opts: Opts):
+    """RPCA by ADMM in one call (cpa_rpca_admm): returns (L, S, E_t list, iterations)."""
+    import torch
+    m, n, ld = _mat(I, "I")
+    if ld != n:
+        raise ValueError("I must be contiguous")
+    L = torch.empty((m, n), device=I.device, dtype=torch.float32)
+    S = torch.empty_like(L)
+    Et = (ctypes.c_double * max(int(max_iters), 1))()
+    done = ctypes.c_int()
+    co = opts.to_c()
+    _check(lib().cpa_rpca_admm(ctypes.c_void_p(context(I.device.index or 0)), _stream(I), m, n,
+                               ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(L.data_ptr()),
+                               ctypes.c_void_p(S.data_ptr()), float(inv_rho), float(eta_over_rho), int(max_iters),
+                               float(tol), ctypes.byref(co), Et, ctypes.byref(done)))
+    return L, S, list(Et[:done.value]), done.value
 
 
 class Inpaint:

@@ -78,6 +78,8 @@ struct cpa_ctx {
     size_t inp_bytes = 0;
     void* f64 = nullptr;       // FP64 shrink: Gram, two Y buffers, product buffer
     size_t f64_bytes = 0;
+    void* rpca = nullptr;      // one-call RPCA driver: its state and E_t slot
+    size_t rpca_bytes = 0;
     int batch_per_cu = 0;      // co-resident workgroups of the batched kernel per CU (0: not queried)
     int cus = 0;
     int* queue = nullptr;      // work-queue counter of the batched kernel
@@ -1010,6 +1012,7 @@ cpa_status cpa_destroy(cpa_ctx* ctx) {
     if (ctx->spf) (void)hipFree(ctx->spf);
     if (ctx->inp) (void)hipFree(ctx->inp);
     if (ctx->f64) (void)hipFree(ctx->f64);
+    if (ctx->rpca) (void)hipFree(ctx->rpca);
     if (ctx->mlp_ws) (void)hipFree(ctx->mlp_ws);
     if (ctx->sws) (void)hipFree(ctx->sws);
     if (ctx->csc) (void)hipFree(ctx->csc);
@@ -2563,6 +2566,64 @@ cpa_status cpa_shrink_dense_f64(cpa_ctx* ctx, void* stream, int m, int n, const 
         if ((s = read_info(st, w, o.K, m, n, info_host, nullptr)) != CPA_OK) return s;
         info_host->side = right ? 0 : 1;
     }
+    return CPA_OK;
+}
+
+}  // extern "C"
+
+// ---- One-call RPCA driver ----
+
+extern "C" {
+
+cpa_status cpa_rpca_admm(cpa_ctx* ctx, void* stream, int m, int n, const float* I_dev, float* L_dev, float* S_dev,
+                         double inv_rho, double eta_over_rho, int max_iters, double tol, const cpa_opts* opts,
+                         double* Et_host, int* iters_done) {
+    cpa_status s;
+    if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
+    if (m < 0 || n < 0) return fail(CPA_ERR_SHAPE, "negative size");
+    if (max_iters < 0) return fail(CPA_ERR_ARG, "max_iters < 0");
+    if (!(tol >= 0.0)) return fail(CPA_ERR_ARG, "tol must be >= 0");
+    if ((s = check_opts(opts)) != CPA_OK) return s;
+    if (iters_done) *iters_done = 0;
+    if (m == 0 || n == 0 || max_iters == 0) return CPA_OK;
+    if (!I_dev || !L_dev || !S_dev) return fail(CPA_ERR_ARG, "I, L or S is NULL");
+    const int64_t mn = (int64_t)m * n;
+    const size_t b = sizeof(float) * (size_t)mn;
+    if (overlaps(L_dev, b, S_dev, b) || overlaps(L_dev, b, I_dev, b) || overlaps(S_dev, b, I_dev, b))
+        return fail(CPA_ERR_ARG, "I, L and S must not overlap");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t need = align_up(sizeof(float) * 7 * (size_t)mn) + sizeof(double);
+    if (need > ctx->rpca_bytes) {
+        if (ctx->rpca) {
+            HIP_TRY(hipDeviceSynchronize());
+            HIP_TRY(hipFree(ctx->rpca));
+            ctx->rpca = nullptr;
+            ctx->rpca_bytes = 0;
+        }
+        if (hipMalloc(&ctx->rpca, need) != hipSuccess) {
+            ctx->rpca = nullptr;
+            return fail(CPA_ERR_ALLOC, "RPCA state allocation of %zu bytes failed", need);
+        }
+        ctx->rpca_bytes = need;
+    }
+    float* state = static_cast<float*>(ctx->rpca);
+    double* et_dev = reinterpret_cast<double*>(static_cast<char*>(ctx->rpca) + align_up(sizeof(float) * 7 * (size_t)mn));
+    if ((s = cpa_rpca_init(ctx, stream, m, n, state)) != CPA_OK) return s;
+    int t = 0;
+    while (t < max_iters) {
+        if ((s = cpa_rpca_iterate(ctx, stream, m, n, I_dev, state, 1, inv_rho, eta_over_rho, opts, et_dev)) != CPA_OK)
+            return s;
+        double e = 0.0;
+        HIP_TRY(hipMemcpyAsync(&e, et_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (Et_host) Et_host[t] = e;
+        ++t;
+        if (e <= tol) break;
+    }
+    if (iters_done) *iters_done = t;
+    HIP_TRY(hipMemcpyAsync(L_dev, state, b, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(S_dev, state + mn, b, hipMemcpyDeviceToDevice, st));
     return CPA_OK;
 }
 

@@ -77,3 +77,29 @@ def test_admm_drift_is_small():
     print(f"  drift after {iters}: l {el:.2e} s {es:.2e}", flush=True)
     assert el < 1e-3 and es < 1e-2
     assert np.max(np.abs(Et.cpu().numpy() - np.array(E_o)) / np.array(E_o)) < 1e-2
+
+
+def test_rpca_one_call_stops_at_tolerance():
+    """cpa_rpca_admm: stops at the first iteration with E_t <= tol, and its L, S
+    and E_t history equal those of the same number of iterations run with the
+    init/iterate pair (cold power bound every iteration, so both runs are the
+    same computation)."""
+    import torch
+    import paper_1705_07112_amd as cpa
+    I, _, _ = synth.rpca_frames(96, 80, rank=10, outlier_frac=0.05, seed=31)
+    Id = torch.from_numpy(I).cuda()
+    opts = cpa.Opts(K=20, warm_start=False, power_iters=100)
+    tol = 5e-3
+    L, S, E, t = cpa.rpca_admm(Id, 1.0, 1.0 / np.sqrt(96), 300, tol, opts)
+    print(f"rpca one call: {t} iterations, E_last={E[-1]:.3e}", flush=True)
+    assert 1 < t < 300 and len(E) == t
+    assert E[-1] <= tol and all(e > tol for e in E[:-1])
+    run = cpa.RpcaAdmm(Id, 1.0, 1.0 / np.sqrt(96), opts)
+    Et = torch.zeros(t, dtype=torch.float64, device="cuda")
+    run.iterate(t, Et)
+    torch.cuda.synchronize()
+    assert torch.equal(L, run.L) and torch.equal(S, run.S)
+    assert np.array_equal(np.array(E), Et.cpu().numpy())
+    # max_iters caps the run
+    _, _, E2, t2 = cpa.rpca_admm(Id, 1.0, 1.0 / np.sqrt(96), 3, 0.0, opts)
+    assert t2 == 3 and len(E2) == 3
