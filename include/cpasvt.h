@@ -50,7 +50,8 @@ typedef enum {
     CPA_ERR_HIP = 4,          /* a HIP runtime call failed */
     CPA_ERR_NONFINITE = 5,    /* a spectral bound came out NaN or infinite */
     CPA_ERR_BOUND = 6,        /* growth check failed even with the guaranteed bound */
-    CPA_ERR_UNSUPPORTED = 7   /* option combination not supported */
+    CPA_ERR_UNSUPPORTED = 7,  /* option combination not supported */
+    CPA_ERR_IO = 8            /* a file could not be read or written, or is not a model file */
 } cpa_status;
 
 /* Members of the shrinkage family of Sec. IV-A (eq. filter_response_ours),
@@ -483,6 +484,13 @@ cpa_status cpa_shrink_batched_predicted(cpa_ctx* ctx, void* stream, int batch, c
                                         const cpa_shrinkage* shrink_host, const cpa_opts* opts,
                                         const float* model_dev, int32_t K_min, double* Lambda_out_dev,
                                         int32_t* K_out_dev, int32_t* status_dev);
+
+/* Model files (host file IO, synchronising): magic "CPAPRED1", int32 version 1,
+ * int32 count = CPA_PRED_MODEL_FLOATS, then the floats (little-endian).  Load
+ * checks the magic, the version and the count (CPA_ERR_IO otherwise) before it
+ * writes model_dev. */
+cpa_status cpa_predictor_save(cpa_ctx* ctx, void* stream, const float* model_dev, const char* path);
+cpa_status cpa_predictor_load(cpa_ctx* ctx, void* stream, const char* path, float* model_dev);
 
 /* Network outputs for n feature rows: y_dev (n x 2) = net(feat_dev (n x 3)).
  * Asynchronous. */

@@ -95,6 +95,8 @@ _SIGS = {
                                         ctypes.POINTER(CpaShrinkage), ctypes.POINTER(CpaOpts),
                                         ctypes.POINTER(CpaInfo)]),
     "cpa_rpca_state_floats": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int]),
+    "cpa_predictor_save": (ctypes.c_int, [_P, _P, _P, ctypes.c_char_p]),
+    "cpa_predictor_load": (ctypes.c_int, [_P, _P, ctypes.c_char_p, _P]),
     "cpa_rpca_admm": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _P, _P, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_int, ctypes.c_double, ctypes.POINTER(CpaOpts), _P,
                                      ctypes.POINTER(ctypes.c_int)]),

@@ -1031,6 +1031,7 @@ const char* cpa_status_string(cpa_status s) {
         case CPA_ERR_NONFINITE: return "CPA_ERR_NONFINITE";
         case CPA_ERR_BOUND: return "CPA_ERR_BOUND";
         case CPA_ERR_UNSUPPORTED: return "CPA_ERR_UNSUPPORTED";
+        case CPA_ERR_IO: return "CPA_ERR_IO";
     }
     return "CPA_ERR_UNKNOWN";
 }
@@ -2624,6 +2625,52 @@ cpa_status cpa_rpca_admm(cpa_ctx* ctx, void* stream, int m, int n, const float* 
     if (iters_done) *iters_done = t;
     HIP_TRY(hipMemcpyAsync(L_dev, state, b, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(S_dev, state + mn, b, hipMemcpyDeviceToDevice, st));
+    return CPA_OK;
+}
+
+}  // extern "C"
+
+// ---- Predictor model files ----
+
+extern "C" {
+
+static const char kModelMagic[8] = {'C', 'P', 'A', 'P', 'R', 'E', 'D', '1'};
+
+cpa_status cpa_predictor_save(cpa_ctx* ctx, void* stream, const float* model_dev, const char* path) {
+    if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
+    if (!model_dev || !path) return fail(CPA_ERR_ARG, "model or path is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<float> h(CPA_PRED_MODEL_FLOATS);
+    HIP_TRY(hipMemcpyAsync(h.data(), model_dev, sizeof(float) * h.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    FILE* fp = std::fopen(path, "wb");
+    if (!fp) return fail(CPA_ERR_IO, "cannot open %s for writing", path);
+    const int32_t hdr[2] = {1, CPA_PRED_MODEL_FLOATS};
+    bool ok = std::fwrite(kModelMagic, 1, 8, fp) == 8 && std::fwrite(hdr, sizeof(int32_t), 2, fp) == 2 &&
+              std::fwrite(h.data(), sizeof(float), h.size(), fp) == h.size();
+    ok = (std::fclose(fp) == 0) && ok;
+    if (!ok) return fail(CPA_ERR_IO, "write to %s failed", path);
+    return CPA_OK;
+}
+
+cpa_status cpa_predictor_load(cpa_ctx* ctx, void* stream, const char* path, float* model_dev) {
+    if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
+    if (!model_dev || !path) return fail(CPA_ERR_ARG, "model or path is NULL");
+    FILE* fp = std::fopen(path, "rb");
+    if (!fp) return fail(CPA_ERR_IO, "cannot open %s", path);
+    char magic[8];
+    int32_t hdr[2] = {0, 0};
+    std::vector<float> h(CPA_PRED_MODEL_FLOATS);
+    const bool head = std::fread(magic, 1, 8, fp) == 8 && std::fread(hdr, sizeof(int32_t), 2, fp) == 2;
+    const bool good = head && std::memcmp(magic, kModelMagic, 8) == 0 && hdr[0] == 1 &&
+                      hdr[1] == CPA_PRED_MODEL_FLOATS && std::fread(h.data(), sizeof(float), h.size(), fp) == h.size();
+    std::fclose(fp);
+    if (!good) return fail(CPA_ERR_IO, "%s is not a version-1 model file of %d floats", path, CPA_PRED_MODEL_FLOATS);
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(model_dev, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
     return CPA_OK;
 }
 

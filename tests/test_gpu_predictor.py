@@ -354,3 +354,32 @@ def test_predictor_pipeline_small():
         got = Yh[offs[j]:offs[j] + A.size].reshape(A.shape).astype(np.float64)
         ref = ocpa.cpa_shrink(A, Shrinkage(0, float(taus[j]), 0, 0, 0), float(lamh[j]), int(kh[j]))
         assert metrics.rel_fro(got, ref, A) <= TOL32, j
+
+
+def test_model_file_roundtrip(tmp_path):
+    """cpa_predictor_save / cpa_predictor_load: the model comes back bit for bit;
+    a file with the wrong magic, version or length is refused before the device
+    buffer is written."""
+    import torch
+    import paper_1705_07112_amd as cpa
+    from paper_1705_07112_amd import predictor
+    g = torch.Generator().manual_seed(5)
+    model = torch.randn(cpa.PRED_MODEL_FLOATS, generator=g).cuda()
+    path = tmp_path / "model.cpap"
+    predictor.save_model_file(str(path), model)
+    back = torch.zeros_like(model)
+    predictor.load_model_file(str(path), back)
+    torch.cuda.synchronize()
+    assert torch.equal(model, back)
+    raw = path.read_bytes()
+    assert raw[:8] == b"CPAPRED1" and len(raw) == 16 + 4 * cpa.PRED_MODEL_FLOATS
+    sentinel = torch.full_like(model, 7.0)
+    for bad in (b"XPAPRED1" + raw[8:], raw[:8] + (2).to_bytes(4, "little") + raw[12:], raw[:-4]):
+        p2 = tmp_path / "bad.cpap"
+        p2.write_bytes(bad)
+        with pytest.raises(cpa.CpaError):
+            predictor.load_model_file(str(p2), sentinel)
+    torch.cuda.synchronize()
+    assert bool((sentinel == 7.0).all())
+    with pytest.raises(cpa.CpaError):
+        predictor.load_model_file(str(tmp_path / "missing.cpap"), sentinel)
