@@ -6,9 +6,10 @@
 // kernels as the FP32 path (power iteration on the FP64 Gram).
 //
 // gemm_f64_kernel: C = op(A) op(B) with 64 x 64 output tiles, K-steps of 16,
-// 256 threads each holding a 4 x 4 block of FP64 accumulators; operand tiles go
-// through LDS with zero fill outside the matrix.  op(A)[i][k] is A[k][i] when TA
-// (the Gram X^T X reads X transposed), op(B)[k][j] is B[j][k] when TB (X X^T).
+// on the FP64 matrix cores (v_mfma_f64_16x16x4f64): four waves, each a 32 x 32
+// output as 2 x 2 blocks of 16 x 16; operand tiles go through LDS ([k][i] and
+// [k][j], zero fill outside the matrix).  op(A)[i][k] is A[k][i] when TA (the
+// Gram X^T X reads X transposed), op(B)[k][j] is B[j][k] when TB (X X^T).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,6 +20,7 @@
 namespace cpa {
 
 constexpr int F64_BM = 64, F64_BN = 64, F64_BK = 16;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256) gemm_f64_kernel(int M, int N, int Kd, const double* A, int64_t lda,
@@ -26,13 +28,14 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(int M, int N, int Kd, con
     __shared__ double As[F64_BK][F64_BM + 1];   // [k][i]
     __shared__ double Bs[F64_BK][F64_BN + 1];   // [k][j]
     const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;   // the wave's 32 x 32 output
     const int i0 = blockIdx.y * F64_BM, j0 = blockIdx.x * F64_BN;
-    double acc[4][4];
+    f64x4 acc[2][2];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+        for (int y = 0; y < 2; ++y) acc[x][y] = (f64x4){0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < Kd; k0 += F64_BK) {
         // consecutive threads read consecutive addresses of each operand
         for (int e = tid; e < F64_BM * F64_BK; e += 256) {
@@ -52,30 +55,34 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(int M, int N, int Kd, con
             Bs[kk][jj] = v;
         }
         __syncthreads();
+        // four k sub-steps of 4: lane l supplies row (or column) l % 16 at k = l / 16
 #pragma unroll
-        for (int kk = 0; kk < F64_BK; ++kk) {
-            double a[4], b[4];
+        for (int ks = 0; ks < F64_BK / 4; ++ks) {
+            const int kk = 4 * ks + (lane >> 4);
+            double a[2], b[2];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = As[kk][ty * 4 + r];
+            for (int x = 0; x < 2; ++x) a[x] = As[kk][wr * 32 + x * 16 + (lane & 15)];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tx * 4 + c];
+            for (int y = 0; y < 2; ++y) b[y] = Bs[kk][wc * 32 + y * 16 + (lane & 15)];
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int x = 0; x < 2; ++x)
 #pragma unroll
-                for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+                for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
         }
         __syncthreads();
     }
+    // lane l holds rows l / 16 + 4 r and column l % 16 of each 16 x 16 block (the
+    // FP64 instruction interleaves the rows; the FP32 one gives 4 (l / 16) + r)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = i0 + ty * 4 + r;
-        if (i >= M) continue;
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int j = j0 + tx * 4 + c;
-            if (j < N) C[(int64_t)i * ldc + j] = acc[r][c];
-        }
-    }
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wr * 32 + x * 16 + (lane >> 4) + 4 * r;
+                const int j = j0 + wc * 32 + y * 16 + (lane & 15);
+                if (i < M && j < N) C[(int64_t)i * ldc + j] = acc[x][y][r];
+            }
 }
 
 // One recurrence step on an m x n matrix, element (r, c) per thread:
