@@ -403,6 +403,38 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
                                        const cpa_sparsify* sparsify, cpa_info* info_host, double* eps_host,
                                        int64_t* nnz_host);
 
+/* Adaptive keep count of eq. (recommendation_epsilon) (Sec. V, with the counts
+ * k_1, k_2, k_3 of Table IV) for a d x d transformed Gram and the ADMM change E_t:
+ *   *keep = ceil(d^2 / 20000)    (0.5e-4 d^2) if E_t > E_l,
+ *           ceil(3 d^2 / 20000)  (1.5e-4 d^2) if E_l >= E_t > E_m,
+ *           ceil(d^2 / 2000)     (0.5e-3 d^2) otherwise,
+ * in exact integer arithmetic, clamped to [1, d^2].  The paper's switch points are
+ * E_l = CPA_SCHEDULE_E_L and E_m = CPA_SCHEDULE_E_M.  E_t = +inf (no previous
+ * iteration) gives the first case.  Host only; CPA_ERR_ARG for a NaN E_t, a NULL
+ * keep, or switch points that are not finite with 0 <= E_m <= E_l; CPA_ERR_SHAPE
+ * for d <= 0. */
+#define CPA_SCHEDULE_E_L 0.03
+#define CPA_SCHEDULE_E_M 6e-4
+cpa_status cpa_keep_schedule(double E_t, int d, double E_l, double E_m, int64_t* keep);
+
+/* Texture inpainting (as cpa_inpaint_iterate, Appendix A) with z1 by the
+ * sparsified shrink (cpa_shrink_dense_sparsified with `transform`) and its keep
+ * count from eq. (recommendation_epsilon): iteration t uses
+ * cpa_keep_schedule(E_{t-1}, d, E_l, E_m), d the Gram side, with E_prev before the
+ * first iteration of the call (+inf on a fresh start; the last E_t of the previous
+ * call to continue a run).  Et_dev (device, `iters` doubles) is required: the call
+ * reads each E_t back, so it waits for the stream once per iteration (and the
+ * sparsified shrink once more).  keep_host (host, `iters` int64, may be NULL)
+ * receives the keep counts.  The Gram side must be a multiple of 8; FP32 only.
+ * Errors as cpa_inpaint_iterate and cpa_keep_schedule, plus CPA_ERR_ARG for an
+ * unknown transform or a NULL Et_dev.  The paper's experiment (Table IV) uses the
+ * DCT; the truncated matrix can be indefinite for data that the transform does not
+ * sparsify (cpa_shrink_dense_sparsified), and the iteration then need not converge. */
+cpa_status cpa_inpaint_iterate_scheduled(cpa_ctx* ctx, void* stream, int m, int n, const float* I_dev,
+                                         const float* omega_dev, const float* border_dev, float* state_dev, int iters,
+                                         double inv_rho, double eta_over_rho, const cpa_opts* opts, int32_t transform,
+                                         double E_prev, double E_l, double E_m, double* Et_dev, int64_t* keep_host);
+
 /* ---- Batched plans: the batched shrink as one captured graph, tuned once.
  * Not in the paper (it shrinks one matrix at a time); the per-matrix
  * computation is exactly that of cpa_shrink_batched.

@@ -42,6 +42,10 @@ caller gives; Pi_M adds (mean of I over m_del) - (mean of y over the region) to 
 region and leaves y elsewhere; without the mean term (the random-corruption experiment of
 Sec. V-F) z5 and u5 are dropped and K^T K = 3 Id + Omega.
 
+With the sparsifying transform (Sec. III-B and the experiments of Table IV), z1 is
+the sparsified shrink of oracle.sparsify with K(|Phi|, k) and k from the previous
+iteration's E_t by eq. (recommendation_epsilon) (oracle.sparsify.keep_schedule).
+
 Pins: (K^T K)^{-1} K^T checked by substitution; l1 prox against its closed
 form; E_t falls on a low-rank-plus-sparse input.  Parity: pinned for the
 closed-form pieces; the ADMM hyper-parameters are project choices (parity
@@ -55,7 +59,8 @@ import numpy as np
 
 from . import bound, cpa
 from .shrinkage import soft
-from .sparsify import dct_matrix
+from .sparsify import (cpa_shrink_sparsified, dct_matrix, keep_schedule, kth_largest_abs, transformed_gram,
+                       truncate)
 
 
 def soft_elementwise(x, t):
@@ -183,9 +188,13 @@ def inpaint_start(omega):
 
 
 def inpaint_step(state, I, omega, border, inv_rho: float, eta_over_rho: float, K: int, v=None, seed: int = 0,
-                 power_iters: int = 100, tol_power: float = 1e-7, delta: float = 0.01):
+                 power_iters: int = 100, tol_power: float = 1e-7, delta: float = 0.01, sparsify=None):
     """One ADMM iteration of eq. (admm_algorithm_inp).  omega: observed mask (1/0);
     border: mask of the surrounding pixels m_del, or None for no mean term.
+    sparsify: None for the plain shrink, or dict(T, zero, keep): z1 by the
+    sparsified shrink of Sec. III-B (transform T, the high-frequency mask zero or
+    None, threshold K(|Phi|, keep)), its bound the power bound of the truncated
+    matrix from a cold start.
     Returns (new_state, info) with info = dict(x, Lambda, v, E)."""
     I = np.asarray(I, dtype=np.float64)
     om = np.asarray(omega, dtype=np.float64)
@@ -198,9 +207,19 @@ def inpaint_step(state, I, omega, border, inv_rho: float, eta_over_rho: float, K
     diag = 3.0 + om + (ob if ave else 0.0)
     l_new = r / diag
     x = l_new + st["u1"]
-    Phi, _ = cpa.gram(x)
-    Lam, _, _, _, v = bound.power_bound(Phi, seed=seed, max_iter=power_iters, tol=tol_power, delta=delta, v0=v)
-    z1 = cpa.cpa_shrink(x, soft(inv_rho), Lam, K)
+    if sparsify is None:
+        Phi, _ = cpa.gram(x)
+        Lam, _, _, _, v = bound.power_bound(Phi, seed=seed, max_iter=power_iters, tol=tol_power, delta=delta, v0=v)
+        z1 = cpa.cpa_shrink(x, soft(inv_rho), Lam, K)
+    else:
+        T, zero, keep = sparsify["T"], sparsify.get("zero"), sparsify["keep"]
+        Phi, _ = transformed_gram(x, T)
+        if zero is not None:
+            Phi[zero, :] = 0.0
+            Phi[:, zero] = 0.0
+        Phil = truncate(Phi, kth_largest_abs(Phi, keep))
+        Lam, _, _, _, v = bound.power_bound(Phil, seed=seed, max_iter=power_iters, tol=tol_power, delta=delta)
+        z1 = cpa_shrink_sparsified(x, soft(inv_rho), Lam, K, T, keep, zero=zero)[0]
     P = dct2(l_new)
     z2 = soft_elementwise(P + st["u2"], eta_over_rho)
     z3 = om * I
@@ -225,15 +244,29 @@ def inpaint_step(state, I, omega, border, inv_rho: float, eta_over_rho: float, K
 
 
 def inpaint_admm(I, omega, border, inv_rho: float, eta_over_rho: float, iters: int, K: int, seed: int = 0,
-                 power_iters: int = 100, tol_power: float = 1e-7, delta: float = 0.01):
-    """``iters`` iterations of eq. (admm_algorithm_inp) from inpaint_start; returns
-    (l, E_hist).  The power bound of each shrink is warm-started."""
-    state = inpaint_start(omega)
+                 power_iters: int = 100, tol_power: float = 1e-7, delta: float = 0.01, schedule=None, state=None):
+    """``iters`` iterations of eq. (admm_algorithm_inp) from inpaint_start (or from
+    ``state``); returns (l, E_hist), or (state, E_hist, keeps) with a schedule.
+    The power bound of each plain shrink is warm-started.
+    schedule: None, or dict(T, zero, E_l, E_m, E_prev): z1 by the sparsified shrink
+    with keep = keep_schedule(E, d) of the previous iteration's E (E_prev before
+    the first), d the side of the Gram (eq. recommendation_epsilon)."""
+    state = inpaint_start(omega) if state is None else state
     v = None
     E = []
+    keeps = []
     for _ in range(iters):
+        sp = None
+        if schedule is not None:
+            d = min(np.shape(I))
+            e_prev = E[-1] if E else schedule.get("E_prev", math.inf)
+            sp = {"T": schedule["T"], "zero": schedule.get("zero"),
+                  "keep": keep_schedule(e_prev, d, schedule.get("E_l", 0.03), schedule.get("E_m", 6e-4))}
+            keeps.append(sp["keep"])
         state, info = inpaint_step(state, I, omega, border, inv_rho, eta_over_rho, K, v=v, seed=seed,
-                                   power_iters=power_iters, tol_power=tol_power, delta=delta)
+                                   power_iters=power_iters, tol_power=tol_power, delta=delta, sparsify=sp)
         v = info["v"]
         E.append(info["E"])
+    if schedule is not None:
+        return state, E, keeps
     return state["l"], E

@@ -39,10 +39,20 @@ truncated matrix; eps equals the k-th value of a full sort; the Haar matrix
 maps hand-computed vectors to their sums and differences; with the high
 frequencies zeroed the result equals B T_L^T hat h(Phi_LL) T_L + hat h(0) B T_H^T T_H
 from an eigendecomposition of the low-pass block.  Parity: pinned.
+
+Adaptive keep count (eq. recommendation_epsilon, with the thresholds E_l = 0.03
+and E_m = 6e-4 and the counts k_1, k_2, k_3 of Table IV):
+  k = (0.5e-4) n^2 if E_t > E_l;  (1.5e-4) n^2 if E_l >= E_t > E_m;  (0.5e-3) n^2 otherwise.
+Readings: a fractional count is rounded up, in exact rational arithmetic (the
+fractions are 1/20000, 3/20000 and 1/2000 of n^2), and clamped to [1, n^2]; E_t is
+the previous iteration's ADMM change, and the first iteration, which has none,
+takes E_t = +inf (the first case).  Pins: Table IV's caption gives k_1 = 50,
+k_2 = 150, k_3 = 500 at n = 1000; the case edges E_t = E_l and E_t = E_m.
 """
 from __future__ import annotations
 
 import math
+from fractions import Fraction
 
 import numpy as np
 
@@ -111,6 +121,21 @@ def keep_count(n: int, fraction: float) -> int:
     """k for a kept fraction of the n x n entries (eq. recommendation_epsilon writes
     k = f n^2): ceil(f n^2), at least 1."""
     return max(1, int(math.ceil(fraction * n * n)))
+
+
+def keep_schedule(E_t: float, n: int, E_l: float = 0.03, E_m: float = 6e-4) -> int:
+    """eq. (recommendation_epsilon): the keep count k of K(|Phi|, k) for the ADMM
+    change E_t, on an n x n transformed Gram."""
+    if math.isnan(E_t):
+        raise ValueError("E_t is NaN")
+    if E_t > E_l:
+        f = Fraction(1, 20000)     # 0.5e-4
+    elif E_t > E_m:
+        f = Fraction(3, 20000)     # 1.5e-4
+    else:
+        f = Fraction(1, 2000)      # 0.5e-3
+    k = math.ceil(f * n * n)
+    return min(max(k, 1), n * n)
 
 
 def cpa_shrink_sparsified(B: np.ndarray, shrink, Lambda: float, K: int, T: np.ndarray, k: int, zero=None):

@@ -104,6 +104,12 @@ _SIGS = {
     "cpa_inpaint_init": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _P]),
     "cpa_inpaint_iterate": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, ctypes.c_int,
                                            ctypes.c_double, ctypes.c_double, ctypes.POINTER(CpaOpts), _P]),
+    "cpa_keep_schedule": (ctypes.c_int, [ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                         ctypes.POINTER(ctypes.c_int64)]),
+    "cpa_inpaint_iterate_scheduled": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P,
+                                                     ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                                     ctypes.POINTER(CpaOpts), ctypes.c_int32, ctypes.c_double,
+                                                     ctypes.c_double, ctypes.c_double, _P, _P]),
     "cpa_timing_enable": (ctypes.c_int, [_P, ctypes.c_int]),
     "cpa_peak_mfma": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
     "cpa_workspace_bytes": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(CpaOpts),
@@ -273,6 +279,18 @@ def damping_factors(K: int, kind: str = "jackson"):
     out = (ctypes.c_double * int(K))()
     _check(lib().cpa_damping_factors(int(K), {"none": 0, "jackson": 1, "lanczos": 2}[kind], out))
     return list(out)
+
+
+SCHEDULE_E_L = 0.03
+SCHEDULE_E_M = 6e-4
+
+
+def keep_schedule(E_t: float, d: int, E_l: float = SCHEDULE_E_L, E_m: float = SCHEDULE_E_M) -> int:
+    """The keep count of eq. (recommendation_epsilon) for E_t on a d x d transformed
+    Gram (cpa_keep_schedule)."""
+    k = ctypes.c_int64(0)
+    _check(lib().cpa_keep_schedule(float(E_t), int(d), float(E_l), float(E_m), ctypes.byref(k)))
+    return int(k.value)
 
 
 def shrink_dense(X, shrink: CpaShrinkage, opts: Opts, out=None, info: bool = False):
@@ -612,6 +630,25 @@ class Inpaint:
                                          ctypes.c_void_p(self.I.data_ptr()), ctypes.c_void_p(self.omega.data_ptr()),
                                          bptr, ctypes.c_void_p(self.state.data_ptr()), int(iters), self.inv_rho,
                                          self.eta_over_rho, ctypes.byref(co), ptr))
+
+
+    def iterate_scheduled(self, iters: int, Et, transform: str = "dct", E_prev: float = float("inf"),
+                          E_l: float = SCHEDULE_E_L, E_m: float = SCHEDULE_E_M):
+        """Runs ``iters`` iterations with z1 by the sparsified shrink and the keep
+        count of eq. (recommendation_epsilon) from the previous E_t (E_prev before
+        the first); ``Et`` (float64 CUDA tensor, >= iters) is required.  Returns the
+        keep counts (cpa_inpaint_iterate_scheduled)."""
+        if Et is None or Et.numel() < iters:
+            raise ValueError("Et must hold iters float64 values")
+        co = self.opts.to_c()
+        keeps = (ctypes.c_int64 * max(int(iters), 1))()
+        bptr = ctypes.c_void_p(self.border.data_ptr()) if self.border is not None else None
+        _check(lib().cpa_inpaint_iterate_scheduled(
+            ctypes.c_void_p(self.ctx), _stream(self.I), self.m, self.n, ctypes.c_void_p(self.I.data_ptr()),
+            ctypes.c_void_p(self.omega.data_ptr()), bptr, ctypes.c_void_p(self.state.data_ptr()), int(iters),
+            self.inv_rho, self.eta_over_rho, ctypes.byref(co), _TRANSFORMS[transform], float(E_prev), float(E_l),
+            float(E_m), ctypes.c_void_p(Et.data_ptr()), keeps))
+        return [int(k) for k in keeps[:int(iters)]]
 
 
 class RpcaAdmm:

@@ -2348,6 +2348,124 @@ cpa_status inp_psi(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* src,
                      CPA_PREC_FP32, true);
 }
 
+// eq. (recommendation_epsilon) with Table IV's counts: k = d^2 / 20000 (0.5e-4 d^2)
+// while E_t > E_l, 3 d^2 / 20000 (1.5e-4 d^2) while E_t > E_m, d^2 / 2000 (0.5e-3 d^2)
+// after that; a fractional count is rounded up, exactly, and the result lies in [1, d^2].
+int64_t schedule_keep(double E_t, int d, double E_l, double E_m) {
+    const unsigned __int128 dd = (unsigned __int128)d * (unsigned __int128)d;
+    unsigned __int128 num, den;
+    if (E_t > E_l) {
+        num = dd;
+        den = 20000;
+    } else if (E_t > E_m) {
+        num = 3 * dd;
+        den = 20000;
+    } else {
+        num = dd;
+        den = 2000;
+    }
+    unsigned __int128 k = (num + den - 1) / den;
+    if (k < 1) k = 1;
+    if (k > dd) k = dd;
+    return (int64_t)k;
+}
+
+// The adaptive sparsified shrink of the inpainting driver: transform, the E_t
+// before the first iteration, the switch points, and where the keeps go.
+struct InpSchedule {
+    int32_t transform;
+    double E_prev, E_l, E_m;
+    int64_t* keep_host;
+};
+
+cpa_status inpaint_run(cpa_ctx* ctx, void* stream, int m, int n, const float* I_dev, const float* omega_dev,
+                       const float* border_dev, float* state_dev, int iters, double inv_rho, double eta_over_rho,
+                       const cpa_opts* opts, double* Et_dev, const InpSchedule* sched) {
+    cpa_status s;
+    if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
+    if (m < 0 || n < 0) return fail(CPA_ERR_SHAPE, "negative size");
+    if (iters < 0) return fail(CPA_ERR_ARG, "iters < 0");
+    if ((s = check_opts(opts)) != CPA_OK) return s;
+    if (!(std::isfinite(inv_rho) && inv_rho >= 0.0 && std::isfinite(eta_over_rho) && eta_over_rho >= 0.0))
+        return fail(CPA_ERR_ARG, "inv_rho and eta_over_rho must be finite and >= 0");
+    if (m == 0 || n == 0 || iters == 0) return CPA_OK;
+    if (!I_dev || !omega_dev || !state_dev) return fail(CPA_ERR_ARG, "I, omega or state is NULL");
+    if (opts->check) return fail(CPA_ERR_UNSUPPORTED, "the growth check is not available inside the ADMM driver");
+    const int64_t mn = (int64_t)m * n;
+    const size_t sb = sizeof(float) * 11 * mn, ib = sizeof(float) * mn;
+    if (overlaps(I_dev, ib, state_dev, sb) || overlaps(omega_dev, ib, state_dev, sb) ||
+        (border_dev && overlaps(border_dev, ib, state_dev, sb)))
+        return fail(CPA_ERR_ARG, "an input overlaps the state");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    Work w;
+    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    const int d = right_side(opts, m, n) ? n : m;
+    if (sched) {
+        // the sparsified shrink's own checks, before anything is launched
+        if (d % 8 != 0) return fail(CPA_ERR_SHAPE, "the Gram side (%d) must be a multiple of 8 (8 x 8 tiles)", d);
+        if ((int64_t)d * d > INT32_MAX) return fail(CPA_ERR_SHAPE, "Gram too large for 32-bit indices");
+        if (opts->precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "the sparsified path is FP32");
+    } else if ((s = ensure_ws(ctx, m, n, opts->K, maxit, false, w, right_side(opts, m, n), poly_choice(opts, m, n))) !=
+               CPA_OK) {
+        return s;
+    }
+    InpWork f;
+    if ((s = ensure_inp(ctx, m, n, f)) != CPA_OK) return s;
+    if ((s = inp_dct(st, m, n, f)) != CPA_OK) return s;
+    const int grid = (int)std::min<int64_t>(kInpGrid, (mn + 255) / 256);
+    hipLaunchKernelGGL(inp_const_kernel, dim3(grid), dim3(256), 0, st, mn, I_dev, omega_dev, border_dev, f.part);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(inp_const_finish_kernel, dim3(1), dim3(256), 0, st, (const double*)f.part, grid,
+                       border_dev ? 1 : 0, f.cst);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, st, f.counter, 1, 0);
+    HIP_TRY(hipGetLastError());
+    InpPtrs P;
+    P.l = state_dev;
+    for (int k = 0; k < 5; ++k) {
+        P.z[k] = state_dev + (1 + k) * mn;
+        P.u[k] = state_dev + (6 + k) * mn;
+    }
+    P.I = I_dev;
+    P.om = omega_dev;
+    P.x = f.x;
+    P.T = f.T;
+    P.ave = border_dev ? 1 : 0;
+    cpa_shrinkage sh = {CPA_SOFT, 0, inv_rho, 0.0, 0.0, 1.0};
+    double e_prev = sched ? sched->E_prev : 0.0;
+    for (int t = 0; t < iters; ++t) {
+        // T = Psi^T (z2 - u2)
+        hipLaunchKernelGGL(inp_diff_kernel, dim3(grid), dim3(256), 0, st, mn, (const float*)P.z[1],
+                           (const float*)P.u[1], f.A);
+        HIP_TRY(hipGetLastError());
+        if ((s = inp_psi(ctx, st, m, n, f.A, f.T, false, f)) != CPA_OK) return s;
+        hipLaunchKernelGGL(inp_pre_kernel, dim3(grid), dim3(256), 0, st, P, mn, f.part);
+        HIP_TRY(hipGetLastError());
+        // z1 = the CPA shrink of x = l + u1 (sparsified: keep from the previous E_t)
+        if (sched) {
+            const cpa_sparsify sp = {sched->transform, 0, schedule_keep(e_prev, d, sched->E_l, sched->E_m)};
+            if (sched->keep_host) sched->keep_host[t] = sp.keep;
+            if ((s = cpa_shrink_dense_sparsified(ctx, stream, m, n, f.x, n, P.z[0], n, &sh, opts, &sp, nullptr,
+                                                 nullptr, nullptr)) != CPA_OK)
+                return s;
+        } else if ((s = shrink_impl(ctx, st, m, n, f.x, n, P.z[0], n, &sh, opts, nullptr, w)) != CPA_OK) {
+            return s;
+        }
+        // T = Psi l
+        if ((s = inp_psi(ctx, st, m, n, P.l, f.T, true, f)) != CPA_OK) return s;
+        hipLaunchKernelGGL(inp_post_kernel, dim3(grid), dim3(256), 0, st, P, mn, (float)eta_over_rho,
+                           (const double*)f.part, grid, (const double*)f.cst, Et_dev, f.counter);
+        HIP_TRY(hipGetLastError());
+        if (sched) {
+            HIP_TRY(hipMemcpyAsync(&e_prev, Et_dev + t, sizeof(double), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+    }
+    return CPA_OK;
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -2381,68 +2499,34 @@ cpa_status cpa_inpaint_init(cpa_ctx* ctx, void* stream, int m, int n, const floa
 cpa_status cpa_inpaint_iterate(cpa_ctx* ctx, void* stream, int m, int n, const float* I_dev, const float* omega_dev,
                                const float* border_dev, float* state_dev, int iters, double inv_rho,
                                double eta_over_rho, const cpa_opts* opts, double* Et_dev) {
-    cpa_status s;
-    if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
-    if (m < 0 || n < 0) return fail(CPA_ERR_SHAPE, "negative size");
-    if (iters < 0) return fail(CPA_ERR_ARG, "iters < 0");
-    if ((s = check_opts(opts)) != CPA_OK) return s;
-    if (!(std::isfinite(inv_rho) && inv_rho >= 0.0 && std::isfinite(eta_over_rho) && eta_over_rho >= 0.0))
-        return fail(CPA_ERR_ARG, "inv_rho and eta_over_rho must be finite and >= 0");
-    if (m == 0 || n == 0 || iters == 0) return CPA_OK;
-    if (!I_dev || !omega_dev || !state_dev) return fail(CPA_ERR_ARG, "I, omega or state is NULL");
-    if (opts->check) return fail(CPA_ERR_UNSUPPORTED, "the growth check is not available inside the ADMM driver");
-    const int64_t mn = (int64_t)m * n;
-    const size_t sb = sizeof(float) * 11 * mn, ib = sizeof(float) * mn;
-    if (overlaps(I_dev, ib, state_dev, sb) || overlaps(omega_dev, ib, state_dev, sb) ||
-        (border_dev && overlaps(border_dev, ib, state_dev, sb)))
-        return fail(CPA_ERR_ARG, "an input overlaps the state");
-    HIP_TRY(hipSetDevice(ctx->device));
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    Work w;
-    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
-    if ((s = ensure_ws(ctx, m, n, opts->K, maxit, false, w, right_side(opts, m, n), poly_choice(opts, m, n))) !=
-        CPA_OK)
-        return s;
-    InpWork f;
-    if ((s = ensure_inp(ctx, m, n, f)) != CPA_OK) return s;
-    if ((s = inp_dct(st, m, n, f)) != CPA_OK) return s;
-    const int grid = (int)std::min<int64_t>(kInpGrid, (mn + 255) / 256);
-    hipLaunchKernelGGL(inp_const_kernel, dim3(grid), dim3(256), 0, st, mn, I_dev, omega_dev, border_dev, f.part);
-    HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(inp_const_finish_kernel, dim3(1), dim3(256), 0, st, (const double*)f.part, grid,
-                       border_dev ? 1 : 0, f.cst);
-    HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, st, f.counter, 1, 0);
-    HIP_TRY(hipGetLastError());
-    InpPtrs P;
-    P.l = state_dev;
-    for (int k = 0; k < 5; ++k) {
-        P.z[k] = state_dev + (1 + k) * mn;
-        P.u[k] = state_dev + (6 + k) * mn;
-    }
-    P.I = I_dev;
-    P.om = omega_dev;
-    P.x = f.x;
-    P.T = f.T;
-    P.ave = border_dev ? 1 : 0;
-    cpa_shrinkage sh = {CPA_SOFT, 0, inv_rho, 0.0, 0.0, 1.0};
-    for (int t = 0; t < iters; ++t) {
-        // T = Psi^T (z2 - u2)
-        hipLaunchKernelGGL(inp_diff_kernel, dim3(grid), dim3(256), 0, st, mn, (const float*)P.z[1],
-                           (const float*)P.u[1], f.A);
-        HIP_TRY(hipGetLastError());
-        if ((s = inp_psi(ctx, st, m, n, f.A, f.T, false, f)) != CPA_OK) return s;
-        hipLaunchKernelGGL(inp_pre_kernel, dim3(grid), dim3(256), 0, st, P, mn, f.part);
-        HIP_TRY(hipGetLastError());
-        // z1 = the CPA shrink of x = l + u1
-        if ((s = shrink_impl(ctx, st, m, n, f.x, n, P.z[0], n, &sh, opts, nullptr, w)) != CPA_OK) return s;
-        // T = Psi l
-        if ((s = inp_psi(ctx, st, m, n, P.l, f.T, true, f)) != CPA_OK) return s;
-        hipLaunchKernelGGL(inp_post_kernel, dim3(grid), dim3(256), 0, st, P, mn, (float)eta_over_rho,
-                           (const double*)f.part, grid, (const double*)f.cst, Et_dev, f.counter);
-        HIP_TRY(hipGetLastError());
-    }
+    return inpaint_run(ctx, stream, m, n, I_dev, omega_dev, border_dev, state_dev, iters, inv_rho, eta_over_rho, opts,
+                       Et_dev, nullptr);
+}
+
+cpa_status cpa_keep_schedule(double E_t, int d, double E_l, double E_m, int64_t* keep) {
+    if (!keep) return fail(CPA_ERR_ARG, "keep is NULL");
+    if (std::isnan(E_t)) return fail(CPA_ERR_ARG, "E_t is NaN");
+    if (d <= 0) return fail(CPA_ERR_SHAPE, "d must be positive");
+    if (!(std::isfinite(E_l) && std::isfinite(E_m) && E_m >= 0.0 && E_l >= E_m))
+        return fail(CPA_ERR_ARG, "the switch points must satisfy 0 <= E_m <= E_l (finite)");
+    *keep = schedule_keep(E_t, d, E_l, E_m);
     return CPA_OK;
+}
+
+cpa_status cpa_inpaint_iterate_scheduled(cpa_ctx* ctx, void* stream, int m, int n, const float* I_dev,
+                                         const float* omega_dev, const float* border_dev, float* state_dev, int iters,
+                                         double inv_rho, double eta_over_rho, const cpa_opts* opts, int32_t transform,
+                                         double E_prev, double E_l, double E_m, double* Et_dev, int64_t* keep_host) {
+    if (transform != CPA_TRANSFORM_IDENTITY && transform != CPA_TRANSFORM_BLOCK_DCT8 &&
+        transform != CPA_TRANSFORM_HAAR1 && transform != CPA_TRANSFORM_HAAR1_LOWPASS && transform != CPA_TRANSFORM_DCT)
+        return fail(CPA_ERR_ARG, "unknown transform %d", transform);
+    if (std::isnan(E_prev)) return fail(CPA_ERR_ARG, "E_prev is NaN");
+    if (!(std::isfinite(E_l) && std::isfinite(E_m) && E_m >= 0.0 && E_l >= E_m))
+        return fail(CPA_ERR_ARG, "the switch points must satisfy 0 <= E_m <= E_l (finite)");
+    if (!Et_dev && iters > 0 && m > 0 && n > 0) return fail(CPA_ERR_ARG, "Et is required (the schedule reads E_t)");
+    InpSchedule sc{transform, E_prev, E_l, E_m, keep_host};
+    return inpaint_run(ctx, stream, m, n, I_dev, omega_dev, border_dev, state_dev, iters, inv_rho, eta_over_rho, opts,
+                       Et_dev, &sc);
 }
 
 }  // extern "C"

@@ -94,6 +94,40 @@ def test_inpaint_and_sparsified_argument_errors_before_any_device_work():
     assert st == 1 and b"context" in lib.cpa_last_error()
 
 
+def test_keep_schedule_matches_oracle():
+    """cpa_keep_schedule (integer arithmetic) against the oracle's exact rationals,
+    at and around the switch points and for sizes up to the largest int."""
+    from oracle.sparsify import keep_schedule
+    for d in (1, 7, 8, 44, 45, 96, 141, 1000, 1024, 1920, 46341, 2 ** 31 - 1):
+        for E in (math.inf, 10.0, math.nextafter(0.03, 1.0), 0.03, 0.01, math.nextafter(6e-4, 1.0), 6e-4, 0.0, -1.0):
+            assert cpa.keep_schedule(E, d) == keep_schedule(E, d), (d, E)
+        for E_l, E_m in ((0.5, 0.2), (0.2, 0.2), (1e-3, 0.0)):
+            for E in (0.6, 0.5, 0.3, 0.2, 0.1, 0.0):
+                assert cpa.keep_schedule(E, d, E_l, E_m) == keep_schedule(E, d, E_l, E_m), (d, E, E_l, E_m)
+    lib = cpa.lib()
+    k = ctypes.c_int64(0)
+    for args, status in (((math.nan, 8, 0.03, 6e-4), 1), ((1.0, 0, 0.03, 6e-4), 2), ((1.0, 8, 1e-4, 1e-2), 1),
+                         ((1.0, 8, math.inf, 6e-4), 1), ((1.0, 8, 0.03, -1.0), 1)):
+        assert lib.cpa_keep_schedule(*args, ctypes.byref(k)) == status, args
+    assert lib.cpa_keep_schedule(1.0, 8, 0.03, 6e-4, None) == 1
+
+
+def test_scheduled_inpaint_argument_errors_before_any_device_work():
+    lib = cpa.lib()
+    o = cpa.Opts(K=4).to_c()
+    keeps = (ctypes.c_int64 * 2)()
+
+    def call(ctx=None, transform=cpa.TRANSFORM_DCT, E_prev=math.inf, E_l=0.03, E_m=6e-4, Et=ctypes.c_void_p(1 << 24)):
+        return lib.cpa_inpaint_iterate_scheduled(ctx, None, 16, 16, ctypes.c_void_p(16), ctypes.c_void_p(4096), None,
+                                                 ctypes.c_void_p(1 << 20), 2, 1.0, 0.1, ctypes.byref(o), transform,
+                                                 E_prev, E_l, E_m, Et, keeps)
+    assert call(transform=9) == 1 and b"transform" in lib.cpa_last_error()
+    assert call(E_prev=math.nan) == 1 and b"E_prev" in lib.cpa_last_error()
+    assert call(E_l=1e-4, E_m=1e-2) == 1
+    assert call(Et=None) == 1 and b"Et" in lib.cpa_last_error()
+    assert call() == 1 and b"context" in lib.cpa_last_error()
+
+
 @pytest.mark.parametrize("K", [1, 2, 7, 30, 256])
 def test_damping_factors_match_oracle(K):
     import numpy as np

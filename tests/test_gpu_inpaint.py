@@ -5,12 +5,18 @@ Gated: one iteration started from the same state on both sides (the GPU's own
 state, copied to the host) must agree to the FP32 tolerance, every block of
 [l, z1..z5, u1..u5]; each dual block's error is measured against the size of
 the terms it sums.  Then the recovery of a low-rank texture's missing block
-with the pin's parameters."""
+with the pin's parameters.  The scheduled driver (z1 by the sparsified shrink
+with the DCT, keep from eq. recommendation_epsilon) is gated the same way for
+each of the schedule's three cases, where the oracle's |Phi| has a clear gap at
+the keep count (so FP32 and FP64 keep the same entries), and over a run whose
+keep sequence must match the oracle's exactly."""
+import math
+
 import numpy as np
 import pytest
 
 import synth
-from oracle import drivers, metrics
+from oracle import drivers, metrics, sparsify
 
 pytestmark = pytest.mark.gpu
 
@@ -80,3 +86,87 @@ def test_inpaint_recovers_a_low_rank_texture():
     assert Et[-1].item() < 1e-4
     assert err < 0.25
     assert abs(err - err_o) <= 0.01
+
+
+def _errs(before, after, ref, om):
+    P = drivers.dct2(ref["l"])
+    scale = {"u1": metrics.fro(before["u1"]) + metrics.fro(ref["l"]) + metrics.fro(ref["z1"]),
+             "u2": metrics.fro(before["u2"]) + metrics.fro(P) + metrics.fro(ref["z2"]),
+             "u3": metrics.fro(before["u3"]) + metrics.fro(om * ref["l"]) + metrics.fro(ref["z3"]),
+             "u4": metrics.fro(before["u4"]) + metrics.fro(ref["l"]) + metrics.fro(ref["z4"]),
+             "u5": metrics.fro(before["u5"]) + metrics.fro((1 - om) * ref["l"]) + metrics.fro(ref["z5"])}
+    return {k: (metrics.fro(after[k] - ref[k]) / scale[k] if k in scale else metrics.rel_fro(after[k], ref[k]))
+            for k in NAMES}
+
+
+def _clear_gap(x, T, keep, rel=1e-4):
+    """|Phi| of the shrink input has its keep-th value at least rel * max|Phi| away
+    from every other distinct magnitude (equal magnitudes: the mirrored entries)."""
+    Phi, _ = sparsify.transformed_gram(x, T)
+    a = np.sort(np.abs(Phi).ravel())[::-1]
+    eps = a[keep - 1]
+    tie = np.abs(a - eps) <= 1e-12 * a[0]
+    others = a[~tie]
+    return others.size == 0 or float(np.min(np.abs(others - eps))) > rel * a[0]
+
+
+@pytest.mark.parametrize("E_prev", [1.0, 0.01, 1e-4])
+def test_scheduled_inpaint_one_iteration_each_case(E_prev):
+    import torch
+    m, n, K, inv_rho, eta = 256, 192, 15, 1.0, 0.01
+    run, I, om, bd, _ = _run(m, n, None, 4, True, K, inv_rho, eta, 5)
+    T = sparsify.dct_matrix(n)
+    keep_o = sparsify.keep_schedule(E_prev, n)
+    # from the start state the shrink input is nearly constant and Phi nearly rank
+    # one: its k-th magnitude is rounding noise, so the gated states come later
+    done = 0
+    for warm in (3, 3):
+        run.iterate(warm)
+        done += warm
+        before = _state_host(run)
+        saved = run.state.clone()
+        Et = torch.zeros(1, dtype=torch.float64, device="cuda")
+        keeps = run.iterate_scheduled(1, Et, transform="dct", E_prev=E_prev)
+        torch.cuda.synchronize()
+        after = _state_host(run)
+        run.state.copy_(saved)
+        ref, info = drivers.inpaint_step(before, I, om, bd, inv_rho, eta, K, sparsify={"T": T, "keep": keep_o})
+        assert _clear_gap(info["x"], T, keep_o), "data: no clear gap at the keep count"
+        errs = _errs(before, after, ref, om)
+        print(f"scheduled inpaint E_prev={E_prev} after {done}: keep gpu {keeps[0]} oracle {keep_o}; "
+              + " ".join(f"{k}={v:.1e}" for k, v in errs.items()) + f" E gpu={Et.item():.6g} oracle={info['E']:.6g}",
+              flush=True)
+        assert keeps == [keep_o]
+        for k in NAMES:
+            assert errs[k] <= 1e-5, (k, errs[k])
+        assert abs(Et.item() - info["E"]) <= 1e-5 * max(info["E"], 1e-12)
+
+
+def test_scheduled_inpaint_run_follows_the_oracle():
+    """24 iterations from the start (E_prev = +inf) with the paper's switch points:
+    the keep moves from k_1 to k_2 as E_t falls below E_l; both sides take the same
+    keeps, E_t agrees and the final image drifts by FP32 rounding only."""
+    import torch
+    m = n = 256
+    K, inv_rho, eta, iters = 15, 1.0, 0.01, 24
+    run, I, om, bd, L0 = _run(m, n, None, 4, True, K, inv_rho, eta, 5)
+    Et = torch.zeros(iters, dtype=torch.float64, device="cuda")
+    keeps = run.iterate_scheduled(iters, Et, transform="dct")
+    torch.cuda.synchronize()
+    l = run.L.cpu().numpy().astype(np.float64)
+    st, E_o, keeps_o = drivers.inpaint_admm(I, om, bd, inv_rho, eta, iters, K,
+                                            schedule={"T": sparsify.dct_matrix(n), "E_prev": math.inf})
+    # the oracle's E_t stay clear of the switch points, so FP32 drift cannot flip a keep
+    assert all(abs(e - 0.03) > 0.01 * 0.03 and abs(e - 6e-4) > 0.01 * 6e-4 for e in E_o)
+    E_g = Et.cpu().numpy()
+    dE = float(np.max(np.abs(E_g - np.array(E_o)) / np.maximum(np.array(E_o), 1e-12)))
+    drift = metrics.rel_fro(l, st["l"])
+    reg = om == 0.0
+    err = np.linalg.norm((l - L0)[reg]) / np.linalg.norm(L0[reg])
+    err_o = np.linalg.norm((st["l"] - L0)[reg]) / np.linalg.norm(L0[reg])
+    print(f"scheduled inpaint run: keeps gpu {keeps} oracle {keeps_o}; max rel dE {dE:.2e}; drift {drift:.2e}; "
+          f"hole err gpu {err:.4f} oracle {err_o:.4f}", flush=True)
+    assert keeps == keeps_o
+    assert len(set(keeps)) == 2
+    assert dE <= 1e-3
+    assert drift <= 1e-3

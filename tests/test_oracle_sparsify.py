@@ -177,3 +177,79 @@ def test_block_ordered_haar_gives_the_same_result():
         Y2, e2, n2 = sparsify.cpa_shrink_sparsified(B, sh, Lam, 12, Tb, k, zero=zb)
         assert n1 == n2 and abs(e1 - e2) <= 1e-12 * e1
         assert np.abs(Y1 - Y2).max() <= 1e-10 * np.abs(Y1).max()
+
+
+def _schedule_fixture():
+    """The fractions and switch points printed in eq. (recommendation_epsilon) and
+    Table IV's caption (tests/golden/keep_schedule.txt), as exact decimals."""
+    from decimal import Decimal
+    from fractions import Fraction
+    from pathlib import Path
+    vals = {}
+    for line in (Path(__file__).parent / "golden" / "keep_schedule.txt").read_text().splitlines():
+        if line.strip() and not line.startswith("#"):
+            parts = line.split()
+            vals[parts[0]] = Fraction(Decimal(parts[1]))
+    return vals
+
+
+def test_keep_schedule_matches_the_printed_fractions():
+    """k = ceil(f n^2) with the printed fraction f of each case, for sizes where the
+    product is and is not an integer; the paper's own n = 1000 comparison gives
+    k_1, k_2, k_3 = 50, 150, 500."""
+    g = _schedule_fixture()
+    E_l, E_m = float(g["E_l"]), float(g["E_m"])
+    assert (E_l, E_m) == (0.03, 6e-4)
+    for n in (8, 96, 141, 256, 1000, 1024, 1920, 4000):
+        for E, key in ((math.inf, "k_1"), (1.0, "k_1"), (0.01, "k_2"), (1e-4, "k_3"), (0.0, "k_3")):
+            want = max(1, math.ceil(g[key] * n * n))
+            assert sparsify.keep_schedule(E, n) == want, (n, E)
+    assert [sparsify.keep_schedule(E, 1000) for E in (1.0, 0.01, 1e-4)] == [50, 150, 500]
+    assert math.ceil(g["k_4"] * 1000 ** 2) == 1000 ** 2
+
+
+def test_keep_schedule_case_edges():
+    """E_t = E_l falls in the second case and E_t = E_m in the third (the equation's
+    inequalities); the count never leaves [1, n^2]."""
+    assert sparsify.keep_schedule(0.03, 1000) == 150
+    assert sparsify.keep_schedule(math.nextafter(0.03, 1.0), 1000) == 50
+    assert sparsify.keep_schedule(6e-4, 1000) == 500
+    assert sparsify.keep_schedule(math.nextafter(6e-4, 1.0), 1000) == 150
+    assert sparsify.keep_schedule(1.0, 1) == 1 and sparsify.keep_schedule(0.0, 1) == 1
+    assert sparsify.keep_schedule(0.0, 44) == 1          # 1936 / 2000 rounds up to 1
+    assert sparsify.keep_schedule(0.0, 45) == 2          # 2025 / 2000 rounds up to 2
+    with pytest.raises(ValueError):
+        sparsify.keep_schedule(math.nan, 8)
+
+
+def test_inpaint_step_without_truncation_is_the_plain_step():
+    """With every component kept (k = n^2, Table IV's k_4) the sparsified z1 of the
+    inpainting step is the plain shrink (an orthogonal similarity), for the DCT
+    and the block DCT; with a keep count below n^2 it differs."""
+    from oracle import drivers
+    import synth
+    I, om, bd, _ = synth.texture(48, 40, border=4, seed=5)
+    st = drivers.inpaint_start(om)
+    st, _ = drivers.inpaint_step(st, I, om, bd, 1.0, 0.01, 15)
+    ref, info = drivers.inpaint_step(st, I, om, bd, 1.0, 0.01, 15, power_iters=300, tol_power=1e-12)
+    for T in (sparsify.dct_matrix(40), sparsify.block_dct(40, 8)):
+        sp, info_s = drivers.inpaint_step(st, I, om, bd, 1.0, 0.01, 15, power_iters=300, tol_power=1e-12,
+                                          sparsify={"T": T, "keep": 40 * 40})
+        for k in ("l", "z1", "u1", "z2", "z5"):
+            assert np.linalg.norm(sp[k] - ref[k]) <= 1e-9 * max(np.linalg.norm(ref[k]), 1.0), k
+        assert abs(info_s["E"] - info["E"]) <= 1e-12
+        cut, _ = drivers.inpaint_step(st, I, om, bd, 1.0, 0.01, 15, sparsify={"T": T, "keep": 4})
+        assert np.linalg.norm(cut["z1"] - ref["z1"]) > 1e-3 * np.linalg.norm(ref["z1"])
+
+
+def test_scheduled_inpaint_uses_the_previous_change():
+    """The scheduled ADMM takes iteration t's keep from E_{t-1} (E_prev first)."""
+    from oracle import drivers
+    import synth
+    I, om, bd, _ = synth.texture(64, 64, border=4, seed=5)
+    st, E, keeps = drivers.inpaint_admm(I, om, bd, 1.0, 0.01, 8, 15,
+                                        schedule={"T": sparsify.dct_matrix(64), "E_l": 0.7, "E_m": 0.3,
+                                                  "E_prev": 0.3})
+    want = [sparsify.keep_schedule(e, 64, 0.7, 0.3) for e in [0.3] + E[:-1]]
+    assert keeps == want
+    assert len(set(keeps)) >= 2
