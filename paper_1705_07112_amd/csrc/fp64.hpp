@@ -5,10 +5,11 @@
 // double precision.  The bound and the coefficients come from the same FP64
 // kernels as the FP32 path (power iteration on the FP64 Gram).
 //
-// gemm_f64_kernel: C = op(A) op(B) with 64 x 64 output tiles, K-steps of 16,
+// gemm_f64_kernel: C = op(A) op(B) with 64 x 64 output tiles, K-steps of 32,
 // on the FP64 matrix cores (v_mfma_f64_16x16x4f64): four waves, each a 32 x 32
 // output as 2 x 2 blocks of 16 x 16; operand tiles go through LDS ([k][i] and
-// [k][j], zero fill outside the matrix).  op(A)[i][k] is A[k][i] when TA (the
+// [k][j], zero fill outside the matrix), the next tile's global reads in flight
+// in registers while the current tile is multiplied.  op(A)[i][k] is A[k][i] when TA (the
 // Gram X^T X reads X transposed), op(B)[k][j] is B[j][k] when TB (X X^T).
 #pragma once
 
@@ -19,8 +20,24 @@
 
 namespace cpa {
 
-constexpr int F64_BM = 64, F64_BN = 64, F64_BK = 16;
+constexpr int F64_BM = 64, F64_BN = 64, F64_BK = 32;
+constexpr int F64_LOADS = F64_BM * F64_BK / 256;   // operand elements per thread and tile
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Operand element r of thread tid for the K-tile at k0: (row or column index,
+// k index) inside the tile, chosen so that consecutive threads read consecutive
+// addresses of the operand.
+template <bool KMAJOR>
+__device__ inline void f64_tile_pos(int tid, int r, int& x, int& k) {
+    const int e = tid + 256 * r;
+    if (KMAJOR) {   // the operand's row index runs along k: consecutive x are adjacent
+        x = e % F64_BM;
+        k = e / F64_BM;
+    } else {        // k is contiguous
+        x = e / F64_BK;
+        k = e % F64_BK;
+    }
+}
 
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256) gemm_f64_kernel(int M, int N, int Kd, const double* A, int64_t lda,
@@ -36,26 +53,39 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(int M, int N, int Kd, con
     for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) acc[x][y] = (f64x4){0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < Kd; k0 += F64_BK) {
-        // consecutive threads read consecutive addresses of each operand
-        for (int e = tid; e < F64_BM * F64_BK; e += 256) {
-            const int ii = TA ? e % F64_BM : e / F64_BK;
-            const int kk = TA ? e / F64_BM : e % F64_BK;
+    // the next K-tile is read into registers while the current one is multiplied
+    double ra[F64_LOADS], rb[F64_LOADS];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < F64_LOADS; ++r) {
+            int ii, kk;
+            f64_tile_pos<TA>(tid, r, ii, kk);
             const int gi = i0 + ii, gk = k0 + kk;
-            double v = 0.0;
-            if (gi < M && gk < Kd) v = TA ? A[(int64_t)gk * lda + gi] : A[(int64_t)gi * lda + gk];
-            As[kk][ii] = v;
+            ra[r] = (gi < M && gk < Kd) ? (TA ? A[(int64_t)gk * lda + gi] : A[(int64_t)gi * lda + gk]) : 0.0;
+            int jj;
+            f64_tile_pos<!TB>(tid, r, jj, kk);
+            const int gj = j0 + jj;
+            const int gk2 = k0 + kk;
+            rb[r] = (gj < N && gk2 < Kd) ? (TB ? B[(int64_t)gj * ldb + gk2] : B[(int64_t)gk2 * ldb + gj]) : 0.0;
         }
-        for (int e = tid; e < F64_BN * F64_BK; e += 256) {
-            const int jj = TB ? e / F64_BK : e % F64_BN;
-            const int kk = TB ? e % F64_BK : e / F64_BN;
-            const int gj = j0 + jj, gk = k0 + kk;
-            double v = 0.0;
-            if (gj < N && gk < Kd) v = TB ? B[(int64_t)gj * ldb + gk] : B[(int64_t)gk * ldb + gj];
-            Bs[kk][jj] = v;
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int r = 0; r < F64_LOADS; ++r) {
+            int ii, jj, kk;
+            f64_tile_pos<TA>(tid, r, ii, kk);
+            As[kk][ii] = ra[r];
+            f64_tile_pos<!TB>(tid, r, jj, kk);
+            Bs[kk][jj] = rb[r];
         }
-        __syncthreads();
-        // four k sub-steps of 4: lane l supplies row (or column) l % 16 at k = l / 16
+    };
+    fetch(0);
+    stash();
+    __syncthreads();
+    for (int k0 = 0; k0 < Kd; k0 += F64_BK) {
+        const bool more = k0 + F64_BK < Kd;
+        if (more) fetch(k0 + F64_BK);
+        // k sub-steps of 4: lane l supplies row (or column) l % 16 at k = l / 16
 #pragma unroll
         for (int ks = 0; ks < F64_BK / 4; ++ks) {
             const int kk = 4 * ks + (lane >> 4);
@@ -70,6 +100,10 @@ __global__ void __launch_bounds__(256) gemm_f64_kernel(int M, int N, int Kd, con
                 for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
         }
         __syncthreads();
+        if (more) {
+            stash();
+            __syncthreads();
+        }
     }
     // lane l holds rows l / 16 + 4 r and column l % 16 of each 16 x 16 block (the
     // FP64 instruction interleaves the rows; the FP32 one gives 4 (l / 16) + r)
