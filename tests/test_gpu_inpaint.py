@@ -170,3 +170,48 @@ def test_scheduled_inpaint_run_follows_the_oracle():
     assert len(set(keeps)) == 2
     assert dE <= 1e-3
     assert drift <= 1e-3
+
+
+def test_scheduled_inpaint_continues_across_calls():
+    """16 iterations in one call equal 8 + 8 with the second call given the first's
+    last E_t as E_prev, bit for bit (the same keeps, E_t and state).  The power
+    bound starts cold in every shrink here, so the two runs do not share a warm
+    start through the context."""
+    import torch
+    import paper_1705_07112_amd as cpa
+    m, n = 128, 96
+    I, om, bd, _ = synth.texture(m, n, border=4, seed=5)
+    runs = []
+    for split in (False, True):
+        run = cpa.Inpaint(torch.from_numpy(I.astype(np.float32)).cuda(), torch.from_numpy(om), 1.0, 0.01,
+                          cpa.Opts(K=15, warm_start=False, power_iters=100),
+                          border=torch.from_numpy(bd.astype(np.float32)))
+        Et = torch.zeros(16, dtype=torch.float64, device="cuda")
+        if split:
+            keeps = run.iterate_scheduled(8, Et[:8], transform="dct")
+            torch.cuda.synchronize()
+            keeps += run.iterate_scheduled(8, Et[8:], transform="dct", E_prev=Et[7].item())
+        else:
+            keeps = run.iterate_scheduled(16, Et, transform="dct")
+        torch.cuda.synchronize()
+        runs.append((keeps, Et.cpu().numpy(), run.state.cpu().numpy()))
+    (k1, e1, s1), (k2, e2, s2) = runs
+    print(f"scheduled inpaint split run: keeps {k1}", flush=True)
+    assert k1 == k2
+    assert np.array_equal(e1, e2)
+    assert np.array_equal(s1, s2)
+
+
+def test_scheduled_inpaint_rejects_a_gram_side_off_the_8_grid():
+    """The sparsified shrink needs a Gram side that is a multiple of 8: the
+    scheduled driver says so before any work is queued, and the state is unchanged."""
+    import torch
+    import paper_1705_07112_amd as cpa
+    run, *_ = _run(100, 90, (40, 60, 30, 50), 3, True, 12, 1.0, 0.01, 7)
+    before = run.state.clone()
+    Et = torch.zeros(2, dtype=torch.float64, device="cuda")
+    with pytest.raises(cpa.CpaError) as e:
+        run.iterate_scheduled(2, Et, transform="dct")
+    assert e.value.status == 2 and "multiple of 8" in str(e.value)
+    torch.cuda.synchronize()
+    assert torch.equal(run.state, before)
