@@ -728,7 +728,7 @@ def main():
     out["fp64"] = {"ms_per_shrink": round(ms64, 3), "shrinks_per_s": round(1e3 / ms64, 2),
                    "tflops": round(flop64 / (ms64 * 1e-3) / 1e12, 2), "peak_fp64_tflops": 78.6,
                    "note": "cpa_shrink_dense_f64 on the 1024 x 1024 frames: FP64 Gram, power bound and K - 1 = 29 "
-                           "FP64 products (FP64 matrix cores, 64 x 64 tiles, K-steps of 32 with register prefetch)"}
+                           "FP64 products (FP64 matrix cores, 64 x 64 tiles, 8 waves, K-steps of 32 split in two, two LDS stages, register prefetch)"}
     del X64d
 
     check = None

@@ -2573,7 +2573,7 @@ template <bool TA, bool TB>
 cpa_status gemm64(hipStream_t st, int M, int N, int Kd, const double* A, int64_t lda, const double* B, int64_t ldb,
                   double* C, int64_t ldc) {
     const dim3 grid((N + F64_BN - 1) / F64_BN, (M + F64_BM - 1) / F64_BM);
-    hipLaunchKernelGGL((gemm_f64_kernel<TA, TB>), grid, dim3(256), 0, st, M, N, Kd, A, lda, B, ldb, C, ldc);
+    hipLaunchKernelGGL((gemm_f64_kernel<TA, TB>), grid, dim3(F64_THREADS), 0, st, M, N, Kd, A, lda, B, ldb, C, ldc);
     HIP_TRY(hipGetLastError());
     return CPA_OK;
 }

@@ -6,10 +6,11 @@
 // kernels as the FP32 path (power iteration on the FP64 Gram).
 //
 // gemm_f64_kernel: C = op(A) op(B) with 64 x 64 output tiles, K-steps of 32,
-// on the FP64 matrix cores (v_mfma_f64_16x16x4f64): four waves, each a 32 x 32
-// output as 2 x 2 blocks of 16 x 16; operand tiles go through LDS ([k][i] and
-// [k][j], zero fill outside the matrix), the next tile's global reads in flight
-// in registers while the current tile is multiplied.  op(A)[i][k] is A[k][i] when TA (the
+// on the FP64 matrix cores (v_mfma_f64_16x16x4f64): eight waves, two per 32 x 32
+// output (2 x 2 blocks of 16 x 16), each taking half of every K-step, their
+// partial sums added through LDS at the end; operand tiles go through two LDS
+// stages ([k][i] and [k][j], zero fill outside the matrix), the next tile's
+// global reads in flight in registers while the current tile is multiplied.  op(A)[i][k] is A[k][i] when TA (the
 // Gram X^T X reads X transposed), op(B)[k][j] is B[j][k] when TB (X X^T).
 #pragma once
 
@@ -21,7 +22,9 @@
 namespace cpa {
 
 constexpr int F64_BM = 64, F64_BN = 64, F64_BK = 32;
-constexpr int F64_LOADS = F64_BM * F64_BK / 256;   // operand elements per thread and tile
+constexpr int F64_THREADS = 512;                            // 8 waves: 2 x 2 output blocks x K-split 2
+constexpr int F64_LOADS = F64_BM * F64_BK / F64_THREADS;    // operand elements per thread and tile
+constexpr int F64_PITCH = F64_BM + 1;
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // Operand element r of thread tid for the K-tile at k0: (row or column index,
@@ -29,7 +32,7 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 // addresses of the operand.
 template <bool KMAJOR>
 __device__ inline void f64_tile_pos(int tid, int r, int& x, int& k) {
-    const int e = tid + 256 * r;
+    const int e = tid + F64_THREADS * r;
     if (KMAJOR) {   // the operand's row index runs along k: consecutive x are adjacent
         x = e % F64_BM;
         k = e / F64_BM;
@@ -40,83 +43,98 @@ __device__ inline void f64_tile_pos(int tid, int r, int& x, int& k) {
 }
 
 template <bool TA, bool TB>
-__global__ void __launch_bounds__(256) gemm_f64_kernel(int M, int N, int Kd, const double* A, int64_t lda,
-                                                       const double* B, int64_t ldb, double* C, int64_t ldc) {
-    __shared__ double As[F64_BK][F64_BM + 1];   // [k][i]
-    __shared__ double Bs[F64_BK][F64_BN + 1];   // [k][j]
+__global__ void __launch_bounds__(F64_THREADS) gemm_f64_kernel(int M, int N, int Kd, const double* A, int64_t lda,
+                                                               const double* B, int64_t ldb, double* C, int64_t ldc) {
+    // two stages of [k][i] and [k][j] tiles; the epilogue reuses stage 0 for the
+    // K-split sum
+    __shared__ double lds[2][2][F64_BK][F64_PITCH];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;   // the wave's 32 x 32 output
+    const int wo = wave & 3, kh = wave >> 2;   // output block, half of each K-tile
+    const int wr = wo >> 1, wc = wo & 1;       // the wave's 32 x 32 output
     const int i0 = blockIdx.y * F64_BM, j0 = blockIdx.x * F64_BN;
     f64x4 acc[2][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y) acc[x][y] = (f64x4){0.0, 0.0, 0.0, 0.0};
-    // the next K-tile is read into registers while the current one is multiplied
+    // the next K-tile is read into registers while the current one is multiplied,
+    // then written to the other stage (last read one step earlier)
     double ra[F64_LOADS], rb[F64_LOADS];
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int r = 0; r < F64_LOADS; ++r) {
-            int ii, kk;
+            int ii, jj, kk;
             f64_tile_pos<TA>(tid, r, ii, kk);
             const int gi = i0 + ii, gk = k0 + kk;
             ra[r] = (gi < M && gk < Kd) ? (TA ? A[(int64_t)gk * lda + gi] : A[(int64_t)gi * lda + gk]) : 0.0;
-            int jj;
             f64_tile_pos<!TB>(tid, r, jj, kk);
-            const int gj = j0 + jj;
-            const int gk2 = k0 + kk;
+            const int gj = j0 + jj, gk2 = k0 + kk;
             rb[r] = (gj < N && gk2 < Kd) ? (TB ? B[(int64_t)gj * ldb + gk2] : B[(int64_t)gk2 * ldb + gj]) : 0.0;
         }
     };
-    auto stash = [&]() {
+    auto stash = [&](int st) {
 #pragma unroll
         for (int r = 0; r < F64_LOADS; ++r) {
             int ii, jj, kk;
             f64_tile_pos<TA>(tid, r, ii, kk);
-            As[kk][ii] = ra[r];
+            lds[st][0][kk][ii] = ra[r];
             f64_tile_pos<!TB>(tid, r, jj, kk);
-            Bs[kk][jj] = rb[r];
+            lds[st][1][kk][jj] = rb[r];
         }
     };
     fetch(0);
-    stash();
+    stash(0);
     __syncthreads();
+    int st = 0;
     for (int k0 = 0; k0 < Kd; k0 += F64_BK) {
         const bool more = k0 + F64_BK < Kd;
         if (more) fetch(k0 + F64_BK);
-        // k sub-steps of 4: lane l supplies row (or column) l % 16 at k = l / 16
+        // this wave's k sub-steps of 4: lane l supplies row (or column) l % 16 at k = l / 16
 #pragma unroll
-        for (int ks = 0; ks < F64_BK / 4; ++ks) {
-            const int kk = 4 * ks + (lane >> 4);
+        for (int ks = 0; ks < F64_BK / 8; ++ks) {
+            const int kk = kh * (F64_BK / 2) + 4 * ks + (lane >> 4);
             double a[2], b[2];
 #pragma unroll
-            for (int x = 0; x < 2; ++x) a[x] = As[kk][wr * 32 + x * 16 + (lane & 15)];
+            for (int x = 0; x < 2; ++x) a[x] = lds[st][0][kk][wr * 32 + x * 16 + (lane & 15)];
 #pragma unroll
-            for (int y = 0; y < 2; ++y) b[y] = Bs[kk][wc * 32 + y * 16 + (lane & 15)];
+            for (int y = 0; y < 2; ++y) b[y] = lds[st][1][kk][wc * 32 + y * 16 + (lane & 15)];
 #pragma unroll
             for (int x = 0; x < 2; ++x)
 #pragma unroll
                 for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
         }
+        if (more) stash(st ^ 1);
         __syncthreads();
-        if (more) {
-            stash();
-            __syncthreads();
-        }
+        st ^= 1;
     }
     // lane l holds rows l / 16 + 4 r and column l % 16 of each 16 x 16 block (the
-    // FP64 instruction interleaves the rows; the FP32 one gives 4 (l / 16) + r)
+    // FP64 instruction interleaves the rows; the FP32 one gives 4 (l / 16) + r).
+    // The second K half adds its partial sums to the first's through LDS.
+    double (*red)[F64_PITCH] = reinterpret_cast<double (*)[F64_PITCH]>(&lds[0][0][0][0]);
+    if (kh == 1) {
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+        for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+            for (int y = 0; y < 2; ++y)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = i0 + wr * 32 + x * 16 + (lane >> 4) + 4 * r;
-                const int j = j0 + wc * 32 + y * 16 + (lane & 15);
-                if (i < M && j < N) C[(int64_t)i * ldc + j] = acc[x][y][r];
-            }
+                for (int r = 0; r < 4; ++r)
+                    red[wr * 32 + x * 16 + (lane >> 4) + 4 * r][wc * 32 + y * 16 + (lane & 15)] = acc[x][y][r];
+    }
+    __syncthreads();
+    if (kh == 0) {
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int li = wr * 32 + x * 16 + (lane >> 4) + 4 * r;
+                    const int lj = wc * 32 + y * 16 + (lane & 15);
+                    const int i = i0 + li, j = j0 + lj;
+                    if (i < M && j < N) C[(int64_t)i * ldc + j] = acc[x][y][r] + red[li][lj];
+                }
+    }
 }
 
 // One recurrence step on an m x n matrix, element (r, c) per thread:
