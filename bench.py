@@ -596,6 +596,17 @@ def main():
     wall = time.perf_counter() - wall0
     ms = t0.elapsed_time(t1)
 
+    # spread of the step time (untimed for `value`): single replays, each
+    # bracketed by its own pair of events on the same stream
+    n_spread = max(args.steps, 20)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_spread)]
+    for a_, b_ in ev:
+        a_.record()
+        run.iterate(1, Et)
+        b_.record()
+    torch.cuda.synchronize()
+    per_step = np.array([a_.elapsed_time(b_) for a_, b_ in ev])
+
     # roofline pass: the same iterations again with every GEMM launch bracketed by
     # HIP events on the launch stream (event timing needs direct launches)
     cpa.timing_enable(True)
@@ -652,7 +663,7 @@ def main():
 
     # achievable rates on this device, measured beside the spec peaks: pure-register
     # MFMA streams (cpa_peak_mfma) and a plain 256 MiB device copy
-    peak32 = cpa.peak_mfma("fp32")
+    peak32, clock32 = cpa.peak_mfma("fp32", clock=True)
     peak16 = cpa.peak_mfma("bf16")
     csrc = torch.ones(64 << 20, dtype=torch.float32, device=dev)
     cdst = torch.empty_like(csrc)
@@ -667,7 +678,12 @@ def main():
     del csrc, cdst
     out["roofline"]["achievable_peak"] = round(peak32, 1)
     out["roofline"]["frac_of_achievable"] = round(achieved / peak32, 4)
+    out["step_ms_spread"] = {"median": round(float(np.median(per_step)), 4),
+                             "p10": round(float(np.percentile(per_step, 10)), 4),
+                             "p90": round(float(np.percentile(per_step, 90)), 4), "steps": n_spread,
+                             "method": "single graph replays after the timed region, each between two events"}
     out["achievable_peaks"] = {"mfma_fp32_tflops": round(peak32, 1), "mfma_bf16_tflops": round(peak16, 1),
+                               "clock_ghz_under_fp32_mfma": round(clock32, 3),
                                "hbm_copy_tbps": round(copy_tbps, 2),
                                "method": "cpa_peak_mfma (register-only MFMA streams, 4 waves/SIMD); "
                                          "device copy of 256 MiB (read + write bytes)"}

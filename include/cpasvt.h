@@ -565,8 +565,12 @@ cpa_status cpa_timing_read(cpa_ctx* ctx, int which, double* total_ms_host, int64
  * of eight independent MFMAs on register operands (kind 0:
  * v_mfma_f32_16x16x4f32, 1: v_mfma_f32_16x16x32_bf16; four waves per SIMD, no
  * memory traffic), twice, and returns the second launch's rate in TFLOP/s
- * (dense flops).  Synchronises `stream`. */
-cpa_status cpa_peak_mfma(cpa_ctx* ctx, void* stream, int kind, int iters, double* tflops_host);
+ * (dense flops).  clock_ghz_host (nullable) receives the shader clock during the
+ * second launch's MFMA loop: the first wave's shader-cycle count over its span of
+ * the constant-rate wall counter (hipDeviceAttributeWallClockRate).  Synchronises
+ * `stream`. */
+cpa_status cpa_peak_mfma(cpa_ctx* ctx, void* stream, int kind, int iters, double* tflops_host,
+                         double* clock_ghz_host);
 
 #ifdef __cplusplus
 }

@@ -111,7 +111,8 @@ _SIGS = {
                                                      ctypes.POINTER(CpaOpts), ctypes.c_int32, ctypes.c_double,
                                                      ctypes.c_double, ctypes.c_double, _P, _P]),
     "cpa_timing_enable": (ctypes.c_int, [_P, ctypes.c_int]),
-    "cpa_peak_mfma": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]),
+    "cpa_peak_mfma": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]),
     "cpa_workspace_bytes": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(CpaOpts),
                                            ctypes.POINTER(ctypes.c_size_t)]),
     "cpa_timing_read": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
@@ -544,14 +545,17 @@ def workspace_bytes(m: int, n: int, opts: Opts, device: int = 0) -> int:
     return int(out.value)
 
 
-def peak_mfma(kind: str = "fp32", iters: int = 4000, device: int = 0) -> float:
-    """Achievable dense MFMA rate of the device in TFLOP/s (see cpa_peak_mfma)."""
+def peak_mfma(kind: str = "fp32", iters: int = 4000, device: int = 0, clock: bool = False):
+    """Achievable dense MFMA rate of the device in TFLOP/s (see cpa_peak_mfma);
+    with clock=True, (rate, shader clock in GHz during the MFMA loop)."""
     import torch
     out = ctypes.c_double()
+    ghz = ctypes.c_double()
     _check(lib().cpa_peak_mfma(ctypes.c_void_p(context(device)),
                                ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream),
-                               {"fp32": 0, "bf16": 1}[kind], int(iters), ctypes.byref(out)))
-    return out.value
+                               {"fp32": 0, "bf16": 1}[kind], int(iters), ctypes.byref(out),
+                               ctypes.byref(ghz) if clock else None))
+    return (out.value, ghz.value) if clock else out.value
 
 
 def timing_enable(enable: bool = True, device: int = 0):

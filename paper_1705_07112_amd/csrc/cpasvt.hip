@@ -1912,7 +1912,8 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
 
 extern "C" {
 
-cpa_status cpa_peak_mfma(cpa_ctx* ctx, void* stream, int kind, int iters, double* tflops_host) {
+cpa_status cpa_peak_mfma(cpa_ctx* ctx, void* stream, int kind, int iters, double* tflops_host,
+                         double* clock_ghz_host) {
     if (!ctx || !tflops_host) return fail(CPA_ERR_ARG, "NULL argument");
     if (kind != 0 && kind != 1) return fail(CPA_ERR_ARG, "kind must be 0 (FP32) or 1 (BF16)");
     if (iters < 1 || iters > (1 << 20)) return fail(CPA_ERR_ARG, "iters must be in [1, 2^20]");
@@ -1921,8 +1922,15 @@ cpa_status cpa_peak_mfma(cpa_ctx* ctx, void* stream, int kind, int iters, double
     int cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
     const int grid = 4 * cus;   // four 4-wave workgroups per CU: four waves per SIMD
+    int wall_khz = 0;
+    if (clock_ghz_host) HIP_TRY(hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, ctx->device));
     float* out = nullptr;
-    if (hipMalloc(&out, sizeof(float) * (size_t)grid * 256) != hipSuccess) return fail(CPA_ERR_ALLOC, "allocation failed");
+    // the two counter spans follow the per-thread outputs
+    const size_t out_bytes = sizeof(float) * (size_t)grid * 256;
+    if (hipMalloc(&out, out_bytes + 2 * sizeof(unsigned long long)) != hipSuccess)
+        return fail(CPA_ERR_ALLOC, "allocation failed");
+    unsigned long long* clk =
+        clock_ghz_host ? reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(out) + out_bytes) : nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     cpa_status s = CPA_OK;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) s = fail(CPA_ERR_HIP, "event creation failed");
@@ -1930,9 +1938,9 @@ cpa_status cpa_peak_mfma(cpa_ctx* ctx, void* stream, int kind, int iters, double
     for (int r = 0; s == CPA_OK && r < 2; ++r) {   // the first launch warms the clocks up
         if (hipEventRecord(e0, st) != hipSuccess) s = fail(CPA_ERR_HIP, "event record failed");
         if (kind == 0)
-            hipLaunchKernelGGL(peak_mfma_kernel<0>, dim3(grid), dim3(256), 0, st, iters, out);
+            hipLaunchKernelGGL(peak_mfma_kernel<0>, dim3(grid), dim3(256), 0, st, iters, out, clk);
         else
-            hipLaunchKernelGGL(peak_mfma_kernel<1>, dim3(grid), dim3(256), 0, st, iters, out);
+            hipLaunchKernelGGL(peak_mfma_kernel<1>, dim3(grid), dim3(256), 0, st, iters, out, clk);
         if (s == CPA_OK && hipGetLastError() != hipSuccess) s = fail(CPA_ERR_HIP, "launch failed");
         if (s == CPA_OK && hipEventRecord(e1, st) != hipSuccess) s = fail(CPA_ERR_HIP, "event record failed");
         if (s == CPA_OK && hipEventSynchronize(e1) != hipSuccess) s = fail(CPA_ERR_HIP, "event wait failed");
@@ -1940,8 +1948,14 @@ cpa_status cpa_peak_mfma(cpa_ctx* ctx, void* stream, int kind, int iters, double
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
+    unsigned long long span[2] = {0, 0};
+    if (s == CPA_OK && clk && hipMemcpy(span, clk, sizeof(span), hipMemcpyDeviceToHost) != hipSuccess)
+        s = fail(CPA_ERR_HIP, "counter read failed");
     (void)hipFree(out);
     if (s != CPA_OK) return s;
+    if (clock_ghz_host)
+        *clock_ghz_host = (span[1] > 0 && wall_khz > 0) ? (double)span[0] / ((double)span[1] / (wall_khz * 1e3)) / 1e9
+                                                        : 0.0;
     const double flop = (double)grid * 4 /* waves */ * iters * kPeakChains * (kind == 0 ? 2048.0 : 16384.0);
     *tflops_host = flop / (1e-3 * ms) / 1e12;
     return CPA_OK;

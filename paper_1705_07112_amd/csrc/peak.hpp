@@ -13,8 +13,17 @@ namespace cpa {
 constexpr int kPeakChains = 8;
 
 // KIND 0: v_mfma_f32_16x16x4f32 (2048 flop), 1: v_mfma_f32_16x16x32_bf16 (16384 flop).
+// clk (nullable): the first wave of the first workgroup stores the shader-clock
+// counter and the constant-rate wall counter before and after its MFMA loop, so
+// the host can tell the clock the matrix cores ran at.
 template <int KIND>
-__global__ void __launch_bounds__(256) peak_mfma_kernel(int iters, float* out) {
+__global__ void __launch_bounds__(256) peak_mfma_kernel(int iters, float* out, unsigned long long* clk) {
+    const bool timer = clk != nullptr && blockIdx.x == 0 && threadIdx.x == 0;
+    unsigned long long cyc0 = 0, wall0 = 0;
+    if (timer) {
+        cyc0 = clock64();
+        wall0 = wall_clock64();
+    }
     f32x4 c[kPeakChains];
 #pragma unroll
     for (int i = 0; i < kPeakChains; ++i) c[i] = (f32x4){0.f, 0.f, 0.f, 0.f};
@@ -42,6 +51,11 @@ __global__ void __launch_bounds__(256) peak_mfma_kernel(int iters, float* out) {
 #pragma unroll
     for (int i = 0; i < kPeakChains; ++i) s += (c[i][0] + c[i][1]) + (c[i][2] + c[i][3]);
     out[(size_t)blockIdx.x * 256 + threadIdx.x] = s;
+    if (timer) {
+        const unsigned long long cyc1 = clock64(), wall1 = wall_clock64();
+        clk[0] = cyc1 - cyc0;
+        clk[1] = wall1 - wall0;
+    }
 }
 
 }  // namespace cpa
