@@ -378,7 +378,15 @@ cpa_status cpa_shrink_batched(cpa_ctx* ctx, void* stream, int batch, const int32
  *              CPA_TRANSFORM_DCT (the orthonormal DCT-II over the whole side, dense:
  *              T G T^T and T^T hat H T by FP32 products, Phi then symmetrised), or
  *              CPA_TRANSFORM_IDENTITY (truncation of the Gram itself).
- *   keep: 1 <= keep <= d^2 (d: the Gram side, a multiple of 8).
+ *   threshold: CPA_THRESHOLD_KEEP: eps = the keep-th largest |Phi_ij|,
+ *              1 <= keep <= d^2 (d: the Gram side, a multiple of 8) -- the
+ *              K(|Phi|, k) of eq. (recommendation_epsilon);
+ *              CPA_THRESHOLD_ABSOLUTE: eps given (finite, >= 0; the experiments
+ *              of Table III fix eps), compared with the FP32 |Phi_ij| after rounding
+ *              to FP32; keep is ignored.  An eps above every |Phi_ij| keeps nothing:
+ *              the truncated matrix is zero, its bound is 0 and Y = 0 (on both
+ *              routes; the kept count is read back, so the call waits for the
+ *              stream once on the recurrence route too).
  * FP32, check = 0 only.  eps_host and nnz_host (nullable) receive the threshold
  * and the number of kept entries (synchronising).
  * The truncated matrix need not be positive semidefinite: its spectrum can leave
@@ -392,10 +400,13 @@ typedef enum {
     CPA_TRANSFORM_DCT = 4
 } cpa_transform;
 
+typedef enum { CPA_THRESHOLD_KEEP = 0, CPA_THRESHOLD_ABSOLUTE = 1 } cpa_threshold;
+
 typedef struct {
     int32_t transform;  /* cpa_transform */
-    int32_t reserved;   /* must be 0 */
-    int64_t keep;       /* entries of |Phi| at or above the threshold: eps = keep-th largest */
+    int32_t threshold;  /* cpa_threshold */
+    int64_t keep;       /* CPA_THRESHOLD_KEEP: eps = the keep-th largest |Phi_ij| */
+    double eps;         /* CPA_THRESHOLD_ABSOLUTE: the threshold itself */
 } cpa_sparsify;
 
 cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n, const float* X_dev, int64_t ldx,

@@ -138,8 +138,10 @@ def keep_schedule(E_t: float, n: int, E_l: float = 0.03, E_m: float = 6e-4) -> i
     return min(max(k, 1), n * n)
 
 
-def cpa_shrink_sparsified(B: np.ndarray, shrink, Lambda: float, K: int, T: np.ndarray, k: int, zero=None):
-    """hat G(B) by Algorithm 1 with transform T and threshold eps = K(|Phi|, k).
+def cpa_shrink_sparsified(B: np.ndarray, shrink, Lambda: float, K: int, T: np.ndarray, k, zero=None, eps=None):
+    """hat G(B) by Algorithm 1 with transform T and threshold eps = K(|Phi|, k), or
+    the given eps of eq. (threshold_components) (k = None; the experiments of Table
+    III fix eps).
     zero (optional boolean mask over the transform's components): those rows and
     columns of Phi are set to zero first (the high frequencies of the DWT in
     Sec. V).  Lambda must bound the largest eigenvalue of the truncated matrix; it
@@ -151,10 +153,13 @@ def cpa_shrink_sparsified(B: np.ndarray, shrink, Lambda: float, K: int, T: np.nd
         Phi = Phi.copy()
         Phi[zero, :] = 0.0
         Phi[:, zero] = 0.0
-    eps = kth_largest_abs(Phi, k)
+    if eps is None:
+        eps = kth_largest_abs(Phi, k)
     Phil = truncate(Phi, eps)
     nnz = int(np.count_nonzero(np.abs(Phi) >= eps))
-    if Lambda <= 0.0:
+    # nothing kept: the truncated matrix is zero and so is its largest eigenvalue;
+    # every shrink function here has h(0) = 0, so the result is zero whatever Lambda
+    if Lambda <= 0.0 or nnz == 0:
         return np.zeros((m, n)), eps, nnz
     c = chebyshev.coefficients_shifted(shrink, Lambda, K)
     H = chebyshev_matrix_sum(Phil, c, Lambda)

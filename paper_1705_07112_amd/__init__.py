@@ -60,8 +60,12 @@ class CpaError(RuntimeError):
         self.status = status
 
 
+THRESHOLD_KEEP, THRESHOLD_ABSOLUTE = 0, 1
+
+
 class CpaSparsify(ctypes.Structure):
-    _fields_ = [("transform", ctypes.c_int32), ("reserved", ctypes.c_int32), ("keep", ctypes.c_int64)]
+    _fields_ = [("transform", ctypes.c_int32), ("threshold", ctypes.c_int32), ("keep", ctypes.c_int64),
+                ("eps", ctypes.c_double)]
 
 
 TRANSFORM_IDENTITY, TRANSFORM_BLOCK_DCT8, TRANSFORM_HAAR1, TRANSFORM_HAAR1_LOWPASS, TRANSFORM_DCT = 0, 1, 2, 3, 4
@@ -329,12 +333,14 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def shrink_dense_sparsified(X, shrink: CpaShrinkage, opts: Opts, keep: int, transform: str = "block_dct8",
-                            out=None, info: bool = False):
+def shrink_dense_sparsified(X, shrink: CpaShrinkage, opts: Opts, keep: int | None = None,
+                            transform: str = "block_dct8", out=None, info: bool = False, eps: float | None = None):
     """Algorithm 1 with a transform and truncation (see cpa_shrink_dense_sparsified):
     Phi = T G T^T, entries below the keep-th largest |Phi| dropped.  transform:
     "block_dct8", "haar1", "haar1_lowpass" (high frequencies set to zero), "dct"
-    (the full DCT-II) or "identity".  Returns Y, or (Y, info dict with 'eps' and 'nnz' added)."""
+    (the full DCT-II) or "identity".  The threshold is the keep-th largest |Phi|
+    (``keep``) or a given value (``eps``): exactly one of them.  Returns Y, or
+    (Y, info dict with 'eps' and 'nnz' added)."""
     import torch
     m, n, ldx = _mat(X, "X")
     if out is None:
@@ -342,7 +348,12 @@ def shrink_dense_sparsified(X, shrink: CpaShrinkage, opts: Opts, keep: int, tran
     _, _, ldy = _mat(out, "out")
     if tuple(out.shape) != (m, n):
         raise ValueError("out has the wrong shape")
-    sp = CpaSparsify(_TRANSFORMS[transform], 0, int(keep))
+    if (keep is None) == (eps is None):
+        raise ValueError("give exactly one of keep and eps")
+    if eps is None:
+        sp = CpaSparsify(_TRANSFORMS[transform], THRESHOLD_KEEP, int(keep), 0.0)
+    else:
+        sp = CpaSparsify(_TRANSFORMS[transform], THRESHOLD_ABSOLUTE, 0, float(eps))
     ci = CpaInfo()
     eps = ctypes.c_double()
     nnz = ctypes.c_int64()

@@ -2081,7 +2081,11 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
         sp->transform != CPA_TRANSFORM_HAAR1 && sp->transform != CPA_TRANSFORM_HAAR1_LOWPASS &&
         sp->transform != CPA_TRANSFORM_DCT)
         return fail(CPA_ERR_ARG, "unknown transform %d", sp->transform);
-    if (sp->reserved != 0) return fail(CPA_ERR_ARG, "sparsify.reserved must be 0");
+    if (sp->threshold != CPA_THRESHOLD_KEEP && sp->threshold != CPA_THRESHOLD_ABSOLUTE)
+        return fail(CPA_ERR_ARG, "unknown threshold mode %d", sp->threshold);
+    const bool abs_eps = sp->threshold == CPA_THRESHOLD_ABSOLUTE;
+    if (abs_eps && !(std::isfinite(sp->eps) && sp->eps >= 0.0))
+        return fail(CPA_ERR_ARG, "eps must be finite and >= 0");
     if (opts->check) return fail(CPA_ERR_UNSUPPORTED, "the growth check is not available on the sparsified path");
     if (opts->precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "the sparsified path is FP32");
     if (m == 0 || n == 0) {
@@ -2095,7 +2099,7 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
     const bool right = right_side(opts, m, n);
     const int d = right ? n : m;
     if (d % 8 != 0) return fail(CPA_ERR_SHAPE, "the Gram side (%d) must be a multiple of 8 (8 x 8 tiles)", d);
-    if (sp->keep < 1 || sp->keep > (int64_t)d * d) return fail(CPA_ERR_ARG, "keep must be in [1, d^2]");
+    if (!abs_eps && (sp->keep < 1 || sp->keep > (int64_t)d * d)) return fail(CPA_ERR_ARG, "keep must be in [1, d^2]");
     if ((int64_t)d * d > INT32_MAX) return fail(CPA_ERR_SHAPE, "Gram too large for 32-bit indices");
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
@@ -2155,16 +2159,22 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
             return r;
         return poly_gemm(ctx, st, make_op(f.Dm, d, d), make_op(f.P[1], d, d), d, d, d, em, CPA_PREC_FP32, false);
     };
-    // eps = the keep-th largest |Phi|
-    hipLaunchKernelGGL(sel_init_kernel, dim3(1), dim3(256), 0, st, f.sel, (uint32_t)sp->keep, f.hist);
-    HIP_TRY(hipGetLastError());
-    const int gh = (int)std::min<int64_t>(1024, ((int64_t)d * d + 255) / 256);
-    for (int pass = 0; pass < 3; ++pass) {
-        hipLaunchKernelGGL(sel_hist_kernel, dim3(gh), dim3(256), 0, st, d, (const float*)f.Phi, (int64_t)d, pass,
-                           (const SelState*)f.sel, f.hist);
+    if (abs_eps) {
+        // the given eps, as the key of its FP32 value
+        hipLaunchKernelGGL(sel_fixed_kernel, dim3(1), dim3(64), 0, st, f.sel, (float)sp->eps);
         HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(sel_pick_kernel, dim3(1), dim3(256), 0, st, pass, f.sel, f.hist);
+    } else {
+        // eps = the keep-th largest |Phi|
+        hipLaunchKernelGGL(sel_init_kernel, dim3(1), dim3(256), 0, st, f.sel, (uint32_t)sp->keep, f.hist);
         HIP_TRY(hipGetLastError());
+        const int gh = (int)std::min<int64_t>(1024, ((int64_t)d * d + 255) / 256);
+        for (int pass = 0; pass < 3; ++pass) {
+            hipLaunchKernelGGL(sel_hist_kernel, dim3(gh), dim3(256), 0, st, d, (const float*)f.Phi, (int64_t)d,
+                               pass, (const SelState*)f.sel, f.hist);
+            HIP_TRY(hipGetLastError());
+            hipLaunchKernelGGL(sel_pick_kernel, dim3(1), dim3(256), 0, st, pass, f.sel, f.hist);
+            HIP_TRY(hipGetLastError());
+        }
     }
     // the truncated matrix: CSR, and dense in place
     const int gr = (d + 3) / 4;
@@ -2182,12 +2192,44 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
     HIP_TRY(hipGetLastError());
     const EpiLin ey = lin_epi(Y_dev, ldy, nullptr, 0, 1.f, 0.f, 0.f, 0.f);
     Work wi = w;   // the layout read_info uses
-    if (poly) {
-        // the block's size sets every launch below: one wait for the stream
-        int32_t ns = 0;
+    // the requested host results: info, the threshold and the kept count
+    auto report = [&](const Work& wr) -> cpa_status {
+        cpa_status r;
+        if (info_host) {
+            if ((r = read_info(st, wr, opts->K, m, n, info_host, nullptr)) != CPA_OK) return r;
+        }
+        if (eps_host || nnz_host) {
+            SelState hs;
+            int32_t nnz = 0;
+            HIP_TRY(hipMemcpyAsync(&hs, f.sel, sizeof(hs), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(&nnz, f.rowptr + d, sizeof(nnz), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (eps_host) {
+                float e;
+                std::memcpy(&e, &hs.prefix, sizeof(e));
+                *eps_host = (double)e;
+            }
+            if (nnz_host) *nnz_host = nnz;
+        }
+        return CPA_OK;
+    };
+    // the block's size: it sets every launch of the polynomial route, and with a
+    // given eps it may be zero -- one wait for the stream in either case
+    int32_t ns = -1;
+    if (poly || abs_eps) {
         HIP_TRY(hipMemcpyAsync(&ns, f.nrows, sizeof(ns), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        if (ns < 1 || ns > d) return fail(CPA_ERR_HIP, "compact block size %d read back out of range", ns);
+        if (ns < 0 || ns > d || (ns == 0 && !abs_eps))
+            return fail(CPA_ERR_HIP, "compact block size %d read back out of range", ns);
+        if (ns == 0) {
+            // nothing kept (a given eps above every |Phi_ij|): the truncated matrix is
+            // zero, so is its largest eigenvalue, and the shrink is zero on either
+            // route (h(0) = 0 for every shrink function; the bound stays 0)
+            HIP_TRY(hipMemset2DAsync(Y_dev, sizeof(float) * (size_t)ldy, 0, sizeof(float) * (size_t)n, m, st));
+            return report(w);
+        }
+    }
+    if (poly) {
         // zero rows and columns appended to the block are empty ones too (eigenvalue 0,
         // never read back): a multiple of 64 gives full tiles to every product
         int nb = (ns + 63) / 64 * 64;
@@ -2255,23 +2297,7 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
             if (s != CPA_OK) return s;
         }
     }
-    if (info_host) {
-        if ((s = read_info(st, wi, opts->K, m, n, info_host, nullptr)) != CPA_OK) return s;
-    }
-    if (eps_host || nnz_host) {
-        SelState hs;
-        int32_t nnz = 0;
-        HIP_TRY(hipMemcpyAsync(&hs, f.sel, sizeof(hs), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(&nnz, f.rowptr + d, sizeof(nnz), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        if (eps_host) {
-            float e;
-            std::memcpy(&e, &hs.prefix, sizeof(e));
-            *eps_host = (double)e;
-        }
-        if (nnz_host) *nnz_host = nnz;
-    }
-    return CPA_OK;
+    return report(wi);
 }
 
 }  // extern "C"
@@ -2458,7 +2484,8 @@ cpa_status inpaint_run(cpa_ctx* ctx, void* stream, int m, int n, const float* I_
         HIP_TRY(hipGetLastError());
         // z1 = the CPA shrink of x = l + u1 (sparsified: keep from the previous E_t)
         if (sched) {
-            const cpa_sparsify sp = {sched->transform, 0, schedule_keep(e_prev, d, sched->E_l, sched->E_m)};
+            const cpa_sparsify sp = {sched->transform, CPA_THRESHOLD_KEEP, schedule_keep(e_prev, d, sched->E_l, sched->E_m),
+                                     0.0};
             if (sched->keep_host) sched->keep_host[t] = sp.keep;
             if ((s = cpa_shrink_dense_sparsified(ctx, stream, m, n, f.x, n, P.z[0], n, &sh, opts, &sp, nullptr,
                                                  nullptr, nullptr)) != CPA_OK)

@@ -281,6 +281,16 @@ __global__ void sel_init_kernel(SelState* st, uint32_t k, unsigned* hist) {
     }
 }
 
+// A given threshold: the key of |eps| (FP32), every bit fixed.
+__global__ void sel_fixed_kernel(SelState* st, float eps) {
+    if (threadIdx.x == 0) {
+        st->prefix = abs_key(eps);
+        st->mask = 0xffffffffu;
+        st->krem = 0u;
+        st->pad = 0u;
+    }
+}
+
 // One step of the recurrence on the truncated matrix (CSR):
 //   Z = underline Phi Psi_k,  Psi_{k+1} = a Z + b Psi_k + c Psi_{k-1},
 //   out = c_0/2 Psi_0 + c_1 Psi_1 (step 0) or out += c_{k+1} Psi_{k+1}

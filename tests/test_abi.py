@@ -35,6 +35,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(cpa.CpaOpts) == 80
     assert ctypes.sizeof(cpa.CpaInfo) == 56
     assert ctypes.sizeof(cpa.CpaBatchedTuning) == 32
+    assert ctypes.sizeof(cpa.CpaSparsify) == 24
 
 
 @pytest.mark.parametrize("kind,tau", [(0, 1.3), (1, 0.9), (2, 2.0)])
@@ -86,7 +87,7 @@ def test_inpaint_and_sparsified_argument_errors_before_any_device_work():
     assert st == 1 and b"context" in lib.cpa_last_error()
     st = lib.cpa_inpaint_init(None, None, 4, 4, ctypes.c_void_p(16), ctypes.c_void_p(4096))
     assert st == 1 and b"context" in lib.cpa_last_error()
-    sp = cpa.CpaSparsify(cpa.TRANSFORM_BLOCK_DCT8, 0, 4)
+    sp = cpa.CpaSparsify(cpa.TRANSFORM_BLOCK_DCT8, 0, 4, 0.0)
     info = cpa.CpaInfo()
     st = lib.cpa_shrink_dense_sparsified(None, None, 8, 8, ctypes.c_void_p(16), 8, ctypes.c_void_p(4096), 8,
                                          ctypes.byref(cpa.soft(1.0)), ctypes.byref(o), ctypes.byref(sp),

@@ -219,3 +219,72 @@ def test_sparsified_is_deterministic_and_rejects_bad_arguments():
     X2 = torch.ones((40, 36), device="cuda")
     with pytest.raises(cpa.CpaError):
         cpa.shrink_dense_sparsified(X2, cpa.soft(1.0), o, keep=10)
+
+
+@pytest.mark.parametrize("ev", ["auto", "recurrence"])
+@pytest.mark.parametrize("transform", ["block_dct8", "dct"])
+def test_given_threshold_matches_oracle(transform, ev):
+    """eq. (threshold_components) with eps given (the experiments of Table III fix
+    eps): the kernels take the FP32 eps as the threshold key and skip the selection.
+    eps sits midway in a gap of more than 2% of the sorted |Phi|, so the kernel's
+    FP32 and the oracle's FP64 keep the same entries."""
+    import torch
+    cpa = _lib()
+    m, n = 256, 128
+    if transform == "block_dct8":
+        X = synth.as_f32_exact(synth.block_smooth(m, n, rank=4, noise=1e-3, seed=9900))
+        T, frac = sparsify.block_dct(n, 8), 0.02
+    else:
+        X = synth.as_f32_exact(synth.smooth_lowrank(m, n, rank=4, freqs=6, noise=1e-3, seed=9901))
+        T, frac = sparsify.dct_matrix(n), 36.0 / (n * n)
+    Phi, _ = sparsify.transformed_gram(X, T)
+    keep = _gap_keep(Phi, frac)
+    a = np.sort(np.abs(Phi).ravel())[::-1]
+    eps = 0.5 * (a[keep - 1] + a[keep])
+    lam = 1.01 * float(np.linalg.eigvalsh(sparsify.truncate(Phi, eps))[-1])
+    s1 = math.sqrt(float(np.linalg.eigvalsh(X.T @ X)[-1]))
+    ref, _, nnz_o = sparsify.cpa_shrink_sparsified(X, Shrinkage(0, 0.2 * s1), lam, 20, T, None, eps=eps)
+    Y, info = cpa.shrink_dense_sparsified(torch.from_numpy(X.astype(np.float32)).cuda(), cpa.soft(0.2 * s1),
+                                          cpa.Opts(K=20, Lambda=lam, eval=ev), eps=eps, transform=transform,
+                                          info=True)
+    torch.cuda.synchronize()
+    err = metrics.rel_fro(Y.cpu().numpy().astype(np.float64), ref, X)
+    print(f"given eps {transform} {ev}: eps={eps:.6e} nnz={info['nnz']} (oracle {nnz_o}) rel_fro={err:.3e}",
+          flush=True)
+    assert info["nnz"] == nnz_o
+    assert info["eps"] == float(np.float32(eps))
+    assert err <= TOL32
+
+
+@pytest.mark.parametrize("ev", ["auto", "recurrence"])
+def test_given_threshold_above_every_entry_gives_zero(ev):
+    """An eps above every |Phi_ij| keeps nothing: Y = 0 exactly on both routes, with
+    a power bound and with a given one, and the kept count 0."""
+    import torch
+    cpa = _lib()
+    X = synth.as_f32_exact(synth.block_smooth(200, 96, rank=4, noise=1e-3, seed=9910))
+    Phi, _ = sparsify.transformed_gram(X, sparsify.block_dct(96, 8))
+    eps = 2.0 * float(np.abs(Phi).max())
+    Xd = torch.from_numpy(X.astype(np.float32)).cuda()
+    for opts in (cpa.Opts(K=16, eval=ev), cpa.Opts(K=16, Lambda=float(np.abs(Phi).max()), eval=ev)):
+        Y = torch.full_like(Xd, float("nan"))
+        _, info = cpa.shrink_dense_sparsified(Xd, cpa.soft(1.0), opts, eps=eps, out=Y, info=True)
+        torch.cuda.synchronize()
+        print(f"eps above every entry ({ev}): nnz {info['nnz']}, nonzeros in Y {int(torch.count_nonzero(Y))}",
+              flush=True)
+        assert info["nnz"] == 0
+        assert int(torch.count_nonzero(Y)) == 0
+
+
+def test_given_threshold_argument_errors():
+    import torch
+    cpa = _lib()
+    Xd = torch.ones(64, 32, device="cuda")
+    with pytest.raises(ValueError):
+        cpa.shrink_dense_sparsified(Xd, cpa.soft(1.0), cpa.Opts(K=8), keep=10, eps=1.0)
+    with pytest.raises(ValueError):
+        cpa.shrink_dense_sparsified(Xd, cpa.soft(1.0), cpa.Opts(K=8))
+    for bad in (-1.0, float("nan"), float("inf")):
+        with pytest.raises(cpa.CpaError) as e:
+            cpa.shrink_dense_sparsified(Xd, cpa.soft(1.0), cpa.Opts(K=8), eps=bad)
+        assert e.value.status == 1

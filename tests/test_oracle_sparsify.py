@@ -253,3 +253,33 @@ def test_scheduled_inpaint_uses_the_previous_change():
     want = [sparsify.keep_schedule(e, 64, 0.7, 0.3) for e in [0.3] + E[:-1]]
     assert keeps == want
     assert len(set(keeps)) >= 2
+
+
+def test_given_threshold():
+    """eq. (threshold_components) with eps given: eps = K(|Phi|, k) gives the keep-k
+    result; eps = 0 keeps every component (the T = Id shrinkage, an orthogonal
+    similarity); an eps above every |Phi_ij| keeps nothing (zero matrix, zero bound,
+    zero result)."""
+    from oracle.shrinkage import Shrinkage
+    rng = np.random.default_rng(4)
+    B = rng.standard_normal((40, 24)) @ np.diag(np.linspace(3.0, 0.2, 24))
+    T = sparsify.block_dct(24, 8)
+    Phi, _ = sparsify.transformed_gram(B, T)
+    sh = Shrinkage(0, 1.5)
+    for k in (5, 40, 200):
+        e = sparsify.kth_largest_abs(Phi, k)
+        Lam = 1.01 * float(np.linalg.eigvalsh(sparsify.truncate(Phi, e))[-1])
+        a = sparsify.cpa_shrink_sparsified(B, sh, Lam, 20, T, k)
+        b = sparsify.cpa_shrink_sparsified(B, sh, Lam, 20, T, None, eps=e)
+        assert np.array_equal(a[0], b[0]) and a[2] == b[2]
+    Lam = 1.01 * float(np.linalg.eigvalsh(Phi)[-1])
+    full, _, nnz = sparsify.cpa_shrink_sparsified(B, sh, Lam, 20, T, None, eps=0.0)
+    plain = cpa.cpa_shrink(B, sh, Lam, 20)
+    assert nnz == 24 * 24
+    assert np.linalg.norm(full - plain) <= 1e-10 * np.linalg.norm(plain)
+    top = float(np.abs(Phi).max())
+    Phil = sparsify.truncate(Phi, 2.0 * top)
+    assert not Phil.any()
+    for lam in (0.0, Lam):   # zero whatever the bound: h(0) = 0
+        zero, _, nnz = sparsify.cpa_shrink_sparsified(B, sh, lam, 20, T, None, eps=2.0 * top)
+        assert nnz == 0 and not zero.any()
