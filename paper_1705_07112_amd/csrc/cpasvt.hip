@@ -151,6 +151,25 @@ int gram_grid(int d) {
 
 // Power-iteration workgroups: about 16 rows each, at most 64 (the grid barrier
 // is one counter; few arrivals keep it cheap), never above what is co-resident.
+// The power kernels synchronise their workgroups with a bounded grid barrier.
+// With at most one workgroup per CU every workgroup runs, or starts as soon as a
+// CU frees up (the waiting ones hold at most `grid` CUs, and other work on the
+// device ends), so a plain launch reaches every barrier; the cooperative launch,
+// which leaves the device idle around it in a captured graph, is kept for larger
+// grids.
+cpa_status launch_power(cpa_ctx* ctx, const void* fn, int grid, void** args, hipStream_t st) {
+    if (ctx->cus == 0) {
+        int cus = 0;
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        ctx->cus = std::max(1, cus);
+    }
+    if (grid <= ctx->cus)
+        HIP_TRY(hipLaunchKernel(fn, dim3(grid), dim3(kPowerThreads), args, 0, st));
+    else
+        HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(kPowerThreads), args, 0, st));
+    return CPA_OK;
+}
+
 int power_grid(cpa_ctx* ctx, int d) {
     int want = std::max(1, std::min(64, (d + 15) / 16));
     if (ctx->coop_max > 0) want = std::min(want, ctx->coop_max);
@@ -421,15 +440,15 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
         unsigned* counter = reinterpret_cast<unsigned*>(w.scal + SC_BARRIER);
         double* scal = w.scal;
         double tol = o->power_tol;
+        cpa_status ls;
         if (G64) {
             void* args[] = {&d_, &G64, &ldg, &wb0, &wb1, &part, &counter, &scal, &maxit_, &tol, &pw_mu, &pw_w2};
-            HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(power_coop_kernel<double>),
-                                               dim3(w.lay.pwg), dim3(kPowerThreads), args, 0, st));
+            ls = launch_power(ctx, reinterpret_cast<const void*>(power_coop_kernel<double>), w.lay.pwg, args, st);
         } else {
             void* args[] = {&d_, &G, &ldg, &wb0, &wb1, &part, &counter, &scal, &maxit_, &tol, &pw_mu, &pw_w2};
-            HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(power_coop_kernel<float>),
-                                               dim3(w.lay.pwg), dim3(kPowerThreads), args, 0, st));
+            ls = launch_power(ctx, reinterpret_cast<const void*>(power_coop_kernel<float>), w.lay.pwg, args, st);
         }
+        if (ls != CPA_OK) return ls;
     }
     hipLaunchKernelGGL(finish_bound_kernel, dim3(1), dim3(256), 0, st, mode, o->Lambda, d, o->power_iters, o->margin,
                        (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? ctx->warm : nullptr, w.scal,
@@ -892,8 +911,8 @@ cpa_status shrink_csr_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t n
         double tol = o->power_tol;
         void* args[] = {&m_, &n_, &rowptr, &colidx, &val, &colptr, &crow, &csrc, &tvec, &wb0, &wb1,
                         &part, &counter, &scal, &maxit_, &tol, &pw_mu, &pw_w2};
-        HIP_TRY(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(power_op_kernel), dim3(w.lay.pwg),
-                                           dim3(kPowerThreads), args, 0, st));
+        const cpa_status ls = launch_power(ctx, reinterpret_cast<const void*>(power_op_kernel), w.lay.pwg, args, st);
+        if (ls != CPA_OK) return ls;
     }
     hipLaunchKernelGGL(finish_bound_kernel, dim3(1), dim3(256), 0, st, mode, o->Lambda, n, o->power_iters, o->margin,
                        (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? ctx->warm : nullptr, w.scal,

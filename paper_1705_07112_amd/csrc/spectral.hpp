@@ -110,10 +110,11 @@ __global__ void power_init_kernel(int d, uint64_t seed, const double* warm, doub
 
 constexpr int kPowerThreads = 512;
 
-// Grid barrier for a cooperative launch: a monotonically increasing arrival
-// counter (zeroed before the launch); barrier number b completes when the
-// counter reaches b * gridDim.x.  The wait is bounded: on time-out the
-// workgroup records SC_TIMEOUT and reports failure, so every wave exits.
+// Grid barrier: a monotonically increasing arrival counter (zeroed before the
+// launch); barrier number b completes when the counter reaches b * gridDim.x.
+// Every workgroup of the grid must become resident (a cooperative launch, or at
+// most one workgroup per CU).  The wait is bounded: on time-out the workgroup
+// records SC_TIMEOUT and reports failure, so every wave exits.
 __device__ inline bool grid_barrier(unsigned* counter, unsigned target, double* scal) {
     __shared__ int ok;
     __syncthreads();
