@@ -103,3 +103,37 @@ def test_rpca_one_call_stops_at_tolerance():
     # max_iters caps the run
     _, _, E2, t2 = cpa.rpca_admm(Id, 1.0, 1.0 / np.sqrt(96), 3, 0.0, opts)
     assert t2 == 3 and len(E2) == 3
+
+
+def test_graph_replays_equal_direct_launches():
+    """The ADMM iteration replayed from its captured graph equals the same
+    iterations launched directly, bit for bit: runs of 5, 4 and 2 replays with
+    synchronisations and eager work between them, each run's E_t and the state
+    compared (cold power starts, so neither run depends on the other)."""
+    import torch
+    import paper_1705_07112_amd as cpa
+    I, _, _ = synth.rpca_frames(128, 96, rank=12, outlier_frac=0.05, seed=41)
+    Id = torch.from_numpy(I).cuda()
+    opts = cpa.Opts(K=20, warm_start=False, power_iters=100)
+    chunks = (5, 4, 2)
+    direct = cpa.RpcaAdmm(Id, 1.0, 1.0 / np.sqrt(128), opts)
+    Ed = torch.zeros(sum(chunks), dtype=torch.float64, device="cuda")
+    cpa.timing_enable(True)      # per-launch timing forces direct launches
+    try:
+        direct.iterate(sum(chunks), Ed)
+        torch.cuda.synchronize()
+    finally:
+        cpa.timing_enable(False)
+    graphed = cpa.RpcaAdmm(Id, 1.0, 1.0 / np.sqrt(128), opts)
+    Eg = torch.zeros(sum(chunks), dtype=torch.float64, device="cuda")
+    o = 0
+    for c in chunks:
+        graphed.iterate(c, Eg[o:o + c])
+        torch.cuda.synchronize()
+        _ = float((graphed.L * 2.0).sum())   # eager work between the replays
+        o += c
+    torch.cuda.synchronize()
+    print(f"graph vs direct: E_t equal {torch.equal(Ed, Eg)}, state equal {torch.equal(direct.state, graphed.state)}",
+          flush=True)
+    assert torch.equal(Ed, Eg)
+    assert torch.equal(direct.state, graphed.state)
