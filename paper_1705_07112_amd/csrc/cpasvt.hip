@@ -149,8 +149,6 @@ int gram_grid(int d) {
     return ((d + 63) / 64) * ((d + 63) / 64);
 }
 
-// Power-iteration workgroups: about 16 rows each, at most 64 (the grid barrier
-// is one counter; few arrivals keep it cheap), never above what is co-resident.
 // The power kernels synchronise their workgroups with a bounded grid barrier.
 // With at most one workgroup per CU every workgroup runs, or starts as soon as a
 // CU frees up (the waiting ones hold at most `grid` CUs, and other work on the
@@ -170,6 +168,8 @@ cpa_status launch_power(cpa_ctx* ctx, const void* fn, int grid, void** args, hip
     return CPA_OK;
 }
 
+// Power-iteration workgroups: about 16 rows each, at most 64 (the grid barrier
+// is one counter; few arrivals keep it cheap), never above what is co-resident.
 int power_grid(cpa_ctx* ctx, int d) {
     int want = std::max(1, std::min(64, (d + 15) / 16));
     if (ctx->coop_max > 0) want = std::min(want, ctx->coop_max);
