@@ -24,7 +24,7 @@
 // are combined in a fixed order (xor shuffles), so results do not depend on
 // scheduling.
 //   power_op_kernel  power iteration on S^T S through two sparse products per step,
-//                    one cooperative launch (two grid barriers per product); the
+//                    one launch of resident workgroups (two grid barriers per product); the
 //                    vectors and partial sums go through agent-scope atomic
 //                    accesses, so the barriers flush no cache and the pattern
 //                    stays in L2 from one product to the next.

@@ -3,8 +3,8 @@
 // rule, and the FP64 Chebyshev coefficients (Sec. III-A,
 // eq. chebychev_coeff_shifted) computed on the device from that bound.
 //
-// Power iteration runs in one cooperative launch (all workgroups co-resident,
-// which the cooperative launch guarantees) with a grid barrier per product:
+// Power iteration runs in one launch whose workgroups are all resident (at most
+// one per CU, or a cooperative launch) with a grid barrier per product:
 //   w_0 = v_0 (SplitMix64 start vector or the warm-start vector)
 //   product t: v_t = w_{t-1} / ||w_{t-1}||, w_t = G v_t,
 //              mu_t = v_t . w_t and ||w_t||^2 in FP64: each workgroup stores its
@@ -175,7 +175,7 @@ __device__ inline double ordered_sum(const double* part, int n, double* red) {
     return block_sum(a, red);
 }
 
-// All products of the power iteration in one cooperative launch (see top).
+// All products of the power iteration in one launch (see top).
 // The iterate and the partial sums written during the launch are exchanged
 // through agent-scope atomic stores and loads (grid_barrier_coherent); each
 // workgroup copies w_{t-1} into LDS once per product (d <= kPowerVecLds; above
