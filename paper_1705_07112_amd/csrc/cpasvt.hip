@@ -422,6 +422,10 @@ cpa_status enqueue_gram_impl(hipStream_t st, int m, int n, const float* X, int64
 }
 
 // G64 != nullptr: the power iteration reads that FP64 Gram (pitch d) instead of w.G.
+// A Work that carries the matrix-polynomial route gets its coefficients rewritten
+// for that route by the bound's finish kernel (enqueue_poly_core then skips it).
+bool poly_fused(const Work& w, int K) { return w.poly_s > 0 && K >= 2; }
+
 cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkage* sh, const cpa_opts* o,
                          const Work& w, int mode_override, const double* G64 = nullptr) {
     int mode = o->bound == CPA_BOUND_POWER ? 0 : (o->bound == CPA_BOUND_GIVEN ? 1 : 2);
@@ -453,7 +457,7 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
     hipLaunchKernelGGL(finish_bound_kernel, dim3(1), dim3(256), 0, st, mode, o->Lambda, d, o->power_iters, o->margin,
                        (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? ctx->warm : nullptr, w.scal,
                        to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)(w.scal + w.lay.gpart()),
-                       w.lay.gwg, 0, o->damping);
+                       w.lay.gwg, 0, o->damping, w.poly_s, poly_fused(w, o->K) ? w.lay.ps() : -1);
     HIP_TRY(hipGetLastError());
     if (mode == 0) ctx->warm_d = d;
     return CPA_OK;
@@ -590,15 +594,17 @@ EpiLin lin_epi(float* D, int64_t ldd, const float* Mx, int64_t ldm, float alpha,
 // The polynomial p(Ghat) (d x d, pitch d) from the Gram G (pitch ldg) and the
 // coefficients in scal; `poly` holds poly_mats(K, s) matrices of d x d.  Returns p's buffer.
 cpa_status enqueue_poly_core(cpa_ctx* ctx, hipStream_t st, int d, const float* G, int64_t ldg, double* scal,
-                             int roff, float* poly, int s, int K, int precision, float** F_out) {
+                             int roff, float* poly, int s, int K, int precision, float** F_out, bool coeff_ready) {
     const int J = (K + s - 1) / s;
     const int64_t dd = (int64_t)d * d;
     float* T1 = poly;                         // T_q at T1 + (q - 1) dd, q = 1..s
     float* R = poly + (int64_t)s * dd;        // R_j at R + j dd
     float* Bf[3] = {R + (int64_t)J * dd, R + (int64_t)(J + 1) * dd, R + (int64_t)(J + 2) * dd};
     const int ge = (int)std::min<int64_t>(4096, (dd + 255) / 256);
-    hipLaunchKernelGGL(ps_coeff_kernel, dim3(1), dim3(256), 0, st, K, s, J, scal, roff);
-    HIP_TRY(hipGetLastError());
+    if (!coeff_ready) {
+        hipLaunchKernelGGL(ps_coeff_kernel, dim3(1), dim3(256), 0, st, K, s, J, scal, roff);
+        HIP_TRY(hipGetLastError());
+    }
     hipLaunchKernelGGL(ps_shift_kernel, dim3(ge), dim3(256), 0, st, d, G, ldg, T1, (const double*)scal);
     HIP_TRY(hipGetLastError());
     cpa_status r;
@@ -648,7 +654,9 @@ cpa_status enqueue_poly(cpa_ctx* ctx, hipStream_t st, int m, int n, const float*
                         int64_t ldy, int K, const Work& w, int precision) {
     const int d = w.d;
     float* F = nullptr;
-    cpa_status r = enqueue_poly_core(ctx, st, d, w.G, d, w.scal, w.lay.ps(), w.poly, w.poly_s, K, precision, &F);
+    // enqueue_bound on this Work rewrote the coefficients already
+    cpa_status r = enqueue_poly_core(ctx, st, d, w.G, d, w.scal, w.lay.ps(), w.poly, w.poly_s, K, precision, &F,
+                                     poly_fused(w, K));
     if (r != CPA_OK) return r;
     // Y = X p (right) or p X (left); p read transposed (it is the fixed operand)
     const EpiLin e = lin_epi(Y, ldy, nullptr, 0, 1.f, 0.f, 0.f, 0.f);
@@ -916,7 +924,7 @@ cpa_status shrink_csr_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t n
     }
     hipLaunchKernelGGL(finish_bound_kernel, dim3(1), dim3(256), 0, st, mode, o->Lambda, n, o->power_iters, o->margin,
                        (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? ctx->warm : nullptr, w.scal,
-                       to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)gpart, kSqGrid, 1, o->damping);
+                       to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)gpart, kSqGrid, 1, o->damping, 0, -1);
     HIP_TRY(hipGetLastError());
     if (mode == 0) ctx->warm_d = n;
     // Y_0 = S densified
@@ -947,7 +955,7 @@ cpa_status shrink_csr_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t n
         HIP_TRY(hipGetLastError());
         float* F = nullptr;
         cpa_status r = enqueue_poly_core(ctx, st, n, w.W, w.ld, w.scal, w.lay.ps(), w.poly, w.poly_s, o->K,
-                                         CPA_PREC_FP32, &F);
+                                         CPA_PREC_FP32, &F, false);
         if (r != CPA_OK) return r;
         hipLaunchKernelGGL(spmm_out_kernel, dim3(((m + SP_WAVES - 1) / SP_WAVES) * ((n + SPC_J - 1) / SPC_J)),
                            dim3(SP_THREADS), 0, st, m, n, rowptr, colidx, val, (const float*)F, (int64_t)n, Y, ldy,
@@ -2265,7 +2273,7 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
         if ((s = enqueue_bound(ctx, st, nb, shrink, opts, wc, -1)) != CPA_OK) return s;
         float* F = nullptr;
         if ((s = enqueue_poly_core(ctx, st, nb, w.G, nb, w.scal, wc.lay.ps(), w.poly, ps, opts->K, CPA_PREC_FP32,
-                                   &F)) != CPA_OK)
+                                   &F, poly_fused(wc, opts->K))) != CPA_OK)
             return s;
         // M = T^T hat H T (hat h(0) on the empty diagonal), then Y = X M (right) or M X (left)
         if ((s = inverse(F, nb)) != CPA_OK) return s;

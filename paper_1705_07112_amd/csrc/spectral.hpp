@@ -300,10 +300,14 @@ constexpr int kCoefLds = 64;   // orders up to this use the parallel coefficient
 //   mode 1: Lambda given
 //   mode 2: Lambda = ||G||_F (tr G when cap_trace)
 // For mode 0 the warm-start buffer receives v_T (the unit vector of the last product).
+__device__ inline void ps_coeff_block(int K, int s, int J, double* scal, int out);
+
+// ps_out >= 0: the coefficients are also rewritten for the matrix-polynomial route
+// with baby steps of ps_s (ps_coeff_block), saving that route a launch.
 __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int maxit, double margin,
                                     const double* wbuf0, const double* wbuf1, double* warm_out, double* scal,
                                     ShrinkParams sp, int K, int pw_mu, int pw_w2, const double* gpart, int gwg,
-                                    int cap_trace, int damping) {
+                                    int cap_trace, int damping, int ps_s, int ps_out) {
     __shared__ double sLambda;
     __shared__ int sT;
     __shared__ double red[16];
@@ -383,6 +387,10 @@ __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int ma
         const double inv = 1.0 / sqrt(scal[pw_w2 + sT - 1]);
         for (int i = threadIdx.x; i < d; i += blockDim.x) warm_out[i] = src[i] * inv;
     }
+    if (ps_out >= 0) {
+        __syncthreads();   // every c_k stored
+        ps_coeff_block(K, ps_s, (K + ps_s - 1) / ps_s, scal, ps_out);
+    }
 }
 
 // K == 1: Y = c_0/2 X.
@@ -402,7 +410,7 @@ __global__ void scale_copy_kernel(int m, int n, const float* X, int64_t ldx, flo
 // using T_j(T_s(x)) = T_{js}(x) and T_i T_{js} = (T_{js+i} + T_{js-i}) / 2: from
 // the highest degree down, r_{j,i} = 2 w_{js+i} and w_{js-i} -= w_{js+i} (i >= 1),
 // r_{j,0} = w_{js}, r_{0,i} = w_i.  One thread, FP64; r is written row by row.
-__global__ void ps_coeff_kernel(int K, int s, int J, double* scal, int out) {
+__device__ inline void ps_coeff_block(int K, int s, int J, double* scal, int out) {
     __shared__ double w[kPsMaxS * kPsMaxS + kPsMaxS];
     const int n = J * s;   // <= K + s - 1 <= 271
     for (int k = threadIdx.x; k < n; k += blockDim.x)
@@ -422,6 +430,8 @@ __global__ void ps_coeff_kernel(int K, int s, int J, double* scal, int out) {
     __syncthreads();
     for (int k = threadIdx.x; k < n; k += blockDim.x) scal[out + k] = w[k];
 }
+
+__global__ void ps_coeff_kernel(int K, int s, int J, double* scal, int out) { ps_coeff_block(K, s, J, scal, out); }
 
 // T1 = (2 / Lambda) G - I, d x d (G with pitch ldg, T1 with pitch d).
 __global__ void ps_shift_kernel(int d, const float* G, int64_t ldg, float* T1, const double* scal) {
