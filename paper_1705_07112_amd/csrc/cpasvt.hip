@@ -74,6 +74,8 @@ struct cpa_ctx {
     int coop_max = 0;          // co-resident power-iteration workgroups (0: not queried)
     void* spf = nullptr;       // sparsified path: Phi, CSR of the truncated matrix, Psi buffers, H, M, selection state
     size_t spf_bytes = 0;
+    int spf_dct_d = 0;         // the full-DCT matrices in spf are built for this side (0: none)
+    int spf_last_d = 0;        // the side of the last sparsified call (the layout depends on it)
     void* inp = nullptr;       // inpainting driver: DCT matrices, product scratch, partial sums
     size_t inp_bytes = 0;
     void* f64 = nullptr;       // FP64 shrink: Gram, two Y buffers, product buffer
@@ -2058,7 +2060,11 @@ cpa_status ensure_spf(cpa_ctx* ctx, int d, bool dense_t, SpfWork& s) {
         oDm = off; off = align_up(off + sizeof(float) * dd);
         oDt = off; off = align_up(off + sizeof(float) * dd);
     }
+    // another side moves every buffer: the DCT matrices must be rebuilt
+    if (d != ctx->spf_last_d) ctx->spf_dct_d = 0;
+    ctx->spf_last_d = d;
     if (off > ctx->spf_bytes) {
+        ctx->spf_dct_d = 0;
         if (ctx->spf) {
             HIP_TRY(hipDeviceSynchronize());
             HIP_TRY(hipFree(ctx->spf));
@@ -2150,8 +2156,11 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
         // full DCT: C = D G, Phi = C D^T (FP32 products), then (Phi + Phi^T)/2
         const EpiLin ec = lin_epi(f.P[0], d, nullptr, 0, 1.f, 0.f, 0.f, 0.f);
         const EpiLin ep = lin_epi(f.Phi, d, nullptr, 0, 1.f, 0.f, 0.f, 0.f);
-        hipLaunchKernelGGL(dct_fill_kernel, dim3(gd), dim3(256), 0, st, d, f.Dm, f.Dt);
-        HIP_TRY(hipGetLastError());
+        if (ctx->spf_dct_d != d) {
+            hipLaunchKernelGGL(dct_fill_kernel, dim3(gd), dim3(256), 0, st, d, f.Dm, f.Dt);
+            HIP_TRY(hipGetLastError());
+            ctx->spf_dct_d = d;
+        }
         if ((s = poly_gemm(ctx, st, make_op(f.Dt, d, d), make_op(w.G, d, d), d, d, d, ec, CPA_PREC_FP32, false)) !=
             CPA_OK)
             return s;
