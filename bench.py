@@ -549,7 +549,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
-              "(the multi-GPU layout is described in DESIGN.md)", file=sys.stderr)
+              "(a row-sharded X would need one all-reduce of the d x d Gram partials per shrink; "
+              "that path is not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
