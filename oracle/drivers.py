@@ -47,9 +47,18 @@ the sparsified shrink of oracle.sparsify with K(|Phi|, k) and k from the previou
 iteration's E_t by eq. (recommendation_epsilon) (oracle.sparsify.keep_schedule).
 
 Pins: (K^T K)^{-1} K^T checked by substitution; l1 prox against its closed
-form; E_t falls on a low-rank-plus-sparse input.  Parity: pinned for the
-closed-form pieces; the ADMM hyper-parameters are project choices (parity
-does not depend on them, both sides take the same values).
+form; with the exact nuclear-norm prox in place of the CPA shrink the RPCA
+iteration reaches a point meeting principal component pursuit's optimality
+conditions (L + S = I, u1 = u2 = -u3, rho u1 and rho u2 subgradients of the
+two norms) and recovers the planted parts of an exactly recoverable input, and
+with the CPA shrink at a high order it recovers them to that order's accuracy;
+SVT: k0 against inputs whose ||P_Omega M||_2 is known in closed form and the
+defining inequality (k0 - 1) delta ||P_Omega M||_2 < tau <= k0 delta ||P_Omega M||_2,
+recovery of an exactly recoverable rank-2 matrix (to rounding with the exact
+prox, to the order's accuracy with CPA).  Planted slips (z1 from l, u3 without
+-I, l and s swapped, the l1 threshold, k0 rounded down, the step's sign) each
+fail a pin.  Parity: pinned; the ADMM hyper-parameters are project choices
+(parity does not depend on them, both sides take the same values).
 """
 from __future__ import annotations
 

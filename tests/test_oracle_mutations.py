@@ -177,3 +177,131 @@ mlp_orig_pinball = mlp_mod.pinball
 def test_mlp_planted_mistake_is_caught(name, fn, monkeypatch):
     monkeypatch.setattr(mlp_mod, name, fn)
     assert _mlp_pin_fails()
+
+
+# ---- drivers (Appendix B ADMM, SVT): slips in the iteration's algebra --------
+
+import tests.test_oracle_drivers as drv_pins
+from oracle import drivers as drv_mod
+from oracle import bound as bound_mod
+from oracle.shrinkage import soft as _soft
+
+_rpca_step_orig = drv_mod.rpca_step
+_svt_orig = drv_mod.svt_complete
+
+
+def _rpca_pins_fail(monkeypatch):
+    for f in (drv_pins.test_rpca_exact_prox_meets_pcp_optimality, drv_pins.test_rpca_cpa_recovers_planted_parts):
+        try:
+            with monkeypatch.context() as mp:
+                f(mp) if f is drv_pins.test_rpca_exact_prox_meets_pcp_optimality else f()
+        except (AssertionError, FloatingPointError, np.linalg.LinAlgError, ValueError):
+            return True
+    return False
+
+
+def _rpca_step_variant(z1_from_l=False, u3_keeps_I=False, swap_ls=False, z2_tau_from_rho=False):
+    def step(state, I, inv_rho, eta_over_rho, K, v=None, seed=0, power_iters=100, tol_power=1e-7, delta=0.01):
+        I = np.asarray(I, dtype=np.float64)
+        l_new, s_new = drv_mod.admm_lsolve(state["z1"], state["z2"], I, state["u1"], state["u2"], state["u3"])
+        if swap_ls:
+            l_new, s_new = s_new, l_new
+        x = l_new if z1_from_l else l_new + state["u1"]
+        Phi, _ = cpa.gram(x)
+        Lam, _, _, _, v = bound_mod.power_bound(Phi, seed=seed, max_iter=power_iters, tol=tol_power,
+                                                delta=delta, v0=v)
+        z1 = cpa.cpa_shrink(x, _soft(inv_rho), Lam, K)
+        z2 = drv_mod.soft_elementwise(s_new + state["u2"], inv_rho if z2_tau_from_rho else eta_over_rho)
+        new = {"l": l_new, "s": s_new, "z1": z1, "z2": z2,
+               "u1": state["u1"] + l_new - z1, "u2": state["u2"] + s_new - z2,
+               "u3": state["u3"] + l_new + s_new - (0.0 if u3_keeps_I else I)}
+        num = math.sqrt(float(np.sum((l_new - state["l"]) ** 2)))
+        den = math.sqrt(float(np.sum(l_new ** 2)))
+        return new, {"x": x, "Lambda": Lam, "v": v, "E": (num / den if den > 0 else 0.0)}
+    return step
+
+
+RPCA_MUTATIONS = [
+    ("z1 shrinks l instead of l + u1", dict(z1_from_l=True)),
+    ("u3 update without -I", dict(u3_keeps_I=True)),
+    ("l and s swapped in the least-squares step", dict(swap_ls=True)),
+    ("l1 prox threshold 1/rho instead of eta/rho", dict(z2_tau_from_rho=True)),
+]
+
+
+@pytest.mark.parametrize("name,kw", RPCA_MUTATIONS, ids=[m[0] for m in RPCA_MUTATIONS])
+def test_rpca_planted_mistake_is_caught(monkeypatch, name, kw):
+    assert not _rpca_pins_fail(monkeypatch), "pins must pass on the unmodified oracle"
+    with np.errstate(all="ignore"):
+        monkeypatch.setattr(drv_mod, "rpca_step", _rpca_step_variant(**kw))
+        assert _rpca_pins_fail(monkeypatch), f"planted mistake not detected: {name}"
+
+
+def _svt_variant(k0_floor=False, step_sign=1.0):
+    def svt(m, n, rows, cols, vals, tau, step, iters, K, seed=0, power_iters=100, tol_power=1e-7,
+            delta_bound=0.01):
+        vals = np.asarray(vals, dtype=np.float64)
+        P = np.zeros((m, n))
+        P[rows, cols] = vals
+        G0 = P.T @ P if m >= n else P @ P.T
+        _, mu0, _, _, v = bound_mod.power_bound(G0, seed=seed, max_iter=200, tol=1e-9, delta=delta_bound,
+                                                cap=float(np.trace(G0)))
+        nrm2 = math.sqrt(max(mu0, 0.0))
+        q = tau / (step * nrm2) if nrm2 > 0 else 1.0
+        k0 = max(math.floor(q), 1) if k0_floor else math.ceil(q)
+        Y = np.zeros((m, n))
+        Y[rows, cols] = k0 * step * vals
+        X = np.zeros((m, n))
+        res = []
+        nrm = math.sqrt(float(vals @ vals))
+        for _ in range(iters):
+            Phi, _ = cpa.gram(Y)
+            Lam, _, _, _, v = bound_mod.power_bound(Phi, seed=seed, max_iter=power_iters, tol=tol_power,
+                                                    delta=delta_bound, v0=v, cap=float(np.trace(Phi)))
+            X = cpa.cpa_shrink(Y, _soft(tau), Lam, K)
+            r = vals - X[rows, cols]
+            Y[rows, cols] += step_sign * step * r
+            res.append(math.sqrt(float(r @ r)) / nrm)
+        return X, res, k0
+    return svt
+
+
+def _svt_pins_fail(monkeypatch):
+    for f in (drv_pins.test_svt_k0_closed_form, drv_pins.test_svt_k0_defining_inequality,
+              drv_pins.test_svt_exact_prox_recovers, drv_pins.test_svt_cpa_recovers):
+        try:
+            with monkeypatch.context() as mp:
+                f(mp) if f is drv_pins.test_svt_exact_prox_recovers else f()
+        except (AssertionError, FloatingPointError, np.linalg.LinAlgError, ValueError, OverflowError):
+            return True
+    return False
+
+
+SVT_MUTATIONS = [
+    ("k0 rounded down", dict(k0_floor=True)),
+    ("step sign flipped", dict(step_sign=-1.0)),
+]
+
+
+@pytest.mark.parametrize("name,kw", SVT_MUTATIONS, ids=[m[0] for m in SVT_MUTATIONS])
+def test_svt_planted_mistake_is_caught(monkeypatch, name, kw):
+    # the unmodified SVT oracle passes its pins (one run here; the pins file runs them too)
+    monkeypatch.setattr(drv_mod, "svt_complete", _svt_variant())
+    assert not _svt_pins_fail(monkeypatch), "the restated SVT must pass the pins"
+    with np.errstate(all="ignore"):
+        monkeypatch.setattr(drv_mod, "svt_complete", _svt_variant(**kw))
+        assert _svt_pins_fail(monkeypatch), f"planted mistake not detected: {name}"
+
+
+def test_restated_drivers_equal_the_oracle():
+    """The unmutated restatements above compute exactly what the oracle does, so a
+    caught mutation is a mistake the pins would catch in the oracle itself."""
+    I, _, _ = drv_pins._rpca_instance()
+    st = drv_mod.rpca_start(I)
+    a, ia = _rpca_step_orig(st, I, 1.0, 0.125, 20)
+    b, ib = _rpca_step_variant()(st, I, 1.0, 0.125, 20)
+    assert all(np.array_equal(a[k], b[k]) for k in a) and ia["E"] == ib["E"]
+    m, n, M, rows, cols, tau, step = drv_pins._svt_instance()
+    Xa, ra, ka = _svt_orig(m, n, rows, cols, M[rows, cols], tau, step, 5, 25)
+    Xb, rb, kb = _svt_variant()(m, n, rows, cols, M[rows, cols], tau, step, 5, 25)
+    assert np.array_equal(Xa, Xb) and ra == rb and ka == kb
