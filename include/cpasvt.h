@@ -161,7 +161,9 @@ typedef struct {
 
 typedef struct cpa_ctx cpa_ctx;
 
-/* Context bound to one HIP device.  Allocates no device memory until first use. */
+/* Context bound to one HIP device.  Allocates no device memory until first use
+ * (the first context on a device looks up that device's address of the static
+ * scratch array of cpa_shrink_dense_noalloc, which loads the library's code on it). */
 cpa_status cpa_create(cpa_ctx** ctx_out, int device);
 cpa_status cpa_destroy(cpa_ctx* ctx);
 
@@ -209,6 +211,30 @@ cpa_status cpa_shrink_dense(cpa_ctx* ctx, void* stream, int m, int n,
                             const float* X_dev, int64_t ldx, float* Y_dev, int64_t ldy,
                             const cpa_shrinkage* shrink, const cpa_opts* opts,
                             cpa_info* info_host);
+
+/* For callers that cannot allocate device memory (work recorded under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the shrinkage
+ * of cpa_shrink_dense with the same kernels, arguments, options, results, errors
+ * and synchronisation, but its workspace (Gram, power vectors, scalar block,
+ * matrix-polynomial or Y ping-pong buffers, warm-start vector) lives in a static
+ * 64 MiB device array that each GPU holds from its first cpa_create until the
+ * process ends.  The call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine; info is read through a fixed host buffer; per-launch timing is
+ * skipped).  Limits: Gram side d = min(m, n) (or the side opts->side picks) at
+ * most 4096, and the workspace for (m, n, K) at most 64 MiB - 32 KiB: d^2 floats
+ * for the Gram plus, on the matrix-polynomial route, (s + ceil(K/s) + 3) d^2 floats
+ * (s = ceil(sqrt K)), or on the recurrence route 2 m n floats; e.g. 1024 x 1024 at
+ * K = 30 (61 MB) fits, at K = 64 it does not.  Larger requests return
+ * CPA_ERR_SHAPE before anything is enqueued.  Every call on a GPU shares that
+ * GPU's array, whose contents persist between calls (the scalar block is cleared
+ * by a fill kernel at the start of each call; everything else is written before
+ * it is read): calls that overlap on one GPU, from any stream, thread or context,
+ * race and give wrong results.  With opts->warm_start the power iteration starts
+ * from the vector the previous call on that GPU left, when its length matches. */
+cpa_status cpa_shrink_dense_noalloc(cpa_ctx* ctx, void* stream, int m, int n,
+                                    const float* X_dev, int64_t ldx, float* Y_dev, int64_t ldy,
+                                    const cpa_shrinkage* shrink, const cpa_opts* opts,
+                                    cpa_info* info_host);
 
 /* The same shrinkage with FP64 input, output and arithmetic (Algorithm 1, with
  * the recurrence of eq. recurrence_our_method distributed over X as in the FP32

@@ -28,6 +28,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "cpasvt.h")
 SOFT, HARD, WEIGHTED_CONST, WEIGHTED_FN = 0, 1, 2, 3
 BOUND_POWER, BOUND_GIVEN, BOUND_FROBENIUS = 0, 1, 2
 PREC_FP32, PREC_BF16X3, PREC_FP64 = 0, 1, 2
+OK, ERR_ARG, ERR_SHAPE, ERR_ALLOC, ERR_HIP, ERR_NONFINITE, ERR_BOUND, ERR_UNSUPPORTED, ERR_IO = range(9)
 
 
 class CpaShrinkage(ctypes.Structure):
@@ -95,6 +96,9 @@ _SIGS = {
     "cpa_shrink_dense": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _I64, _P, _I64,
                                         ctypes.POINTER(CpaShrinkage), ctypes.POINTER(CpaOpts),
                                         ctypes.POINTER(CpaInfo)]),
+    "cpa_shrink_dense_noalloc": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _I64, _P, _I64,
+                                                ctypes.POINTER(CpaShrinkage), ctypes.POINTER(CpaOpts),
+                                                ctypes.POINTER(CpaInfo)]),
     "cpa_shrink_dense_f64": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _I64, _P, _I64,
                                         ctypes.POINTER(CpaShrinkage), ctypes.POINTER(CpaOpts),
                                         ctypes.POINTER(CpaInfo)]),
@@ -314,6 +318,21 @@ def shrink_dense(X, shrink: CpaShrinkage, opts: Opts, out=None, info: bool = Fal
     _check(fn(ctypes.c_void_p(context(X.device.index or 0)), _stream(X), m, n, ctypes.c_void_p(X.data_ptr()), ldx,
               ctypes.c_void_p(out.data_ptr()), ldy, ctypes.byref(shrink), ctypes.byref(co),
               ctypes.byref(ci) if info else None))
+    return (out, ci.as_dict()) if info else out
+
+
+def shrink_dense_noalloc(X, shrink: CpaShrinkage, opts: Opts, out, info: bool = False):
+    """cpa_shrink_dense_noalloc: the FP32 shrink with its workspace in the library's
+    static scratch (the caller passes the output).  Returns out, or (out, info dict)."""
+    m, n, ldx = _mat(X, "X")
+    _, _, ldy = _mat(out, "out")
+    if tuple(out.shape) != (m, n) or out.device != X.device:
+        raise ValueError("out has the wrong shape or device")
+    ci = CpaInfo()
+    co = opts.to_c()
+    _check(lib().cpa_shrink_dense_noalloc(ctypes.c_void_p(context(X.device.index or 0)), _stream(X), m, n,
+                                          ctypes.c_void_p(X.data_ptr()), ldx, ctypes.c_void_p(out.data_ptr()), ldy,
+                                          ctypes.byref(shrink), ctypes.byref(co), ctypes.byref(ci) if info else None))
     return (out, ci.as_dict()) if info else out
 
 

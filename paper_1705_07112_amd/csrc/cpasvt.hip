@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -62,8 +63,28 @@ struct TimingLog {
     size_t used = 0;              // pairs recorded since the last reset
 };
 
+// ---- scratch of the allocation-free dense shrink ---------------------------------
+// The workspace of cpa_shrink_dense_noalloc lives in this array.  Every GPU that
+// loads the library holds its own copy until the process ends.  In host code the
+// name only identifies the symbol: kernels receive the device address that
+// hipGetSymbolAddress returned for that device (kept per device at cpa_create),
+// never the name.  Layout: the power iteration's warm-start vector at offset 0
+// (kScratchWarmBytes, for d <= kScratchMaxD), then the shrink's workspace.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kScratchMaxD = 4096;
+constexpr size_t kScratchWarmBytes = sizeof(double) * kScratchMaxD;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];      // device address of `scratch` on each device (nullptr: not yet)
+int g_scratch_warm_d[kMaxDevices];     // length of the warm vector stored there (-1: none)
+}  // namespace
+
 struct cpa_ctx {
     int device = 0;
+    void* scratch = nullptr;   // this device's address of the allocation-free entry point's scratch
     int timing = 0;               // 1: bracket launches with events
     TimingLog tlog[2];            // 0: recurrence GEMMs, 1: Gram GEMMs
     void* ws = nullptr;        // main workspace
@@ -134,6 +155,10 @@ struct Work {
     bool right;       // Gram = X^T X (n x n) and products on the right; else X X^T (m x m), on the left
     int d;            // side of the Gram
     ScalarLayout lay;
+    // warm-start vector of the power iteration and the length of what it holds
+    // (-1: nothing); nullptr: the context's
+    double* warm_vec = nullptr;
+    int* warm_len = nullptr;
 };
 
 // The Gram side: CPA_SIDE_AUTO takes the smaller one (X^T X when m >= n).
@@ -178,38 +203,78 @@ int power_grid(cpa_ctx* ctx, int d) {
     return want;
 }
 
-// size_only != nullptr: report the bytes of the main workspace and the power
-// vector this call needs and allocate nothing.
-cpa_status ensure_ws(cpa_ctx* ctx, int m, int n, int K, int maxit, bool admm, Work& w, bool right, int poly_s = 0,
-                     size_t* size_only = nullptr) {
-    const int d = right ? n : m;
-    w.right = right;
-    w.d = d;
-    const int64_t mn = (int64_t)m * n;
+// Co-resident workgroups of the power kernel (queried once per context).
+cpa_status query_coop(cpa_ctx* ctx) {
     if (ctx->coop_max == 0) {
         int per_cu = 0, cus = 0;
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, power_coop_kernel<float>, kPowerThreads, 0));
         HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device));
         ctx->coop_max = std::max(1, per_cu * cus);
     }
+    return CPA_OK;
+}
+
+// Byte offsets of the dense workspace regions.  need_y: the two m x n ping-pong
+// buffers of the recurrence over X (the matrix-polynomial route does without).
+// warm: a d-double warm-start vector at the end (the allocation-free entry point
+// keeps it there; the other entry points keep theirs in the context).
+struct WsPlan {
+    size_t oG = 0, oY0 = 0, oY1 = 0, ow0 = 0, ow1 = 0, os = 0, opl = 0, ox = 0, oa = 0, owarm = 0, total = 0;
+};
+
+WsPlan plan_ws(int m, int n, int K, int maxit, bool admm, Work& w, bool right, int poly_s, int pwg, bool need_y,
+               bool warm) {
+    const int d = right ? n : m;
+    w.right = right;
+    w.d = d;
+    const int64_t mn = (int64_t)m * n;
     w.lay.K = K;
     w.lay.maxit = maxit;
     w.lay.gwg = gram_grid(d);
-    w.lay.pwg = power_grid(ctx, d);
+    w.lay.pwg = pwg;
+    WsPlan p;
     size_t off = 0;
-    const size_t oG = off; off = align_up(off + sizeof(float) * (size_t)d * d);
-    const size_t oY0 = off; off = align_up(off + sizeof(float) * (size_t)mn);
-    const size_t oY1 = off; off = align_up(off + sizeof(float) * (size_t)mn);
-    const size_t ow0 = off; off = align_up(off + sizeof(double) * (size_t)d);
-    const size_t ow1 = off; off = align_up(off + sizeof(double) * (size_t)d);
-    const size_t os = off; off = align_up(off + sizeof(double) * (size_t)w.lay.total());
-    size_t opl = 0;
-    if (poly_s > 0) { opl = off; off = align_up(off + sizeof(float) * (size_t)poly_mats(K, poly_s) * d * d); }
-    size_t ox = 0, oa = 0;
-    if (admm) {
-        ox = off; off = align_up(off + sizeof(float) * (size_t)mn);
-        oa = off; off = align_up(off + sizeof(double) * 2 * kAdmmGrid + 256);
+    p.oG = off; off = align_up(off + sizeof(float) * (size_t)d * d);
+    if (need_y) {
+        p.oY0 = off; off = align_up(off + sizeof(float) * (size_t)mn);
+        p.oY1 = off; off = align_up(off + sizeof(float) * (size_t)mn);
     }
+    p.ow0 = off; off = align_up(off + sizeof(double) * (size_t)d);
+    p.ow1 = off; off = align_up(off + sizeof(double) * (size_t)d);
+    p.os = off; off = align_up(off + sizeof(double) * (size_t)w.lay.total());
+    if (poly_s > 0) { p.opl = off; off = align_up(off + sizeof(float) * (size_t)poly_mats(K, poly_s) * d * d); }
+    if (admm) {
+        p.ox = off; off = align_up(off + sizeof(float) * (size_t)mn);
+        p.oa = off; off = align_up(off + sizeof(double) * 2 * kAdmmGrid + 256);
+    }
+    if (warm) { p.owarm = off; off = align_up(off + sizeof(double) * (size_t)std::max(d, 1)); }
+    p.total = off;
+    return p;
+}
+
+void bind_ws(Work& w, char* b, const WsPlan& p, bool admm, int poly_s, bool need_y) {
+    w.G = reinterpret_cast<float*>(b + p.oG);
+    w.Yb[0] = need_y ? reinterpret_cast<float*>(b + p.oY0) : nullptr;
+    w.Yb[1] = need_y ? reinterpret_cast<float*>(b + p.oY1) : nullptr;
+    w.w[0] = reinterpret_cast<double*>(b + p.ow0);
+    w.w[1] = reinterpret_cast<double*>(b + p.ow1);
+    w.scal = reinterpret_cast<double*>(b + p.os);
+    w.x = admm ? reinterpret_cast<float*>(b + p.ox) : nullptr;
+    w.admm = admm ? reinterpret_cast<double*>(b + p.oa) : nullptr;
+    w.et_counter = admm ? reinterpret_cast<int*>(b + p.oa + sizeof(double) * 2 * kAdmmGrid) : nullptr;
+    w.poly = poly_s > 0 ? reinterpret_cast<float*>(b + p.opl) : nullptr;
+    w.poly_s = poly_s;
+}
+
+// size_only != nullptr: report the bytes of the main workspace and the power
+// vector this call needs and allocate nothing.
+cpa_status ensure_ws(cpa_ctx* ctx, int m, int n, int K, int maxit, bool admm, Work& w, bool right, int poly_s = 0,
+                     size_t* size_only = nullptr) {
+    cpa_status s;
+    if ((s = query_coop(ctx)) != CPA_OK) return s;
+    const int d = right ? n : m;
+    const WsPlan p = plan_ws(m, n, K, maxit, admm, w, right, poly_s, power_grid(ctx, d), true, false);
+    const size_t off = p.total;
     if (size_only) {
         *size_only = off + sizeof(double) * (size_t)std::max(d, 1);
         return CPA_OK;
@@ -227,18 +292,7 @@ cpa_status ensure_ws(cpa_ctx* ctx, int m, int n, int K, int maxit, bool admm, Wo
         }
         ctx->ws_bytes = off;
     }
-    char* b = static_cast<char*>(ctx->ws);
-    w.G = reinterpret_cast<float*>(b + oG);
-    w.Yb[0] = reinterpret_cast<float*>(b + oY0);
-    w.Yb[1] = reinterpret_cast<float*>(b + oY1);
-    w.w[0] = reinterpret_cast<double*>(b + ow0);
-    w.w[1] = reinterpret_cast<double*>(b + ow1);
-    w.scal = reinterpret_cast<double*>(b + os);
-    w.x = admm ? reinterpret_cast<float*>(b + ox) : nullptr;
-    w.admm = admm ? reinterpret_cast<double*>(b + oa) : nullptr;
-    w.et_counter = admm ? reinterpret_cast<int*>(b + oa + sizeof(double) * 2 * kAdmmGrid) : nullptr;
-    w.poly = poly_s > 0 ? reinterpret_cast<float*>(b + opl) : nullptr;
-    w.poly_s = poly_s;
+    bind_ws(w, static_cast<char*>(ctx->ws), p, admm, poly_s, true);
     if (d > ctx->warm_cap) {
         if (ctx->warm) {
             HIP_TRY(hipDeviceSynchronize());
@@ -432,10 +486,12 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
                          const Work& w, int mode_override, const double* G64 = nullptr) {
     int mode = o->bound == CPA_BOUND_POWER ? 0 : (o->bound == CPA_BOUND_GIVEN ? 1 : 2);
     if (mode_override >= 0) mode = mode_override;
+    double* warm_vec = w.warm_vec ? w.warm_vec : ctx->warm;
+    int& warm_len = w.warm_len ? *w.warm_len : ctx->warm_d;
     if (mode == 0) {
-        const bool warm = o->warm_start && ctx->warm_d == d;
+        const bool warm = o->warm_start && warm_len == d;
         hipLaunchKernelGGL(power_init_kernel, dim3(1), dim3(256), 0, st, d, (uint64_t)o->seed,
-                           warm ? (const double*)ctx->warm : nullptr, w.w[0], w.scal, w.lay.pw_w2());
+                           warm ? (const double*)warm_vec : nullptr, w.w[0], w.scal, w.lay.pw_w2());
         HIP_TRY(hipGetLastError());
         int d_ = d, maxit_ = o->power_iters, pw_mu = w.lay.pw_mu(), pw_w2 = w.lay.pw_w2();
         const float* G = w.G;
@@ -457,11 +513,11 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
         if (ls != CPA_OK) return ls;
     }
     hipLaunchKernelGGL(finish_bound_kernel, dim3(1), dim3(256), 0, st, mode, o->Lambda, d, o->power_iters, o->margin,
-                       (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? ctx->warm : nullptr, w.scal,
+                       (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? warm_vec : nullptr, w.scal,
                        to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)(w.scal + w.lay.gpart()),
                        w.lay.gwg, 0, o->damping, w.poly_s, poly_fused(w, o->K) ? w.lay.ps() : -1);
     HIP_TRY(hipGetLastError());
-    if (mode == 0) ctx->warm_d = d;
+    if (mode == 0) warm_len = d;
     return CPA_OK;
 }
 
@@ -478,6 +534,7 @@ cpa_status enqueue_recurrence(cpa_ctx* ctx, hipStream_t st, int m, int n, const 
     }
     const int d = w.d;
     const int norms = w.lay.norms();
+    if (!w.Yb[0] || !w.Yb[1]) return fail(CPA_ERR_ARG, "internal: the recurrence has no Y buffers in this workspace");
     for (int k = 0; k + 1 <= K - 1; ++k) {
         EpiCheb epi;
         const float* yk = k == 0 ? X : w.Yb[(k - 1) & 1];
@@ -667,32 +724,47 @@ cpa_status enqueue_poly(cpa_ctx* ctx, hipStream_t st, int m, int n, const float*
     return poly_gemm(ctx, st, make_op(F, d, m), make_op(X, ldx, n), m, n, m, e, precision, false);
 }
 
+// Reads the scalar block's header and the growth-check norms through a fixed
+// host buffer (no heap allocation; one copy while K <= 48, else a few).
 cpa_status read_info(hipStream_t st, const Work& w, int K, int m, int n, cpa_info* info, double* growth_out) {
-    std::vector<double> h(w.lay.total());
-    HIP_TRY(hipMemcpyAsync(h.data(), w.scal, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+    constexpr int kBuf = 3200;
+    double h[kBuf];
+    const int nrm = w.lay.norms();
+    const int first = std::min(kBuf, nrm + std::max(K, 1) * kNormSlots);
+    HIP_TRY(hipMemcpyAsync(h, w.scal, sizeof(double) * first, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    double hdr[SC_COEF];
+    std::memcpy(hdr, h, sizeof(hdr));
     double g = 0.0;
-    const double x2 = h[SC_TRACE];
+    const double x2 = hdr[SC_TRACE];
+    int base = 0, have = first;   // h holds scal[base, base + have)
     for (int k = 1; k < K; ++k) {
+        const int at = nrm + k * kNormSlots;
+        if (at + kNormSlots > base + have) {
+            base = at;
+            have = std::min(kBuf / kNormSlots, K - k) * kNormSlots;
+            HIP_TRY(hipMemcpyAsync(h, w.scal + base, sizeof(double) * have, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
         double nk = 0.0;
-        for (int q = 0; q < kNormSlots; ++q) nk += h[w.lay.norms() + k * kNormSlots + q];
+        for (int q = 0; q < kNormSlots; ++q) nk += h[at - base + q];
         const double r = x2 > 0.0 ? std::sqrt(nk / x2) : 0.0;
         g = std::max(g, r);
     }
     if (growth_out) *growth_out = g;
     if (info) {
-        info->Lambda = h[SC_LAMBDA];
-        info->mu = h[SC_MU];
-        info->resid = h[SC_RESID];
-        info->fro_gram = std::sqrt(std::max(h[SC_FRO2], 0.0));
+        info->Lambda = hdr[SC_LAMBDA];
+        info->mu = hdr[SC_MU];
+        info->resid = hdr[SC_RESID];
+        info->fro_gram = std::sqrt(std::max(hdr[SC_FRO2], 0.0));
         info->max_growth = g;
-        info->power_iters_done = (int)h[SC_ITERS];
+        info->power_iters_done = (int)hdr[SC_ITERS];
         info->fallback = 0;
         info->side = w.right ? 0 : 1;
         info->reserved = 0;
     }
-    if (h[SC_TIMEOUT] != 0.0) return fail(CPA_ERR_HIP, "power iteration grid barrier timed out");
-    if (!std::isfinite(h[SC_LAMBDA])) return fail(CPA_ERR_NONFINITE, "spectral bound is not finite");
+    if (hdr[SC_TIMEOUT] != 0.0) return fail(CPA_ERR_HIP, "power iteration grid barrier timed out");
+    if (!std::isfinite(hdr[SC_LAMBDA])) return fail(CPA_ERR_NONFINITE, "spectral bound is not finite");
     return CPA_OK;
 }
 
@@ -1021,9 +1093,23 @@ cpa_status cpa_create(cpa_ctx** ctx_out, int device) {
     HIP_TRY(hipGetDeviceCount(&count));
     if (device < 0 || device >= count) return fail(CPA_ERR_ARG, "device %d out of range (%d devices)", device, count);
     HIP_TRY(hipSetDevice(device));
+    void* scratch_ptr = nullptr;
+    if (device < kMaxDevices) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            void* p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p)
+                return fail(CPA_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+            g_scratch_ptr[device] = p;
+            g_scratch_warm_d[device] = -1;
+        }
+        scratch_ptr = g_scratch_ptr[device];
+    }
     cpa_ctx* c = new (std::nothrow) cpa_ctx();
     if (!c) return fail(CPA_ERR_ALLOC, "context allocation failed");
     c->device = device;
+    c->scratch = scratch_ptr;
     *ctx_out = c;
     return CPA_OK;
 }
@@ -1166,6 +1252,51 @@ cpa_status cpa_shrink_dense(cpa_ctx* ctx, void* stream, int m, int n, const floa
     if ((s = ensure_ws(ctx, m, n, opts->K, maxit, false, w, right_side(opts, m, n), poly_choice(opts, m, n))) != CPA_OK)
         return s;
     return shrink_impl(ctx, st, m, n, X_dev, ldx, Y_dev, ldy, shrink, opts, info_host, w);
+}
+
+cpa_status cpa_shrink_dense_noalloc(cpa_ctx* ctx, void* stream, int m, int n, const float* X_dev, int64_t ldx,
+                                    float* Y_dev, int64_t ldy, const cpa_shrinkage* shrink, const cpa_opts* opts,
+                                    cpa_info* info_host) {
+    cpa_status s;
+    if ((s = check_dense_args(ctx, m, n, X_dev, ldx)) != CPA_OK) return s;
+    if ((s = check_shrinkage(shrink)) != CPA_OK) return s;
+    if ((s = check_opts(opts)) != CPA_OK) return s;
+    if (m == 0 || n == 0) {
+        if (info_host) std::memset(info_host, 0, sizeof(*info_host));
+        return CPA_OK;
+    }
+    if (!Y_dev) return fail(CPA_ERR_ARG, "Y is NULL");
+    if (ldy < n) return fail(CPA_ERR_SHAPE, "ldy %lld < n %d", (long long)ldy, n);
+    const size_t xb = sizeof(float) * ((size_t)(m - 1) * ldx + n);
+    const size_t yb = sizeof(float) * ((size_t)(m - 1) * ldy + n);
+    if (overlaps(X_dev, xb, Y_dev, yb)) return fail(CPA_ERR_ARG, "Y overlaps X");
+    if (!ctx->scratch) return fail(CPA_ERR_UNSUPPORTED, "no scratch on device %d", ctx->device);
+    const bool right = right_side(opts, m, n);
+    const int d = right ? n : m;
+    if (d > kScratchMaxD)
+        return fail(CPA_ERR_SHAPE, "Gram side %d exceeds the allocation-free limit of %d", d, kScratchMaxD);
+    HIP_TRY(hipSetDevice(ctx->device));
+    if ((s = query_coop(ctx)) != CPA_OK) return s;
+    Work w;
+    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    const int ps = poly_choice(opts, m, n);
+    const bool need_y = ps == 0;   // the recurrence over X (and the growth check's redo) needs the Y pair
+    const WsPlan p = plan_ws(m, n, opts->K, maxit, false, w, right, ps, power_grid(ctx, d), need_y, false);
+    if (p.total > kScratchBytes - kScratchWarmBytes)
+        return fail(CPA_ERR_SHAPE, "this shrink needs %zu bytes of workspace; the allocation-free entry point has %zu",
+                    p.total, kScratchBytes - kScratchWarmBytes);
+    char* base = static_cast<char*>(ctx->scratch);
+    bind_ws(w, base + kScratchWarmBytes, p, false, ps, need_y);
+    w.warm_vec = reinterpret_cast<double*>(base);
+    w.warm_len = &g_scratch_warm_d[ctx->device];
+    // per-launch timing would create events: off for this call
+    struct TimingOff {
+        cpa_ctx* c;
+        int saved;
+        ~TimingOff() { c->timing = saved; }
+    } guard{ctx, ctx->timing};
+    ctx->timing = 0;
+    return shrink_impl(ctx, static_cast<hipStream_t>(stream), m, n, X_dev, ldx, Y_dev, ldy, shrink, opts, info_host, w);
 }
 
 cpa_status cpa_timing_enable(cpa_ctx* ctx, int enable) {
