@@ -14,9 +14,11 @@ Typical use::
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import re
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -251,6 +253,7 @@ class Opts:
 # ---- device plumbing -----------------------------------------------------------
 
 _contexts: dict[int, int] = {}
+_plans = weakref.WeakSet()       # open BatchedPlan objects
 
 
 def context(device: int = 0) -> int:
@@ -259,6 +262,24 @@ def context(device: int = 0) -> int:
         _check(lib().cpa_create(ctypes.byref(h), int(device)))
         _contexts[device] = h.value
     return _contexts[device]
+
+
+def release() -> None:
+    """Destroys every open batched plan and every context (their graphs, streams,
+    events and device buffers).  Runs at interpreter exit, before the HIP runtime
+    is torn down, so nothing the library owns is left for the runtime's own exit
+    handlers; a later call creates a fresh context."""
+    for p in list(_plans):
+        try:
+            p.close()
+        except Exception:
+            pass
+    while _contexts:
+        _, h = _contexts.popitem()
+        lib().cpa_destroy(ctypes.c_void_p(h))
+
+
+atexit.register(release)
 
 
 def _stream(t):
@@ -271,8 +292,11 @@ def _mat(t, name, dtypes=("float32",)):
     ok = tuple(getattr(torch, d) for d in dtypes)
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype not in ok or t.dim() != 2:
         raise TypeError(f"{name} must be a 2-D {' or '.join(dtypes)} CUDA tensor")
-    if t.stride(1) != 1:
-        raise ValueError(f"{name} must have unit column stride (row-major)")
+    if t.shape[0] > 0 and t.shape[1] > 0:
+        if t.stride(1) != 1 and t.shape[1] > 1:
+            raise ValueError(f"{name} must have unit column stride (row-major)")
+        if t.shape[0] > 1 and t.stride(0) < t.shape[1]:
+            raise ValueError(f"{name} has rows that overlap (row stride {t.stride(0)} < {t.shape[1]} columns)")
     return t.shape[0], t.shape[1], max(t.stride(0), t.shape[1])
 
 
@@ -390,17 +414,61 @@ def shrink_dense_sparsified(X, shrink: CpaShrinkage, opts: Opts, keep: int | Non
     return out, d
 
 
+def _vec(t, name, dtype, count, device, nullable=True):
+    """Checks a 1-D contiguous CUDA tensor of `dtype` with at least `count` entries."""
+    import torch
+    if t is None:
+        if nullable:
+            return
+        raise TypeError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or t.device != device or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor on {device}")
+    if t.numel() < count:
+        raise ValueError(f"{name} holds {t.numel()} entries, {count} needed")
+
+
+def _batch_args(X, m, n, off, out, shrink_per_matrix=None, Lambda=None, lambda_out=None, status=None,
+                layout=True):
+    """Type, device and length checks of a packed batch's tensors; with `layout`,
+    also every matrix's extent against X and out (one host read of m, n, off)."""
+    import torch
+    if not isinstance(X, torch.Tensor) or not X.is_cuda or X.dtype != torch.float32 or not X.is_contiguous():
+        raise TypeError("X must be a contiguous float32 CUDA tensor")
+    dev = X.device
+    if not isinstance(m, torch.Tensor) or m.dim() != 1:
+        raise TypeError("m must be a 1-D int32 CUDA tensor")
+    batch = int(m.numel())
+    _vec(m, "m", torch.int32, batch, dev, False)
+    _vec(n, "n", torch.int32, batch, dev, False)
+    _vec(off, "off", torch.int64, batch, dev, False)
+    _vec(out, "out", torch.float32, X.numel(), dev, False)
+    _vec(shrink_per_matrix, "shrink_per_matrix", torch.uint8, batch * ctypes.sizeof(CpaShrinkage), dev)
+    _vec(Lambda, "Lambda", torch.float64, batch, dev)
+    _vec(lambda_out, "lambda_out", torch.float64, batch, dev)
+    _vec(status, "status", torch.int32, batch, dev)
+    if layout and batch > 0:
+        mh = m.cpu().numpy().astype(np.int64)
+        nh = n.cpu().numpy().astype(np.int64)
+        oh = off.cpu().numpy()
+        if (mh < 0).any() or (nh < 0).any() or (oh < 0).any():
+            raise ValueError("negative size or offset in the batch")
+        if (oh + mh * nh > X.numel()).any():
+            raise ValueError("a matrix of the batch extends past the end of X")
+    return batch
+
+
 def shrink_batched(X, m, n, off, shrink, opts: Opts, shrink_per_matrix=None, Lambda=None, out=None,
-                   lambda_out=None, status=None):
+                   lambda_out=None, status=None, check_layout: bool = True):
     """Shrinks every matrix of a packed batch (see cpa_shrink_batched).
 
     X: 1-D float32 CUDA tensor; m, n: int32 CUDA tensors; off: int64 CUDA tensor.
     shrink_per_matrix: optional uint8 CUDA tensor holding `batch` packed
-    cpa_shrinkage records (see shrinkage_records).  Returns Y."""
+    cpa_shrinkage records (see shrinkage_records).  check_layout reads m, n and off
+    to the host to check every matrix lies inside X.  Returns Y."""
     import torch
-    batch = int(m.numel())
-    if out is None:
+    if out is None and isinstance(X, torch.Tensor):
         out = torch.empty_like(X)
+    batch = _batch_args(X, m, n, off, out, shrink_per_matrix, Lambda, lambda_out, status, check_layout)
     co = opts.to_c()
     _check(lib().cpa_shrink_batched(ctypes.c_void_p(context(X.device.index or 0)), _stream(X), batch, _ptr(m),
                                     _ptr(n), _ptr(off), _ptr(X), _ptr(out), _ptr(shrink_per_matrix),
@@ -419,8 +487,10 @@ class BatchedPlan:
     def __init__(self, X, m, n, off, shrink, opts: Opts, shrink_per_matrix=None, Lambda=None, out=None,
                  lambda_out=None, status=None, tune: bool = True):
         import torch
-        if out is None:
+        if out is None and isinstance(X, torch.Tensor):
             out = torch.empty_like(X)
+        _batch_args(X, m, n, off, out, shrink_per_matrix, Lambda, lambda_out, status)
+        self._h = None
         self._keep = (X, m, n, off, shrink_per_matrix, Lambda, out, lambda_out, status)
         self._shrink = shrink
         self._co = opts.to_c()
@@ -433,6 +503,7 @@ class BatchedPlan:
                                              ctypes.byref(self._co), _ptr(Lambda), _ptr(lambda_out), _ptr(status),
                                              1 if tune else 0, ctypes.byref(h)))
         self._h = h.value
+        _plans.add(self)
 
     def run(self):
         if self._h is None:
@@ -469,6 +540,8 @@ def batched_features(X, m, n, off, out=None, status=None):
     batch = int(m.numel())
     if out is None:
         out = torch.empty((batch, 3), device=X.device, dtype=torch.float32)
+    _batch_args(X, m, n, off, X, status=status)
+    _vec(out, "out", torch.float32, 3 * batch, X.device, False)
     _check(lib().cpa_batched_features(ctypes.c_void_p(context(X.device.index or 0)), _stream(X), batch, _ptr(m),
                                       _ptr(n), _ptr(off), _ptr(X), _ptr(out), _ptr(status)))
     return out
@@ -479,11 +552,13 @@ def shrink_batched_predicted(X, m, n, off, shrink, opts: Opts, model, K_min: int
     """Batched shrinkage with Lambda and K_j from the predictor `model` (float32 CUDA
     tensor of PRED_MODEL_FLOATS entries); opts.K is the largest order."""
     import torch
-    batch = int(m.numel())
-    if out is None:
+    if out is None and isinstance(X, torch.Tensor):
         out = torch.empty_like(X)
-    if model.dtype != torch.float32 or model.numel() != PRED_MODEL_FLOATS or not model.is_contiguous():
-        raise ValueError("model must be a contiguous float32 tensor of %d entries" % PRED_MODEL_FLOATS)
+    batch = _batch_args(X, m, n, off, out, shrink_per_matrix, None, lambda_out, status)
+    _vec(K_out, "K_out", torch.int32, batch, X.device)
+    if not isinstance(model, torch.Tensor) or model.device != X.device or model.dtype != torch.float32 \
+            or model.numel() != PRED_MODEL_FLOATS or not model.is_contiguous():
+        raise ValueError("model must be a contiguous float32 tensor of %d entries on X's device" % PRED_MODEL_FLOATS)
     co = opts.to_c()
     _check(lib().cpa_shrink_batched_predicted(ctypes.c_void_p(context(X.device.index or 0)), _stream(X), batch,
                                               _ptr(m), _ptr(n), _ptr(off), _ptr(X), _ptr(out),

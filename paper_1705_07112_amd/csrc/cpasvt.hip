@@ -2260,6 +2260,8 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
     }
     if (!Y_dev) return fail(CPA_ERR_ARG, "Y is NULL");
     if (ldy < n) return fail(CPA_ERR_SHAPE, "ldy < n");
+    if (overlaps(X_dev, sizeof(float) * ((size_t)(m - 1) * ldx + n), Y_dev, sizeof(float) * ((size_t)(m - 1) * ldy + n)))
+        return fail(CPA_ERR_ARG, "Y overlaps X");
     const bool right = right_side(opts, m, n);
     const int d = right ? n : m;
     if (d % 8 != 0) return fail(CPA_ERR_SHAPE, "the Gram side (%d) must be a multiple of 8 (8 x 8 tiles)", d);

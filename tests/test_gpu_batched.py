@@ -164,6 +164,34 @@ def test_batched_rejects_out_of_range_shapes():
     assert list(status) == [2, 2, 0]
 
 
+def test_batched_binding_checks_its_tensors():
+    """The binding rejects tensors of the wrong type, device or length, and
+    matrices that extend past the end of X, before anything reaches the library."""
+    import torch
+    import paper_1705_07112_amd as cpa
+    X = torch.zeros(64 * 40 + 64 * 50, device="cuda")
+    m = torch.tensor([64, 64], dtype=torch.int32, device="cuda")
+    n = torch.tensor([40, 50], dtype=torch.int32, device="cuda")
+    off = torch.tensor([0, 64 * 40], dtype=torch.int64, device="cuda")
+    opts = cpa.Opts(K=8)
+    cpa.shrink_batched(X, m, n, off, cpa.soft(1.0), opts)
+    with pytest.raises(TypeError):
+        cpa.shrink_batched(X, m.long(), n, off, cpa.soft(1.0), opts)
+    with pytest.raises(TypeError):
+        cpa.shrink_batched(X, m, n, off.int(), cpa.soft(1.0), opts)
+    with pytest.raises(TypeError):
+        cpa.shrink_batched(X, m, n.cpu(), off, cpa.soft(1.0), opts)
+    with pytest.raises(ValueError):
+        cpa.shrink_batched(X, m, n[:1], off, cpa.soft(1.0), opts)
+    with pytest.raises(ValueError):
+        cpa.shrink_batched(X, m, n, off, cpa.soft(1.0), opts,
+                           lambda_out=torch.zeros(1, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        cpa.shrink_batched(X, m, n, off + 1, cpa.soft(1.0), opts)
+    with pytest.raises(ValueError):
+        cpa.BatchedPlan(X[:100], m, n, off, cpa.soft(1.0), opts)
+
+
 def test_batched_rejects_damping():
     """Coefficient damping is not available on the batched path (checked before
     any launch)."""

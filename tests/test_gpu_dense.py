@@ -334,3 +334,23 @@ def test_damped_coefficients_match_oracle(damping, ev):
               f"(damped vs undamped oracle {metrics.rel_fro(ref, undamped, X):.2e})", flush=True)
         assert err <= TOL32
         assert metrics.rel_fro(ref, undamped, X) > 1e-4   # the damping changed the result
+
+
+def test_release_and_row_stride_checks():
+    """release() destroys the contexts (as at interpreter exit); the next call
+    makes a fresh one and gives the same result.  Tensors whose rows overlap are
+    refused by the binding."""
+    import torch
+    import paper_1705_07112_amd as cpa
+    X = torch.from_numpy(synth.as_f32_exact(synth.dense_lowrank(100, 70, rank=4, seed=77)).astype(np.float32)).cuda()
+    Y1 = cpa.shrink_dense(X, cpa.soft(1.0), cpa.Opts(K=12)).clone()
+    cpa.release()
+    Y2 = cpa.shrink_dense(X, cpa.soft(1.0), cpa.Opts(K=12))
+    torch.cuda.synchronize()
+    assert torch.equal(Y1, Y2)
+    row = torch.ones((1, 70), device="cuda")
+    with pytest.raises(ValueError):
+        cpa.shrink_dense(row.expand(100, 70), cpa.soft(1.0), cpa.Opts(K=4))
+    with pytest.raises(ValueError):
+        cpa.shrink_dense(torch.ones(8 * 99 + 70, device="cuda").as_strided((100, 70), (8, 1)), cpa.soft(1.0),
+                         cpa.Opts(K=4))

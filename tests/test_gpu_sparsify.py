@@ -219,6 +219,18 @@ def test_sparsified_is_deterministic_and_rejects_bad_arguments():
     X2 = torch.ones((40, 36), device="cuda")
     with pytest.raises(cpa.CpaError):
         cpa.shrink_dense_sparsified(X2, cpa.soft(1.0), o, keep=10)
+    # Y written over X (or over part of it) is an argument error, caught before any launch
+    before = X.clone()
+    with pytest.raises(cpa.CpaError) as e:
+        cpa.shrink_dense_sparsified(X, cpa.soft(1.0), o, keep=100, out=X)
+    assert e.value.status == cpa.ERR_ARG
+    big = torch.zeros((256, 64), device="cuda")
+    big[:128] = X
+    with pytest.raises(cpa.CpaError) as e:
+        cpa.shrink_dense_sparsified(big[:128], cpa.soft(1.0), o, keep=100, out=big[64:192])
+    assert e.value.status == cpa.ERR_ARG
+    torch.cuda.synchronize()
+    assert torch.equal(X, before)
 
 
 @pytest.mark.parametrize("ev", ["auto", "recurrence"])
