@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import synth
+from tests import parity
 from oracle import bound as obound
 from oracle import cpa as ocpa
 from oracle import metrics
@@ -87,10 +88,10 @@ def test_batched_matches_oracle_given_lambda(K):
     worst = 0.0
     for X, Y, sh, lam in zip(mats, outs, shr_o, lams):
         ref = ocpa.cpa_shrink(X, sh, lam, K)
-        err = metrics.rel_fro(Y, ref, X)
-        worst = max(worst, err)
-        assert err <= TOL32, (X.shape, K, err)
-    print(f"batched K={K}: worst rel_fro {worst:.3e} over {len(mats)} matrices", flush=True)
+        err, mx = parity.errors(Y, ref, X)
+        worst = max(worst, err, mx)
+        assert err <= TOL32 and mx <= parity.ELEM_FACTOR * TOL32, (X.shape, K, err, mx)
+    print(f"batched K={K}: worst rel_fro / max_elem {worst:.3e} over {len(mats)} matrices", flush=True)
     assert np.allclose(lam_out, lams)
 
 
@@ -104,9 +105,9 @@ def test_batched_split_precision_matches_oracle(K):
     worst = 0.0
     for X, Y, sh, lam in zip(mats, outs, shr_o, lams):
         ref = ocpa.cpa_shrink(X, sh, lam, K)
-        err = metrics.rel_fro(Y, ref, X)
-        worst = max(worst, err)
-        assert err <= TOL_SPLIT, (X.shape, K, err)
+        err, mx = parity.errors(Y, ref, X)
+        worst = max(worst, err, mx)
+        assert err <= TOL_SPLIT and mx <= parity.ELEM_FACTOR * TOL_SPLIT, (X.shape, K, err, mx)
     print(f"batched split K={K}: worst rel_fro {worst:.3e} over {len(mats)} matrices", flush=True)
     assert np.allclose(lam_out, lams)
 

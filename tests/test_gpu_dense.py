@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import synth
+from tests import parity
 from oracle import bound as obound
 from oracle import cpa as ocpa
 from oracle import metrics
@@ -65,9 +66,7 @@ def _case(m, n, K, kind, seed, ld=None, offset=0, ev="auto", side="auto"):
         sh_o, sh_c = Shrinkage(3, 0.0, wc, ws, 1e-3), cpa.weighted_fn(wc, ws, 1e-3)
     ref = ocpa.cpa_shrink(X, sh_o, Lam, K)
     got, info = _run(X, sh_c, K, Lam, ld=ld, offset=offset, ev=ev, side=side)
-    err = metrics.rel_fro(got, ref, X)
-    print(f"  rel_fro={err:.3e}", flush=True)
-    assert err <= TOL32, (m, n, K, kind, err)
+    err, _ = parity.check(got, ref, TOL32, X, f"{m}x{n} K={K} kind={kind}")
     assert info["side"] == {"auto": 0 if m >= n else 1, "right": 0, "left": 1}[side]
     return err
 
@@ -187,8 +186,7 @@ def test_full_size_rpca_matrix_sampled_rows():
     Y = cpa.shrink_dense(Xd, cpa.soft(tau), cpa.Opts(K=K, Lambda=lam_o)).cpu().numpy()
     rows = np.array([0, 1, 2, 63, 64, 65, 511, 512, 777, 1000, 1022, 1023])
     ref = ocpa.cpa_rows(X, Shrinkage(0, tau), lam_o, K, rows)
-    err = metrics.rel_fro(Y[rows].astype(np.float64), ref)
-    print(f"full-size sampled rows rel_fro={err:.3e}", flush=True)
+    err, _ = parity.check(Y[rows].astype(np.float64), ref, TOL32, label="full-size sampled rows")
     assert err <= TOL32
     # the power bound path on the device agrees with the oracle's bound
     lam_g, _ = cpa.spectral_bound(Xd, cpa.Opts(K=K))
@@ -220,8 +218,7 @@ def test_polynomial_route_full_size_and_unaligned():
     for K in (16, 30, 64):
         Y = cpa.shrink_dense(Xd, cpa.soft(10.0), cpa.Opts(K=K, Lambda=lam_o, eval="polynomial")).cpu().numpy()
         ref = ocpa.cpa_rows(X, Shrinkage(0, 10.0), lam_o, K, rows)
-        err = metrics.rel_fro(Y[rows].astype(np.float64), ref)
-        print(f"polynomial route 1024^2 K={K} sampled rel_fro={err:.3e}", flush=True)
+        err, _ = parity.check(Y[rows].astype(np.float64), ref, TOL32, label=f"polynomial route 1024^2 K={K} sampled")
         assert err <= TOL32
     # odd d (no 16-byte rows) and a strided input
     _case(131, 77, 25, 0, seed=91, ev="polynomial")
@@ -354,3 +351,29 @@ def test_release_and_row_stride_checks():
     with pytest.raises(ValueError):
         cpa.shrink_dense(torch.ones(8 * 99 + 70, device="cuda").as_strided((100, 70), (8, 1)), cpa.soft(1.0),
                          cpa.Opts(K=4))
+
+
+@pytest.mark.parametrize("ev", ["recurrence", "polynomial"])
+def test_frobenius_bound_without_margin_on_rpca_frames(ev):
+    """Lambda = ||G||_F with no margin (the Frobenius rule, and the bound the
+    growth-check and barrier-timeout fallbacks take): on the 1024 x 1024 frames
+    ||G||_F / lambda_max is 1 + 1e-5, so the top eigenvalue sits at the end of
+    [-1, 1], where T_k has slope k^2 and rounding is amplified the most.  The
+    whole output against the oracle at the same Lambda, on both routes; then the
+    device's own Frobenius rule (its FP32 Gram's norm) at the Lambda it reports."""
+    torch = _torch()
+    cpa = _lib()
+    I, _, _ = synth.rpca_frames()
+    X = I.astype(np.float64)
+    G = X.T @ X
+    Lam = float(np.linalg.norm(G))
+    lmax = float(np.linalg.eigvalsh(G)[-1])
+    print(f"frames: ||G||_F / lambda_max - 1 = {Lam / lmax - 1:.3e}, eval={ev}", flush=True)
+    Xd = torch.from_numpy(I).cuda()
+    Y = cpa.shrink_dense(Xd, cpa.soft(10.0), cpa.Opts(K=30, Lambda=Lam, eval=ev)).cpu().numpy()
+    ref = ocpa.cpa_shrink(X, Shrinkage(0, 10.0), Lam, 30)
+    parity.check(Y, ref, TOL32, X, f"Lambda = ||G||_F {ev}")
+    Y2, info = cpa.shrink_dense(Xd, cpa.soft(10.0), cpa.Opts(K=30, bound="frobenius", eval=ev), info=True)
+    assert abs(info["Lambda"] - Lam) <= 1e-6 * Lam
+    ref2 = ocpa.cpa_shrink(X, Shrinkage(0, 10.0), info["Lambda"], 30)
+    parity.check(Y2.cpu().numpy(), ref2, TOL32, X, f"device Frobenius rule {ev}")

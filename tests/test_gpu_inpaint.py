@@ -215,3 +215,29 @@ def test_scheduled_inpaint_rejects_a_gram_side_off_the_8_grid():
     assert e.value.status == 2 and "multiple of 8" in str(e.value)
     torch.cuda.synchronize()
     assert torch.equal(run.state, before)
+
+
+def test_inpaint_one_iteration_full_size():
+    """The bench's inpainting workload at full size (2560 x 1920, 300 x 300 hole,
+    8-pixel frame, K = 20, 1/rho = 6, eta/rho = 0.1): one iteration from the GPU's
+    own state after two, every block against the oracle step."""
+    import torch
+    m, n, K, inv_rho, eta = 2560, 1920, 20, 6.0, 0.1
+    hole = (m // 2 - 150, m // 2 + 150, n // 2 - 150, n // 2 + 150)
+    I, om, bd, _ = synth.texture(m, n, terms=4, hole=hole, border=8, seed=synth.BASE_SEED + 7)
+    import paper_1705_07112_amd as cpa
+    run = cpa.Inpaint(torch.from_numpy(I.astype(np.float32)).cuda(), torch.from_numpy(om), inv_rho, eta,
+                      cpa.Opts(K=K, warm_start=True, power_iters=100), border=torch.from_numpy(bd.astype(np.float32)))
+    run.iterate(2)
+    before = _state_host(run)
+    Et = torch.zeros(1, dtype=torch.float64, device="cuda")
+    run.iterate(1, Et)
+    torch.cuda.synchronize()
+    after = _state_host(run)
+    ref, info = drivers.inpaint_step(before, I.astype(np.float32).astype(np.float64), om, bd, inv_rho, eta, K)
+    errs = _errs(before, after, ref, om)
+    print("inpaint 2560x1920 one iteration: " + " ".join(f"{k}={v:.1e}" for k, v in errs.items())
+          + f" E gpu={Et.item():.6g} oracle={info['E']:.6g}", flush=True)
+    for k in NAMES:
+        assert errs[k] <= 1e-5, (k, errs[k])
+    assert abs(Et.item() - info["E"]) <= 1e-5 * max(info["E"], 1e-12)

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import synth
+from tests import parity
 from oracle import bound as obound
 from oracle import cpa as ocpa
 from oracle import drivers, metrics
@@ -54,9 +55,7 @@ def test_csr_matches_oracle(m, n, frac, K):
     Lam, tau = 1.01 * lmax, 0.3 * math.sqrt(lmax)
     Y = _gpu_csr(m, n, rowptr, cols, vals, cpa.soft(tau), cpa.Opts(K=K, Lambda=Lam)).cpu().numpy()
     ref = ocpa.cpa_shrink(S, Shrinkage(0, tau), Lam, K)
-    err = metrics.rel_fro(Y, ref, S)
-    print(f"csr {m}x{n} nnz={len(vals)} K={K} rel_fro={err:.3e}", flush=True)
-    assert err <= TOL32
+    parity.check(Y, ref, TOL32, S, f"csr {m}x{n} nnz={len(vals)} K={K}")
 
 
 def test_csr_edge_cases():
@@ -89,9 +88,12 @@ def test_csr_operator_bound_matches_oracle():
     assert abs(info["Lambda"] - lam_o) <= 2e-6 * lam_o
 
 
-def test_csr_full_size_sampled_rows():
-    """20000 x 4000, 2% observed (1.6M entries), K = 25: rows of the result against
-    the oracle's Y-form on the same rows, with the Gram from a sparse product."""
+@pytest.mark.parametrize("ev", ["auto", "recurrence"])
+def test_csr_full_size_sampled_rows(ev):
+    """20000 x 4000, 2% observed (1.6M entries), K = 25, on both routes (the
+    operator form is eval = recurrence): rows from the first, middle and last
+    row panels of the result against the oracle's Y-form on the same rows, with
+    the Gram from a sparse product."""
     import scipy.sparse as sp
     import torch
     import paper_1705_07112_amd as cpa
@@ -101,13 +103,11 @@ def test_csr_full_size_sampled_rows():
     G = (S.T @ S).toarray()
     lam = float(obound.power_bound(G, seed=0, max_iter=300, tol=1e-10, cap=float(np.trace(G)))[0])
     tau = 0.5 * math.sqrt(lam)
-    Y = _gpu_csr(m, n, rowptr, cols, vals, cpa.soft(tau), cpa.Opts(K=25, Lambda=lam))
-    rows = np.array([0, 1, 777, 10000, 19999])
+    Y = _gpu_csr(m, n, rowptr, cols, vals, cpa.soft(tau), cpa.Opts(K=25, Lambda=lam, eval=ev))
+    rows = np.r_[0:8, 777, 9996:10004, 19992:20000]
     got = Y[torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.float64)
     ref = ocpa.cpa_rows_yform(G, S[rows].toarray(), Shrinkage(0, tau), lam, 25)
-    err = metrics.rel_fro(got, ref)
-    print(f"csr full size sampled rows rel_fro={err:.3e}", flush=True)
-    assert err <= TOL32
+    parity.check(got, ref, TOL32, label=f"csr full size sampled rows {ev}")
 
 
 def test_svt_completion_matches_oracle():
@@ -150,9 +150,7 @@ def test_csr_both_evaluation_routes(ev, m, n, frac, K):
     Lam, tau = 1.01 * lmax, 0.3 * math.sqrt(lmax)
     Y = _gpu_csr(m, n, rowptr, cols, vals, cpa.soft(tau), cpa.Opts(K=K, Lambda=Lam, eval=ev)).cpu().numpy()
     ref = ocpa.cpa_shrink(S, Shrinkage(0, tau), Lam, K)
-    err = metrics.rel_fro(Y.astype(np.float64), ref, S)
-    print(f"csr {m}x{n} K={K} eval={ev} rel_fro={err:.3e}", flush=True)
-    assert err <= TOL32
+    parity.check(Y.astype(np.float64), ref, TOL32, S, f"csr {m}x{n} K={K} eval={ev}")
 
 
 def test_csr_damped_coefficients_match_oracle():
@@ -165,6 +163,4 @@ def test_csr_damped_coefficients_match_oracle():
         Y = _gpu_csr(m, n, rowptr, cols, vals, cpa.hard(tau),
                      cpa.Opts(K=K, Lambda=Lam, eval=ev, damping="jackson")).cpu().numpy()
         ref = ocpa.cpa_shrink(S, Shrinkage(1, tau), Lam, K, damping="jackson")
-        err = metrics.rel_fro(Y, ref, S)
-        print(f"csr damped {ev}: rel_fro={err:.3e}", flush=True)
-        assert err <= TOL32
+        parity.check(Y, ref, TOL32, S, f"csr damped {ev}")

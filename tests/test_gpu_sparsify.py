@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import synth
+from tests import parity
 from oracle import bound as obound
 from oracle import cpa as ocpa
 from oracle import metrics, sparsify
@@ -60,7 +61,7 @@ def _case(X, T, transform, frac, K, sh_o, sh_c, side_right=True, ev="auto", zero
     # on the scale of the largest entry of Phi
     assert abs(info["eps"] - eps_o) <= eps_tol * float(np.abs(Phi).max())
     assert info["side"] == (0 if side_right else 1)
-    assert err <= TOL32
+    parity.check(Y.cpu().numpy().astype(np.float64), ref, TOL32, X, f"sparsified {transform} {ev}")
     return Y
 
 
@@ -300,3 +301,51 @@ def test_given_threshold_argument_errors():
         with pytest.raises(cpa.CpaError) as e:
             cpa.shrink_dense_sparsified(Xd, cpa.soft(1.0), cpa.Opts(K=8), eps=bad)
         assert e.value.status == 1
+
+
+@pytest.mark.parametrize("ev", ["auto", "recurrence"])
+def test_selection_at_ties_is_exact(ev):
+    """Integer entries |x| <= 3 make the FP32 Gram exact (T = Id, Phi = G), with
+    long runs of equal magnitudes.  For keep counts inside such runs the threshold
+    must be the k-th largest |Phi| exactly and every entry equal to it kept, so
+    the kept count (above k) matches numpy's count on the same integers; then the
+    result against the oracle with that keep."""
+    import torch
+    cpa = _lib()
+    g = synth.rng(9700)
+    m, n, K = 200, 64, 12
+    X = g.integers(-3, 4, size=(m, n)).astype(np.float64)
+    G = X.T @ X
+    a = np.sort(np.abs(G).ravel())[::-1]
+    inside = [k for k in range(3, a.size) if a[k - 2] == a[k - 1] == a[k]]
+    picks = sorted({inside[len(inside) // 6], inside[len(inside) // 2], inside[(5 * len(inside)) // 6]})
+    Xd = torch.from_numpy(X.astype(np.float32)).cuda()
+    T = np.eye(n)
+    for k in picks:
+        eps_o = sparsify.kth_largest_abs(G, k)
+        nnz_o = int(np.count_nonzero(np.abs(G) >= eps_o))
+        Phil = sparsify.truncate(G, eps_o)
+        lam = 1.01 * float(np.linalg.eigvalsh(Phil)[-1])
+        tau = 0.3 * math.sqrt(lam)
+        Y, info = cpa.shrink_dense_sparsified(Xd, cpa.soft(tau), cpa.Opts(K=K, Lambda=lam, eval=ev), keep=k,
+                                              transform="identity", info=True)
+        torch.cuda.synchronize()
+        print(f"ties {ev}: keep {k} -> eps gpu {info['eps']} oracle {eps_o}, kept gpu {info['nnz']} "
+              f"oracle {nnz_o}", flush=True)
+        assert nnz_o > k
+        assert info["eps"] == eps_o and info["nnz"] == nnz_o
+        ref, _, nnz_r = sparsify.cpa_shrink_sparsified(X, Shrinkage(0, tau), lam, K, T, k)
+        assert nnz_r == nnz_o
+        parity.check(Y.cpu().numpy().astype(np.float64), ref, TOL32, X, f"ties keep={k} {ev}")
+
+
+@pytest.mark.parametrize("ev", ["auto", "recurrence"])
+def test_block_dct_full_size(ev):
+    """The bench's sparsified workload at full size: 1024 x 1024 block-smooth
+    input (rank 4, 8-blocks), block DCT, K = 30, soft tau = 0.2 sigma_1, about
+    1.6% of the transformed Gram kept (at a gap in |Phi|)."""
+    cpa = _lib()
+    X = synth.as_f32_exact(synth.block_smooth(1024, 1024, rank=4, noise=1e-3, seed=synth.BASE_SEED + 6))
+    T = sparsify.block_dct(1024, 8)
+    s1 = math.sqrt(float(np.linalg.eigvalsh(X.T @ X)[-1]))
+    _case(X, T, "block_dct8", 0.016, 30, Shrinkage(0, 0.2 * s1), cpa.soft(0.2 * s1), ev=ev)

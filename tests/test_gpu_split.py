@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import synth
+from tests import parity
 from oracle import bound as obound
 from oracle import cpa as ocpa
 from oracle import metrics
@@ -37,9 +38,8 @@ def _case(m, n, K, kind, seed, ld=None, ev="auto"):
     buf.view(m, ld)[:, :n] = torch.from_numpy(X.astype(np.float32))
     Xd = buf.cuda().view(m, ld)[:, :n]
     Y = cpa.shrink_dense(Xd, sh_c, cpa.Opts(K=K, Lambda=Lam, precision="bf16x3", eval=ev)).cpu().numpy()
-    err = metrics.rel_fro(Y, ocpa.cpa_shrink(X, sh_o, Lam, K), X)
-    print(f"bf16x3 m={m} n={n} K={K} kind={kind} eval={ev} rel_fro={err:.3e}", flush=True)
-    assert err <= TOL_SPLIT
+    err, _ = parity.check(Y, ocpa.cpa_shrink(X, sh_o, Lam, K), TOL_SPLIT, X,
+                          f"bf16x3 m={m} n={n} K={K} kind={kind} eval={ev}")
     return err
 
 
@@ -67,9 +67,8 @@ def test_split_full_size_rpca_matrix():
     Y = cpa.shrink_dense(torch.from_numpy(I).cuda(), cpa.soft(10.0),
                          cpa.Opts(K=30, Lambda=lam, precision="bf16x3")).cpu().numpy()
     rows = np.array([0, 1, 63, 64, 500, 1023])
-    err = metrics.rel_fro(Y[rows].astype(np.float64), ocpa.cpa_rows(X, Shrinkage(0, 10.0), lam, 30, rows))
-    print(f"bf16x3 full size sampled rows rel_fro={err:.3e}", flush=True)
-    assert err <= TOL_SPLIT
+    parity.check(Y[rows].astype(np.float64), ocpa.cpa_rows(X, Shrinkage(0, 10.0), lam, 30, rows), TOL_SPLIT,
+                 label="bf16x3 full size sampled rows")
 
 
 @pytest.mark.parametrize("ev", ["recurrence", "polynomial"])
