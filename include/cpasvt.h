@@ -337,16 +337,28 @@ cpa_status cpa_shrink_csr(cpa_ctx* ctx, void* stream, int m, int n, int64_t nnz,
 
 /* Matrix completion by singular value thresholding (Cai, Candes, Shen; the paper
  * uses the nuclear-norm prox of Sec. V-B.1 inside its solvers) on the observed
- * entries P_Omega(M) given in CSR (the pattern is Omega):
+ * entries P_Omega(M) given in CSR (the pattern is Omega; columns strictly
+ * increasing within a row):
  *   Y^0 = k0 delta P_Omega(M), k0 = ceil(tau / (delta ||P_Omega(M)||_2)),
- *   X^t = shrink_tau(Y^{t-1})  (cpa_shrink_csr, soft threshold tau),
+ *   X^t = shrink_tau(Y^{t-1})  (the CSR shrinkage, soft threshold tau),
  *   Y^t = Y^{t-1} + delta P_Omega(M - X^t).
- * X_dev (m x n dense, ldx >= n) receives X^iters.  resid_dev
+ * The iterate Y^t lives on Omega (nnz values in CSR order).  On the
+ * matrix-polynomial route with n <= 4096 the iterations before the last form only
+ * the observed entries of X^t (the Gram by rows of Y, the polynomial p on the
+ * n x n side, then (Y p)[r][c] for (r, c) in Omega); the last iteration forms the
+ * dense X^iters.  X_dev (m x n dense, ldx >= n) receives X^iters.  resid_dev
  * (device, iters doubles, nullable) receives ||P_Omega(M - X^t)||_F / ||P_Omega M||_F.
- * *k0_host (nullable) receives k0.  Synchronises once (for k0). */
+ * Y0_vals_dev (device, nnz floats, nullable): start from this iterate instead of
+ * k0 delta P_Omega(M) (k0 is then neither computed nor reported: *k0_host = 0);
+ * Y_vals_dev (device, nnz floats, nullable; may equal Y0_vals_dev, must not
+ * partly overlap it): receives Y^iters, so a later call can continue the run.
+ * Lambda_dev (device, iters doubles, nullable): the bound of each iteration's
+ * shrink.  *k0_host (nullable) receives k0.  Synchronises once (for k0 and the
+ * norm of P_Omega M). */
 cpa_status cpa_svt_complete(cpa_ctx* ctx, void* stream, int m, int n, int64_t nnz, const int32_t* rowptr_dev,
                             const int32_t* colidx_dev, const float* Mobs_dev, double tau, double delta, int iters,
-                            float* X_dev, int64_t ldx, const cpa_opts* opts, double* resid_dev, double* k0_host);
+                            float* X_dev, int64_t ldx, const cpa_opts* opts, double* resid_dev, double* k0_host,
+                            const float* Y0_vals_dev, float* Y_vals_dev, double* Lambda_dev);
 
 /* Batched shrinkage of many small matrices in one persistent launch (each
  * matrix: Algorithm 1 with T = Id, evaluated as in cpa_shrink_dense, inside one

@@ -132,7 +132,7 @@ _SIGS = {
                                       ctypes.POINTER(CpaShrinkage), ctypes.POINTER(CpaOpts), ctypes.POINTER(CpaInfo)]),
     "cpa_svt_complete": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _P, _P, _P, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_int, _P, _I64, ctypes.POINTER(CpaOpts), _P,
-                                        ctypes.POINTER(ctypes.c_double)]),
+                                        ctypes.POINTER(ctypes.c_double), _P, _P, _P]),
     "cpa_shrink_batched": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.POINTER(CpaShrinkage),
                                           ctypes.POINTER(CpaOpts), _P, _P, _P]),
     "cpa_batched_features": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P, _P, _P, _P, _P]),
@@ -621,18 +621,27 @@ def shrink_csr(m, n, rowptr, colidx, vals, shrink, opts: Opts, out=None, info: b
 
 
 def svt_complete(m, n, rowptr, colidx, mvals, tau: float, delta: float, iters: int, opts: Opts, out=None,
-                 resid=None):
-    """SVT matrix completion on the observed CSR entries; returns (X, k0)."""
+                 resid=None, y_start=None, y_end=None, lambdas=None):
+    """SVT matrix completion on the observed CSR entries; returns (X, k0).
+
+    y_start / y_end: float32 CUDA tensors of nnz values (the iterate on the
+    observed set, CSR order) to continue from / to receive the final iterate;
+    lambdas: float64 CUDA tensor of `iters` entries for each iteration's bound."""
     import torch
     if out is None:
         out = torch.empty((m, n), device=mvals.device, dtype=torch.float32)
     _, _, ldx = _mat(out, "out")
+    nnz = int(mvals.numel())
+    _vec(y_start, "y_start", torch.float32, nnz, mvals.device)
+    _vec(y_end, "y_end", torch.float32, nnz, mvals.device)
+    _vec(lambdas, "lambdas", torch.float64, int(iters), mvals.device)
+    _vec(resid, "resid", torch.float64, int(iters), mvals.device)
     k0 = ctypes.c_double()
     co = opts.to_c()
     _check(lib().cpa_svt_complete(ctypes.c_void_p(context(mvals.device.index or 0)), _stream(mvals), int(m), int(n),
-                                  int(mvals.numel()), _ptr(rowptr), _ptr(colidx), _ptr(mvals), float(tau),
+                                  nnz, _ptr(rowptr), _ptr(colidx), _ptr(mvals), float(tau),
                                   float(delta), int(iters), _ptr(out), ldx, ctypes.byref(co), _ptr(resid),
-                                  ctypes.byref(k0)))
+                                  ctypes.byref(k0), _ptr(y_start), _ptr(y_end), _ptr(lambdas)))
     return out, k0.value
 
 

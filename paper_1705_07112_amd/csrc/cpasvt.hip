@@ -811,6 +811,7 @@ struct SpWork {
     double* w[2];
     double* scal;
     float* yv;         // SVT iterate values (nnz), when requested
+    float* xv;         // SVT: observed entries of the shrink (nnz), when requested
     float* poly;       // matrix-polynomial route: poly_mats(K, s) matrices of n x n (or nullptr)
     int poly_s;
     ScalarLayout lay;
@@ -839,7 +840,11 @@ cpa_status ensure_sparse_ws(cpa_ctx* ctx, int m, int n, int64_t nnz, int K, int 
     const size_t os = off; off = align_up(off + sizeof(double) * (size_t)w.lay.total());
     const size_t ocv = off; off = align_up(off + sizeof(float) * (size_t)std::max<int64_t>(nnz, 1));
     size_t oy = 0;
-    if (svt) { oy = off; off = align_up(off + sizeof(float) * (size_t)std::max<int64_t>(nnz, 1)); }
+    size_t oxv = 0;
+    if (svt) {
+        oy = off; off = align_up(off + sizeof(float) * (size_t)std::max<int64_t>(nnz, 1));
+        oxv = off; off = align_up(off + sizeof(float) * (size_t)std::max<int64_t>(nnz, 1));
+    }
     size_t opl = 0;
     if (poly_s > 0) { opl = off; off = align_up(off + sizeof(float) * (size_t)poly_mats(K, poly_s) * n * n); }
     if (off > ctx->sws_bytes) {
@@ -867,6 +872,7 @@ cpa_status ensure_sparse_ws(cpa_ctx* ctx, int m, int n, int64_t nnz, int K, int 
     w.w[1] = reinterpret_cast<double*>(b + ow1);
     w.scal = reinterpret_cast<double*>(b + os);
     w.yv = svt ? reinterpret_cast<float*>(b + oy) : nullptr;
+    w.xv = svt ? reinterpret_cast<float*>(b + oxv) : nullptr;
     if (n > ctx->warm_cap) {
         if (ctx->warm) {
             HIP_TRY(hipDeviceSynchronize());
@@ -964,9 +970,11 @@ int sparse_poly_choice(const cpa_opts* o, int n) {
     return (s - 1 + J - 1 + 2) < 2 * (o->K - 1) ? s : 0;
 }
 
+// xv != nullptr (the SVT driver, matrix-polynomial route only): the observed
+// entries of the result go to xv (nnz, CSR order) and Y is not written.
 cpa_status shrink_csr_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t nnz, const int32_t* rowptr,
                            const int32_t* colidx, const float* val, float* Y, int64_t ldy,
-                           const cpa_shrinkage* sh, const cpa_opts* o, const SpWork& w) {
+                           const cpa_shrinkage* sh, const cpa_opts* o, const SpWork& w, float* xv = nullptr) {
     const int32_t* colptr = ctx->csc;
     const int32_t* crow = colptr + n + 1;
     const int32_t* csrc = crow + nnz;
@@ -1001,14 +1009,20 @@ cpa_status shrink_csr_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t n
                        to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)gpart, kSqGrid, 1, o->damping, 0, -1);
     HIP_TRY(hipGetLastError());
     if (mode == 0) ctx->warm_d = n;
-    // Y_0 = S densified
+    const bool poly = w.poly_s > 0 && o->K >= 2;
+    // the Gram by rows of S (no densified copy) when its LDS rows hold n floats
+    const bool row_gram = poly && n <= SPG_MAXN;
+    if (xv && !row_gram) return fail(CPA_ERR_ARG, "internal: observed-entry output needs the row-Gram route");
     const int64_t total = (int64_t)m * w.ld;
-    hipLaunchKernelGGL(fill_f32_kernel, dim3((int)std::min<int64_t>(8192, (total + 255) / 256)), dim3(256), 0, st,
-                       w.Y[0], total, 0.f);
-    HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(densify_kernel, dim3(std::min(m, 8192)), dim3(256), 0, st, m, rowptr, colidx, val, w.Y[0],
-                       w.ld);
-    HIP_TRY(hipGetLastError());
+    if (!row_gram) {
+        // Y_0 = S densified
+        hipLaunchKernelGGL(fill_f32_kernel, dim3((int)std::min<int64_t>(8192, (total + 255) / 256)), dim3(256), 0, st,
+                           w.Y[0], total, 0.f);
+        HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(densify_kernel, dim3(std::min(m, 8192)), dim3(256), 0, st, m, rowptr, colidx, val, w.Y[0],
+                           w.ld);
+        HIP_TRY(hipGetLastError());
+    }
     if (o->K == 1) {
         hipLaunchKernelGGL(scale_copy_kernel, dim3((int)std::min<int64_t>(4096, (total + 255) / 256)), dim3(256), 0,
                            st, m, n, (const float*)w.Y[0], w.ld, Y, ldy, (const double*)w.scal);
@@ -1020,17 +1034,28 @@ cpa_status shrink_csr_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t n
                            nnz, csrc, val, w.cval);
         HIP_TRY(hipGetLastError());
     }
-    if (w.poly_s > 0) {
-        // matrix-polynomial route: Gram S^T S (one sparse product with the densified S),
-        // the polynomial on the n x n side, then Y = S p
-        hipLaunchKernelGGL(spmm_t_kernel, dim3(((n + SP_WAVES - 1) / SP_WAVES) * ((n + SPT_J - 1) / SPT_J)),
-                           dim3(SP_THREADS), 0, st, n, n, colptr, crow, (const float*)w.cval, (const float*)w.Y[0],
-                           w.ld, w.W, w.ld);
+    if (poly) {
+        // matrix-polynomial route: Gram S^T S (by rows of S, or one sparse product with
+        // the densified S for n above the LDS rows), the polynomial on the n x n side,
+        // then Y = S p (or its observed entries)
+        if (row_gram)
+            hipLaunchKernelGGL(sp_gram_kernel, dim3(n), dim3(64 * SPG_WAVES), 0, st, n, colptr, crow,
+                               (const float*)w.cval, rowptr, colidx, val, w.W, w.ld);
+        else
+            hipLaunchKernelGGL(spmm_t_kernel, dim3(((n + SP_WAVES - 1) / SP_WAVES) * ((n + SPT_J - 1) / SPT_J)),
+                               dim3(SP_THREADS), 0, st, n, n, colptr, crow, (const float*)w.cval,
+                               (const float*)w.Y[0], w.ld, w.W, w.ld);
         HIP_TRY(hipGetLastError());
         float* F = nullptr;
         cpa_status r = enqueue_poly_core(ctx, st, n, w.W, w.ld, w.scal, w.lay.ps(), w.poly, w.poly_s, o->K,
                                          CPA_PREC_FP32, &F, false);
         if (r != CPA_OK) return r;
+        if (xv) {
+            hipLaunchKernelGGL(sp_sddmm_kernel, dim3(n), dim3(64 * SPS_WAVES), 0, st, n, colptr, crow, csrc, rowptr,
+                               colidx, val, (const float*)F, (int64_t)n, xv);
+            HIP_TRY(hipGetLastError());
+            return CPA_OK;
+        }
         hipLaunchKernelGGL(spmm_out_kernel, dim3(((m + SP_WAVES - 1) / SP_WAVES) * ((n + SPC_J - 1) / SPC_J)),
                            dim3(SP_THREADS), 0, st, m, n, rowptr, colidx, val, (const float*)F, (int64_t)n, Y, ldy,
                            aligned16(F, n) ? 1 : 0, aligned16(Y, ldy) ? 1 : 0);
@@ -1895,7 +1920,8 @@ cpa_status cpa_shrink_csr(cpa_ctx* ctx, void* stream, int m, int n, int64_t nnz,
 
 cpa_status cpa_svt_complete(cpa_ctx* ctx, void* stream, int m, int n, int64_t nnz, const int32_t* rowptr_dev,
                             const int32_t* colidx_dev, const float* Mobs_dev, double tau, double delta, int iters,
-                            float* X_dev, int64_t ldx, const cpa_opts* opts, double* resid_dev, double* k0_host) {
+                            float* X_dev, int64_t ldx, const cpa_opts* opts, double* resid_dev, double* k0_host,
+                            const float* Y0_vals_dev, float* Y_vals_dev, double* Lambda_dev) {
     cpa_status s;
     if ((s = check_csr_args(ctx, m, n, nnz, rowptr_dev, colidx_dev, Mobs_dev, X_dev, ldx)) != CPA_OK) return s;
     if (opts && opts->side == CPA_SIDE_LEFT) return fail(CPA_ERR_UNSUPPORTED, "sparse path forms S^T S (side right)");
@@ -1903,34 +1929,43 @@ cpa_status cpa_svt_complete(cpa_ctx* ctx, void* stream, int m, int n, int64_t nn
     if (opts->precision != CPA_PREC_FP32 || opts->check) return fail(CPA_ERR_UNSUPPORTED, "unsupported option");
     if (!(std::isfinite(tau) && tau >= 0.0 && std::isfinite(delta) && delta > 0.0) || iters < 0)
         return fail(CPA_ERR_ARG, "tau >= 0, delta > 0 and iters >= 0 required");
+    if (k0_host) *k0_host = 0.0;
     if (m == 0 || n == 0 || iters == 0) return CPA_OK;
+    if (Y_vals_dev && Y0_vals_dev && Y_vals_dev != Y0_vals_dev &&
+        overlaps(Y_vals_dev, sizeof(float) * nnz, Y0_vals_dev, sizeof(float) * nnz))
+        return fail(CPA_ERR_ARG, "Y_vals overlaps Y0_vals (pass the same buffer to update in place)");
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
     SpWork w;
     const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
-    if ((s = ensure_sparse_ws(ctx, m, n, nnz, opts->K, std::max(maxit, 200), true, w, sparse_poly_choice(opts, n))) !=
-        CPA_OK)
-        return s;
+    const int ps = sparse_poly_choice(opts, n);
+    if ((s = ensure_sparse_ws(ctx, m, n, nnz, opts->K, std::max(maxit, 200), true, w, ps)) != CPA_OK) return s;
     if ((s = ensure_csc(ctx, st, m, n, nnz, rowptr_dev, colidx_dev)) != CPA_OK) return s;
-    // k0 = ceil(tau / (delta ||P_Omega M||_2)) from a converged power iteration (one sync)
-    cpa_opts ob = *opts;
-    ob.bound = CPA_BOUND_POWER;
-    ob.power_iters = 200;
-    ob.power_tol = 1e-9;
-    ob.warm_start = 0;
-    ob.K = 1;
-    cpa_shrinkage s0 = {CPA_SOFT, 0, 0.0, 0.0, 0.0, 1.0};
-    if ((s = shrink_csr_impl(ctx, st, m, n, nnz, rowptr_dev, colidx_dev, Mobs_dev, X_dev, ldx, &s0, &ob, w)) != CPA_OK)
-        return s;
-    double mu = 0.0;
-    HIP_TRY(hipMemcpyAsync(&mu, w.scal + SC_MU, sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    const double nrm2 = std::sqrt(std::max(mu, 0.0));
-    const double k0 = nrm2 > 0.0 ? std::ceil(tau / (delta * nrm2)) : 1.0;
-    if (k0_host) *k0_host = k0;
     const int gv = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (nnz + 255) / 256));
-    hipLaunchKernelGGL(scale_vals_kernel, dim3(gv), dim3(256), 0, st, nnz, Mobs_dev, w.yv, (float)(k0 * delta));
-    HIP_TRY(hipGetLastError());
+    if (Y0_vals_dev) {
+        // continue from the caller's iterate
+        if (nnz > 0) HIP_TRY(hipMemcpyAsync(w.yv, Y0_vals_dev, sizeof(float) * nnz, hipMemcpyDeviceToDevice, st));
+    } else {
+        // k0 = ceil(tau / (delta ||P_Omega M||_2)) from a converged power iteration (one sync)
+        cpa_opts ob = *opts;
+        ob.bound = CPA_BOUND_POWER;
+        ob.power_iters = 200;
+        ob.power_tol = 1e-9;
+        ob.warm_start = 0;
+        ob.K = 1;
+        cpa_shrinkage s0 = {CPA_SOFT, 0, 0.0, 0.0, 0.0, 1.0};
+        if ((s = shrink_csr_impl(ctx, st, m, n, nnz, rowptr_dev, colidx_dev, Mobs_dev, X_dev, ldx, &s0, &ob, w)) !=
+            CPA_OK)
+            return s;
+        double mu = 0.0;
+        HIP_TRY(hipMemcpyAsync(&mu, w.scal + SC_MU, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const double nrm2 = std::sqrt(std::max(mu, 0.0));
+        const double k0 = nrm2 > 0.0 ? std::ceil(tau / (delta * nrm2)) : 1.0;
+        if (k0_host) *k0_host = k0;
+        hipLaunchKernelGGL(scale_vals_kernel, dim3(gv), dim3(256), 0, st, nnz, Mobs_dev, w.yv, (float)(k0 * delta));
+        HIP_TRY(hipGetLastError());
+    }
     // ||P_Omega M||_F for the residual normalisation (host, once)
     std::vector<float> hv(nnz);
     HIP_TRY(hipMemcpyAsync(hv.data(), Mobs_dev, sizeof(float) * nnz, hipMemcpyDeviceToHost, st));
@@ -1939,18 +1974,42 @@ cpa_status cpa_svt_complete(cpa_ctx* ctx, void* stream, int m, int n, int64_t nn
     for (float v : hv) nm += (double)v * v;
     nm = std::sqrt(nm);
     cpa_shrinkage sh = {CPA_SOFT, 0, tau, 0.0, 0.0, 1.0};
+    // iterations before the last need only the observed entries of X^t (on the
+    // matrix-polynomial route with the row Gram); the last one forms X^iters
+    const bool observed_only = ps > 0 && opts->K >= 2 && n <= SPG_MAXN;
     const int gu = std::min(m, 4096);
+    const int gvu = std::max(1, std::min(gv, gu));   // partials go to tvec (m doubles)
     for (int t = 0; t < iters; ++t) {
-        if ((s = shrink_csr_impl(ctx, st, m, n, nnz, rowptr_dev, colidx_dev, w.yv, X_dev, ldx, &sh, opts, w)) != CPA_OK)
-            return s;
-        // residual partials reuse the power-iteration vector buffer (m doubles >= gu)
-        hipLaunchKernelGGL(svt_update_kernel, dim3(gu), dim3(256), 0, st, m, rowptr_dev, colidx_dev, Mobs_dev,
-                           (const float*)X_dev, ldx, w.yv, (float)delta, w.tvec);
+        const bool last = t + 1 == iters;
+        if (observed_only && !last) {
+            if ((s = shrink_csr_impl(ctx, st, m, n, nnz, rowptr_dev, colidx_dev, w.yv, X_dev, ldx, &sh, opts, w,
+                                     w.xv)) != CPA_OK)
+                return s;
+            hipLaunchKernelGGL(svt_update_vals_kernel, dim3(gvu), dim3(256), 0, st, nnz, Mobs_dev, (const float*)w.xv,
+                               w.yv, (float)delta, w.tvec);
+            HIP_TRY(hipGetLastError());
+            hipLaunchKernelGGL(svt_resid_kernel, dim3(1), dim3(256), 0, st, (const double*)w.tvec, gvu, nm,
+                               resid_dev ? resid_dev + t : nullptr);
+        } else {
+            if ((s = shrink_csr_impl(ctx, st, m, n, nnz, rowptr_dev, colidx_dev, w.yv, X_dev, ldx, &sh, opts, w)) !=
+                CPA_OK)
+                return s;
+            // residual partials reuse the power-iteration vector buffer (m doubles >= gu)
+            hipLaunchKernelGGL(svt_update_kernel, dim3(gu), dim3(256), 0, st, m, rowptr_dev, colidx_dev, Mobs_dev,
+                               (const float*)X_dev, ldx, w.yv, (float)delta, w.tvec);
+            HIP_TRY(hipGetLastError());
+            hipLaunchKernelGGL(svt_resid_kernel, dim3(1), dim3(256), 0, st, (const double*)w.tvec, gu, nm,
+                               resid_dev ? resid_dev + t : nullptr);
+        }
         HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(svt_resid_kernel, dim3(1), dim3(256), 0, st, (const double*)w.tvec, gu, nm,
-                           resid_dev ? resid_dev + t : nullptr);
-        HIP_TRY(hipGetLastError());
+        if (Lambda_dev) {
+            hipLaunchKernelGGL(copy_f64_kernel, dim3(1), dim3(64), 0, st, (const double*)(w.scal + SC_LAMBDA),
+                               Lambda_dev + t);
+            HIP_TRY(hipGetLastError());
+        }
     }
+    if (Y_vals_dev && nnz > 0)
+        HIP_TRY(hipMemcpyAsync(Y_vals_dev, w.yv, sizeof(float) * nnz, hipMemcpyDeviceToDevice, st));
     return CPA_OK;
 }
 

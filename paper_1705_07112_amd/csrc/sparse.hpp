@@ -43,15 +43,24 @@ constexpr int SPT_J = 32;                   // panel width of S^T Y_k
 constexpr int SPC_J = 128;                  // panel width of S W
 
 // Flags a malformed CSR (rowptr[0] != 0, rowptr[m] != nnz, decreasing row
-// pointers, or a column index outside [0, n)).  Reads only rowptr[0..m] and
-// colidx[0..nnz).
+// pointers, a column index outside [0, n), or columns of a row not strictly
+// increasing).  Reads only rowptr[0..m] and colidx[0..nnz) (row extents are
+// clamped to [0, nnz] before a row's columns are read).
 __global__ void csr_validate_kernel(int m, int n, int64_t nnz, const int32_t* rowptr, const int32_t* colidx,
                                     int* bad) {
     const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     if (tid == 0 && (rowptr[0] != 0 || rowptr[m] != nnz)) atomicOr(bad, 1);
-    for (int64_t r = tid; r < m; r += stride)
-        if (rowptr[r] > rowptr[r + 1]) atomicOr(bad, 1);
+    for (int64_t r = tid; r < m; r += stride) {
+        const int64_t lo = rowptr[r], hi = rowptr[r + 1];
+        if (lo > hi) atomicOr(bad, 1);
+        const int64_t a = lo < 0 ? 0 : (lo > nnz ? nnz : lo), z = hi < 0 ? 0 : (hi > nnz ? nnz : hi);
+        for (int64_t e = a + 1; e < z; ++e)
+            if (colidx[e] <= colidx[e - 1]) {
+                atomicOr(bad, 1);
+                break;
+            }
+    }
     for (int64_t e = tid; e < nnz; e += stride)
         if (colidx[e] < 0 || colidx[e] >= n) atomicOr(bad, 1);
 }
@@ -486,6 +495,130 @@ __global__ void svt_resid_kernel(const double* part, int np, double normM, doubl
     for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
     s = block_sum(s, red);
     if (threadIdx.x == 0 && resid_out) *resid_out = normM > 0.0 ? sqrt(s) / normM : 0.0;
+}
+
+// ---- the matrix-polynomial route without the densified S -----------------------
+//
+// sp_gram_kernel   G = S^T S by rows of S: row i of G is the sum, over the rows r
+//                  of column i of S, of s_ri times row r of S (nnz_r entries), i.e.
+//                  sum_r nnz_r^2 products instead of the 2 nnz n of a product with
+//                  the densified S.  One workgroup per row i of G; the column's
+//                  rows are split into SPG_WAVES contiguous runs, each wave adds its
+//                  run's scaled rows in ascending row order into its own LDS copy of
+//                  the output row (the entries of one row of S have distinct
+//                  columns, so the lanes' read-modify-writes never collide) and the
+//                  copies are added in wave order: the sum order is fixed.
+// sp_sddmm_kernel  the observed entries of S p, (S p)[r][c] for (r, c) in the
+//                  pattern: the sum over row r of S of s_rk p[c][k] -- row c of p,
+//                  as the dense route's last product reads p (p is a polynomial in
+//                  the symmetric Gram, so p = p^T in exact arithmetic).  One
+//                  workgroup per column c with row c of p staged in LDS; the
+//                  column's rows go four to a wave (16 lanes each), partial sums
+//                  added by xor shuffles.  Output in CSR order (through csrc).
+constexpr int SPG_WAVES = 2;
+constexpr int SPS_WAVES = 4;
+constexpr int SPG_MAXN = 4096;   // the LDS rows of both kernels hold n floats
+
+__global__ void __launch_bounds__(64 * SPG_WAVES) sp_gram_kernel(int n, const int32_t* colptr, const int32_t* crow,
+                                                                 const float* cval, const int32_t* rowptr,
+                                                                 const int32_t* colidx, const float* val, float* G,
+                                                                 int64_t ldg) {
+    __shared__ float acc[SPG_WAVES][SPG_MAXN];
+    const int i = blockIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float* a_row = acc[wave];
+    for (int j = lane; j < n; j += 64) a_row[j] = 0.f;
+    const int32_t b = colptr[i], len = colptr[i + 1] - b;
+    const int32_t chunk = (len + SPG_WAVES - 1) / SPG_WAVES;
+    const int32_t lo = b + min(len, wave * chunk), hi = b + min(len, (wave + 1) * chunk);
+    for (int32_t p0 = lo; p0 < hi; p0 += 64) {
+        const int cnt = min(64, hi - p0);
+        // lane l holds the scale and the extent of the batch's row l
+        float a_l = 0.f;
+        int32_t rb_l = 0, re_l = 0;
+        if (lane < cnt) {
+            const int32_t r = crow[p0 + lane];
+            a_l = cval[p0 + lane];
+            rb_l = rowptr[r];
+            re_l = rowptr[r + 1];
+        }
+        // the first 128 entries of the next row are loaded while the current one is added
+        int32_t rb = __shfl(rb_l, 0, 64), re = __shfl(re_l, 0, 64);
+        int32_t c0 = 0, c1 = 0;
+        float v0 = 0.f, v1 = 0.f;
+        if (rb + lane < re) { c0 = colidx[rb + lane]; v0 = val[rb + lane]; }
+        if (rb + 64 + lane < re) { c1 = colidx[rb + 64 + lane]; v1 = val[rb + 64 + lane]; }
+        for (int q = 0; q < cnt; ++q) {
+            const float a = __shfl(a_l, q, 64);
+            const int32_t qb = rb, qe = re;
+            const int32_t qc0 = c0, qc1 = c1;
+            const float qv0 = v0, qv1 = v1;
+            if (q + 1 < cnt) {
+                rb = __shfl(rb_l, q + 1, 64);
+                re = __shfl(re_l, q + 1, 64);
+                c0 = c1 = 0;
+                v0 = v1 = 0.f;
+                if (rb + lane < re) { c0 = colidx[rb + lane]; v0 = val[rb + lane]; }
+                if (rb + 64 + lane < re) { c1 = colidx[rb + 64 + lane]; v1 = val[rb + 64 + lane]; }
+            }
+            if (qb + lane < qe) a_row[qc0] += a * qv0;
+            if (qb + 64 + lane < qe) a_row[qc1] += a * qv1;
+            for (int32_t e = qb + 128 + lane; e < qe; e += 64) a_row[colidx[e]] += a * val[e];
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += 64 * SPG_WAVES) {
+        float sum = acc[0][j];
+        for (int w = 1; w < SPG_WAVES; ++w) sum += acc[w][j];
+        G[(int64_t)i * ldg + j] = sum;
+    }
+}
+
+__global__ void __launch_bounds__(64 * SPS_WAVES) sp_sddmm_kernel(int n, const int32_t* colptr, const int32_t* crow,
+                                                                  const int32_t* csrc, const int32_t* rowptr,
+                                                                  const int32_t* colidx, const float* val,
+                                                                  const float* F, int64_t ldf, float* out) {
+    __shared__ float fr[SPG_MAXN];
+    const int c = blockIdx.x;
+    for (int j = threadIdx.x; j < n; j += 64 * SPS_WAVES) fr[j] = F[(int64_t)c * ldf + j];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, q = lane & 15;
+    const int32_t b = colptr[c], end = colptr[c + 1];
+    for (int32_t base = b + 4 * wave; base < end; base += 4 * SPS_WAVES) {
+        const int32_t p = base + g;
+        const bool valid = p < end;
+        float sum = 0.f;
+        if (valid) {
+            const int32_t r = crow[p];
+            const int32_t re = rowptr[r + 1];
+            for (int32_t e = rowptr[r] + q; e < re; e += 16) sum += val[e] * fr[colidx[e]];
+        }
+        sum += __shfl_xor(sum, 8, 64);
+        sum += __shfl_xor(sum, 4, 64);
+        sum += __shfl_xor(sum, 2, 64);
+        sum += __shfl_xor(sum, 1, 64);
+        if (valid && q == 0) out[csrc[p]] = sum;
+    }
+}
+
+// SVT update from the observed values of X (CSR order): r_e = M_e - Xv_e,
+// Yv_e += delta r_e, per-workgroup partial sums of r^2 (grid-stride, fixed grid).
+__global__ void svt_update_vals_kernel(int64_t nnz, const float* Mv, const float* Xv, float* Yv, float delta,
+                                       double* part) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+        const float res = Mv[e] - Xv[e];
+        Yv[e] += delta * res;
+        s += (double)res * res;
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// dst[t] = src[0] (the bound of an iteration copied into a caller's history).
+__global__ void copy_f64_kernel(const double* src, double* dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
 }
 
 __global__ void scale_vals_kernel(int64_t nnz, const float* src, float* dst, float f) {

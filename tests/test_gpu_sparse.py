@@ -164,3 +164,78 @@ def test_csr_damped_coefficients_match_oracle():
                      cpa.Opts(K=K, Lambda=Lam, eval=ev, damping="jackson")).cpu().numpy()
         ref = ocpa.cpa_shrink(S, Shrinkage(1, tau), Lam, K, damping="jackson")
         parity.check(Y, ref, TOL32, S, f"csr damped {ev}")
+
+
+def _svt_problem(m, n, r, frac, seed):
+    g = synth.rng(seed)
+    M = g.standard_normal((m, r)) @ g.standard_normal((r, n))
+    idx = np.sort(g.choice(m * n, size=int(frac * m * n), replace=False))
+    rows, cols = idx // n, idx % n
+    vals = M[rows, cols].astype(np.float32)
+    rowptr = np.zeros(m + 1, dtype=np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr).astype(np.int32)
+    return M, rows, cols, vals, rowptr
+
+
+@pytest.mark.parametrize("ev", ["auto", "recurrence"])
+def test_svt_iterations_from_the_gpu_state(ev):
+    """Gated like the ADMM driver: the GPU's own iterate Y^t (on the observed set)
+    after five iterations, then one and two more iterations continued from it;
+    the oracle applies its shrink to the same Y^t at the bounds the GPU reports
+    and the SVT update, and X (whole matrix) and Y (observed set) must agree to
+    the FP32 tolerance.  On the matrix-polynomial route the first of the two
+    iterations forms only the observed entries of X."""
+    import torch
+    import paper_1705_07112_amd as cpa
+    m, n, K = 600, 200, 25
+    M, rows, cols, vals, rowptr = _svt_problem(m, n, 3, 0.2, 20700)
+    tau, step = 5 * math.sqrt(m * n), 1.2 * m * n / len(vals)
+    r_d = torch.from_numpy(rowptr).cuda()
+    c_d = torch.from_numpy(cols.astype(np.int32)).cuda()
+    v_d = torch.from_numpy(vals).cuda()
+    opts = cpa.Opts(K=K, warm_start=True, eval=ev)
+    y5 = torch.empty(len(vals), dtype=torch.float32, device="cuda")
+    cpa.svt_complete(m, n, r_d, c_d, v_d, tau, step, 5, opts, y_end=y5)
+    Y5 = np.zeros((m, n))
+    Y5[rows, cols] = y5.cpu().numpy()
+    sh = Shrinkage(0, tau)
+    for extra in (1, 2):
+        lam = torch.zeros(extra, dtype=torch.float64, device="cuda")
+        yend = torch.empty_like(y5)
+        X, _ = cpa.svt_complete(m, n, r_d, c_d, v_d, tau, step, extra, opts, y_start=y5, y_end=yend, lambdas=lam)
+        torch.cuda.synchronize()
+        Yo = Y5.copy()
+        for t in range(extra):
+            Xo = ocpa.cpa_shrink(Yo, sh, float(lam[t].item()), K)
+            Yo[rows, cols] += step * (vals.astype(np.float64) - Xo[rows, cols])
+        parity.check(X.cpu().numpy(), Xo, TOL32, label=f"svt X after {extra} from Y^5 ({ev})")
+        parity.check(yend.cpu().numpy(), Yo[rows, cols], TOL32, label=f"svt Y on the observed set ({ev})")
+
+
+def test_csr_polynomial_route_above_the_lds_rows():
+    """n = 4100 > 4096: the Gram falls back to the product with the densified S
+    (the row kernel's LDS rows hold 4096 floats); sampled rows against the oracle."""
+    import scipy.sparse as sp
+    import torch
+    import paper_1705_07112_amd as cpa
+    m, n = 4300, 4100
+    rowptr, cols, vals, _ = _random_csr(m, n, 0.002, 20800)
+    S = sp.csr_matrix((vals.astype(np.float64), cols, rowptr), shape=(m, n))
+    G = (S.T @ S).toarray()
+    lam = 1.01 * float(np.linalg.eigvalsh(G)[-1])
+    tau = 0.3 * math.sqrt(lam)
+    Y = _gpu_csr(m, n, rowptr, cols, vals, cpa.soft(tau), cpa.Opts(K=16, Lambda=lam, eval="polynomial"))
+    rsel = np.r_[0:4, 2150, 4296:4300]
+    got = Y[torch.from_numpy(rsel).cuda()].cpu().numpy().astype(np.float64)
+    ref = ocpa.cpa_rows_yform(G, S[rsel].toarray(), Shrinkage(0, tau), lam, 16)
+    parity.check(got, ref, TOL32, label="csr n=4100 polynomial (densified Gram)")
+
+
+def test_csr_rejects_unsorted_or_repeated_columns():
+    import paper_1705_07112_amd as cpa
+    for cols in ([2, 1, 3], [1, 1, 3]):
+        rowptr = np.array([0, 3, 3, 3, 3], dtype=np.int32)
+        with pytest.raises(cpa.CpaError) as e:
+            _gpu_csr(4, 4, rowptr, np.array(cols, np.int32), np.ones(3, np.float32), cpa.soft(0.1), cpa.Opts(K=5))
+        assert e.value.status == cpa.ERR_ARG
