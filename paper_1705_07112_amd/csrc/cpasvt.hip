@@ -329,11 +329,19 @@ bool vec_operand(const Operand& o, int layout, int Kd) {
     return aligned16(o.p, o.ld) && run % 4 == 0 && run >= 4;
 }
 
+// Workgroups of a product: every tile, or the upper-triangle tiles of a
+// symmetric one (M == N).
+template <class Epi>
+int gemm_grid(int ntm, int ntn, const Epi& epi) {
+    return epi_sym(epi) ? ntm * (ntm + 1) / 2 : ntm * ntn;
+}
+
 template <int BM, int BN, int LA, int LB, class Epi>
 cpa_status launch_gemm(hipStream_t st, const Operand& A, const Operand& B, int M, int N, int Kd, const Epi& epi,
                        int sc_a1, int sc_a2, int sc_coef) {
     const int ntm = (M + BM - 1) / BM, ntn = (N + BN - 1) / BN;
-    const int grid = ntm * ntn;
+    if (epi_sym(epi) && M != N) return fail(CPA_ERR_ARG, "internal: a symmetric product must be square");
+    const int grid = gemm_grid(ntm, ntn, epi);
     if (grid <= 0 || Kd <= 0) return CPA_OK;
     if (vec_operand(A, LA, Kd) && vec_operand(B, LB, Kd))
         hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, LA, LB, true, Epi>), dim3(grid), dim3(GTHREADS), 0, st, A, B, M,
@@ -348,6 +356,7 @@ cpa_status launch_gemm(hipStream_t st, const Operand& A, const Operand& B, int M
 template <int LA, int LB, class Epi>
 cpa_status launch_gemm_split(hipStream_t st, const Operand& A, const Operand& B, int M, int N, int Kd,
                              const Epi& epi, int sc_a1, int sc_a2, int sc_coef) {
+    if (epi_sym(epi)) return fail(CPA_ERR_ARG, "internal: the split-precision products have no symmetric mode");
     const int grid = ((M + 63) / 64) * ((N + 63) / 64);
     if (grid <= 0 || Kd <= 0) return CPA_OK;
     if (vec_operand(A, LA, Kd) && vec_operand(B, LB, Kd))
@@ -377,7 +386,8 @@ cpa_status gemm_dispatch(hipStream_t st, const Operand& A, const Operand& B, int
     // the Chebyshev and Gram epilogues run faster on the register-staged kernel)
     if constexpr (LA == KCONTIG && LB == KCONTIG && std::is_same<Epi, EpiLin>::value) {
         if (lds_pipeline_ok(A, B, M, N, Kd)) {
-            const int grid = (M / 64) * (N / 64);
+            if (epi_sym(epi) && M != N) return fail(CPA_ERR_ARG, "internal: a symmetric product must be square");
+            const int grid = gemm_grid(M / 64, N / 64, epi);
             hipLaunchKernelGGL((gemm_f32_lds_kernel<64, 64, Epi, 16>), dim3(grid), dim3(1024), 0, st, A, B, M, N, Kd,
                                epi, sc_a1, sc_a2, sc_coef);
             HIP_TRY(hipGetLastError());
@@ -652,9 +662,23 @@ EpiLin lin_epi(float* D, int64_t ldd, const float* Mx, int64_t ldm, float alpha,
 
 // The polynomial p(Ghat) (d x d, pitch d) from the Gram G (pitch ldg) and the
 // coefficients in scal; `poly` holds poly_mats(K, s) matrices of d x d.  Returns p's buffer.
+// The upper-triangle (symmetric) products pay when they take fewer rounds of
+// 64 x 64 tiles over the CUs than the full ones: not at d = 1024 (136 against
+// 256 tiles, one round either way on 256 CUs), from d = 1088 on.
+bool sym_pays(cpa_ctx* ctx, int d) {
+    if (ctx->cus == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) return false;
+        ctx->cus = std::max(1, cus);
+    }
+    const int64_t nt = (d + 63) / 64, full = nt * nt, tri = nt * (nt + 1) / 2, c = ctx->cus;
+    return (tri + c - 1) / c < (full + c - 1) / c;
+}
+
 cpa_status enqueue_poly_core(cpa_ctx* ctx, hipStream_t st, int d, const float* G, int64_t ldg, double* scal,
                              int roff, float* poly, int s, int K, int precision, float** F_out, bool coeff_ready) {
     const int J = (K + s - 1) / s;
+    const int sym = precision == CPA_PREC_FP32 && sym_pays(ctx, d) ? 1 : 0;
     const int64_t dd = (int64_t)d * d;
     float* T1 = poly;                         // T_q at T1 + (q - 1) dd, q = 1..s
     float* R = poly + (int64_t)s * dd;        // R_j at R + j dd
@@ -672,6 +696,7 @@ cpa_status enqueue_poly_core(cpa_ctx* ctx, hipStream_t st, int d, const float* G
     for (int i = 1; i < s; ++i) {
         EpiLin e = lin_epi(Tq(i + 1), d, i > 1 ? Tq(i - 1) : nullptr, d, 2.f, 0.f, i > 1 ? -1.f : 0.f,
                            i > 1 ? 0.f : -1.f);
+        e.sym = sym;
         if ((r = poly_gemm(ctx, st, make_op(Tq(i), d, d), make_op(T1, d, d), d, d, d, e, precision, true)) != CPA_OK)
             return r;
     }
@@ -696,6 +721,7 @@ cpa_status enqueue_poly_core(cpa_ctx* ctx, hipStream_t st, int d, const float* G
                 break;
             }
         EpiLin e = lin_epi(dst, d, prev, d, j > 0 ? 2.f : 1.f, 1.f, prev ? -1.f : 0.f, 0.f);
+        e.sym = sym;
         e.C = R + (int64_t)j * dd;
         e.ldc = d;
         e.vec_ok = e.vec_ok && aligned16(e.C, d);

@@ -205,6 +205,39 @@ __device__ inline void tile_coords(int ntm, int ntn, int& tm, int& tn) {
     tn = r / rows;
 }
 
+// Upper-triangle tiles (tm <= tn) of a square product whose result is symmetric,
+// in bands of GM tile rows: each band's tiles column by column (its first GM
+// columns are triangular), bands in order; the XCD interleave of tile_coords is
+// applied to the linear index first.  nt (nt + 1) / 2 workgroups.
+__device__ inline void tile_coords_sym(int nt, int& tm, int& tn) {
+    const int T = nt * (nt + 1) / 2;
+    int t = blockIdx.x;
+    if (T % 8 == 0) t = (t % 8) * (T / 8) + t / 8;
+    constexpr int GM = 4;
+    int first = 0;
+    tm = tn = 0;
+    while (first < nt) {
+        const int rows = min(GM, nt - first);
+        const int tri = rows * (rows + 1) / 2;
+        const int cnt = tri + rows * (nt - first - rows);
+        if (t < cnt) {
+            if (t < tri) {
+                int k = 0;
+                while ((k + 1) * (k + 2) / 2 <= t) ++k;
+                tn = first + k;
+                tm = first + (t - k * (k + 1) / 2);
+            } else {
+                const int r = t - tri;
+                tn = first + rows + r / rows;
+                tm = first + r % rows;
+            }
+            return;
+        }
+        t -= cnt;
+        first += rows;
+    }
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -401,12 +434,29 @@ struct EpiLin {
     int64_t ldm;
     float alpha, beta, gamma, delta;
     bool vec_ok;
+    // sym: the product is square and its result symmetric (a polynomial in one
+    // symmetric matrix); the grid covers the upper-triangle tiles only
+    // (tile_coords_sym), C and Mx are read there, and each result tile is written
+    // twice, as itself and mirrored, a diagonal tile from its upper half: D comes
+    // out exactly symmetric
+    int sym = 0;
 
     template <int BM, int BN, int NG>
-    __device__ inline void run(const float* tile, int m0, int n0, int M, int N, const double*, int, int, int) const {
+    __device__ inline void run(float* tile, int m0, int n0, int M, int N, const double* sc, int a1, int a2,
+                               int cf) const {
+        if (sym) {
+            run_sym<BM, BN, NG>(tile, m0, n0, M);
+            return;
+        }
+        run_plain<BM, BN, NG>(tile, m0, n0, M, N);
+    }
+
+    // o = alpha acc + beta C + gamma Mx + delta I of the thread's float4 groups
+    template <int BM, int BN, int NG>
+    __device__ inline void values(const float* tile, int m0, int n0, int M, int N, f32x4 (&o)[NG],
+                                  bool (&full)[NG]) const {
         constexpr int P = BN + 4, GPR = BN / 4;
         f32x4 vd[NG], vm[NG];
-        bool full[NG];
 #pragma unroll
         for (int q = 0; q < NG; ++q) {
             const int g = threadIdx.x + q * GTHREADS;
@@ -431,19 +481,65 @@ struct EpiLin {
             const int r = g / GPR, cc = (g % GPR) * 4;
             const int i = m0 + r, j = n0 + cc;
             const f32x4 acc = *reinterpret_cast<const f32x4*>(tile + r * P + cc);
-            f32x4 o;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 float v = alpha * acc[e] + beta * vd[q][e] + gamma * vm[q][e];
                 if (i == j + e) v += delta;
-                o[e] = v;
+                o[q][e] = v;
             }
-            if (full[q]) {
-                *reinterpret_cast<f32x4*>(D + (int64_t)i * ldd + j) = o;
-            } else if (i < M) {
-                for (int e = 0; e < 4; ++e)
-                    if (j + e < N) D[(int64_t)i * ldd + j + e] = o[e];
+        }
+    }
+
+    __device__ inline void store4(int i, int j, int M, int N, bool vec, const f32x4& v) const {
+        if (i >= M) return;
+        if (vec && j + 3 < N) {
+            *reinterpret_cast<f32x4*>(D + (int64_t)i * ldd + j) = v;
+        } else {
+            for (int e = 0; e < 4; ++e)
+                if (j + e < N) D[(int64_t)i * ldd + j + e] = v[e];
+        }
+    }
+
+    template <int BM, int BN, int NG>
+    __device__ inline void run_sym(float* tile, int m0, int n0, int M) const {
+        constexpr int P = BN + 4, GPR = BN / 4;
+        f32x4 o[NG];
+        bool full[NG];
+        values<BM, BN, NG>(tile, m0, n0, M, M, o, full);
+        __syncthreads();   // every accumulator is read before the tile is overwritten
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+            const int g = threadIdx.x + q * GTHREADS;
+            *reinterpret_cast<f32x4*>(tile + (g / GPR) * P + (g % GPR) * 4) = o[q];
+        }
+        __syncthreads();
+        const bool diag = m0 == n0;
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+            const int g = threadIdx.x + q * GTHREADS;
+            const int r = g / GPR, cc = (g % GPR) * 4;
+            f32x4 v, w;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int c = cc + e;
+                v[e] = (!diag || r <= c) ? tile[r * P + c] : tile[c * P + r];
+                w[e] = tile[c * P + r];
             }
+            store4(m0 + r, n0 + cc, M, M, vec_ok, v);
+            if (!diag) store4(n0 + r, m0 + cc, M, M, vec_ok, w);
+        }
+    }
+
+    template <int BM, int BN, int NG>
+    __device__ inline void run_plain(const float* tile, int m0, int n0, int M, int N) const {
+        constexpr int GPR = BN / 4;
+        f32x4 o[NG];
+        bool full[NG];
+        values<BM, BN, NG>(tile, m0, n0, M, N, o, full);
+#pragma unroll
+        for (int q = 0; q < NG; ++q) {
+            const int g = threadIdx.x + q * GTHREADS;
+            store4(m0 + g / GPR, n0 + (g % GPR) * 4, M, N, vec_ok, o[q]);
         }
     }
 };
@@ -451,6 +547,20 @@ struct EpiLin {
 __device__ inline const double* epi_scal(const EpiLin&) { return nullptr; }
 __device__ inline const double* epi_scal(const EpiGram&) { return nullptr; }
 __device__ inline const double* epi_scal(const EpiCheb& e) { return e.scal; }
+// The symmetric tile order applies to linear-epilogue products flagged sym.
+template <class E>
+__host__ __device__ inline bool epi_sym(const E&) { return false; }
+template <>
+__host__ __device__ inline bool epi_sym<EpiLin>(const EpiLin& e) { return e.sym != 0; }
+
+// Tile of this workgroup: the upper-triangle order for symmetric products.
+template <class E>
+__device__ inline void tile_of(const E& epi, int ntm, int ntn, int& tm, int& tn) {
+    if (epi_sym(epi))
+        tile_coords_sym(ntm, tm, tn);
+    else
+        tile_coords(ntm, ntn, tm, tn);
+}
 
 // Wave layout: WM x WN waves over the output tile, times KS waves that split
 // each K-tile's sub-steps between them (their partial sums are added once,
@@ -542,7 +652,7 @@ __global__ void __launch_bounds__(GTHREADS) gemm_f32_kernel(Operand A, Operand B
     const int ntm = (M + BM - 1) / BM;
     const int ntn = (N + BN - 1) / BN;
     int tm, tn;
-    tile_coords(ntm, ntn, tm, tn);
+    tile_of(epi, ntm, ntn, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
 
     const int lane = threadIdx.x & 63;

@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(64 * NW) gemm_f32_lds_kernel(Operand A, Operan
     const int ntm = M / BM;
     const int ntn = N / BN;
     int tm, tn;
-    tile_coords(ntm, ntn, tm, tn);
+    tile_of(epi, ntm, ntn, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
 
     const int lane = threadIdx.x & 63;

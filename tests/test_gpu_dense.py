@@ -377,3 +377,20 @@ def test_frobenius_bound_without_margin_on_rpca_frames(ev):
     assert abs(info["Lambda"] - Lam) <= 1e-6 * Lam
     ref2 = ocpa.cpa_shrink(X, Shrinkage(0, 10.0), info["Lambda"], 30)
     parity.check(Y2.cpu().numpy(), ref2, TOL32, X, f"device Frobenius rule {ev}")
+
+
+@pytest.mark.parametrize("shape", [(1400, 1344), (1300, 1300), (1250, 1400)])
+def test_polynomial_route_symmetric_products(shape):
+    """Gram sides above 1024: the matrix polynomial's products cover only the
+    upper-triangle tiles and write each tile mirrored (d = 1344 through the
+    direct-to-LDS kernel; 1300 and the left side, d = 1250, through the
+    register-staged one), against the oracle at two orders."""
+    m, n = shape
+    cpa = _lib()
+    X = synth.as_f32_exact(synth.dense_lowrank(m, n, rank=6, noise=0.2, seed=7300 + m + n))
+    lmax = _gram_lmax(X)
+    Lam, tau = 1.01 * lmax, 0.4 * math.sqrt(lmax)
+    for K in (9, 30):
+        got, info = _run(X, cpa.soft(tau), K, Lam, ev="polynomial")
+        ref = ocpa.cpa_shrink(X, Shrinkage(0, tau), Lam, K)
+        parity.check(got, ref, TOL32, X, f"symmetric products {m}x{n} K={K}")
