@@ -104,8 +104,8 @@ typedef enum { CPA_PREC_FP32 = 0, CPA_PREC_BF16X3 = 1, CPA_PREC_FP64 = 2 } cpa_p
  *                        the recurrence (s = ceil(sqrt K), at most 16), then
  *                        p = sum_j R_j T_j(T_s) by Clenshaw's recurrence, using
  *                        T_j(T_s(x)) = T_{js}(x): about 2 sqrt(K) products of d x d x d.
- *                        Same polynomial; rounding differs.  K <= 256; not with check = 1.
- *   CPA_EVAL_AUTO        POLYNOMIAL when check = 0, K <= 256 and it costs fewer flops,
+ *                        Same polynomial; rounding differs.  K <= 256.
+ *   CPA_EVAL_AUTO        POLYNOMIAL when K <= 256 and it costs fewer flops,
  *                        otherwise RECURRENCE. */
 typedef enum { CPA_EVAL_AUTO = 0, CPA_EVAL_RECURRENCE = 1, CPA_EVAL_POLYNOMIAL = 2 } cpa_eval;
 
@@ -132,8 +132,14 @@ typedef struct {
     double power_tol;     /* relative tolerance on successive Rayleigh quotients */
     double margin;        /* relative margin delta added to the Rayleigh quotient */
     uint64_t seed;        /* start-vector seed */
-    int32_t check;        /* 1: growth check max_k ||Y_k||_F / ||X||_F <= 1 + growth_tol, with one
-                             recompute at Lambda = ||Gram||_F on failure (synchronises the stream) */
+    int32_t check;        /* 1: a-posteriori check of the bound (consequence of |T_k| <= 1 on
+                             [-1, 1], Sec. II-B), with one recompute at Lambda = ||Gram||_F on
+                             failure (synchronises the stream).  Recurrence route: the growth
+                             max_k ||Y_k||_F / ||X||_F <= 1 + growth_tol.  Matrix-polynomial
+                             route: the Gram-weighted means of the baby steps,
+                             max_{q=2..s} <Gram, T_q(Ghat)>_F / tr Gram <= 1 + growth_tol
+                             (= sum_i lambda_i T_q(x_i) / sum_i lambda_i, at most 1 when every
+                             eigenvalue maps into [-1, 1]) */
     int32_t precision;    /* cpa_precision */
     double growth_tol;    /* tolerance of the growth check */
     int32_t eval;         /* cpa_eval (dense and sparse paths; the batched path uses the recurrence) */
@@ -151,10 +157,11 @@ typedef struct {
     double mu;            /* last Rayleigh quotient (0 unless CPA_BOUND_POWER) */
     double resid;         /* last residual norm ||Gram v - mu v|| */
     double fro_gram;      /* ||Gram||_F */
-    double max_growth;    /* max_k ||Y_k||_F / ||X||_F over k = 1..K-1 (0 if K == 1 or when the
-                             matrix-polynomial route ran: it never forms Y_k) */
+    double max_growth;    /* recurrence route: max_k ||Y_k||_F / ||X||_F over k = 1..K-1 (0 if
+                             K == 1); matrix-polynomial route: the check's largest weighted
+                             mean when check = 1, else 0 */
     int32_t power_iters_done;
-    int32_t fallback;     /* 1 when the growth check forced Lambda = ||Gram||_F */
+    int32_t fallback;     /* 1 when the check forced Lambda = ||Gram||_F */
     int32_t side;         /* 0: Gram = X^T X (right side), 1: Gram = X X^T (left side) */
     int32_t reserved;
 } cpa_info;

@@ -432,8 +432,6 @@ cpa_status check_opts(const cpa_opts* o) {
     if (o->precision != CPA_PREC_FP32 && o->precision != CPA_PREC_BF16X3)
         return fail(CPA_ERR_UNSUPPORTED, "precision %d not supported", o->precision);
     if (o->eval < CPA_EVAL_AUTO || o->eval > CPA_EVAL_POLYNOMIAL) return fail(CPA_ERR_ARG, "unknown eval %d", o->eval);
-    if (o->eval == CPA_EVAL_POLYNOMIAL && o->check)
-        return fail(CPA_ERR_UNSUPPORTED, "the growth check needs the recurrence (eval AUTO or RECURRENCE)");
     if (o->eval == CPA_EVAL_POLYNOMIAL && o->K > 256)
         return fail(CPA_ERR_UNSUPPORTED, "the matrix-polynomial route supports K <= 256");
     if (o->side < CPA_SIDE_AUTO || o->side > CPA_SIDE_LEFT) return fail(CPA_ERR_ARG, "unknown side %d", o->side);
@@ -618,7 +616,6 @@ int poly_choice(const cpa_opts* o, int m, int n) {
     if (o->K < 2 || o->K > kPolyMaxK || o->eval == CPA_EVAL_RECURRENCE) return 0;
     const int s = poly_s_of(o->K), J = (o->K + s - 1) / s;
     if (o->eval == CPA_EVAL_POLYNOMIAL) return s;
-    if (o->check) return 0;   // the growth check needs every ||Y_k||
     const bool right = right_side(o, m, n);
     const double d = right ? n : m, e = right ? m : n;
     const double cost_poly = (double)(s - 1 + J - 1) * d * d * d + e * d * d;
@@ -675,8 +672,11 @@ bool sym_pays(cpa_ctx* ctx, int d) {
     return (tri + c - 1) / c < (full + c - 1) / c;
 }
 
+// check_off >= 0: after the baby steps, the Gram-weighted means of T_2..T_s go
+// to the scalar block at check_off (ps_check_kernel).
 cpa_status enqueue_poly_core(cpa_ctx* ctx, hipStream_t st, int d, const float* G, int64_t ldg, double* scal,
-                             int roff, float* poly, int s, int K, int precision, float** F_out, bool coeff_ready) {
+                             int roff, float* poly, int s, int K, int precision, float** F_out, bool coeff_ready,
+                             int check_off = -1) {
     const int J = (K + s - 1) / s;
     const int sym = precision == CPA_PREC_FP32 && sym_pays(ctx, d) ? 1 : 0;
     const int64_t dd = (int64_t)d * d;
@@ -699,6 +699,11 @@ cpa_status enqueue_poly_core(cpa_ctx* ctx, hipStream_t st, int d, const float* G
         e.sym = sym;
         if ((r = poly_gemm(ctx, st, make_op(Tq(i), d, d), make_op(T1, d, d), d, d, d, e, precision, true)) != CPA_OK)
             return r;
+    }
+    if (check_off >= 0 && s >= 2) {
+        hipLaunchKernelGGL(ps_check_kernel, dim3(kPsCheckWg), dim3(256), 0, st, d, G, ldg, (const float*)T1, s,
+                           scal + check_off);
+        HIP_TRY(hipGetLastError());
     }
     // every R_j = sum_i r_{j,i} T_i in one pass
     hipLaunchKernelGGL(ps_lincomb_kernel, dim3((int)std::min<int64_t>(4096, (dd / 4 + 255) / 256 + 1)), dim3(256), 0,
@@ -736,12 +741,12 @@ cpa_status enqueue_poly_core(cpa_ctx* ctx, hipStream_t st, int d, const float* G
 }
 
 cpa_status enqueue_poly(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* X, int64_t ldx, float* Y,
-                        int64_t ldy, int K, const Work& w, int precision) {
+                        int64_t ldy, int K, const Work& w, int precision, bool check = false) {
     const int d = w.d;
     float* F = nullptr;
     // enqueue_bound on this Work rewrote the coefficients already
     cpa_status r = enqueue_poly_core(ctx, st, d, w.G, d, w.scal, w.lay.ps(), w.poly, w.poly_s, K, precision, &F,
-                                     poly_fused(w, K));
+                                     poly_fused(w, K), check ? w.lay.pchk() : -1);
     if (r != CPA_OK) return r;
     // Y = X p (right) or p X (left); p read transposed (it is the fixed operand)
     const EpiLin e = lin_epi(Y, ldy, nullptr, 0, 1.f, 0.f, 0.f, 0.f);
@@ -794,6 +799,29 @@ cpa_status read_info(hipStream_t st, const Work& w, int K, int m, int n, cpa_inf
     return CPA_OK;
 }
 
+// max_q mu_q of the matrix-polynomial route's check (ps_check_kernel), from the
+// scalar block (synchronising); 0 when tr G = 0.
+cpa_status read_poly_check(hipStream_t st, const Work& w, double* growth) {
+    constexpr int kMaxPart = (kPsMaxS - 1) * kPsCheckWg;
+    double h[kMaxPart];
+    double tr = 0.0;
+    const int s = w.poly_s;
+    *growth = 0.0;
+    if (s < 2) return CPA_OK;
+    HIP_TRY(hipMemcpyAsync(h, w.scal + w.lay.pchk(), sizeof(double) * (s - 1) * kPsCheckWg, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&tr, w.scal + SC_TRACE, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (!(tr > 0.0)) return CPA_OK;
+    double g = -INFINITY;
+    for (int q = 2; q <= s; ++q) {
+        double sum = 0.0;
+        for (int b = 0; b < kPsCheckWg; ++b) sum += h[(q - 2) * kPsCheckWg + b];
+        g = std::max(g, sum / tr);
+    }
+    *growth = g;
+    return CPA_OK;
+}
+
 cpa_status shrink_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* X, int64_t ldx, float* Y,
                        int64_t ldy, const cpa_shrinkage* sh, const cpa_opts* o, cpa_info* info, const Work& w) {
     const int d = w.d;
@@ -802,7 +830,30 @@ cpa_status shrink_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* 
     if ((s = enqueue_gram(ctx, st, m, n, X, ldx, w)) != CPA_OK) return s;
     if ((s = enqueue_bound(ctx, st, d, sh, o, w, -1)) != CPA_OK) return s;
     if (w.poly_s > 0 && o->K >= 2) {
-        if ((s = enqueue_poly(ctx, st, m, n, X, ldx, Y, ldy, o->K, w, o->precision)) != CPA_OK) return s;
+        if ((s = enqueue_poly(ctx, st, m, n, X, ldx, Y, ldy, o->K, w, o->precision, o->check != 0)) != CPA_OK)
+            return s;
+        if (!info && !o->check) return CPA_OK;
+        if ((s = read_info(st, w, 1, m, n, info, nullptr)) != CPA_OK) return s;
+        if (!o->check) return CPA_OK;
+        double growth = 0.0;
+        if ((s = read_poly_check(st, w, &growth)) != CPA_OK) return s;
+        if (info) info->max_growth = growth;
+        if (growth <= 1.0 + o->growth_tol) return CPA_OK;
+        // bound too small: redo with the guaranteed bound ||G||_F (Gram still valid)
+        if ((s = fill_scalars(st, w)) != CPA_OK) return s;
+        if ((s = enqueue_gram(ctx, st, m, n, X, ldx, w)) != CPA_OK) return s;
+        if ((s = enqueue_bound(ctx, st, d, sh, o, w, 2)) != CPA_OK) return s;
+        if ((s = enqueue_poly(ctx, st, m, n, X, ldx, Y, ldy, o->K, w, o->precision, true)) != CPA_OK) return s;
+        if ((s = read_info(st, w, 1, m, n, info, nullptr)) != CPA_OK) return s;
+        if ((s = read_poly_check(st, w, &growth)) != CPA_OK) return s;
+        if (info) {
+            info->fallback = 1;
+            info->max_growth = growth;
+        }
+        if (growth > 1.0 + o->growth_tol)
+            return fail(CPA_ERR_BOUND, "weighted mean %.6g exceeds 1 + %.3g even with Lambda = ||G||_F", growth,
+                        o->growth_tol);
+        return CPA_OK;
     } else if ((s = enqueue_recurrence(ctx, st, m, n, X, ldx, Y, ldy, o->K, w, info != nullptr || o->check,
                                        o->precision)) != CPA_OK) {
         return s;

@@ -54,6 +54,7 @@ constexpr int kNormSlots = 64;   // partial-sum slots per growth-check norm
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPsMaxS = 16;   // largest baby-step count of the matrix-polynomial route
+constexpr int kPsCheckWg = 64;   // workgroups of the matrix-polynomial route's a-posteriori check
 
 struct ScalarLayout {
     int K, maxit, gwg, pwg;      // gwg: Gram workgroups, pwg: power-iteration workgroups
@@ -64,7 +65,8 @@ struct ScalarLayout {
     int gpart() const { return pw_w2() + maxit + 1; }                 // 2 per Gram workgroup
     int ppart() const { return gpart() + 2 * gwg; }                   // 2 x 2 per power workgroup
     int ps() const { return ppart() + 4 * pwg; }                       // matrix-polynomial coefficients
-    int total() const { return ps() + K + kPsMaxS; }
+    int pchk() const { return ps() + K + kPsMaxS; }                     // check partials, (q - 2) x kPsCheckWg
+    int total() const { return pchk() + (kPsMaxS - 1) * kPsCheckWg; }
 };
 
 __global__ void fill_f64_kernel(double* p, int n, double v) {
@@ -440,6 +442,33 @@ __global__ void ps_shift_kernel(int d, const float* G, int64_t ldg, float* T1, c
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = p / d, j = p - i * d;
         T1[p] = a1 * G[i * ldg + j] - (i == j ? 1.f : 0.f);
+    }
+}
+
+// A-posteriori check of the matrix-polynomial route: the Gram-weighted means
+//   mu_q = <G, T_q(Ghat)>_F / tr G = sum_i lambda_i T_q(x_i) / sum_i lambda_i,  q = 2..s,
+// over the baby steps already formed (T_q at T1 + (q - 1) d^2, pitch d).  With
+// Lambda >= lambda_max every x_i = 2 lambda_i / Lambda - 1 lies in [-1, 1], so
+// |T_q(x_i)| <= 1 and mu_q <= 1; a bound below lambda_max puts the top eigenvalue,
+// which carries the largest weight, beyond 1, where T_q grows like cosh.  Per
+// workgroup FP64 partials of <G, T_q> at part[(q - 2) kPsCheckWg + b] (grid
+// kPsCheckWg, fixed element split, so the sums do not depend on scheduling).
+__global__ void ps_check_kernel(int d, const float* G, int64_t ldg, const float* T1, int s, double* part) {
+    __shared__ double red[16];
+    const int64_t dd = (int64_t)d * d;
+    double acc[kPsMaxS];
+#pragma unroll
+    for (int q = 0; q < kPsMaxS; ++q) acc[q] = 0.0;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < dd; p += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = p / d, j = p - i * d;
+        const double g = G[i * ldg + j];
+#pragma unroll
+        for (int q = 2; q < kPsMaxS + 1; ++q)
+            if (q <= s) acc[q - 1] += g * (double)T1[(int64_t)(q - 1) * dd + p];
+    }
+    for (int q = 2; q <= s; ++q) {
+        const double v = block_sum(acc[q - 1], red);
+        if (threadIdx.x == 0) part[(q - 2) * kPsCheckWg + blockIdx.x] = v;
     }
 }
 

@@ -239,17 +239,49 @@ def test_polynomial_route_is_deterministic():
         assert torch.equal(Y1, Y2), d
 
 
-def test_polynomial_route_rejects_growth_check():
+def test_polynomial_route_limits_and_check():
     torch = _torch()
     cpa = _lib()
     Xd = torch.ones((8, 4), device="cuda")
     with pytest.raises(cpa.CpaError):
-        cpa.shrink_dense(Xd, cpa.soft(0.1), cpa.Opts(K=9, eval="polynomial", check=True))
-    with pytest.raises(cpa.CpaError):
         cpa.shrink_dense(Xd, cpa.soft(0.1), cpa.Opts(K=257, eval="polynomial"))
-    # auto with the check takes the recurrence and reports its growth
-    _, info = cpa.shrink_dense(Xd, cpa.soft(0.1), cpa.Opts(K=9, check=True), info=True)
+    # the recurrence reports its growth, the polynomial route its weighted means (<= 1)
+    _, info = cpa.shrink_dense(Xd, cpa.soft(0.1), cpa.Opts(K=9, check=True, eval="recurrence"), info=True)
     assert info["max_growth"] > 0.0
+    _, info = cpa.shrink_dense(Xd, cpa.soft(0.1), cpa.Opts(K=9, check=True, eval="polynomial"), info=True)
+    assert 0.0 < info["max_growth"] <= 1.0 + 1e-3 and info["fallback"] == 0
+
+
+@pytest.mark.parametrize("ev", ["polynomial", "recurrence"])
+@pytest.mark.parametrize("shape,factor", [((300, 200), 0.9), ((1024, 1024), 0.9), ((120, 300), 0.6)])
+def test_check_catches_a_bound_below_lambda_max(ev, shape, factor):
+    """Lambda = 0.9 (or 0.6) lambda_max puts the top eigenvalue outside [-1, 1]: the
+    check fires on both routes and the result is recomputed at Lambda = ||G||_F,
+    equal to the oracle there; a sound bound passes with no fallback.  The 1024 x
+    1024 case is the RPCA frames (the headline shape, where the top eigenvalue
+    carries almost all the weight of tr G)."""
+    torch = _torch()
+    cpa = _lib()
+    m, n = shape
+    if shape == (1024, 1024):
+        X = synth.rpca_frames()[0].astype(np.float64)
+        tau = 10.0
+    else:
+        X = synth.as_f32_exact(synth.dense_lowrank(m, n, rank=8, noise=0.3, seed=7500 + m))
+        tau = 0.2 * math.sqrt(_gram_lmax(X))
+    lmax = _gram_lmax(X)
+    Xd = torch.from_numpy(X.astype(np.float32)).cuda()
+    Y, info = cpa.shrink_dense(Xd, cpa.soft(tau), cpa.Opts(K=30, Lambda=factor * lmax, check=True, eval=ev),
+                               info=True)
+    print(f"check {ev} {m}x{n} Lambda={factor} lambda_max: max_growth {info['max_growth']:.4g} "
+          f"fallback {info['fallback']}", flush=True)
+    assert info["fallback"] == 1
+    G = X.T @ X if m >= n else X @ X.T
+    assert info["Lambda"] == pytest.approx(math.sqrt(float(np.sum(G * G))), rel=1e-5)
+    ref = ocpa.cpa_shrink(X, Shrinkage(0, tau), info["Lambda"], 30)
+    parity.check(Y.cpu().numpy(), ref, TOL32, X, f"after fallback {ev}")
+    _, info = cpa.shrink_dense(Xd, cpa.soft(tau), cpa.Opts(K=30, check=True, eval=ev), info=True)
+    assert info["fallback"] == 0 and info["max_growth"] <= 1.0 + 1e-3
 
 
 def test_power_bound_large_d_reads_iterate_from_global():
