@@ -80,8 +80,16 @@ typedef struct {
  *                        or after power_iters products; ||r|| = sqrt(max(||w||^2 - mu^2, 0));
  *                        Lambda = min(mu + max(margin * mu, ||r||), (1 + margin) ||Gram||_F)
  *   CPA_BOUND_GIVEN      Lambda = opts.Lambda (must be >= 0 and finite)
- *   CPA_BOUND_FROBENIUS  Lambda = ||Gram||_F (always an upper bound) */
-typedef enum { CPA_BOUND_POWER = 0, CPA_BOUND_GIVEN = 1, CPA_BOUND_FROBENIUS = 2 } cpa_bound_rule;
+ *   CPA_BOUND_FROBENIUS  Lambda = ||Gram||_F (always an upper bound)
+ *   CPA_BOUND_LEARNED    the predictor network opts.model (see cpa_predictor_forward) on the
+ *                        features (log ||X||_F, log ||Gram||_F^2, log(m n)), outputs (y0, y1):
+ *                        Lambda = (1 + margin) ||Gram||_F exp(min(y0, 0)); K stays opts.K
+ *                        (the per-matrix order is the batched path's,
+ *                        cpa_shrink_batched_predicted).  With check = 1 a failed check
+ *                        recomputes with the power-iteration bound (power_iters, power_tol).
+ *                        Dense entry points only (cpa_shrink_dense, _noalloc,
+ *                        cpa_spectral_bound); the others return CPA_ERR_UNSUPPORTED */
+typedef enum { CPA_BOUND_POWER = 0, CPA_BOUND_GIVEN = 1, CPA_BOUND_FROBENIUS = 2, CPA_BOUND_LEARNED = 3 } cpa_bound_rule;
 
 /* Arithmetic of the recurrence products (the Gram and the bound are always FP32
  * MFMA with FP64 reductions).
@@ -133,8 +141,9 @@ typedef struct {
     double margin;        /* relative margin delta added to the Rayleigh quotient */
     uint64_t seed;        /* start-vector seed */
     int32_t check;        /* 1: a-posteriori check of the bound (consequence of |T_k| <= 1 on
-                             [-1, 1], Sec. II-B), with one recompute at Lambda = ||Gram||_F on
-                             failure (synchronises the stream).  Recurrence route: the growth
+                             [-1, 1], Sec. II-B), with one recompute on failure at Lambda =
+                             ||Gram||_F (at the power bound after CPA_BOUND_LEARNED)
+                             (synchronises the stream).  Recurrence route: the growth
                              max_k ||Y_k||_F / ||X||_F <= 1 + growth_tol.  Matrix-polynomial
                              route: the Gram-weighted means of the baby steps,
                              max_{q=2..s} <Gram, T_q(Ghat)>_F / tr Gram <= 1 + growth_tol
@@ -149,6 +158,8 @@ typedef struct {
                              threshold).  Dense, CSR and sparsified paths and the drivers; the
                              batched path rejects it */
     int32_t reserved;     /* must be 0 */
+    const float* model;   /* CPA_BOUND_LEARNED: the predictor model, CPA_PRED_MODEL_FLOATS floats in
+                             device memory (caller-owned); ignored by the other rules */
 } cpa_opts;
 
 /* Per-call report (host struct).  Filling it synchronises the stream. */

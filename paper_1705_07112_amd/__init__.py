@@ -28,7 +28,7 @@ LIB_PATH = os.path.join(_HERE, "libcpasvt.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "cpasvt.h")
 
 SOFT, HARD, WEIGHTED_CONST, WEIGHTED_FN = 0, 1, 2, 3
-BOUND_POWER, BOUND_GIVEN, BOUND_FROBENIUS = 0, 1, 2
+BOUND_POWER, BOUND_GIVEN, BOUND_FROBENIUS, BOUND_LEARNED = 0, 1, 2, 3
 PREC_FP32, PREC_BF16X3, PREC_FP64 = 0, 1, 2
 OK, ERR_ARG, ERR_SHAPE, ERR_ALLOC, ERR_HIP, ERR_NONFINITE, ERR_BOUND, ERR_UNSUPPORTED, ERR_IO = range(9)
 
@@ -44,7 +44,7 @@ class CpaOpts(ctypes.Structure):
                 ("power_tol", ctypes.c_double), ("margin", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("check", ctypes.c_int32), ("precision", ctypes.c_int32), ("growth_tol", ctypes.c_double),
                 ("eval", ctypes.c_int32), ("side", ctypes.c_int32), ("damping", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("model", ctypes.c_void_p)]
 
 
 class CpaInfo(ctypes.Structure):
@@ -213,7 +213,7 @@ def weighted_fn(w_c: float, w_sigma: float, w_eps: float = 1e-6) -> CpaShrinkage
 @dataclass
 class Opts:
     K: int = 16
-    bound: str = "power"          # "power" | "given" | "frobenius"
+    bound: str = "power"          # "power" | "given" | "frobenius" | "learned" (needs model)
     Lambda: float | None = None
     power_iters: int = 100
     warm_start: bool = False
@@ -226,6 +226,7 @@ class Opts:
     eval: str = "auto"           # "auto" | "recurrence" | "polynomial"
     side: str = "auto"           # "auto" | "right" (Gram X^T X) | "left" (Gram X X^T)
     damping: str = "none"        # "none" | "jackson" | "lanczos" (coefficient damping; not in the paper)
+    model: object = None          # bound "learned": the predictor model (float32 CUDA tensor)
 
     def to_c(self) -> CpaOpts:
         o = CpaOpts()
@@ -234,7 +235,13 @@ class Opts:
         bound = self.bound
         if self.Lambda is not None and bound == "power":
             bound = "given"
-        o.bound = {"power": BOUND_POWER, "given": BOUND_GIVEN, "frobenius": BOUND_FROBENIUS}[bound]
+        o.bound = {"power": BOUND_POWER, "given": BOUND_GIVEN, "frobenius": BOUND_FROBENIUS,
+                   "learned": BOUND_LEARNED}[bound]
+        if self.model is not None:
+            if self.model.dtype.itemsize != 4 or not self.model.is_cuda or not self.model.is_contiguous() \
+                    or self.model.numel() != PRED_MODEL_FLOATS:
+                raise ValueError("model must be a contiguous float32 CUDA tensor of %d entries" % PRED_MODEL_FLOATS)
+            o.model = self.model.data_ptr()
         o.Lambda = float(self.Lambda or 0.0)
         o.power_iters = int(self.power_iters)
         o.warm_start = int(bool(self.warm_start))

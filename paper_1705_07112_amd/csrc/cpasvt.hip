@@ -418,13 +418,29 @@ cpa_status check_shrinkage(const cpa_shrinkage* s) {
     return CPA_OK;
 }
 
+// The learned bound rule is the dense single-matrix paths' (the batched path
+// takes the predictor through cpa_shrink_batched_predicted).
+cpa_status no_learned_bound(const cpa_opts* o) {
+    if (o->bound == CPA_BOUND_LEARNED)
+        return fail(CPA_ERR_UNSUPPORTED, "the learned bound rule is available on cpa_shrink_dense(_noalloc) and "
+                                         "cpa_spectral_bound only");
+    return CPA_OK;
+}
+
+// Power-iteration slots of the scalar block: the power rule, and the learned
+// rule, whose check falls back to power iteration.
+int power_slots(const cpa_opts* o) {
+    return (o->bound == CPA_BOUND_POWER || o->bound == CPA_BOUND_LEARNED) ? o->power_iters : 1;
+}
+
 cpa_status check_opts(const cpa_opts* o) {
     if (!o) return fail(CPA_ERR_ARG, "opts is NULL");
     if (o->K < 1 || o->K > kMaxK) return fail(CPA_ERR_ARG, "K must be in [1, %d], got %d", kMaxK, o->K);
-    if (o->bound < 0 || o->bound > 2) return fail(CPA_ERR_ARG, "unknown bound rule %d", o->bound);
+    if (o->bound < 0 || o->bound > 3) return fail(CPA_ERR_ARG, "unknown bound rule %d", o->bound);
+    if (o->bound == CPA_BOUND_LEARNED && !o->model) return fail(CPA_ERR_ARG, "the learned bound needs opts.model");
     if (o->bound == CPA_BOUND_GIVEN && !(std::isfinite(o->Lambda) && o->Lambda >= 0.0))
         return fail(CPA_ERR_ARG, "given Lambda must be finite and >= 0");
-    if (o->bound == CPA_BOUND_POWER) {
+    if (o->bound == CPA_BOUND_POWER || o->bound == CPA_BOUND_LEARNED) {
         if (o->power_iters < 1 || o->power_iters > kMaxPowerIters)
             return fail(CPA_ERR_ARG, "power_iters must be in [1, %d]", kMaxPowerIters);
         if (!(o->power_tol >= 0.0) || !(o->margin >= 0.0)) return fail(CPA_ERR_ARG, "power_tol and margin must be >= 0");
@@ -490,9 +506,15 @@ cpa_status enqueue_gram_impl(hipStream_t st, int m, int n, const float* X, int64
 // for that route by the bound's finish kernel (enqueue_poly_core then skips it).
 bool poly_fused(const Work& w, int K) { return w.poly_s > 0 && K >= 2; }
 
+// The finish kernel's bound mode of a rule: 0 power, 1 given, 2 Frobenius, 3 learned.
+int bound_mode(int rule) {
+    return rule == CPA_BOUND_POWER ? 0 : rule == CPA_BOUND_GIVEN ? 1 : rule == CPA_BOUND_FROBENIUS ? 2 : 3;
+}
+
+// logmn: log(m n) of the input (the learned rule's third feature).
 cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkage* sh, const cpa_opts* o,
-                         const Work& w, int mode_override, const double* G64 = nullptr) {
-    int mode = o->bound == CPA_BOUND_POWER ? 0 : (o->bound == CPA_BOUND_GIVEN ? 1 : 2);
+                         const Work& w, int mode_override, const double* G64 = nullptr, double logmn = 0.0) {
+    int mode = bound_mode(o->bound);
     if (mode_override >= 0) mode = mode_override;
     double* warm_vec = w.warm_vec ? w.warm_vec : ctx->warm;
     int& warm_len = w.warm_len ? *w.warm_len : ctx->warm_d;
@@ -523,7 +545,8 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
     hipLaunchKernelGGL(finish_bound_kernel, dim3(1), dim3(256), 0, st, mode, o->Lambda, d, o->power_iters, o->margin,
                        (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? warm_vec : nullptr, w.scal,
                        to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)(w.scal + w.lay.gpart()),
-                       w.lay.gwg, 0, o->damping, w.poly_s, poly_fused(w, o->K) ? w.lay.ps() : -1);
+                       w.lay.gwg, 0, o->damping, w.poly_s, poly_fused(w, o->K) ? w.lay.ps() : -1,
+                       mode == 3 ? o->model : nullptr, logmn);
     HIP_TRY(hipGetLastError());
     if (mode == 0) warm_len = d;
     return CPA_OK;
@@ -795,6 +818,8 @@ cpa_status read_info(hipStream_t st, const Work& w, int K, int m, int n, cpa_inf
         info->reserved = 0;
     }
     if (hdr[SC_TIMEOUT] != 0.0) return fail(CPA_ERR_HIP, "power iteration grid barrier timed out");
+    if (!std::isfinite(hdr[SC_TRACE]) || !std::isfinite(hdr[SC_FRO2]))
+        return fail(CPA_ERR_NONFINITE, "X holds NaN or infinite entries (or its Gram overflows FP32)");
     if (!std::isfinite(hdr[SC_LAMBDA])) return fail(CPA_ERR_NONFINITE, "spectral bound is not finite");
     return CPA_OK;
 }
@@ -825,10 +850,14 @@ cpa_status read_poly_check(hipStream_t st, const Work& w, double* growth) {
 cpa_status shrink_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* X, int64_t ldx, float* Y,
                        int64_t ldy, const cpa_shrinkage* sh, const cpa_opts* o, cpa_info* info, const Work& w) {
     const int d = w.d;
+    const double logmn = std::log((double)m * n);
+    // the check's recompute: power iteration after the learned bound (the fallback
+    // the predictor stands in for), the guaranteed ||G||_F after the others
+    const int redo_mode = o->bound == CPA_BOUND_LEARNED ? 0 : 2;
     cpa_status s;
     if ((s = fill_scalars(st, w)) != CPA_OK) return s;
     if ((s = enqueue_gram(ctx, st, m, n, X, ldx, w)) != CPA_OK) return s;
-    if ((s = enqueue_bound(ctx, st, d, sh, o, w, -1)) != CPA_OK) return s;
+    if ((s = enqueue_bound(ctx, st, d, sh, o, w, -1, nullptr, logmn)) != CPA_OK) return s;
     if (w.poly_s > 0 && o->K >= 2) {
         if ((s = enqueue_poly(ctx, st, m, n, X, ldx, Y, ldy, o->K, w, o->precision, o->check != 0)) != CPA_OK)
             return s;
@@ -839,10 +868,10 @@ cpa_status shrink_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* 
         if ((s = read_poly_check(st, w, &growth)) != CPA_OK) return s;
         if (info) info->max_growth = growth;
         if (growth <= 1.0 + o->growth_tol) return CPA_OK;
-        // bound too small: redo with the guaranteed bound ||G||_F (Gram still valid)
+        // bound too small: redo with the safer bound (Gram still valid)
         if ((s = fill_scalars(st, w)) != CPA_OK) return s;
         if ((s = enqueue_gram(ctx, st, m, n, X, ldx, w)) != CPA_OK) return s;
-        if ((s = enqueue_bound(ctx, st, d, sh, o, w, 2)) != CPA_OK) return s;
+        if ((s = enqueue_bound(ctx, st, d, sh, o, w, redo_mode, nullptr, logmn)) != CPA_OK) return s;
         if ((s = enqueue_poly(ctx, st, m, n, X, ldx, Y, ldy, o->K, w, o->precision, true)) != CPA_OK) return s;
         if ((s = read_info(st, w, 1, m, n, info, nullptr)) != CPA_OK) return s;
         if ((s = read_poly_check(st, w, &growth)) != CPA_OK) return s;
@@ -851,7 +880,7 @@ cpa_status shrink_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* 
             info->max_growth = growth;
         }
         if (growth > 1.0 + o->growth_tol)
-            return fail(CPA_ERR_BOUND, "weighted mean %.6g exceeds 1 + %.3g even with Lambda = ||G||_F", growth,
+            return fail(CPA_ERR_BOUND, "weighted mean %.6g exceeds 1 + %.3g even after the recompute", growth,
                         o->growth_tol);
         return CPA_OK;
     } else if ((s = enqueue_recurrence(ctx, st, m, n, X, ldx, Y, ldy, o->K, w, info != nullptr || o->check,
@@ -862,15 +891,15 @@ cpa_status shrink_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* 
     double growth = 0.0;
     if ((s = read_info(st, w, o->K, m, n, info, &growth)) != CPA_OK) return s;
     if (o->check && growth > 1.0 + o->growth_tol) {
-        // bound too small: redo with the guaranteed bound ||G||_F (Gram is still valid)
+        // bound too small: redo with the safer bound (Gram is still valid)
         if ((s = fill_scalars(st, w)) != CPA_OK) return s;
         if ((s = enqueue_gram(ctx, st, m, n, X, ldx, w)) != CPA_OK) return s;
-        if ((s = enqueue_bound(ctx, st, d, sh, o, w, 2)) != CPA_OK) return s;
+        if ((s = enqueue_bound(ctx, st, d, sh, o, w, redo_mode, nullptr, logmn)) != CPA_OK) return s;
         if ((s = enqueue_recurrence(ctx, st, m, n, X, ldx, Y, ldy, o->K, w, info != nullptr || o->check, o->precision)) != CPA_OK) return s;
         if ((s = read_info(st, w, o->K, m, n, info, &growth)) != CPA_OK) return s;
         if (info) info->fallback = 1;
         if (growth > 1.0 + o->growth_tol)
-            return fail(CPA_ERR_BOUND, "growth %.6g exceeds 1 + %.3g even with Lambda = ||G||_F", growth, o->growth_tol);
+            return fail(CPA_ERR_BOUND, "growth %.6g exceeds 1 + %.3g even after the recompute", growth, o->growth_tol);
     }
     return CPA_OK;
 }
@@ -1062,7 +1091,7 @@ cpa_status shrink_csr_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t n
     double* gpart = w.scal + w.lay.gpart();
     hipLaunchKernelGGL(sq_norm_kernel, dim3(kSqGrid), dim3(256), 0, st, nnz, val, gpart);
     HIP_TRY(hipGetLastError());
-    int mode = o->bound == CPA_BOUND_POWER ? 0 : (o->bound == CPA_BOUND_GIVEN ? 1 : 2);
+    int mode = bound_mode(o->bound);
     if (mode == 0) {
         const bool warm = o->warm_start && ctx->warm_d == n;
         hipLaunchKernelGGL(power_init_kernel, dim3(1), dim3(256), 0, st, n, (uint64_t)o->seed,
@@ -1083,7 +1112,8 @@ cpa_status shrink_csr_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t n
     }
     hipLaunchKernelGGL(finish_bound_kernel, dim3(1), dim3(256), 0, st, mode, o->Lambda, n, o->power_iters, o->margin,
                        (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? ctx->warm : nullptr, w.scal,
-                       to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)gpart, kSqGrid, 1, o->damping, 0, -1);
+                       to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)gpart, kSqGrid, 1, o->damping, 0, -1,
+                       nullptr, 0.0);
     HIP_TRY(hipGetLastError());
     if (mode == 0) ctx->warm_d = n;
     const bool poly = w.poly_s > 0 && o->K >= 2;
@@ -1264,7 +1294,7 @@ cpa_status cpa_workspace_bytes(cpa_ctx* ctx, int m, int n, const cpa_opts* opts,
     if (m == 0 || n == 0) return CPA_OK;
     HIP_TRY(hipSetDevice(ctx->device));
     Work w;
-    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    const int maxit = power_slots(opts);
     return ensure_ws(ctx, m, n, opts->K, maxit, false, w, right_side(opts, m, n), poly_choice(opts, m, n), bytes_host);
 }
 
@@ -1319,12 +1349,12 @@ cpa_status cpa_spectral_bound(cpa_ctx* ctx, void* stream, int m, int n, const fl
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
     Work w;
-    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    const int maxit = power_slots(opts);
     if ((s = ensure_ws(ctx, m, n, opts->K, maxit, false, w, right_side(opts, m, n))) != CPA_OK) return s;
     cpa_shrinkage soft0 = {CPA_SOFT, 0, 0.0, 0.0, 0.0, 1.0};
     if ((s = fill_scalars(st, w)) != CPA_OK) return s;
     if ((s = enqueue_gram(ctx, st, m, n, X_dev, ldx, w)) != CPA_OK) return s;
-    if ((s = enqueue_bound(ctx, st, w.d, &soft0, opts, w, -1)) != CPA_OK) return s;
+    if ((s = enqueue_bound(ctx, st, w.d, &soft0, opts, w, -1, nullptr, std::log((double)m * n))) != CPA_OK) return s;
     cpa_info tmp;
     if ((s = read_info(st, w, 1, m, n, &tmp, nullptr)) != CPA_OK) return s;
     *Lambda_host = tmp.Lambda;
@@ -1350,7 +1380,7 @@ cpa_status cpa_shrink_dense(cpa_ctx* ctx, void* stream, int m, int n, const floa
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
     Work w;
-    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    const int maxit = power_slots(opts);
     if ((s = ensure_ws(ctx, m, n, opts->K, maxit, false, w, right_side(opts, m, n), poly_choice(opts, m, n))) != CPA_OK)
         return s;
     return shrink_impl(ctx, st, m, n, X_dev, ldx, Y_dev, ldy, shrink, opts, info_host, w);
@@ -1380,7 +1410,7 @@ cpa_status cpa_shrink_dense_noalloc(cpa_ctx* ctx, void* stream, int m, int n, co
     HIP_TRY(hipSetDevice(ctx->device));
     if ((s = query_coop(ctx)) != CPA_OK) return s;
     Work w;
-    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    const int maxit = power_slots(opts);
     const int ps = poly_choice(opts, m, n);
     const bool need_y = ps == 0;   // the recurrence over X (and the growth check's redo) needs the Y pair
     const WsPlan p = plan_ws(m, n, opts->K, maxit, false, w, right, ps, power_grid(ctx, d), need_y, false);
@@ -1500,6 +1530,7 @@ cpa_status batched_shrink_args(const cpa_opts* opts, const float* X_dev, float* 
                                const cpa_shrinkage* shrink_dev, const cpa_shrinkage* shrink_host, BatchArgs& a) {
     cpa_status s;
     if ((s = check_opts(opts)) != CPA_OK) return s;
+    if ((s = no_learned_bound(opts)) != CPA_OK) return s;
     if (opts->K > 64) return fail(CPA_ERR_ARG, "batched shrinkage supports K <= 64");
     if (opts->side != CPA_SIDE_AUTO) return fail(CPA_ERR_UNSUPPORTED, "batched shrinkage takes the smaller Gram (side auto)");
     if (opts->damping != CPA_DAMP_NONE) return fail(CPA_ERR_UNSUPPORTED, "batched shrinkage takes undamped coefficients");
@@ -1964,6 +1995,7 @@ cpa_status cpa_shrink_csr(cpa_ctx* ctx, void* stream, int m, int n, int64_t nnz,
     if (opts && opts->side == CPA_SIDE_LEFT) return fail(CPA_ERR_UNSUPPORTED, "sparse path forms S^T S (side right)");
     if ((s = check_shrinkage(shrink)) != CPA_OK) return s;
     if ((s = check_opts(opts)) != CPA_OK) return s;
+    if ((s = no_learned_bound(opts)) != CPA_OK) return s;
     if (opts->precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "sparse path is FP32");
     if (opts->check) return fail(CPA_ERR_UNSUPPORTED, "the growth check is not available on the sparse path");
     if (m == 0 || n == 0) {
@@ -1980,8 +2012,8 @@ cpa_status cpa_shrink_csr(cpa_ctx* ctx, void* stream, int m, int n, int64_t nnz,
     if ((s = shrink_csr_impl(ctx, st, m, n, nnz, rowptr_dev, colidx_dev, val_dev, Y_dev, ldy, shrink, opts, w)) != CPA_OK)
         return s;
     if (info_host) {
-        std::vector<double> h(w.lay.total());
-        HIP_TRY(hipMemcpyAsync(h.data(), w.scal, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+        double h[SC_COEF];
+        HIP_TRY(hipMemcpyAsync(h, w.scal, sizeof(h), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         std::memset(info_host, 0, sizeof(*info_host));
         info_host->Lambda = h[SC_LAMBDA];
@@ -1990,6 +2022,7 @@ cpa_status cpa_shrink_csr(cpa_ctx* ctx, void* stream, int m, int n, int64_t nnz,
         info_host->fro_gram = h[SC_TRACE];
         info_host->power_iters_done = (int)h[SC_ITERS];
         if (h[SC_TIMEOUT] != 0.0) return fail(CPA_ERR_HIP, "power iteration grid barrier timed out");
+        if (!std::isfinite(h[SC_TRACE])) return fail(CPA_ERR_NONFINITE, "S holds NaN or infinite values");
         if (!std::isfinite(h[SC_LAMBDA])) return fail(CPA_ERR_NONFINITE, "spectral bound is not finite");
     }
     return CPA_OK;
@@ -2003,6 +2036,7 @@ cpa_status cpa_svt_complete(cpa_ctx* ctx, void* stream, int m, int n, int64_t nn
     if ((s = check_csr_args(ctx, m, n, nnz, rowptr_dev, colidx_dev, Mobs_dev, X_dev, ldx)) != CPA_OK) return s;
     if (opts && opts->side == CPA_SIDE_LEFT) return fail(CPA_ERR_UNSUPPORTED, "sparse path forms S^T S (side right)");
     if ((s = check_opts(opts)) != CPA_OK) return s;
+    if ((s = no_learned_bound(opts)) != CPA_OK) return s;
     if (opts->precision != CPA_PREC_FP32 || opts->check) return fail(CPA_ERR_UNSUPPORTED, "unsupported option");
     if (!(std::isfinite(tau) && tau >= 0.0 && std::isfinite(delta) && delta > 0.0) || iters < 0)
         return fail(CPA_ERR_ARG, "tau >= 0, delta > 0 and iters >= 0 required");
@@ -2115,6 +2149,7 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
     if (m < 0 || n < 0) return fail(CPA_ERR_SHAPE, "negative size");
     if (iters < 0) return fail(CPA_ERR_ARG, "iters < 0");
     if ((s = check_opts(opts)) != CPA_OK) return s;
+    if ((s = no_learned_bound(opts)) != CPA_OK) return s;
     if (!(std::isfinite(inv_rho) && inv_rho >= 0.0 && std::isfinite(eta_over_rho) && eta_over_rho >= 0.0))
         return fail(CPA_ERR_ARG, "inv_rho and eta_over_rho must be finite and >= 0");
     if (m == 0 || n == 0 || iters == 0) return CPA_OK;
@@ -2375,6 +2410,7 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
     cpa_status s;
     if ((s = check_dense_args(ctx, m, n, X_dev, ldx)) != CPA_OK) return s;
     if ((s = check_opts(opts)) != CPA_OK) return s;
+    if ((s = no_learned_bound(opts)) != CPA_OK) return s;
     if ((s = check_shrinkage(shrink)) != CPA_OK) return s;
     if (!sp) return fail(CPA_ERR_ARG, "sparsify is NULL");
     if (sp->transform != CPA_TRANSFORM_IDENTITY && sp->transform != CPA_TRANSFORM_BLOCK_DCT8 &&
@@ -2731,6 +2767,7 @@ cpa_status inpaint_run(cpa_ctx* ctx, void* stream, int m, int n, const float* I_
     if (m < 0 || n < 0) return fail(CPA_ERR_SHAPE, "negative size");
     if (iters < 0) return fail(CPA_ERR_ARG, "iters < 0");
     if ((s = check_opts(opts)) != CPA_OK) return s;
+    if ((s = no_learned_bound(opts)) != CPA_OK) return s;
     if (!(std::isfinite(inv_rho) && inv_rho >= 0.0 && std::isfinite(eta_over_rho) && eta_over_rho >= 0.0))
         return fail(CPA_ERR_ARG, "inv_rho and eta_over_rho must be finite and >= 0");
     if (m == 0 || n == 0 || iters == 0) return CPA_OK;
@@ -2938,6 +2975,7 @@ cpa_status cpa_shrink_dense_f64(cpa_ctx* ctx, void* stream, int m, int n, const 
     cpa_opts o = *opts_in;
     if (o.precision == CPA_PREC_FP64) o.precision = CPA_PREC_FP32;   // the arithmetic here is FP64 in any case
     if ((s = check_opts(&o)) != CPA_OK) return s;
+    if ((s = no_learned_bound(&o)) != CPA_OK) return s;
     if (o.precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "the FP64 path has no split precision");
     if (o.check) return fail(CPA_ERR_UNSUPPORTED, "the growth check is not available on the FP64 path");
     if (o.eval == CPA_EVAL_POLYNOMIAL) return fail(CPA_ERR_UNSUPPORTED, "the FP64 path evaluates by the recurrence");
@@ -3015,6 +3053,7 @@ cpa_status cpa_rpca_admm(cpa_ctx* ctx, void* stream, int m, int n, const float* 
     if (max_iters < 0) return fail(CPA_ERR_ARG, "max_iters < 0");
     if (!(tol >= 0.0)) return fail(CPA_ERR_ARG, "tol must be >= 0");
     if ((s = check_opts(opts)) != CPA_OK) return s;
+    if ((s = no_learned_bound(opts)) != CPA_OK) return s;
     if (iters_done) *iters_done = 0;
     if (m == 0 || n == 0 || max_iters == 0) return CPA_OK;
     if (!I_dev || !L_dev || !S_dev) return fail(CPA_ERR_ARG, "I, L or S is NULL");

@@ -25,6 +25,7 @@
 
 #include <type_traits>
 
+#include "mlp.hpp"
 #include "shrink_fn.hpp"
 
 namespace cpa {
@@ -306,13 +307,18 @@ __device__ inline void ps_coeff_block(int K, int s, int J, double* scal, int out
 
 // ps_out >= 0: the coefficients are also rewritten for the matrix-polynomial route
 // with baby steps of ps_s (ps_coeff_block), saving that route a launch.
+// mode: 0 power iteration, 1 given, 2 Frobenius, 3 the predictor network
+// `model` on the features (log ||X||_F, log ||G||_F^2, log mn) (logmn = log mn):
+// Lambda = (1 + margin) ||G||_F exp(min(y0, 0)), never above the Frobenius cap.
 __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int maxit, double margin,
                                     const double* wbuf0, const double* wbuf1, double* warm_out, double* scal,
                                     ShrinkParams sp, int K, int pw_mu, int pw_w2, const double* gpart, int gwg,
-                                    int cap_trace, int damping, int ps_s, int ps_out) {
+                                    int cap_trace, int damping, int ps_s, int ps_out, const float* model,
+                                    double logmn) {
     __shared__ double sLambda;
     __shared__ int sT;
     __shared__ double red[16];
+    __shared__ float mlp_h[2 * kMlpH], mlp_y[2];
     // Gram statistics from the per-workgroup partials, in a fixed order
     double f2 = 0.0, tr = 0.0;
     for (int i = threadIdx.x; i < gwg; i += blockDim.x) {
@@ -321,6 +327,11 @@ __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int ma
     }
     f2 = block_sum(f2, red);
     tr = block_sum(tr, red);
+    float y0 = 0.f;
+    if (mode == 3 && f2 > 0.0 && tr > 0.0) {
+        float y1;
+        mlp_infer_wg(model, (float)(0.5 * log(tr)), (float)log(f2), (float)logmn, mlp_h, mlp_y, y0, y1);
+    }
     if (threadIdx.x == 0) {
         scal[SC_FRO2] = f2;
         scal[SC_TRACE] = tr;
@@ -332,6 +343,8 @@ __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int ma
             Lam = Lambda_given;
         } else if (mode == 2) {
             Lam = fro;
+        } else if (mode == 3) {
+            Lam = fro > 0.0 ? (1.0 + margin) * fro * exp((double)(y0 < 0.f ? y0 : 0.f)) : 0.0;
         } else if (fro > 0.0) {
             T = (int)scal[SC_STOP];
             if (scal[SC_VANISH] != 0.0 || scal[SC_TIMEOUT] != 0.0 || T < 1) {

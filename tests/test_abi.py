@@ -1,6 +1,7 @@
 """The C-ABI library: it builds, loads, exports every symbol include/cpasvt.h
 declares, and its host-only entry points behave (no GPU needed)."""
 import ctypes
+import os
 import math
 
 import numpy as np
@@ -30,12 +31,28 @@ def test_status_strings_and_defaults():
     assert o.power_tol == 1e-7 and o.margin == 0.01 and o.growth_tol == 1e-3
 
 
-def test_struct_layouts_match_header():
-    assert ctypes.sizeof(cpa.CpaShrinkage) == 40
-    assert ctypes.sizeof(cpa.CpaOpts) == 80
-    assert ctypes.sizeof(cpa.CpaInfo) == 56
-    assert ctypes.sizeof(cpa.CpaBatchedTuning) == 32
-    assert ctypes.sizeof(cpa.CpaSparsify) == 24
+def test_struct_layouts_match_header(tmp_path):
+    """Every field offset and struct size of the ctypes declarations equals what
+    a C compiler makes of include/cpasvt.h."""
+    import subprocess
+    structs = {"cpa_shrinkage": cpa.CpaShrinkage, "cpa_opts": cpa.CpaOpts, "cpa_info": cpa.CpaInfo,
+               "cpa_batched_tuning": cpa.CpaBatchedTuning, "cpa_sparsify": cpa.CpaSparsify}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "cpasvt.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(cpa.HEADER_PATH), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "sizeof")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 @pytest.mark.parametrize("kind,tau", [(0, 1.3), (1, 0.9), (2, 2.0)])

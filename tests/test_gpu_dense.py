@@ -426,3 +426,101 @@ def test_polynomial_route_symmetric_products(shape):
         got, info = _run(X, cpa.soft(tau), K, Lam, ev="polynomial")
         ref = ocpa.cpa_shrink(X, Shrinkage(0, tau), Lam, K)
         parity.check(got, ref, TOL32, X, f"symmetric products {m}x{n} K={K}")
+
+
+def test_non_finite_input():
+    """A NaN or an infinity in X: synchronising calls (info, check) return
+    CPA_ERR_NONFINITE, whatever the bound rule; an asynchronous call cannot
+    report it and the NaN propagates into Y (as the header states)."""
+    torch = _torch()
+    cpa = _lib()
+    X = synth.as_f32_exact(synth.dense_lowrank(130, 70, rank=4, seed=76)).astype(np.float32)
+    for bad in (float("nan"), float("inf"), -float("inf")):
+        Xb = X.copy()
+        Xb[17, 33] = bad
+        Xd = torch.from_numpy(Xb).cuda()
+        for opts in (cpa.Opts(K=12), cpa.Opts(K=12, Lambda=100.0), cpa.Opts(K=12, bound="frobenius"),
+                     cpa.Opts(K=12, eval="recurrence")):
+            with pytest.raises(cpa.CpaError) as e:
+                cpa.shrink_dense(Xd, cpa.soft(1.0), opts, info=True)
+            assert e.value.status == cpa.ERR_NONFINITE, (bad, opts)
+        with pytest.raises(cpa.CpaError) as e:
+            cpa.shrink_dense(Xd, cpa.soft(1.0), cpa.Opts(K=12, check=True))
+        assert e.value.status == cpa.ERR_NONFINITE
+        Y = cpa.shrink_dense(Xd, cpa.soft(1.0), cpa.Opts(K=12))
+        torch.cuda.synchronize()
+        assert not torch.isfinite(Y).all()
+    # the sparse path reports it too (through info)
+    rowptr = np.array([0, 1, 2, 3], dtype=np.int32)
+    vals = np.array([1.0, float("nan"), 2.0], dtype=np.float32)
+    with pytest.raises(cpa.CpaError) as e:
+        cpa.shrink_csr(3, 3, torch.from_numpy(rowptr).cuda(), torch.from_numpy(np.array([0, 1, 2], np.int32)).cuda(),
+                       torch.from_numpy(vals).cuda(), cpa.soft(0.1), cpa.Opts(K=5), info=True)
+    assert e.value.status == cpa.ERR_NONFINITE
+
+
+def _model(seed, X, bias0=None):
+    """A predictor model whose input normalisation centres X's features."""
+    from oracle import mlp as omlp
+    from paper_1705_07112_amd import predictor
+    f = omlp.features(X)
+    m = predictor.init_model(seed, f - np.array([0.7, -0.4, 0.9]), np.ones(3))
+    g = synth.rng(seed)
+    m[192:256] = g.uniform(-0.3, 0.3, 64)      # hidden biases, so every layer matters
+    m[4352:4416] = g.uniform(-0.3, 0.3, 64)
+    m[4544] = -0.4
+    if bias0 is not None:
+        m[4416:4480] = 0.0        # y0 = bias only
+        m[4544] = bias0
+    return m
+
+
+def test_learned_bound_rule():
+    """CPA_BOUND_LEARNED on the dense path: Lambda = (1 + margin) ||G||_F exp(min(y0, 0))
+    from the network on (log ||X||_F, log ||G||_F^2, log mn), against the oracle
+    network; the shrink at that Lambda against the oracle; a network that says
+    Lambda = 0.05 ||G||_F (below lambda_max) is caught by the check and the result
+    recomputed at the power bound; the allocation-free entry point agrees; the
+    other paths refuse the rule."""
+    torch = _torch()
+    cpa = _lib()
+    from oracle import mlp as omlp
+    X = synth.as_f32_exact(synth.dense_lowrank(200, 150, rank=5, noise=0.2, seed=78))
+    Xd = torch.from_numpy(X.astype(np.float32)).cuda()
+    G = X.T @ X
+    fro = math.sqrt(float(np.sum(G * G)))
+    tau = 0.3 * math.sqrt(float(np.linalg.eigvalsh(G)[-1]))
+    for ev in ("polynomial", "recurrence"):
+        m = _model(91, X)
+        md = torch.from_numpy(m).cuda()
+        y = omlp.forward_model(m, omlp.features(X))[0]
+        lam_o = omlp.decide(y, fro, 0.01, 2, 64)[0]
+        Y, info = cpa.shrink_dense(Xd, cpa.soft(tau), cpa.Opts(K=20, bound="learned", model=md, eval=ev), info=True)
+        print(f"learned {ev}: Lambda gpu {info['Lambda']:.8g} oracle {lam_o:.8g} (y0 {y[0]:.4f})", flush=True)
+        assert y[0] < -0.05 and info["Lambda"] == pytest.approx(lam_o, rel=2e-5)
+        parity.check(Y.cpu().numpy(), ocpa.cpa_shrink(X, Shrinkage(0, tau), info["Lambda"], 20), TOL32, X,
+                      f"learned bound {ev}")
+        out = torch.empty_like(Xd)
+        cpa.shrink_dense_noalloc(Xd, cpa.soft(tau), cpa.Opts(K=20, bound="learned", model=md, eval=ev), out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, Y)
+        # a network that underestimates: check -> recompute at the power bound
+        low = torch.from_numpy(_model(92, X, bias0=-3.0)).cuda()
+        Y2, info2 = cpa.shrink_dense(Xd, cpa.soft(tau), cpa.Opts(K=20, bound="learned", model=low, eval=ev,
+                                                                 check=True), info=True)
+        lam_p, _ = cpa.spectral_bound(Xd, cpa.Opts(K=20))
+        print(f"  low network {ev}: fallback {info2['fallback']} Lambda {info2['Lambda']:.8g} power {lam_p:.8g}",
+              flush=True)
+        assert info2["fallback"] == 1 and info2["Lambda"] == pytest.approx(lam_p, rel=1e-12)
+        parity.check(Y2.cpu().numpy(), ocpa.cpa_shrink(X, Shrinkage(0, tau), info2["Lambda"], 20), TOL32, X,
+                     f"learned fallback {ev}")
+    lam_l, _ = cpa.spectral_bound(Xd, cpa.Opts(K=20, bound="learned", model=md))
+    assert lam_l == pytest.approx(lam_o, rel=2e-5)
+    with pytest.raises(cpa.CpaError) as e:
+        cpa.shrink_csr(3, 3, torch.tensor([0, 1, 2, 3], dtype=torch.int32, device="cuda"),
+                       torch.tensor([0, 1, 2], dtype=torch.int32, device="cuda"),
+                       torch.ones(3, device="cuda"), cpa.soft(0.1), cpa.Opts(K=5, bound="learned", model=md))
+    assert e.value.status == cpa.ERR_UNSUPPORTED
+    with pytest.raises(cpa.CpaError) as e:
+        cpa.shrink_dense(Xd, cpa.soft(tau), cpa.Opts(K=20, bound="learned"))
+    assert e.value.status == cpa.ERR_ARG
