@@ -109,11 +109,11 @@ typedef enum { CPA_PREC_FP32 = 0, CPA_PREC_BF16X3 = 1, CPA_PREC_FP64 = 2 } cpa_p
  *   CPA_EVAL_POLYNOMIAL  the matrix polynomial on the d x d side first (Algorithm 1's
  *                        H), then one product with X.  The polynomial is formed with
  *                        baby steps / giant steps in the Chebyshev basis: T_1..T_s by
- *                        the recurrence (s = ceil(sqrt K), at most 16), then
+ *                        the recurrence (s = ceil(sqrt K), at most 32), then
  *                        p = sum_j R_j T_j(T_s) by Clenshaw's recurrence, using
  *                        T_j(T_s(x)) = T_{js}(x): about 2 sqrt(K) products of d x d x d.
- *                        Same polynomial; rounding differs.  K <= 256.
- *   CPA_EVAL_AUTO        POLYNOMIAL when K <= 256 and it costs fewer flops,
+ *                        Same polynomial; rounding differs.  K <= 1024.
+ *   CPA_EVAL_AUTO        POLYNOMIAL when K <= 1024 and it costs fewer flops,
  *                        otherwise RECURRENCE. */
 typedef enum { CPA_EVAL_AUTO = 0, CPA_EVAL_RECURRENCE = 1, CPA_EVAL_POLYNOMIAL = 2 } cpa_eval;
 
@@ -419,11 +419,11 @@ cpa_status cpa_shrink_batched(cpa_ctx* ctx, void* stream, int batch, const int32
  * hat H is computed on the rows of the truncated matrix that keep an entry: an
  * empty row (and, by symmetry, column) is an eigenvector with eigenvalue 0, where
  * hat H is hat h(0).  opts->eval selects how:
- *   AUTO / POLYNOMIAL (2 <= K <= 256): the bound and the baby-step / giant-step
+ *   AUTO / POLYNOMIAL (2 <= K <= 1024): the bound and the baby-step / giant-step
  *     matrix polynomial on that block as a dense matrix (zero-padded to full
  *     64 x 64 tiles).  Its size is read back once: the call waits for the
  *     stream once, after the truncation.
- *   RECURRENCE (and K = 1 or K > 256): Algorithm 1's recurrence with the block
+ *   RECURRENCE (and K = 1 or K > 1024): Algorithm 1's recurrence with the block
  *     stored sparse (one sparse-dense product per step), the bound on the whole
  *     truncated matrix; no wait unless info/eps/nnz are requested.
  *   transform: CPA_TRANSFORM_BLOCK_DCT8 (the 8 x 8 block DCT, T = kron(I, D_8)),

@@ -448,8 +448,8 @@ cpa_status check_opts(const cpa_opts* o) {
     if (o->precision != CPA_PREC_FP32 && o->precision != CPA_PREC_BF16X3)
         return fail(CPA_ERR_UNSUPPORTED, "precision %d not supported", o->precision);
     if (o->eval < CPA_EVAL_AUTO || o->eval > CPA_EVAL_POLYNOMIAL) return fail(CPA_ERR_ARG, "unknown eval %d", o->eval);
-    if (o->eval == CPA_EVAL_POLYNOMIAL && o->K > 256)
-        return fail(CPA_ERR_UNSUPPORTED, "the matrix-polynomial route supports K <= 256");
+    if (o->eval == CPA_EVAL_POLYNOMIAL && o->K > kPsMaxS * kPsMaxS)
+        return fail(CPA_ERR_UNSUPPORTED, "the matrix-polynomial route supports K <= %d", kPsMaxS * kPsMaxS);
     if (o->side < CPA_SIDE_AUTO || o->side > CPA_SIDE_LEFT) return fail(CPA_ERR_ARG, "unknown side %d", o->side);
     if (o->damping < CPA_DAMP_NONE || o->damping > CPA_DAMP_LANCZOS)
         return fail(CPA_ERR_ARG, "unknown damping %d", o->damping);
@@ -617,7 +617,7 @@ cpa_status enqueue_recurrence(cpa_ctx* ctx, hipStream_t st, int m, int n, const 
 //   T_1 = Ghat, T_{i+1} = 2 T_1 T_i - T_{i-1}            (i < s: s - 1 products)
 //   p = sum_j R_j T_j(y), y = T_s, R_j = sum_i r_{j,i} T_i   (Clenshaw in y: J - 1 products)
 //   Y = X p (right side) or p X (left side)                 (one product)
-// with s = ceil(sqrt(K)) and J = ceil(K / s) (K <= 256, so s, J <= 16): about
+// with s = ceil(sqrt(K)) and J = ceil(K / s) (K <= 1024, so s, J <= 32): about
 // 2 sqrt(K) products instead of K - 1.  All matrices of the route are polynomials
 // in Ghat, hence symmetric in exact arithmetic, and the engine reads the second
 // operand along k, i.e. transposed.  Only the fixed operands (T_1 in the baby
@@ -626,7 +626,7 @@ cpa_status enqueue_recurrence(cpa_ctx* ctx, hipStream_t st, int m, int n, const 
 // the operand that changes from step to step lets its rounding asymmetry grow
 // (about 3e-5 at s = 10 in FP32, and relative errors near 1e-3 at K = 144).
 
-constexpr int kPolyMaxK = kPsMaxS * kPsMaxS;   // 256
+constexpr int kPolyMaxK = kPsMaxS * kPsMaxS;   // 1024
 
 int poly_s_of(int K) {
     int s = 1;
@@ -729,8 +729,13 @@ cpa_status enqueue_poly_core(cpa_ctx* ctx, hipStream_t st, int d, const float* G
         HIP_TRY(hipGetLastError());
     }
     // every R_j = sum_i r_{j,i} T_i in one pass
-    hipLaunchKernelGGL(ps_lincomb_kernel, dim3((int)std::min<int64_t>(4096, (dd / 4 + 255) / 256 + 1)), dim3(256), 0,
-                       st, d, s, J, (const float*)T1, (const double*)scal, roff, R);
+    const dim3 glc((int)std::min<int64_t>(4096, (dd / 4 + 255) / 256 + 1));
+    if (s <= 16)
+        hipLaunchKernelGGL(ps_lincomb_kernel<16>, glc, dim3(256), 0, st, d, s, J, (const float*)T1,
+                           (const double*)scal, roff, R);
+    else
+        hipLaunchKernelGGL(ps_lincomb_kernel<kPsMaxS>, glc, dim3(256), 0, st, d, s, J, (const float*)T1,
+                           (const double*)scal, roff, R);
     HIP_TRY(hipGetLastError());
     if (J == 1) {
         *F_out = R;

@@ -54,7 +54,7 @@ constexpr int kNormSlots = 64;   // partial-sum slots per growth-check norm
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kPsMaxS = 16;   // largest baby-step count of the matrix-polynomial route
+constexpr int kPsMaxS = 32;   // largest baby-step count of the matrix-polynomial route (K <= 1024)
 constexpr int kPsCheckWg = 64;   // workgroups of the matrix-polynomial route's a-posteriori check
 
 struct ScalarLayout {
@@ -488,9 +488,11 @@ __global__ void ps_check_kernel(int d, const float* G, int64_t ldg, const float*
 // R_j = r_{j,0} I + sum_{q=1}^{s-1} r_{j,q} T_q for every j < J in one pass: each
 // element of T_1..T_{s-1} is read once (T_q at T1 + (q - 1) d^2, pitch d) and R_j
 // goes to R + j d^2.  Four consecutive elements per thread (16-byte accesses when
-// d % 4 == 0).
+// d % 4 == 0).  MAXS >= s: the register block of the T_q (launched with 16 for
+// s <= 16, else 32).
+template <int MAXS>
 __global__ void ps_lincomb_kernel(int d, int s, int J, const float* T1, const double* scal, int roff, float* R) {
-    __shared__ float rc[kPsMaxS * kPsMaxS];
+    __shared__ float rc[MAXS * MAXS];
     for (int k = threadIdx.x; k < J * s; k += blockDim.x) rc[k] = (float)scal[roff + k];
     __syncthreads();
     const int64_t dd = (int64_t)d * d;
@@ -498,9 +500,9 @@ __global__ void ps_lincomb_kernel(int d, int s, int J, const float* T1, const do
     const int64_t nq = (dd + 3) / 4;
     for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < nq; g += (int64_t)gridDim.x * blockDim.x) {
         const int64_t p0 = 4 * g;
-        f32x4 t[kPsMaxS];
+        f32x4 t[MAXS];
 #pragma unroll
-        for (int q = 1; q < kPsMaxS; ++q) {
+        for (int q = 1; q < MAXS; ++q) {
             t[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
             if (q < s) {
                 const float* src = T1 + (int64_t)(q - 1) * dd + p0;
@@ -520,7 +522,7 @@ __global__ void ps_lincomb_kernel(int d, int s, int J, const float* T1, const do
                 v[e] = (p / d == p % d) ? rc[j * s] : 0.f;
             }
 #pragma unroll
-            for (int q = 1; q < kPsMaxS; ++q)
+            for (int q = 1; q < MAXS; ++q)
                 if (q < s) v += rc[j * s + q] * t[q];
             float* dst = R + (int64_t)j * dd + p0;
             if (vec) {

@@ -244,7 +244,7 @@ def test_polynomial_route_limits_and_check():
     cpa = _lib()
     Xd = torch.ones((8, 4), device="cuda")
     with pytest.raises(cpa.CpaError):
-        cpa.shrink_dense(Xd, cpa.soft(0.1), cpa.Opts(K=257, eval="polynomial"))
+        cpa.shrink_dense(Xd, cpa.soft(0.1), cpa.Opts(K=1025, eval="polynomial"))
     # the recurrence reports its growth, the polynomial route its weighted means (<= 1)
     _, info = cpa.shrink_dense(Xd, cpa.soft(0.1), cpa.Opts(K=9, check=True, eval="recurrence"), info=True)
     assert info["max_growth"] > 0.0
@@ -524,3 +524,33 @@ def test_learned_bound_rule():
     with pytest.raises(cpa.CpaError) as e:
         cpa.shrink_dense(Xd, cpa.soft(tau), cpa.Opts(K=20, bound="learned"))
     assert e.value.status == cpa.ERR_ARG
+
+
+@pytest.mark.parametrize("K,damping", [(300, "none"), (512, "lanczos"), (1024, "none")])
+def test_polynomial_route_high_orders(K, damping):
+    """Orders beyond 256 on the matrix-polynomial route (s = ceil(sqrt K) up to
+    32 baby steps): both Gram sides against the oracle."""
+    cpa = _lib()
+    for m, n in ((150, 100), (90, 140)):
+        X = synth.as_f32_exact(synth.dense_lowrank(m, n, rank=5, noise=0.2, seed=7700 + K + m))
+        lmax = _gram_lmax(X)
+        Lam, tau = 1.01 * lmax, 0.3 * math.sqrt(lmax)
+        torch = _torch()
+        Y = cpa.shrink_dense(torch.from_numpy(X.astype(np.float32)).cuda(), cpa.soft(tau),
+                             cpa.Opts(K=K, Lambda=Lam, eval="polynomial", damping=damping)).cpu().numpy()
+        ref = ocpa.cpa_shrink(X, Shrinkage(0, tau), Lam, K, damping=damping)
+        parity.check(Y, ref, TOL32, X, f"polynomial K={K} {damping} {m}x{n}")
+
+
+def test_high_order_on_rpca_frames():
+    """K = 360 on the 1024 x 1024 frames (the order at which this workload's CPA
+    meets 1e-3 against the exact shrinkage): sampled rows against the oracle."""
+    torch = _torch()
+    cpa = _lib()
+    I, _, _ = synth.rpca_frames()
+    X = I.astype(np.float64)
+    lam = obound.power_bound(X.T @ X, seed=0)[0]
+    Y = cpa.shrink_dense(torch.from_numpy(I).cuda(), cpa.soft(10.0), cpa.Opts(K=360, Lambda=lam)).cpu().numpy()
+    rows = np.array([0, 5, 511, 1023])
+    parity.check(Y[rows].astype(np.float64), ocpa.cpa_rows(X, Shrinkage(0, 10.0), lam, 360, rows), TOL32,
+                 label="frames K=360 sampled rows")
