@@ -41,24 +41,38 @@ def cpu_baseline(I, budget_s: float = 15.0, check=None, samples=None):
     the largest such error over each leg's sample is reported as well."""
     import numpy as np
     from oracle import drivers
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+    from threadpoolctl import threadpool_info, threadpool_limits
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
     X = I.astype(np.float64)
-    t0 = time.perf_counter()
-    done = 0
-    # run growing batches of iterations from the same start until the budget is used
-    while True:
-        drivers.rpca_admm(X, INV_RHO, ETA_OVER_RHO, 1, K)
-        done += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or done >= 50:
-            break
+
+    def timed(budget, cap):
+        # one ADMM iteration from the start state per call, until the budget is used
+        t0 = time.perf_counter()
+        done = 0
+        while True:
+            drivers.rpca_admm(X, INV_RHO, ETA_OVER_RHO, 1, K)
+            done += 1
+            el = time.perf_counter() - t0
+            if el >= budget or done >= cap:
+                return done, el
+
+    done, el = timed(budget_s, 50)
+    with threadpool_limits(limits=1):
+        done1, el1 = timed(0.8 * budget_s, 8)
+    cpu_model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     res = {"value": done / el, "unit": "matrices/s", "cores": int(threads), "kind": "oracle",
            "sample": f"{done} FP64 oracle ADMM iterations (one shrink each: Algorithm 1 H-form, "
-                     f"K={K}, 1024x1024) in {el:.1f} s"}
+                     f"K={K}, 1024x1024) in {el:.1f} s on {threads} BLAS threads",
+           "single_thread": {"value": done1 / el1, "unit": "matrices/s", "cores": 1,
+                             "sample": f"{done1} of the same iterations in {el1:.1f} s, BLAS limited to one thread"},
+           "cpu_model": cpu_model, "host_cpus": os.cpu_count()}
     if check is not None:
         from oracle import cpa as ocpa
         from oracle import metrics
@@ -110,9 +124,48 @@ def exact_shrink(X, g):
 
 
 def rel_fro(A, B, scale):
+    """||A - B||_F / ||scale||_F (the accuracy legs pass the reference itself as scale)."""
     import numpy as np
     d = float(np.linalg.norm(scale))
     return float(np.linalg.norm(A - B)) / (d if d > 0 else 1.0)
+
+
+K_METRIC = 512
+
+
+def bench_metric_order(cpa, torch, np, Id, args):
+    """RPCA ADMM of the headline workload at K = K_METRIC, with the error of its shrink
+    against the exact soft shrinkage at the start and the end of the timed window."""
+    def shrink_error(run):
+        Xd = (run.block(0) + run.block(4)).contiguous()
+        Y = cpa.shrink_dense(Xd, cpa.soft(INV_RHO), cpa.Opts(K=K_METRIC)).cpu().numpy().astype(np.float64)
+        X64 = Xd.cpu().numpy().astype(np.float64)
+        ex = exact_shrink(X64, lambda sv: np.maximum(sv - INV_RHO, 0.0))
+        return rel_fro(Y, ex, ex)
+
+    run = cpa.RpcaAdmm(Id, INV_RHO, ETA_OVER_RHO, cpa.Opts(K=K_METRIC, warm_start=True, power_iters=100))
+    Et = torch.zeros(max(args.warmup, args.steps, 1), dtype=torch.float64, device=Id.device)
+    run.iterate(max(args.warmup, 1), Et)
+    torch.cuda.synchronize()
+    e0 = shrink_error(run)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    run.iterate(args.steps, Et)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    e1 = shrink_error(run)
+    s_ps = math.isqrt(K_METRIC - 1) + 1
+    j_ps = -(-K_METRIC // s_ps)
+    return {"K": K_METRIC, "value": round(args.steps / (ms / 1e3), 3), "unit": "matrices/s",
+            "ms_per_step": round(ms / args.steps, 4),
+            "err_vs_fp64_svt": [float("%.3e" % e0), float("%.3e" % e1)],
+            "meets_metric": bool(max(e0, e1) <= 1e-3),
+            "products_per_shrink": 1 + (s_ps - 1) + (j_ps - 1) + 1,
+            "note": "same ADMM workload at the order whose CPA is within 1e-3 of the exact shrinkage (errors on "
+                    "the iterates opening and closing the timed window); matrix-polynomial route, "
+                    f"s={s_ps}, J={j_ps}"}
 
 
 def bench_batched(cpa, torch, np, synth, timed_runs: int = 10):
@@ -187,8 +240,8 @@ def bench_batched(cpa, torch, np, synth, timed_runs: int = 10):
             w = r.w_c / (np.sqrt(np.maximum(sv * sv - r.w_sigma, 0.0)) + r.w_eps)
             return np.where(sv > w, sv - w, 0.0)
         ex = exact_shrink(Xi, g)
-        e_svt.append(rel_fro(Yi, ex, Xi))
-        e_svt_split.append(rel_fro(Ys, ex, Xi))
+        e_svt.append(rel_fro(Yi, ex, ex))
+        e_svt_split.append(rel_fro(Ys, ex, ex))
         rec = (3, 0.0, r.w_c, r.w_sigma, r.w_eps)
         SAMPLES.setdefault("batched_fp32", []).append((Xi, Yi, rec, float(lam[i].item()), 16))
         SAMPLES.setdefault("batched_bf16x3", []).append((Xi, Ys, rec, float(lam_sp[i].item()), 16))
@@ -333,7 +386,7 @@ def bench_sparsified(cpa, torch, np, synth, reps: int = 10):
     opts = cpa.Opts(K=K)
     Yd = torch.empty_like(X)
     ms_dense = timed(lambda: cpa.shrink_dense(X, cpa.soft(tau), opts, out=Yd))
-    dense_err = rel_fro(Yd.cpu().numpy().astype(np.float64), ex, X64)
+    dense_err = rel_fro(Yd.cpu().numpy().astype(np.float64), ex, ex)
     out = {"workload": "1024 x 1024 block-smooth (rank 4, 8-blocks) + N(0,1e-3^2), block DCT 8x8, K=30, soft "
                        "tau = 0.2 sigma_1, power bound",
            "dense_polynomial_route": {"ms_per_shrink": round(ms_dense, 4), "err_vs_fp64_svt": float("%.3e" % dense_err)},
@@ -349,7 +402,7 @@ def bench_sparsified(cpa, torch, np, synth, reps: int = 10):
         out["keep"].append({"fraction": frac, "keep": keep, "nnz": info["nnz"], "eps": float("%.5e" % info["eps"]),
                             "ms_per_shrink": round(ms_s, 4), "speedup_vs_dense": round(ms_dense / ms_s, 3),
                             "sparse_recurrence_ms_per_shrink": round(ms_r, 4),
-                            "err_vs_fp64_svt": float("%.3e" % rel_fro(Yh, ex, X64)),
+                            "err_vs_fp64_svt": float("%.3e" % rel_fro(Yh, ex, ex)),
                             "err_vs_dense_route": float("%.3e" % rel_fro(Yh, Yd.cpu().numpy().astype(np.float64),
                                                                          X64))})
     return out
@@ -544,6 +597,7 @@ def main():
     ap.add_argument("--no-predictor", action="store_true")
     ap.add_argument("--no-sparsified", action="store_true")
     ap.add_argument("--no-inpaint", action="store_true")
+    ap.add_argument("--no-metric-order", action="store_true", help="skip the K = 512 leg at the metric's error bar")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -625,7 +679,6 @@ def main():
     j_ps = -(-K // s_ps)
     products = 1 + (s_ps - 1) + (j_ps - 1) + 1
     flop_shrink = products * flop_gemm
-    flop_shrink_rec = K * flop_gemm
     ms_per_step = ms / args.steps
     value = args.steps / (ms / 1e3)
     rec_avg_us = 1e3 * rec_ms / max(rec_n, 1)
@@ -650,7 +703,6 @@ def main():
         "tflops": round(flop_shrink * value / 1e12, 3),
         "tflops_note": f"executed: {products} products of 2 x 1024^3 per shrink (Gram + matrix polynomial, "
                        f"s={s_ps}, J={j_ps}); the recurrence over X would execute {K}",
-        "tflops_recurrence_equivalent": round(flop_shrink_rec * value / 1e12, 3),
         "wall_s_timed": round(wall, 4),
         "roofline": {"bound": "mfma", "kernel": "matrix-polynomial GEMM, 1024^3 (FP32 MFMA, direct global-to-LDS copies, 16 waves, fused linear epilogue)",
                      "achieved": round(achieved, 3), "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
@@ -758,13 +810,19 @@ def main():
         X64 = Xd.cpu().numpy().astype(np.float64)
         Y = Yd.cpu().numpy().astype(np.float64)
         ex = exact_shrink(X64, lambda sv: np.maximum(sv - INV_RHO, 0.0))
-        out["err_vs_fp64_svt"] = float("%.3e" % rel_fro(Y, ex, X64))
+        out["err_vs_fp64_svt"] = float("%.3e" % rel_fro(Y, ex, ex))
         Y2 = cpa.shrink_dense(Xd, cpa.soft(INV_RHO), cpa.Opts(K=K, Lambda=info["Lambda"], precision="bf16x3"))
         Y2 = Y2.cpu().numpy().astype(np.float64)
-        out["bf16x3"]["err_vs_fp64_svt"] = float("%.3e" % rel_fro(Y2, ex, X64))
+        out["bf16x3"]["err_vs_fp64_svt"] = float("%.3e" % rel_fro(Y2, ex, ex))
         out["E_t_last"] = float("%.3e" % Et[args.steps - 1].item())
         check = (X64, {"fp32": Y, "bf16x3": Y2}, info["Lambda"])
 
+    # the same ADMM at the order where this workload's CPA meets the metric's error bar
+    # (<= 1e-3 relative Frobenius against the exact shrinkage): K = 512 on the matrix-
+    # polynomial route; the error is measured on the iterates that open and close the
+    # timed window (LAPACK SVD of l + u1 on the host)
+    if not args.no_metric_order:
+        out["at_metric_error"] = bench_metric_order(cpa, torch, np, Id, args)
     progress("dense RPCA legs done")
     if not args.no_batched:
         out["batched"] = bench_batched(cpa, torch, np, synth)
