@@ -733,6 +733,9 @@ cpa_status enqueue_poly_core(cpa_ctx* ctx, hipStream_t st, int d, const float* G
     if (s <= 16)
         hipLaunchKernelGGL(ps_lincomb_kernel<16>, glc, dim3(256), 0, st, d, s, J, (const float*)T1,
                            (const double*)scal, roff, R);
+    else if (s <= 24)
+        hipLaunchKernelGGL(ps_lincomb_kernel<24>, glc, dim3(256), 0, st, d, s, J, (const float*)T1,
+                           (const double*)scal, roff, R);
     else
         hipLaunchKernelGGL(ps_lincomb_kernel<kPsMaxS>, glc, dim3(256), 0, st, d, s, J, (const float*)T1,
                            (const double*)scal, roff, R);

@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(kPowerThreads) power_coop_kernel(int d, const 
     }
 }
 
-constexpr int kCoefLds = 64;   // orders up to this use the parallel coefficient path
+constexpr int kCoefLds = 1024;   // orders up to this use the cosine-table coefficient path
 
 // Bound rule + coefficients + recurrence scalars.  Single workgroup.
 //   mode 0: power iteration result (products 1..maxit in the slots)
@@ -372,24 +372,28 @@ __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int ma
     __syncthreads();
     const double Lam = sLambda;
     if (K <= kCoefLds) {
-        // the K x K terms cos(k theta_l) h(x_l) in parallel, then each c_k sums its
-        // row with l ascending (the order of the definition)
+        // k theta_l = pi k (2l + 1) / (2K): only the 4K angles pi m / (2K), m = k (2l + 1)
+        // mod 4K, occur, so their cosines are tabled once, h is evaluated once per node,
+        // and each c_k sums its row with l ascending (the order of the definition)
+        __shared__ double ctab[4 * kCoefLds];
         __shared__ double hval[kCoefLds];
-        __shared__ double term[kCoefLds * kCoefLds];
         const double pi = 3.14159265358979323846;
+        const int M4 = 4 * K;
+        for (int m = threadIdx.x; m < M4; m += blockDim.x) ctab[m] = cos(pi * m / (2.0 * K));
         for (int l = threadIdx.x; l < K; l += blockDim.x) {
             const double th = pi * (l + 0.5) / K;
             hval[l] = Lam > 0.0 ? shrink_h(sp, 0.5 * Lam * (cos(th) + 1.0)) : 0.0;
         }
         __syncthreads();
-        for (int p = threadIdx.x; p < K * K; p += blockDim.x) {
-            const int k = p / K, l = p % K;
-            term[p] = cos(k * (pi * (l + 0.5) / K)) * hval[l];
-        }
-        __syncthreads();
         for (int k = threadIdx.x; k < K; k += blockDim.x) {
             double acc = 0.0;
-            for (int l = 0; l < K; ++l) acc += term[k * K + l];
+            int idx = k;                       // k (2l + 1) mod 4K at l = 0
+            const int step = (2 * k) % M4;
+            for (int l = 0; l < K; ++l) {
+                acc += ctab[idx] * hval[l];
+                idx += step;
+                if (idx >= M4) idx -= M4;
+            }
             scal[SC_COEF + k] = Lam > 0.0 ? 2.0 / K * acc * damping_factor(damping, K, k) : 0.0;
         }
     } else {
@@ -488,8 +492,8 @@ __global__ void ps_check_kernel(int d, const float* G, int64_t ldg, const float*
 // R_j = r_{j,0} I + sum_{q=1}^{s-1} r_{j,q} T_q for every j < J in one pass: each
 // element of T_1..T_{s-1} is read once (T_q at T1 + (q - 1) d^2, pitch d) and R_j
 // goes to R + j d^2.  Four consecutive elements per thread (16-byte accesses when
-// d % 4 == 0).  MAXS >= s: the register block of the T_q (launched with 16 for
-// s <= 16, else 32).
+// d % 4 == 0).  MAXS >= s: the register block of the T_q (launched with 16, 24
+// or 32, the smallest that holds s).
 template <int MAXS>
 __global__ void ps_lincomb_kernel(int d, int s, int J, const float* T1, const double* scal, int roff, float* R) {
     __shared__ float rc[MAXS * MAXS];
