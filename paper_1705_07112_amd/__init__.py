@@ -734,8 +734,8 @@ class Inpaint:
         self.inv_rho, self.eta_over_rho, self.opts = float(inv_rho), float(eta_over_rho), opts
         count = lib().cpa_inpaint_state_floats(m, n)
         self.state = torch.empty(count, device=I.device, dtype=torch.float32)
-        self.ctx = context(I.device.index or 0)
-        _check(lib().cpa_inpaint_init(ctypes.c_void_p(self.ctx), _stream(I), m, n,
+        self.dev_index = I.device.index or 0
+        _check(lib().cpa_inpaint_init(ctypes.c_void_p(context(self.dev_index)), _stream(I), m, n,
                                       ctypes.c_void_p(self.omega.data_ptr()), ctypes.c_void_p(self.state.data_ptr())))
 
     def block(self, i: int):
@@ -751,7 +751,7 @@ class Inpaint:
         co = self.opts.to_c()
         ptr = ctypes.c_void_p(Et.data_ptr()) if Et is not None else None
         bptr = ctypes.c_void_p(self.border.data_ptr()) if self.border is not None else None
-        _check(lib().cpa_inpaint_iterate(ctypes.c_void_p(self.ctx), _stream(self.I), self.m, self.n,
+        _check(lib().cpa_inpaint_iterate(ctypes.c_void_p(context(self.dev_index)), _stream(self.I), self.m, self.n,
                                          ctypes.c_void_p(self.I.data_ptr()), ctypes.c_void_p(self.omega.data_ptr()),
                                          bptr, ctypes.c_void_p(self.state.data_ptr()), int(iters), self.inv_rho,
                                          self.eta_over_rho, ctypes.byref(co), ptr))
@@ -769,7 +769,7 @@ class Inpaint:
         keeps = (ctypes.c_int64 * max(int(iters), 1))()
         bptr = ctypes.c_void_p(self.border.data_ptr()) if self.border is not None else None
         _check(lib().cpa_inpaint_iterate_scheduled(
-            ctypes.c_void_p(self.ctx), _stream(self.I), self.m, self.n, ctypes.c_void_p(self.I.data_ptr()),
+            ctypes.c_void_p(context(self.dev_index)), _stream(self.I), self.m, self.n, ctypes.c_void_p(self.I.data_ptr()),
             ctypes.c_void_p(self.omega.data_ptr()), bptr, ctypes.c_void_p(self.state.data_ptr()), int(iters),
             self.inv_rho, self.eta_over_rho, ctypes.byref(co), _TRANSFORMS[transform], float(E_prev), float(E_l),
             float(E_m), ctypes.c_void_p(Et.data_ptr()), keeps))
@@ -791,9 +791,9 @@ class RpcaAdmm:
         self.inv_rho, self.eta_over_rho, self.opts = float(inv_rho), float(eta_over_rho), opts
         count = lib().cpa_rpca_state_floats(m, n)
         self.state = torch.empty(count, device=I.device, dtype=torch.float32)
-        self.ctx = context(I.device.index or 0)
+        self.dev_index = I.device.index or 0
         self.t = 0
-        _check(lib().cpa_rpca_init(ctypes.c_void_p(self.ctx), _stream(I), m, n,
+        _check(lib().cpa_rpca_init(ctypes.c_void_p(context(self.dev_index)), _stream(I), m, n,
                                    ctypes.c_void_p(self.state.data_ptr())))
 
     def block(self, i: int):
@@ -812,7 +812,7 @@ class RpcaAdmm:
         """Runs ``iters`` iterations; ``Et`` (float64 CUDA tensor, >= iters) receives E_t."""
         co = self.opts.to_c()
         ptr = ctypes.c_void_p(Et.data_ptr()) if Et is not None else None
-        _check(lib().cpa_rpca_iterate(ctypes.c_void_p(self.ctx), _stream(self.I), self.m, self.n,
+        _check(lib().cpa_rpca_iterate(ctypes.c_void_p(context(self.dev_index)), _stream(self.I), self.m, self.n,
                                       ctypes.c_void_p(self.I.data_ptr()), ctypes.c_void_p(self.state.data_ptr()),
                                       int(iters), self.inv_rho, self.eta_over_rho, ctypes.byref(co), ptr))
         self.t += iters

@@ -97,6 +97,7 @@ struct cpa_ctx {
     size_t spf_bytes = 0;
     int spf_dct_d = 0;         // the full-DCT matrices in spf are built for this side (0: none)
     int spf_last_d = 0;        // the side of the last sparsified call (the layout depends on it)
+    int spf_warm_d = -1;       // side of the full-coordinate warm vector in spf (-1: none)
     void* inp = nullptr;       // inpainting driver: DCT matrices, product scratch, partial sums
     size_t inp_bytes = 0;
     void* f64 = nullptr;       // FP64 shrink: Gram, two Y buffers, product buffer
@@ -2346,6 +2347,7 @@ struct SpfWork {
     int32_t* nrows;  // 1
     float* Dm;       // d x d, the full DCT (dense transform only, else null)
     float* Dt;       // its transpose
+    double* warm;    // d: the compact block's power vector in full coordinates (warm start)
 };
 
 cpa_status ensure_spf(cpa_ctx* ctx, int d, bool dense_t, SpfWork& s) {
@@ -2365,16 +2367,22 @@ cpa_status ensure_spf(cpa_ctx* ctx, int d, bool dense_t, SpfWork& s) {
     const size_t oPos = off; off = align_up(off + sizeof(int32_t) * d);
     const size_t oRows = off; off = align_up(off + sizeof(int32_t) * d);
     const size_t oN = off; off = align_up(off + sizeof(int32_t));
+    const size_t oW = off; off = align_up(off + sizeof(double) * d);
     size_t oDm = 0, oDt = 0;
     if (dense_t) {
         oDm = off; off = align_up(off + sizeof(float) * dd);
         oDt = off; off = align_up(off + sizeof(float) * dd);
     }
-    // another side moves every buffer: the DCT matrices must be rebuilt
-    if (d != ctx->spf_last_d) ctx->spf_dct_d = 0;
+    // another side moves every buffer: the DCT matrices must be rebuilt and the warm
+    // vector is gone
+    if (d != ctx->spf_last_d) {
+        ctx->spf_dct_d = 0;
+        ctx->spf_warm_d = -1;
+    }
     ctx->spf_last_d = d;
     if (off > ctx->spf_bytes) {
         ctx->spf_dct_d = 0;
+        ctx->spf_warm_d = -1;
         if (ctx->spf) {
             HIP_TRY(hipDeviceSynchronize());
             HIP_TRY(hipFree(ctx->spf));
@@ -2404,6 +2412,7 @@ cpa_status ensure_spf(cpa_ctx* ctx, int d, bool dense_t, SpfWork& s) {
     s.nrows = reinterpret_cast<int32_t*>(b + oN);
     s.Dm = dense_t ? reinterpret_cast<float*>(b + oDm) : nullptr;
     s.Dt = dense_t ? reinterpret_cast<float*>(b + oDt) : nullptr;
+    s.warm = reinterpret_cast<double*>(b + oW);
     return CPA_OK;
 }
 
@@ -2592,7 +2601,26 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
         Work wc = w;
         wc.d = nb;
         wc.lay.pwg = power_grid(ctx, nb);
+        // warm start: the previous call's vector, mapped from full coordinates onto this
+        // call's block
+        const bool warm_map = opts->warm_start && opts->bound == CPA_BOUND_POWER;
+        if (warm_map) {
+            if (ctx->spf_warm_d == d) {
+                hipLaunchKernelGGL(warm_gather_kernel, dim3((nb + 255) / 256), dim3(256), 0, st, ns, nb,
+                                   (const int32_t*)f.rows, (const double*)f.warm, ctx->warm);
+                HIP_TRY(hipGetLastError());
+                ctx->warm_d = nb;
+            } else {
+                ctx->warm_d = -1;
+            }
+        }
         if ((s = enqueue_bound(ctx, st, nb, shrink, opts, wc, -1)) != CPA_OK) return s;
+        if (warm_map) {
+            hipLaunchKernelGGL(warm_scatter_kernel, dim3((d + 255) / 256), dim3(256), 0, st, d,
+                               (const int32_t*)f.pos, (const double*)ctx->warm, f.warm);
+            HIP_TRY(hipGetLastError());
+            ctx->spf_warm_d = d;
+        }
         float* F = nullptr;
         if ((s = enqueue_poly_core(ctx, st, nb, w.G, nb, w.scal, wc.lay.ps(), w.poly, ps, opts->K, CPA_PREC_FP32,
                                    &F, poly_fused(wc, opts->K))) != CPA_OK)

@@ -476,4 +476,19 @@ __global__ void eye_compact_kernel(const int32_t* nrows, float* P, int64_t ld) {
     }
 }
 
+// Warm start of the compact block's power iteration across calls, kept in the
+// coordinates of the full transformed Gram (the block's rows change from call to
+// call): before the bound, compact[i] = full[rows[i]] for the ns kept rows and 0 on
+// the padding rows up to nb; after it, full[j] = compact[pos[j]] on kept rows, 0 on
+// empty ones.
+__global__ void warm_gather_kernel(int ns, int nb, const int32_t* rows, const double* full, double* compact) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += gridDim.x * blockDim.x)
+        compact[i] = i < ns ? full[rows[i]] : 0.0;
+}
+
+__global__ void warm_scatter_kernel(int d, const int32_t* pos, const double* compact, double* full) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d; j += gridDim.x * blockDim.x)
+        full[j] = pos[j] >= 0 ? compact[pos[j]] : 0.0;
+}
+
 }  // namespace cpa

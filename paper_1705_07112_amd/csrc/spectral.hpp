@@ -91,10 +91,19 @@ __device__ inline double block_sum(double v, double* red) {
     return s;
 }
 
-// w0 = start vector; ||w0||^2 into pw_w2[0].  warm != nullptr: copy it.
+// w0 = start vector; ||w0||^2 into pw_w2[0].  warm != nullptr: copy it (unless its
+// norm is zero).
 // Single workgroup (fixed summation order).
 __global__ void power_init_kernel(int d, uint64_t seed, const double* warm, double* w0, double* scal, int pw_w2) {
     __shared__ double red[16];
+    if (warm) {
+        // a warm vector without weight (e.g. mapped from rows that are all gone) gives
+        // way to the seeded start
+        double wn = 0.0;
+        for (int i = threadIdx.x; i < d; i += blockDim.x) wn += warm[i] * warm[i];
+        wn = block_sum(wn, red);
+        if (!(wn > 0.0)) warm = nullptr;
+    }
     double acc = 0.0;
     for (int i = threadIdx.x; i < d; i += blockDim.x) {
         double v;

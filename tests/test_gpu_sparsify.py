@@ -349,3 +349,30 @@ def test_block_dct_full_size(ev):
     T = sparsify.block_dct(1024, 8)
     s1 = math.sqrt(float(np.linalg.eigvalsh(X.T @ X)[-1]))
     _case(X, T, "block_dct8", 0.016, 30, Shrinkage(0, 0.2 * s1), cpa.soft(0.2 * s1), ev=ev)
+
+
+def test_warm_start_maps_the_block_rows():
+    """opts.warm_start on the polynomial route: the compact block's power vector is
+    kept in the coordinates of the full transformed Gram and mapped onto the next
+    call's block.  A repeated call needs fewer products and gives the same bound to
+    the iteration's tolerance; a call on another input (other kept rows) still
+    matches the oracle at the bound it reports."""
+    import torch
+    cpa = _lib()
+    T = sparsify.block_dct(128, 8)
+    opts = cpa.Opts(K=20, warm_start=True, power_tol=1e-9, power_iters=300)
+    res = []
+    for seed in (9801, 9801, 9802):
+        X = synth.as_f32_exact(synth.block_smooth(256, 128, rank=4, noise=1e-3, seed=seed))
+        Phi, _ = sparsify.transformed_gram(X, T)
+        keep = _gap_keep(Phi, 0.02)
+        s1 = math.sqrt(float(np.linalg.eigvalsh(X.T @ X)[-1]))
+        Xd = torch.from_numpy(X.astype(np.float32)).cuda()
+        Y, info = cpa.shrink_dense_sparsified(Xd, cpa.soft(0.2 * s1), opts, keep=keep, info=True)
+        torch.cuda.synchronize()
+        ref, _, _ = sparsify.cpa_shrink_sparsified(X, Shrinkage(0, 0.2 * s1), info["Lambda"], 20, T, keep)
+        parity.check(Y.cpu().numpy().astype(np.float64), ref, TOL32, X, f"warm sparsified seed {seed}")
+        res.append(info)
+        print(f"  seed {seed}: power products {info['power_iters_done']} Lambda {info['Lambda']:.10g}", flush=True)
+    assert res[1]["power_iters_done"] < res[0]["power_iters_done"]
+    assert abs(res[1]["Lambda"] - res[0]["Lambda"]) <= 1e-7 * res[0]["Lambda"]
