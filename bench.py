@@ -168,6 +168,40 @@ def bench_metric_order(cpa, torch, np, Id, args):
                     f"s={s_ps}, J={j_ps}"}
 
 
+def bench_designs(cpa, torch, np, Xd, X64, ex, Lam, orders=(10, 20, 30, 50)):
+    """Other polynomial designs against CPA on the ADMM iterate (Sec. IV-B: least squares
+    and minimax, eq. l_p_norm_for_approximation): host FP64 coefficients
+    (cpa_design_coeffs) run through the same device evaluation (opts.coeffs) at the
+    same bound; error against the exact soft shrinkage, host design time, device time."""
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    out = {}
+    for K in orders:
+        row = {}
+        for kind in ("chebyshev", "lsq", "minimax"):
+            w0 = time.perf_counter()
+            c, resp_err = cpa.design_coeffs(cpa.soft(INV_RHO), Lam, K, kind)
+            design_ms = 1e3 * (time.perf_counter() - w0)
+            cd = torch.from_numpy(c).to(Xd.device)
+            o = cpa.Opts(K=K, bound="given", Lambda=Lam, coeffs=cd)
+            Y = cpa.shrink_dense(Xd, cpa.soft(INV_RHO), o)
+            torch.cuda.synchronize()
+            t0.record()
+            for _ in range(5):
+                cpa.shrink_dense(Xd, cpa.soft(INV_RHO), o)
+            t1.record()
+            torch.cuda.synchronize()
+            err = rel_fro(Y.cpu().numpy().astype(np.float64), ex, ex)
+            row[kind] = {"err_vs_fp64_svt": float("%.3e" % err), "response_err": float("%.3e" % resp_err),
+                         "design_ms": round(design_ms, 3), "shrink_ms": round(t0.elapsed_time(t1) / 5, 4)}
+        out[f"K{K}"] = row
+    out["note"] = ("soft shrinkage of the 1024 x 1024 ADMM iterate at its device bound; 'chebyshev' is CPA; "
+                   "lsq over 2000 uniform samples of [0, Lambda], minimax on an 8000-point Chebyshev-spaced grid "
+                   "(Remez); response_err: largest |h - p| on the design's own points (0 at CPA's nodes); "
+                   "same kernels for all three (given coefficients)")
+    return out
+
+
 def bench_batched(cpa, torch, np, synth, timed_runs: int = 10):
     """Batched weighted soft shrinkage of 8192 patch-group matrices (64 x U{40..120},
     rank 4 + N(0, 0.2^2)), K = 16, per-matrix power bound: one persistent launch,
@@ -643,6 +677,7 @@ def main():
     ap.add_argument("--no-sparsified", action="store_true")
     ap.add_argument("--no-inpaint", action="store_true")
     ap.add_argument("--no-metric-order", action="store_true", help="skip the K = 512 leg at the metric's error bar")
+    ap.add_argument("--no-designs", action="store_true", help="skip the least-squares / minimax comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -861,6 +896,8 @@ def main():
         out["bf16x3"]["err_vs_fp64_svt"] = float("%.3e" % rel_fro(Y2, ex, ex))
         out["E_t_last"] = float("%.3e" % Et[args.steps - 1].item())
         check = (X64, {"fp32": Y, "bf16x3": Y2}, info["Lambda"])
+        if not args.no_designs:
+            out["designs"] = bench_designs(cpa, torch, np, Xd, X64, ex, info["Lambda"])
 
     # the same ADMM at the order where this workload's CPA meets the metric's error bar
     # (<= 1e-3 relative Frobenius against the exact shrinkage): K = 512 on the matrix-

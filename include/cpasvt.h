@@ -160,6 +160,13 @@ typedef struct {
     int32_t reserved;     /* must be 0 */
     const float* model;   /* CPA_BOUND_LEARNED: the predictor model, CPA_PRED_MODEL_FLOATS floats in
                              device memory (caller-owned); ignored by the other rules */
+    const double* coeffs; /* NULL: the shrinkage's Chebyshev coefficients (Sec. III-A).  Else K
+                             doubles in device memory (caller-owned, read by the stream's kernels)
+                             used as c_0..c_{K-1} of p(x) = c_0/2 + sum_k c_k T_k(2x/Lambda - 1),
+                             e.g. another design from cpa_design_coeffs.  Needs CPA_BOUND_GIVEN
+                             (the coefficients belong to that Lambda), check = 0 and no damping;
+                             taken by cpa_shrink_dense, cpa_shrink_dense_noalloc and
+                             cpa_shrink_csr, CPA_ERR_UNSUPPORTED elsewhere */
 } cpa_opts;
 
 /* Per-call report (host struct).  Filling it synchronises the stream. */
@@ -201,6 +208,30 @@ void cpa_default_opts(cpa_opts* opts);
  *   theta_l = pi (l - 1/2) / K,  k = 0..K-1.
  * c_host must hold K doubles.  Lambda == 0 gives all zeros.  Pure host code. */
 cpa_status cpa_chebyshev_coeffs(const cpa_shrinkage* shrink, double Lambda, int K, double* c_host);
+
+/* Other polynomial designs of degree K - 1 on [0, Lambda] for the shrinkage's response h,
+ * the alternatives Sec. IV-B compares CPA with (eq. l_p_norm_for_approximation: p = 2 and
+ * p = infinity), returned in the convention of opts.coeffs so the same kernels evaluate them:
+ *   CPA_DESIGN_CHEBYSHEV  the CPA coefficients themselves (as cpa_chebyshev_coeffs; n unused)
+ *   CPA_DESIGN_LSQ        least squares over the n uniform samples x_i = Lambda i / (n - 1),
+ *                         i = 0..n-1 (n >= K, n >= 2; 2000 when n == 0), solved by Householder
+ *                         QR in the Chebyshev basis (the same polynomial as the paper's
+ *                         pseudo-inverse of the monomial Vandermonde matrix, without its
+ *                         ill-conditioning at large K)
+ *   CPA_DESIGN_MINIMAX    best uniform approximation on the n-point grid
+ *                         x_i = (Lambda/2)(1 - cos(pi i / (n - 1))) (n >= 2 K + 1; 8000 when
+ *                         n == 0) by the Remez exchange, started at the grid points nearest the
+ *                         extrema of T_K, stopped when the largest grid error is within a
+ *                         relative 1e-10 of the levelled error (at most 200 exchanges)
+ * c_host receives K doubles.  err_host (may be NULL) receives the largest |h - p| over the
+ * design's own points (samples, grid; the K Chebyshev nodes for CPA_DESIGN_CHEBYSHEV).
+ * Lambda == 0 gives all zeros.  Pure host code; O(n K^2) time.  Errors: CPA_ERR_ARG for an
+ * invalid shrinkage, Lambda, NULL c_host, unknown design or n out of range; K outside
+ * [1, 1024] (CPA_ERR_ARG); CPA_ERR_NONFINITE if a reference system of the exchange is
+ * singular. */
+typedef enum { CPA_DESIGN_CHEBYSHEV = 0, CPA_DESIGN_LSQ = 1, CPA_DESIGN_MINIMAX = 2 } cpa_design;
+cpa_status cpa_design_coeffs(const cpa_shrinkage* shrink, double Lambda, int K, int design, int n, double* c_host,
+                             double* err_host);
 
 /* The damping factors g_0..g_{K-1} of the kind (cpa_damping), host FP64; the
  * shrink uses c_k g_k.  Errors: K outside [1, 4096] or an unknown kind. */

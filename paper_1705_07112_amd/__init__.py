@@ -44,7 +44,7 @@ class CpaOpts(ctypes.Structure):
                 ("power_tol", ctypes.c_double), ("margin", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("check", ctypes.c_int32), ("precision", ctypes.c_int32), ("growth_tol", ctypes.c_double),
                 ("eval", ctypes.c_int32), ("side", ctypes.c_int32), ("damping", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("model", ctypes.c_void_p)]
+                ("reserved", ctypes.c_int32), ("model", ctypes.c_void_p), ("coeffs", ctypes.c_void_p)]
 
 
 class CpaInfo(ctypes.Structure):
@@ -93,6 +93,8 @@ _SIGS = {
     "cpa_damping_factors": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P]),
     "cpa_chebyshev_coeffs": (ctypes.c_int, [ctypes.POINTER(CpaShrinkage), ctypes.c_double, ctypes.c_int,
                                             ctypes.POINTER(ctypes.c_double)]),
+    "cpa_design_coeffs": (ctypes.c_int, [ctypes.POINTER(CpaShrinkage), ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "cpa_spectral_bound": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _I64, ctypes.POINTER(CpaOpts),
                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(CpaInfo)]),
     "cpa_shrink_dense": (ctypes.c_int, [_P, _P, ctypes.c_int, ctypes.c_int, _P, _I64, _P, _I64,
@@ -227,6 +229,7 @@ class Opts:
     side: str = "auto"           # "auto" | "right" (Gram X^T X) | "left" (Gram X X^T)
     damping: str = "none"        # "none" | "jackson" | "lanczos" (coefficient damping; not in the paper)
     model: object = None          # bound "learned": the predictor model (float32 CUDA tensor)
+    coeffs: object = None         # caller-given coefficients (float64 CUDA tensor of K entries; bound "given")
 
     def to_c(self) -> CpaOpts:
         o = CpaOpts()
@@ -242,6 +245,11 @@ class Opts:
                     or self.model.numel() != PRED_MODEL_FLOATS:
                 raise ValueError("model must be a contiguous float32 CUDA tensor of %d entries" % PRED_MODEL_FLOATS)
             o.model = self.model.data_ptr()
+        if self.coeffs is not None:
+            if self.coeffs.dtype.itemsize != 8 or not self.coeffs.is_cuda or not self.coeffs.is_contiguous() \
+                    or not self.coeffs.is_floating_point() or self.coeffs.numel() != int(self.K):
+                raise ValueError("coeffs must be a contiguous float64 CUDA tensor of K entries")
+            o.coeffs = self.coeffs.data_ptr()
         o.Lambda = float(self.Lambda or 0.0)
         o.power_iters = int(self.power_iters)
         o.warm_start = int(bool(self.warm_start))
@@ -312,6 +320,19 @@ def chebyshev_coeffs(shrink: CpaShrinkage, Lambda: float, K: int) -> np.ndarray:
     out = (ctypes.c_double * int(K))()
     _check(lib().cpa_chebyshev_coeffs(ctypes.byref(shrink), float(Lambda), int(K), out))
     return np.array(out[:], dtype=np.float64)
+
+
+DESIGNS = {"chebyshev": 0, "lsq": 1, "minimax": 2}
+
+
+def design_coeffs(shrink: CpaShrinkage, Lambda: float, K: int, design: str, n: int = 0):
+    """(coefficients, largest error on the design's points) of another polynomial design
+    (cpa_design_coeffs), in the convention Opts.coeffs takes."""
+    out = (ctypes.c_double * int(K))()
+    err = ctypes.c_double()
+    _check(lib().cpa_design_coeffs(ctypes.byref(shrink), float(Lambda), int(K), DESIGNS[design], int(n), out,
+                                   ctypes.byref(err)))
+    return np.array(out[:], dtype=np.float64), float(err.value)
 
 
 def damping_factors(K: int, kind: str = "jackson"):

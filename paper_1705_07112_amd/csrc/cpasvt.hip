@@ -19,6 +19,7 @@
 #include "../../include/cpasvt.h"
 #include "admm.hpp"
 #include "batched.hpp"
+#include "design.hpp"
 #include "sparse.hpp"
 #include "sparsify.hpp"
 #include "inpaint.hpp"
@@ -53,6 +54,9 @@ cpa_status fail(cpa_status s, const char* fmt, ...) {
 constexpr int kMaxPowerIters = 1000;
 constexpr int kAdmmGrid = 2048;   // workgroups of the ADMM elementwise kernels
 constexpr int kMaxK = 4096;
+constexpr int kMaxDesignK = 1024;        // cpa_design_coeffs orders
+constexpr int kMaxDesignN = 1 << 20;     // and sample / grid points
+constexpr int64_t kMaxDesignNK = int64_t(1) << 26;   // n K: 512 MiB of basis values
 
 }  // namespace
 
@@ -420,12 +424,25 @@ cpa_status check_shrinkage(const cpa_shrinkage* s) {
 }
 
 // The learned bound rule is the dense single-matrix paths' (the batched path
-// takes the predictor through cpa_shrink_batched_predicted).
-cpa_status no_learned_bound(const cpa_opts* o) {
+// takes the predictor through cpa_shrink_batched_predicted); caller-given
+// coefficients are the single-matrix FP32 shrinks' (dense and CSR).
+cpa_status no_given_coeffs(const cpa_opts* o) {
+    if (o->coeffs)
+        return fail(CPA_ERR_UNSUPPORTED, "caller-given coefficients are taken by cpa_shrink_dense(_noalloc) and "
+                                         "cpa_shrink_csr only");
+    return CPA_OK;
+}
+
+cpa_status learned_bound_unsupported(const cpa_opts* o) {
     if (o->bound == CPA_BOUND_LEARNED)
         return fail(CPA_ERR_UNSUPPORTED, "the learned bound rule is available on cpa_shrink_dense(_noalloc) and "
                                          "cpa_spectral_bound only");
     return CPA_OK;
+}
+
+cpa_status no_learned_bound(const cpa_opts* o) {
+    const cpa_status s = learned_bound_unsupported(o);
+    return s != CPA_OK ? s : no_given_coeffs(o);
 }
 
 // Power-iteration slots of the scalar block: the power rule, and the learned
@@ -455,6 +472,12 @@ cpa_status check_opts(const cpa_opts* o) {
     if (o->damping < CPA_DAMP_NONE || o->damping > CPA_DAMP_LANCZOS)
         return fail(CPA_ERR_ARG, "unknown damping %d", o->damping);
     if (o->reserved != 0) return fail(CPA_ERR_ARG, "opts.reserved must be 0");
+    if (o->coeffs) {
+        if (o->bound != CPA_BOUND_GIVEN)
+            return fail(CPA_ERR_ARG, "caller-given coefficients need the given bound (they belong to one Lambda)");
+        if (o->check || o->damping != CPA_DAMP_NONE)
+            return fail(CPA_ERR_UNSUPPORTED, "caller-given coefficients take neither the check nor damping");
+    }
     return CPA_OK;
 }
 
@@ -547,7 +570,7 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
                        (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? warm_vec : nullptr, w.scal,
                        to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)(w.scal + w.lay.gpart()),
                        w.lay.gwg, 0, o->damping, w.poly_s, poly_fused(w, o->K) ? w.lay.ps() : -1,
-                       mode == 3 ? o->model : nullptr, logmn);
+                       mode == 3 ? o->model : nullptr, logmn, o->coeffs);
     HIP_TRY(hipGetLastError());
     if (mode == 0) warm_len = d;
     return CPA_OK;
@@ -1122,7 +1145,7 @@ cpa_status shrink_csr_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t n
     hipLaunchKernelGGL(finish_bound_kernel, dim3(1), dim3(256), 0, st, mode, o->Lambda, n, o->power_iters, o->margin,
                        (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? ctx->warm : nullptr, w.scal,
                        to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)gpart, kSqGrid, 1, o->damping, 0, -1,
-                       nullptr, 0.0);
+                       nullptr, 0.0, o->coeffs);
     HIP_TRY(hipGetLastError());
     if (mode == 0) ctx->warm_d = n;
     const bool poly = w.poly_s > 0 && o->K >= 2;
@@ -1341,6 +1364,45 @@ cpa_status cpa_chebyshev_coeffs(const cpa_shrinkage* shrink, double Lambda, int 
     if (!(std::isfinite(Lambda) && Lambda >= 0.0)) return fail(CPA_ERR_ARG, "Lambda must be finite and >= 0");
     const ShrinkParams p = to_params(shrink);
     for (int k = 0; k < K; ++k) c_host[k] = cheb_coeff(p, Lambda, K, k);
+    return CPA_OK;
+}
+
+cpa_status cpa_design_coeffs(const cpa_shrinkage* shrink, double Lambda, int K, int design_kind, int n,
+                             double* c_host, double* err_host) {
+    cpa_status s = check_shrinkage(shrink);
+    if (s != CPA_OK) return s;
+    if (!c_host) return fail(CPA_ERR_ARG, "c_host is NULL");
+    if (K < 1 || K > kMaxDesignK) return fail(CPA_ERR_ARG, "K must be in [1, %d], got %d", kMaxDesignK, K);
+    if (!(std::isfinite(Lambda) && Lambda >= 0.0)) return fail(CPA_ERR_ARG, "Lambda must be finite and >= 0");
+    if (design_kind < CPA_DESIGN_CHEBYSHEV || design_kind > CPA_DESIGN_MINIMAX)
+        return fail(CPA_ERR_ARG, "unknown design %d", design_kind);
+    if (n == 0) n = design_kind == CPA_DESIGN_MINIMAX ? 8000 : 2000;
+    if (design_kind == CPA_DESIGN_LSQ && (n < K || n < 2 || n > kMaxDesignN))
+        return fail(CPA_ERR_ARG, "least squares needs K <= n <= %d samples (n >= 2), got %d", kMaxDesignN, n);
+    if (design_kind == CPA_DESIGN_MINIMAX && (n < 2 * K + 1 || n > kMaxDesignN))
+        return fail(CPA_ERR_ARG, "minimax needs 2 K + 1 <= n <= %d grid points, got %d", kMaxDesignN, n);
+    if (design_kind != CPA_DESIGN_CHEBYSHEV && (int64_t)n * K > kMaxDesignNK)
+        return fail(CPA_ERR_ARG, "n K = %lld exceeds %lld (the n x K basis matrix is held in host memory)",
+                    (long long)n * K, (long long)kMaxDesignNK);
+    const ShrinkParams p = to_params(shrink);
+    double err = 0.0;
+    if (!(Lambda > 0.0)) {
+        for (int k = 0; k < K; ++k) c_host[k] = 0.0;
+    } else if (design_kind == CPA_DESIGN_CHEBYSHEV) {
+        for (int k = 0; k < K; ++k) c_host[k] = cheb_coeff(p, Lambda, K, k);
+        for (int l = 0; l < K; ++l) {
+            const double th = design::kPi * (l + 0.5) / K;
+            double v = 0.5 * c_host[0];
+            for (int k = 1; k < K; ++k) v += c_host[k] * cos(k * th);
+            err = std::max(err, fabs(shrink_h(p, 0.5 * Lambda * (cos(th) + 1.0)) - v));
+        }
+    } else {
+        err = design_kind == CPA_DESIGN_LSQ ? design::lsq(p, Lambda, K, n, c_host)
+                                            : design::minimax(p, Lambda, K, n, 200, 1e-10, c_host);
+        if (err < 0.0) return fail(CPA_ERR_NONFINITE, "a reference system of the Remez exchange is singular");
+        c_host[0] *= 2.0;   // plain coefficients -> the c_0 / 2 convention
+    }
+    if (err_host) *err_host = err;
     return CPA_OK;
 }
 
@@ -2004,7 +2066,7 @@ cpa_status cpa_shrink_csr(cpa_ctx* ctx, void* stream, int m, int n, int64_t nnz,
     if (opts && opts->side == CPA_SIDE_LEFT) return fail(CPA_ERR_UNSUPPORTED, "sparse path forms S^T S (side right)");
     if ((s = check_shrinkage(shrink)) != CPA_OK) return s;
     if ((s = check_opts(opts)) != CPA_OK) return s;
-    if ((s = no_learned_bound(opts)) != CPA_OK) return s;
+    if ((s = learned_bound_unsupported(opts)) != CPA_OK) return s;
     if (opts->precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "sparse path is FP32");
     if (opts->check) return fail(CPA_ERR_UNSUPPORTED, "the growth check is not available on the sparse path");
     if (m == 0 || n == 0) {

@@ -314,6 +314,7 @@ constexpr int kCoefLds = 1024;   // orders up to this use the cosine-table coeff
 // For mode 0 the warm-start buffer receives v_T (the unit vector of the last product).
 __device__ inline void ps_coeff_block(int K, int s, int J, double* scal, int out);
 
+// coeffs != nullptr: c_0..c_{K-1} are copied from there instead of computed.
 // ps_out >= 0: the coefficients are also rewritten for the matrix-polynomial route
 // with baby steps of ps_s (ps_coeff_block), saving that route a launch.
 // mode: 0 power iteration, 1 given, 2 Frobenius, 3 the predictor network
@@ -323,7 +324,7 @@ __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int ma
                                     const double* wbuf0, const double* wbuf1, double* warm_out, double* scal,
                                     ShrinkParams sp, int K, int pw_mu, int pw_w2, const double* gpart, int gwg,
                                     int cap_trace, int damping, int ps_s, int ps_out, const float* model,
-                                    double logmn) {
+                                    double logmn, const double* coeffs) {
     __shared__ double sLambda;
     __shared__ int sT;
     __shared__ double red[16];
@@ -380,7 +381,10 @@ __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int ma
     }
     __syncthreads();
     const double Lam = sLambda;
-    if (K <= kCoefLds) {
+    if (coeffs) {
+        // caller-given coefficients (another polynomial design for this Lambda)
+        for (int k = threadIdx.x; k < K; k += blockDim.x) scal[SC_COEF + k] = Lam > 0.0 ? coeffs[k] : 0.0;
+    } else if (K <= kCoefLds) {
         // k theta_l = pi k (2l + 1) / (2K): only the 4K angles pi m / (2K), m = k (2l + 1)
         // mod 4K, occur, so their cosines are tabled once, h is evaluated once per node,
         // and each c_k sums its row with l ascending (the order of the definition)
