@@ -115,3 +115,18 @@ def test_error_orders_of_the_designs():
     linf = {k: float(np.max(np.abs(hg - chebyshev.series_shifted(c, LAM, xg)))) for k, c in cs.items()}
     assert l2["lsq"] <= min(l2.values()) * (1 + 1e-12)
     assert linf["minimax"] <= min(linf.values()) * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("K", [20, 50])
+def test_stop_band_ripple_of_the_hard_threshold(K):
+    """The comparison of Sec. IV-B: on the hard threshold CPA leaves less ripple in
+    the stop band (x < tau^2, where h = 0) than least squares and minimax, which
+    both keep about half the step height there (Gibbs-like, and levelled)."""
+    sh, Lam = hard(0.3), 1.0
+    x = np.linspace(0.0, Lam, 20001)
+    stop = x < 0.3 ** 2
+    cs = {"cpa": chebyshev.coefficients_shifted(sh, Lam, K), "lsq": design.lsq(sh, Lam, K, 2000),
+          "minimax": design.minimax(sh, Lam, K, 8000)[0]}
+    ripple = {k: float(np.max(np.abs(chebyshev.series_shifted(c, Lam, x)[stop]))) for k, c in cs.items()}
+    assert ripple["cpa"] < 0.8 * min(ripple["lsq"], ripple["minimax"]), ripple
+    assert min(ripple["lsq"], ripple["minimax"]) > 0.45
