@@ -650,8 +650,10 @@ cpa_status cpa_predictor_train(cpa_ctx* ctx, void* stream, int64_t n, const floa
                                float* model_dev, float* adam_dev, int64_t* step_io_host, double* epoch_loss_dev);
 
 /* Instrumentation: per-launch timing with HIP events.  While enabled, every
- * launch of the recurrence GEMM (which = 0) and of the Gram GEMM (which = 1) is
- * bracketed by a pair of events recorded on the caller's stream.
+ * launch of the recurrence and full matrix-polynomial GEMMs (which = 0), of the
+ * Gram GEMM (which = 1) and of the matrix-polynomial products computed as
+ * symmetric pieces (which = 2) is bracketed by a pair of events recorded on the
+ * caller's stream.
  * cpa_timing_enable resets the record; cpa_timing_read waits for the recorded
  * events and returns the summed kernel time in milliseconds and the number of
  * launches since the last reset. */

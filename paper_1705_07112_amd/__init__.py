@@ -709,7 +709,7 @@ def timing_read(which: str = "recurrence", device: int = 0):
     """(total kernel milliseconds, launches) recorded since timing_enable."""
     ms = ctypes.c_double()
     cnt = ctypes.c_int64()
-    _check(lib().cpa_timing_read(ctypes.c_void_p(context(device)), {"recurrence": 0, "gram": 1}[which],
+    _check(lib().cpa_timing_read(ctypes.c_void_p(context(device)), {"recurrence": 0, "gram": 1, "pieces": 2}[which],
                                  ctypes.byref(ms), ctypes.byref(cnt)))
     return ms.value, cnt.value
 

@@ -90,7 +90,7 @@ struct cpa_ctx {
     int device = 0;
     void* scratch = nullptr;   // this device's address of the allocation-free entry point's scratch
     int timing = 0;               // 1: bracket launches with events
-    TimingLog tlog[2];            // 0: recurrence GEMMs, 1: Gram GEMMs
+    TimingLog tlog[3];            // 0: recurrence and full polynomial GEMMs, 1: Gram GEMMs, 2: symmetric pieces
     void* ws = nullptr;        // main workspace
     size_t ws_bytes = 0;
     double* warm = nullptr;    // warm-start vector for power iteration
@@ -136,8 +136,9 @@ cpa_status timing_pair(cpa_ctx* ctx, int which, hipEvent_t& a, hipEvent_t& b) {
     TimingLog& L = ctx->tlog[which];
     if (2 * (L.used + 1) > L.ev.size()) {
         for (int q = 0; q < 2; ++q) {
+            // timing only: no system-scope fence (cache write-back) when the event is recorded
             hipEvent_t e;
-            HIP_TRY(hipEventCreate(&e));
+            HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
             L.ev.push_back(e);
         }
     }
@@ -157,6 +158,9 @@ struct Work {
     int* et_counter;  // next E_t slot
     float* poly;      // matrix-polynomial route: T_1..T_s, R_0..R_{J-1}, three Clenshaw buffers (d x d each)
     int poly_s;       // s of that route (0: not allocated)
+    float* xt = nullptr;   // room for X^T (padded) while the Gram is formed: the polynomial buffers on
+                           // that route, else the first Y buffer of the recurrence (free until then)
+    int64_t xt_cap = 0;    // its capacity in floats (0: none)
     bool right;       // Gram = X^T X (n x n) and products on the right; else X X^T (m x m), on the left
     int d;            // side of the Gram
     ScalarLayout lay;
@@ -269,6 +273,13 @@ void bind_ws(Work& w, char* b, const WsPlan& p, bool admm, int poly_s, bool need
     w.et_counter = admm ? reinterpret_cast<int*>(b + p.oa + sizeof(double) * 2 * kAdmmGrid) : nullptr;
     w.poly = poly_s > 0 ? reinterpret_cast<float*>(b + p.opl) : nullptr;
     w.poly_s = poly_s;
+    if (poly_s > 0) {
+        w.xt = w.poly;
+        w.xt_cap = (int64_t)poly_mats(w.lay.K, poly_s) * w.d * w.d;
+    } else {
+        w.xt = w.Yb[0];
+        w.xt_cap = w.Yb[0] ? (int64_t)(p.oY1 - p.oY0) / (int64_t)sizeof(float) : 0;
+    }
 }
 
 // size_only != nullptr: report the bytes of the main workspace and the power
@@ -341,19 +352,32 @@ int gemm_grid(int ntm, int ntn, const Epi& epi) {
     return epi_sym(epi) ? ntm * (ntm + 1) / 2 : ntm * ntn;
 }
 
+// A symmetric product that cannot run in pieces runs as upper-triangle tiles.
+template <class Epi>
+Epi tiles_not_pieces(const Epi& e) {
+    return e;
+}
+template <>
+EpiLin tiles_not_pieces<EpiLin>(const EpiLin& e) {
+    EpiLin r = e;
+    if (r.sym == 2) r.sym = 1;
+    return r;
+}
+
 template <int BM, int BN, int LA, int LB, class Epi>
 cpa_status launch_gemm(hipStream_t st, const Operand& A, const Operand& B, int M, int N, int Kd, const Epi& epi,
                        int sc_a1, int sc_a2, int sc_coef) {
     const int ntm = (M + BM - 1) / BM, ntn = (N + BN - 1) / BN;
     if (epi_sym(epi) && M != N) return fail(CPA_ERR_ARG, "internal: a symmetric product must be square");
-    const int grid = gemm_grid(ntm, ntn, epi);
+    const Epi et = tiles_not_pieces(epi);
+    const int grid = gemm_grid(ntm, ntn, et);
     if (grid <= 0 || Kd <= 0) return CPA_OK;
     if (vec_operand(A, LA, Kd) && vec_operand(B, LB, Kd))
         hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, LA, LB, true, Epi>), dim3(grid), dim3(GTHREADS), 0, st, A, B, M,
-                           N, Kd, epi, sc_a1, sc_a2, sc_coef);
+                           N, Kd, et, sc_a1, sc_a2, sc_coef);
     else
         hipLaunchKernelGGL((gemm_f32_kernel<BM, BN, LA, LB, false, Epi>), dim3(grid), dim3(GTHREADS), 0, st, A, B,
-                           M, N, Kd, epi, sc_a1, sc_a2, sc_coef);
+                           M, N, Kd, et, sc_a1, sc_a2, sc_coef);
     HIP_TRY(hipGetLastError());
     return CPA_OK;
 }
@@ -392,9 +416,17 @@ cpa_status gemm_dispatch(hipStream_t st, const Operand& A, const Operand& B, int
     if constexpr (LA == KCONTIG && LB == KCONTIG && std::is_same<Epi, EpiLin>::value) {
         if (lds_pipeline_ok(A, B, M, N, Kd)) {
             if (epi_sym(epi) && M != N) return fail(CPA_ERR_ARG, "internal: a symmetric product must be square");
-            const int grid = gemm_grid(M / 64, N / 64, epi);
+            if (epi.sym == 2 && epi.vec_ok) {
+                // symmetric product in pieces: (M / 64)^2 workgroups
+                hipLaunchKernelGGL(gemm_f32_piece_kernel<EpiLin>, dim3((M / 64) * (M / 64)), dim3(1024), 0, st, A, B,
+                                   M, Kd, epi);
+                HIP_TRY(hipGetLastError());
+                return CPA_OK;
+            }
+            const Epi et = tiles_not_pieces(epi);
+            const int grid = gemm_grid(M / 64, N / 64, et);
             hipLaunchKernelGGL((gemm_f32_lds_kernel<64, 64, Epi, 16>), dim3(grid), dim3(1024), 0, st, A, B, M, N, Kd,
-                               epi, sc_a1, sc_a2, sc_coef);
+                               et, sc_a1, sc_a2, sc_coef);
             HIP_TRY(hipGetLastError());
             return CPA_OK;
         }
@@ -515,6 +547,30 @@ cpa_status enqueue_gram_impl(hipStream_t st, int m, int n, const float* X, int64
     epi.ldc = d;
     epi.part = w.scal + w.lay.gpart();
     epi.vec_ok = aligned16(w.G, d);
+    // the Gram as a symmetric product in pieces (gemm_f32_piece_kernel) when its
+    // side is a multiple of 64: on the right side from X^T (transposed, the
+    // contraction padded with zeros to a multiple of 64), on the left from X itself
+    if (d % 64 == 0 && epi.vec_ok && gram_grid(d) == w.lay.gwg) {
+        const int nt = d / 64;
+        if (w.right) {
+            const int64_t ldt = ((int64_t)m + 63) / 64 * 64;
+            if (w.xt && aligned16(w.xt, ldt) && (int64_t)n * ldt <= w.xt_cap && ldt <= INT32_MAX) {
+                hipLaunchKernelGGL(transpose_pad_kernel, dim3((unsigned)(ldt / 64), (unsigned)(n / 64)), dim3(256), 0,
+                                   st, m, n, X, ldx, w.xt, ldt);
+                HIP_TRY(hipGetLastError());
+                const Operand T = make_op(w.xt, ldt, n);
+                hipLaunchKernelGGL(gemm_f32_piece_kernel<EpiGram>, dim3(nt * nt), dim3(1024), 0, st, T, T, n, (int)ldt,
+                                   epi);
+                HIP_TRY(hipGetLastError());
+                return CPA_OK;
+            }
+        } else if (n % 64 == 0 && aligned16(X, ldx)) {
+            const Operand A = make_op(X, ldx, m);
+            hipLaunchKernelGGL(gemm_f32_piece_kernel<EpiGram>, dim3(nt * nt), dim3(1024), 0, st, A, A, m, n, epi);
+            HIP_TRY(hipGetLastError());
+            return CPA_OK;
+        }
+    }
     if (w.right) {
         // G(i, j) = sum_r X[r][i] X[r][j]
         Operand A = make_op(X, ldx, n), B = make_op(X, ldx, n);
@@ -670,11 +726,22 @@ int poly_choice(const cpa_opts* o, int m, int n) {
     return cost_poly < cost_rec ? s : 0;
 }
 
+// Timing family of a matrix-polynomial product: 2 for a symmetric product in
+// pieces, else 0 (with the recurrence products).
+template <class Epi>
+int poly_family(const Epi&) {
+    return 0;
+}
+template <>
+int poly_family<EpiLin>(const EpiLin& e) {
+    return e.sym == 2 ? 2 : 0;
+}
+
 template <class Epi>
 cpa_status poly_gemm(cpa_ctx* ctx, hipStream_t st, const Operand& A, const Operand& B, int M, int N, int Kd,
                      const Epi& epi, int precision, bool kk) {
     hipEvent_t ea, eb;
-    cpa_status s = timing_pair(ctx, 0, ea, eb);
+    cpa_status s = timing_pair(ctx, poly_family(epi), ea, eb);
     if (s != CPA_OK) return s;
     if (ea) HIP_TRY(hipEventRecord(ea, st));
     if (kk)
@@ -706,17 +773,23 @@ EpiLin lin_epi(float* D, int64_t ldd, const float* Mx, int64_t ldm, float alpha,
 
 // The polynomial p(Ghat) (d x d, pitch d) from the Gram G (pitch ldg) and the
 // coefficients in scal; `poly` holds poly_mats(K, s) matrices of d x d.  Returns p's buffer.
-// The upper-triangle (symmetric) products pay when they take fewer rounds of
-// 64 x 64 tiles over the CUs than the full ones: not at d = 1024 (136 against
-// 256 tiles, one round either way on 256 CUs), from d = 1088 on.
-bool sym_pays(cpa_ctx* ctx, int d) {
+// How the symmetric products of the route run (EpiLin::sym): 0 all tiles, 1 the
+// upper-triangle tiles, 2 in pieces (gemm_f32_piece_kernel; d % 64 == 0).  Cost
+// in MFMA blocks per CU: rounds of workgroups over the CUs times the blocks of
+// the largest workgroup (16 for a tile, 10 for a diagonal piece).  d = 1024 on
+// 256 CUs: 16 (all tiles or the 136 upper ones, one round) against 10 (256
+// pieces); d = 1344: 2 x 16 and 2 x 10 against 16 for the 231 upper tiles.
+int sym_mode(cpa_ctx* ctx, int d) {
     if (ctx->cus == 0) {
         int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) return false;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) return 0;
         ctx->cus = std::max(1, cus);
     }
     const int64_t nt = (d + 63) / 64, full = nt * nt, tri = nt * (nt + 1) / 2, c = ctx->cus;
-    return (tri + c - 1) / c < (full + c - 1) / c;
+    const int64_t cost_full = (full + c - 1) / c * 16, cost_tri = (tri + c - 1) / c * 16;
+    const int64_t cost_piece = d % 64 == 0 ? (full + c - 1) / c * 10 : INT64_MAX;
+    if (cost_piece < cost_tri && cost_piece < cost_full) return 2;
+    return cost_tri < cost_full ? 1 : 0;
 }
 
 // check_off >= 0: after the baby steps, the Gram-weighted means of T_2..T_s go
@@ -725,7 +798,7 @@ cpa_status enqueue_poly_core(cpa_ctx* ctx, hipStream_t st, int d, const float* G
                              int roff, float* poly, int s, int K, int precision, float** F_out, bool coeff_ready,
                              int check_off = -1) {
     const int J = (K + s - 1) / s;
-    const int sym = precision == CPA_PREC_FP32 && sym_pays(ctx, d) ? 1 : 0;
+    const int sym = precision == CPA_PREC_FP32 ? sym_mode(ctx, d) : 0;
     const int64_t dd = (int64_t)d * d;
     float* T1 = poly;                         // T_q at T1 + (q - 1) dd, q = 1..s
     float* R = poly + (int64_t)s * dd;        // R_j at R + j dd
@@ -1511,7 +1584,7 @@ cpa_status cpa_timing_enable(cpa_ctx* ctx, int enable) {
 
 cpa_status cpa_timing_read(cpa_ctx* ctx, int which, double* total_ms_host, int64_t* launches_host) {
     if (!ctx) return fail(CPA_ERR_ARG, "context is NULL");
-    if (which < 0 || which > 1) return fail(CPA_ERR_ARG, "unknown kernel family %d", which);
+    if (which < 0 || which > 2) return fail(CPA_ERR_ARG, "unknown kernel family %d", which);
     if (!total_ms_host || !launches_host) return fail(CPA_ERR_ARG, "output pointer is NULL");
     HIP_TRY(hipSetDevice(ctx->device));
     TimingLog& L = ctx->tlog[which];

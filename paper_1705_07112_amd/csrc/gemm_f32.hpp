@@ -264,6 +264,27 @@ __device__ inline void block_sum2(double& a, double& b) {
     }
 }
 
+// block_sum2 for NW waves.
+template <int NW>
+__device__ inline void block_sum2_w(double& a, double& b) {
+    __shared__ double red[2][NW];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = a;
+        red[1][w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = b = 0.0;
+        for (int i = 0; i < NW; ++i) {
+            a += red[0][i];
+            b += red[1][i];
+        }
+    }
+}
+
 // Epilogues run after the K loop on a tile staged in LDS (row-major, pitch
 // BN + 4), so that every thread handles whole float4 groups of a row: all
 // global loads of a thread are issued before any arithmetic, and each wave
@@ -308,6 +329,47 @@ struct EpiGram {
         }
         block_sum2(s1, s2);
         if (threadIdx.x == 0) {
+            part[2 * blockIdx.x] = s1;
+            part[2 * blockIdx.x + 1] = s2;
+        }
+    }
+
+    // One piece of the Gram computed as a symmetric product (gemm_f32_piece_kernel,
+    // 1024 threads; C % 16 bytes and ldc % 4 checked by the host): the piece and its
+    // mirror are stored; the workgroup's partial sums count every stored entry once
+    // (||G||_F^2 with the mirrored entries twice, the trace from the diagonal).
+    __device__ inline void run_piece(float* tile, int m0, int n0, int half) const {
+        constexpr int P = 68;
+        const int t = threadIdx.x;
+        double s1 = 0.0, s2 = 0.0;
+        if (half < 0) {
+            const int r = t / 16, cc = (t % 16) * 4;
+            f32x4 v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int c = cc + e;
+                v[e] = r <= c ? tile[r * P + c] : tile[c * P + r];
+                if (r <= c) s1 += (r == c ? 1.0 : 2.0) * (double)v[e] * v[e];
+                if (r == c) s2 += v[e];
+            }
+            *reinterpret_cast<f32x4*>(C + (int64_t)(m0 + r) * ldc + n0 + cc) = v;
+        } else {
+            const int c0 = 32 * half;
+            if (t < 512) {
+                const int r = t / 8, cc = c0 + (t % 8) * 4;
+                const f32x4 v = *reinterpret_cast<const f32x4*>(tile + r * P + cc);
+                *reinterpret_cast<f32x4*>(C + (int64_t)(m0 + r) * ldc + n0 + cc) = v;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) s1 += 2.0 * (double)v[e] * v[e];
+                const int r2 = t / 16, c2 = (t % 16) * 4;
+                f32x4 w;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) w[e] = tile[(c2 + e) * P + c0 + r2];
+                *reinterpret_cast<f32x4*>(C + (int64_t)(n0 + c0 + r2) * ldc + m0 + c2) = w;
+            }
+        }
+        block_sum2_w<16>(s1, s2);
+        if (t == 0) {
             part[2 * blockIdx.x] = s1;
             part[2 * blockIdx.x + 1] = s2;
         }
@@ -527,6 +589,56 @@ struct EpiLin {
             }
             store4(m0 + r, n0 + cc, M, M, vec_ok, v);
             if (!diag) store4(n0 + r, m0 + cc, M, M, vec_ok, w);
+        }
+    }
+
+    // Epilogue of one piece of a symmetric product (gemm_f32_piece_kernel, 1024
+    // threads; M % 64 == 0 and vec_ok, both checked by the host).  half >= 0: the
+    // 64 x 32 block at (m0, n0 + 32 half) above the diagonal, stored and mirrored;
+    // half < 0: the diagonal tile at (m0, m0), its upper triangle mirrored onto
+    // the lower one.  tile: 64 x 68 floats, the product at its tile positions.
+    __device__ inline void run_piece(float* tile, int m0, int n0, int half) const {
+        constexpr int P = 68;
+        const int t = threadIdx.x;
+        // values o = alpha acc + beta C + gamma Mx (+ delta on the diagonal) at the
+        // stored positions: 64 rows x 8 groups (half piece) or 64 x 16 (diagonal)
+        const int gpr = half >= 0 ? 8 : 16;
+        const int c0 = half >= 0 ? 32 * half : 0;
+        const bool mine = t < 64 * gpr;
+        const int r = t / gpr, cc = c0 + (t % gpr) * 4;
+        const int i = m0 + r, j = n0 + cc;
+        f32x4 o = (f32x4){0.f, 0.f, 0.f, 0.f};
+        if (mine) {
+            const f32x4 a = *reinterpret_cast<const f32x4*>(tile + r * P + cc);
+            f32x4 vd = (f32x4){0.f, 0.f, 0.f, 0.f}, vm = vd;
+            if (beta != 0.f) vd = *reinterpret_cast<const f32x4*>(C + (int64_t)i * ldc + j);
+            if (gamma != 0.f) vm = *reinterpret_cast<const f32x4*>(Mx + (int64_t)i * ldm + j);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float v = alpha * a[e] + beta * vd[e] + gamma * vm[e];
+                if (i == j + e) v += delta;
+                o[e] = v;
+            }
+        }
+        __syncthreads();   // every product value read before the tile is overwritten
+        if (mine) *reinterpret_cast<f32x4*>(tile + r * P + cc) = o;
+        __syncthreads();
+        if (half < 0) {
+            // the full diagonal tile from its upper triangle
+            f32x4 v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = r <= cc + e ? tile[r * P + cc + e] : tile[(cc + e) * P + r];
+            *reinterpret_cast<f32x4*>(D + (int64_t)i * ldd + j) = v;
+            return;
+        }
+        if (mine) *reinterpret_cast<f32x4*>(D + (int64_t)i * ldd + j) = o;
+        // the mirror: rows n0 + c0 .. + 31, columns m0 .. m0 + 63 (32 x 16 groups)
+        if (t < 512) {
+            const int r2 = t / 16, c2 = (t % 16) * 4;
+            f32x4 w;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) w[e] = tile[(c2 + e) * P + c0 + r2];
+            *reinterpret_cast<f32x4*>(D + (int64_t)(n0 + c0 + r2) * ldd + m0 + c2) = w;
         }
     }
 

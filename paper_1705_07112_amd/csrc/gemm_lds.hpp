@@ -30,6 +30,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "gemm_f32.hpp"
 
 namespace cpa {
@@ -204,6 +206,218 @@ __global__ void __launch_bounds__(64 * NW) gemm_f32_lds_kernel(Operand A, Operan
     static_assert(NG * 4 * NT == BM * BN, "tile must split evenly into float4 groups");
     static_assert(NG == 1 || NT == GTHREADS, "epilogues index float4 groups in steps of GTHREADS");
     epi.template run<BM, BN, NG>(tile, m0, n0, M, N, epi_scal(epi), sc_a1, sc_a2, sc_coef);
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric products in pieces.  A product whose result is symmetric (every
+// product of the matrix-polynomial route is a polynomial in one symmetric
+// matrix) needs only the tiles on and above the diagonal: nt (nt + 1) / 2 of the
+// nt x nt tiles of 64.  At nt = 16 that is 136 tiles for 256 CUs, one round
+// either way.  The pieces below give every CU less work instead: each tile above
+// the diagonal is split into its two 64 x 32 column halves (eight 16 x 16 MFMA
+// blocks each) and each diagonal tile keeps the blocks on or above its diagonal
+// (ten): nt^2 pieces, as many as the tiles of the full product, with at most 10
+// of 16 blocks per workgroup.
+//
+// Waves: the 64 x 64 tile is four 32 x 32 quadrants of 2 x 2 blocks.  A half
+// piece has two quadrants, a diagonal piece three ((0,0), (0,1), (1,1)); wave w
+// < 4 nq takes quadrant slot w / 4 over K-slice w % 4 (the K-split of the full
+// kernel), so each SIMD (w % 4) holds one wave of every quadrant and the MFMA
+// count per SIMD is even: 32 blocks x K-steps on a half piece, 40 on a diagonal
+// one (whose diagonal quadrants skip the block below their diagonal).  Waves past
+// 4 nq only copy tiles.  Operand tiles are copied whole (the B tile of a half
+// piece is used in one half), by the same four-stage direct global-to-LDS
+// pipeline as gemm_f32_lds_kernel.
+//
+// Stores: each piece writes its blocks and their mirror images, a diagonal piece
+// its upper triangle mirrored onto the lower one, so the result is exactly
+// symmetric (Epi::run_piece: the linear epilogue reads C and Mx at the stored,
+// upper positions only; the Gram epilogue adds the piece's share of ||G||_F^2
+// and of the trace).
+
+// X^T into a k-contiguous operand: Xt[j][i] = X[i][j] (i < m, j < n), and 0 for
+// m <= i < ldt, the padding of the contraction length to a multiple of 64.  One
+// 64 x 64 block per workgroup (256 threads) through LDS, so that both the reads
+// of X and the writes of Xt are row segments.  Grid (ldt / 64, ceil(n / 64)).
+__global__ void __launch_bounds__(256) transpose_pad_kernel(int m, int n, const float* X, int64_t ldx, float* Xt,
+                                                            int64_t ldt) {
+    __shared__ float blk[64][65];
+    const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int i = i0 + ty + 4 * q, j = j0 + tx;
+        blk[ty + 4 * q][tx] = (i < m && j < n) ? X[(int64_t)i * ldx + j] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int j = j0 + ty + 4 * q, i = i0 + tx;
+        if (j < n) Xt[(int64_t)j * ldt + i] = blk[tx][ty + 4 * q];
+    }
+}
+
+// Piece p of nt^2 (XCD-compact order, as tile_coords): p < nt (nt - 1) is half
+// p % 2 of the p / 2-th tile above the diagonal in row-major order; the rest are
+// the diagonal tiles (half = -1).
+__device__ inline void piece_of(int nt, int& tm, int& tn, int& half) {
+    const int P = nt * nt;
+    int p = blockIdx.x;
+    if (P % 8 == 0) p = (p % 8) * (P / 8) + p / 8;
+    const int off = nt * (nt - 1);
+    if (p >= off) {
+        tm = tn = p - off;
+        half = -1;
+        return;
+    }
+    int q = p >> 1;
+    half = p & 1;
+    int r = 0;
+    while (q >= nt - 1 - r) {
+        q -= nt - 1 - r;
+        ++r;
+    }
+    tm = r;
+    tn = r + 1 + q;
+}
+
+// MFMAs of one K-tile for a wave's quadrant into the fresh partial `part`; on a
+// diagonal quadrant the block below its diagonal (i = 1, j = 0) is skipped.
+template <class C, bool DIAG>
+__device__ inline void mfma_quadrant(const typename C::Frags& f, f32x4 (&part)[C::MB][C::NB]) {
+#pragma unroll
+    for (int i = 0; i < C::MB; ++i)
+#pragma unroll
+        for (int j = 0; j < C::NB; ++j) part[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < C::KQ; ++kk)
+#pragma unroll
+        for (int i = 0; i < C::MB; ++i)
+#pragma unroll
+            for (int j = 0; j < C::NB; ++j)
+                if (!(DIAG && i > j))
+                    part[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(f.a[i][kk], f.b[j][kk], part[i][j], 0, 0, 0);
+}
+
+template <class Epi>
+__global__ void __launch_bounds__(1024) gemm_f32_piece_kernel(Operand A, Operand B, int M, int Kd, Epi epi) {
+    constexpr int NW = 16, BM = 64, BN = 64;
+    constexpr int DMA = dma_per_tile<NW>();
+    using C = GemmCore<BM, BN, KCONTIG, KCONTIG, NW>;
+    using Frags = typename C::Frags;
+    constexpr int MB = C::MB, NB = C::NB;
+    static_assert(MB == 2 && NB == 2 && C::KS == 4, "quadrants of 2 x 2 blocks over a K-split of four");
+    __shared__ __attribute__((aligned(16))) float lds[LDS_STAGES * 2 * LDS_TILE];
+
+    const int nt = M / 64;
+    int tm, tn, half;
+    piece_of(nt, tm, tn, half);
+    const int m0 = tm * 64, n0 = tn * 64;
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nq = half < 0 ? 3 : 2;
+    const bool active = wave < 4 * nq;
+    const int qi = wave >> 2, kh = wave & 3;
+    // quadrant (qr, qc) of the tile: a half piece's column half, or (0,0), (0,1), (1,1)
+    const int qr = half >= 0 ? qi : (qi == 2 ? 1 : 0);
+    const int qc = half >= 0 ? half : (qi >= 1 ? 1 : 0);
+    const bool diagq = half < 0 && qr == qc;
+
+    f32x4 acc[MB][NB], p0[MB][NB], p1[MB][NB];
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc[i][j] = p0[i][j] = p1[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+    Frags f0, f1;
+    const int nkt = Kd / GBK;
+    const int last = nkt - 1;
+    auto kof = [&](int t) { return min(t, last) * GBK; };
+    auto sa = [&](int t) { return lds + (t % LDS_STAGES) * 2 * LDS_TILE; };
+    auto sb = [&](int t) { return lds + (t % LDS_STAGES) * 2 * LDS_TILE + LDS_TILE; };
+    auto copy = [&](int t) {
+        tile_dma<NW>(A, m0, kof(t), sa(t), wave, lane);
+        tile_dma<NW>(B, n0, kof(t), sb(t), wave, lane);
+    };
+    auto read = [&](int t, Frags& f) {
+#pragma unroll
+        for (int i = 0; i < MB; ++i) frag_read_swz<C::KQ>(sa(t), qr * 32 + i * 16, lane, kh * C::KQ, f.a[i]);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) frag_read_swz<C::KQ>(sb(t), qc * 32 + j * 16, lane, kh * C::KQ, f.b[j]);
+    };
+
+    // the pipeline of gemm_f32_lds_kernel in three straight-line variants (MODE 0:
+    // copies only, 1: a full quadrant, 2: a diagonal quadrant); every wave runs the
+    // same sequence of copies and barriers
+    auto pipeline = [&](auto mode) {
+        constexpr int MODE = decltype(mode)::value;
+        constexpr int NMF = MODE == 2 ? C::kMfma * 3 / 4 : C::kMfma;
+        copy(0);
+        copy(1);
+        copy(2);
+        wait_vm<DMA>();
+        __builtin_amdgcn_s_barrier();
+        if constexpr (MODE > 0) read(0, f0);
+        for (int kt = 0; kt < nkt; kt += 2) {
+            copy(kt + 3);
+            CPA_SCHED_FENCE();
+            if constexpr (MODE > 0) {
+                mfma_quadrant<C, MODE == 2>(f0, p0);
+                C::add_into(acc, p1);
+                read(kt + 1, f1);
+                interleave_step<NMF, C::kReads, 0>();
+            }
+            wait_vm_lds<DMA>();
+            __builtin_amdgcn_s_barrier();
+            if (kt + 1 >= nkt) {
+                if constexpr (MODE > 0) C::add_into(acc, p0);
+                break;
+            }
+            copy(kt + 4);
+            CPA_SCHED_FENCE();
+            if constexpr (MODE > 0) {
+                mfma_quadrant<C, MODE == 2>(f1, p1);
+                C::add_into(acc, p0);
+                read(kt + 2, f0);
+                interleave_step<NMF, C::kReads, 0>();
+            }
+            wait_vm_lds<DMA>();
+            __builtin_amdgcn_s_barrier();
+            if constexpr (MODE > 0)
+                if (kt + 2 >= nkt) C::add_into(acc, p1);
+        }
+    };
+    if (!active)
+        pipeline(std::integral_constant<int, 0>());
+    else if (diagq)
+        pipeline(std::integral_constant<int, 2>());
+    else
+        pipeline(std::integral_constant<int, 1>());
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");
+    __syncthreads();
+
+    // K-split partials summed in a fixed order (K-slice 0, 1, 2, 3) into the tile
+    constexpr int P = BN + 4;
+    float* tile = lds;
+#pragma unroll
+    for (int h = 0; h < C::KS; ++h) {
+        if (active && kh == h) {
+#pragma unroll
+            for (int a = 0; a < MB; ++a)
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = qr * 32 + a * 16 + 4 * (lane >> 4) + r;
+                        const int j = qc * 32 + b * 16 + (lane & 15);
+                        float* t = tile + i * P + j;
+                        *t = (h == 0) ? acc[a][b][r] : *t + acc[a][b][r];
+                    }
+        }
+        __syncthreads();
+    }
+    epi.run_piece(tile, m0, n0, half);
 }
 
 }  // namespace cpa

@@ -428,6 +428,26 @@ def test_polynomial_route_symmetric_products(shape):
         parity.check(got, ref, TOL32, X, f"symmetric products {m}x{n} K={K}")
 
 
+@pytest.mark.parametrize("shape,orders", [((130, 64), (9, 30)), ((300, 128), (9, 30)), ((400, 320), (5, 30)),
+                                          ((128, 700), (9, 30)), ((1100, 1024), (9, 30)), ((2100, 2048), (9,))])
+def test_polynomial_route_symmetric_pieces(shape, orders):
+    """Gram sides that are multiples of 64 up to 2048: the products of the matrix
+    polynomial run in pieces (each tile above the diagonal as two 64 x 32 halves,
+    each diagonal tile's upper triangle; stored and mirrored): one diagonal piece
+    only (d = 64), no XCD interleave (d = 320, 25 pieces), the left side (d = 128),
+    one round on 256 CUs (d = 1024) and four rounds (d = 2048), against the oracle."""
+    m, n = shape
+    cpa = _lib()
+    X = synth.as_f32_exact(synth.dense_lowrank(m, n, rank=6, noise=0.2, seed=7400 + m + n))
+    lmax = _gram_lmax(X)
+    Lam, tau = 1.01 * lmax, 0.4 * math.sqrt(lmax)
+    for K in orders:
+        print(f"case pieces {m}x{n} K={K}", flush=True)
+        got, info = _run(X, cpa.soft(tau), K, Lam, ev="polynomial")
+        ref = ocpa.cpa_shrink(X, Shrinkage(0, tau), Lam, K)
+        parity.check(got, ref, TOL32, X, f"symmetric pieces {m}x{n} K={K}")
+
+
 def test_non_finite_input():
     """A NaN or an infinity in X: synchronising calls (info, check) return
     CPA_ERR_NONFINITE, whatever the bound rule; an asynchronous call cannot
