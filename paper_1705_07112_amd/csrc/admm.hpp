@@ -27,7 +27,8 @@ struct AdmmPtrs {
     float* x;   // shrink input l + u1
 };
 
-__device__ inline void admm_pre_elem(const AdmmPtrs& P, int64_t e, double& dn, double& dd) {
+// Returns x = l + u1, the element of the shrink input.
+__device__ inline float admm_pre_elem(const AdmmPtrs& P, int64_t e, double& dn, double& dd) {
     const float Ie = P.I[e], u3 = P.u3[e];
     const float a = (P.z1[e] - P.u1[e]) + (Ie - u3);
     const float b = (P.z2[e] - P.u2[e]) + (Ie - u3);
@@ -38,7 +39,9 @@ __device__ inline void admm_pre_elem(const AdmmPtrs& P, int64_t e, double& dn, d
     dd += (double)l * l;
     P.l[e] = l;
     P.s[e] = s;
-    P.x[e] = l + P.u1[e];
+    const float x = l + P.u1[e];
+    P.x[e] = x;
+    return x;
 }
 
 // l, s <- (K^T K)^{-1} K^T (z - u); x <- l + u1; E_t partial sums.
@@ -86,6 +89,86 @@ __global__ void __launch_bounds__(256) admm_post_kernel(AdmmPtrs P, int64_t tota
             const int t = *counter;
             Et_base[t] = den > 0.0 ? sqrt(num / den) : 0.0;
             *counter = t + 1;
+        }
+    }
+}
+
+// The work before a dense shrink in one launch.  Workgroups 0 .. ntile_wg - 1
+// take 32 x 32 tiles of the m x n input (grid-stride; small tiles keep many
+// waves in flight, the kernel being bound by memory latency): with admm set they
+// run the ADMM pre-step on them (admm_pre_elem: l, s, x = l + u1 and the E_t
+// partials, one pair per workgroup in part) and the tile's shrink input is that
+// x, else it is read from X.  With xt set, each tile is also stored transposed,
+// Xt[j][i] = X[i][j], the rows i from m to ldt (the contraction padded to a
+// multiple of 64) as zeros: the tiles then cover ldt rows.  Workgroup ntile_wg
+// clears the scalar block and, with d > 0, writes the power iteration's start
+// vector (power_init_body).  256 threads.
+struct PrepArgs {
+    int m, n;
+    const float* X;
+    int64_t ldx;
+    AdmmPtrs P;
+    int admm;
+    double* part;
+    float* xt;
+    int64_t ldt;
+    double* scal;
+    int nscal;
+    int d;
+    uint64_t seed;
+    const double* warm;
+    double* w0;
+    int pw_w2;
+    int ntile_wg;
+};
+
+constexpr int kPrepTile = 32;
+
+__global__ void __launch_bounds__(256) prep_kernel(PrepArgs a) {
+    constexpr int T = kPrepTile, RPW = 256 / T;   // rows per pass
+    __shared__ float blk[T][T + 1];
+    __shared__ double red[16];
+    if ((int)blockIdx.x == a.ntile_wg) {
+        for (int i = threadIdx.x; i < a.nscal; i += blockDim.x) a.scal[i] = 0.0;
+        if (a.d > 0) {
+            __syncthreads();   // the cleared block before the start vector's norm is stored in it
+            power_init_body(a.d, a.seed, a.warm, a.w0, a.scal, a.pw_w2, red);
+        }
+        return;
+    }
+    const int tx = threadIdx.x % T, ty = threadIdx.x / T;
+    const int rows = a.xt ? (int)(a.ldt / T) : (a.m + T - 1) / T;
+    const int cols = (a.n + T - 1) / T;
+    double dn = 0.0, dd = 0.0;
+    for (int t = blockIdx.x; t < rows * cols; t += a.ntile_wg) {
+        const int i0 = (t / cols) * T, j0 = (t % cols) * T;
+#pragma unroll
+        for (int q = 0; q < T / RPW; ++q) {
+            const int i = i0 + ty + RPW * q, j = j0 + tx;
+            float v = 0.f;
+            if (i < a.m && j < a.n) {
+                if (a.admm)
+                    v = admm_pre_elem(a.P, (int64_t)i * a.n + j, dn, dd);
+                else
+                    v = a.X[(int64_t)i * a.ldx + j];
+            }
+            blk[ty + RPW * q][tx] = v;
+        }
+        if (!a.xt) continue;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < T / RPW; ++q) {
+            const int j = j0 + ty + RPW * q, i = i0 + tx;
+            if (j < a.n) a.xt[(int64_t)j * a.ldt + i] = blk[tx][ty + RPW * q];
+        }
+        __syncthreads();   // the block is reused by the next tile
+    }
+    if (a.admm) {
+        dn = block_sum(dn, red);
+        dd = block_sum(dd, red);
+        if (threadIdx.x == 0) {
+            a.part[2 * blockIdx.x] = dn;
+            a.part[2 * blockIdx.x + 1] = dd;
         }
     }
 }

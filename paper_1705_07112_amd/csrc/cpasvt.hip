@@ -527,20 +527,32 @@ cpa_status fill_scalars(hipStream_t st, const Work& w) {
 }
 
 // Gram into w.G (d x d, ld = d) with ||G||_F^2 and trace accumulated.
-cpa_status enqueue_gram_impl(hipStream_t st, int m, int n, const float* X, int64_t ldx, const Work& w);
+cpa_status enqueue_gram_impl(hipStream_t st, int m, int n, const float* X, int64_t ldx, const Work& w, bool xt_ready);
 
-cpa_status enqueue_gram(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* X, int64_t ldx, const Work& w) {
+cpa_status enqueue_gram(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* X, int64_t ldx, const Work& w,
+                        bool xt_ready = false) {
     hipEvent_t a, b;
     cpa_status s = timing_pair(ctx, 1, a, b);
     if (s != CPA_OK) return s;
     if (a) HIP_TRY(hipEventRecord(a, st));
-    s = enqueue_gram_impl(st, m, n, X, ldx, w);
+    s = enqueue_gram_impl(st, m, n, X, ldx, w, xt_ready);
     if (s != CPA_OK) return s;
     if (b) HIP_TRY(hipEventRecord(b, st));
     return CPA_OK;
 }
 
-cpa_status enqueue_gram_impl(hipStream_t st, int m, int n, const float* X, int64_t ldx, const Work& w) {
+// Leading dimension of X^T when the right-side Gram is formed from it as a
+// symmetric product in pieces (its side a multiple of 64, room for X^T with the
+// contraction padded to a multiple of 64), else 0.
+int64_t gram_xt_ld(const Work& w, int m, int n) {
+    const int d = w.d;
+    if (!w.right || d % 64 != 0 || !aligned16(w.G, d) || gram_grid(d) != w.lay.gwg || !w.xt) return 0;
+    const int64_t ldt = ((int64_t)m + 63) / 64 * 64;
+    if (!aligned16(w.xt, ldt) || (int64_t)n * ldt > w.xt_cap || ldt > INT32_MAX) return 0;
+    return ldt;
+}
+
+cpa_status enqueue_gram_impl(hipStream_t st, int m, int n, const float* X, int64_t ldx, const Work& w, bool xt_ready) {
     EpiGram epi;
     const int d = w.d;
     epi.C = w.G;
@@ -549,15 +561,18 @@ cpa_status enqueue_gram_impl(hipStream_t st, int m, int n, const float* X, int64
     epi.vec_ok = aligned16(w.G, d);
     // the Gram as a symmetric product in pieces (gemm_f32_piece_kernel) when its
     // side is a multiple of 64: on the right side from X^T (transposed, the
-    // contraction padded with zeros to a multiple of 64), on the left from X itself
+    // contraction padded with zeros to a multiple of 64; xt_ready: already there),
+    // on the left from X itself
     if (d % 64 == 0 && epi.vec_ok && gram_grid(d) == w.lay.gwg) {
         const int nt = d / 64;
         if (w.right) {
-            const int64_t ldt = ((int64_t)m + 63) / 64 * 64;
-            if (w.xt && aligned16(w.xt, ldt) && (int64_t)n * ldt <= w.xt_cap && ldt <= INT32_MAX) {
-                hipLaunchKernelGGL(transpose_pad_kernel, dim3((unsigned)(ldt / 64), (unsigned)(n / 64)), dim3(256), 0,
-                                   st, m, n, X, ldx, w.xt, ldt);
-                HIP_TRY(hipGetLastError());
+            const int64_t ldt = gram_xt_ld(w, m, n);
+            if (ldt > 0) {
+                if (!xt_ready) {
+                    hipLaunchKernelGGL(transpose_pad_kernel, dim3((unsigned)(ldt / 64), (unsigned)(n / 64)), dim3(256),
+                                       0, st, m, n, X, ldx, w.xt, ldt);
+                    HIP_TRY(hipGetLastError());
+                }
                 const Operand T = make_op(w.xt, ldt, n);
                 hipLaunchKernelGGL(gemm_f32_piece_kernel<EpiGram>, dim3(nt * nt), dim3(1024), 0, st, T, T, n, (int)ldt,
                                    epi);
@@ -593,16 +608,19 @@ int bound_mode(int rule) {
 
 // logmn: log(m n) of the input (the learned rule's third feature).
 cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkage* sh, const cpa_opts* o,
-                         const Work& w, int mode_override, const double* G64 = nullptr, double logmn = 0.0) {
+                         const Work& w, int mode_override, const double* G64 = nullptr, double logmn = 0.0,
+                         bool start_ready = false) {
     int mode = bound_mode(o->bound);
     if (mode_override >= 0) mode = mode_override;
     double* warm_vec = w.warm_vec ? w.warm_vec : ctx->warm;
     int& warm_len = w.warm_len ? *w.warm_len : ctx->warm_d;
     if (mode == 0) {
         const bool warm = o->warm_start && warm_len == d;
-        hipLaunchKernelGGL(power_init_kernel, dim3(1), dim3(256), 0, st, d, (uint64_t)o->seed,
-                           warm ? (const double*)warm_vec : nullptr, w.w[0], w.scal, w.lay.pw_w2());
-        HIP_TRY(hipGetLastError());
+        if (!start_ready) {
+            hipLaunchKernelGGL(power_init_kernel, dim3(1), dim3(256), 0, st, d, (uint64_t)o->seed,
+                               warm ? (const double*)warm_vec : nullptr, w.w[0], w.scal, w.lay.pw_w2());
+            HIP_TRY(hipGetLastError());
+        }
         int d_ = d, maxit_ = o->power_iters, pw_mu = w.lay.pw_mu(), pw_w2 = w.lay.pw_w2();
         const float* G = w.G;
         int64_t ldg = d;
@@ -622,11 +640,15 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
         }
         if (ls != CPA_OK) return ls;
     }
-    hipLaunchKernelGGL(finish_bound_kernel, dim3(1), dim3(256), 0, st, mode, o->Lambda, d, o->power_iters, o->margin,
-                       (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? warm_vec : nullptr, w.scal,
+    // on the matrix-polynomial route the finish kernel also forms T1 (extra workgroups)
+    const bool shift = poly_fused(w, o->K);
+    const int shift_wg = shift ? (int)std::min<int64_t>(4096, ((int64_t)d * d / 4 + 255) / 256 + 1) : 0;
+    hipLaunchKernelGGL(finish_bound_kernel, dim3(1 + shift_wg), dim3(256), 0, st, mode, o->Lambda, d, o->power_iters,
+                       o->margin, (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? warm_vec : nullptr, w.scal,
                        to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)(w.scal + w.lay.gpart()),
                        w.lay.gwg, 0, o->damping, w.poly_s, poly_fused(w, o->K) ? w.lay.ps() : -1,
-                       mode == 3 ? o->model : nullptr, logmn, o->coeffs);
+                       mode == 3 ? o->model : nullptr, logmn, o->coeffs, shift ? (const float*)w.G : nullptr,
+                       (int64_t)d, shift ? w.poly : nullptr);
     HIP_TRY(hipGetLastError());
     if (mode == 0) warm_len = d;
     return CPA_OK;
@@ -796,7 +818,7 @@ int sym_mode(cpa_ctx* ctx, int d) {
 // to the scalar block at check_off (ps_check_kernel).
 cpa_status enqueue_poly_core(cpa_ctx* ctx, hipStream_t st, int d, const float* G, int64_t ldg, double* scal,
                              int roff, float* poly, int s, int K, int precision, float** F_out, bool coeff_ready,
-                             int check_off = -1) {
+                             int check_off = -1, bool shift_ready = false) {
     const int J = (K + s - 1) / s;
     const int sym = precision == CPA_PREC_FP32 ? sym_mode(ctx, d) : 0;
     const int64_t dd = (int64_t)d * d;
@@ -808,8 +830,10 @@ cpa_status enqueue_poly_core(cpa_ctx* ctx, hipStream_t st, int d, const float* G
         hipLaunchKernelGGL(ps_coeff_kernel, dim3(1), dim3(256), 0, st, K, s, J, scal, roff);
         HIP_TRY(hipGetLastError());
     }
-    hipLaunchKernelGGL(ps_shift_kernel, dim3(ge), dim3(256), 0, st, d, G, ldg, T1, (const double*)scal);
-    HIP_TRY(hipGetLastError());
+    if (!shift_ready) {
+        hipLaunchKernelGGL(ps_shift_kernel, dim3(ge), dim3(256), 0, st, d, G, ldg, T1, (const double*)scal);
+        HIP_TRY(hipGetLastError());
+    }
     cpa_status r;
     auto Tq = [&](int q) { return T1 + (int64_t)(q - 1) * dd; };
     // baby steps: T_{i+1} = 2 T_i T_1 - T_{i-1}, T_0 = I (T_1 is the operand read transposed)
@@ -872,9 +896,9 @@ cpa_status enqueue_poly(cpa_ctx* ctx, hipStream_t st, int m, int n, const float*
                         int64_t ldy, int K, const Work& w, int precision, bool check = false) {
     const int d = w.d;
     float* F = nullptr;
-    // enqueue_bound on this Work rewrote the coefficients already
+    // enqueue_bound on this Work rewrote the coefficients and formed T1 already
     cpa_status r = enqueue_poly_core(ctx, st, d, w.G, d, w.scal, w.lay.ps(), w.poly, w.poly_s, K, precision, &F,
-                                     poly_fused(w, K), check ? w.lay.pchk() : -1);
+                                     poly_fused(w, K), check ? w.lay.pchk() : -1, poly_fused(w, K));
     if (r != CPA_OK) return r;
     // Y = X p (right) or p X (left); p read transposed (it is the fixed operand)
     const EpiLin e = lin_epi(Y, ldy, nullptr, 0, 1.f, 0.f, 0.f, 0.f);
@@ -952,17 +976,75 @@ cpa_status read_poly_check(hipStream_t st, const Work& w, double* growth) {
     return CPA_OK;
 }
 
+// What enqueue_prep has done for the shrink that follows it.
+struct PrepDone {
+    bool xt = false;      // X^T stored for the Gram (gram_xt_ld)
+    bool start = false;   // the power iteration's start vector written
+};
+
+// One launch before a shrink (prep_kernel): clears the scalar block, writes the
+// power iteration's start vector when the bound `mode` (0: power) needs it, and
+// stores X^T when the Gram is formed from it; with P, the ADMM pre-step runs on
+// the same tiles (its E_t partials into part, *npart of them) and the shrink
+// input is P->x.
+cpa_status enqueue_prep(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* X, int64_t ldx, const Work& w,
+                        const cpa_opts* o, int mode, const AdmmPtrs* P, double* part, int* npart, PrepDone& done) {
+    PrepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.m = m;
+    a.n = n;
+    a.X = X;
+    a.ldx = ldx;
+    if (P) {
+        a.P = *P;
+        a.admm = 1;
+        a.part = part;
+    }
+    const int64_t ldt = gram_xt_ld(w, m, n);
+    a.xt = ldt > 0 ? w.xt : nullptr;
+    a.ldt = ldt;
+    a.scal = w.scal;
+    a.nscal = w.lay.total();
+    const int d = w.d;
+    if (mode == 0) {
+        const double* warm_vec = w.warm_vec ? w.warm_vec : ctx->warm;
+        const int warm_len = w.warm_len ? *w.warm_len : ctx->warm_d;
+        a.d = d;
+        a.seed = (uint64_t)o->seed;
+        a.warm = o->warm_start && warm_len == d ? warm_vec : nullptr;
+        a.w0 = w.w[0];
+        a.pw_w2 = w.lay.pw_w2();
+    }
+    const int64_t rows = ldt > 0 ? ldt / kPrepTile : ((int64_t)m + kPrepTile - 1) / kPrepTile,
+                  cols = ((int64_t)n + kPrepTile - 1) / kPrepTile;
+    const int64_t tiles = (P || ldt > 0) ? rows * cols : 0;
+    a.ntile_wg = (int)std::min<int64_t>(tiles, P ? kAdmmGrid : 4096);
+    hipLaunchKernelGGL(prep_kernel, dim3(a.ntile_wg + 1), dim3(256), 0, st, a);
+    HIP_TRY(hipGetLastError());
+    if (npart) *npart = a.ntile_wg;
+    done.xt = ldt > 0;
+    done.start = mode == 0;
+    return CPA_OK;
+}
+
 cpa_status shrink_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, const float* X, int64_t ldx, float* Y,
-                       int64_t ldy, const cpa_shrinkage* sh, const cpa_opts* o, cpa_info* info, const Work& w) {
+                       int64_t ldy, const cpa_shrinkage* sh, const cpa_opts* o, cpa_info* info, const Work& w,
+                       const PrepDone* pre = nullptr) {
     const int d = w.d;
     const double logmn = std::log((double)m * n);
     // the check's recompute: power iteration after the learned bound (the fallback
     // the predictor stands in for), the guaranteed ||G||_F after the others
     const int redo_mode = o->bound == CPA_BOUND_LEARNED ? 0 : 2;
     cpa_status s;
-    if ((s = fill_scalars(st, w)) != CPA_OK) return s;
-    if ((s = enqueue_gram(ctx, st, m, n, X, ldx, w)) != CPA_OK) return s;
-    if ((s = enqueue_bound(ctx, st, d, sh, o, w, -1, nullptr, logmn)) != CPA_OK) return s;
+    PrepDone pd;
+    if (pre) {
+        pd = *pre;
+    } else if ((s = enqueue_prep(ctx, st, m, n, X, ldx, w, o, bound_mode(o->bound), nullptr, nullptr, nullptr, pd)) !=
+               CPA_OK) {
+        return s;
+    }
+    if ((s = enqueue_gram(ctx, st, m, n, X, ldx, w, pd.xt)) != CPA_OK) return s;
+    if ((s = enqueue_bound(ctx, st, d, sh, o, w, -1, nullptr, logmn, pd.start)) != CPA_OK) return s;
     if (w.poly_s > 0 && o->K >= 2) {
         if ((s = enqueue_poly(ctx, st, m, n, X, ldx, Y, ldy, o->K, w, o->precision, o->check != 0)) != CPA_OK)
             return s;
@@ -1218,7 +1300,7 @@ cpa_status shrink_csr_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t n
     hipLaunchKernelGGL(finish_bound_kernel, dim3(1), dim3(256), 0, st, mode, o->Lambda, n, o->power_iters, o->margin,
                        (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? ctx->warm : nullptr, w.scal,
                        to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)gpart, kSqGrid, 1, o->damping, 0, -1,
-                       nullptr, 0.0, o->coeffs);
+                       nullptr, 0.0, o->coeffs, nullptr, (int64_t)0, nullptr);
     HIP_TRY(hipGetLastError());
     if (mode == 0) ctx->warm_d = n;
     const bool poly = w.poly_s > 0 && o->K >= 2;
@@ -2320,13 +2402,19 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
     P.x = w.x;
     cpa_shrinkage sh = {CPA_SOFT, 0, inv_rho, 0.0, 0.0, 1.0};
     const int grid = (int)std::min<int64_t>(kAdmmGrid, (mn + 255) / 256);
+    (void)grid;
     auto one_iteration = [&](hipStream_t q) -> cpa_status {
         cpa_status r;
-        hipLaunchKernelGGL(admm_pre_kernel, dim3(grid), dim3(256), 0, q, P, mn, w.admm);
-        HIP_TRY(hipGetLastError());
-        if ((r = shrink_impl(ctx, q, m, n, w.x, n, P.z1, n, &sh, opts, nullptr, w)) != CPA_OK) return r;
-        hipLaunchKernelGGL(admm_post_kernel, dim3(grid), dim3(256), 0, q, P, mn, (float)eta_over_rho,
-                           (const double*)w.admm, grid, Et_dev, w.et_counter);
+        // the ADMM pre-step, fused with the shrink's preparation (prep_kernel)
+        PrepDone pd;
+        int npart = 0;
+        if ((r = enqueue_prep(ctx, q, m, n, w.x, n, w, opts, bound_mode(opts->bound), &P, w.admm, &npart, pd)) !=
+            CPA_OK)
+            return r;
+        if ((r = shrink_impl(ctx, q, m, n, w.x, n, P.z1, n, &sh, opts, nullptr, w, &pd)) != CPA_OK) return r;
+        const int pgrid = (int)std::min<int64_t>(kAdmmGrid, (mn + 255) / 256);
+        hipLaunchKernelGGL(admm_post_kernel, dim3(pgrid), dim3(256), 0, q, P, mn, (float)eta_over_rho,
+                           (const double*)w.admm, npart, Et_dev, w.et_counter);
         HIP_TRY(hipGetLastError());
         return CPA_OK;
     };
@@ -2758,7 +2846,7 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
         }
         float* F = nullptr;
         if ((s = enqueue_poly_core(ctx, st, nb, w.G, nb, w.scal, wc.lay.ps(), w.poly, ps, opts->K, CPA_PREC_FP32,
-                                   &F, poly_fused(wc, opts->K))) != CPA_OK)
+                                   &F, poly_fused(wc, opts->K), -1, poly_fused(wc, opts->K))) != CPA_OK)
             return s;
         // M = T^T hat H T (hat h(0) on the empty diagonal), then Y = X M (right) or M X (left)
         if ((s = inverse(F, nb)) != CPA_OK) return s;

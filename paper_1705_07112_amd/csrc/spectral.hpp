@@ -94,8 +94,8 @@ __device__ inline double block_sum(double v, double* red) {
 // w0 = start vector; ||w0||^2 into pw_w2[0].  warm != nullptr: copy it (unless its
 // norm is zero).
 // Single workgroup (fixed summation order).
-__global__ void power_init_kernel(int d, uint64_t seed, const double* warm, double* w0, double* scal, int pw_w2) {
-    __shared__ double red[16];
+__device__ inline void power_init_body(int d, uint64_t seed, const double* warm, double* w0, double* scal, int pw_w2,
+                                       double* red) {
     if (warm) {
         // a warm vector without weight (e.g. mapped from rows that are all gone) gives
         // way to the seeded start
@@ -118,6 +118,11 @@ __global__ void power_init_kernel(int d, uint64_t seed, const double* warm, doub
     }
     acc = block_sum(acc, red);
     if (threadIdx.x == 0) scal[pw_w2] = acc;
+}
+
+__global__ void power_init_kernel(int d, uint64_t seed, const double* warm, double* w0, double* scal, int pw_w2) {
+    __shared__ double red[16];
+    power_init_body(d, seed, warm, w0, scal, pw_w2, red);
 }
 
 constexpr int kPowerThreads = 512;
@@ -315,6 +320,9 @@ constexpr int kCoefLds = 1024;   // orders up to this use the cosine-table coeff
 __device__ inline void ps_coeff_block(int K, int s, int J, double* scal, int out);
 
 // coeffs != nullptr: c_0..c_{K-1} are copied from there instead of computed.
+// Workgroups past the first (launched when T1s is set) form the
+// matrix-polynomial route's T1 = (2 / Lambda) G - I from G (pitch ldgs), the
+// work of ps_shift_kernel, once each has the bound.
 // ps_out >= 0: the coefficients are also rewritten for the matrix-polynomial route
 // with baby steps of ps_s (ps_coeff_block), saving that route a launch.
 // mode: 0 power iteration, 1 given, 2 Frobenius, 3 the predictor network
@@ -324,7 +332,7 @@ __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int ma
                                     const double* wbuf0, const double* wbuf1, double* warm_out, double* scal,
                                     ShrinkParams sp, int K, int pw_mu, int pw_w2, const double* gpart, int gwg,
                                     int cap_trace, int damping, int ps_s, int ps_out, const float* model,
-                                    double logmn, const double* coeffs) {
+                                    double logmn, const double* coeffs, const float* Gs, int64_t ldgs, float* T1s) {
     __shared__ double sLambda;
     __shared__ int sT;
     __shared__ double red[16];
@@ -342,9 +350,14 @@ __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int ma
         float y1;
         mlp_infer_wg(model, (float)(0.5 * log(tr)), (float)log(f2), (float)logmn, mlp_h, mlp_y, y0, y1);
     }
+    // workgroup 0 stores the bound and the coefficients; the others (T1s set)
+    // arrive at the same Lambda from the same inputs and form T1 = (2 / Lambda) G - I
+    const bool lead = blockIdx.x == 0;
     if (threadIdx.x == 0) {
-        scal[SC_FRO2] = f2;
-        scal[SC_TRACE] = tr;
+        if (lead) {
+            scal[SC_FRO2] = f2;
+            scal[SC_TRACE] = tr;
+        }
         // cap_trace: only tr(G) is known (operator form); tr(G) >= ||G||_F >= lambda_max
         const double fro = cap_trace ? tr : sqrt(f2 > 0.0 ? f2 : 0.0);
         double Lam = 0.0;
@@ -368,19 +381,51 @@ __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int ma
                 const double add = (margin * mu > r) ? margin * mu : r;
                 Lam = mu + add;
                 if (Lam > (1.0 + margin) * fro) Lam = (1.0 + margin) * fro;
-                scal[SC_MU] = mu;
-                scal[SC_RESID] = r;
+                if (lead) {
+                    scal[SC_MU] = mu;
+                    scal[SC_RESID] = r;
+                }
             }
         }
-        scal[SC_ITERS] = T;
-        scal[SC_LAMBDA] = Lam;
-        scal[SC_A1] = Lam > 0.0 ? 2.0 / Lam : 0.0;
-        scal[SC_A2] = Lam > 0.0 ? 4.0 / Lam : 0.0;
+        if (lead) {
+            scal[SC_ITERS] = T;
+            scal[SC_LAMBDA] = Lam;
+            scal[SC_A1] = Lam > 0.0 ? 2.0 / Lam : 0.0;
+            scal[SC_A2] = Lam > 0.0 ? 4.0 / Lam : 0.0;
+        }
         sLambda = Lam;
         sT = T;
     }
     __syncthreads();
     const double Lam = sLambda;
+    if (!lead) {
+        // T1 = (2 / Lambda) G - I (d x d, pitch d; G with pitch ldgs), the scale
+        // rounded to FP32 as the polynomial's products read it
+        const float a1 = (float)(Lam > 0.0 ? 2.0 / Lam : 0.0);
+        const int64_t stride = (int64_t)(gridDim.x - 1) * blockDim.x;
+        const int64_t first = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
+        if ((d & 3) == 0 && (ldgs & 3) == 0 && ((uintptr_t)Gs & 15) == 0 && ((uintptr_t)T1s & 15) == 0) {
+            // four elements of one row per thread
+            const int64_t total4 = (int64_t)d * d / 4;
+            for (int64_t q = first; q < total4; q += stride) {
+                const int64_t i = (4 * q) / d, j = 4 * q - i * d;
+                const float4 g = *reinterpret_cast<const float4*>(Gs + i * ldgs + j);
+                float4 t;
+                t.x = a1 * g.x - (i == j ? 1.f : 0.f);
+                t.y = a1 * g.y - (i == j + 1 ? 1.f : 0.f);
+                t.z = a1 * g.z - (i == j + 2 ? 1.f : 0.f);
+                t.w = a1 * g.w - (i == j + 3 ? 1.f : 0.f);
+                *reinterpret_cast<float4*>(T1s + 4 * q) = t;
+            }
+        } else {
+            const int64_t total = (int64_t)d * d;
+            for (int64_t p = first; p < total; p += stride) {
+                const int64_t i = p / d, j = p - i * d;
+                T1s[p] = a1 * Gs[i * ldgs + j] - (i == j ? 1.f : 0.f);
+            }
+        }
+        return;
+    }
     if (coeffs) {
         // caller-given coefficients (another polynomial design for this Lambda)
         for (int k = threadIdx.x; k < K; k += blockDim.x) scal[SC_COEF + k] = Lam > 0.0 ? coeffs[k] : 0.0;
