@@ -250,6 +250,7 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
     __shared__ __attribute__((aligned(16))) float YT[BT_EMAX * BT_DP];
     __shared__ __attribute__((aligned(16))) float Gs[BT_DMAX * BT_DP];
     __shared__ double vv[BT_DMAX], coef[64], red[4];   // vv: scratch of the predictor network
+    __shared__ double ctab[4 * 64], hval[64];            // coefficient tables (K <= 64)
     __shared__ double pw[2 * BT_THREADS];                 // power iteration: partial rows, by parity
     __shared__ int s_idx;
     __shared__ double s_scal[4];
@@ -424,9 +425,29 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
                 }
             }
 
-            // ---- coefficients (FP64, l ascending per k)
-            __syncthreads();   // coef is rewritten on a second attempt
-            for (int k = threadIdx.x; k < Kj; k += BT_THREADS) coef[k] = cheb_coeff(sp, Lam, Kj, k);
+            // ---- coefficients (FP64, l ascending per k): k theta_l = pi k (2l + 1) / (2K)
+            // takes only the 4K angles pi m / (2K), m = k (2l + 1) mod 4K, so their cosines
+            // and the K values of h are formed once, in parallel, and each c_k sums its row
+            __syncthreads();   // coef and the tables are rewritten on a second attempt
+            {
+                const double pi = 3.14159265358979323846;
+                const int M4 = 4 * Kj;
+                for (int q = threadIdx.x; q < M4; q += BT_THREADS) ctab[q] = cos(pi * q / (2.0 * Kj));
+                for (int l = threadIdx.x; l < Kj; l += BT_THREADS)
+                    hval[l] = Lam > 0.0 ? shrink_h(sp, 0.5 * Lam * (cos(pi * (l + 0.5) / Kj) + 1.0)) : 0.0;
+                __syncthreads();
+                for (int k = threadIdx.x; k < Kj; k += BT_THREADS) {
+                    double acc = 0.0;
+                    int idx = k;
+                    const int step2 = (2 * k) % M4;
+                    for (int l = 0; l < Kj; ++l) {
+                        acc += ctab[idx] * hval[l];
+                        idx += step2;
+                        if (idx >= M4) idx -= M4;
+                    }
+                    coef[k] = Lam > 0.0 ? 2.0 / Kj * acc : 0.0;
+                }
+            }
             __syncthreads();
             const float a1 = Lam > 0.0 ? (float)(2.0 / Lam) : 0.f;
             const float a2 = Lam > 0.0 ? (float)(4.0 / Lam) : 0.f;
