@@ -661,6 +661,11 @@ def bench_predictor(cpa, torch, np, synth, n_train: int = 32768, n_eval: int = 8
         "plain_cpa": {"K": chosen[0], "pass_rate": round(chosen[1], 4),
                       "matrices_per_s": round(nb / (ms_plain / 1e3), 1), "ms_per_batch": round(ms_plain, 4)},
         "gain": round(ms_plain / ms_pred, 3),
+        "as_stated": "not measured as stated (200k training matrices, K* for a 1e-3 gate on orders up to 128): "
+                     "the batched kernel takes K <= 64, and soft thresholding on this family meets 1e-3 against "
+                     "the exact shrinkage for almost no matrix at K <= 64 (its kink at tau limits the polynomial), "
+                     f"so the gate is {gate:g} and the run trains on {n_train} matrices to stay within the bench's "
+                     "time; the gain test in the GPU suite asserts gain > 1 at equal pass rate",
     }
 
 

@@ -356,6 +356,79 @@ def test_predictor_pipeline_small():
         assert metrics.rel_fro(got, ref, A) <= TOL32, j
 
 
+def test_predictor_gain_at_equal_pass_rate():
+    """The predictor's gain as the bench measures it, on a smaller family run
+    (8192 training, 4096 held-out patch groups, 40 epochs, gate 1e-2): the
+    predicted path (no power iteration, per-matrix K, growth check) is faster than
+    plain CPA (power bound, the smallest single K whose pass rate of the gate is at
+    least the predicted path's), timed over the same held-out batch."""
+    import torch
+    import paper_1705_07112_amd as cpa
+    from paper_1705_07112_amd import predictor as P
+    dev = torch.device("cuda:0")
+    gate = 1e-2
+
+    def make(batch, seed):
+        flat, ms, ns, offs, _, noises = synth.patch_groups(batch=batch, rank_range=(1, 16),
+                                                           noise_range=(0.05, 0.5), seed=seed)
+        taus = noises * (np.sqrt(ms) + np.sqrt(ns))
+        ex = P.exact_soft_batch(flat, ms, ns, offs, taus)
+        return (ms, ns, offs, torch.from_numpy(flat).to(dev), torch.from_numpy(ms).to(dev),
+                torch.from_numpy(ns).to(dev), torch.from_numpy(offs).to(dev), P.soft_records(torch, taus, dev),
+                torch.from_numpy(ex).to(dev))
+
+    print("case predictor gain: labels", flush=True)
+    ms, ns, offs, X, m, n, off, recs, Yex = make(8192, 911)
+    feat, targ, _, _ = P.make_labels(torch, X, m, n, off, recs, ms, ns, offs, Yex, gate=gate)
+    ok = torch.isfinite(targ).all(dim=1)
+    feat, targ = feat[ok].contiguous(), targ[ok].contiguous()
+    mean = feat.double().mean(0).cpu().numpy()
+    std = feat.double().std(0).cpu().numpy()
+    model = torch.from_numpy(P.init_model(0, mean, std)).to(dev)
+    adam = torch.zeros(2 * cpa.PRED_PARAMS, dtype=torch.float32, device=dev)
+    cpa.predictor_train(feat, targ, model, adam, 0, (0.99, 0.9), batch_size=1024, epochs=40, lr=2e-3)
+    print("case predictor gain: held-out timing", flush=True)
+    ms, ns, offs, X, m, n, off, recs, Yex = make(4096, 912)
+    nb = 4096
+    bounds = P.segment_bounds(torch, ms, ns, offs, dev)
+    Y = torch.empty_like(X)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def predicted():
+        cpa.shrink_batched_predicted(X, m, n, off, cpa.soft(0.0), cpa.Opts(K=64, check=True), model, K_min=4,
+                                     shrink_per_matrix=recs, out=Y)
+
+    ms_pred = timed(predicted)
+    err, ref2 = P.rel_errors(torch, Y, Yex, bounds)
+    pass_pred = float((err <= gate).double().mean())
+    chosen = None
+    for Kc in P.K_GRID:
+        cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), cpa.Opts(K=Kc), shrink_per_matrix=recs, out=Y)
+        e, _ = P.rel_errors(torch, Y, Yex, bounds, ref2)
+        if float((e <= gate).double().mean()) >= pass_pred:
+            chosen = Kc
+            break
+    assert chosen is not None, "no single K reaches the predicted path's pass rate"
+    ms_plain = timed(lambda: cpa.shrink_batched(X, m, n, off, cpa.soft(0.0), cpa.Opts(K=chosen),
+                                                shrink_per_matrix=recs, out=Y))
+    gain = ms_plain / ms_pred
+    print(f"  predicted pass {pass_pred:.3f} at {ms_pred:.3f} ms; plain K={chosen} at {ms_plain:.3f} ms; "
+          f"gain {gain:.3f}", flush=True)
+    assert pass_pred >= 0.7
+    assert gain > 1.0
+
+
 def test_model_file_roundtrip(tmp_path):
     """cpa_predictor_save / cpa_predictor_load: the model comes back bit for bit;
     a file with the wrong magic, version or length is refused before the device
