@@ -95,6 +95,35 @@ __device__ inline void frag_read_swz(const float* stage, int xb, int lane, int k
     }
 }
 
+// The K-split partial tiles summed into lds (pitch BN + 4): every K-slice group
+// stores its partials in a tile of its own (the stages are free once the loop has
+// drained), then each thread adds its positions' KS values in the order K-slice
+// 0, 1, ... -- the sums of the one-tile-at-a-time accumulation, with one barrier
+// instead of KS.  (r0, c0): the wave's output corner in the tile.
+template <class C, int BM, int BN, int NT>
+__device__ inline void ksplit_sum(float* lds, const f32x4 (&acc)[C::MB][C::NB], int kh, int r0, int c0, int lane) {
+    constexpr int P = BN + 4, TS = BM * P;
+    static_assert(C::KS * TS <= LDS_STAGES * 2 * LDS_TILE, "the partial tiles must fit the stages");
+#pragma unroll
+    for (int a = 0; a < C::MB; ++a)
+#pragma unroll
+        for (int b = 0; b < C::NB; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                lds[kh * TS + (r0 + a * 16 + 4 * (lane >> 4) + r) * P + c0 + b * 16 + (lane & 15)] = acc[a][b][r];
+    __syncthreads();
+    if (C::KS > 1) {
+        for (int p = threadIdx.x; p < BM * BN; p += NT) {
+            const int q = (p / BN) * P + p % BN;
+            float v = lds[q];
+#pragma unroll
+            for (int h = 1; h < C::KS; ++h) v += lds[h * TS + q];
+            lds[q] = v;
+        }
+        __syncthreads();
+    }
+}
+
 // NW: waves per workgroup (8: K-split 2, two waves per SIMD; 16: K-split 4,
 // four waves per SIMD, half the fragment registers per wave).
 template <int BM, int BN, class Epi, int NW = GWAVES>
@@ -184,24 +213,7 @@ __global__ void __launch_bounds__(64 * NW) gemm_f32_lds_kernel(Operand A, Operan
     __syncthreads();
 
     float* tile = lds;
-#pragma unroll
-    for (int h = 0; h < C::KS; ++h) {
-        if (kh == h) {
-#pragma unroll
-            for (int a = 0; a < MB; ++a)
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int i = wr * (BM / C::WM) + a * 16 + 4 * (lane >> 4) + r;
-                        const int j = wc * (BN / C::WN) + b * 16 + (lane & 15);
-                        float* t = tile + i * (BN + 4) + j;
-                        *t = (h == 0) ? acc[a][b][r] : *t + acc[a][b][r];
-                    }
-        }
-        if (C::KS > 1) __syncthreads();
-    }
-    __syncthreads();
+    ksplit_sum<C, BM, BN, NT>(lds, acc, kh, wr * (BM / C::WM), wc * (BN / C::WN), lane);
     constexpr int NG = BM * BN / 4 / NT;
     static_assert(NG * 4 * NT == BM * BN, "tile must split evenly into float4 groups");
     static_assert(NG == 1 || NT == GTHREADS, "epilogues index float4 groups in steps of GTHREADS");
@@ -257,21 +269,40 @@ __global__ void __launch_bounds__(256) transpose_pad_kernel(int m, int n, const 
     }
 }
 
-// Piece p of nt^2 (XCD-compact order, as tile_coords): p < nt (nt - 1) is half
-// p % 2 of the p / 2-th tile above the diagonal in row-major order; the rest are
-// the diagonal tiles (half = -1).
+// Piece of workgroup blockIdx.x among the nt^2: the diagonal pieces (the longest,
+// ten blocks) come first, so they are dispatched first, and, when nt^2 % 8 == 0,
+// they take the first slots of every XCD's range (dispatch is round-robin over
+// the 8 XCDs and workgroup b runs on XCD b % 8: range x holds the virtual pieces
+// x nt^2 / 8 ..), spreading them over the XCDs' L2 caches; the half pieces follow,
+// half h % 2 of the h / 2-th tile above the diagonal in row-major order, so
+// neighbouring workgroups of an XCD share operand panels.  half = -1 on a
+// diagonal piece.
 __device__ inline void piece_of(int nt, int& tm, int& tn, int& half) {
     const int P = nt * nt;
-    int p = blockIdx.x;
-    if (P % 8 == 0) p = (p % 8) * (P / 8) + p / 8;
-    const int off = nt * (nt - 1);
-    if (p >= off) {
-        tm = tn = p - off;
-        half = -1;
-        return;
+    int h;
+    const int b = blockIdx.x;
+    if (P % 8 == 0) {
+        const int per = P / 8, x = b % 8, slot = b / 8;
+        const int ndx = (nt - x + 7) / 8;   // diagonal tiles t with t % 8 == x
+        if (slot < ndx) {
+            tm = tn = x + 8 * slot;
+            half = -1;
+            return;
+        }
+        // diagonal pieces in the ranges 0..x (those of range x precede this slot)
+        int before = 0;
+        for (int y = 0; y <= x; ++y) before += (nt - y + 7) / 8;
+        h = x * per + slot - before;
+    } else {
+        if (b < nt) {
+            tm = tn = b;
+            half = -1;
+            return;
+        }
+        h = b - nt;
     }
-    int q = p >> 1;
-    half = p & 1;
+    int q = h >> 1;
+    half = h & 1;
     int r = 0;
     while (q >= nt - 1 - r) {
         q -= nt - 1 - r;
@@ -398,25 +429,27 @@ __global__ void __launch_bounds__(1024) gemm_f32_piece_kernel(Operand A, Operand
     __syncthreads();
 
     // K-split partials summed in a fixed order (K-slice 0, 1, 2, 3) into the tile
-    constexpr int P = BN + 4;
+    // (waves without a quadrant store nothing: the positions they would cover are
+    // never stored)
     float* tile = lds;
+    if (active) {
+        constexpr int TS = BM * (BN + 4);
 #pragma unroll
-    for (int h = 0; h < C::KS; ++h) {
-        if (active && kh == h) {
+        for (int a = 0; a < MB; ++a)
 #pragma unroll
-            for (int a = 0; a < MB; ++a)
+            for (int b = 0; b < NB; ++b)
 #pragma unroll
-                for (int b = 0; b < NB; ++b)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int i = qr * 32 + a * 16 + 4 * (lane >> 4) + r;
-                        const int j = qc * 32 + b * 16 + (lane & 15);
-                        float* t = tile + i * P + j;
-                        *t = (h == 0) ? acc[a][b][r] : *t + acc[a][b][r];
-                    }
-        }
-        __syncthreads();
+                for (int r = 0; r < 4; ++r)
+                    lds[kh * TS + (qr * 32 + a * 16 + 4 * (lane >> 4) + r) * (BN + 4) + qc * 32 + b * 16 + (lane & 15)] =
+                        acc[a][b][r];
     }
+    __syncthreads();
+    for (int p = threadIdx.x; p < BM * BN; p += 1024) {
+        constexpr int TS = BM * (BN + 4);
+        const int q = (p / BN) * (BN + 4) + p % BN;
+        lds[q] = ((lds[q] + lds[TS + q]) + lds[2 * TS + q]) + lds[3 * TS + q];
+    }
+    __syncthreads();
     epi.run_piece(tile, m0, n0, half);
 }
 
