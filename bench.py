@@ -95,8 +95,8 @@ def cpu_baseline(I, budget_s: float = 15.0, check=None, samples=None):
     return res
 
 
-def measured_traffic(path: str = os.path.join(ROOT, "profiles", "poly_gemm_f32_1024_K30_pmc_traffic.md")):
-    """HBM bytes per launch of the dense polynomial GEMM from its committed counter summary,
+def measured_traffic(path: str = os.path.join(ROOT, "profiles", "piece_gemm_f32_1024_K30_pmc_traffic.md")):
+    """HBM bytes per launch of the symmetric piece product from its committed counter summary,
     or None when the summary is missing or the kernel source changed since."""
     import hashlib
     try:
