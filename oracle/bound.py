@@ -24,9 +24,26 @@ Reading (documented as a project choice):
 For a sparse S the operator form caps with tr(Phi) = ||S||_F^2 instead of
 ||Phi||_F (both bound lambda_max of a PSD matrix).
 
+k-step Lanczos (a second reading of the same step; the paper names no method):
+  * q_1 = v_0 / ||v_0|| (the same start vector), beta_0 = 0; for j = 1..k:
+    u = Phi q_j - beta_{j-1} q_{j-1}, alpha_j = q_j.u, u <- u - alpha_j q_j,
+    beta_j = ||u||, q_{j+1} = u / beta_j (plain three-term recurrence, no
+    reorthogonalisation; an exactly vanishing beta_j ends the run at step j);
+  * T_k = tridiagonal (alpha on the diagonal, beta_1..beta_{k-1} beside it),
+    theta = its largest eigenvalue, s its unit eigenvector, Ritz vector
+    y = sum_i s_i q_i, residual norm ||Phi y - theta y|| = beta_k |s_k|;
+  * Lambda = min(theta + max(delta * theta, ||r||), (1 + delta) ||Phi||_F), the
+    rule of the power iteration with (theta, ||r||) in place of (mu, ||r||);
+    k = min(steps, d).  theta never exceeds lambda_max (interlacing), and one
+    step is one power product: theta_1 = mu_1, ||r||_1 = the power residual.
+
 Pins: the bound is >= the true largest eigenvalue (from eigh) on seeded
 matrices; on diagonal matrices it converges to the known maximum; the start
-vector reproduces SplitMix64's published first outputs for seed 0.
+vector reproduces SplitMix64's published first outputs for seed 0.  Lanczos:
+on the [-1, 2, -1] Toeplitz matrix from e_1 the recurrence returns the matrix's
+own leading block, so theta and ||r|| have closed forms; with as many steps as
+distinct eigenvalues it finds the largest one exactly; one step equals one
+power product; the Ritz pair's residual equals beta_k |s_k|; theta <= lambda_max.
 Parity: pinned (the margin delta is a project choice, stated above).
 """
 from __future__ import annotations
@@ -90,3 +107,41 @@ def power_bound(Phi: np.ndarray, seed: int = 0, max_iter: int = 100, tol: float 
     resid = math.sqrt(max(wn2 - mu * mu, 0.0))
     Lam = min(mu + max(delta * mu, resid), (1.0 + delta) * fro)
     return Lam, mu, resid, it, v
+
+
+def lanczos_bound(Phi: np.ndarray, seed: int = 0, steps: int = 12, delta: float = 0.01, v0=None, cap=None):
+    """Returns (Lambda, theta, resid, steps_done, y, alpha, beta)."""
+    Phi = np.asarray(Phi, dtype=np.float64)
+    d = Phi.shape[0]
+    fro = math.sqrt(float(np.sum(Phi * Phi))) if cap is None else float(cap)
+    if d == 0 or fro == 0.0:
+        return 0.0, 0.0, 0.0, 0, np.zeros(d), np.zeros(0), np.zeros(0)
+    v = start_vector(d, seed) if v0 is None else np.asarray(v0, dtype=np.float64).copy()
+    nv = math.sqrt(float(v @ v))
+    if nv == 0.0:
+        return fro, 0.0, 0.0, 0, v, np.zeros(0), np.zeros(0)
+    k = min(int(steps), d)
+    Q = np.zeros((k, d))
+    alpha, beta = [], []
+    q, q_prev, b_prev = v / nv, np.zeros(d), 0.0
+    for j in range(k):
+        Q[j] = q
+        u = Phi @ q - b_prev * q_prev
+        a = float(q @ u)
+        u = u - a * q
+        b = math.sqrt(float(u @ u))
+        alpha.append(a)
+        beta.append(b)
+        if b == 0.0:
+            break
+        q_prev, q, b_prev = q, u / b, b
+    m = len(alpha)
+    if m == 1 and alpha[0] == 0.0 and beta[0] == 0.0:
+        return fro, 0.0, 0.0, 1, Q[0], np.array(alpha), np.array(beta)   # the product vanished
+    T = np.diag(alpha) + np.diag(beta[:m - 1], 1) + np.diag(beta[:m - 1], -1)
+    ev, S = np.linalg.eigh(T)
+    theta, s = float(ev[-1]), S[:, -1]
+    resid = beta[m - 1] * abs(float(s[m - 1]))
+    y = s @ Q[:m]
+    Lam = min(theta + max(delta * theta, resid), (1.0 + delta) * fro)
+    return Lam, theta, resid, m, y, np.array(alpha), np.array(beta)
