@@ -102,6 +102,7 @@ struct cpa_ctx {
     int spf_dct_d = 0;         // the full-DCT matrices in spf are built for this side (0: none)
     int spf_last_d = 0;        // the side of the last sparsified call (the layout depends on it)
     int spf_warm_d = -1;       // side of the full-coordinate warm vector in spf (-1: none)
+    int32_t* spf_host = nullptr;   // pinned host word: the compact block's size, read back per call
     void* inp = nullptr;       // inpainting driver: DCT matrices, product scratch, partial sums
     size_t inp_bytes = 0;
     void* f64 = nullptr;       // FP64 shrink: Gram, two Y buffers, product buffer
@@ -634,6 +635,12 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
         if (G64) {
             void* args[] = {&d_, &G64, &ldg, &wb0, &wb1, &part, &counter, &scal, &maxit_, &tol, &pw_mu, &pw_w2};
             ls = launch_power(ctx, reinterpret_cast<const void*>(power_coop_kernel<double>), w.lay.pwg, args, st);
+        } else if (d <= kPowerWgMaxD) {
+            // small sides: one workgroup with G in registers, no grid barrier
+            hipLaunchKernelGGL(power_wg_kernel, dim3(1), dim3(kPowerWgThreads), 0, st, d, G, ldg, wb0, wb1, scal,
+                               maxit_, tol, pw_mu, pw_w2);
+            HIP_TRY(hipGetLastError());
+            ls = CPA_OK;
         } else {
             void* args[] = {&d_, &G, &ldg, &wb0, &wb1, &part, &counter, &scal, &maxit_, &tol, &pw_mu, &pw_w2};
             ls = launch_power(ctx, reinterpret_cast<const void*>(power_coop_kernel<float>), w.lay.pwg, args, st);
@@ -1444,6 +1451,7 @@ cpa_status cpa_destroy(cpa_ctx* ctx) {
     if (ctx->admm_exec) (void)hipGraphExecDestroy(ctx->admm_exec);
     if (ctx->queue) (void)hipFree(ctx->queue);
     if (ctx->spf) (void)hipFree(ctx->spf);
+    if (ctx->spf_host) (void)hipHostFree(ctx->spf_host);
     if (ctx->inp) (void)hipFree(ctx->inp);
     if (ctx->f64) (void)hipFree(ctx->f64);
     if (ctx->rpca) (void)hipFree(ctx->rpca);
@@ -2798,8 +2806,11 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
     // given eps it may be zero -- one wait for the stream in either case
     int32_t ns = -1;
     if (poly || abs_eps) {
-        HIP_TRY(hipMemcpyAsync(&ns, f.nrows, sizeof(ns), hipMemcpyDeviceToHost, st));
+        // into pinned memory: a direct copy, not the staged one of pageable memory
+        if (!ctx->spf_host) HIP_TRY(hipHostMalloc((void**)&ctx->spf_host, sizeof(int32_t), hipHostMallocDefault));
+        HIP_TRY(hipMemcpyAsync(ctx->spf_host, f.nrows, sizeof(ns), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
+        ns = *ctx->spf_host;
         if (ns < 0 || ns > d || (ns == 0 && !abs_eps))
             return fail(CPA_ERR_HIP, "compact block size %d read back out of range", ns);
         if (ns == 0) {

@@ -310,6 +310,137 @@ __global__ void __launch_bounds__(kPowerThreads) power_coop_kernel(int d, const 
     }
 }
 
+// Power iteration for a Gram of side d <= kPowerWgMaxD in one workgroup: the same
+// products, Rayleigh quotients, stopping rule and outputs as power_coop_kernel
+// (w_t in the buffer of t's parity, mu_t and ||w_t||^2 in their slots, the stop
+// record), with G held in registers for the whole iteration, so that a product
+// costs two workgroup barriers instead of device-wide round trips.  Wave w takes
+// the 64 x 64 block of G at row block w % 4 and column block w / 4: lane l holds
+// row 64 (w % 4) + l of that block (64 floats) and v's entry for column
+// 64 (w / 4) + l, which the products broadcast by readlane.  Entries past d are
+// zero, so every wave runs the same steps.  The four partial row sums meet in LDS
+// and are added in a fixed order; each sum over the d rows is four wave sums
+// (DPP, fixed order) added in a fixed order, so every wave takes the same
+// stopping decision.
+constexpr int kPowerWgMaxD = 256;
+constexpr int kPowerWgThreads = 1024;
+
+__device__ inline double pw_readlane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <int CTRL>
+__device__ inline double pw_dpp(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sums of a and b over the 64 lanes (equal in every lane): within rows of 16
+// lanes swap neighbours, swap pairs, mirror halves, mirror the row; then the
+// four row sums in a fixed order.
+__device__ inline void pw_wave_sum2(double& a, double& b) {
+    a += pw_dpp<0xB1>(a);
+    b += pw_dpp<0xB1>(b);
+    a += pw_dpp<0x4E>(a);
+    b += pw_dpp<0x4E>(b);
+    a += pw_dpp<0x141>(a);
+    b += pw_dpp<0x141>(b);
+    a += pw_dpp<0x140>(a);
+    b += pw_dpp<0x140>(b);
+    a = (pw_readlane(a, 0) + pw_readlane(a, 16)) + (pw_readlane(a, 32) + pw_readlane(a, 48));
+    b = (pw_readlane(b, 0) + pw_readlane(b, 16)) + (pw_readlane(b, 32) + pw_readlane(b, 48));
+}
+
+__global__ void __launch_bounds__(kPowerWgThreads) power_wg_kernel(int d, const float* G, int64_t ldg, double* wb0,
+                                                                 double* wb1, double* scal, int maxit, double tol,
+                                                                 int pw_mu, int pw_w2) {
+    __shared__ double rowp[2][4][kPowerWgMaxD];   // partial row sums by column block, by parity
+    __shared__ double red[2][2][4];               // per column block: v.w and ||w||^2 parts, by parity
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int rb = wave & 3, cb = wave >> 2;
+    const int row = 64 * rb + lane, col = 64 * cb + lane;
+    const bool live = 64 * rb < d && 64 * cb < d;   // uniform per wave
+    float g[64];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) g[j] = 0.f;
+    if (live && row < d) {
+        const float* gr = G + (int64_t)row * ldg + 64 * cb;
+        if (((ldg & 3) == 0) && ((reinterpret_cast<uintptr_t>(G) & 15) == 0) && 64 * cb + 64 <= d) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const f32x4 x = *reinterpret_cast<const f32x4*>(gr + 4 * q);
+                g[4 * q] = x[0];
+                g[4 * q + 1] = x[1];
+                g[4 * q + 2] = x[2];
+                g[4 * q + 3] = x[3];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 64; ++j)
+                if (64 * cb + j < d) g[j] = gr[j];
+        }
+    }
+    double v = col < d ? wb0[col] : 0.0;   // w_{t-1} for this lane's column (unnormalised)
+    double w2prev = scal[pw_w2 + 0];
+    double muprev = 0.0;
+    int stop = 0, vanish = !(w2prev > 0.0);
+    int t = 1;
+    for (; !vanish && t <= maxit; ++t) {
+        const int par = t & 1;
+        const double inv = 1.0 / sqrt(w2prev);
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        if (live) {
+            // the empty asm keeps the FP64 conversions of G inside the loop (hoisted,
+            // they would take 128 registers)
+#pragma unroll
+            for (int j = 0; j < 64; ++j) asm volatile("" : "+v"(g[j]));
+#pragma unroll
+            for (int j = 0; j < 64; ++j) a[j & 3] += (double)g[j] * pw_readlane(v, j);
+        }
+        rowp[par][cb][row] = (a[0] + a[1]) + (a[2] + a[3]);
+        __syncthreads();
+        // w_t for this lane's column, the new iterate (rows and columns share the index)
+        const double wi = ((rowp[par][0][col] + rowp[par][1][col]) + (rowp[par][2][col] + rowp[par][3][col])) * inv;
+        double mu_p = (v * inv) * wi, w2_p = wi * wi;
+        pw_wave_sum2(mu_p, w2_p);
+        if (rb == 0) {
+            if (lane == 0) {
+                red[par][0][cb] = mu_p;
+                red[par][1][cb] = w2_p;
+            }
+            if (col < d) ((t & 1) ? wb1 : wb0)[col] = wi;
+        }
+        __syncthreads();
+        const double mu = (red[par][0][0] + red[par][0][1]) + (red[par][0][2] + red[par][0][3]);
+        const double w2 = (red[par][1][0] + red[par][1][1]) + (red[par][1][2] + red[par][1][3]);
+        if (threadIdx.x == 0) {
+            scal[pw_mu + t] = mu;
+            scal[pw_w2 + t] = w2;
+        }
+        if (!(w2 > 0.0)) {
+            vanish = 1;
+            break;
+        }
+        if (t >= 2 && fabs(mu - muprev) <= tol * mu) {
+            stop = t;
+            break;
+        }
+        muprev = mu;
+        w2prev = w2;
+        v = wi;
+    }
+    if (threadIdx.x == 0) {
+        scal[SC_STOP] = stop ? stop : (vanish ? 0 : maxit);
+        scal[SC_VANISH] = vanish;
+    }
+}
+
 constexpr int kCoefLds = 1024;   // orders up to this use the cosine-table coefficient path
 
 // Bound rule + coefficients + recurrence scalars.  Single workgroup.
