@@ -88,8 +88,27 @@ typedef struct {
  *                        cpa_shrink_batched_predicted).  With check = 1 a failed check
  *                        recomputes with the power-iteration bound (power_iters, power_tol).
  *                        Dense entry points only (cpa_shrink_dense, _noalloc,
- *                        cpa_spectral_bound); the others return CPA_ERR_UNSUPPORTED */
-typedef enum { CPA_BOUND_POWER = 0, CPA_BOUND_GIVEN = 1, CPA_BOUND_FROBENIUS = 2, CPA_BOUND_LEARNED = 3 } cpa_bound_rule;
+ *                        cpa_spectral_bound); the others return CPA_ERR_UNSUPPORTED
+ *   CPA_BOUND_LANCZOS    k-step Lanczos on the Gram from the power rule's start vector (or the
+ *                        warm-start vector): q_1 = v/||v||, u = Gram q_j - beta_{j-1} q_{j-1},
+ *                        alpha_j = q_j.u, u -= alpha_j q_j, beta_j = ||u||, q_{j+1} = u/beta_j
+ *                        (no reorthogonalisation; k = min(lanczos_steps, d) steps, fewer if a
+ *                        beta_j is exactly 0); theta = largest eigenvalue of the tridiagonal
+ *                        T_k, ||r|| = beta_k |s_k| with s its unit eigenvector;
+ *                        Lambda = min(theta + max(margin * theta, ||r||), (1 + margin) ||Gram||_F).
+ *                        The Ritz vector sum_j s_j q_j is the next warm start; info.mu and
+ *                        info.resid report theta and ||r||, power_iters_done the steps.
+ *                        Gram sides up to 256 on the dense FP32 entry points (cpa_shrink_dense,
+ *                        _noalloc, cpa_spectral_bound, the sparsified shrink's compact block)
+ *                        and every matrix of the batched path (d <= 64); CPA_ERR_UNSUPPORTED
+ *                        on larger sides and on the CSR, FP64 and driver entry points */
+typedef enum {
+    CPA_BOUND_POWER = 0,
+    CPA_BOUND_GIVEN = 1,
+    CPA_BOUND_FROBENIUS = 2,
+    CPA_BOUND_LEARNED = 3,
+    CPA_BOUND_LANCZOS = 4
+} cpa_bound_rule;
 
 /* Arithmetic of the recurrence products (the Gram and the bound are always FP32
  * MFMA with FP64 reductions).
@@ -157,7 +176,7 @@ typedef struct {
                              paper; a ripple reducer for steep responses such as the high-order hard
                              threshold).  Dense, CSR and sparsified paths and the drivers; the
                              batched path rejects it */
-    int32_t reserved;     /* must be 0 */
+    int32_t lanczos_steps; /* CPA_BOUND_LANCZOS: Lanczos steps in [1, 32]; 0 selects 12 */
     const float* model;   /* CPA_BOUND_LEARNED: the predictor model, CPA_PRED_MODEL_FLOATS floats in
                              device memory (caller-owned); ignored by the other rules */
     const double* coeffs; /* NULL: the shrinkage's Chebyshev coefficients (Sec. III-A).  Else K

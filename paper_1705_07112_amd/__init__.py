@@ -28,7 +28,7 @@ LIB_PATH = os.path.join(_HERE, "libcpasvt.so")
 HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "cpasvt.h")
 
 SOFT, HARD, WEIGHTED_CONST, WEIGHTED_FN = 0, 1, 2, 3
-BOUND_POWER, BOUND_GIVEN, BOUND_FROBENIUS, BOUND_LEARNED = 0, 1, 2, 3
+BOUND_POWER, BOUND_GIVEN, BOUND_FROBENIUS, BOUND_LEARNED, BOUND_LANCZOS = 0, 1, 2, 3, 4
 PREC_FP32, PREC_BF16X3, PREC_FP64 = 0, 1, 2
 OK, ERR_ARG, ERR_SHAPE, ERR_ALLOC, ERR_HIP, ERR_NONFINITE, ERR_BOUND, ERR_UNSUPPORTED, ERR_IO = range(9)
 
@@ -44,7 +44,7 @@ class CpaOpts(ctypes.Structure):
                 ("power_tol", ctypes.c_double), ("margin", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("check", ctypes.c_int32), ("precision", ctypes.c_int32), ("growth_tol", ctypes.c_double),
                 ("eval", ctypes.c_int32), ("side", ctypes.c_int32), ("damping", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("model", ctypes.c_void_p), ("coeffs", ctypes.c_void_p)]
+                ("lanczos_steps", ctypes.c_int32), ("model", ctypes.c_void_p), ("coeffs", ctypes.c_void_p)]
 
 
 class CpaInfo(ctypes.Structure):
@@ -215,7 +215,7 @@ def weighted_fn(w_c: float, w_sigma: float, w_eps: float = 1e-6) -> CpaShrinkage
 @dataclass
 class Opts:
     K: int = 16
-    bound: str = "power"          # "power" | "given" | "frobenius" | "learned" (needs model)
+    bound: str = "power"          # "power" | "given" | "frobenius" | "learned" (needs model) | "lanczos"
     Lambda: float | None = None
     power_iters: int = 100
     warm_start: bool = False
@@ -228,6 +228,7 @@ class Opts:
     eval: str = "auto"           # "auto" | "recurrence" | "polynomial"
     side: str = "auto"           # "auto" | "right" (Gram X^T X) | "left" (Gram X X^T)
     damping: str = "none"        # "none" | "jackson" | "lanczos" (coefficient damping; not in the paper)
+    lanczos_steps: int = 0        # bound "lanczos": steps (1..32; 0: the library's default, 12)
     model: object = None          # bound "learned": the predictor model (float32 CUDA tensor)
     coeffs: object = None         # caller-given coefficients (float64 CUDA tensor of K entries; bound "given")
 
@@ -239,7 +240,7 @@ class Opts:
         if self.Lambda is not None and bound == "power":
             bound = "given"
         o.bound = {"power": BOUND_POWER, "given": BOUND_GIVEN, "frobenius": BOUND_FROBENIUS,
-                   "learned": BOUND_LEARNED}[bound]
+                   "learned": BOUND_LEARNED, "lanczos": BOUND_LANCZOS}[bound]
         if self.model is not None:
             if self.model.dtype.itemsize != 4 or not self.model.is_cuda or not self.model.is_contiguous() \
                     or self.model.numel() != PRED_MODEL_FLOATS:
@@ -262,6 +263,7 @@ class Opts:
         o.eval = {"auto": 0, "recurrence": 1, "polynomial": 2}[self.eval]
         o.side = {"auto": 0, "right": 1, "left": 2}[self.side]
         o.damping = {"none": 0, "jackson": 1, "lanczos": 2}[self.damping]
+        o.lanczos_steps = int(self.lanczos_steps)
         return o
 
 

@@ -5,8 +5,9 @@
 //   Z = X_j viewed so that its short side is first: Z = X_j when m_j <= n_j,
 //       Z = X_j^T otherwise (d = min(m_j, n_j) <= 64 rows, e = max <= 128 columns);
 //   Gram G = Z Z^T (d x d) with MFMA, ||G||_F^2 in FP64;
-//   bound: power iteration on G in LDS (FP64), Lambda given, (1+delta)||G||_F, or
-//       the learned predictor (features of G -> perceptron -> Lambda and K_j);
+//   bound: power iteration or k-step Lanczos on G in LDS (FP64), Lambda given,
+//       (1+delta)||G||_F, or the learned predictor (features of G -> perceptron ->
+//       Lambda and K_j);
 //   coefficients c_k in FP64 (eq. chebychev_coeff_shifted);
 //   Y_0 = Z, Y_1 = Ghat Y_0, Y_{k+1} = 2 Ghat Y_k - Y_{k-1}, out = sum c_k Y_k with
 //   Ghat = (2/Lambda) G - I fused as (2/Lambda) G Y - Y.
@@ -42,6 +43,7 @@
 #include "gemm_f32.hpp"
 #include "mlp.hpp"
 #include "shrink_fn.hpp"
+#include "spectral.hpp"
 
 namespace cpa {
 
@@ -80,6 +82,7 @@ struct BatchArgs {
     int check;                 // growth check on/off
     double growth_tol;
     int power_iters;
+    int lanczos;               // mode 0: 0 power iteration, > 0 Lanczos steps
     double tol, margin;
     uint64_t seed;
     int* queue;                // next queue position (zeroed before launch)
@@ -364,6 +367,67 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
                 Lam = a.lambda_in[idx];
             } else if (mode == 2 || !(fro > 0.0)) {
                 Lam = (1.0 + a.margin) * fro;
+            } else if (mode == 0 && a.lanczos > 0) {
+                // k-step Lanczos on G (the dense path's rule; the power branch's start
+                // vector, layout and products): after each product's barrier every wave
+                // forms u, alpha and beta alike, so the stop decisions agree; lane j keeps
+                // alpha_j and beta_j for the Ritz pair (lz_ritz)
+                double q = 0.0;
+                if (lane < d) {
+                    const uint64_t z = a.seed + (uint64_t)(lane + 1) * 0x9E3779B97F4A7C15ull;
+                    uint64_t o = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+                    o = (o ^ (o >> 27)) * 0x94D049BB133111EBull;
+                    o ^= o >> 31;
+                    q = 2.0 * ((double)(o >> 11) * (1.0 / 9007199254740992.0)) - 1.0;
+                }
+                const double nv = bt_wave_sum(q * q);
+                bool vanish = !(nv > 0.0);
+                double al = 0.0, be = 0.0;
+                int k = 0;
+                if (!vanish) {
+                    q = q / sqrt(nv);
+                    const int j0 = __builtin_amdgcn_readfirstlane(16 * wave);
+                    f32x4 grow[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) grow[t] = *reinterpret_cast<const f32x4*>(&Gs[lane * BT_DP + j0 + 4 * t]);
+                    double qprev = 0.0, bprev = 0.0;
+                    const int steps = a.lanczos < d ? a.lanczos : d;
+                    for (int j = 0; j < steps; ++j) {
+                        double p4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int u = 0; u < 16; ++u) p4[u & 3] += (double)grow[u >> 2][u & 3] * bt_readlane(q, j0 + u);
+                        double* pb = pw + (j & 1) * BT_THREADS;
+                        pb[threadIdx.x] = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+                        __syncthreads();
+                        double uu = ((pb[lane] + pb[64 + lane]) + (pb[128 + lane] + pb[192 + lane])) - bprev * qprev;
+                        const double alpha = bt_wave_sum(q * uu);
+                        uu -= alpha * q;
+                        const double beta = sqrt(bt_wave_sum(uu * uu));
+                        if (lane == j) {
+                            al = alpha;
+                            be = beta;
+                        }
+                        k = j + 1;
+                        int stop = (j == 0 && alpha == 0.0 && beta == 0.0) ? 2 : (beta == 0.0 ? 1 : 0);
+                        stop = __builtin_amdgcn_readfirstlane(stop);
+                        if (stop == 2) {
+                            vanish = true;
+                            break;
+                        }
+                        if (stop == 1) break;
+                        qprev = q;
+                        q = uu / beta;
+                        bprev = beta;
+                    }
+                }
+                if (vanish) {
+                    Lam = (1.0 + a.margin) * fro;
+                } else {
+                    double theta, r, s;
+                    lz_ritz(al, be, k, theta, r, s);
+                    Lam = theta + (a.margin * theta > r ? a.margin * theta : r);
+                    if (Lam > (1.0 + a.margin) * fro) Lam = (1.0 + a.margin) * fro;
+                }
             } else if (mode == 0) {
                 // power iteration on G (d x d), FP64, start vector as in the dense path.
                 // Lane i owns row i; wave w adds the columns j in [16 w, 16 w + 16)

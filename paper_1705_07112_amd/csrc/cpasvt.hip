@@ -478,16 +478,28 @@ cpa_status no_learned_bound(const cpa_opts* o) {
     return s != CPA_OK ? s : no_given_coeffs(o);
 }
 
+// Lanczos steps of the Lanczos rule (0 selects the default).
+int lanczos_steps(const cpa_opts* o) { return o->lanczos_steps > 0 ? o->lanczos_steps : kLanczosDefault; }
+
+// The Lanczos rule runs where the bound is a dense FP32 Gram of side <= 256 (one
+// workgroup holds it) or a batched matrix; elsewhere it is refused.
+cpa_status lanczos_unsupported(const cpa_opts* o, const char* where) {
+    if (o->bound == CPA_BOUND_LANCZOS)
+        return fail(CPA_ERR_UNSUPPORTED, "the Lanczos bound is not available on %s", where);
+    return CPA_OK;
+}
+
 // Power-iteration slots of the scalar block: the power rule, and the learned
-// rule, whose check falls back to power iteration.
+// rule, whose check falls back to power iteration; the Lanczos rule's steps.
 int power_slots(const cpa_opts* o) {
+    if (o->bound == CPA_BOUND_LANCZOS) return lanczos_steps(o);
     return (o->bound == CPA_BOUND_POWER || o->bound == CPA_BOUND_LEARNED) ? o->power_iters : 1;
 }
 
 cpa_status check_opts(const cpa_opts* o) {
     if (!o) return fail(CPA_ERR_ARG, "opts is NULL");
     if (o->K < 1 || o->K > kMaxK) return fail(CPA_ERR_ARG, "K must be in [1, %d], got %d", kMaxK, o->K);
-    if (o->bound < 0 || o->bound > 3) return fail(CPA_ERR_ARG, "unknown bound rule %d", o->bound);
+    if (o->bound < 0 || o->bound > 4) return fail(CPA_ERR_ARG, "unknown bound rule %d", o->bound);
     if (o->bound == CPA_BOUND_LEARNED && !o->model) return fail(CPA_ERR_ARG, "the learned bound needs opts.model");
     if (o->bound == CPA_BOUND_GIVEN && !(std::isfinite(o->Lambda) && o->Lambda >= 0.0))
         return fail(CPA_ERR_ARG, "given Lambda must be finite and >= 0");
@@ -496,6 +508,9 @@ cpa_status check_opts(const cpa_opts* o) {
             return fail(CPA_ERR_ARG, "power_iters must be in [1, %d]", kMaxPowerIters);
         if (!(o->power_tol >= 0.0) || !(o->margin >= 0.0)) return fail(CPA_ERR_ARG, "power_tol and margin must be >= 0");
     }
+    if (o->lanczos_steps < 0 || o->lanczos_steps > kLanczosMax)
+        return fail(CPA_ERR_ARG, "lanczos_steps must be in [0, %d]", kLanczosMax);
+    if (o->bound == CPA_BOUND_LANCZOS && !(o->margin >= 0.0)) return fail(CPA_ERR_ARG, "margin must be >= 0");
     if (o->precision != CPA_PREC_FP32 && o->precision != CPA_PREC_BF16X3)
         return fail(CPA_ERR_UNSUPPORTED, "precision %d not supported", o->precision);
     if (o->eval < CPA_EVAL_AUTO || o->eval > CPA_EVAL_POLYNOMIAL) return fail(CPA_ERR_ARG, "unknown eval %d", o->eval);
@@ -504,7 +519,6 @@ cpa_status check_opts(const cpa_opts* o) {
     if (o->side < CPA_SIDE_AUTO || o->side > CPA_SIDE_LEFT) return fail(CPA_ERR_ARG, "unknown side %d", o->side);
     if (o->damping < CPA_DAMP_NONE || o->damping > CPA_DAMP_LANCZOS)
         return fail(CPA_ERR_ARG, "unknown damping %d", o->damping);
-    if (o->reserved != 0) return fail(CPA_ERR_ARG, "opts.reserved must be 0");
     if (o->coeffs) {
         if (o->bound != CPA_BOUND_GIVEN)
             return fail(CPA_ERR_ARG, "caller-given coefficients need the given bound (they belong to one Lambda)");
@@ -604,7 +618,10 @@ bool poly_fused(const Work& w, int K) { return w.poly_s > 0 && K >= 2; }
 
 // The finish kernel's bound mode of a rule: 0 power, 1 given, 2 Frobenius, 3 learned.
 int bound_mode(int rule) {
-    return rule == CPA_BOUND_POWER ? 0 : rule == CPA_BOUND_GIVEN ? 1 : rule == CPA_BOUND_FROBENIUS ? 2 : 3;
+    return (rule == CPA_BOUND_POWER || rule == CPA_BOUND_LANCZOS) ? 0
+           : rule == CPA_BOUND_GIVEN                              ? 1
+           : rule == CPA_BOUND_FROBENIUS                          ? 2
+                                                                  : 3;
 }
 
 // logmn: log(m n) of the input (the learned rule's third feature).
@@ -635,6 +652,14 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
         if (G64) {
             void* args[] = {&d_, &G64, &ldg, &wb0, &wb1, &part, &counter, &scal, &maxit_, &tol, &pw_mu, &pw_w2};
             ls = launch_power(ctx, reinterpret_cast<const void*>(power_coop_kernel<double>), w.lay.pwg, args, st);
+        } else if (o->bound == CPA_BOUND_LANCZOS) {
+            if (d > kPowerWgMaxD)
+                return fail(CPA_ERR_UNSUPPORTED, "the Lanczos bound takes Gram sides up to %d (got %d)", kPowerWgMaxD, d);
+            const int steps = std::min(lanczos_steps(o), d);
+            hipLaunchKernelGGL(lanczos_wg_kernel, dim3(1), dim3(kPowerWgThreads), 0, st, d, G, ldg, wb0, wb1, scal,
+                               steps, pw_mu, pw_w2);
+            HIP_TRY(hipGetLastError());
+            ls = CPA_OK;
         } else if (d <= kPowerWgMaxD) {
             // small sides: one workgroup with G in registers, no grid barrier
             hipLaunchKernelGGL(power_wg_kernel, dim3(1), dim3(kPowerWgThreads), 0, st, d, G, ldg, wb0, wb1, scal,
@@ -1778,6 +1803,7 @@ cpa_status batched_shrink_args(const cpa_opts* opts, const float* X_dev, float* 
     if (!shrink_dev) a.shrink0 = to_params(shrink_host);
     a.K = opts->K;
     a.power_iters = opts->power_iters;
+    a.lanczos = opts->bound == CPA_BOUND_LANCZOS ? lanczos_steps(opts) : 0;
     a.tol = opts->power_tol;
     a.margin = opts->margin;
     a.seed = opts->seed;
@@ -1799,7 +1825,9 @@ cpa_status cpa_shrink_batched(cpa_ctx* ctx, void* stream, int batch, const int32
     if ((s = batched_shrink_args(opts, X_dev, Y_dev, shrink_dev, shrink_host, a)) != CPA_OK) return s;
     if (opts->bound == CPA_BOUND_GIVEN && !Lambda_dev) return fail(CPA_ERR_ARG, "Lambda_dev is NULL");
     if (batch == 0) return CPA_OK;
-    a.mode = opts->bound == CPA_BOUND_POWER ? 0 : (opts->bound == CPA_BOUND_GIVEN ? 1 : 2);
+    a.mode = (opts->bound == CPA_BOUND_POWER || opts->bound == CPA_BOUND_LANCZOS) ? 0
+             : opts->bound == CPA_BOUND_GIVEN                                     ? 1
+                                                                                  : 2;
     a.lambda_in = Lambda_dev;
     a.lambda_out = Lambda_out_dev;
     a.status = status_dev;
@@ -1938,7 +1966,9 @@ cpa_status cpa_batched_plan_create(cpa_ctx* ctx, void* stream, int batch, const 
     if ((s = batched_shrink_args(opts, X_dev, Y_dev, shrink_dev, shrink_host, a)) != CPA_OK) return s;
     if (opts->bound == CPA_BOUND_GIVEN && !Lambda_dev) return fail(CPA_ERR_ARG, "Lambda_dev is NULL");
     if (tune != 0 && tune != 1) return fail(CPA_ERR_ARG, "tune must be 0 or 1");
-    a.mode = opts->bound == CPA_BOUND_POWER ? 0 : (opts->bound == CPA_BOUND_GIVEN ? 1 : 2);
+    a.mode = (opts->bound == CPA_BOUND_POWER || opts->bound == CPA_BOUND_LANCZOS) ? 0
+             : opts->bound == CPA_BOUND_GIVEN                                     ? 1
+                                                                                  : 2;
     a.lambda_in = Lambda_dev;
     a.lambda_out = Lambda_out_dev;
     a.status = status_dev;
@@ -2230,6 +2260,7 @@ cpa_status cpa_shrink_csr(cpa_ctx* ctx, void* stream, int m, int n, int64_t nnz,
     if ((s = check_shrinkage(shrink)) != CPA_OK) return s;
     if ((s = check_opts(opts)) != CPA_OK) return s;
     if ((s = learned_bound_unsupported(opts)) != CPA_OK) return s;
+    if ((s = lanczos_unsupported(opts, "the CSR path")) != CPA_OK) return s;
     if (opts->precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "sparse path is FP32");
     if (opts->check) return fail(CPA_ERR_UNSUPPORTED, "the growth check is not available on the sparse path");
     if (m == 0 || n == 0) {
@@ -2271,6 +2302,7 @@ cpa_status cpa_svt_complete(cpa_ctx* ctx, void* stream, int m, int n, int64_t nn
     if (opts && opts->side == CPA_SIDE_LEFT) return fail(CPA_ERR_UNSUPPORTED, "sparse path forms S^T S (side right)");
     if ((s = check_opts(opts)) != CPA_OK) return s;
     if ((s = no_learned_bound(opts)) != CPA_OK) return s;
+    if ((s = lanczos_unsupported(opts, "the CSR path")) != CPA_OK) return s;
     if (opts->precision != CPA_PREC_FP32 || opts->check) return fail(CPA_ERR_UNSUPPORTED, "unsupported option");
     if (!(std::isfinite(tau) && tau >= 0.0 && std::isfinite(delta) && delta > 0.0) || iters < 0)
         return fail(CPA_ERR_ARG, "tau >= 0, delta > 0 and iters >= 0 required");
@@ -2384,6 +2416,7 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
     if (iters < 0) return fail(CPA_ERR_ARG, "iters < 0");
     if ((s = check_opts(opts)) != CPA_OK) return s;
     if ((s = no_learned_bound(opts)) != CPA_OK) return s;
+    if ((s = lanczos_unsupported(opts, "the RPCA driver")) != CPA_OK) return s;
     if (!(std::isfinite(inv_rho) && inv_rho >= 0.0 && std::isfinite(eta_over_rho) && eta_over_rho >= 0.0))
         return fail(CPA_ERR_ARG, "inv_rho and eta_over_rho must be finite and >= 0");
     if (m == 0 || n == 0 || iters == 0) return CPA_OK;
@@ -2837,7 +2870,8 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
         wc.lay.pwg = power_grid(ctx, nb);
         // warm start: the previous call's vector, mapped from full coordinates onto this
         // call's block
-        const bool warm_map = opts->warm_start && opts->bound == CPA_BOUND_POWER;
+        const bool warm_map =
+            opts->warm_start && (opts->bound == CPA_BOUND_POWER || opts->bound == CPA_BOUND_LANCZOS);
         if (warm_map) {
             if (ctx->spf_warm_d == d) {
                 hipLaunchKernelGGL(warm_gather_kernel, dim3((nb + 255) / 256), dim3(256), 0, st, ns, nb,
@@ -3038,6 +3072,7 @@ cpa_status inpaint_run(cpa_ctx* ctx, void* stream, int m, int n, const float* I_
     if (iters < 0) return fail(CPA_ERR_ARG, "iters < 0");
     if ((s = check_opts(opts)) != CPA_OK) return s;
     if ((s = no_learned_bound(opts)) != CPA_OK) return s;
+    if ((s = lanczos_unsupported(opts, "the inpainting driver")) != CPA_OK) return s;
     if (!(std::isfinite(inv_rho) && inv_rho >= 0.0 && std::isfinite(eta_over_rho) && eta_over_rho >= 0.0))
         return fail(CPA_ERR_ARG, "inv_rho and eta_over_rho must be finite and >= 0");
     if (m == 0 || n == 0 || iters == 0) return CPA_OK;
@@ -3246,6 +3281,7 @@ cpa_status cpa_shrink_dense_f64(cpa_ctx* ctx, void* stream, int m, int n, const 
     if (o.precision == CPA_PREC_FP64) o.precision = CPA_PREC_FP32;   // the arithmetic here is FP64 in any case
     if ((s = check_opts(&o)) != CPA_OK) return s;
     if ((s = no_learned_bound(&o)) != CPA_OK) return s;
+    if ((s = lanczos_unsupported(&o, "the FP64 path")) != CPA_OK) return s;
     if (o.precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "the FP64 path has no split precision");
     if (o.check) return fail(CPA_ERR_UNSUPPORTED, "the growth check is not available on the FP64 path");
     if (o.eval == CPA_EVAL_POLYNOMIAL) return fail(CPA_ERR_UNSUPPORTED, "the FP64 path evaluates by the recurrence");
@@ -3324,6 +3360,7 @@ cpa_status cpa_rpca_admm(cpa_ctx* ctx, void* stream, int m, int n, const float* 
     if (!(tol >= 0.0)) return fail(CPA_ERR_ARG, "tol must be >= 0");
     if ((s = check_opts(opts)) != CPA_OK) return s;
     if ((s = no_learned_bound(opts)) != CPA_OK) return s;
+    if ((s = lanczos_unsupported(opts, "the RPCA driver")) != CPA_OK) return s;
     if (iters_done) *iters_done = 0;
     if (m == 0 || n == 0 || max_iters == 0) return CPA_OK;
     if (!I_dev || !L_dev || !S_dev) return fail(CPA_ERR_ARG, "I, L or S is NULL");

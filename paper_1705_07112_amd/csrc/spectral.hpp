@@ -441,6 +441,219 @@ __global__ void __launch_bounds__(kPowerWgThreads) power_wg_kernel(int d, const 
     }
 }
 
+// ---- k-step Lanczos bound (a second reading of the maximum-eigenvalue step)
+//   q_1 = w_0 / ||w_0||, beta_0 = 0; step j: u = G q_j - beta_{j-1} q_{j-1},
+//   alpha_j = q_j.u, u <- u - alpha_j q_j, beta_j = ||u||, q_{j+1} = u / beta_j
+//   (no reorthogonalisation; an exactly vanishing beta_j ends the run), then the
+//   largest eigenvalue theta of the tridiagonal T_k, its unit eigenvector s, the
+//   Ritz residual ||r|| = beta_k |s_k| and the Ritz vector y = sum_j s_j q_j.  The
+//   power slots receive mu_T = theta and ||w_T||^2 = theta^2 + ||r||^2, so the
+//   finishing kernel's rule gives Lambda = min(theta + max(margin theta, ||r||),
+//   (1 + margin) ||G||_F), and y goes where the power iteration leaves its last
+//   vector (the warm start of the next call).
+constexpr int kLanczosMax = 32;
+constexpr int kLanczosDefault = 12;
+
+__device__ inline double pw_wave_sum(double a) {
+    a += pw_dpp<0xB1>(a);
+    a += pw_dpp<0x4E>(a);
+    a += pw_dpp<0x141>(a);
+    a += pw_dpp<0x140>(a);
+    return (pw_readlane(a, 0) + pw_readlane(a, 16)) + (pw_readlane(a, 32) + pw_readlane(a, 48));
+}
+
+// 1 / x: the hardware estimate and one Newton step (relative error near 2^-44,
+// a relative perturbation of that size of the pivots' quotients).
+__device__ inline double lz_rcp(double x) {
+    const double r = __builtin_amdgcn_rcp(x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// Ritz pair of T_k for its largest eigenvalue, by one wave: lane i < k holds
+// al = alpha_i and be = beta_i (T(i, i+1) for i < k - 1; lane k - 1 holds beta_k,
+// the coupling to the next Krylov vector, which is not part of T_k).
+//   theta: multisection -- each round the 64 lanes count the eigenvalues above 64
+//     equispaced points of the bracket [max alpha_i, Gershgorin bound] by the signs
+//     of the LDL^T pivots of T - x I (a zero pivot taken as -pivmin), and the
+//     bracket shrinks to the gap above the highest point with a count of at least
+//     one, until it is 2^-30 of theta wide (the bound adds a relative margin of
+//     about 1e-2, so theta is kept to about 1e-9; five rounds from a bracket of
+//     theta's size);
+//   s: the backward three-term recurrence s_{k-1} = 1,
+//     s_{i-1} = ((theta - alpha_i) s_i - beta_i s_{i+1}) / beta_{i-1} (the direction
+//     in which the top Ritz vector's entries grow), rescaled by 2^-400 whenever an
+//     entry passes 2^400, then normalised; lane i receives s_i;
+//   resid = beta_k |s_{k-1}|.
+// theta and resid are the same in every lane (same operations on the same data).
+__device__ inline void lz_ritz(double al, double be, int k, double& theta, double& resid, double& s_out) {
+    const int lane = threadIdx.x & 63;
+    const double bsq = be * be;
+    double lo = pw_readlane(al, 0), hi = lo, bmax2 = 0.0;
+    for (int i = 0; i < k; ++i) {
+        const double a = pw_readlane(al, i);
+        const double b0 = i > 0 ? fabs(pw_readlane(be, i - 1)) : 0.0;
+        const double b1 = i + 1 < k ? fabs(pw_readlane(be, i)) : 0.0;
+        lo = fmax(lo, a);
+        hi = fmax(hi, a + b0 + b1);
+        if (i + 1 < k) bmax2 = fmax(bmax2, pw_readlane(bsq, i));
+    }
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, bmax2);
+    for (int round = 0; round < 12; ++round) {
+        if (!(hi - lo > 0x1p-30 * fmax(fabs(lo), fabs(hi)))) break;
+        const double x = lo + (hi - lo) * ((double)(lane + 1) * (1.0 / 65.0));
+        int neg = 0;
+        double q = 1.0;
+        for (int i = 0; i < k; ++i) {
+            q = (pw_readlane(al, i) - x) - (i > 0 ? pw_readlane(bsq, i - 1) * lz_rcp(q) : 0.0);
+            if (fabs(q) < pivmin) q = -pivmin;
+            neg += q < 0.0 ? 1 : 0;
+        }
+        const uint64_t mask = __ballot(k - neg >= 1);
+        const int L = mask ? 63 - __clzll(mask) : -1;
+        const double xl = pw_readlane(x, L < 0 ? 0 : L);
+        const double xh = pw_readlane(x, L < 63 ? L + 1 : 63);
+        if (L >= 0) lo = xl;
+        if (L < 63) hi = xh;
+    }
+    theta = 0.5 * (lo + hi);
+    double s_mine = lane == k - 1 ? 1.0 : 0.0;
+    double s_next = 0.0, s_cur = 1.0;
+    for (int i = k - 1; i >= 1; --i) {
+        const double bi = i + 1 < k ? pw_readlane(be, i) : 0.0;
+        double s_prev = ((theta - pw_readlane(al, i)) * s_cur - bi * s_next) * lz_rcp(pw_readlane(be, i - 1));
+        if (fabs(s_prev) > 0x1p400) {
+            s_prev *= 0x1p-400;
+            s_cur *= 0x1p-400;
+            s_mine *= 0x1p-400;
+        }
+        if (lane == i - 1) s_mine = s_prev;
+        s_next = s_cur;
+        s_cur = s_prev;
+    }
+    const double nrm = sqrt(pw_wave_sum(s_mine * s_mine));
+    s_out = s_mine / nrm;
+    resid = fabs(pw_readlane(be, k - 1)) * fabs(pw_readlane(s_out, k - 1));
+}
+
+// k-step Lanczos for a Gram of side d <= kPowerWgMaxD in one workgroup, steps <=
+// kLanczosMax: the register layout of power_wg_kernel for the products; the
+// Lanczos vectors stay in LDS (for the Ritz vector).  Each step takes one
+// workgroup barrier: after it every wave forms u on all d entries from the four
+// partial row sums and adds alpha and ||u||^2 itself (the same operations in every
+// wave, so every wave holds the same alpha_j, beta_j and stopping decision).
+__global__ void __launch_bounds__(kPowerWgThreads) lanczos_wg_kernel(int d, const float* G, int64_t ldg, double* wb0,
+                                                                   double* wb1, double* scal, int steps, int pw_mu,
+                                                                   int pw_w2) {
+    __shared__ double rowp[2][4][kPowerWgMaxD];   // partial row sums by column block, by parity
+    __shared__ double Q[kLanczosMax][kPowerWgMaxD];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int rb = wave & 3, cb = wave >> 2;
+    const int row = 64 * rb + lane, col = 64 * cb + lane;
+    const bool live = 64 * rb < d && 64 * cb < d;
+    float g[64];
+#pragma unroll
+    for (int j = 0; j < 64; ++j) g[j] = 0.f;
+    if (live && row < d) {
+        const float* gr = G + (int64_t)row * ldg + 64 * cb;
+        if (((ldg & 3) == 0) && ((reinterpret_cast<uintptr_t>(G) & 15) == 0) && 64 * cb + 64 <= d) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const f32x4 x = *reinterpret_cast<const f32x4*>(gr + 4 * q);
+                g[4 * q] = x[0];
+                g[4 * q + 1] = x[1];
+                g[4 * q + 2] = x[2];
+                g[4 * q + 3] = x[3];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 64; ++j)
+                if (64 * cb + j < d) g[j] = gr[j];
+        }
+    }
+    const double n0 = scal[pw_w2 + 0];
+    if (!(n0 > 0.0)) {
+        // no start vector: the finishing kernel falls back to ||G||_F
+        if (threadIdx.x == 0) {
+            scal[SC_STOP] = 0;
+            scal[SC_VANISH] = 1;
+        }
+        return;
+    }
+    double q = col < d ? wb0[col] / sqrt(n0) : 0.0;   // q_j at this lane's column
+    double bprev = 0.0;
+    double al = 0.0, be = 0.0;   // lane j: alpha_j, beta_j
+    int k = 0, vanish = 0;
+    for (int j = 0; j < steps; ++j) {
+        const int par = j & 1;
+        if (rb == 0) Q[j][col] = q;
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        if (live) {
+#pragma unroll
+            for (int jj = 0; jj < 64; ++jj) asm volatile("" : "+v"(g[jj]));
+#pragma unroll
+            for (int jj = 0; jj < 64; ++jj) a[jj & 3] += (double)g[jj] * pw_readlane(q, jj);
+        }
+        rowp[par][cb][row] = (a[0] + a[1]) + (a[2] + a[3]);
+        __syncthreads();
+        double u[4], qc[4];
+        double pa = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int cc = 64 * c + lane;
+            const double gq = (rowp[par][0][cc] + rowp[par][1][cc]) + (rowp[par][2][cc] + rowp[par][3][cc]);
+            qc[c] = Q[j][cc];
+            u[c] = gq - (j > 0 ? bprev * Q[j - 1][cc] : 0.0);
+            pa += qc[c] * u[c];
+        }
+        const double alpha = pw_wave_sum(pa);
+        double pb = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            u[c] -= alpha * qc[c];
+            pb += u[c] * u[c];
+        }
+        const double beta = sqrt(pw_wave_sum(pb));
+        if (lane == j) {
+            al = alpha;
+            be = beta;
+        }
+        k = j + 1;
+        if (j == 0 && alpha == 0.0 && beta == 0.0) {
+            vanish = 1;
+            break;
+        }
+        if (beta == 0.0) break;
+        const double uc = cb == 0 ? u[0] : (cb == 1 ? u[1] : (cb == 2 ? u[2] : u[3]));
+        q = uc / beta;
+        bprev = beta;
+    }
+    if (vanish) {
+        if (threadIdx.x == 0) {
+            scal[SC_STOP] = 0;
+            scal[SC_VANISH] = 1;
+        }
+        return;
+    }
+    double theta, resid, s;
+    lz_ritz(al, be, k, theta, resid, s);
+    // the Ritz vector into the buffer the finishing kernel reads the last vector
+    // from (slot T - 1 holds its squared length: s is a unit vector)
+    double* yb = ((k - 1) & 1) ? wb1 : wb0;
+    if (threadIdx.x < d) {
+        double y = 0.0;
+        for (int i = 0; i < k; ++i) y += pw_readlane(s, i) * Q[i][threadIdx.x];
+        yb[threadIdx.x] = y;
+    }
+    if (threadIdx.x == 0) {
+        scal[pw_mu + k] = theta;
+        scal[pw_w2 + k] = theta * theta + resid * resid;
+        scal[pw_w2 + k - 1] = 1.0;
+        scal[SC_STOP] = k;
+        scal[SC_VANISH] = 0;
+    }
+}
+
 constexpr int kCoefLds = 1024;   // orders up to this use the cosine-table coefficient path
 
 // Bound rule + coefficients + recurrence scalars.  Single workgroup.
