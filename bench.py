@@ -29,6 +29,9 @@ ETA_OVER_RHO = 10.0 / 32.0
 MFMA_FP32_PEAK_TFLOPS = 157.3
 METRIC = "shrunk matrices/sec & TFLOP/s at rel. Frobenius err ≤1e-3 vs FP64 SVT"
 SAMPLES = {}   # GPU results of the other legs kept for the oracle leg's FP64 CPA comparison
+# Lanczos steps of the batched leg's bound: on 400 patch groups drawn like the leg's, 8 steps
+# reach the largest eigenvalue to 2e-15 relative (the bound then adds its 1% margin)
+LANCZOS_STEPS_BATCHED = 8
 
 
 def cpu_baseline(I, budget_s: float = 15.0, check=None, samples=None):
@@ -204,10 +207,12 @@ def bench_designs(cpa, torch, np, Xd, X64, ex, Lam, orders=(10, 20, 30, 50)):
 
 def bench_batched(cpa, torch, np, synth, timed_runs: int = 10):
     """Batched weighted soft shrinkage of 8192 patch-group matrices (64 x U{40..120},
-    rank 4 + N(0, 0.2^2)), K = 16, per-matrix power bound: one persistent launch,
+    rank 4 + N(0, 0.2^2)), K = 16, per-matrix bound: one persistent launch,
     captured in a graph after the autotuner picked its configuration.  Main figure:
-    split-precision products (bf16 hi/lo x3, FP32 accumulation); beside it the
-    same plan with FP32 products."""
+    split-precision products (bf16 hi/lo x3, FP32 accumulation) with the 8-step
+    Lanczos bound; beside it the power-iteration bound (tol 1e-7) and FP32
+    products with either bound, and the largest relative difference between the
+    two bounds over the batch."""
     import math
     flat, ms, ns, offs, _, _ = synth.patch_groups(batch=8192)
     dev = torch.device("cuda:0")
@@ -225,9 +230,11 @@ def bench_batched(cpa, torch, np, synth, timed_runs: int = 10):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
 
-    def run_plan(precision):
+    def run_plan(precision, bound="lanczos"):
         lam = torch.zeros(len(ms), dtype=torch.float64, device=dev)
-        plan = cpa.BatchedPlan(X, m, n, off, cpa.soft(0.0), cpa.Opts(K=16, precision=precision),
+        # a fixed number of Lanczos steps (power_tol = 0: no per-step Ritz test)
+        kw = {"bound": "lanczos", "lanczos_steps": LANCZOS_STEPS_BATCHED, "power_tol": 0.0} if bound == "lanczos" else {}
+        plan = cpa.BatchedPlan(X, m, n, off, cpa.soft(0.0), cpa.Opts(K=16, precision=precision, **kw),
                                shrink_per_matrix=rec_t, lambda_out=lam)
         plan.run()
         torch.cuda.synchronize()
@@ -244,6 +251,9 @@ def bench_batched(cpa, torch, np, synth, timed_runs: int = 10):
 
     ms_split, tun_split, Ysh, lam_sp = run_plan("bf16x3")
     ms_32, tun_32, Yh, lam = run_plan("fp32")
+    ms_split_p, tun_split_p, Ysh_p, lam_sp_p = run_plan("bf16x3", "power")
+    ms_32_p, tun_32_p, _, _ = run_plan("fp32", "power")
+    lam_diff = float(torch.max(torch.abs(lam_sp - lam_sp_p) / lam_sp_p).item())
     d = np.minimum(ms, ns).astype(np.float64)
     e = np.maximum(ms, ns).astype(np.float64)
     flop = float(np.sum(16 * 2.0 * d * d * e))
@@ -263,11 +273,12 @@ def bench_batched(cpa, torch, np, synth, timed_runs: int = 10):
     ms_single = e0.elapsed_time(e1) / nb
     # accuracy on a sample against the exact weighted shrinkage (LAPACK SVD):
     # g(s) = s - w(s^2) when s > w(s^2), w(x) = w_c / (sqrt(max(x - w_sigma, 0)) + w_eps)
-    e_svt, e_svt_split = [], []
+    e_svt, e_svt_split, e_svt_split_p = [], [], []
     for i in range(0, 8192, 256):
         Xi = flat[offs[i]:offs[i] + ms[i] * ns[i]].reshape(ms[i], ns[i]).astype(np.float64)
         Yi = Yh[offs[i]:offs[i] + ms[i] * ns[i]].reshape(ms[i], ns[i]).astype(np.float64)
         Ys = Ysh[offs[i]:offs[i] + ms[i] * ns[i]].reshape(ms[i], ns[i]).astype(np.float64)
+        Ysp = Ysh_p[offs[i]:offs[i] + ms[i] * ns[i]].reshape(ms[i], ns[i]).astype(np.float64)
         r = recs[i]
 
         def g(sv, r=r):
@@ -276,6 +287,7 @@ def bench_batched(cpa, torch, np, synth, timed_runs: int = 10):
         ex = exact_shrink(Xi, g)
         e_svt.append(rel_fro(Yi, ex, ex))
         e_svt_split.append(rel_fro(Ys, ex, ex))
+        e_svt_split_p.append(rel_fro(Ysp, ex, ex))
         rec = (3, 0.0, r.w_c, r.w_sigma, r.w_eps)
         SAMPLES.setdefault("batched_fp32", []).append((Xi, Yi, rec, float(lam[i].item()), 16))
         SAMPLES.setdefault("batched_bf16x3", []).append((Xi, Ys, rec, float(lam_sp[i].item()), 16))
@@ -284,7 +296,8 @@ def bench_batched(cpa, torch, np, synth, timed_runs: int = 10):
         return {"grid": t["grid"], "pair": t["pair"], "order": t["order"], "candidates": t["candidates"],
                 "tuned_us": round(t["best_us"], 1), "untuned_us": round(t["default_us"], 1)}
     return {
-        "workload": "8192 patch groups 64 x U{40..120}, rank 4 + N(0,0.2^2), weighted soft, K=16, power bound",
+        "workload": "8192 patch groups 64 x U{40..120}, rank 4 + N(0,0.2^2), weighted soft, K=16, "
+                    f"{LANCZOS_STEPS_BATCHED}-step Lanczos bound (all steps, no early stop)",
         "precision": "bf16x3 (split products, FP32 accumulation)",
         "value": round(8192 / (ms_split / 1e3), 1), "unit": "matrices/s", "ms_per_batch": round(ms_split, 4),
         "tflops": round(flop / (ms_split * 1e-3) / 1e12, 3),
@@ -292,6 +305,13 @@ def bench_batched(cpa, torch, np, synth, timed_runs: int = 10):
         "autotuner": tun_rec(tun_split),
         "err_vs_fp64_svt_median": float("%.3e" % float(np.median(e_svt_split))),
         "err_vs_fp64_svt_max": float("%.3e" % max(e_svt_split)),
+        "bound_rel_diff_lanczos_vs_power_max": float("%.3e" % lam_diff),
+        "power_bound": {"value": round(8192 / (ms_split_p / 1e3), 1), "unit": "matrices/s",
+                        "ms_per_batch": round(ms_split_p, 4), "autotuner": tun_rec(tun_split_p),
+                        "note": "the same split plan with the power-iteration bound (power_tol 1e-7, at most 100 "
+                                "products)",
+                        "err_vs_fp64_svt_median": float("%.3e" % float(np.median(e_svt_split_p))),
+                        "fp32_value": round(8192 / (ms_32_p / 1e3), 1)},
         "fp32": {"value": round(8192 / (ms_32 / 1e3), 1), "unit": "matrices/s", "ms_per_batch": round(ms_32, 4),
                  "tflops": round(flop / (ms_32 * 1e-3) / 1e12, 3), "autotuner": tun_rec(tun_32),
                  "err_vs_fp64_svt_median": float("%.3e" % float(np.median(e_svt))),
@@ -436,20 +456,37 @@ def bench_sparsified(cpa, torch, np, synth, reps: int = 10):
                                       "err_vs_fp64_svt": float("%.3e" % dense_err)},
            "keep": [],
            "note": "cold: every call starts its power iteration from the seeded vector; warm: from the previous "
-                   "call's vector (as inside an ADMM run), on both routes"}
+                   "call's vector (as inside an ADMM run), on both routes.  lanczos_bound: the sparsified shrink "
+                   "with the 12-step Lanczos bound on its compact block (the dense route keeps the power bound: "
+                   "its 1024-wide Gram is past the one-workgroup Lanczos kernel's 256)"}
     Ys = torch.empty_like(X)
     opts_rec = cpa.Opts(K=K, eval="recurrence")
+    opts_lz = cpa.Opts(K=K, bound="lanczos")
+    warm_lz = cpa.Opts(K=K, bound="lanczos", warm_start=True)
     for frac in (0.016, 0.03):
         keep = int(frac * n * n)
         ms_s = timed(lambda: cpa.shrink_dense_sparsified(X, cpa.soft(tau), opts, keep=keep, out=Ys))
         ms_sw = timed(lambda: cpa.shrink_dense_sparsified(X, cpa.soft(tau), warm, keep=keep, out=Ys))
         ms_r = timed(lambda: cpa.shrink_dense_sparsified(X, cpa.soft(tau), opts_rec, keep=keep, out=Ys))
+        # the Lanczos bound on the compact block (blocks up to 256 wide)
+        lz = None
+        try:
+            ms_l = timed(lambda: cpa.shrink_dense_sparsified(X, cpa.soft(tau), opts_lz, keep=keep, out=Ys))
+            ms_lw = timed(lambda: cpa.shrink_dense_sparsified(X, cpa.soft(tau), warm_lz, keep=keep, out=Ys))
+            _, il = cpa.shrink_dense_sparsified(X, cpa.soft(tau), opts_lz, keep=keep, out=Ys, info=True)
+            lz = {"ms_per_shrink": round(ms_l, 4), "speedup_vs_dense": round(ms_dense / ms_l, 3),
+                  "ms_per_shrink_warm": round(ms_lw, 4), "speedup_vs_dense_warm": round(ms_dense_w / ms_lw, 3),
+                  "Lambda": il["Lambda"], "steps": il["power_iters_done"]}
+        except cpa.CpaError as e:
+            lz = {"unsupported": str(e)}
         _, info = cpa.shrink_dense_sparsified(X, cpa.soft(tau), opts, keep=keep, out=Ys, info=True)
         Yh = Ys.cpu().numpy().astype(np.float64)
         out["keep"].append({"fraction": frac, "keep": keep, "nnz": info["nnz"], "eps": float("%.5e" % info["eps"]),
                             "ms_per_shrink": round(ms_s, 4), "speedup_vs_dense": round(ms_dense / ms_s, 3),
                             "ms_per_shrink_warm": round(ms_sw, 4), "speedup_vs_dense_warm": round(ms_dense_w / ms_sw, 3),
                             "sparse_recurrence_ms_per_shrink": round(ms_r, 4),
+                            "lanczos_bound": lz, "Lambda": info["Lambda"],
+                            "power_products": info["power_iters_done"],
                             "err_vs_fp64_svt": float("%.3e" % rel_fro(Yh, ex, ex)),
                             "err_vs_dense_route": float("%.3e" % rel_fro(Yh, Yd.cpu().numpy().astype(np.float64),
                                                                          Yd.cpu().numpy().astype(np.float64)))})

@@ -93,7 +93,10 @@ typedef struct {
  *                        warm-start vector): q_1 = v/||v||, u = Gram q_j - beta_{j-1} q_{j-1},
  *                        alpha_j = q_j.u, u -= alpha_j q_j, beta_j = ||u||, q_{j+1} = u/beta_j
  *                        (no reorthogonalisation; k = min(lanczos_steps, d) steps, fewer if a
- *                        beta_j is exactly 0); theta = largest eigenvalue of the tridiagonal
+ *                        beta_j is exactly 0 or, with power_tol > 0, at the first step j >= 2
+ *                        whose Ritz value theta_j (largest eigenvalue of T_j) satisfies
+ *                        |theta_j - theta_{j-1}| <= power_tol theta_j; power_tol = 0 runs all
+ *                        k steps); theta = largest eigenvalue of the tridiagonal
  *                        T_k, ||r|| = beta_k |s_k| with s its unit eigenvector;
  *                        Lambda = min(theta + max(margin * theta, ||r||), (1 + margin) ||Gram||_F).
  *                        The Ritz vector sum_j s_j q_j is the next warm start; info.mu and

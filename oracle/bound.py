@@ -28,7 +28,10 @@ k-step Lanczos (a second reading of the same step; the paper names no method):
   * q_1 = v_0 / ||v_0|| (the same start vector), beta_0 = 0; for j = 1..k:
     u = Phi q_j - beta_{j-1} q_{j-1}, alpha_j = q_j.u, u <- u - alpha_j q_j,
     beta_j = ||u||, q_{j+1} = u / beta_j (plain three-term recurrence, no
-    reorthogonalisation; an exactly vanishing beta_j ends the run at step j);
+    reorthogonalisation; an exactly vanishing beta_j ends the run at step j,
+    and with tol > 0 so does the first step j >= 2 whose Ritz value theta_j,
+    the largest eigenvalue of T_j, satisfies |theta_j - theta_{j-1}| <= tol theta_j,
+    the power iteration's test with the Ritz values in place of the quotients);
   * T_k = tridiagonal (alpha on the diagonal, beta_1..beta_{k-1} beside it),
     theta = its largest eigenvalue, s its unit eigenvector, Ritz vector
     y = sum_i s_i q_i, residual norm ||Phi y - theta y|| = beta_k |s_k|;
@@ -109,7 +112,8 @@ def power_bound(Phi: np.ndarray, seed: int = 0, max_iter: int = 100, tol: float 
     return Lam, mu, resid, it, v
 
 
-def lanczos_bound(Phi: np.ndarray, seed: int = 0, steps: int = 12, delta: float = 0.01, v0=None, cap=None):
+def lanczos_bound(Phi: np.ndarray, seed: int = 0, steps: int = 12, delta: float = 0.01, v0=None, cap=None,
+                  tol: float = 0.0):
     """Returns (Lambda, theta, resid, steps_done, y, alpha, beta)."""
     Phi = np.asarray(Phi, dtype=np.float64)
     d = Phi.shape[0]
@@ -124,6 +128,7 @@ def lanczos_bound(Phi: np.ndarray, seed: int = 0, steps: int = 12, delta: float 
     Q = np.zeros((k, d))
     alpha, beta = [], []
     q, q_prev, b_prev = v / nv, np.zeros(d), 0.0
+    th_prev = None
     for j in range(k):
         Q[j] = q
         u = Phi @ q - b_prev * q_prev
@@ -134,6 +139,13 @@ def lanczos_bound(Phi: np.ndarray, seed: int = 0, steps: int = 12, delta: float 
         beta.append(b)
         if b == 0.0:
             break
+        if tol > 0.0:
+            m = len(alpha)
+            Tj = np.diag(alpha) + np.diag(beta[:m - 1], 1) + np.diag(beta[:m - 1], -1)
+            th = float(np.linalg.eigvalsh(Tj)[-1])
+            if th_prev is not None and abs(th - th_prev) <= tol * th:
+                break
+            th_prev = th
         q_prev, q, b_prev = q, u / b, b
     m = len(alpha)
     if m == 1 and alpha[0] == 0.0 and beta[0] == 0.0:

@@ -382,8 +382,9 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
                 }
                 const double nv = bt_wave_sum(q * q);
                 bool vanish = !(nv > 0.0);
-                double al = 0.0, be = 0.0;
+                double al = 0.0, be = 0.0, theta = 0.0, r = 0.0, sv = 0.0, th_prev = 0.0;
                 int k = 0;
+                bool fresh = false;   // theta and r belong to T_k
                 if (!vanish) {
                     q = q / sqrt(nv);
                     const int j0 = __builtin_amdgcn_readfirstlane(16 * wave);
@@ -414,7 +415,15 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
                             vanish = true;
                             break;
                         }
+                        fresh = false;
                         if (stop == 1) break;
+                        if (a.tol > 0.0) {
+                            // early stop: successive Ritz values within tol (same in every wave)
+                            lz_ritz(al, be, k, theta, r, sv);
+                            fresh = true;
+                            if (j >= 1 && fabs(theta - th_prev) <= a.tol * theta) break;
+                            th_prev = theta;
+                        }
                         qprev = q;
                         q = uu / beta;
                         bprev = beta;
@@ -423,8 +432,7 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
                 if (vanish) {
                     Lam = (1.0 + a.margin) * fro;
                 } else {
-                    double theta, r, s;
-                    lz_ritz(al, be, k, theta, r, s);
+                    if (!fresh) lz_ritz(al, be, k, theta, r, sv);
                     Lam = theta + (a.margin * theta > r ? a.margin * theta : r);
                     if (Lam > (1.0 + a.margin) * fro) Lam = (1.0 + a.margin) * fro;
                 }

@@ -657,7 +657,7 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
                 return fail(CPA_ERR_UNSUPPORTED, "the Lanczos bound takes Gram sides up to %d (got %d)", kPowerWgMaxD, d);
             const int steps = std::min(lanczos_steps(o), d);
             hipLaunchKernelGGL(lanczos_wg_kernel, dim3(1), dim3(kPowerWgThreads), 0, st, d, G, ldg, wb0, wb1, scal,
-                               steps, pw_mu, pw_w2);
+                               steps, o->power_tol, pw_mu, pw_w2);
             HIP_TRY(hipGetLastError());
             ls = CPA_OK;
         } else if (d <= kPowerWgMaxD) {
@@ -2608,7 +2608,7 @@ struct SpfWork {
     SelState* sel;
     int32_t* pos;    // d: compact index of a nonempty row, -1 for an empty one
     int32_t* rows;   // d: the nonempty rows
-    int32_t* nrows;  // 1
+    int32_t* nrows;  // 2: the nonempty rows, the kept entries
     float* Dm;       // d x d, the full DCT (dense transform only, else null)
     float* Dt;       // its transpose
     double* warm;    // d: the compact block's power vector in full coordinates (warm start)
@@ -2630,7 +2630,7 @@ cpa_status ensure_spf(cpa_ctx* ctx, int d, bool dense_t, SpfWork& s) {
     const size_t oS = off; off = align_up(off + sizeof(SelState));
     const size_t oPos = off; off = align_up(off + sizeof(int32_t) * d);
     const size_t oRows = off; off = align_up(off + sizeof(int32_t) * d);
-    const size_t oN = off; off = align_up(off + sizeof(int32_t));
+    const size_t oN = off; off = align_up(off + 2 * sizeof(int32_t));
     const size_t oW = off; off = align_up(off + sizeof(double) * d);
     size_t oDm = 0, oDt = 0;
     if (dense_t) {
@@ -2798,16 +2798,20 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
             HIP_TRY(hipGetLastError());
         }
     }
-    // the truncated matrix: CSR, and dense in place
+    // the truncated matrix: kept entries per row; the recurrence route also builds
+    // its CSR and the dense truncated matrix in place (the polynomial route gathers
+    // the compact block with the threshold applied)
     const int gr = (d + 3) / 4;
     hipLaunchKernelGGL(trunc_count_kernel, dim3(gr), dim3(256), 0, st, d, (const float*)f.Phi, (int64_t)d,
                        (const SelState*)f.sel, f.cnt);
     HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(csc_scan_kernel, dim3(1), dim3(SP_THREADS), 0, st, d, (const int32_t*)f.cnt, f.rowptr);
-    HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(trunc_fill_kernel, dim3(gr), dim3(256), 0, st, d, f.Phi, (int64_t)d, (const SelState*)f.sel,
-                       (const int32_t*)f.rowptr, f.colidx, f.val);
-    HIP_TRY(hipGetLastError());
+    if (!poly) {
+        hipLaunchKernelGGL(csc_scan_kernel, dim3(1), dim3(SP_THREADS), 0, st, d, (const int32_t*)f.cnt, f.rowptr);
+        HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(trunc_fill_kernel, dim3(gr), dim3(256), 0, st, d, f.Phi, (int64_t)d,
+                           (const SelState*)f.sel, (const int32_t*)f.rowptr, f.colidx, f.val);
+        HIP_TRY(hipGetLastError());
+    }
     // hat H is computed on the nonempty rows and columns only
     hipLaunchKernelGGL(compact_rows_kernel, dim3(1), dim3(256), 0, st, d, (const int32_t*)f.cnt, f.pos, f.rows,
                        f.nrows);
@@ -2824,7 +2828,7 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
             SelState hs;
             int32_t nnz = 0;
             HIP_TRY(hipMemcpyAsync(&hs, f.sel, sizeof(hs), hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipMemcpyAsync(&nnz, f.rowptr + d, sizeof(nnz), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(&nnz, f.nrows + 1, sizeof(nnz), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
             if (eps_host) {
                 float e;
@@ -2861,7 +2865,7 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
         if (nb > d) nb = (ns + 3) / 4 * 4;   // d % 8 == 0, so this fits
         const int gg = (int)std::min<int64_t>(4096, ((int64_t)nb * nb + 255) / 256);
         hipLaunchKernelGGL(gather_compact_kernel, dim3(gg), dim3(256), 0, st, ns, nb, (const int32_t*)f.rows,
-                           (const float*)f.Phi, (int64_t)d, w.G);
+                           (const float*)f.Phi, (int64_t)d, (const SelState*)f.sel, w.G);
         HIP_TRY(hipGetLastError());
         // bound, coefficients and p(Phi_S) on the nb x nb block (pitch nb, in the Gram's buffer);
         // the Gram partials keep their place (they depend on K and maxit only)

@@ -388,17 +388,27 @@ __global__ void __launch_bounds__(256) psi_step_kernel(int d, const int32_t* row
 }
 
 // The nonempty rows of the truncated matrix (cnt[r] > 0), single workgroup of
-// 256: pos[r] = compact index or -1, rows[i] = the i-th nonempty row, *nrows.
+// 256: pos[r] = compact index or -1, rows[i] = the i-th nonempty row,
+// nrows[0] = their number, nrows[1] = the kept entries (sum of cnt).
 __global__ void __launch_bounds__(256) compact_rows_kernel(int d, const int32_t* cnt, int32_t* pos, int32_t* rows,
                                                            int32_t* nrows) {
     __shared__ int32_t part[256];
+    __shared__ int32_t tot[256];
     const int t = threadIdx.x;
     const int per = (d + 255) / 256;
     const int lo = min(d, t * per), hi = min(d, lo + per);
-    int32_t sum = 0;
-    for (int i = lo; i < hi; ++i) sum += cnt[i] > 0 ? 1 : 0;
+    int32_t sum = 0, all = 0;
+    for (int i = lo; i < hi; ++i) {
+        sum += cnt[i] > 0 ? 1 : 0;
+        all += cnt[i];
+    }
     part[t] = sum;
+    tot[t] = all;
     __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) tot[t] += tot[t + off];
+        __syncthreads();
+    }
     for (int off = 1; off < 256; off <<= 1) {
         const int32_t v = t >= off ? part[t - off] : 0;
         __syncthreads();
@@ -415,7 +425,10 @@ __global__ void __launch_bounds__(256) compact_rows_kernel(int d, const int32_t*
             pos[i] = -1;
         }
     }
-    if (t == 255) *nrows = part[255];
+    if (t == 255) {
+        nrows[0] = part[255];
+        nrows[1] = tot[0];
+    }
 }
 
 // Column indices of the CSR to compact ones (every kept column is a nonempty row:
@@ -454,14 +467,21 @@ __global__ void symmetrize_kernel(int d, float* P, int64_t ld) {
     }
 }
 
-// The compact block Phi_S[i][j] = Phi[rows[i]][rows[j]] for i, j < ns, zero up to
-// nb x nb (pitch nb).
+// The compact block of the truncated matrix, Phi_S[i][j] = Phi[rows[i]][rows[j]]
+// where |Phi| >= eps (the selected key) and 0 elsewhere, for i, j < ns, zero up to
+// nb x nb (pitch nb); Phi itself is untruncated.
 __global__ void gather_compact_kernel(int ns, int nb, const int32_t* rows, const float* Phi, int64_t ldp,
-                                      float* out) {
+                                      const SelState* st, float* out) {
+    const uint32_t eps = st->prefix;
     const int64_t total = (int64_t)nb * nb;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
         const int r = (int)(e / nb), c = (int)(e % nb);
-        out[e] = (r < ns && c < ns) ? Phi[(int64_t)rows[r] * ldp + rows[c]] : 0.f;
+        float v = 0.f;
+        if (r < ns && c < ns) {
+            v = Phi[(int64_t)rows[r] * ldp + rows[c]];
+            if (abs_key(v) < eps) v = 0.f;
+        }
+        out[e] = v;
     }
 }
 

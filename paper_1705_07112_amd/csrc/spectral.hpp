@@ -444,8 +444,10 @@ __global__ void __launch_bounds__(kPowerWgThreads) power_wg_kernel(int d, const 
 // ---- k-step Lanczos bound (a second reading of the maximum-eigenvalue step)
 //   q_1 = w_0 / ||w_0||, beta_0 = 0; step j: u = G q_j - beta_{j-1} q_{j-1},
 //   alpha_j = q_j.u, u <- u - alpha_j q_j, beta_j = ||u||, q_{j+1} = u / beta_j
-//   (no reorthogonalisation; an exactly vanishing beta_j ends the run), then the
-//   largest eigenvalue theta of the tridiagonal T_k, its unit eigenvector s, the
+//   (no reorthogonalisation; an exactly vanishing beta_j ends the run, and with
+//   tol > 0 so does the first step j >= 2 whose Ritz value moved by at most
+//   tol theta_j), then the largest eigenvalue theta of the tridiagonal T_k, its
+//   unit eigenvector s, the
 //   Ritz residual ||r|| = beta_k |s_k| and the Ritz vector y = sum_j s_j q_j.  The
 //   power slots receive mu_T = theta and ||w_T||^2 = theta^2 + ||r||^2, so the
 //   finishing kernel's rule gives Lambda = min(theta + max(margin theta, ||r||),
@@ -542,8 +544,8 @@ __device__ inline void lz_ritz(double al, double be, int k, double& theta, doubl
 // partial row sums and adds alpha and ||u||^2 itself (the same operations in every
 // wave, so every wave holds the same alpha_j, beta_j and stopping decision).
 __global__ void __launch_bounds__(kPowerWgThreads) lanczos_wg_kernel(int d, const float* G, int64_t ldg, double* wb0,
-                                                                   double* wb1, double* scal, int steps, int pw_mu,
-                                                                   int pw_w2) {
+                                                                   double* wb1, double* scal, int steps, double tol,
+                                                                   int pw_mu, int pw_w2) {
     __shared__ double rowp[2][4][kPowerWgMaxD];   // partial row sums by column block, by parity
     __shared__ double Q[kLanczosMax][kPowerWgMaxD];
     const int lane = threadIdx.x & 63;
@@ -583,7 +585,9 @@ __global__ void __launch_bounds__(kPowerWgThreads) lanczos_wg_kernel(int d, cons
     double q = col < d ? wb0[col] / sqrt(n0) : 0.0;   // q_j at this lane's column
     double bprev = 0.0;
     double al = 0.0, be = 0.0;   // lane j: alpha_j, beta_j
+    double theta = 0.0, resid = 0.0, s = 0.0, th_prev = 0.0;
     int k = 0, vanish = 0;
+    bool fresh = false;   // theta, resid, s belong to T_k
     for (int j = 0; j < steps; ++j) {
         const int par = j & 1;
         if (rb == 0) Q[j][col] = q;
@@ -623,7 +627,15 @@ __global__ void __launch_bounds__(kPowerWgThreads) lanczos_wg_kernel(int d, cons
             vanish = 1;
             break;
         }
+        fresh = false;
         if (beta == 0.0) break;
+        if (tol > 0.0) {
+            // the Ritz pair of T_{j+1}; kept when the run ends here
+            lz_ritz(al, be, k, theta, resid, s);
+            fresh = true;
+            if (j >= 1 && fabs(theta - th_prev) <= tol * theta) break;
+            th_prev = theta;
+        }
         const double uc = cb == 0 ? u[0] : (cb == 1 ? u[1] : (cb == 2 ? u[2] : u[3]));
         q = uc / beta;
         bprev = beta;
@@ -635,8 +647,8 @@ __global__ void __launch_bounds__(kPowerWgThreads) lanczos_wg_kernel(int d, cons
         }
         return;
     }
-    double theta, resid, s;
-    lz_ritz(al, be, k, theta, resid, s);
+    // the Ritz pair of T_k unless the last step formed it
+    if (!fresh) lz_ritz(al, be, k, theta, resid, s);
     // the Ritz vector into the buffer the finishing kernel reads the last vector
     // from (slot T - 1 holds its squared length: s is a unit vector)
     double* yb = ((k - 1) & 1) ? wb1 : wb0;

@@ -30,22 +30,29 @@ def _gram(X):
 
 @pytest.mark.parametrize("shape", [(64, 48), (200, 120), (90, 300), (400, 256), (256, 4), (130, 70), (7, 1)])
 @pytest.mark.parametrize("steps", [1, 5, 12, 32])
-def test_dense_bound_matches_oracle(shape, steps):
+@pytest.mark.parametrize("tol", [0.0, 1e-7])
+def test_dense_bound_matches_oracle(shape, steps, tol):
+    """tol = 0: all the steps; tol = 1e-7 (the default): the early stop, whose step
+    may differ by one where a Ritz value moves by about tol (the device forms the
+    Ritz values to about 1e-9)."""
     import torch
     import paper_1705_07112_amd as cpa
     m, n = shape
-    print(f"case lanczos bound {m}x{n} steps={steps}", flush=True)
+    print(f"case lanczos bound {m}x{n} steps={steps} tol={tol}", flush=True)
     X = synth.as_f32_exact(synth.dense_lowrank(m, n, rank=min(5, m, n), noise=0.3, seed=7100 + m + n))
     G = _gram(X)
-    Lo, th_o, r_o, k_o, *_ = obound.lanczos_bound(G, seed=0, steps=steps)
+    Lo, th_o, r_o, k_o, *_ = obound.lanczos_bound(G, seed=0, steps=steps, tol=tol)
     Xd = torch.from_numpy(X.astype(np.float32)).cuda()
-    lam_g, info = cpa.spectral_bound(Xd, cpa.Opts(K=4, bound="lanczos", lanczos_steps=steps))
+    lam_g, info = cpa.spectral_bound(Xd, cpa.Opts(K=4, bound="lanczos", lanczos_steps=steps, power_tol=tol))
     print(f"  gpu {lam_g:.12g} oracle {Lo:.12g} theta {info['mu']:.12g}/{th_o:.12g} "
           f"resid {info['resid']:.4g}/{r_o:.4g} steps {info['power_iters_done']}/{k_o}", flush=True)
-    assert info["power_iters_done"] == k_o
+    if tol == 0.0:
+        assert info["power_iters_done"] == k_o
+    else:
+        assert abs(info["power_iters_done"] - k_o) <= 1
     assert abs(lam_g - Lo) <= LAM_TOL * Lo
     assert abs(info["mu"] - th_o) <= LAM_TOL * th_o
-    if r_o > 1e-3 * th_o:
+    if r_o > 1e-3 * th_o and info["power_iters_done"] == k_o:
         assert abs(info["resid"] - r_o) <= 1e-4 * r_o
     if steps >= 12:
         assert lam_g >= float(np.linalg.eigvalsh(G)[-1]) * (1 - 1e-6)
@@ -60,7 +67,7 @@ def test_dense_shrink_at_the_lanczos_bound(ev, shape, K):
     print(f"case lanczos shrink {m}x{n} K={K} {ev}", flush=True)
     X = synth.as_f32_exact(synth.dense_lowrank(m, n, rank=4, noise=0.2, seed=7200 + m))
     G = _gram(X)
-    Lo = obound.lanczos_bound(G, seed=0, steps=12)[0]
+    Lo = obound.lanczos_bound(G, seed=0, steps=12, tol=1e-7)[0]
     tau = 0.3 * math.sqrt(Lo)
     Y, info = cpa.shrink_dense(torch.from_numpy(X.astype(np.float32)).cuda(), cpa.soft(tau),
                                cpa.Opts(K=K, bound="lanczos", eval=ev), info=True)
@@ -78,7 +85,7 @@ def test_warm_start_from_the_ritz_vector():
     import paper_1705_07112_amd as cpa
     X = synth.as_f32_exact(synth.dense_lowrank(150, 96, rank=4, noise=0.3, seed=7300))
     G = _gram(X)
-    Lo, th, r, k, y = obound.lanczos_bound(G, seed=0, steps=12)[:5]
+    Lo, th, r, k, y = obound.lanczos_bound(G, seed=0, steps=12, tol=1e-7)[:5]
     L1 = obound.lanczos_bound(G, steps=1, v0=y)
     Xd = torch.from_numpy(X.astype(np.float32)).cuda()
     cpa.spectral_bound(Xd, cpa.Opts(K=4, bound="lanczos", lanczos_steps=12))
@@ -109,7 +116,7 @@ def test_sparsified_compact_block():
     assert nb <= 256
     P = np.zeros((nb, nb))
     P[:ns, :ns] = Phil[np.ix_(rows, rows)]
-    Lo = obound.lanczos_bound(P, seed=0, steps=12)[0]
+    Lo = obound.lanczos_bound(P, seed=0, steps=12, tol=1e-7)[0]
     tau = 0.2 * math.sqrt(Lo)
     print(f"case sparsified lanczos: block {ns} -> {nb}", flush=True)
     Y, info = cpa.shrink_dense_sparsified(torch.from_numpy(X.astype(np.float32)).cuda(), cpa.soft(tau),
@@ -151,7 +158,7 @@ def test_batched_lanczos_bound(precision):
     lam = lam_out.cpu().numpy()
     tol = TOL32 if precision == "fp32" else 1e-3
     for i, X in enumerate(mats):
-        Lo = obound.lanczos_bound(_gram(X), seed=0, steps=12)[0]
+        Lo = obound.lanczos_bound(_gram(X), seed=0, steps=12, tol=1e-7)[0]
         assert abs(lam[i] - Lo) <= LAM_TOL * Lo, (i, lam[i], Lo)
         ref = ocpa.cpa_shrink(X, Shrinkage(0, taus[i]), float(lam[i]), 16)
         Yi = Yh[offs[i]:offs[i] + X.size].reshape(X.shape).astype(np.float64)

@@ -100,3 +100,22 @@ def test_degenerate_inputs():
     # the 1 x 1 matrix: theta is its entry after one step, the residual zero
     Lam, theta, r, m, *_ = bound.lanczos_bound(np.array([[3.0]]), steps=5, delta=0.0)
     assert m == 1 and theta == 3.0 and r == 0.0
+
+
+def test_early_stop_matches_a_fixed_run():
+    """With tol > 0 the run stops at the first step j >= 2 whose Ritz value moved
+    by at most tol theta_j: a fixed run of that many steps gives the same bound,
+    the Ritz values of the fixed runs of j - 1 and j steps meet the test, and
+    those of every earlier pair of consecutive steps do not."""
+    g = np.random.default_rng(21)
+    A = g.standard_normal((80, 50)) @ np.diag(np.linspace(2.0, 0.2, 50))
+    G = A.T @ A
+    tol = 1e-7
+    L, th, r, m, *_ = bound.lanczos_bound(G, seed=1, steps=32, tol=tol)
+    assert 2 <= m < 32
+    Lf, thf, rf, mf, *_ = bound.lanczos_bound(G, seed=1, steps=m)
+    assert mf == m and Lf == L and thf == th and rf == r
+    ths = [bound.lanczos_bound(G, seed=1, steps=j)[1] for j in range(1, m + 1)]
+    assert abs(ths[-1] - ths[-2]) <= tol * ths[-1]
+    for j in range(1, m - 1):
+        assert abs(ths[j] - ths[j - 1]) > tol * ths[j]
