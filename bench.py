@@ -253,7 +253,14 @@ def bench_batched(cpa, torch, np, synth, timed_runs: int = 10):
     ms_32, tun_32, Yh, lam = run_plan("fp32")
     ms_split_p, tun_split_p, Ysh_p, lam_sp_p = run_plan("bf16x3", "power")
     ms_32_p, tun_32_p, _, _ = run_plan("fp32", "power")
-    lam_diff = float(torch.max(torch.abs(lam_sp - lam_sp_p) / lam_sp_p).item())
+    rel = torch.abs(lam_sp - lam_sp_p) / lam_sp_p
+    lam_diff = float(torch.max(rel).item())
+    # the matrix where the two bounds differ most, against its largest eigenvalue (LAPACK)
+    iw = int(torch.argmax(rel).item())
+    Xw = flat[offs[iw]:offs[iw] + ms[iw] * ns[iw]].reshape(ms[iw], ns[iw]).astype(np.float64)
+    lmax_w = float(np.linalg.eigvalsh(Xw.T @ Xw if ms[iw] >= ns[iw] else Xw @ Xw.T)[-1])
+    lam_worst = {"matrix": iw, "lanczos_over_lambda_max": round(float(lam_sp[iw].item()) / lmax_w, 6),
+                 "power_over_lambda_max": round(float(lam_sp_p[iw].item()) / lmax_w, 6)}
     d = np.minimum(ms, ns).astype(np.float64)
     e = np.maximum(ms, ns).astype(np.float64)
     flop = float(np.sum(16 * 2.0 * d * d * e))
@@ -306,6 +313,7 @@ def bench_batched(cpa, torch, np, synth, timed_runs: int = 10):
         "err_vs_fp64_svt_median": float("%.3e" % float(np.median(e_svt_split))),
         "err_vs_fp64_svt_max": float("%.3e" % max(e_svt_split)),
         "bound_rel_diff_lanczos_vs_power_max": float("%.3e" % lam_diff),
+        "bound_worst_matrix": lam_worst,
         "power_bound": {"value": round(8192 / (ms_split_p / 1e3), 1), "unit": "matrices/s",
                         "ms_per_batch": round(ms_split_p, 4), "autotuner": tun_rec(tun_split_p),
                         "note": "the same split plan with the power-iteration bound (power_tol 1e-7, at most 100 "
@@ -449,16 +457,21 @@ def bench_sparsified(cpa, torch, np, synth, reps: int = 10):
     Yd = torch.empty_like(X)
     ms_dense = timed(lambda: cpa.shrink_dense(X, cpa.soft(tau), opts, out=Yd))
     ms_dense_w = timed(lambda: cpa.shrink_dense(X, cpa.soft(tau), warm, out=Yd))
+    ms_dense_l = timed(lambda: cpa.shrink_dense(X, cpa.soft(tau), cpa.Opts(K=K, bound="lanczos"), out=Yd))
+    ms_dense_lw = timed(lambda: cpa.shrink_dense(X, cpa.soft(tau), cpa.Opts(K=K, bound="lanczos", warm_start=True),
+                                                 out=Yd))
     dense_err = rel_fro(Yd.cpu().numpy().astype(np.float64), ex, ex)
     out = {"workload": "1024 x 1024 block-smooth (rank 4, 8-blocks) + N(0,1e-3^2), block DCT 8x8, K=30, soft "
                        "tau = 0.2 sigma_1, power bound",
            "dense_polynomial_route": {"ms_per_shrink": round(ms_dense, 4), "ms_per_shrink_warm": round(ms_dense_w, 4),
+                                      "lanczos_ms_per_shrink": round(ms_dense_l, 4),
+                                      "lanczos_ms_per_shrink_warm": round(ms_dense_lw, 4),
                                       "err_vs_fp64_svt": float("%.3e" % dense_err)},
            "keep": [],
            "note": "cold: every call starts its power iteration from the seeded vector; warm: from the previous "
-                   "call's vector (as inside an ADMM run), on both routes.  lanczos_bound: the sparsified shrink "
-                   "with the 12-step Lanczos bound on its compact block (the dense route keeps the power bound: "
-                   "its 1024-wide Gram is past the one-workgroup Lanczos kernel's 256)"}
+                   "call's vector (as inside an ADMM run), on both routes.  lanczos_bound: both routes with the "
+                   "Lanczos bound (at most 12 steps, early stop at power_tol), speedups against the dense route "
+                   "with the same bound (and, beside it, with the power bound)"}
     Ys = torch.empty_like(X)
     opts_rec = cpa.Opts(K=K, eval="recurrence")
     opts_lz = cpa.Opts(K=K, bound="lanczos")
@@ -474,8 +487,9 @@ def bench_sparsified(cpa, torch, np, synth, reps: int = 10):
             ms_l = timed(lambda: cpa.shrink_dense_sparsified(X, cpa.soft(tau), opts_lz, keep=keep, out=Ys))
             ms_lw = timed(lambda: cpa.shrink_dense_sparsified(X, cpa.soft(tau), warm_lz, keep=keep, out=Ys))
             _, il = cpa.shrink_dense_sparsified(X, cpa.soft(tau), opts_lz, keep=keep, out=Ys, info=True)
-            lz = {"ms_per_shrink": round(ms_l, 4), "speedup_vs_dense": round(ms_dense / ms_l, 3),
-                  "ms_per_shrink_warm": round(ms_lw, 4), "speedup_vs_dense_warm": round(ms_dense_w / ms_lw, 3),
+            lz = {"ms_per_shrink": round(ms_l, 4), "speedup_vs_dense": round(ms_dense_l / ms_l, 3),
+                  "ms_per_shrink_warm": round(ms_lw, 4), "speedup_vs_dense_warm": round(ms_dense_lw / ms_lw, 3),
+                  "speedup_vs_dense_power_bound": round(ms_dense / ms_l, 3),
                   "Lambda": il["Lambda"], "steps": il["power_iters_done"]}
         except cpa.CpaError as e:
             lz = {"unsupported": str(e)}
@@ -504,6 +518,11 @@ def bench_sparsified(cpa, torch, np, synth, reps: int = 10):
     ms2_dw = timed(lambda: cpa.shrink_dense(X2, cpa.soft(tau2), warm, out=Y2d))
     ms2_s = timed(lambda: cpa.shrink_dense_sparsified(X2, cpa.soft(tau2), opts, keep=keep2, out=Y2s))
     ms2_sw = timed(lambda: cpa.shrink_dense_sparsified(X2, cpa.soft(tau2), warm, keep=keep2, out=Y2s))
+    olz, wlz = cpa.Opts(K=K, bound="lanczos"), cpa.Opts(K=K, bound="lanczos", warm_start=True)
+    ms2_dl = timed(lambda: cpa.shrink_dense(X2, cpa.soft(tau2), olz, out=Y2d))
+    ms2_sl = timed(lambda: cpa.shrink_dense_sparsified(X2, cpa.soft(tau2), olz, keep=keep2, out=Y2s))
+    ms2_dlw = timed(lambda: cpa.shrink_dense(X2, cpa.soft(tau2), wlz, out=Y2d))
+    ms2_slw = timed(lambda: cpa.shrink_dense_sparsified(X2, cpa.soft(tau2), wlz, keep=keep2, out=Y2s))
     Yd2 = Y2d.cpu().numpy().astype(np.float64)
     out["paper_shape"] = {
         "workload": "2560 x 1920 block-smooth (rank 4, 8-blocks) + N(0,1e-3^2), block DCT 8x8, K=30, soft "
@@ -511,6 +530,11 @@ def bench_sparsified(cpa, torch, np, synth, reps: int = 10):
         "dense_ms_per_shrink": round(ms2_d, 4), "dense_ms_per_shrink_warm": round(ms2_dw, 4),
         "sparsified_ms_per_shrink": round(ms2_s, 4), "sparsified_ms_per_shrink_warm": round(ms2_sw, 4),
         "speedup_vs_dense": round(ms2_d / ms2_s, 3), "speedup_vs_dense_warm": round(ms2_dw / ms2_sw, 3),
+        "lanczos_bound": {"dense_ms_per_shrink": round(ms2_dl, 4), "sparsified_ms_per_shrink": round(ms2_sl, 4),
+                          "speedup_vs_dense": round(ms2_dl / ms2_sl, 3),
+                          "dense_ms_per_shrink_warm": round(ms2_dlw, 4),
+                          "sparsified_ms_per_shrink_warm": round(ms2_slw, 4),
+                          "speedup_vs_dense_warm": round(ms2_dlw / ms2_slw, 3)},
         "err_vs_dense_route": float("%.3e" % rel_fro(Y2s.cpu().numpy().astype(np.float64), Yd2, Yd2))}
     return out
 

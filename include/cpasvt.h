@@ -101,10 +101,10 @@ typedef struct {
  *                        Lambda = min(theta + max(margin * theta, ||r||), (1 + margin) ||Gram||_F).
  *                        The Ritz vector sum_j s_j q_j is the next warm start; info.mu and
  *                        info.resid report theta and ||r||, power_iters_done the steps.
- *                        Gram sides up to 256 on the dense FP32 entry points (cpa_shrink_dense,
- *                        _noalloc, cpa_spectral_bound, the sparsified shrink's compact block)
- *                        and every matrix of the batched path (d <= 64); CPA_ERR_UNSUPPORTED
- *                        on larger sides and on the CSR, FP64 and driver entry points */
+ *                        Gram sides up to 4096 on the dense FP32 entry points (cpa_shrink_dense,
+ *                        _noalloc, cpa_spectral_bound, cpa_shrink_dense_sparsified) and every
+ *                        matrix of the batched path (d <= 64); CPA_ERR_UNSUPPORTED on larger
+ *                        sides and on the CSR, FP64 and driver entry points */
 typedef enum {
     CPA_BOUND_POWER = 0,
     CPA_BOUND_GIVEN = 1,

@@ -162,6 +162,7 @@ struct Work {
     float* xt = nullptr;   // room for X^T (padded) while the Gram is formed: the polynomial buffers on
                            // that route, else the first Y buffer of the recurrence (free until then)
     int64_t xt_cap = 0;    // its capacity in floats (0: none)
+    int64_t yb_cap = 0;    // floats in each Y buffer (0: none)
     bool right;       // Gram = X^T X (n x n) and products on the right; else X X^T (m x m), on the left
     int d;            // side of the Gram
     ScalarLayout lay;
@@ -274,6 +275,7 @@ void bind_ws(Work& w, char* b, const WsPlan& p, bool admm, int poly_s, bool need
     w.et_counter = admm ? reinterpret_cast<int*>(b + p.oa + sizeof(double) * 2 * kAdmmGrid) : nullptr;
     w.poly = poly_s > 0 ? reinterpret_cast<float*>(b + p.opl) : nullptr;
     w.poly_s = poly_s;
+    w.yb_cap = need_y ? (int64_t)(p.oY1 - p.oY0) / (int64_t)sizeof(float) : 0;
     if (poly_s > 0) {
         w.xt = w.poly;
         w.xt_cap = (int64_t)poly_mats(w.lay.K, poly_s) * w.d * w.d;
@@ -653,13 +655,30 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
             void* args[] = {&d_, &G64, &ldg, &wb0, &wb1, &part, &counter, &scal, &maxit_, &tol, &pw_mu, &pw_w2};
             ls = launch_power(ctx, reinterpret_cast<const void*>(power_coop_kernel<double>), w.lay.pwg, args, st);
         } else if (o->bound == CPA_BOUND_LANCZOS) {
-            if (d > kPowerWgMaxD)
-                return fail(CPA_ERR_UNSUPPORTED, "the Lanczos bound takes Gram sides up to %d (got %d)", kPowerWgMaxD, d);
-            const int steps = std::min(lanczos_steps(o), d);
-            hipLaunchKernelGGL(lanczos_wg_kernel, dim3(1), dim3(kPowerWgThreads), 0, st, d, G, ldg, wb0, wb1, scal,
-                               steps, o->power_tol, pw_mu, pw_w2);
-            HIP_TRY(hipGetLastError());
-            ls = CPA_OK;
+            int steps = std::min(lanczos_steps(o), d);
+            if (d <= kPowerWgMaxD) {
+                hipLaunchKernelGGL(lanczos_wg_kernel, dim3(1), dim3(kPowerWgThreads), 0, st, d, G, ldg, wb0, wb1, scal,
+                                   steps, o->power_tol, pw_mu, pw_w2);
+                HIP_TRY(hipGetLastError());
+                ls = CPA_OK;
+            } else {
+                // the Lanczos vectors (and the shared u by parity) in a buffer that is
+                // idle while the bound runs: the second recurrence buffer, or the
+                // matrix-polynomial region (read again only after the bound)
+                if (d > kPowerVecLds)
+                    return fail(CPA_ERR_UNSUPPORTED, "the Lanczos bound takes Gram sides up to %d (got %d)",
+                                kPowerVecLds, d);
+                const size_t need = sizeof(double) * (size_t)(steps + 2) * d;
+                double* Q = nullptr;
+                if (w.Yb[1] && need <= sizeof(float) * (size_t)w.yb_cap)
+                    Q = reinterpret_cast<double*>(w.Yb[1]);
+                else if (w.poly && need <= sizeof(float) * (size_t)poly_mats(w.lay.K, w.poly_s) * w.d * w.d)
+                    Q = reinterpret_cast<double*>(w.poly);
+                if (!Q) return fail(CPA_ERR_UNSUPPORTED, "no room for the Lanczos vectors in this workspace");
+                double tol = o->power_tol;
+                void* args[] = {&d_, &G, &ldg, &wb0, &wb1, &Q, &part, &counter, &scal, &steps, &tol, &pw_mu, &pw_w2};
+                ls = launch_power(ctx, reinterpret_cast<const void*>(lanczos_coop_kernel), w.lay.pwg, args, st);
+            }
         } else if (d <= kPowerWgMaxD) {
             // small sides: one workgroup with G in registers, no grid barrier
             hipLaunchKernelGGL(power_wg_kernel, dim3(1), dim3(kPowerWgThreads), 0, st, d, G, ldg, wb0, wb1, scal,

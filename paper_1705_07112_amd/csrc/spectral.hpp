@@ -666,6 +666,149 @@ __global__ void __launch_bounds__(kPowerWgThreads) lanczos_wg_kernel(int d, cons
     }
 }
 
+// k-step Lanczos for Gram sides kPowerWgMaxD < d <= kPowerVecLds, in the power
+// iteration's resident grid with one grid barrier per step:
+//   before it, each workgroup's waves take rows of G q_j (q_j and q_{j-1} in
+//   LDS), form u_i = (G q_j)_i - beta_{j-1} q_{j-1,i}, store u_i and q_{j,i}
+//   (U and Q, agent scope) and add q_{j,i} u_i into the workgroup's partial;
+//   after it, every workgroup adds the partials in a fixed order (alpha_j), loads
+//   all of u, forms u - alpha_j q_j and ||.||^2 over the d entries itself (same
+//   operations in every workgroup) and keeps q_{j+1} = u / beta_j in LDS.
+// Every workgroup holds the same alpha, beta and stopping decision, and forms the
+// same Ritz pair; the Ritz vector's entry i is formed by the thread that stored
+// Q[.][i].  Q holds steps + 2 vectors of d: the Lanczos vectors, then U by step
+// parity (a workgroup that runs ahead writes the other one while the rest still
+// read theirs; the same parity rule as the partial sums).
+__global__ void __launch_bounds__(kPowerThreads) lanczos_coop_kernel(int d, const float* G, int64_t ldg, double* wb0,
+                                                                     double* wb1, double* Q, double* part,
+                                                                     unsigned* counter, double* scal, int steps,
+                                                                     double tol, int pw_mu, int pw_w2) {
+    __shared__ double red[kPowerThreads / 64];
+    __shared__ __attribute__((aligned(16))) double va[kPowerVecLds];
+    __shared__ __attribute__((aligned(16))) double vb[kPowerVecLds];
+    const int P = gridDim.x;
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * (kPowerThreads / 64) + (threadIdx.x >> 6);
+    const int nw = P * (kPowerThreads / 64);
+    const double n0 = scal[pw_w2 + 0];
+    if (!(n0 > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            scal[SC_STOP] = 0;
+            scal[SC_VANISH] = 1;
+        }
+        return;
+    }
+    const double inv0 = 1.0 / sqrt(n0);
+    for (int i = threadIdx.x; i < d; i += kPowerThreads) {
+        va[i] = wb0[i] * inv0;   // q_1
+        vb[i] = 0.0;             // q_0
+    }
+    __syncthreads();
+    double* vq = va;   // q_j
+    double* vp = vb;   // q_{j-1}, then u
+    const bool vec = ((ldg & 3) == 0) && ((reinterpret_cast<uintptr_t>(G) & 15) == 0);
+    double bprev = 0.0;
+    double al = 0.0, be = 0.0, theta = 0.0, resid = 0.0, s = 0.0, th_prev = 0.0;
+    int k = 0, vanish = 0;
+    bool fresh = false;
+    for (int j = 0; j < steps; ++j) {
+        double* U = Q + (int64_t)(steps + (j & 1)) * d;
+        double apart = 0.0;
+        for (int i = gw; i < d; i += nw) {
+            const float* row = G + (int64_t)i * ldg;
+            double a[4] = {0.0, 0.0, 0.0, 0.0};
+            int c = 4 * lane;
+            if (vec) {
+#pragma unroll 4
+                for (; c + 3 < d; c += 256) {
+                    const f32x4 g = *reinterpret_cast<const f32x4*>(row + c);
+                    const double2 v01 = *reinterpret_cast<const double2*>(vq + c);
+                    const double2 v23 = *reinterpret_cast<const double2*>(vq + c + 2);
+                    a[0] += (double)g[0] * v01.x;
+                    a[1] += (double)g[1] * v01.y;
+                    a[2] += (double)g[2] * v23.x;
+                    a[3] += (double)g[3] * v23.y;
+                }
+            }
+            for (; c < d; c += 256)
+                for (int e = 0; e < 4; ++e)
+                    if (c + e < d) a[e] += (double)row[c + e] * vq[c + e];
+            double acc = (a[0] + a[1]) + (a[2] + a[3]);
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if (lane == 0) {
+                const double ui = acc - bprev * vp[i];
+                st_agent(U + i, ui);
+                st_agent(Q + (int64_t)j * d + i, vq[i]);
+                apart += vq[i] * ui;
+            }
+        }
+        apart = block_sum(apart, red);
+        double* pt = part + (j & 1) * 2 * P;
+        if (threadIdx.x == 0) st_agent(pt + blockIdx.x, apart);
+        if (!grid_barrier_coherent(counter, (unsigned)(j + 1) * P, scal)) return;
+        double sa = 0.0;
+        for (int p = threadIdx.x; p < P; p += kPowerThreads) sa += ld_agent(pt + p);
+        const double alpha = block_sum(sa, red);
+        // u - alpha q_j over all d entries, into vp (q_{j-1} is no longer needed)
+        double b2 = 0.0;
+        for (int i = threadIdx.x; i < d; i += kPowerThreads) {
+            const double ui = ld_agent(U + i) - alpha * vq[i];
+            vp[i] = ui;
+            b2 += ui * ui;
+        }
+        const double beta = sqrt(block_sum(b2, red));
+        if (lane == j) {
+            al = alpha;
+            be = beta;
+        }
+        k = j + 1;
+        if (j == 0 && alpha == 0.0 && beta == 0.0) {
+            vanish = 1;
+            break;
+        }
+        fresh = false;
+        if (beta == 0.0) break;
+        if (tol > 0.0) {
+            lz_ritz(al, be, k, theta, resid, s);
+            fresh = true;
+            if (j >= 1 && fabs(theta - th_prev) <= tol * theta) break;
+            th_prev = theta;
+        }
+        // q_{j+1} = u / beta; the roles of the two LDS vectors swap
+        const double ib = 1.0 / beta;
+        for (int i = threadIdx.x; i < d; i += kPowerThreads) vp[i] *= ib;
+        __syncthreads();
+        double* t = vq;
+        vq = vp;
+        vp = t;
+        bprev = beta;
+    }
+    if (vanish) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            scal[SC_STOP] = 0;
+            scal[SC_VANISH] = 1;
+        }
+        return;
+    }
+    if (!fresh) lz_ritz(al, be, k, theta, resid, s);
+    // the Ritz vector: entry i from the stores of the thread that owns row i
+    double* yb = ((k - 1) & 1) ? wb1 : wb0;
+    if (lane == 0) {
+        for (int i = gw; i < d; i += nw) {
+            double y = 0.0;
+            for (int q = 0; q < k; ++q) y += pw_readlane(s, q) * Q[(int64_t)q * d + i];
+            yb[i] = y;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        scal[pw_mu + k] = theta;
+        scal[pw_w2 + k] = theta * theta + resid * resid;
+        scal[pw_w2 + k - 1] = 1.0;
+        scal[SC_STOP] = k;
+        scal[SC_VANISH] = 0;
+    }
+}
+
 constexpr int kCoefLds = 1024;   // orders up to this use the cosine-table coefficient path
 
 // Bound rule + coefficients + recurrence scalars.  Single workgroup.

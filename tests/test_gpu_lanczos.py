@@ -1,6 +1,7 @@
 """GPU parity of the k-step Lanczos bound (CPA_BOUND_LANCZOS) with the oracle's
-lanczos_bound: the dense entry points (one-workgroup kernel, Gram sides up to
-256), the sparsified shrink's compact block and the batched path, plus the
+lanczos_bound: the dense entry points (one-workgroup kernel for Gram sides up to
+256, the multi-workgroup kernel above), the sparsified shrink's compact block and
+the batched path, plus the
 shrink evaluated at the device's bound, the warm start from the Ritz vector and
 the refusals.  The oracle runs in FP64 on the Gram of the FP32 input; the device
 Gram is FP32 (MFMA), so bounds agree to about 1e-7 relative."""
@@ -28,7 +29,8 @@ def _gram(X):
     return X.T @ X if X.shape[0] >= X.shape[1] else X @ X.T
 
 
-@pytest.mark.parametrize("shape", [(64, 48), (200, 120), (90, 300), (400, 256), (256, 4), (130, 70), (7, 1)])
+@pytest.mark.parametrize("shape", [(64, 48), (200, 120), (90, 300), (400, 256), (256, 4), (130, 70), (7, 1),
+                                   (400, 300), (300, 700), (1100, 1024), (2100, 2050)])
 @pytest.mark.parametrize("steps", [1, 5, 12, 32])
 @pytest.mark.parametrize("tol", [0.0, 1e-7])
 def test_dense_bound_matches_oracle(shape, steps, tol):
@@ -59,7 +61,8 @@ def test_dense_bound_matches_oracle(shape, steps, tol):
 
 
 @pytest.mark.parametrize("ev", ["recurrence", "polynomial"])
-@pytest.mark.parametrize("shape,K", [((130, 70), 30), ((70, 130), 20), ((300, 256), 30), ((64, 64), 16)])
+@pytest.mark.parametrize("shape,K", [((130, 70), 30), ((70, 130), 20), ((300, 256), 30), ((64, 64), 16),
+                                     ((600, 300), 30), ((1100, 1024), 30)])
 def test_dense_shrink_at_the_lanczos_bound(ev, shape, K):
     import torch
     import paper_1705_07112_amd as cpa
@@ -165,13 +168,41 @@ def test_batched_lanczos_bound(precision):
         assert metrics.rel_fro(Yi, ref, X) <= tol, i
 
 
+def test_sparsified_wide_compact_block():
+    """A compact block wider than 256 (about 3% kept of a 1024 x 1024 transformed
+    Gram) takes the multi-workgroup kernel.  Past the block-DC entries |Phi| has no
+    2% gap, so the keep count sits at a 0.05% gap; entries that FP32 and FP64 might
+    still order differently are some 1e-6 of lambda_max and leave the bound alone."""
+    import torch
+    import paper_1705_07112_amd as cpa
+    X = synth.as_f32_exact(synth.block_smooth(1024, 1024, rank=4, noise=1e-3, seed=7450))
+    T = sparsify.block_dct(1024, 8)
+    Phi, _ = sparsify.transformed_gram(X, T)
+    a = np.sort(np.abs(Phi).ravel())[::-1]
+    cand = np.nonzero(a[:-1] / np.maximum(a[1:], 1e-300) > 1.0005)[0]
+    keep = int(cand[np.argmin(np.abs(cand + 1 - int(0.03 * a.size)))] + 1)
+    Phil = sparsify.truncate(Phi, sparsify.kth_largest_abs(Phi, keep))
+    rows = np.nonzero(np.any(Phil != 0.0, axis=1))[0]
+    ns = rows.size
+    nb = (ns + 63) // 64 * 64
+    print(f"case sparsified lanczos wide block: {ns} -> {nb}", flush=True)
+    assert nb > 256
+    P = np.zeros((nb, nb))
+    P[:ns, :ns] = Phil[np.ix_(rows, rows)]
+    Lo = obound.lanczos_bound(P, seed=0, steps=12, tol=1e-7)[0]
+    _, info = cpa.shrink_dense_sparsified(torch.from_numpy(X.astype(np.float32)).cuda(), cpa.soft(1.0),
+                                          cpa.Opts(K=20, bound="lanczos"), keep=keep, info=True)
+    print(f"  gpu {info['Lambda']:.10g} oracle {Lo:.10g}", flush=True)
+    assert abs(info["Lambda"] - Lo) <= 1e-5 * Lo
+
+
 def test_lanczos_refusals():
     import torch
     import paper_1705_07112_amd as cpa
     print("case lanczos refusals", flush=True)
     X = torch.randn(400, 300, device="cuda")
-    with pytest.raises(cpa.CpaError) as e:          # Gram side above 256
-        cpa.shrink_dense(X, cpa.soft(1.0), cpa.Opts(K=8, bound="lanczos"))
+    with pytest.raises(cpa.CpaError) as e:          # Gram side above 4096
+        cpa.spectral_bound(torch.randn(4200, 4100, device="cuda"), cpa.Opts(K=8, bound="lanczos"))
     assert e.value.status == cpa.ERR_UNSUPPORTED
     with pytest.raises(cpa.CpaError) as e:          # the FP64 path keeps the power rule
         cpa.shrink_dense(X[:64, :32].double(), cpa.soft(1.0), cpa.Opts(K=8, bound="lanczos"))
