@@ -2775,20 +2775,20 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
         hipLaunchKernelGGL(symmetrize_kernel, dim3(gd), dim3(256), 0, st, d, f.Phi, (int64_t)d);
         HIP_TRY(hipGetLastError());
     } else {
-        hipLaunchKernelGGL(bt_forward_kernel, dim3(nt * (nt + 1) / 2), dim3(64), 0, st, d, (const float*)w.G,
+        hipLaunchKernelGGL(bt_forward_kernel, dim3((nt * (nt + 1) / 2 + 3) / 4), dim3(256), 0, st, d, (const float*)w.G,
                            (int64_t)d, f.Phi, (int64_t)d, D, sp->transform == CPA_TRANSFORM_HAAR1_LOWPASS ? 1 : 0);
         HIP_TRY(hipGetLastError());
     }
     // M = T^T hat H T from the compact hat H (pitch ldh; hat h(0) on the empty diagonal)
     auto inverse = [&](const float* Hc, int64_t ldh) -> cpa_status {
         if (!dense_t) {
-            hipLaunchKernelGGL(bt_inverse_kernel, dim3(nt * nt), dim3(64), 0, st, d, Hc, ldh, f.M, (int64_t)d, D,
+            hipLaunchKernelGGL(bt_inverse_kernel, dim3((nt * nt + 3) / 4), dim3(256), 0, st, d, Hc, ldh, f.M, (int64_t)d, D,
                                (const int32_t*)f.pos, (const double*)w.scal, opts->K);
             HIP_TRY(hipGetLastError());
             return CPA_OK;
         }
         // expand to the full hat H (identity table), then C = hat H D, M = D^T C
-        hipLaunchKernelGGL(bt_inverse_kernel, dim3(nt * nt), dim3(64), 0, st, d, Hc, ldh, f.P[0], (int64_t)d,
+        hipLaunchKernelGGL(bt_inverse_kernel, dim3((nt * nt + 3) / 4), dim3(256), 0, st, d, Hc, ldh, f.P[0], (int64_t)d,
                            transform_table(CPA_TRANSFORM_IDENTITY), (const int32_t*)f.pos, (const double*)w.scal,
                            opts->K);
         HIP_TRY(hipGetLastError());

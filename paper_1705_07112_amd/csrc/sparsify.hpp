@@ -10,7 +10,7 @@
 //   M = T^T hat H T, then hat G = X M (or M X).
 //
 // Kernels:
-//   bt_forward_kernel   one workgroup per pair of 8 x 8 tiles (I <= J):
+//   bt_forward_kernel   one wave per pair of 8 x 8 tiles (I <= J), four to a workgroup:
 //                       P = D G_IJ D^T in FP64 from the FP32 Gram, written to tile
 //                       (I, J) and transposed to (J, I); diagonal tiles are
 //                       symmetrised ((P + P^T)/2).  Phi is therefore exactly
@@ -35,7 +35,7 @@
 //   psi_step_kernel     one recurrence step on the CSR matrix: a workgroup per row
 //                       and 128-column panel, the row's entries spread over its
 //                       8 lane groups (the kept rows are very uneven).
-//   bt_inverse_kernel   M_IJ = D^T H_IJ D for every tile, FP64 inside; expands the
+//   bt_inverse_kernel   M_IJ = D^T H_IJ D for every tile (one wave each), FP64 inside; expands the
 //                       compact hat H (hat h(0) on the empty diagonal entries).
 #pragma once
 
@@ -67,37 +67,43 @@ __device__ inline uint32_t abs_key(float x) { return __float_as_uint(x) & 0x7fff
 
 // zero_high: rows 4..7 of the table are high-frequency components (the Haar
 // table); every entry of Phi in such a row or column is set to zero.
-__global__ void __launch_bounds__(64) bt_forward_kernel(int d, const float* G, int64_t ldg, float* Phi, int64_t ldp,
-                                                        Dct8 D, int zero_high) {
-    __shared__ double g[8][9];
-    __shared__ double t[8][9];
+// Wave w of the workgroup takes tile pair 4 blockIdx.x + w (waves past the last
+// pair only join the barriers).
+__global__ void __launch_bounds__(256) bt_forward_kernel(int d, const float* G, int64_t ldg, float* Phi, int64_t ldp,
+                                                         Dct8 D, int zero_high) {
+    __shared__ double g[4][8][9];
+    __shared__ double t[4][8][9];
+    const int wv = threadIdx.x >> 6;
     // tile pair index -> (I, J), I <= J, row-major over the upper triangle
     const int nt = d / 8;
-    int p = blockIdx.x, I = 0;
+    const int npair = nt * (nt + 1) / 2;
+    const int pair = blockIdx.x * 4 + wv;
+    const bool valid = pair < npair;
+    int p = valid ? pair : 0, I = 0;
     while (p >= nt - I) {
         p -= nt - I;
         ++I;
     }
     const int J = I + p;
-    const int a = threadIdx.x >> 3, b = threadIdx.x & 7;
-    g[a][b] = (double)G[(int64_t)(8 * I + a) * ldg + 8 * J + b];
+    const int a = (threadIdx.x & 63) >> 3, b = threadIdx.x & 7;
+    g[wv][a][b] = valid ? (double)G[(int64_t)(8 * I + a) * ldg + 8 * J + b] : 0.0;
     __syncthreads();
     // t = G_IJ D^T: t[a][b] = sum_j g[a][j] D[b][j]
     double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) s += g[a][j] * D.d[8 * b + j];
-    t[a][b] = s;
+    for (int j = 0; j < 8; ++j) s += g[wv][a][j] * D.d[8 * b + j];
+    t[wv][a][b] = s;
     __syncthreads();
     // P = D t: P[a][b] = sum_i D[a][i] t[i][b]
     double v = 0.0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v += D.d[8 * a + i] * t[i][b];
+    for (int i = 0; i < 8; ++i) v += D.d[8 * a + i] * t[wv][i][b];
     if (zero_high && (a >= 4 || b >= 4)) v = 0.0;
+    g[wv][a][b] = v;   // reuse: the tile's P (every wave reaches the barrier)
+    __syncthreads();
+    if (!valid) return;
     if (I == J) {
-        __syncthreads();
-        g[a][b] = v;   // reuse: the tile's P
-        __syncthreads();
-        const double sym = 0.5 * (g[a][b] + g[b][a]);
+        const double sym = 0.5 * (g[wv][a][b] + g[wv][b][a]);
         Phi[(int64_t)(8 * I + a) * ldp + 8 * J + b] = (float)sym;
     } else {
         const float f = (float)v;
@@ -127,23 +133,31 @@ __device__ inline float hhat_at_zero(const double* scal, int K) {
 // empty row): an empty row r of the truncated matrix is an eigenvector with
 // eigenvalue 0, so the full hat H is the compact one on the nonempty indices and
 // hat h(0) on the diagonal of the empty ones.
-__global__ void __launch_bounds__(64) bt_inverse_kernel(int d, const float* H, int64_t ldh, float* M, int64_t ldm,
-                                                        Dct8 D, const int32_t* pos, const double* scal, int K) {
-    __shared__ double h[8][9];
-    __shared__ double t[8][9];
+// Wave w of the workgroup takes tile 4 blockIdx.x + w.
+__global__ void __launch_bounds__(256) bt_inverse_kernel(int d, const float* H, int64_t ldh, float* M, int64_t ldm,
+                                                         Dct8 D, const int32_t* pos, const double* scal, int K) {
+    __shared__ double hs[4][8][9];
+    __shared__ double ts[4][8][9];
+    const int wv = threadIdx.x >> 6;
+    double(*h)[9] = hs[wv];
+    double(*t)[9] = ts[wv];
     const int nt = d / 8;
-    const int I = blockIdx.x / nt, J = blockIdx.x % nt;
-    const int a = threadIdx.x >> 3, b = threadIdx.x & 7;
+    const int tile = blockIdx.x * 4 + wv;
+    const bool valid = tile < nt * nt;
+    const int I = valid ? tile / nt : 0, J = valid ? tile % nt : 0;
+    const int a = (threadIdx.x & 63) >> 3, b = threadIdx.x & 7;
     const int r = 8 * I + a, c = 8 * J + b;
-    float hv;
-    if (pos) {
-        const int pr = pos[r], pc = pos[c];
-        if (pr >= 0 && pc >= 0)
-            hv = H[(int64_t)pr * ldh + pc];
-        else
-            hv = r == c ? hhat_at_zero(scal, K) : 0.f;
-    } else {
-        hv = H[(int64_t)r * ldh + c];
+    float hv = 0.f;
+    if (valid) {
+        if (pos) {
+            const int pr = pos[r], pc = pos[c];
+            if (pr >= 0 && pc >= 0)
+                hv = H[(int64_t)pr * ldh + pc];
+            else
+                hv = r == c ? hhat_at_zero(scal, K) : 0.f;
+        } else {
+            hv = H[(int64_t)r * ldh + c];
+        }
     }
     h[a][b] = (double)hv;
     __syncthreads();
@@ -157,10 +171,11 @@ __global__ void __launch_bounds__(64) bt_inverse_kernel(int d, const float* H, i
     double v = 0.0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) v += D.d[8 * i + a] * t[i][b];
-    M[(int64_t)r * ldm + c] = (float)v;
+    if (valid) M[(int64_t)r * ldm + c] = (float)v;
 }
 
-// Histogram of the next digit of |Phi| over the entries matching the prefix.
+// Histogram of the next digit of |Phi| over the entries matching the prefix:
+// rows to workgroups, four columns to a thread (16-byte loads when aligned).
 __global__ void __launch_bounds__(256) sel_hist_kernel(int d, const float* Phi, int64_t ldp, int pass,
                                                        const SelState* st, unsigned* hist) {
     __shared__ unsigned lh[kSelBins];
@@ -168,11 +183,32 @@ __global__ void __launch_bounds__(256) sel_hist_kernel(int d, const float* Phi, 
     __syncthreads();
     const uint32_t prefix = st->prefix, mask = st->mask;
     const int shift = sel_shift(pass), nb = (1 << sel_bits(pass)) - 1;
-    const int64_t total = (int64_t)d * d;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-        const int r = (int)(e / d), c = (int)(e % d);
-        const uint32_t key = abs_key(Phi[(int64_t)r * ldp + c]);
-        if ((key & mask) == prefix) atomicAdd(&lh[(key >> shift) & nb], 1u);
+    const bool vec = (d & 3) == 0 && (ldp & 3) == 0 && ((reinterpret_cast<uintptr_t>(Phi) & 15) == 0);
+    for (int r = blockIdx.x; r < d; r += gridDim.x) {
+        const float* row = Phi + (int64_t)r * ldp;
+        for (int c0 = 0; c0 < d; c0 += 1024) {
+            const int c = c0 + 4 * threadIdx.x;
+            float v[4] = {0.f, 0.f, 0.f, 0.f};
+            bool in[4] = {false, false, false, false};
+            if (vec && c + 3 < d) {
+                const f32x4 x = *reinterpret_cast<const f32x4*>(row + c);
+                for (int e = 0; e < 4; ++e) {
+                    v[e] = x[e];
+                    in[e] = true;
+                }
+            } else {
+                for (int e = 0; e < 4; ++e)
+                    if (c + e < d) {
+                        v[e] = row[c + e];
+                        in[e] = true;
+                    }
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t key = abs_key(v[e]);
+                if (in[e] && (key & mask) == prefix) atomicAdd(&lh[(key >> shift) & nb], 1u);
+            }
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kSelBins; i += 256)

@@ -1,10 +1,13 @@
 // Spectral bound (Algorithm 1, the maximum-eigenvalue step) and the per-call
-// scalar block: power iteration on the Gram with FP64 accumulation, the bound
-// rule, and the FP64 Chebyshev coefficients (Sec. III-A,
+// scalar block: power iteration or k-step Lanczos on the Gram with FP64
+// accumulation, the bound rule, and the FP64 Chebyshev coefficients (Sec. III-A,
 // eq. chebychev_coeff_shifted) computed on the device from that bound.
 //
-// Power iteration runs in one launch whose workgroups are all resident (at most
-// one per CU, or a cooperative launch) with a grid barrier per product:
+// Gram sides up to 256 run either iteration in one workgroup that holds G in
+// registers (power_wg_kernel, lanczos_wg_kernel).  Larger sides run in one launch
+// whose workgroups are all resident (at most one per CU, or a cooperative
+// launch) with a grid barrier per product (power_coop_kernel, lanczos_coop_kernel).
+// The power iteration:
 //   w_0 = v_0 (SplitMix64 start vector or the warm-start vector)
 //   product t: v_t = w_{t-1} / ||w_{t-1}||, w_t = G v_t,
 //              mu_t = v_t . w_t and ||w_t||^2 in FP64: each workgroup stores its

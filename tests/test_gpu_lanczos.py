@@ -216,3 +216,21 @@ def test_lanczos_refusals():
     with pytest.raises(cpa.CpaError) as e:          # the CSR path keeps the power rule
         cpa.shrink_csr(2, 2, rowptr, cols, vals, cpa.soft(0.1), cpa.Opts(K=4, bound="lanczos"))
     assert e.value.status == cpa.ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("shape", [(200, 120), (1100, 1024)])
+def test_noalloc_entry_point_with_the_lanczos_bound(shape):
+    """The allocation-free entry point runs the same Lanczos kernels (its Lanczos
+    vectors in the static workspace's idle buffers) and returns the same bits."""
+    import torch
+    import paper_1705_07112_amd as cpa
+    m, n = shape
+    print(f"case noalloc lanczos {m}x{n}", flush=True)
+    X = torch.from_numpy(synth.as_f32_exact(synth.dense_lowrank(m, n, rank=4, noise=0.2, seed=7600 + m))
+                         .astype(np.float32)).cuda()
+    opts = cpa.Opts(K=30, bound="lanczos")
+    Y1, i1 = cpa.shrink_dense(X, cpa.soft(1.0), opts, info=True)
+    Y2 = cpa.shrink_dense_noalloc(X, cpa.soft(1.0), opts, torch.empty_like(X))
+    torch.cuda.synchronize()
+    assert i1["power_iters_done"] >= 2
+    assert torch.equal(Y1, Y2)

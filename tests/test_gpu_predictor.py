@@ -395,15 +395,20 @@ def test_predictor_gain_at_equal_pass_rate():
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
 
-    def timed(fn, reps=5):
+    def timed(fn, reps=5, windows=3):
+        # the best of three windows: one slow window (a clock or host hiccup) must
+        # not decide a comparison of two paths
         fn()
         torch.cuda.synchronize()
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
+        best = float("inf")
+        for _ in range(windows):
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) / reps)
+        return best
 
     def predicted():
         cpa.shrink_batched_predicted(X, m, n, off, cpa.soft(0.0), cpa.Opts(K=64, check=True), model, K_min=4,
