@@ -2775,20 +2775,31 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
         hipLaunchKernelGGL(symmetrize_kernel, dim3(gd), dim3(256), 0, st, d, f.Phi, (int64_t)d);
         HIP_TRY(hipGetLastError());
     } else {
-        hipLaunchKernelGGL(bt_forward_kernel, dim3((nt * (nt + 1) / 2 + 3) / 4), dim3(256), 0, st, d, (const float*)w.G,
-                           (int64_t)d, f.Phi, (int64_t)d, D, sp->transform == CPA_TRANSFORM_HAAR1_LOWPASS ? 1 : 0);
+        const int zh = sp->transform == CPA_TRANSFORM_HAAR1_LOWPASS ? 1 : 0;
+        if (d % 64 == 0)   // 64 x 64 blocks, rows written whole
+            hipLaunchKernelGGL(bt_forward_blk_kernel, dim3((d / 64) * (d / 64 + 1) / 2), dim3(256), 0, st, d,
+                               (const float*)w.G, (int64_t)d, f.Phi, (int64_t)d, D, zh);
+        else
+            hipLaunchKernelGGL(bt_forward_kernel, dim3((nt * (nt + 1) / 2 + 3) / 4), dim3(256), 0, st, d,
+                               (const float*)w.G, (int64_t)d, f.Phi, (int64_t)d, D, zh);
         HIP_TRY(hipGetLastError());
     }
     // M = T^T hat H T from the compact hat H (pitch ldh; hat h(0) on the empty diagonal)
     auto inverse = [&](const float* Hc, int64_t ldh) -> cpa_status {
         if (!dense_t) {
-            hipLaunchKernelGGL(bt_inverse_kernel, dim3((nt * nt + 3) / 4), dim3(256), 0, st, d, Hc, ldh, f.M, (int64_t)d, D,
-                               (const int32_t*)f.pos, (const double*)w.scal, opts->K);
+            if (d % 64 == 0)
+                hipLaunchKernelGGL(bt_inverse_blk_kernel, dim3((d / 64) * (d / 64)), dim3(256), 0, st, d, Hc, ldh, f.M,
+                                   (int64_t)d, D, (const int32_t*)f.pos, (const double*)w.scal, opts->K);
+            else
+                hipLaunchKernelGGL(bt_inverse_kernel, dim3((nt * nt + 3) / 4), dim3(256), 0, st, d, Hc, ldh, f.M,
+                                   (int64_t)d, D, (const int32_t*)f.pos, (const double*)w.scal, opts->K);
             HIP_TRY(hipGetLastError());
             return CPA_OK;
         }
         // expand to the full hat H (identity table), then C = hat H D, M = D^T C
-        hipLaunchKernelGGL(bt_inverse_kernel, dim3((nt * nt + 3) / 4), dim3(256), 0, st, d, Hc, ldh, f.P[0], (int64_t)d,
+        hipLaunchKernelGGL(d % 64 == 0 ? bt_inverse_blk_kernel : bt_inverse_kernel,
+                           dim3(d % 64 == 0 ? (d / 64) * (d / 64) : (nt * nt + 3) / 4), dim3(256), 0, st, d, Hc, ldh,
+                           f.P[0], (int64_t)d,
                            transform_table(CPA_TRANSFORM_IDENTITY), (const int32_t*)f.pos, (const double*)w.scal,
                            opts->K);
         HIP_TRY(hipGetLastError());
@@ -2808,7 +2819,7 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
         // eps = the keep-th largest |Phi|
         hipLaunchKernelGGL(sel_init_kernel, dim3(1), dim3(256), 0, st, f.sel, (uint32_t)sp->keep, f.hist);
         HIP_TRY(hipGetLastError());
-        const int gh = (int)std::min<int64_t>(1024, ((int64_t)d * d + 255) / 256);
+        const int gh = std::max(1, std::min(1024, (d + 1) / 2));   // pairs of rows (upper triangle)
         for (int pass = 0; pass < 3; ++pass) {
             hipLaunchKernelGGL(sel_hist_kernel, dim3(gh), dim3(256), 0, st, d, (const float*)f.Phi, (int64_t)d,
                                pass, (const SelState*)f.sel, f.hist);

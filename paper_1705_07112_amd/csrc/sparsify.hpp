@@ -10,7 +10,9 @@
 //   M = T^T hat H T, then hat G = X M (or M X).
 //
 // Kernels:
-//   bt_forward_kernel   one wave per pair of 8 x 8 tiles (I <= J), four to a workgroup:
+//   bt_forward_kernel   one wave per pair of 8 x 8 tiles (I <= J), four to a workgroup
+//                       (bt_forward_blk_kernel: one workgroup per 64 x 64 block,
+//                       the same values, when d is a multiple of 64):
 //                       P = D G_IJ D^T in FP64 from the FP32 Gram, written to tile
 //                       (I, J) and transposed to (J, I); diagonal tiles are
 //                       symmetrised ((P + P^T)/2).  Phi is therefore exactly
@@ -21,9 +23,11 @@
 //                       columns can be zeroed.
 //   sel_hist_kernel /   radix selection of the k-th largest |Phi| on the FP32 bit
 //   sel_pick_kernel     patterns of |Phi| (monotone as unsigned integers): three
-//                       passes of 11, 11 and 9 bits; exact integer histograms, so
-//                       the threshold is the same on every run.  The pick finds the
-//                       digit with a suffix scan over the bins (one workgroup).
+//                       passes of 11, 11 and 9 bits over the upper triangle (an
+//                       entry above the diagonal counted twice); exact integer
+//                       histograms, so the threshold is the same on every run.  The
+//                       pick finds the digit with a suffix scan over the bins (one
+//                       workgroup).
 //   trunc_count_kernel, one wave per row: counts the kept entries; after an
 //   trunc_fill_kernel   exclusive scan, writes (column, value) in column order
 //                       (ballot + prefix popcount) and zeroes the dropped entries of
@@ -35,7 +39,8 @@
 //   psi_step_kernel     one recurrence step on the CSR matrix: a workgroup per row
 //                       and 128-column panel, the row's entries spread over its
 //                       8 lane groups (the kept rows are very uneven).
-//   bt_inverse_kernel   M_IJ = D^T H_IJ D for every tile (one wave each), FP64 inside; expands the
+//   bt_inverse_kernel   M_IJ = D^T H_IJ D for every tile (one wave each; by 64 x 64
+//                       blocks in bt_inverse_blk_kernel), FP64 inside; expands the
 //                       compact hat H (hat h(0) on the empty diagonal entries).
 #pragma once
 
@@ -112,6 +117,94 @@ __global__ void __launch_bounds__(256) bt_forward_kernel(int d, const float* G, 
     }
 }
 
+// The forward transform by 64 x 64 blocks (d a multiple of 64): one workgroup of
+// 256 per block (BI, BJ), BI <= BJ; thread t owns row t / 4 of the block and its
+// 16 columns 16 (t % 4) .. + 15 (two 8-column tile groups).  The same FP64
+// operations in the same order as bt_forward_kernel, so Phi is bit for bit the
+// same:  t = G_IJ D^T per tile in registers, t through LDS, P = D t, P through
+// LDS; every global access is a contiguous row segment: the block's P to
+// (BI, BJ) and its transpose to (BJ, BI); on a diagonal block each tile takes
+// the upper tile's values (a diagonal tile (P + P^T) / 2).
+constexpr int kBtPad = 65;
+__global__ void __launch_bounds__(256) bt_forward_blk_kernel(int d, const float* G, int64_t ldg, float* Phi,
+                                                             int64_t ldp, Dct8 D, int zero_high) {
+    __shared__ double ts[64 * kBtPad];
+    const int nbk = d / 64;
+    int p = blockIdx.x, BI = 0;
+    while (p >= nbk - BI) {
+        p -= nbk - BI;
+        ++BI;
+    }
+    const int BJ = BI + p;
+    const int r = threadIdx.x >> 2, c0 = 16 * (threadIdx.x & 3);
+    const int a = r & 7;
+    // this thread's 16 entries of G (row r, columns c0 .. c0 + 15)
+    double g[16];
+    {
+        const float* src = G + (int64_t)(64 * BI + r) * ldg + 64 * BJ + c0;
+        const bool vec = ((ldg & 3) == 0) && ((reinterpret_cast<uintptr_t>(G) & 15) == 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (vec) {
+                const f32x4 x = *reinterpret_cast<const f32x4*>(src + 4 * q);
+                for (int e = 0; e < 4; ++e) g[4 * q + e] = (double)x[e];
+            } else {
+                for (int e = 0; e < 4; ++e) g[4 * q + e] = (double)src[4 * q + e];
+            }
+        }
+    }
+    // t[r][c] = sum_j G[r][8 (c / 8) + j] D[c % 8][j]
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s += g[8 * h + j] * D.d[8 * b + j];
+            ts[r * kBtPad + c0 + 8 * h + b] = s;
+        }
+    __syncthreads();
+    // P[r][c] = sum_i D[r % 8][i] t[8 (r / 8) + i][c]
+    double pv[16];
+    const int rb = r & ~7;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int c = c0 + k;
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v += D.d[8 * a + i] * ts[(rb + i) * kBtPad + c];
+        if (zero_high && (a >= 4 || (c & 7) >= 4)) v = 0.0;
+        pv[k] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) ts[r * kBtPad + c0 + k] = pv[k];
+    __syncthreads();
+    float* dst = Phi + (int64_t)(64 * BI + r) * ldp + 64 * BJ + c0;
+    if (BI == BJ) {
+        const int I = r >> 3;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int c = c0 + k, J = c >> 3;
+            double v;
+            if (I < J)
+                v = ts[r * kBtPad + c];
+            else if (I > J)
+                v = ts[c * kBtPad + r];
+            else
+                v = 0.5 * (ts[r * kBtPad + c] + ts[c * kBtPad + r]);
+            dst[k] = (float)v;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) dst[k] = (float)ts[r * kBtPad + c0 + k];
+        // the mirror: row r of block (BJ, BI) is column r of P
+        float* mir = Phi + (int64_t)(64 * BJ + r) * ldp + 64 * BI + c0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) mir[k] = (float)ts[(c0 + k) * kBtPad + r];
+    }
+}
+
 // hat h(0) with the arithmetic of the recurrence on a row with no kept entries
 // (Z = 0, Psi_0 = 1): Psi_k = (-1)^k exactly, summed in FP32 in step order.
 __device__ inline float hhat_at_zero(const double* scal, int K) {
@@ -174,8 +267,66 @@ __global__ void __launch_bounds__(256) bt_inverse_kernel(int d, const float* H, 
     if (valid) M[(int64_t)r * ldm + c] = (float)v;
 }
 
-// Histogram of the next digit of |Phi| over the entries matching the prefix:
-// rows to workgroups, four columns to a thread (16-byte loads when aligned).
+// The inverse transform by 64 x 64 blocks (d a multiple of 64): one workgroup of
+// 256 per block, thread t owning row t / 4 and 16 columns as in the forward
+// kernel, the same FP64 operations in the same order as bt_inverse_kernel
+// (t = H_IJ D per tile in registers, through LDS, M = D^T t), rows of M written
+// contiguously.
+__global__ void __launch_bounds__(256) bt_inverse_blk_kernel(int d, const float* H, int64_t ldh, float* M,
+                                                             int64_t ldm, Dct8 D, const int32_t* pos,
+                                                             const double* scal, int K) {
+    __shared__ double ts[64 * kBtPad];
+    const int nbk = d / 64;
+    const int BI = blockIdx.x / nbk, BJ = blockIdx.x % nbk;
+    const int r = threadIdx.x >> 2, c0 = 16 * (threadIdx.x & 3);
+    const int a = r & 7;
+    const int gr = 64 * BI + r;
+    double h[16];
+    {
+        const float hz = pos ? hhat_at_zero(scal, K) : 0.f;
+        const int pr = pos ? pos[gr] : gr;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int gc = 64 * BJ + c0 + k;
+            float hv;
+            if (pos) {
+                const int pc = pos[gc];
+                hv = (pr >= 0 && pc >= 0) ? H[(int64_t)pr * ldh + pc] : (gr == gc ? hz : 0.f);
+            } else {
+                hv = H[(int64_t)gr * ldh + gc];
+            }
+            h[k] = (double)hv;
+        }
+    }
+    // t[r][c] = sum_j H[r][8 (c / 8) + j] D[j][c % 8]
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) s += h[8 * hh + j] * D.d[8 * j + b];
+            ts[r * kBtPad + c0 + 8 * hh + b] = s;
+        }
+    __syncthreads();
+    // M[r][c] = sum_i D[i][r % 8] t[8 (r / 8) + i][c]
+    const int rb = r & ~7;
+    float* dst = M + (int64_t)gr * ldm + 64 * BJ + c0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int c = c0 + k;
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v += D.d[8 * i + a] * ts[(rb + i) * kBtPad + c];
+        dst[k] = (float)v;
+    }
+}
+
+// Histogram of the next digit of |Phi| over the entries matching the prefix.
+// Phi is exactly symmetric, so the upper triangle suffices: an entry above the
+// diagonal counts twice (itself and its mirror), a diagonal entry once; the
+// counts are those of all d^2 entries.  Workgroup b takes rows b and d - 1 - b
+// (equal work), four columns to a thread (16-byte loads when aligned).
 __global__ void __launch_bounds__(256) sel_hist_kernel(int d, const float* Phi, int64_t ldp, int pass,
                                                        const SelState* st, unsigned* hist) {
     __shared__ unsigned lh[kSelBins];
@@ -184,29 +335,29 @@ __global__ void __launch_bounds__(256) sel_hist_kernel(int d, const float* Phi, 
     const uint32_t prefix = st->prefix, mask = st->mask;
     const int shift = sel_shift(pass), nb = (1 << sel_bits(pass)) - 1;
     const bool vec = (d & 3) == 0 && (ldp & 3) == 0 && ((reinterpret_cast<uintptr_t>(Phi) & 15) == 0);
-    for (int r = blockIdx.x; r < d; r += gridDim.x) {
-        const float* row = Phi + (int64_t)r * ldp;
-        for (int c0 = 0; c0 < d; c0 += 1024) {
-            const int c = c0 + 4 * threadIdx.x;
-            float v[4] = {0.f, 0.f, 0.f, 0.f};
-            bool in[4] = {false, false, false, false};
-            if (vec && c + 3 < d) {
-                const f32x4 x = *reinterpret_cast<const f32x4*>(row + c);
-                for (int e = 0; e < 4; ++e) {
-                    v[e] = x[e];
-                    in[e] = true;
+    for (int b = blockIdx.x; 2 * b < d; b += gridDim.x) {
+        for (int side = 0; side < 2; ++side) {
+            const int r = side == 0 ? b : d - 1 - b;
+            if (side == 1 && r == b) break;
+            const float* row = Phi + (int64_t)r * ldp;
+            // columns r .. d - 1, from the 4-aligned column at or below r
+            for (int c0 = r & ~3; c0 < d; c0 += 1024) {
+                const int c = c0 + 4 * threadIdx.x;
+                float v[4] = {0.f, 0.f, 0.f, 0.f};
+                if (vec && c + 3 < d) {
+                    const f32x4 x = *reinterpret_cast<const f32x4*>(row + c);
+                    for (int e = 0; e < 4; ++e) v[e] = x[e];
+                } else {
+                    for (int e = 0; e < 4; ++e)
+                        if (c + e < d) v[e] = row[c + e];
                 }
-            } else {
-                for (int e = 0; e < 4; ++e)
-                    if (c + e < d) {
-                        v[e] = row[c + e];
-                        in[e] = true;
-                    }
-            }
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const uint32_t key = abs_key(v[e]);
-                if (in[e] && (key & mask) == prefix) atomicAdd(&lh[(key >> shift) & nb], 1u);
+                for (int e = 0; e < 4; ++e) {
+                    const int ce = c + e;
+                    if (ce < r || ce >= d) continue;
+                    const uint32_t key = abs_key(v[e]);
+                    if ((key & mask) == prefix) atomicAdd(&lh[(key >> shift) & nb], ce == r ? 1u : 2u);
+                }
             }
         }
     }
