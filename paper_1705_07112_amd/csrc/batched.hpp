@@ -291,12 +291,25 @@ __global__ void __launch_bounds__(BT_THREADS, 2) batched_kernel(BatchArgs a) {
         }
 
         auto load_z = [&]() {
-            // YT[j][i] = Z[i][j]; zero padding up to 64 x 128
-            for (int p = threadIdx.x; p < BT_EMAX * BT_DMAX; p += BT_THREADS) {
-                const int j = p / BT_DMAX, i = p % BT_DMAX;
-                float v = 0.f;
-                if (i < d && j < e) v = trans ? X[(int64_t)j * nj + i] : X[(int64_t)i * nj + j];
-                YT[j * BT_DP + i] = v;
+            // YT[j][i] = Z[i][j], zero padding up to 128 x 64.  Threads walk X in its
+            // own row-major order (consecutive threads, consecutive addresses) over a
+            // padded view of 128 x 64 (X = Z^T: YT's rows are X's rows) or 64 x 128
+            // (X = Z: X's rows become YT's columns), eight loads in flight per thread
+            const int lc = trans ? 6 : 7;
+            for (int p0 = threadIdx.x; p0 < BT_EMAX * BT_DMAX; p0 += 8 * BT_THREADS) {
+                float v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int p = p0 + u * BT_THREADS;
+                    const int row = p >> lc, col = p & ((1 << lc) - 1);
+                    v[u] = (row < mj && col < nj) ? X[(int64_t)row * nj + col] : 0.f;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int p = p0 + u * BT_THREADS;
+                    const int row = p >> lc, col = p & ((1 << lc) - 1);
+                    YT[trans ? row * BT_DP + col : col * BT_DP + row] = v[u];
+                }
             }
             __syncthreads();
         };
