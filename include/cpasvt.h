@@ -194,13 +194,14 @@ typedef struct {
 /* Per-call report (host struct).  Filling it synchronises the stream. */
 typedef struct {
     double Lambda;        /* bound used by the final evaluation */
-    double mu;            /* last Rayleigh quotient (0 unless CPA_BOUND_POWER) */
-    double resid;         /* last residual norm ||Gram v - mu v|| */
+    double mu;            /* last Rayleigh quotient, or the Ritz value theta with CPA_BOUND_LANCZOS
+                             (0 with the other rules) */
+    double resid;         /* last residual norm ||Gram v - mu v|| (the Ritz residual with Lanczos) */
     double fro_gram;      /* ||Gram||_F */
     double max_growth;    /* recurrence route: max_k ||Y_k||_F / ||X||_F over k = 1..K-1 (0 if
                              K == 1); matrix-polynomial route: the check's largest weighted
                              mean when check = 1, else 0 */
-    int32_t power_iters_done;
+    int32_t power_iters_done; /* power products, or Lanczos steps */
     int32_t fallback;     /* 1 when the check forced Lambda = ||Gram||_F */
     int32_t side;         /* 0: Gram = X^T X (right side), 1: Gram = X X^T (left side) */
     int32_t reserved;
