@@ -351,6 +351,18 @@ def test_block_dct_full_size(ev):
     _case(X, T, "block_dct8", 0.016, 30, Shrinkage(0, 0.2 * s1), cpa.soft(0.2 * s1), ev=ev)
 
 
+def test_block_dct_paper_shape():
+    """The bench's paper-shape workload: one 2560 x 1920 block-smooth component
+    (Gram side 1920), block DCT, K = 30, soft tau = 0.2 sigma_1, about 1.6% of the
+    transformed Gram kept (at a gap in |Phi|); every output element against the
+    oracle's transform-and-truncate shrink."""
+    cpa = _lib()
+    X = synth.as_f32_exact(synth.block_smooth(2560, 1920, rank=4, noise=1e-3, seed=synth.BASE_SEED + 8))
+    T = sparsify.block_dct(1920, 8)
+    s1 = math.sqrt(float(np.linalg.eigvalsh(X.T @ X)[-1]))
+    _case(X, T, "block_dct8", 0.016, 30, Shrinkage(0, 0.2 * s1), cpa.soft(0.2 * s1), ev="auto")
+
+
 def test_warm_start_maps_the_block_rows():
     """opts.warm_start on the polynomial route: the compact block's power vector is
     kept in the coordinates of the full transformed Gram and mapped onto the next
