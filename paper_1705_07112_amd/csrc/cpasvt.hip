@@ -642,6 +642,10 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
             HIP_TRY(hipGetLastError());
         }
         int d_ = d, maxit_ = o->power_iters, pw_mu = w.lay.pw_mu(), pw_w2 = w.lay.pw_w2();
+        // every product or step has its slots in the scalar block
+        const int slots = o->bound == CPA_BOUND_LANCZOS ? std::min(lanczos_steps(o), d) : maxit_;
+        if (slots > w.lay.maxit)
+            return fail(CPA_ERR_ARG, "internal: %d bound slots laid out for %d products", w.lay.maxit, slots);
         const float* G = w.G;
         int64_t ldg = d;
         double* wb0 = w.w[0];
@@ -2289,7 +2293,7 @@ cpa_status cpa_shrink_csr(cpa_ctx* ctx, void* stream, int m, int n, int64_t nnz,
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
     SpWork w;
-    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    const int maxit = power_slots(opts);
     if ((s = ensure_sparse_ws(ctx, m, n, nnz, opts->K, maxit, false, w, sparse_poly_choice(opts, n))) != CPA_OK)
         return s;
     if ((s = ensure_csc(ctx, st, m, n, nnz, rowptr_dev, colidx_dev)) != CPA_OK) return s;
@@ -2333,7 +2337,7 @@ cpa_status cpa_svt_complete(cpa_ctx* ctx, void* stream, int m, int n, int64_t nn
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
     SpWork w;
-    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    const int maxit = power_slots(opts);
     const int ps = sparse_poly_choice(opts, n);
     if ((s = ensure_sparse_ws(ctx, m, n, nnz, opts->K, std::max(maxit, 200), true, w, ps)) != CPA_OK) return s;
     if ((s = ensure_csc(ctx, st, m, n, nnz, rowptr_dev, colidx_dev)) != CPA_OK) return s;
@@ -2447,7 +2451,7 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
     Work w;
-    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    const int maxit = power_slots(opts);
     if ((s = ensure_ws(ctx, m, n, opts->K, maxit, true, w, right_side(opts, m, n), poly_choice(opts, m, n))) != CPA_OK)
         return s;
     AdmmPtrs P;
@@ -2742,7 +2746,7 @@ cpa_status cpa_shrink_dense_sparsified(cpa_ctx* ctx, void* stream, int m, int n,
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
     Work w;
-    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    const int maxit = power_slots(opts);
     // hat H by the matrix polynomial on the compact block, or by the sparse recurrence
     const bool poly = opts->K >= 2 && opts->K <= kPolyMaxK && opts->eval != CPA_EVAL_RECURRENCE;
     const int ps = poly ? poly_s_of(opts->K) : 0;
@@ -3120,7 +3124,7 @@ cpa_status inpaint_run(cpa_ctx* ctx, void* stream, int m, int n, const float* I_
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t st = static_cast<hipStream_t>(stream);
     Work w;
-    const int maxit = opts->bound == CPA_BOUND_POWER ? opts->power_iters : 1;
+    const int maxit = power_slots(opts);
     const int d = right_side(opts, m, n) ? n : m;
     if (sched) {
         // the sparsified shrink's own checks, before anything is launched
@@ -3332,7 +3336,7 @@ cpa_status cpa_shrink_dense_f64(cpa_ctx* ctx, void* stream, int m, int n, const 
     const bool right = right_side(&o, m, n);
     const int d = right ? n : m;
     Work w;
-    const int maxit = o.bound == CPA_BOUND_POWER ? o.power_iters : 1;
+    const int maxit = power_slots(&o);
     if ((s = ensure_ws(ctx, m, n, o.K, maxit, false, w, right, 0)) != CPA_OK) return s;
     F64Work f;
     if ((s = ensure_f64(ctx, d, m, n, f)) != CPA_OK) return s;

@@ -127,6 +127,9 @@ def test_sparsified_compact_block():
     torch.cuda.synchronize()
     print(f"  gpu {info['Lambda']:.10g} oracle {Lo:.10g}", flush=True)
     assert abs(info["Lambda"] - Lo) <= 1e-5 * Lo
+    # the Gram statistics stay intact beside the Lanczos slots
+    fro = math.sqrt(float(np.sum((X.T @ X) ** 2)))
+    assert abs(info["fro_gram"] - fro) <= 1e-5 * fro
     ref = sparsify.cpa_shrink_sparsified(X, Shrinkage(0, tau), info["Lambda"], 20, T, keep)[0]
     parity.check(Y.cpu().numpy(), ref, 1e-4, X, "sparsified lanczos")
 
@@ -194,6 +197,8 @@ def test_sparsified_wide_compact_block():
                                           cpa.Opts(K=20, bound="lanczos"), keep=keep, info=True)
     print(f"  gpu {info['Lambda']:.10g} oracle {Lo:.10g}", flush=True)
     assert abs(info["Lambda"] - Lo) <= 1e-5 * Lo
+    fro = math.sqrt(float(np.sum((X.T @ X) ** 2)))
+    assert abs(info["fro_gram"] - fro) <= 1e-5 * fro
 
 
 def test_lanczos_refusals():
