@@ -18,7 +18,8 @@ unstated; the reading here is z_0 = [l_0; s_0; I]: the first two blocks equal
 K [l_0; s_0], and the third block is the projection onto the observed data,
 which is I at every iteration, so it starts at I as well.
 The spectral bound of each shrink is a power-iteration bound warm-started from
-the previous iteration's vector.
+the previous iteration's vector, or (bound_rule="lanczos") the k-step Lanczos
+bound of oracle/bound.py warm-started from the previous Ritz vector.
 
 SVT matrix completion (Cai, Candes, Shen 2010; the paper cites completion but
 gives no algorithm): X^t = shrink_tau(Y^{t-1}); Y^t = Y^{t-1} + delta P_Omega(M - X^t),
@@ -85,15 +86,26 @@ def admm_lsolve(z1, z2, z3, u1, u2, u3):
     return (2.0 * a - b) / 3.0, (2.0 * b - a) / 3.0
 
 
+def _bound(Phi, rule, seed, power_iters, tol_power, delta, v0, lanczos_steps):
+    """(Lambda, the next warm-start vector) by the power iteration or by the
+    k-step Lanczos rule (oracle/bound.py), both from the same start."""
+    if rule == "lanczos":
+        r = bound.lanczos_bound(Phi, seed=seed, steps=lanczos_steps, delta=delta, v0=v0, tol=tol_power)
+        return r[0], r[4]
+    r = bound.power_bound(Phi, seed=seed, max_iter=power_iters, tol=tol_power, delta=delta, v0=v0)
+    return r[0], r[4]
+
+
 def rpca_step(state, I, inv_rho: float, eta_over_rho: float, K: int, v=None, seed: int = 0,
-              power_iters: int = 100, tol_power: float = 1e-7, delta: float = 0.01):
+              power_iters: int = 100, tol_power: float = 1e-7, delta: float = 0.01, bound_rule: str = "power",
+              lanczos_steps: int = 12):
     """One ADMM iteration from ``state`` = dict(l, s, z1, z2, u1, u2, u3) (z3 = I).
     Returns (new_state, info) with info = dict(x, Lambda, v, E)."""
     I = np.asarray(I, dtype=np.float64)
     l_new, s_new = admm_lsolve(state["z1"], state["z2"], I, state["u1"], state["u2"], state["u3"])
     x = l_new + state["u1"]
     Phi, _ = cpa.gram(x)
-    Lam, _, _, _, v = bound.power_bound(Phi, seed=seed, max_iter=power_iters, tol=tol_power, delta=delta, v0=v)
+    Lam, v = _bound(Phi, bound_rule, seed, power_iters, tol_power, delta, v, lanczos_steps)
     z1 = cpa.cpa_shrink(x, soft(inv_rho), Lam, K)
     z2 = soft_elementwise(s_new + state["u2"], eta_over_rho)
     new = {
@@ -197,7 +209,8 @@ def inpaint_start(omega):
 
 
 def inpaint_step(state, I, omega, border, inv_rho: float, eta_over_rho: float, K: int, v=None, seed: int = 0,
-                 power_iters: int = 100, tol_power: float = 1e-7, delta: float = 0.01, sparsify=None):
+                 power_iters: int = 100, tol_power: float = 1e-7, delta: float = 0.01, sparsify=None,
+                 bound_rule: str = "power", lanczos_steps: int = 12):
     """One ADMM iteration of eq. (admm_algorithm_inp).  omega: observed mask (1/0);
     border: mask of the surrounding pixels m_del, or None for no mean term.
     sparsify: None for the plain shrink, or dict(T, zero, keep): z1 by the
@@ -218,7 +231,7 @@ def inpaint_step(state, I, omega, border, inv_rho: float, eta_over_rho: float, K
     x = l_new + st["u1"]
     if sparsify is None:
         Phi, _ = cpa.gram(x)
-        Lam, _, _, _, v = bound.power_bound(Phi, seed=seed, max_iter=power_iters, tol=tol_power, delta=delta, v0=v)
+        Lam, v = _bound(Phi, bound_rule, seed, power_iters, tol_power, delta, v, lanczos_steps)
         z1 = cpa.cpa_shrink(x, soft(inv_rho), Lam, K)
     else:
         T, zero, keep = sparsify["T"], sparsify.get("zero"), sparsify["keep"]

@@ -483,8 +483,9 @@ cpa_status no_learned_bound(const cpa_opts* o) {
 // Lanczos steps of the Lanczos rule (0 selects the default).
 int lanczos_steps(const cpa_opts* o) { return o->lanczos_steps > 0 ? o->lanczos_steps : kLanczosDefault; }
 
-// The Lanczos rule runs where the bound is a dense FP32 Gram of side <= 256 (one
-// workgroup holds it) or a batched matrix; elsewhere it is refused.
+// The Lanczos rule runs wherever the bound is a dense FP32 Gram (sides up to the
+// grid kernel's 4096) or a batched matrix; the CSR operator form and the FP64
+// path refuse it.
 cpa_status lanczos_unsupported(const cpa_opts* o, const char* where) {
     if (o->bound == CPA_BOUND_LANCZOS)
         return fail(CPA_ERR_UNSUPPORTED, "the Lanczos bound is not available on %s", where);
@@ -2439,7 +2440,6 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
     if (iters < 0) return fail(CPA_ERR_ARG, "iters < 0");
     if ((s = check_opts(opts)) != CPA_OK) return s;
     if ((s = no_learned_bound(opts)) != CPA_OK) return s;
-    if ((s = lanczos_unsupported(opts, "the RPCA driver")) != CPA_OK) return s;
     if (!(std::isfinite(inv_rho) && inv_rho >= 0.0 && std::isfinite(eta_over_rho) && eta_over_rho >= 0.0))
         return fail(CPA_ERR_ARG, "inv_rho and eta_over_rho must be finite and >= 0");
     if (m == 0 || n == 0 || iters == 0) return CPA_OK;
@@ -2488,7 +2488,8 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
     // A cold power-iteration start is run directly; the captured graph always
     // takes the warm start (or the seeded start when warm starts are off).
     const int d = w.d;
-    if (opts->bound == CPA_BOUND_POWER && opts->warm_start && ctx->warm_d != d) {
+    if ((opts->bound == CPA_BOUND_POWER || opts->bound == CPA_BOUND_LANCZOS) && opts->warm_start &&
+        ctx->warm_d != d) {
         if ((s = one_iteration(st)) != CPA_OK) return s;
         ++t;
     }
@@ -3110,7 +3111,6 @@ cpa_status inpaint_run(cpa_ctx* ctx, void* stream, int m, int n, const float* I_
     if (iters < 0) return fail(CPA_ERR_ARG, "iters < 0");
     if ((s = check_opts(opts)) != CPA_OK) return s;
     if ((s = no_learned_bound(opts)) != CPA_OK) return s;
-    if ((s = lanczos_unsupported(opts, "the inpainting driver")) != CPA_OK) return s;
     if (!(std::isfinite(inv_rho) && inv_rho >= 0.0 && std::isfinite(eta_over_rho) && eta_over_rho >= 0.0))
         return fail(CPA_ERR_ARG, "inv_rho and eta_over_rho must be finite and >= 0");
     if (m == 0 || n == 0 || iters == 0) return CPA_OK;
@@ -3398,7 +3398,6 @@ cpa_status cpa_rpca_admm(cpa_ctx* ctx, void* stream, int m, int n, const float* 
     if (!(tol >= 0.0)) return fail(CPA_ERR_ARG, "tol must be >= 0");
     if ((s = check_opts(opts)) != CPA_OK) return s;
     if ((s = no_learned_bound(opts)) != CPA_OK) return s;
-    if ((s = lanczos_unsupported(opts, "the RPCA driver")) != CPA_OK) return s;
     if (iters_done) *iters_done = 0;
     if (m == 0 || n == 0 || max_iters == 0) return CPA_OK;
     if (!I_dev || !L_dev || !S_dev) return fail(CPA_ERR_ARG, "I, L or S is NULL");

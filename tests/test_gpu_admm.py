@@ -20,12 +20,12 @@ def _state_host(run):
     return {k: run.block(i).cpu().numpy().astype(np.float64) for i, k in enumerate(NAMES)}
 
 
-def _check_one_iteration(m, n, K, inv_rho, eta_over_rho, seed, warm_iters):
+def _check_one_iteration(m, n, K, inv_rho, eta_over_rho, seed, warm_iters, bound="power"):
     import torch
     import paper_1705_07112_amd as cpa
     I, _, _ = synth.rpca_frames(m, n, rank=min(40, m // 4), outlier_frac=0.05, seed=seed)
     Id = torch.from_numpy(I).cuda()
-    run = cpa.RpcaAdmm(Id, inv_rho, eta_over_rho, cpa.Opts(K=K, warm_start=True, power_iters=100))
+    run = cpa.RpcaAdmm(Id, inv_rho, eta_over_rho, cpa.Opts(K=K, warm_start=True, power_iters=100, bound=bound))
     Et = torch.zeros(warm_iters + 1, dtype=torch.float64, device="cuda")
     if warm_iters:
         run.iterate(warm_iters, Et[:warm_iters])
@@ -33,7 +33,7 @@ def _check_one_iteration(m, n, K, inv_rho, eta_over_rho, seed, warm_iters):
     run.iterate(1, Et[warm_iters:])
     torch.cuda.synchronize()
     after = _state_host(run)
-    ref, info = drivers.rpca_step(before, I.astype(np.float64), inv_rho, eta_over_rho, K)
+    ref, info = drivers.rpca_step(before, I.astype(np.float64), inv_rho, eta_over_rho, K, bound_rule=bound)
     # each dual block is a sum of three terms; its error is measured against the
     # size of those terms (the sum itself can cancel to much less)
     scale = {
@@ -55,6 +55,16 @@ def test_admm_one_iteration_small():
     print("admm 96x80", flush=True)
     _check_one_iteration(96, 80, 20, 1.0, 1.0 / np.sqrt(96), 11, warm_iters=0)
     _check_one_iteration(96, 80, 20, 1.0, 1.0 / np.sqrt(96), 11, warm_iters=6)
+
+
+@pytest.mark.parametrize("m,n,K,inv_rho,eta,seed", [(96, 80, 20, 1.0, 1.0 / np.sqrt(96), 12),
+                                                    (1024, 1024, 30, 10.0, 10.0 / 32.0, synth.BASE_SEED + 1)])
+def test_admm_one_iteration_lanczos_bound(m, n, K, inv_rho, eta, seed):
+    """The ADMM iteration with the Lanczos bound (one workgroup at d = 80, the
+    grid kernel at d = 1024; from the fifth iteration inside the captured graph)."""
+    print(f"admm lanczos {m}x{n}", flush=True)
+    _check_one_iteration(m, n, K, inv_rho, eta, seed, warm_iters=0, bound="lanczos")
+    _check_one_iteration(m, n, K, inv_rho, eta, seed, warm_iters=4, bound="lanczos")
 
 
 def test_admm_one_iteration_full_size():

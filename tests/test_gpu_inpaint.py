@@ -27,23 +27,25 @@ def _state_host(run):
     return {k: run.block(i).cpu().numpy().astype(np.float64) for i, k in enumerate(NAMES)}
 
 
-def _run(m, n, hole, border_w, with_mean, K, inv_rho, eta, seed):
+def _run(m, n, hole, border_w, with_mean, K, inv_rho, eta, seed, bound="power"):
     import torch
     import paper_1705_07112_amd as cpa
     I, om, bd, L0 = synth.texture(m, n, hole=hole, border=border_w, seed=seed)
     Id = torch.from_numpy(I.astype(np.float32)).cuda()
-    run = cpa.Inpaint(Id, torch.from_numpy(om), inv_rho, eta, cpa.Opts(K=K, warm_start=True, power_iters=100),
+    run = cpa.Inpaint(Id, torch.from_numpy(om), inv_rho, eta,
+                      cpa.Opts(K=K, warm_start=True, power_iters=100, bound=bound),
                       border=torch.from_numpy(bd.astype(np.float32)) if with_mean else None)
     return run, I.astype(np.float32).astype(np.float64), om, bd, L0
 
 
+@pytest.mark.parametrize("bound", ["power", "lanczos"])
 @pytest.mark.parametrize("with_mean", [True, False])
 @pytest.mark.parametrize("shape,hole", [((96, 80), (30, 60, 20, 44)), ((130, 70), (40, 71, 9, 33))])
-def test_inpaint_one_iteration(shape, hole, with_mean):
+def test_inpaint_one_iteration(shape, hole, with_mean, bound):
     import torch
     m, n = shape
     K, inv_rho, eta = 20, 1.0, 0.01
-    run, I, om, bd, _ = _run(m, n, hole, 3, with_mean, K, inv_rho, eta, 8100 + m)
+    run, I, om, bd, _ = _run(m, n, hole, 3, with_mean, K, inv_rho, eta, 8100 + m, bound)
     for warm in (0, 6):
         if warm:
             run.iterate(warm)
@@ -52,7 +54,7 @@ def test_inpaint_one_iteration(shape, hole, with_mean):
         run.iterate(1, Et)
         torch.cuda.synchronize()
         after = _state_host(run)
-        ref, info = drivers.inpaint_step(before, I, om, bd if with_mean else None, inv_rho, eta, K)
+        ref, info = drivers.inpaint_step(before, I, om, bd if with_mean else None, inv_rho, eta, K, bound_rule=bound)
         P = drivers.dct2(ref["l"])
         scale = {"u1": metrics.fro(before["u1"]) + metrics.fro(ref["l"]) + metrics.fro(ref["z1"]),
                  "u2": metrics.fro(before["u2"]) + metrics.fro(P) + metrics.fro(ref["z2"]),
