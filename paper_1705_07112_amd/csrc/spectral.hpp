@@ -343,6 +343,21 @@ __device__ inline double pw_dpp(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// a[j % 4] += g[j] * (v of lane j), j = 0..63 in order: this lane's row slice
+// against the wave's 64 entries of the vector.  The broadcasts are taken eight at
+// a time ahead of their products, so the scalar registers they fill are not
+// reused back to back.
+__device__ inline void pw_rowdot(const float (&g)[64], double v, double (&a)[4]) {
+#pragma unroll
+    for (int j0 = 0; j0 < 64; j0 += 8) {
+        double vv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) vv[u] = pw_readlane(v, j0 + u);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u & 3] += (double)g[j0 + u] * vv[u];
+    }
+}
+
 // Sums of a and b over the 64 lanes (equal in every lane): within rows of 16
 // lanes swap neighbours, swap pairs, mirror halves, mirror the row; then the
 // four row sums in a fixed order.
@@ -403,8 +418,7 @@ __global__ void __launch_bounds__(kPowerWgThreads) power_wg_kernel(int d, const 
             // they would take 128 registers)
 #pragma unroll
             for (int j = 0; j < 64; ++j) asm volatile("" : "+v"(g[j]));
-#pragma unroll
-            for (int j = 0; j < 64; ++j) a[j & 3] += (double)g[j] * pw_readlane(v, j);
+            pw_rowdot(g, v, a);
         }
         rowp[par][cb][row] = (a[0] + a[1]) + (a[2] + a[3]);
         __syncthreads();
@@ -540,17 +554,27 @@ __device__ inline void lz_ritz(double al, double be, int k, double& theta, doubl
     resid = fabs(pw_readlane(be, k - 1)) * fabs(pw_readlane(s_out, k - 1));
 }
 
+// The Ritz pair of T_j is formed by the first wave only, during step j (while
+// the other waves take their rows of G q_j), into LDS slots by step parity; the
+// step's barrier publishes it together with the stopping decision, and a run
+// that stops there keeps k = j (the products of step j are dropped).  A run
+// that ends by its step count or a vanishing beta forms the pair of T_k after
+// the loop, into a third slot.  kLzSlot: s_0..s_{k-1}, then theta, ||r|| and the
+// stop flag.
+constexpr int kLzSlot = kLanczosMax + 3;
+
 // k-step Lanczos for a Gram of side d <= kPowerWgMaxD in one workgroup, steps <=
 // kLanczosMax: the register layout of power_wg_kernel for the products; the
 // Lanczos vectors stay in LDS (for the Ritz vector).  Each step takes one
 // workgroup barrier: after it every wave forms u on all d entries from the four
 // partial row sums and adds alpha and ||u||^2 itself (the same operations in every
-// wave, so every wave holds the same alpha_j, beta_j and stopping decision).
+// wave, so every wave holds the same alpha_j and beta_j).
 __global__ void __launch_bounds__(kPowerWgThreads) lanczos_wg_kernel(int d, const float* G, int64_t ldg, double* wb0,
                                                                    double* wb1, double* scal, int steps, double tol,
                                                                    int pw_mu, int pw_w2) {
     __shared__ double rowp[2][4][kPowerWgMaxD];   // partial row sums by column block, by parity
     __shared__ double Q[kLanczosMax][kPowerWgMaxD];
+    __shared__ double rz[3][kLzSlot];             // Ritz pairs: by step parity, then the final one
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int rb = wave & 3, cb = wave >> 2;
@@ -588,21 +612,35 @@ __global__ void __launch_bounds__(kPowerWgThreads) lanczos_wg_kernel(int d, cons
     double q = col < d ? wb0[col] / sqrt(n0) : 0.0;   // q_j at this lane's column
     double bprev = 0.0;
     double al = 0.0, be = 0.0;   // lane j: alpha_j, beta_j
-    double theta = 0.0, resid = 0.0, s = 0.0, th_prev = 0.0;
-    int k = 0, vanish = 0;
-    bool fresh = false;   // theta, resid, s belong to T_k
+    double th_prev = 0.0;        // first wave: the Ritz value of T_{j-1}
+    int k = 0, vanish = 0, slot = -1;
     for (int j = 0; j < steps; ++j) {
         const int par = j & 1;
         if (rb == 0) Q[j][col] = q;
+        if (tol > 0.0 && j >= 1 && wave == 0) {
+            double theta, resid, s;
+            lz_ritz(al, be, j, theta, resid, s);
+            const bool stop = j >= 2 && fabs(theta - th_prev) <= tol * theta;
+            th_prev = theta;
+            if (lane < j) rz[par][lane] = s;
+            if (lane == 0) {
+                rz[par][kLanczosMax] = theta;
+                rz[par][kLanczosMax + 1] = resid;
+                rz[par][kLanczosMax + 2] = stop ? 1.0 : 0.0;
+            }
+        }
         double a[4] = {0.0, 0.0, 0.0, 0.0};
         if (live) {
 #pragma unroll
             for (int jj = 0; jj < 64; ++jj) asm volatile("" : "+v"(g[jj]));
-#pragma unroll
-            for (int jj = 0; jj < 64; ++jj) a[jj & 3] += (double)g[jj] * pw_readlane(q, jj);
+            pw_rowdot(g, q, a);
         }
         rowp[par][cb][row] = (a[0] + a[1]) + (a[2] + a[3]);
         __syncthreads();
+        if (tol > 0.0 && j >= 1 && rz[par][kLanczosMax + 2] != 0.0) {
+            slot = par;   // k = j
+            break;
+        }
         double u[4], qc[4];
         double pa = 0.0;
 #pragma unroll
@@ -630,15 +668,7 @@ __global__ void __launch_bounds__(kPowerWgThreads) lanczos_wg_kernel(int d, cons
             vanish = 1;
             break;
         }
-        fresh = false;
         if (beta == 0.0) break;
-        if (tol > 0.0) {
-            // the Ritz pair of T_{j+1}; kept when the run ends here
-            lz_ritz(al, be, k, theta, resid, s);
-            fresh = true;
-            if (j >= 1 && fabs(theta - th_prev) <= tol * theta) break;
-            th_prev = theta;
-        }
         const double uc = cb == 0 ? u[0] : (cb == 1 ? u[1] : (cb == 2 ? u[2] : u[3]));
         q = uc / beta;
         bprev = beta;
@@ -650,17 +680,30 @@ __global__ void __launch_bounds__(kPowerWgThreads) lanczos_wg_kernel(int d, cons
         }
         return;
     }
-    // the Ritz pair of T_k unless the last step formed it
-    if (!fresh) lz_ritz(al, be, k, theta, resid, s);
+    if (slot < 0) {
+        // the Ritz pair of T_k
+        slot = 2;
+        if (wave == 0) {
+            double theta, resid, s;
+            lz_ritz(al, be, k, theta, resid, s);
+            if (lane < k) rz[2][lane] = s;
+            if (lane == 0) {
+                rz[2][kLanczosMax] = theta;
+                rz[2][kLanczosMax + 1] = resid;
+            }
+        }
+        __syncthreads();
+    }
     // the Ritz vector into the buffer the finishing kernel reads the last vector
     // from (slot T - 1 holds its squared length: s is a unit vector)
     double* yb = ((k - 1) & 1) ? wb1 : wb0;
     if (threadIdx.x < d) {
         double y = 0.0;
-        for (int i = 0; i < k; ++i) y += pw_readlane(s, i) * Q[i][threadIdx.x];
+        for (int i = 0; i < k; ++i) y += rz[slot][i] * Q[i][threadIdx.x];
         yb[threadIdx.x] = y;
     }
     if (threadIdx.x == 0) {
+        const double theta = rz[slot][kLanczosMax], resid = rz[slot][kLanczosMax + 1];
         scal[pw_mu + k] = theta;
         scal[pw_w2 + k] = theta * theta + resid * resid;
         scal[pw_w2 + k - 1] = 1.0;
@@ -677,16 +720,19 @@ __global__ void __launch_bounds__(kPowerWgThreads) lanczos_wg_kernel(int d, cons
 //   after it, every workgroup adds the partials in a fixed order (alpha_j), loads
 //   all of u, forms u - alpha_j q_j and ||.||^2 over the d entries itself (same
 //   operations in every workgroup) and keeps q_{j+1} = u / beta_j in LDS.
-// Every workgroup holds the same alpha, beta and stopping decision, and forms the
-// same Ritz pair; the Ritz vector's entry i is formed by the thread that stored
-// Q[.][i].  Q holds steps + 2 vectors of d: the Lanczos vectors, then U by step
-// parity (a workgroup that runs ahead writes the other one while the rest still
-// read theirs; the same parity rule as the partial sums).
+// Every workgroup holds the same alpha and beta; its first wave forms the Ritz
+// pair of T_j during step j (as in lanczos_wg_kernel), so every workgroup takes
+// the same stopping decision after the grid barrier; the Ritz vector's entry i
+// is formed by the thread that stored Q[.][i].  Q holds steps + 2 vectors of d:
+// the Lanczos vectors, then U by step parity (a workgroup that runs ahead writes
+// the other one while the rest still read theirs; the same parity rule as the
+// partial sums).
 __global__ void __launch_bounds__(kPowerThreads) lanczos_coop_kernel(int d, const float* G, int64_t ldg, double* wb0,
                                                                      double* wb1, double* Q, double* part,
                                                                      unsigned* counter, double* scal, int steps,
                                                                      double tol, int pw_mu, int pw_w2) {
     __shared__ double red[kPowerThreads / 64];
+    __shared__ double rz[3][kLzSlot];   // Ritz pairs: by step parity, then the final one
     __shared__ __attribute__((aligned(16))) double va[kPowerVecLds];
     __shared__ __attribute__((aligned(16))) double vb[kPowerVecLds];
     const int P = gridDim.x;
@@ -711,11 +757,23 @@ __global__ void __launch_bounds__(kPowerThreads) lanczos_coop_kernel(int d, cons
     double* vp = vb;   // q_{j-1}, then u
     const bool vec = ((ldg & 3) == 0) && ((reinterpret_cast<uintptr_t>(G) & 15) == 0);
     double bprev = 0.0;
-    double al = 0.0, be = 0.0, theta = 0.0, resid = 0.0, s = 0.0, th_prev = 0.0;
-    int k = 0, vanish = 0;
-    bool fresh = false;
+    double al = 0.0, be = 0.0, th_prev = 0.0;
+    int k = 0, vanish = 0, slot = -1;
     for (int j = 0; j < steps; ++j) {
-        double* U = Q + (int64_t)(steps + (j & 1)) * d;
+        const int par = j & 1;
+        double* U = Q + (int64_t)(steps + par) * d;
+        if (tol > 0.0 && j >= 1 && threadIdx.x < 64) {
+            double theta, resid, s;
+            lz_ritz(al, be, j, theta, resid, s);
+            const bool stop = j >= 2 && fabs(theta - th_prev) <= tol * theta;
+            th_prev = theta;
+            if (lane < j) rz[par][lane] = s;
+            if (lane == 0) {
+                rz[par][kLanczosMax] = theta;
+                rz[par][kLanczosMax + 1] = resid;
+                rz[par][kLanczosMax + 2] = stop ? 1.0 : 0.0;
+            }
+        }
         double apart = 0.0;
         for (int i = gw; i < d; i += nw) {
             const float* row = G + (int64_t)i * ldg;
@@ -749,6 +807,10 @@ __global__ void __launch_bounds__(kPowerThreads) lanczos_coop_kernel(int d, cons
         double* pt = part + (j & 1) * 2 * P;
         if (threadIdx.x == 0) st_agent(pt + blockIdx.x, apart);
         if (!grid_barrier_coherent(counter, (unsigned)(j + 1) * P, scal)) return;
+        if (tol > 0.0 && j >= 1 && rz[par][kLanczosMax + 2] != 0.0) {
+            slot = par;   // k = j
+            break;
+        }
         double sa = 0.0;
         for (int p = threadIdx.x; p < P; p += kPowerThreads) sa += ld_agent(pt + p);
         const double alpha = block_sum(sa, red);
@@ -769,14 +831,7 @@ __global__ void __launch_bounds__(kPowerThreads) lanczos_coop_kernel(int d, cons
             vanish = 1;
             break;
         }
-        fresh = false;
         if (beta == 0.0) break;
-        if (tol > 0.0) {
-            lz_ritz(al, be, k, theta, resid, s);
-            fresh = true;
-            if (j >= 1 && fabs(theta - th_prev) <= tol * theta) break;
-            th_prev = theta;
-        }
         // q_{j+1} = u / beta; the roles of the two LDS vectors swap
         const double ib = 1.0 / beta;
         for (int i = threadIdx.x; i < d; i += kPowerThreads) vp[i] *= ib;
@@ -793,17 +848,31 @@ __global__ void __launch_bounds__(kPowerThreads) lanczos_coop_kernel(int d, cons
         }
         return;
     }
-    if (!fresh) lz_ritz(al, be, k, theta, resid, s);
+    if (slot < 0) {
+        // the Ritz pair of T_k
+        slot = 2;
+        if (threadIdx.x < 64) {
+            double theta, resid, s;
+            lz_ritz(al, be, k, theta, resid, s);
+            if (lane < k) rz[2][lane] = s;
+            if (lane == 0) {
+                rz[2][kLanczosMax] = theta;
+                rz[2][kLanczosMax + 1] = resid;
+            }
+        }
+        __syncthreads();
+    }
     // the Ritz vector: entry i from the stores of the thread that owns row i
     double* yb = ((k - 1) & 1) ? wb1 : wb0;
     if (lane == 0) {
         for (int i = gw; i < d; i += nw) {
             double y = 0.0;
-            for (int q = 0; q < k; ++q) y += pw_readlane(s, q) * Q[(int64_t)q * d + i];
+            for (int q = 0; q < k; ++q) y += rz[slot][q] * Q[(int64_t)q * d + i];
             yb[i] = y;
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const double theta = rz[slot][kLanczosMax], resid = rz[slot][kLanczosMax + 1];
         scal[pw_mu + k] = theta;
         scal[pw_w2 + k] = theta * theta + resid * resid;
         scal[pw_w2 + k - 1] = 1.0;
