@@ -53,6 +53,7 @@ cpa_status fail(cpa_status s, const char* fmt, ...) {
 
 constexpr int kMaxPowerIters = 1000;
 constexpr int kAdmmGrid = 2048;   // workgroups of the ADMM elementwise kernels
+constexpr int kAdmmChunk = 8;     // ADMM iterations in the longer captured graph (one launch between them)
 constexpr int kMaxK = 4096;
 constexpr int kMaxDesignK = 1024;        // cpa_design_coeffs orders
 constexpr int kMaxDesignN = 1 << 20;     // and sample / grid points
@@ -122,9 +123,11 @@ struct cpa_ctx {
     const int32_t* csc_colidx = nullptr;
     int csc_m = -1, csc_n = -1;
     int64_t csc_nnz = -1;
-    // captured ADMM iteration, replayed while its key matches
+    // captured ADMM iterations (one, and kAdmmChunk in a row), replayed while their
+    // key matches
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t admm_exec = nullptr;
+    hipGraphExec_t admm_exec_chunk = nullptr;
     std::vector<char> admm_key;
 };
 
@@ -1498,6 +1501,7 @@ cpa_status cpa_destroy(cpa_ctx* ctx) {
     for (auto& L : ctx->tlog)
         for (hipEvent_t e : L.ev) (void)hipEventDestroy(e);
     if (ctx->admm_exec) (void)hipGraphExecDestroy(ctx->admm_exec);
+    if (ctx->admm_exec_chunk) (void)hipGraphExecDestroy(ctx->admm_exec_chunk);
     if (ctx->queue) (void)hipFree(ctx->queue);
     if (ctx->spf) (void)hipFree(ctx->spf);
     if (ctx->spf_host) (void)hipHostFree(ctx->spf_host);
@@ -2509,29 +2513,41 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
     put(&m, sizeof m); put(&n, sizeof n); put(&I_dev, sizeof I_dev); put(&state_dev, sizeof state_dev);
     put(&Et_dev, sizeof Et_dev); put(&ctx->ws, sizeof ctx->ws); put(&ctx->warm, sizeof ctx->warm);
     put(opts, sizeof *opts); put(&inv_rho, sizeof inv_rho); put(&eta_over_rho, sizeof eta_over_rho);
-    if (!ctx->admm_exec || key != ctx->admm_key) {
-        if (ctx->admm_exec) {
-            HIP_TRY(hipGraphExecDestroy(ctx->admm_exec));
-            ctx->admm_exec = nullptr;
-        }
+    // one graph of `reps` iterations in a row
+    auto capture = [&](int reps, hipGraphExec_t* exec) -> cpa_status {
         if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
         hipGraph_t g;
         HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-        const cpa_status cs = one_iteration(ctx->cap_stream);
+        cpa_status cs = CPA_OK;
+        for (int r = 0; r < reps && cs == CPA_OK; ++r) cs = one_iteration(ctx->cap_stream);
         const hipError_t ce = hipStreamEndCapture(ctx->cap_stream, &g);
         if (cs != CPA_OK) {
             if (ce == hipSuccess) (void)hipGraphDestroy(g);
             return cs;
         }
         if (ce != hipSuccess) return fail(CPA_ERR_HIP, "graph capture failed: %s", hipGetErrorString(ce));
-        const hipError_t ie = hipGraphInstantiate(&ctx->admm_exec, g, nullptr, nullptr, 0);
+        const hipError_t ie = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (ie != hipSuccess) {
-            ctx->admm_exec = nullptr;
+            *exec = nullptr;
             return fail(CPA_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ie));
         }
+        return CPA_OK;
+    };
+    if (!ctx->admm_exec || !ctx->admm_exec_chunk || key != ctx->admm_key) {
+        for (hipGraphExec_t* e : {&ctx->admm_exec, &ctx->admm_exec_chunk})
+            if (*e) {
+                HIP_TRY(hipGraphExecDestroy(*e));
+                *e = nullptr;
+            }
+        ctx->admm_key.clear();
+        // both graphs now, so that a later call with many iterations does not
+        // capture inside its caller's timing
+        if ((s = capture(1, &ctx->admm_exec)) != CPA_OK) return s;
+        if ((s = capture(kAdmmChunk, &ctx->admm_exec_chunk)) != CPA_OK) return s;
         ctx->admm_key = key;
     }
+    for (; iters - t >= kAdmmChunk; t += kAdmmChunk) HIP_TRY(hipGraphLaunch(ctx->admm_exec_chunk, st));
     for (; t < iters; ++t) HIP_TRY(hipGraphLaunch(ctx->admm_exec, st));
     return CPA_OK;
 }

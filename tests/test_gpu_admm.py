@@ -117,15 +117,17 @@ def test_rpca_one_call_stops_at_tolerance():
 
 def test_graph_replays_equal_direct_launches():
     """The ADMM iteration replayed from its captured graph equals the same
-    iterations launched directly, bit for bit: runs of 5, 4 and 2 replays with
-    synchronisations and eager work between them, each run's E_t and the state
-    compared (cold power starts, so neither run depends on the other)."""
+    iterations launched directly, bit for bit: runs of 5, 4, 2 and 19 replays
+    (the last one two replays of the eight-iteration graph and three of the
+    one-iteration graph) with synchronisations and eager work between them, each
+    run's E_t and the state compared (cold power starts, so neither run depends
+    on the other)."""
     import torch
     import paper_1705_07112_amd as cpa
     I, _, _ = synth.rpca_frames(128, 96, rank=12, outlier_frac=0.05, seed=41)
     Id = torch.from_numpy(I).cuda()
     opts = cpa.Opts(K=20, warm_start=False, power_iters=100)
-    chunks = (5, 4, 2)
+    chunks = (5, 4, 2, 19)
     direct = cpa.RpcaAdmm(Id, 1.0, 1.0 / np.sqrt(128), opts)
     Ed = torch.zeros(sum(chunks), dtype=torch.float64, device="cuda")
     cpa.timing_enable(True)      # per-launch timing forces direct launches
