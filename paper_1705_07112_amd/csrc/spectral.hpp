@@ -424,9 +424,10 @@ __global__ void __launch_bounds__(kPowerWgThreads) power_wg_kernel(int d, const 
         __syncthreads();
         // w_t for this lane's column, the new iterate (rows and columns share the index)
         const double wi = ((rowp[par][0][col] + rowp[par][1][col]) + (rowp[par][2][col] + rowp[par][3][col])) * inv;
-        double mu_p = (v * inv) * wi, w2_p = wi * wi;
-        pw_wave_sum2(mu_p, w2_p);
         if (rb == 0) {
+            // the sums over this column block (the other waves hold the same wi)
+            double mu_p = (v * inv) * wi, w2_p = wi * wi;
+            pw_wave_sum2(mu_p, w2_p);
             if (lane == 0) {
                 red[par][0][cb] = mu_p;
                 red[par][1][cb] = w2_p;
@@ -1147,13 +1148,29 @@ __global__ void ps_lincomb_kernel(int d, int s, int J, const float* T1, const do
                 }
             }
         }
-        for (int j = 0; j < J; ++j) {
-            f32x4 v;
+        // which of the four entries lie on the diagonal (with d % 4 == 0 they share
+        // one row: a single division, 32-bit where d^2 allows)
+        bool on_diag[4];
+        if (vec) {
+            int64_t r0;
+            if (dd <= 0x7fffffff)
+                r0 = (int64_t)((uint32_t)p0 / (uint32_t)d);
+            else
+                r0 = p0 / d;
+            const int64_t c0 = p0 - r0 * d;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) on_diag[e] = r0 == c0 + e;
+        } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int64_t p = p0 + e;
-                v[e] = (p / d == p % d) ? rc[j * s] : 0.f;
+                on_diag[e] = p / d == p % d;
             }
+        }
+        for (int j = 0; j < J; ++j) {
+            f32x4 v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = on_diag[e] ? rc[j * s] : 0.f;
 #pragma unroll
             for (int q = 1; q < MAXS; ++q)
                 if (q < s) v += rc[j * s + q] * t[q];
