@@ -422,6 +422,14 @@ cpa_status gemm_dispatch(hipStream_t st, const Operand& A, const Operand& B, int
     if constexpr (LA == KCONTIG && LB == KCONTIG && std::is_same<Epi, EpiLin>::value) {
         if (lds_pipeline_ok(A, B, M, N, Kd)) {
             if (epi_sym(epi) && M != N) return fail(CPA_ERR_ARG, "internal: a symmetric product must be square");
+            if (epi.sym == 2 && epi.vec_ok && M <= kSymSmallMax && Kd == M) {
+                // small symmetric product: one 32 x 32 tile on or above the diagonal per workgroup
+                const int nt = M / 32;
+                hipLaunchKernelGGL(gemm_f32_sym_small_kernel, dim3(nt * (nt + 1) / 2), dim3(kSymSmallThreads), 0, st,
+                                   A, B, M, epi);
+                HIP_TRY(hipGetLastError());
+                return CPA_OK;
+            }
             if (epi.sym == 2 && epi.vec_ok) {
                 // symmetric product in pieces: (M / 64)^2 workgroups
                 hipLaunchKernelGGL(gemm_f32_piece_kernel<EpiLin>, dim3((M / 64) * (M / 64)), dim3(1024), 0, st, A, B,

@@ -453,4 +453,127 @@ __global__ void __launch_bounds__(1024) gemm_f32_piece_kernel(Operand A, Operand
     epi.run_piece(tile, m0, n0, half);
 }
 
+// Symmetric products of side M <= kSymSmallMax (the linear epilogue, Kd = M, both
+// operands k-contiguous with 16-byte rows).  In pieces such a product has only
+// (M / 64)^2 <= 16 workgroups, each with the whole K loop of a 64 x 64 piece
+// behind its pipeline's fill.  Here each workgroup takes one 32 x 32 tile on or
+// above the diagonal (nt (nt + 1) / 2 of them, nt = M / 32) and loads its 32 rows
+// of A and of B whole into LDS (one round trip: every load is issued before the
+// first store).  Wave w computes the 16 x 16 block w % 4 of the tile over half of
+// K (w / 4), one fresh partial sum per 64 k added into its accumulator; the two
+// halves are added in LDS in a fixed order (first half + second half).  The
+// epilogue is EpiLin's: o = alpha acc + beta C + gamma Mx (+ delta on the
+// diagonal), read at the tile's positions, stored as the tile and its mirror (a
+// diagonal tile from its upper triangle), so D comes out exactly symmetric; C may
+// be D (no other workgroup reads this tile's positions).
+constexpr int kSymSmallMax = 256;
+constexpr int kSymSmallThreads = 512;
+
+__global__ void __launch_bounds__(kSymSmallThreads) gemm_f32_sym_small_kernel(Operand A, Operand B, int M, EpiLin epi) {
+    constexpr int T = 32;                    // tile side
+    constexpr int KP = kSymSmallMax + 4;     // LDS pitch of the operand rows (floats)
+    constexpr int TP = T + 4;                // LDS pitch of the result tile
+    constexpr int NL = T * (kSymSmallMax / 4) / kSymSmallThreads;   // float4 loads per thread and operand
+    __shared__ __attribute__((aligned(16))) float sa[T * KP];
+    __shared__ __attribute__((aligned(16))) float sb[T * KP];
+    __shared__ __attribute__((aligned(16))) float tile[T * TP];
+    const int nt = M / T;
+    // the tile of this workgroup: upper-triangle tiles in row order
+    int tm = 0, rem = blockIdx.x;
+    while (rem >= nt - tm) {
+        rem -= nt - tm;
+        ++tm;
+    }
+    const int tn = tm + rem;
+    const int m0 = tm * T, n0 = tn * T;
+    const int Kd = M;
+    const int gpr = Kd / 4;   // float4 groups per row
+    {
+        f32x4 ra[NL], rb[NL];
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int g = threadIdx.x + u * kSymSmallThreads;
+            const int r = g / gpr, c = (g - r * gpr) * 4;
+            if (r < T) {
+                ra[u] = *reinterpret_cast<const f32x4*>(A.p + (int64_t)(m0 + r) * A.ld + c);
+                rb[u] = *reinterpret_cast<const f32x4*>(B.p + (int64_t)(n0 + r) * B.ld + c);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int g = threadIdx.x + u * kSymSmallThreads;
+            const int r = g / gpr, c = (g - r * gpr) * 4;
+            if (r < T) {
+                *reinterpret_cast<f32x4*>(sa + r * KP + c) = ra[u];
+                *reinterpret_cast<f32x4*>(sb + r * KP + c) = rb[u];
+            }
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int br = ((wave & 3) >> 1) * 16, bc = (wave & 1) * 16, kh = wave >> 2;
+    const int li = lane & 15, lg = lane >> 4;
+    const int khalf = Kd / 2;   // a multiple of 16
+    const float* pa = sa + (br + li) * KP + kh * khalf + 4 * lg;
+    const float* pb = sb + (bc + li) * KP + kh * khalf + 4 * lg;
+    f32x4 acc = (f32x4){0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < khalf; k0 += 64) {
+        f32x4 part = (f32x4){0.f, 0.f, 0.f, 0.f};
+        const int kend = min(khalf - k0, 64);
+        for (int kk = 0; kk < kend; kk += 16) {
+            // lane group lg supplies k = k0 + kk + 4 lg + t to the t-th product
+            const f32x4 a4 = *reinterpret_cast<const f32x4*>(pa + k0 + kk);
+            const f32x4 b4 = *reinterpret_cast<const f32x4*>(pb + k0 + kk);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) part = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[t], b4[t], part, 0, 0, 0);
+        }
+        acc += part;
+    }
+    // lane (li, lg) holds rows br + 4 lg + r, column bc + li of the tile
+    if (kh == 1) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tile[(br + 4 * lg + r) * TP + bc + li] = acc[r];
+    }
+    __syncthreads();
+    if (kh == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float& t = tile[(br + 4 * lg + r) * TP + bc + li];
+            t = acc[r] + t;
+        }
+    }
+    __syncthreads();
+    // epilogue: 32 rows x 8 float4 groups on the first 256 threads
+    const bool mine = threadIdx.x < T * (T / 4);
+    const int r = threadIdx.x / (T / 4), cc = (threadIdx.x % (T / 4)) * 4;
+    const int i = m0 + r, j = n0 + cc;
+    f32x4 o = (f32x4){0.f, 0.f, 0.f, 0.f};
+    if (mine) {
+        const f32x4 a = *reinterpret_cast<const f32x4*>(tile + r * TP + cc);
+        f32x4 vd = (f32x4){0.f, 0.f, 0.f, 0.f}, vm = vd;
+        if (epi.beta != 0.f) vd = *reinterpret_cast<const f32x4*>(epi.C + (int64_t)i * epi.ldc + j);
+        if (epi.gamma != 0.f) vm = *reinterpret_cast<const f32x4*>(epi.Mx + (int64_t)i * epi.ldm + j);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float v = epi.alpha * a[e] + epi.beta * vd[e] + epi.gamma * vm[e];
+            if (i == j + e) v += epi.delta;
+            o[e] = v;
+        }
+    }
+    __syncthreads();   // every product value read before the tile is overwritten
+    if (mine) *reinterpret_cast<f32x4*>(tile + r * TP + cc) = o;
+    __syncthreads();
+    if (!mine) return;
+    const bool diag = m0 == n0;
+    f32x4 v, w;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int c = cc + e;
+        v[e] = (!diag || r <= c) ? tile[r * TP + c] : tile[c * TP + r];
+        w[e] = tile[c * TP + r];
+    }
+    *reinterpret_cast<f32x4*>(epi.D + (int64_t)i * epi.ldd + j) = v;
+    if (!diag) *reinterpret_cast<f32x4*>(epi.D + (int64_t)(n0 + r) * epi.ldd + m0 + cc) = w;
+}
+
 }  // namespace cpa
