@@ -424,8 +424,19 @@ __global__ void __launch_bounds__(256) trunc_count_kernel(int d, const float* Ph
     const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (r >= d) return;
     const uint32_t eps = st->prefix;
+    const float* row = Phi + (int64_t)r * ldp;
     int c = 0;
-    for (int j = lane; j < d; j += 64) c += abs_key(Phi[(int64_t)r * ldp + j]) >= eps ? 1 : 0;
+    if ((d & 3) == 0 && (ldp & 3) == 0 && ((reinterpret_cast<uintptr_t>(Phi) & 15) == 0)) {
+        // 16-byte loads, four of them in flight per lane
+#pragma unroll 4
+        for (int j = 4 * lane; j < d; j += 256) {
+            const f32x4 x = *reinterpret_cast<const f32x4*>(row + j);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) c += abs_key(x[e]) >= eps ? 1 : 0;
+        }
+    } else {
+        for (int j = lane; j < d; j += 64) c += abs_key(row[j]) >= eps ? 1 : 0;
+    }
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
     if (lane == 0) cnt[r] = c;
 }
