@@ -721,10 +721,11 @@ __global__ void __launch_bounds__(kPowerWgThreads) lanczos_wg_kernel(int d, cons
 //   after it, every workgroup adds the partials in a fixed order (alpha_j), loads
 //   all of u, forms u - alpha_j q_j and ||.||^2 over the d entries itself (same
 //   operations in every workgroup) and keeps q_{j+1} = u / beta_j in LDS.
-// Every workgroup holds the same alpha and beta; its first wave forms the Ritz
-// pair of T_j during step j (as in lanczos_wg_kernel), so every workgroup takes
-// the same stopping decision after the grid barrier; the Ritz vector's entry i
-// is formed by the thread that stored Q[.][i].  Q holds steps + 2 vectors of d:
+// Every workgroup holds the same alpha and beta; with the early stop its first
+// wave forms the Ritz pair of T_{j+1} once beta_j is known (a grid step costs
+// several times the pair, so the pair is not deferred into the next step as in
+// lanczos_wg_kernel), and every workgroup takes the same stopping decision; the
+// Ritz vector's entry i is formed by the thread that stored Q[.][i].  Q holds steps + 2 vectors of d:
 // the Lanczos vectors, then U by step parity (a workgroup that runs ahead writes
 // the other one while the rest still read theirs; the same parity rule as the
 // partial sums).
@@ -763,18 +764,6 @@ __global__ void __launch_bounds__(kPowerThreads) lanczos_coop_kernel(int d, cons
     for (int j = 0; j < steps; ++j) {
         const int par = j & 1;
         double* U = Q + (int64_t)(steps + par) * d;
-        if (tol > 0.0 && j >= 1 && threadIdx.x < 64) {
-            double theta, resid, s;
-            lz_ritz(al, be, j, theta, resid, s);
-            const bool stop = j >= 2 && fabs(theta - th_prev) <= tol * theta;
-            th_prev = theta;
-            if (lane < j) rz[par][lane] = s;
-            if (lane == 0) {
-                rz[par][kLanczosMax] = theta;
-                rz[par][kLanczosMax + 1] = resid;
-                rz[par][kLanczosMax + 2] = stop ? 1.0 : 0.0;
-            }
-        }
         double apart = 0.0;
         for (int i = gw; i < d; i += nw) {
             const float* row = G + (int64_t)i * ldg;
@@ -808,10 +797,6 @@ __global__ void __launch_bounds__(kPowerThreads) lanczos_coop_kernel(int d, cons
         double* pt = part + (j & 1) * 2 * P;
         if (threadIdx.x == 0) st_agent(pt + blockIdx.x, apart);
         if (!grid_barrier_coherent(counter, (unsigned)(j + 1) * P, scal)) return;
-        if (tol > 0.0 && j >= 1 && rz[par][kLanczosMax + 2] != 0.0) {
-            slot = par;   // k = j
-            break;
-        }
         double sa = 0.0;
         for (int p = threadIdx.x; p < P; p += kPowerThreads) sa += ld_agent(pt + p);
         const double alpha = block_sum(sa, red);
@@ -833,6 +818,26 @@ __global__ void __launch_bounds__(kPowerThreads) lanczos_coop_kernel(int d, cons
             break;
         }
         if (beta == 0.0) break;
+        if (tol > 0.0) {
+            // the Ritz pair of T_{j+1}; kept when the run ends here
+            if (threadIdx.x < 64) {
+                double theta, resid, s;
+                lz_ritz(al, be, k, theta, resid, s);
+                const bool stop = j >= 1 && fabs(theta - th_prev) <= tol * theta;
+                th_prev = theta;
+                if (lane < k) rz[par][lane] = s;
+                if (lane == 0) {
+                    rz[par][kLanczosMax] = theta;
+                    rz[par][kLanczosMax + 1] = resid;
+                    rz[par][kLanczosMax + 2] = stop ? 1.0 : 0.0;
+                }
+            }
+            __syncthreads();
+            if (rz[par][kLanczosMax + 2] != 0.0) {
+                slot = par;
+                break;
+            }
+        }
         // q_{j+1} = u / beta; the roles of the two LDS vectors swap
         const double ib = 1.0 / beta;
         for (int i = threadIdx.x; i < d; i += kPowerThreads) vp[i] *= ib;
