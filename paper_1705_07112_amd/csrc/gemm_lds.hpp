@@ -455,7 +455,7 @@ __global__ void __launch_bounds__(1024) gemm_f32_piece_kernel(Operand A, Operand
 
 // Symmetric products of side M <= kSymSmallMax (the linear epilogue, Kd = M, both
 // operands k-contiguous with 16-byte rows).  In pieces such a product has only
-// (M / 64)^2 <= 16 workgroups, each with the whole K loop of a 64 x 64 piece
+// (M / 64)^2 <= 64 workgroups, each with the whole K loop of a 64 x 64 piece
 // behind its pipeline's fill.  Here each workgroup takes one 32 x 32 tile on or
 // above the diagonal (nt (nt + 1) / 2 of them, nt = M / 32) and loads its 32 rows
 // of A and of B whole into LDS (one round trip: every load is issued before the
@@ -466,14 +466,13 @@ __global__ void __launch_bounds__(1024) gemm_f32_piece_kernel(Operand A, Operand
 // diagonal), read at the tile's positions, stored as the tile and its mirror (a
 // diagonal tile from its upper triangle), so D comes out exactly symmetric; C may
 // be D (no other workgroup reads this tile's positions).
-constexpr int kSymSmallMax = 256;
+constexpr int kSymSmallMax = 512;
 constexpr int kSymSmallThreads = 512;
 
 __global__ void __launch_bounds__(kSymSmallThreads) gemm_f32_sym_small_kernel(Operand A, Operand B, int M, EpiLin epi) {
     constexpr int T = 32;                    // tile side
     constexpr int KP = kSymSmallMax + 4;     // LDS pitch of the operand rows (floats)
     constexpr int TP = T + 4;                // LDS pitch of the result tile
-    constexpr int NL = T * (kSymSmallMax / 4) / kSymSmallThreads;   // float4 loads per thread and operand
     __shared__ __attribute__((aligned(16))) float sa[T * KP];
     __shared__ __attribute__((aligned(16))) float sb[T * KP];
     __shared__ __attribute__((aligned(16))) float tile[T * TP];
@@ -489,23 +488,25 @@ __global__ void __launch_bounds__(kSymSmallThreads) gemm_f32_sym_small_kernel(Op
     const int Kd = M;
     const int gpr = Kd / 4;   // float4 groups per row
     {
-        f32x4 ra[NL], rb[NL];
+        // thread t: float4 column group t % CG of rows t / CG + RPH u (every load
+        // issued before the first store)
+        constexpr int CG = kSymSmallMax / 4;          // groups of a full-width row
+        constexpr int RPH = kSymSmallThreads / CG;    // row phases
+        constexpr int NR = T / RPH;                   // rows per thread
+        const int cg = threadIdx.x % CG, rp = threadIdx.x / CG;
+        if (cg < gpr) {
+            const float* ga = A.p + (int64_t)(m0 + rp) * A.ld + 4 * cg;
+            const float* gb = B.p + (int64_t)(n0 + rp) * B.ld + 4 * cg;
+            f32x4 ra[NR], rb[NR];
 #pragma unroll
-        for (int u = 0; u < NL; ++u) {
-            const int g = threadIdx.x + u * kSymSmallThreads;
-            const int r = g / gpr, c = (g - r * gpr) * 4;
-            if (r < T) {
-                ra[u] = *reinterpret_cast<const f32x4*>(A.p + (int64_t)(m0 + r) * A.ld + c);
-                rb[u] = *reinterpret_cast<const f32x4*>(B.p + (int64_t)(n0 + r) * B.ld + c);
+            for (int u = 0; u < NR; ++u) {
+                ra[u] = *reinterpret_cast<const f32x4*>(ga + (int64_t)(RPH * u) * A.ld);
+                rb[u] = *reinterpret_cast<const f32x4*>(gb + (int64_t)(RPH * u) * B.ld);
             }
-        }
 #pragma unroll
-        for (int u = 0; u < NL; ++u) {
-            const int g = threadIdx.x + u * kSymSmallThreads;
-            const int r = g / gpr, c = (g - r * gpr) * 4;
-            if (r < T) {
-                *reinterpret_cast<f32x4*>(sa + r * KP + c) = ra[u];
-                *reinterpret_cast<f32x4*>(sb + r * KP + c) = rb[u];
+            for (int u = 0; u < NR; ++u) {
+                *reinterpret_cast<f32x4*>(sa + (rp + RPH * u) * KP + 4 * cg) = ra[u];
+                *reinterpret_cast<f32x4*>(sb + (rp + RPH * u) * KP + 4 * cg) = rb[u];
             }
         }
     }
