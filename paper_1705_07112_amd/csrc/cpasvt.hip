@@ -1066,6 +1066,9 @@ cpa_status enqueue_prep(cpa_ctx* ctx, hipStream_t st, int m, int n, const float*
         a.P = *P;
         a.admm = 1;
         a.part = part;
+        auto al = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+        a.vec = n % 4 == 0 && al(P->l) && al(P->s) && al(P->z1) && al(P->z2) && al(P->u1) && al(P->u2) &&
+                al(P->u3) && al(P->I) && al(P->x);
     }
     const int64_t ldt = gram_xt_ld(w, m, n);
     a.xt = ldt > 0 ? w.xt : nullptr;
@@ -2488,9 +2491,12 @@ cpa_status cpa_rpca_iterate(cpa_ctx* ctx, void* stream, int m, int n, const floa
             CPA_OK)
             return r;
         if ((r = shrink_impl(ctx, q, m, n, w.x, n, P.z1, n, &sh, opts, nullptr, w, &pd)) != CPA_OK) return r;
-        const int pgrid = (int)std::min<int64_t>(kAdmmGrid, (mn + 255) / 256);
-        hipLaunchKernelGGL(admm_post_kernel, dim3(pgrid), dim3(256), 0, q, P, mn, (float)eta_over_rho,
-                           (const double*)w.admm, npart, Et_dev, w.et_counter);
+        // 16-byte accesses when every array is aligned (the state's blocks are mn floats apart)
+        const int vec = (mn % 4 == 0) && ((reinterpret_cast<uintptr_t>(state_dev) & 15) == 0) &&
+                        ((reinterpret_cast<uintptr_t>(I_dev) & 15) == 0);
+        const int pgrid = (int)std::min<int64_t>(kAdmmGrid, ((vec ? mn / 4 : mn) + 255) / 256);
+        hipLaunchKernelGGL(admm_post_kernel, dim3(std::max(pgrid, 1)), dim3(256), 0, q, P, mn, (float)eta_over_rho,
+                           (const double*)w.admm, npart, Et_dev, w.et_counter, vec);
         HIP_TRY(hipGetLastError());
         return CPA_OK;
     };

@@ -57,6 +57,14 @@ def test_admm_one_iteration_small():
     _check_one_iteration(96, 80, 20, 1.0, 1.0 / np.sqrt(96), 11, warm_iters=6)
 
 
+def test_admm_one_iteration_odd_width():
+    """n % 4 != 0: the pre- and post-steps take their element-by-element path
+    (at n % 4 == 0 they move four elements per access)."""
+    print("admm 70x53", flush=True)
+    _check_one_iteration(70, 53, 20, 1.0, 1.0 / np.sqrt(70), 13, warm_iters=0)
+    _check_one_iteration(70, 53, 20, 1.0, 1.0 / np.sqrt(70), 13, warm_iters=5)
+
+
 @pytest.mark.parametrize("m,n,K,inv_rho,eta,seed", [(96, 80, 20, 1.0, 1.0 / np.sqrt(96), 12),
                                                     (1024, 1024, 30, 10.0, 10.0 / 32.0, synth.BASE_SEED + 1)])
 def test_admm_one_iteration_lanczos_bound(m, n, K, inv_rho, eta, seed):
