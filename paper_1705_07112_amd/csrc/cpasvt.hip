@@ -709,7 +709,7 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
     }
     // on the matrix-polynomial route the finish kernel also forms T1 (extra workgroups)
     const bool shift = poly_fused(w, o->K);
-    const int shift_wg = shift ? (int)std::min<int64_t>(4096, ((int64_t)d * d / 4 + 255) / 256 + 1) : 0;
+    const int shift_wg = shift ? (int)std::min<int64_t>(4096, ((int64_t)d * d / 16 + 255) / 256 + 1) : 0;
     hipLaunchKernelGGL(finish_bound_kernel, dim3(1 + shift_wg), dim3(256), 0, st, mode, o->Lambda, d, o->power_iters,
                        o->margin, (const double*)w.w[0], (const double*)w.w[1], mode == 0 ? warm_vec : nullptr, w.scal,
                        to_params(sh), o->K, w.lay.pw_mu(), w.lay.pw_w2(), (const double*)(w.scal + w.lay.gpart()),

@@ -982,17 +982,32 @@ __global__ void finish_bound_kernel(int mode, double Lambda_given, int d, int ma
         const int64_t stride = (int64_t)(gridDim.x - 1) * blockDim.x;
         const int64_t first = (int64_t)(blockIdx.x - 1) * blockDim.x + threadIdx.x;
         if ((d & 3) == 0 && (ldgs & 3) == 0 && ((uintptr_t)Gs & 15) == 0 && ((uintptr_t)T1s & 15) == 0) {
-            // four elements of one row per thread
+            // four elements of one row per access, four accesses per thread in flight
+            // (all loads before the first store)
             const int64_t total4 = (int64_t)d * d / 4;
-            for (int64_t q = first; q < total4; q += stride) {
-                const int64_t i = (4 * q) / d, j = 4 * q - i * d;
-                const float4 g = *reinterpret_cast<const float4*>(Gs + i * ldgs + j);
-                float4 t;
-                t.x = a1 * g.x - (i == j ? 1.f : 0.f);
-                t.y = a1 * g.y - (i == j + 1 ? 1.f : 0.f);
-                t.z = a1 * g.z - (i == j + 2 ? 1.f : 0.f);
-                t.w = a1 * g.w - (i == j + 3 ? 1.f : 0.f);
-                *reinterpret_cast<float4*>(T1s + 4 * q) = t;
+            for (int64_t q0 = first; q0 < total4; q0 += 4 * stride) {
+                float4 g[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t q = q0 + u * stride;
+                    if (q < total4) {
+                        const int64_t i = (4 * q) / d, j = 4 * q - i * d;
+                        g[u] = *reinterpret_cast<const float4*>(Gs + i * ldgs + j);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int64_t q = q0 + u * stride;
+                    if (q < total4) {
+                        const int64_t i = (4 * q) / d, j = 4 * q - i * d;
+                        float4 t;
+                        t.x = a1 * g[u].x - (i == j ? 1.f : 0.f);
+                        t.y = a1 * g[u].y - (i == j + 1 ? 1.f : 0.f);
+                        t.z = a1 * g[u].z - (i == j + 2 ? 1.f : 0.f);
+                        t.w = a1 * g[u].w - (i == j + 3 ? 1.f : 0.f);
+                        *reinterpret_cast<float4*>(T1s + 4 * q) = t;
+                    }
+                }
             }
         } else {
             const int64_t total = (int64_t)d * d;
@@ -1070,18 +1085,19 @@ __device__ inline void ps_coeff_block(int K, int s, int J, double* scal, int out
     for (int k = threadIdx.x; k < n; k += blockDim.x)
         w[k] = k < K ? scal[SC_COEF + k] * (k == 0 ? 0.5 : 1.0) : 0.0;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        // in place: entry (j, i) of r lives at w[j s + i]
-        for (int j = J - 1; j >= 1; --j) {
-            for (int i = s - 1; i >= 1; --i) {
-                const int k = j * s + i;
-                const double v = w[k];
-                w[k] = 2.0 * v;
-                w[j * s - i] -= v;
-            }
+    // in place: entry (j, i) of r lives at w[j s + i]; rows from the last down, the
+    // s - 1 updates of a row in parallel (their sources lie in row j and their
+    // targets w[j s - i] are distinct entries of row j - 1)
+    for (int j = J - 1; j >= 1; --j) {
+        const int i = (int)threadIdx.x + 1;
+        if (i < s) {
+            const int k = j * s + i;
+            const double v = w[k];
+            w[k] = 2.0 * v;
+            w[j * s - i] -= v;
         }
+        __syncthreads();
     }
-    __syncthreads();
     for (int k = threadIdx.x; k < n; k += blockDim.x) scal[out + k] = w[k];
 }
 
