@@ -102,10 +102,12 @@ typedef struct {
  *                        The Ritz vector sum_j s_j q_j is the next warm start; info.mu and
  *                        info.resid report theta and ||r||, power_iters_done the steps.
  *                        Gram sides up to 4096 on the dense FP32 entry points (cpa_shrink_dense,
- *                        _noalloc, cpa_spectral_bound, cpa_shrink_dense_sparsified), the RPCA
- *                        and inpainting drivers, and every matrix of the batched path
- *                        (d <= 64); CPA_ERR_UNSUPPORTED on larger sides and on the CSR and
- *                        FP64 entry points */
+ *                        _noalloc, cpa_spectral_bound, cpa_shrink_dense_sparsified), the FP64
+ *                        entry point (its Lanczos vectors take the (lanczos_steps + 2) d
+ *                        doubles of its m x n product buffer: CPA_ERR_UNSUPPORTED when they
+ *                        do not fit), the RPCA and inpainting drivers, and every matrix of
+ *                        the batched path (d <= 64); CPA_ERR_UNSUPPORTED on larger sides and
+ *                        on the CSR entry points */
 typedef enum {
     CPA_BOUND_POWER = 0,
     CPA_BOUND_GIVEN = 1,

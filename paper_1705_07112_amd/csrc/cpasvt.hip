@@ -641,7 +641,7 @@ int bound_mode(int rule) {
 // logmn: log(m n) of the input (the learned rule's third feature).
 cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkage* sh, const cpa_opts* o,
                          const Work& w, int mode_override, const double* G64 = nullptr, double logmn = 0.0,
-                         bool start_ready = false) {
+                         bool start_ready = false, double* Q64 = nullptr, size_t q64_doubles = 0) {
     int mode = bound_mode(o->bound);
     if (mode_override >= 0) mode = mode_override;
     double* warm_vec = w.warm_vec ? w.warm_vec : ctx->warm;
@@ -667,7 +667,17 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
         double* scal = w.scal;
         double tol = o->power_tol;
         cpa_status ls;
-        if (G64) {
+        if (G64 && o->bound == CPA_BOUND_LANCZOS) {
+            // the FP64 Gram: the grid kernel at every side, its vectors in the caller's idle buffer
+            int steps = std::min(lanczos_steps(o), d);
+            if (d > kPowerVecLds)
+                return fail(CPA_ERR_UNSUPPORTED, "the Lanczos bound takes Gram sides up to %d (got %d)", kPowerVecLds,
+                            d);
+            if (!Q64 || (size_t)(steps + 2) * d > q64_doubles)
+                return fail(CPA_ERR_UNSUPPORTED, "no room for the Lanczos vectors in this workspace");
+            void* args[] = {&d_, &G64, &ldg, &wb0, &wb1, &Q64, &part, &counter, &scal, &steps, &tol, &pw_mu, &pw_w2};
+            ls = launch_power(ctx, reinterpret_cast<const void*>(lanczos_coop_kernel<double>), w.lay.pwg, args, st);
+        } else if (G64) {
             void* args[] = {&d_, &G64, &ldg, &wb0, &wb1, &part, &counter, &scal, &maxit_, &tol, &pw_mu, &pw_w2};
             ls = launch_power(ctx, reinterpret_cast<const void*>(power_coop_kernel<double>), w.lay.pwg, args, st);
         } else if (o->bound == CPA_BOUND_LANCZOS) {
@@ -693,7 +703,7 @@ cpa_status enqueue_bound(cpa_ctx* ctx, hipStream_t st, int d, const cpa_shrinkag
                 if (!Q) return fail(CPA_ERR_UNSUPPORTED, "no room for the Lanczos vectors in this workspace");
                 double tol = o->power_tol;
                 void* args[] = {&d_, &G, &ldg, &wb0, &wb1, &Q, &part, &counter, &scal, &steps, &tol, &pw_mu, &pw_w2};
-                ls = launch_power(ctx, reinterpret_cast<const void*>(lanczos_coop_kernel), w.lay.pwg, args, st);
+                ls = launch_power(ctx, reinterpret_cast<const void*>(lanczos_coop_kernel<float>), w.lay.pwg, args, st);
             }
         } else if (d <= kPowerWgMaxD) {
             // small sides: one workgroup with G in registers, no grid barrier
@@ -3349,7 +3359,6 @@ cpa_status cpa_shrink_dense_f64(cpa_ctx* ctx, void* stream, int m, int n, const 
     if (o.precision == CPA_PREC_FP64) o.precision = CPA_PREC_FP32;   // the arithmetic here is FP64 in any case
     if ((s = check_opts(&o)) != CPA_OK) return s;
     if ((s = no_learned_bound(&o)) != CPA_OK) return s;
-    if ((s = lanczos_unsupported(&o, "the FP64 path")) != CPA_OK) return s;
     if (o.precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "the FP64 path has no split precision");
     if (o.check) return fail(CPA_ERR_UNSUPPORTED, "the growth check is not available on the FP64 path");
     if (o.eval == CPA_EVAL_POLYNOMIAL) return fail(CPA_ERR_UNSUPPORTED, "the FP64 path evaluates by the recurrence");
@@ -3380,7 +3389,8 @@ cpa_status cpa_shrink_dense_f64(cpa_ctx* ctx, void* stream, int m, int n, const 
     hipLaunchKernelGGL(gram64_stats_kernel, dim3(w.lay.gwg), dim3(256), 0, st, d, (const double*)f.G,
                        w.scal + w.lay.gpart());
     HIP_TRY(hipGetLastError());
-    if ((s = enqueue_bound(ctx, st, d, shrink, &o, w, -1, f.G)) != CPA_OK) return s;
+    // the Lanczos vectors (if that rule is asked for) in the product buffer Z, idle until the recurrence
+    if ((s = enqueue_bound(ctx, st, d, shrink, &o, w, -1, f.G, 0.0, false, f.Z, (size_t)m * n)) != CPA_OK) return s;
     const int64_t mn = (int64_t)m * n;
     const int ge = (int)std::min<int64_t>(4096, (mn + 255) / 256);
     if (o.K == 1) {

@@ -729,7 +729,9 @@ __global__ void __launch_bounds__(kPowerWgThreads) lanczos_wg_kernel(int d, cons
 // the Lanczos vectors, then U by step parity (a workgroup that runs ahead writes
 // the other one while the rest still read theirs; the same parity rule as the
 // partial sums).
-__global__ void __launch_bounds__(kPowerThreads) lanczos_coop_kernel(int d, const float* G, int64_t ldg, double* wb0,
+// TG: the Gram's element type (float, or double for the FP64 path).
+template <class TG>
+__global__ void __launch_bounds__(kPowerThreads) lanczos_coop_kernel(int d, const TG* G, int64_t ldg, double* wb0,
                                                                      double* wb1, double* Q, double* part,
                                                                      unsigned* counter, double* scal, int steps,
                                                                      double tol, int pw_mu, int pw_w2) {
@@ -757,7 +759,7 @@ __global__ void __launch_bounds__(kPowerThreads) lanczos_coop_kernel(int d, cons
     __syncthreads();
     double* vq = va;   // q_j
     double* vp = vb;   // q_{j-1}, then u
-    const bool vec = ((ldg & 3) == 0) && ((reinterpret_cast<uintptr_t>(G) & 15) == 0);
+    const bool vec = std::is_same<TG, float>::value && ((ldg & 3) == 0) && ((reinterpret_cast<uintptr_t>(G) & 15) == 0);
     double bprev = 0.0;
     double al = 0.0, be = 0.0, th_prev = 0.0;
     int k = 0, vanish = 0, slot = -1;
@@ -766,19 +768,21 @@ __global__ void __launch_bounds__(kPowerThreads) lanczos_coop_kernel(int d, cons
         double* U = Q + (int64_t)(steps + par) * d;
         double apart = 0.0;
         for (int i = gw; i < d; i += nw) {
-            const float* row = G + (int64_t)i * ldg;
+            const TG* row = G + (int64_t)i * ldg;
             double a[4] = {0.0, 0.0, 0.0, 0.0};
             int c = 4 * lane;
-            if (vec) {
+            if constexpr (std::is_same<TG, float>::value) {
+                if (vec) {
 #pragma unroll 4
-                for (; c + 3 < d; c += 256) {
-                    const f32x4 g = *reinterpret_cast<const f32x4*>(row + c);
-                    const double2 v01 = *reinterpret_cast<const double2*>(vq + c);
-                    const double2 v23 = *reinterpret_cast<const double2*>(vq + c + 2);
-                    a[0] += (double)g[0] * v01.x;
-                    a[1] += (double)g[1] * v01.y;
-                    a[2] += (double)g[2] * v23.x;
-                    a[3] += (double)g[3] * v23.y;
+                    for (; c + 3 < d; c += 256) {
+                        const f32x4 g = *reinterpret_cast<const f32x4*>(row + c);
+                        const double2 v01 = *reinterpret_cast<const double2*>(vq + c);
+                        const double2 v23 = *reinterpret_cast<const double2*>(vq + c + 2);
+                        a[0] += (double)g[0] * v01.x;
+                        a[1] += (double)g[1] * v01.y;
+                        a[2] += (double)g[2] * v23.x;
+                        a[3] += (double)g[3] * v23.y;
+                    }
                 }
             }
             for (; c < d; c += 256)

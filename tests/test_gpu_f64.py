@@ -100,3 +100,36 @@ def test_f64_rejections():
             cpa.shrink_dense(X, cpa.soft(0.1), o)
     with pytest.raises(cpa.CpaError):
         cpa.shrink_dense(X, cpa.soft(0.1), cpa.Opts(K=4), out=X)
+
+
+@pytest.mark.parametrize("shape,steps,tol", [((130, 70), 12, 1e-7), ((70, 130), 5, 0.0), ((300, 257), 32, 0.0),
+                                             ((1100, 600), 12, 1e-7), ((40, 3), 12, 0.0)])
+def test_f64_lanczos_bound(shape, steps, tol):
+    """The Lanczos bound on the FP64 Gram (the grid kernel at every side, its
+    vectors in the product buffer) against the oracle's lanczos_bound on the same
+    Gram, and the shrink at that bound against the oracle's CPA.  FP64 on both
+    sides: the bounds agree to rounding (1e-10 relative; the device brackets the
+    Ritz value to 2^-30 of it, well inside)."""
+    import torch
+    cpa = _lib()
+    m, n = shape
+    print(f"case f64 lanczos {m}x{n} steps={steps} tol={tol}", flush=True)
+    X = synth.dense_lowrank(m, n, rank=min(4, m, n), noise=0.2, seed=8900 + m + n)
+    G = X.T @ X if m >= n else X @ X.T
+    Lo, th_o, r_o, k_o, *_ = obound.lanczos_bound(G, seed=0, steps=steps, tol=tol)
+    lmax = float(np.linalg.eigvalsh(G)[-1])
+    sh_o, sh_c = _shrinks(cpa, lmax, 0)
+    Y, info = cpa.shrink_dense(torch.from_numpy(X).cuda(), sh_c,
+                               cpa.Opts(K=20, bound="lanczos", lanczos_steps=steps, power_tol=tol), info=True)
+    torch.cuda.synchronize()
+    print(f"  gpu {info['Lambda']:.15g} oracle {Lo:.15g} steps {info['power_iters_done']}/{k_o}", flush=True)
+    if tol == 0.0:
+        assert info["power_iters_done"] == k_o
+    else:
+        assert abs(info["power_iters_done"] - k_o) <= 1
+    # a stop one step apart (a Ritz value moving by about tol) moves Lambda by about tol
+    assert abs(info["Lambda"] - Lo) <= (1e-8 if info["power_iters_done"] == k_o else 2e-6) * Lo
+    ref = ocpa.cpa_shrink(X, sh_o, info["Lambda"], 20)
+    err = metrics.rel_fro(Y.cpu().numpy(), ref, X)
+    print(f"  shrink rel_fro={err:.3e}", flush=True)
+    assert err <= TOL64

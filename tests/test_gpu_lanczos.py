@@ -3,7 +3,7 @@ lanczos_bound: the dense entry points (one-workgroup kernel for Gram sides up to
 256, the multi-workgroup kernel above), the sparsified shrink's compact block and
 the batched path, plus the
 shrink evaluated at the device's bound, the warm start from the Ritz vector and
-the refusals.  The oracle runs in FP64 on the Gram of the FP32 input; the device
+the refusals (the FP64 entry point's parity is in test_gpu_f64.py).  The oracle runs in FP64 on the Gram of the FP32 input; the device
 Gram is FP32 (MFMA), so bounds agree to about 1e-7 relative."""
 import math
 
@@ -209,8 +209,9 @@ def test_lanczos_refusals():
     with pytest.raises(cpa.CpaError) as e:          # Gram side above 4096
         cpa.spectral_bound(torch.randn(4200, 4100, device="cuda"), cpa.Opts(K=8, bound="lanczos"))
     assert e.value.status == cpa.ERR_UNSUPPORTED
-    with pytest.raises(cpa.CpaError) as e:          # the FP64 path keeps the power rule
-        cpa.shrink_dense(X[:64, :32].double(), cpa.soft(1.0), cpa.Opts(K=8, bound="lanczos"))
+    with pytest.raises(cpa.CpaError) as e:          # the FP64 path: 34 vectors of 32 exceed its 33 x 32 buffer
+        cpa.shrink_dense(X[:33, :32].double().contiguous(), cpa.soft(1.0),
+                         cpa.Opts(K=8, bound="lanczos", lanczos_steps=32))
     assert e.value.status == cpa.ERR_UNSUPPORTED
     with pytest.raises(cpa.CpaError) as e:          # at most 32 steps
         cpa.shrink_dense(X[:64, :32].contiguous(), cpa.soft(1.0), cpa.Opts(K=8, bound="lanczos", lanczos_steps=33))
