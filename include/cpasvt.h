@@ -103,11 +103,13 @@ typedef struct {
  *                        info.resid report theta and ||r||, power_iters_done the steps.
  *                        Gram sides up to 4096 on the dense FP32 entry points (cpa_shrink_dense,
  *                        _noalloc, cpa_spectral_bound, cpa_shrink_dense_sparsified), the FP64
- *                        entry point (its Lanczos vectors take the (lanczos_steps + 2) d
- *                        doubles of its m x n product buffer: CPA_ERR_UNSUPPORTED when they
- *                        do not fit), the RPCA and inpainting drivers, and every matrix of
- *                        the batched path (d <= 64); CPA_ERR_UNSUPPORTED on larger sides and
- *                        on the CSR entry points */
+ *                        entry point, the CSR entry points (cpa_shrink_csr, cpa_svt_complete:
+ *                        the operator form S^T S, n <= 4096), the RPCA and inpainting
+ *                        drivers, and every matrix of the batched path (d <= 64);
+ *                        CPA_ERR_UNSUPPORTED on larger sides, and where the (lanczos_steps
+ *                        + 2) d doubles of Lanczos vectors do not fit an idle workspace
+ *                        buffer (the FP64 path's m x n product buffer; the CSR path's
+ *                        n x n or m x n recurrence buffers, rows padded to 32) */
 typedef enum {
     CPA_BOUND_POWER = 0,
     CPA_BOUND_GIVEN = 1,

@@ -494,15 +494,6 @@ cpa_status no_learned_bound(const cpa_opts* o) {
 // Lanczos steps of the Lanczos rule (0 selects the default).
 int lanczos_steps(const cpa_opts* o) { return o->lanczos_steps > 0 ? o->lanczos_steps : kLanczosDefault; }
 
-// The Lanczos rule runs wherever the bound is a dense FP32 Gram (sides up to the
-// grid kernel's 4096) or a batched matrix; the CSR operator form and the FP64
-// path refuse it.
-cpa_status lanczos_unsupported(const cpa_opts* o, const char* where) {
-    if (o->bound == CPA_BOUND_LANCZOS)
-        return fail(CPA_ERR_UNSUPPORTED, "the Lanczos bound is not available on %s", where);
-    return CPA_OK;
-}
-
 // Power-iteration slots of the scalar block: the power rule, and the learned
 // rule, whose check falls back to power iteration; the Lanczos rule's steps.
 int power_slots(const cpa_opts* o) {
@@ -1372,9 +1363,29 @@ cpa_status shrink_csr_impl(cpa_ctx* ctx, hipStream_t st, int m, int n, int64_t n
         unsigned* counter = reinterpret_cast<unsigned*>(w.scal + SC_BARRIER);
         double* scal = w.scal;
         double tol = o->power_tol;
-        void* args[] = {&m_, &n_, &rowptr, &colidx, &val, &colptr, &crow, &csrc, &tvec, &wb0, &wb1,
-                        &part, &counter, &scal, &maxit_, &tol, &pw_mu, &pw_w2};
-        const cpa_status ls = launch_power(ctx, reinterpret_cast<const void*>(power_op_kernel), w.lay.pwg, args, st);
+        cpa_status ls;
+        if (o->bound == CPA_BOUND_LANCZOS) {
+            // the Lanczos vectors (and u by parity) in a buffer idle until the
+            // evaluation: W (n rows), else the second recurrence buffer (m rows)
+            if (n > kPowerVecLds)
+                return fail(CPA_ERR_UNSUPPORTED, "the Lanczos bound takes Gram sides up to %d (got %d)", kPowerVecLds,
+                            n);
+            int steps = std::min(lanczos_steps(o), n);
+            const size_t need = sizeof(double) * (size_t)(steps + 2) * n;
+            double* Q = nullptr;
+            if (need <= sizeof(float) * (size_t)n * w.ld)
+                Q = reinterpret_cast<double*>(w.W);
+            else if (need <= sizeof(float) * (size_t)m * w.ld)
+                Q = reinterpret_cast<double*>(w.Y[1]);
+            if (!Q) return fail(CPA_ERR_UNSUPPORTED, "no room for the Lanczos vectors in this workspace");
+            void* args[] = {&m_, &n_, &rowptr, &colidx, &val, &colptr, &crow, &csrc, &tvec, &wb0, &wb1,
+                            &Q, &part, &counter, &scal, &steps, &tol, &pw_mu, &pw_w2};
+            ls = launch_power(ctx, reinterpret_cast<const void*>(lanczos_op_kernel), w.lay.pwg, args, st);
+        } else {
+            void* args[] = {&m_, &n_, &rowptr, &colidx, &val, &colptr, &crow, &csrc, &tvec, &wb0, &wb1,
+                            &part, &counter, &scal, &maxit_, &tol, &pw_mu, &pw_w2};
+            ls = launch_power(ctx, reinterpret_cast<const void*>(power_op_kernel), w.lay.pwg, args, st);
+        }
         if (ls != CPA_OK) return ls;
     }
     hipLaunchKernelGGL(finish_bound_kernel, dim3(1), dim3(256), 0, st, mode, o->Lambda, n, o->power_iters, o->margin,
@@ -2309,7 +2320,6 @@ cpa_status cpa_shrink_csr(cpa_ctx* ctx, void* stream, int m, int n, int64_t nnz,
     if ((s = check_shrinkage(shrink)) != CPA_OK) return s;
     if ((s = check_opts(opts)) != CPA_OK) return s;
     if ((s = learned_bound_unsupported(opts)) != CPA_OK) return s;
-    if ((s = lanczos_unsupported(opts, "the CSR path")) != CPA_OK) return s;
     if (opts->precision != CPA_PREC_FP32) return fail(CPA_ERR_UNSUPPORTED, "sparse path is FP32");
     if (opts->check) return fail(CPA_ERR_UNSUPPORTED, "the growth check is not available on the sparse path");
     if (m == 0 || n == 0) {
@@ -2351,7 +2361,6 @@ cpa_status cpa_svt_complete(cpa_ctx* ctx, void* stream, int m, int n, int64_t nn
     if (opts && opts->side == CPA_SIDE_LEFT) return fail(CPA_ERR_UNSUPPORTED, "sparse path forms S^T S (side right)");
     if ((s = check_opts(opts)) != CPA_OK) return s;
     if ((s = no_learned_bound(opts)) != CPA_OK) return s;
-    if ((s = lanczos_unsupported(opts, "the CSR path")) != CPA_OK) return s;
     if (opts->precision != CPA_PREC_FP32 || opts->check) return fail(CPA_ERR_UNSUPPORTED, "unsupported option");
     if (!(std::isfinite(tau) && tau >= 0.0 && std::isfinite(delta) && delta > 0.0) || iters < 0)
         return fail(CPA_ERR_ARG, "tau >= 0, delta > 0 and iters >= 0 required");

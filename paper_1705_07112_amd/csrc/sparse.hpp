@@ -28,6 +28,7 @@
 //                    vectors and partial sums go through agent-scope atomic
 //                    accesses, so the barriers flush no cache and the pattern
 //                    stays in L2 from one product to the next.
+//   lanczos_op_kernel  the k-step Lanczos bound on S^T S in the same way.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -469,6 +470,172 @@ __global__ void __launch_bounds__(kPowerThreads) power_op_kernel(int m, int n, c
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         scal[SC_STOP] = stop ? stop : (vanish ? 0 : maxit);
         scal[SC_VANISH] = vanish;
+    }
+}
+
+// k-step Lanczos on S^T S through two sparse products per step, the operator
+// form's counterpart of lanczos_coop_kernel (n <= kPowerVecLds): in step j
+//   t = S q_j (rows over waves, q_j in LDS), stored with agent scope; grid barrier;
+//   u_c = (S^T t)_c - beta_{j-1} q_{j-1,c} for each wave's columns (rows ascending
+//   within a column), stored with q_{j,c}, and q_{j,c} u_c into the workgroup's
+//   alpha partial; grid barrier;
+//   every workgroup adds the partials in a fixed order (alpha_j), loads all of u,
+//   forms u - alpha_j q_j and ||.||^2 over the n entries itself (the same
+//   operations in every workgroup) and keeps q_{j+1} = u / beta_j in LDS.
+// The Ritz pair, the stop and the result slots as in lanczos_coop_kernel; entry c
+// of the Ritz vector is formed by the thread that stored Q[.][c].  Q holds
+// steps + 2 vectors of n: the Lanczos vectors, then U by step parity.
+__global__ void __launch_bounds__(kPowerThreads) lanczos_op_kernel(int m, int n, const int32_t* rowptr,
+                                                                   const int32_t* colidx, const float* val,
+                                                                   const int32_t* colptr, const int32_t* crow,
+                                                                   const int32_t* csrc, double* tvec, double* wb0,
+                                                                   double* wb1, double* Q, double* part,
+                                                                   unsigned* counter, double* scal, int steps,
+                                                                   double tol, int pw_mu, int pw_w2) {
+    __shared__ double red[kPowerThreads / 64];
+    __shared__ double rz[3][kLzSlot];   // Ritz pairs: by step parity, then the final one
+    __shared__ __attribute__((aligned(16))) double va[kPowerVecLds];
+    __shared__ __attribute__((aligned(16))) double vb[kPowerVecLds];
+    const int P = gridDim.x;
+    const int lane = threadIdx.x & 63;
+    const int gw = blockIdx.x * (kPowerThreads / 64) + (threadIdx.x >> 6);
+    const int nw = P * (kPowerThreads / 64);
+    const double n0 = scal[pw_w2 + 0];
+    if (!(n0 > 0.0)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            scal[SC_STOP] = 0;
+            scal[SC_VANISH] = 1;
+        }
+        return;
+    }
+    const double inv0 = 1.0 / sqrt(n0);
+    for (int i = threadIdx.x; i < n; i += kPowerThreads) {
+        va[i] = wb0[i] * inv0;   // q_1
+        vb[i] = 0.0;             // q_0
+    }
+    __syncthreads();
+    double* vq = va;   // q_j
+    double* vp = vb;   // q_{j-1}, then u
+    double bprev = 0.0;
+    double al = 0.0, be = 0.0, th_prev = 0.0;
+    int k = 0, vanish = 0, slot = -1;
+    unsigned bar = 0;
+    for (int j = 0; j < steps; ++j) {
+        const int par = j & 1;
+        double* U = Q + (int64_t)(steps + par) * n;
+        // t = S q_j
+        for (int r = gw; r < m; r += nw) {
+            double acc = 0.0;
+            for (int32_t e = rowptr[r] + lane; e < rowptr[r + 1]; e += 64) acc += (double)val[e] * vq[colidx[e]];
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if (lane == 0) st_agent(tvec + r, acc);
+        }
+        if (!grid_barrier_coherent(counter, (++bar) * P, scal)) return;
+        // u = S^T t - beta_{j-1} q_{j-1} on this wave's columns
+        double apart = 0.0;
+        for (int c = gw; c < n; c += nw) {
+            double acc = 0.0;
+            for (int32_t p = colptr[c] + lane; p < colptr[c + 1]; p += 64)
+                acc += (double)val[csrc[p]] * ld_agent(tvec + crow[p]);
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+            if (lane == 0) {
+                const double uc = acc - bprev * vp[c];
+                st_agent(U + c, uc);
+                st_agent(Q + (int64_t)j * n + c, vq[c]);
+                apart += vq[c] * uc;
+            }
+        }
+        apart = block_sum(apart, red);
+        double* pt = part + par * 2 * P;
+        if (threadIdx.x == 0) st_agent(pt + blockIdx.x, apart);
+        if (!grid_barrier_coherent(counter, (++bar) * P, scal)) return;
+        double sa = 0.0;
+        for (int p = threadIdx.x; p < P; p += kPowerThreads) sa += ld_agent(pt + p);
+        const double alpha = block_sum(sa, red);
+        // u - alpha q_j over all n entries, into vp (q_{j-1} is no longer needed)
+        double b2 = 0.0;
+        for (int i = threadIdx.x; i < n; i += kPowerThreads) {
+            const double ui = ld_agent(U + i) - alpha * vq[i];
+            vp[i] = ui;
+            b2 += ui * ui;
+        }
+        const double beta = sqrt(block_sum(b2, red));
+        if (lane == j) {
+            al = alpha;
+            be = beta;
+        }
+        k = j + 1;
+        if (j == 0 && alpha == 0.0 && beta == 0.0) {
+            vanish = 1;
+            break;
+        }
+        if (beta == 0.0) break;
+        if (tol > 0.0) {
+            // the Ritz pair of T_{j+1}; kept when the run ends here
+            if (threadIdx.x < 64) {
+                double theta, resid, sv;
+                lz_ritz(al, be, k, theta, resid, sv);
+                const bool stop = j >= 1 && fabs(theta - th_prev) <= tol * theta;
+                th_prev = theta;
+                if (lane < k) rz[par][lane] = sv;
+                if (lane == 0) {
+                    rz[par][kLanczosMax] = theta;
+                    rz[par][kLanczosMax + 1] = resid;
+                    rz[par][kLanczosMax + 2] = stop ? 1.0 : 0.0;
+                }
+            }
+            __syncthreads();
+            if (rz[par][kLanczosMax + 2] != 0.0) {
+                slot = par;
+                break;
+            }
+        }
+        // q_{j+1} = u / beta; the roles of the two LDS vectors swap
+        const double ib = 1.0 / beta;
+        for (int i = threadIdx.x; i < n; i += kPowerThreads) vp[i] *= ib;
+        __syncthreads();
+        double* t = vq;
+        vq = vp;
+        vp = t;
+        bprev = beta;
+    }
+    if (vanish) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            scal[SC_STOP] = 0;
+            scal[SC_VANISH] = 1;
+        }
+        return;
+    }
+    if (slot < 0) {
+        // the Ritz pair of T_k
+        slot = 2;
+        if (threadIdx.x < 64) {
+            double theta, resid, sv;
+            lz_ritz(al, be, k, theta, resid, sv);
+            if (lane < k) rz[2][lane] = sv;
+            if (lane == 0) {
+                rz[2][kLanczosMax] = theta;
+                rz[2][kLanczosMax + 1] = resid;
+            }
+        }
+        __syncthreads();
+    }
+    // the Ritz vector: entry c from the stores of the thread that owns column c
+    double* yb = ((k - 1) & 1) ? wb1 : wb0;
+    if (lane == 0) {
+        for (int c = gw; c < n; c += nw) {
+            double y = 0.0;
+            for (int q = 0; q < k; ++q) y += rz[slot][q] * Q[(int64_t)q * n + c];
+            yb[c] = y;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const double theta = rz[slot][kLanczosMax], resid = rz[slot][kLanczosMax + 1];
+        scal[pw_mu + k] = theta;
+        scal[pw_w2 + k] = theta * theta + resid * resid;
+        scal[pw_w2 + k - 1] = 1.0;
+        scal[SC_STOP] = k;
+        scal[SC_VANISH] = 0;
     }
 }
 

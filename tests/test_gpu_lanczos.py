@@ -217,10 +217,10 @@ def test_lanczos_refusals():
         cpa.shrink_dense(X[:64, :32].contiguous(), cpa.soft(1.0), cpa.Opts(K=8, bound="lanczos", lanczos_steps=33))
     assert e.value.status == cpa.ERR_ARG
     rowptr = torch.tensor([0, 1, 2], dtype=torch.int32, device="cuda")
-    cols = torch.tensor([0, 1], dtype=torch.int32, device="cuda")
+    cols = torch.tensor([0, 4199], dtype=torch.int32, device="cuda")
     vals = torch.tensor([1.0, 2.0], device="cuda")
-    with pytest.raises(cpa.CpaError) as e:          # the CSR path keeps the power rule
-        cpa.shrink_csr(2, 2, rowptr, cols, vals, cpa.soft(0.1), cpa.Opts(K=4, bound="lanczos"))
+    with pytest.raises(cpa.CpaError) as e:          # the CSR path: n above 4096
+        cpa.shrink_csr(2, 4200, rowptr, cols, vals, cpa.soft(0.1), cpa.Opts(K=4, bound="lanczos"))
     assert e.value.status == cpa.ERR_UNSUPPORTED
 
 

@@ -178,14 +178,16 @@ def _svt_problem(m, n, r, frac, seed):
     return M, rows, cols, vals, rowptr
 
 
-@pytest.mark.parametrize("ev", ["auto", "recurrence"])
-def test_svt_iterations_from_the_gpu_state(ev):
+@pytest.mark.parametrize("ev,bound", [("auto", "power"), ("recurrence", "power"), ("auto", "lanczos")])
+def test_svt_iterations_from_the_gpu_state(ev, bound):
     """Gated like the ADMM driver: the GPU's own iterate Y^t (on the observed set)
     after five iterations, then one and two more iterations continued from it;
     the oracle applies its shrink to the same Y^t at the bounds the GPU reports
     and the SVT update, and X (whole matrix) and Y (observed set) must agree to
     the FP32 tolerance.  On the matrix-polynomial route the first of the two
-    iterations forms only the observed entries of X."""
+    iterations forms only the observed entries of X.  Every reported bound is at
+    least the top eigenvalue of its iterate's Gram (the Lanczos rule warm-starts
+    from the previous Ritz vector)."""
     import torch
     import paper_1705_07112_amd as cpa
     m, n, K = 600, 200, 25
@@ -194,7 +196,7 @@ def test_svt_iterations_from_the_gpu_state(ev):
     r_d = torch.from_numpy(rowptr).cuda()
     c_d = torch.from_numpy(cols.astype(np.int32)).cuda()
     v_d = torch.from_numpy(vals).cuda()
-    opts = cpa.Opts(K=K, warm_start=True, eval=ev)
+    opts = cpa.Opts(K=K, warm_start=True, eval=ev, bound=bound)
     y5 = torch.empty(len(vals), dtype=torch.float32, device="cuda")
     cpa.svt_complete(m, n, r_d, c_d, v_d, tau, step, 5, opts, y_end=y5)
     Y5 = np.zeros((m, n))
@@ -207,6 +209,8 @@ def test_svt_iterations_from_the_gpu_state(ev):
         torch.cuda.synchronize()
         Yo = Y5.copy()
         for t in range(extra):
+            lmax = float(np.linalg.eigvalsh(Yo.T @ Yo)[-1])
+            assert float(lam[t].item()) >= lmax * (1 - 1e-6), (bound, t, float(lam[t].item()), lmax)
             Xo = ocpa.cpa_shrink(Yo, sh, float(lam[t].item()), K)
             Yo[rows, cols] += step * (vals.astype(np.float64) - Xo[rows, cols])
         parity.check(X.cpu().numpy(), Xo, TOL32, label=f"svt X after {extra} from Y^5 ({ev})")
@@ -239,3 +243,33 @@ def test_csr_rejects_unsorted_or_repeated_columns():
         with pytest.raises(cpa.CpaError) as e:
             _gpu_csr(4, 4, rowptr, np.array(cols, np.int32), np.ones(3, np.float32), cpa.soft(0.1), cpa.Opts(K=5))
         assert e.value.status == cpa.ERR_ARG
+
+
+@pytest.mark.parametrize("m,n,frac,steps,tol", [(2000, 400, 0.02, 12, 1e-7), (300, 120, 0.05, 32, 0.0),
+                                                (64, 48, 0.1, 5, 0.0), (5000, 1500, 0.004, 12, 1e-7),
+                                                (40, 3, 0.3, 12, 0.0)])
+def test_csr_lanczos_bound_matches_oracle(m, n, frac, steps, tol):
+    """The Lanczos bound on the operator form S^T S (two sparse products per step)
+    against the oracle's lanczos_bound on the densified Gram with the same cap
+    (tr G = ||S||_F^2), and the shrink at the device's bound against the oracle's
+    CPA.  S holds FP32 values and both sides accumulate in FP64: the bounds agree
+    to rounding (1e-8 relative; 2e-6 where the early stop lands one step apart)."""
+    import paper_1705_07112_amd as cpa
+    print(f"case csr lanczos {m}x{n} steps={steps} tol={tol}", flush=True)
+    rowptr, cols, vals, S = _random_csr(m, n, frac, 20800 + m + n, empty_rows=(0,), empty_cols=(1,))
+    G = S.T @ S
+    Lo, th_o, r_o, k_o, *_ = obound.lanczos_bound(G, seed=0, steps=steps, tol=tol, cap=float(np.trace(G)))
+    lmax = float(np.linalg.eigvalsh(G)[-1])
+    tau = 0.3 * math.sqrt(lmax)
+    Y, info = _gpu_csr(m, n, rowptr, cols, vals, cpa.soft(tau),
+                       cpa.Opts(K=16, bound="lanczos", lanczos_steps=steps, power_tol=tol), info=True)
+    print(f"  gpu {info['Lambda']:.15g} oracle {Lo:.15g} steps {info['power_iters_done']}/{k_o}", flush=True)
+    if tol == 0.0:
+        assert info["power_iters_done"] == k_o
+    else:
+        assert abs(info["power_iters_done"] - k_o) <= 1
+    assert abs(info["Lambda"] - Lo) <= (1e-8 if info["power_iters_done"] == k_o else 2e-6) * Lo
+    if steps >= 12:
+        assert info["Lambda"] >= lmax * (1 - 1e-6)
+    ref = ocpa.cpa_shrink(S, Shrinkage(0, tau), info["Lambda"], 16)
+    parity.check(Y.cpu().numpy(), ref, TOL32, S, f"csr lanczos {m}x{n}")
