@@ -375,6 +375,20 @@ def bench_sparse(cpa, torch, np, synth):
     step_bytes = (dense + 8.0 * nnz + 4.0 * n * n) + (8.0 * nnz + 4.0 * n * n + 5 * dense)
     ms_p, us_p, l_p = res["auto"]
     ms_r, us_r, l_r = res["recurrence"]
+    # the cold bound alone on the operator form (K = 2: the bound, then one product):
+    # the power iteration against the Lanczos rule, both from the seeded vector
+    bound_cold = {}
+    for rule in ("power", "lanczos"):
+        ob = cpa.Opts(K=2, bound=rule)
+        _, ib = cpa.shrink_csr(m, n, r, c, v, cpa.soft(tau), ob, out=out, info=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(3):
+            cpa.shrink_csr(m, n, r, c, v, cpa.soft(tau), ob, out=out)
+        e1.record()
+        torch.cuda.synchronize()
+        bound_cold[rule] = {"ms_per_call": round(e0.elapsed_time(e1) / 3, 3), "Lambda": ib["Lambda"],
+                            "products_or_steps": ib["power_iters_done"]}
     flop_gemm = 2.0 * n * n * n
     nt_s = (n + 63) // 64
     flop_issued = (nt_s * (nt_s + 1) // 2) * 64.0 * 64.0 * 2.0 * n
@@ -413,6 +427,8 @@ def bench_sparse(cpa, torch, np, synth):
                      "issued_frac": round(flop_issued / (us_p * 1e-6) / 1e12 / MFMA_FP32_PEAK_TFLOPS, 4),
                      "avg_launch_us": round(us_p, 1), "launches": l_p, "traffic": None},
         "svt_completion": svt,
+        "cold_bound_K2": dict(bound_cold, note="one cold K = 2 call per rule (bound on S^T S through two "
+                                               "sparse products per product or step, then one product)"),
         "operator_form": {"ms_per_shrink": round(ms_r, 3), "shrinks_per_s": round(1e3 / ms_r, 2),
                           "spmm_pair_avg_us": round(us_r, 1),
                           "roofline": {"bound": "hbm", "achieved": round(step_bytes / (us_r * 1e-6) / 1e9, 1),
